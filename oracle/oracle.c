@@ -1,0 +1,814 @@
+/*
+ * Plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see oracle.h).
+ *
+ * Written for obviousness, not speed: every basis value is produced by the literal
+ * Cox-de Boor recursion at every quadrature point, every element integral by the naive
+ * per-quadrature-point double loop over (a, b), and every CSR slot by binary search.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXP 7            /* functions per axis per element (degree <= 6) */
+#define ORC_MAXLOC 343        /* ORC_MAXP^3 */
+#define ORC_MAXQ 12
+
+/* ------------------------------------------------------------------------------------ */
+/* Gauss-Legendre rule on [-1,1]: Newton iteration on P_n from the three-term recurrence  */
+/* (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1}; weights 2 / ((1-x^2) P_n'(x)^2).              */
+/* ------------------------------------------------------------------------------------ */
+int orc_gauss_legendre(int n, double *x, double *w) {
+  if (n < 1 || n > 64 || !x || !w) return 1;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), pn = 0.0, pm = 0.0, dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      pn = z;                               /* P_1 */
+      pm = 1.0;                             /* P_0 */
+      for (int k = 1; k < n; ++k) {
+        double pk = ((2.0 * k + 1.0) * z * pn - k * pm) / (k + 1.0);
+        pm = pn;
+        pn = pk;
+      }
+      if (n == 1) { pn = z; pm = 1.0; }
+      dp = n * (z * pn - pm) / (z * z - 1.0);    /* P_n'(z) */
+      double dz = pn / dp;
+      z -= dz;
+      if (fabs(dz) <= 1e-17) break;
+    }
+    pn = z; pm = 1.0;
+    for (int k = 1; k < n; ++k) {
+      double pk = ((2.0 * k + 1.0) * z * pn - k * pm) / (k + 1.0);
+      pm = pn;
+      pn = pk;
+    }
+    dp = n * (z * pn - pm) / (z * z - 1.0);
+    double wt = 2.0 / ((1.0 - z * z) * dp * dp);
+    x[n - 1 - i] = z;  w[n - 1 - i] = wt;      /* ascending order, symmetric pairs */
+    x[i] = -z;         w[i] = wt;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Cox-de Boor recursion taken literally (Sec. 2.1), with 0/0 := 0.  B_{i,0} is the       */
+/* half-open indicator of [xi_i, xi_{i+1}); by convention the last non-empty span is also  */
+/* closed on the right so that the basis is defined at the end of the patch.               */
+/* ------------------------------------------------------------------------------------ */
+static double cdb(const double *U, int nk, int i, int p, double xi) {
+  if (p == 0) {
+    if (U[i] <= xi && xi < U[i + 1]) return 1.0;
+    if (xi == U[nk - 1] && U[i] < U[i + 1] && U[i + 1] == U[nk - 1]) return 1.0;
+    return 0.0;
+  }
+  double a = U[i + p] - U[i];
+  double b = U[i + p + 1] - U[i + 1];
+  double left = 0.0, right = 0.0;
+  if (a != 0.0) left = (xi - U[i]) / a * cdb(U, nk, i, p - 1, xi);
+  if (b != 0.0) right = (U[i + p + 1] - xi) / b * cdb(U, nk, i + 1, p - 1, xi);
+  return left + right;
+}
+
+/* First derivative: p/(xi_{i+p}-xi_i) B_{i,p-1} - p/(xi_{i+p+1}-xi_{i+1}) B_{i+1,p-1}.
+ * (The paper prints a plus sign between the two terms; the minus sign is the one that
+ * differentiates the recursion above, and it is what makes the derivatives sum to zero.) */
+static double cdb_der(const double *U, int nk, int i, int p, double xi) {
+  if (p == 0) return 0.0;
+  double a = U[i + p] - U[i];
+  double b = U[i + p + 1] - U[i + 1];
+  double d = 0.0;
+  if (a != 0.0) d += p / a * cdb(U, nk, i, p - 1, xi);
+  if (b != 0.0) d -= p / b * cdb(U, nk, i + 1, p - 1, xi);
+  return d;
+}
+
+int orc_basis_1d(int p, const double *U, int nk, int i, double xi, double *val, double *der) {
+  if (p < 0 || !U || i < 0 || i + p + 1 >= nk) return 1;
+  if (val) *val = cdb(U, nk, i, p, xi);
+  if (der) *der = cdb_der(U, nk, i, p, xi);
+  return 0;
+}
+
+/* Algorithm 2: left-most and right-most indices of the functions whose support overlaps
+ * the support of function i (clamped to the valid range). */
+int orc_stencil(int p, const double *U, int nk, int i, int *l, int *r) {
+  int n = nk - p - 1;
+  if (i < 0 || i >= n) return 1;
+  int j = i;
+  while (j + 1 < nk && U[j] == U[j + 1]) j++;
+  int ll = j - p;
+  j = i + p + 1;
+  while (j - 1 >= 0 && U[j] == U[j - 1]) j--;
+  int rr = j - 1;
+  if (ll < 0) ll = 0;
+  if (rr > n - 1) rr = n - 1;
+  *l = ll;
+  *r = rr;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Problem layout                                                                        */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+  int dim;
+  int p[3], n[3], nq[3], ne[3];
+  int *span[3];            /* span index s of each element: functions s-p..s are nonzero */
+  double gx[3][ORC_MAXQ], gw[3][ORC_MAXQ];
+  int64_t N, E;
+} layout;
+
+static void lay_free(layout *L) {
+  for (int d = 0; d < 3; ++d) free(L->span[d]);
+}
+
+static int lay_init(const orc_problem *pb, layout *L) {
+  memset(L, 0, sizeof(*L));
+  if (!pb || pb->dim < 1 || pb->dim > 3) return 1;
+  L->dim = pb->dim;
+  L->N = 1;
+  L->E = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (d >= pb->dim) {
+      L->p[d] = 0; L->n[d] = 1; L->nq[d] = 1; L->ne[d] = 1;
+      L->span[d] = (int *)calloc(1, sizeof(int));
+      L->gx[d][0] = 0.0; L->gw[d][0] = 2.0;
+      continue;
+    }
+    int p = pb->degree[d], nk = pb->nknots[d];
+    const double *U = pb->knots[d];
+    if (p < 1 || p > ORC_MAXP - 1 || !U || nk < 2 * p + 2) { lay_free(L); return 1; }
+    for (int k = 0; k + 1 < nk; ++k)
+      if (!(U[k] <= U[k + 1])) { lay_free(L); return 1; }
+    for (int k = 0; k < p; ++k)
+      if (U[k] != U[k + 1] || U[nk - 1 - k] != U[nk - 2 - k]) { lay_free(L); return 1; }
+    L->p[d] = p;
+    L->n[d] = nk - p - 1;
+    L->nq[d] = pb->nquad[d] > 0 ? pb->nquad[d] : p + 1;
+    if (L->nq[d] > ORC_MAXQ) { lay_free(L); return 1; }
+    orc_gauss_legendre(L->nq[d], L->gx[d], L->gw[d]);
+    L->span[d] = (int *)malloc(sizeof(int) * nk);
+    int ne = 0;
+    for (int s = p; s < L->n[d]; ++s)
+      if (U[s] < U[s + 1]) L->span[d][ne++] = s;
+    if (ne == 0) { lay_free(L); return 1; }
+    L->ne[d] = ne;
+  }
+  for (int d = 0; d < 3; ++d) { L->N *= L->n[d]; L->E *= L->ne[d]; }
+  if (pb->weights)
+    for (int64_t A = 0; A < L->N; ++A)
+      if (!(pb->weights[A] > 0.0)) { lay_free(L); return 1; }
+  if (pb->kappa_mode < 0 || pb->kappa_mode > 2) { lay_free(L); return 1; }
+  if (pb->kappa_mode != 0 && !pb->kappa) { lay_free(L); return 1; }
+  return 0;
+}
+
+static int is_dirichlet(const orc_problem *pb, const layout *L, int64_t A) {
+  int64_t i[3] = {A % L->n[0], (A / L->n[0]) % L->n[1], A / ((int64_t)L->n[0] * L->n[1])};
+  for (int d = 0; d < pb->dim; ++d) {
+    if ((pb->dirichlet_mask >> (2 * d)) & 1u)
+      if (i[d] == 0) return 1;
+    if ((pb->dirichlet_mask >> (2 * d + 1)) & 1u)
+      if (i[d] == L->n[d] - 1) return 1;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Shape functions at one quadrature point of one element (ShapeFuns in Algorithm 3)     */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+  int nloc;
+  int64_t A[ORC_MAXLOC];     /* global index of each local function (a0 fastest) */
+  double N[ORC_MAXLOC];      /* rational basis values */
+  double dN[ORC_MAXLOC][3];  /* spatial gradients */
+  double x[3];
+  double W;                  /* quadrature weight * span factors * det J */
+  double u, gu[3], kap, f;
+} qpoint;
+
+static int eval_qp(const orc_problem *pb, const layout *L, const int e[3], const int g[3],
+                   const double *U, qpoint *q) {
+  int dim = L->dim;
+  double B[3][ORC_MAXP], dB[3][ORC_MAXP], wq = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    if (d >= dim) { B[d][0] = 1.0; dB[d][0] = 0.0; continue; }
+    const double *K = pb->knots[d];
+    int s = L->span[d][e[d]], p = L->p[d];
+    double a = K[s], b = K[s + 1];
+    double xi = 0.5 * ((a + b) + (b - a) * L->gx[d][g[d]]);
+    wq *= L->gw[d][g[d]] * 0.5 * (b - a);
+    for (int k = 0; k <= p; ++k)
+      orc_basis_1d(p, K, pb->nknots[d], s - p + k, xi, &B[d][k], &dB[d][k]);
+  }
+  int P0 = L->p[0] + 1, P1 = L->p[1] + 1, P2 = L->p[2] + 1;
+  int nloc = P0 * P1 * P2;
+  q->nloc = nloc;
+  double M[ORC_MAXLOC], dM[ORC_MAXLOC][3];
+  for (int a2 = 0; a2 < P2; ++a2)
+    for (int a1 = 0; a1 < P1; ++a1)
+      for (int a0 = 0; a0 < P0; ++a0) {
+        int a = a0 + P0 * (a1 + P1 * a2);
+        int64_t i0 = L->span[0][e[0]] - L->p[0] + a0;
+        int64_t i1 = L->span[1][e[1]] - L->p[1] + a1;
+        int64_t i2 = L->span[2][e[2]] - L->p[2] + a2;
+        q->A[a] = i0 + (int64_t)L->n[0] * (i1 + (int64_t)L->n[1] * i2);
+        M[a] = B[0][a0] * B[1][a1] * B[2][a2];
+        dM[a][0] = dB[0][a0] * B[1][a1] * B[2][a2];
+        dM[a][1] = B[0][a0] * dB[1][a1] * B[2][a2];
+        dM[a][2] = B[0][a0] * B[1][a1] * dB[2][a2];
+      }
+  /* rational basis (eq:rational) and parametric derivatives (eq:drational) */
+  double dNp[ORC_MAXLOC][3];
+  if (pb->weights) {
+    double w = 0.0, dw[3] = {0, 0, 0};
+    for (int a = 0; a < nloc; ++a) {
+      double wa = pb->weights[q->A[a]];
+      w += wa * M[a];
+      for (int al = 0; al < 3; ++al) dw[al] += wa * dM[a][al];
+    }
+    for (int a = 0; a < nloc; ++a) {
+      double wa = pb->weights[q->A[a]];
+      q->N[a] = wa * M[a] / w;
+      for (int al = 0; al < 3; ++al) dNp[a][al] = (wa * dM[a][al] - q->N[a] * dw[al]) / w;
+    }
+  } else {
+    for (int a = 0; a < nloc; ++a) {
+      q->N[a] = M[a];
+      for (int al = 0; al < 3; ++al) dNp[a][al] = dM[a][al];
+    }
+  }
+  /* geometry: x_{i,alpha} = sum_A x_{A,i} N_{A,alpha}; inverse via eq:identity */
+  double J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  double xi_phys[3] = {0, 0, 0};
+  if (pb->ctrl) {
+    for (int i = 0; i < dim; ++i)
+      for (int al = 0; al < dim; ++al) J[i][al] = 0.0;
+    for (int a = 0; a < nloc; ++a)
+      for (int i = 0; i < dim; ++i) {
+        double xa = pb->ctrl[q->A[a] * dim + i];
+        xi_phys[i] += xa * q->N[a];
+        for (int al = 0; al < dim; ++al) J[i][al] += xa * dNp[a][al];
+      }
+  } else {
+    for (int d = 0; d < dim; ++d) {
+      const double *K = pb->knots[d];
+      int s = L->span[d][e[d]];
+      xi_phys[d] = 0.5 * ((K[s] + K[s + 1]) + (K[s + 1] - K[s]) * L->gx[d][g[d]]);
+    }
+  }
+  double det, Ji[3][3];
+  if (dim == 1) {
+    det = J[0][0];
+    Ji[0][0] = 1.0 / det;
+  } else if (dim == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    Ji[0][0] = J[1][1] / det;  Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+  } else {
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+        - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+        + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  }
+  if (!(det > 0.0)) return 2;
+  /* Ji[alpha][i] = d xi_alpha / d x_i ; spatial gradient N_{A,i} = N_{A,alpha} xi_{alpha,i} */
+  for (int a = 0; a < nloc; ++a)
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+      if (i < dim)
+        for (int al = 0; al < dim; ++al) s += dNp[a][al] * Ji[al][i];
+      q->dN[a][i] = s;
+    }
+  for (int i = 0; i < 3; ++i) q->x[i] = xi_phys[i];
+  q->W = wq * det;
+  /* state, coefficient and source at the point */
+  q->u = 0.0;
+  q->gu[0] = q->gu[1] = q->gu[2] = 0.0;
+  for (int a = 0; a < nloc; ++a) {
+    double Ua = U ? U[q->A[a]] : 0.0;
+    q->u += Ua * q->N[a];
+    for (int i = 0; i < 3; ++i) q->gu[i] += Ua * q->dN[a][i];
+  }
+  if (pb->kappa_mode == 0) {
+    q->kap = 1.0;
+  } else if (pb->kappa_mode == 1) {
+    q->kap = 0.0;
+    for (int a = 0; a < nloc; ++a) q->kap += pb->kappa[q->A[a]] * q->N[a];
+  } else {
+    int64_t ee = e[0] + (int64_t)L->ne[0] * (e[1] + (int64_t)L->ne[1] * e[2]);
+    q->kap = pb->kappa[ee];
+  }
+  q->f = 0.0;
+  if (pb->source)
+    for (int a = 0; a < nloc; ++a) q->f += pb->source[q->A[a]] * q->N[a];
+  return 0;
+}
+
+static void elem_multi(const layout *L, int64_t e, int em[3]) {
+  em[0] = (int)(e % L->ne[0]);
+  em[1] = (int)((e / L->ne[0]) % L->ne[1]);
+  em[2] = (int)(e / ((int64_t)L->ne[0] * L->ne[1]));
+}
+
+static void qp_multi(const layout *L, int g, int gm[3]) {
+  gm[0] = g % L->nq[0];
+  gm[1] = (g / L->nq[0]) % L->nq[1];
+  gm[2] = g / (L->nq[0] * L->nq[1]);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Sizes and the CSR pattern (Algorithm 2 per axis, tensor product, sorted columns)      */
+/* ------------------------------------------------------------------------------------ */
+int orc_sizes(const orc_problem *pb, int64_t *ndof, int64_t *nelem, int64_t *nnz) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  int64_t cnt = 0;
+  for (int64_t A = 0; A < L.N; ++A) {
+    int64_t i[3] = {A % L.n[0], (A / L.n[0]) % L.n[1], A / ((int64_t)L.n[0] * L.n[1])};
+    int64_t w = 1;
+    for (int d = 0; d < pb->dim; ++d) {
+      int l, r;
+      orc_stencil(L.p[d], pb->knots[d], pb->nknots[d], (int)i[d], &l, &r);
+      w *= (r - l + 1);
+    }
+    cnt += w;
+  }
+  if (ndof) *ndof = L.N;
+  if (nelem) *nelem = L.E;
+  if (nnz) *nnz = cnt;
+  lay_free(&L);
+  return 0;
+}
+
+int orc_csr_pattern(const orc_problem *pb, int64_t *row_ptr, int32_t *col_idx) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  int64_t pos = 0;
+  row_ptr[0] = 0;
+  for (int64_t A = 0; A < L.N; ++A) {
+    int64_t i[3] = {A % L.n[0], (A / L.n[0]) % L.n[1], A / ((int64_t)L.n[0] * L.n[1])};
+    int l[3] = {0, 0, 0}, r[3] = {0, 0, 0};
+    for (int d = 0; d < pb->dim; ++d)
+      orc_stencil(L.p[d], pb->knots[d], pb->nknots[d], (int)i[d], &l[d], &r[d]);
+    for (int j2 = l[2]; j2 <= r[2]; ++j2)
+      for (int j1 = l[1]; j1 <= r[1]; ++j1)
+        for (int j0 = l[0]; j0 <= r[0]; ++j0)
+          col_idx[pos++] = (int32_t)(j0 + (int64_t)L.n[0] * (j1 + (int64_t)L.n[1] * j2));
+    row_ptr[A + 1] = pos;
+  }
+  lay_free(&L);
+  return 0;
+}
+
+static int64_t csr_find(const int64_t *row_ptr, const int32_t *col_idx, int64_t A, int64_t B) {
+  int64_t lo = row_ptr[A], hi = row_ptr[A + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (col_idx[mid] == B) return mid;
+    if (col_idx[mid] < B) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Integrands (eq:residual, eq:jacobian, with kappa and an optional source f)            */
+/*   R_a += W ( kappa grad N_a . grad u - N_a (lambda e^u + f) )                          */
+/*   K_ab += W ( kappa grad N_a . grad N_b - lambda e^u N_a N_b )                         */
+/* ------------------------------------------------------------------------------------ */
+static double res_term(const orc_problem *pb, const qpoint *q, int a) {
+  double g = q->dN[a][0] * q->gu[0] + q->dN[a][1] * q->gu[1] + q->dN[a][2] * q->gu[2];
+  return q->W * (q->kap * g - q->N[a] * (pb->lambda * exp(q->u) + q->f));
+}
+
+static double jac_term(const orc_problem *pb, const qpoint *q, int a, int b) {
+  double g = q->dN[a][0] * q->dN[b][0] + q->dN[a][1] * q->dN[b][1] + q->dN[a][2] * q->dN[b][2];
+  return q->W * (q->kap * g - pb->lambda * exp(q->u) * q->N[a] * q->N[b]);
+}
+
+int orc_residual(const orc_problem *pb, const double *U, double *R) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  memset(R, 0, sizeof(double) * L.N);
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0;
+  for (int64_t e = 0; e < L.E && !rc; ++e) {
+    int em[3], gm[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqe && !rc; ++g) {
+      qp_multi(&L, g, gm);
+      if ((rc = eval_qp(pb, &L, em, gm, U, q))) break;
+      for (int a = 0; a < q->nloc; ++a) R[q->A[a]] += res_term(pb, q, a);
+    }
+  }
+  for (int64_t A = 0; A < L.N; ++A)
+    if (is_dirichlet(pb, &L, A)) R[A] = U[A];
+  free(q);
+  lay_free(&L);
+  return rc;
+}
+
+static void jac_bc_rows(const orc_problem *pb, const layout *L, const int64_t *row_ptr,
+                        const int32_t *col_idx, double *vals, int64_t A, double *rowvals) {
+  int64_t base = row_ptr[A];
+  double *v = rowvals ? rowvals : vals + base;
+  if (is_dirichlet(pb, L, A)) {
+    for (int64_t k = base; k < row_ptr[A + 1]; ++k) v[k - base] = (col_idx[k] == A) ? 1.0 : 0.0;
+  } else {
+    for (int64_t k = base; k < row_ptr[A + 1]; ++k)
+      if (is_dirichlet(pb, L, col_idx[k])) v[k - base] = 0.0;
+  }
+}
+
+int orc_jacobian(const orc_problem *pb, const double *U, const int64_t *row_ptr,
+                 const int32_t *col_idx, double *vals) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  memset(vals, 0, sizeof(double) * row_ptr[L.N]);
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0;
+  for (int64_t e = 0; e < L.E && !rc; ++e) {
+    int em[3], gm[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqe && !rc; ++g) {
+      qp_multi(&L, g, gm);
+      if ((rc = eval_qp(pb, &L, em, gm, U, q))) break;
+      for (int a = 0; a < q->nloc; ++a)
+        for (int b = 0; b < q->nloc; ++b) {
+          int64_t k = csr_find(row_ptr, col_idx, q->A[a], q->A[b]);
+          if (k < 0) { rc = 3; break; }
+          vals[k] += jac_term(pb, q, a, b);
+        }
+    }
+  }
+  if (!rc)
+    for (int64_t A = 0; A < L.N; ++A) jac_bc_rows(pb, &L, row_ptr, col_idx, vals, A, NULL);
+  free(q);
+  lay_free(&L);
+  return rc;
+}
+
+/* elements of one axis whose span contains function i */
+static int elems_of_fn(const layout *L, int d, int i, int *out) {
+  int c = 0;
+  for (int e = 0; e < L->ne[d]; ++e) {
+    int s = L->span[d][e];
+    if (s - L->p[d] <= i && i <= s) out[c++] = e;
+  }
+  return c;
+}
+
+static int row_contrib(const orc_problem *pb, const layout *L, const double *U, int64_t A,
+                       int want_jac, const int64_t *row_ptr, const int32_t *col_idx,
+                       double *rowvals, double *rval) {
+  int64_t i[3] = {A % L->n[0], (A / L->n[0]) % L->n[1], A / ((int64_t)L->n[0] * L->n[1])};
+  int el[3][ORC_MAXP + 8], ce[3];
+  for (int d = 0; d < 3; ++d) {
+    if (d >= L->dim) { el[d][0] = 0; ce[d] = 1; continue; }
+    ce[d] = elems_of_fn(L, d, (int)i[d], el[d]);
+  }
+  int64_t len = want_jac ? row_ptr[A + 1] - row_ptr[A] : 0;
+  if (want_jac) memset(rowvals, 0, sizeof(double) * len);
+  double r = 0.0;
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int nqe = L->nq[0] * L->nq[1] * L->nq[2], rc = 0;
+  for (int c2 = 0; c2 < ce[2] && !rc; ++c2)
+    for (int c1 = 0; c1 < ce[1] && !rc; ++c1)
+      for (int c0 = 0; c0 < ce[0] && !rc; ++c0) {
+        int em[3] = {el[0][c0], el[1][c1], el[2][c2]}, gm[3];
+        for (int g = 0; g < nqe && !rc; ++g) {
+          qp_multi(L, g, gm);
+          if ((rc = eval_qp(pb, L, em, gm, U, q))) break;
+          int a = -1;
+          for (int k = 0; k < q->nloc; ++k)
+            if (q->A[k] == A) a = k;
+          if (a < 0) continue;
+          r += res_term(pb, q, a);
+          if (want_jac)
+            for (int b = 0; b < q->nloc; ++b) {
+              int64_t k = csr_find(row_ptr, col_idx, A, q->A[b]);
+              if (k < 0) { rc = 3; break; }
+              rowvals[k - row_ptr[A]] += jac_term(pb, q, a, b);
+            }
+        }
+      }
+  free(q);
+  if (rc) return rc;
+  if (want_jac) jac_bc_rows(pb, L, row_ptr, col_idx, NULL, A, rowvals);
+  if (rval) *rval = is_dirichlet(pb, L, A) ? U[A] : r;
+  return 0;
+}
+
+int orc_residual_rows(const orc_problem *pb, const double *U, const int64_t *rows, int64_t nrows,
+                      double *out) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  int rc = 0;
+  for (int64_t k = 0; k < nrows && !rc; ++k) {
+    if (rows[k] < 0 || rows[k] >= L.N) { rc = 1; break; }
+    rc = row_contrib(pb, &L, U, rows[k], 0, NULL, NULL, NULL, &out[k]);
+  }
+  lay_free(&L);
+  return rc;
+}
+
+int orc_jacobian_rows(const orc_problem *pb, const double *U, const int64_t *rows, int64_t nrows,
+                      const int64_t *row_ptr, const int32_t *col_idx, double *out) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  int rc = 0;
+  int64_t pos = 0;
+  for (int64_t k = 0; k < nrows && !rc; ++k) {
+    if (rows[k] < 0 || rows[k] >= L.N) { rc = 1; break; }
+    rc = row_contrib(pb, &L, U, rows[k], 1, row_ptr, col_idx, out + pos, NULL);
+    pos += row_ptr[rows[k] + 1] - row_ptr[rows[k]];
+  }
+  lay_free(&L);
+  return rc;
+}
+
+int orc_element_matrix(const orc_problem *pb, const double *U, int64_t elem, double *Ke, double *Re) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  if (elem < 0 || elem >= L.E) { lay_free(&L); return 1; }
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int em[3], gm[3], nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0;
+  int nloc = (L.p[0] + 1) * (L.p[1] + 1) * (L.p[2] + 1);
+  if (Ke) memset(Ke, 0, sizeof(double) * nloc * nloc);
+  if (Re) memset(Re, 0, sizeof(double) * nloc);
+  elem_multi(&L, elem, em);
+  for (int g = 0; g < nqe && !rc; ++g) {
+    qp_multi(&L, g, gm);
+    if ((rc = eval_qp(pb, &L, em, gm, U, q))) break;
+    for (int a = 0; a < nloc; ++a) {
+      if (Re) Re[a] += res_term(pb, q, a);
+      if (Ke)
+        for (int b = 0; b < nloc; ++b) Ke[a * nloc + b] += jac_term(pb, q, a, b);
+    }
+  }
+  free(q);
+  lay_free(&L);
+  return rc;
+}
+
+int orc_jacobian_elements(const orc_problem *pb, const double *U, const int64_t *elems, int64_t n,
+                          const int64_t *row_ptr, const int32_t *col_idx, double *vals) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0;
+  for (int64_t k = 0; k < n && !rc; ++k) {
+    int em[3], gm[3];
+    if (elems[k] < 0 || elems[k] >= L.E) { rc = 1; break; }
+    elem_multi(&L, elems[k], em);
+    for (int g = 0; g < nqe && !rc; ++g) {
+      qp_multi(&L, g, gm);
+      if ((rc = eval_qp(pb, &L, em, gm, U, q))) break;
+      for (int a = 0; a < q->nloc; ++a)
+        for (int b = 0; b < q->nloc; ++b) {
+          int64_t s = csr_find(row_ptr, col_idx, q->A[a], q->A[b]);
+          if (s < 0) { rc = 3; break; }
+          vals[s] += jac_term(pb, q, a, b);
+        }
+    }
+  }
+  free(q);
+  lay_free(&L);
+  return rc;
+}
+
+int orc_spmv(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const double *vals,
+             const double *x, double *y) {
+  for (int64_t A = 0; A < n; ++A) {
+    double s = 0.0;
+    for (int64_t k = row_ptr[A]; k < row_ptr[A + 1]; ++k) s += vals[k] * x[col_idx[k]];
+    y[A] = s;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Linear solvers for Newton: banded LU without pivoting (the Jacobian is symmetric      */
+/* positive definite on the lower solution branch) and Jacobi-preconditioned CG.          */
+/* ------------------------------------------------------------------------------------ */
+static int banded_solve(int64_t N, const int64_t *rp, const int32_t *ci, const double *v,
+                        const double *rhs, double *x) {
+  int64_t bw = 0;
+  for (int64_t A = 0; A < N; ++A)
+    for (int64_t k = rp[A]; k < rp[A + 1]; ++k) {
+      int64_t d = ci[k] - A;
+      if (d < 0) d = -d;
+      if (d > bw) bw = d;
+    }
+  int64_t W = 2 * bw + 1;
+  double *band = (double *)calloc((size_t)(N * W), sizeof(double));
+  if (!band) return 2;
+#define BAND(i, j) band[(i) * W + ((j) - (i) + bw)]
+  for (int64_t A = 0; A < N; ++A)
+    for (int64_t k = rp[A]; k < rp[A + 1]; ++k) BAND(A, (int64_t)ci[k]) = v[k];
+  for (int64_t k = 0; k < N; ++k) {
+    double piv = BAND(k, k);
+    if (piv == 0.0) { free(band); return 4; }
+    int64_t iend = k + bw < N - 1 ? k + bw : N - 1;
+    for (int64_t i = k + 1; i <= iend; ++i) {
+      double l = BAND(i, k) / piv;
+      if (l == 0.0) continue;
+      BAND(i, k) = l;
+      for (int64_t j = k + 1; j <= iend; ++j) BAND(i, j) -= l * BAND(k, j);
+    }
+  }
+  for (int64_t i = 0; i < N; ++i) {
+    double s = rhs[i];
+    int64_t j0 = i - bw > 0 ? i - bw : 0;
+    for (int64_t j = j0; j < i; ++j) s -= BAND(i, j) * x[j];
+    x[i] = s;
+  }
+  for (int64_t i = N - 1; i >= 0; --i) {
+    double s = x[i];
+    int64_t j1 = i + bw < N - 1 ? i + bw : N - 1;
+    for (int64_t j = i + 1; j <= j1; ++j) s -= BAND(i, j) * x[j];
+    x[i] = s / BAND(i, i);
+  }
+#undef BAND
+  free(band);
+  return 0;
+}
+
+static int cg_solve(int64_t N, const int64_t *rp, const int32_t *ci, const double *v,
+                    const double *b, double *x, double rtol, int maxit) {
+  double *r = (double *)malloc(sizeof(double) * N), *z = (double *)malloc(sizeof(double) * N);
+  double *p = (double *)malloc(sizeof(double) * N), *q = (double *)malloc(sizeof(double) * N);
+  double *dinv = (double *)malloc(sizeof(double) * N);
+  for (int64_t A = 0; A < N; ++A) {
+    double d = 1.0;
+    for (int64_t k = rp[A]; k < rp[A + 1]; ++k)
+      if (ci[k] == A) d = v[k];
+    dinv[A] = 1.0 / d;
+    x[A] = 0.0;
+    r[A] = b[A];
+  }
+  double bn = 0.0, rz = 0.0;
+  for (int64_t A = 0; A < N; ++A) {
+    z[A] = dinv[A] * r[A];
+    p[A] = z[A];
+    bn += b[A] * b[A];
+    rz += r[A] * z[A];
+  }
+  bn = sqrt(bn);
+  int rc = 4;
+  for (int it = 0; it < maxit; ++it) {
+    orc_spmv(N, rp, ci, v, p, q);
+    double pq = 0.0;
+    for (int64_t A = 0; A < N; ++A) pq += p[A] * q[A];
+    double al = rz / pq, rn = 0.0;
+    for (int64_t A = 0; A < N; ++A) {
+      x[A] += al * p[A];
+      r[A] -= al * q[A];
+      rn += r[A] * r[A];
+    }
+    if (sqrt(rn) <= rtol * bn) { rc = 0; break; }
+    double rz2 = 0.0;
+    for (int64_t A = 0; A < N; ++A) {
+      z[A] = dinv[A] * r[A];
+      rz2 += r[A] * z[A];
+    }
+    double be = rz2 / rz;
+    rz = rz2;
+    for (int64_t A = 0; A < N; ++A) p[A] = z[A] + be * p[A];
+  }
+  free(r); free(z); free(p); free(q); free(dinv);
+  return rc;
+}
+
+int orc_newton(const orc_problem *pb, double *U, double atol, double rtol, int maxit,
+               int linear_solver, double cg_rtol, double *hist, int *iters) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  int64_t N = L.N, nnz;
+  orc_sizes(pb, NULL, NULL, &nnz);
+  int64_t *rp = (int64_t *)malloc(sizeof(int64_t) * (N + 1));
+  int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * nnz);
+  double *v = (double *)malloc(sizeof(double) * nnz);
+  double *R = (double *)malloc(sizeof(double) * N), *d = (double *)malloc(sizeof(double) * N);
+  orc_csr_pattern(pb, rp, ci);
+  for (int64_t A = 0; A < N; ++A)
+    if (is_dirichlet(pb, &L, A)) U[A] = 0.0;
+  int rc = 4, k;
+  double r0 = -1.0;
+  for (k = 0; k <= maxit; ++k) {
+    if (orc_residual(pb, U, R)) { rc = 2; break; }
+    double nr = 0.0;
+    for (int64_t A = 0; A < N; ++A) nr += R[A] * R[A];
+    nr = sqrt(nr);
+    if (hist) hist[k] = nr;
+    if (r0 < 0) r0 = nr;
+    if (!(nr == nr)) { rc = 4; break; }
+    if (nr < atol || nr <= rtol * r0) { rc = 0; break; }
+    if (k == maxit) break;
+    if (orc_jacobian(pb, U, rp, ci, v)) { rc = 2; break; }
+    for (int64_t A = 0; A < N; ++A) R[A] = -R[A];
+    int ls = linear_solver;
+    if (ls == 0) ls = (pb->dim <= 2 && N <= 200000) ? 1 : 2;
+    int lrc = (ls == 1) ? banded_solve(N, rp, ci, v, R, d) : cg_solve(N, rp, ci, v, R, d, cg_rtol, 20000);
+    if (lrc) { rc = 5; break; }
+    for (int64_t A = 0; A < N; ++A) U[A] += d[A];
+  }
+  if (iters) *iters = k;
+  free(rp); free(ci); free(v); free(R); free(d);
+  lay_free(&L);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Quadrature-point data, load vectors and mass matrices (for convergence tests)         */
+/* ------------------------------------------------------------------------------------ */
+int64_t orc_nqp(const orc_problem *pb) {
+  layout L;
+  if (lay_init(pb, &L)) return -1;
+  int64_t n = L.E * L.nq[0] * L.nq[1] * L.nq[2];
+  lay_free(&L);
+  return n;
+}
+
+int orc_qp_data(const orc_problem *pb, const double *U, double *xq, double *Wq, double *uq,
+                double *gradu) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0, dim = pb->dim;
+  int64_t k = 0;
+  for (int64_t e = 0; e < L.E && !rc; ++e) {
+    int em[3], gm[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqe && !rc; ++g, ++k) {
+      qp_multi(&L, g, gm);
+      if ((rc = eval_qp(pb, &L, em, gm, U, q))) break;
+      for (int i = 0; i < dim; ++i) {
+        if (xq) xq[k * dim + i] = q->x[i];
+        if (gradu) gradu[k * dim + i] = q->gu[i];
+      }
+      if (Wq) Wq[k] = q->W;
+      if (uq) uq[k] = q->u;
+    }
+  }
+  free(q);
+  lay_free(&L);
+  return rc;
+}
+
+int orc_load_vector(const orc_problem *pb, const double *fq, double *b) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  memset(b, 0, sizeof(double) * L.N);
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0;
+  int64_t k = 0;
+  for (int64_t e = 0; e < L.E && !rc; ++e) {
+    int em[3], gm[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqe && !rc; ++g, ++k) {
+      qp_multi(&L, g, gm);
+      if ((rc = eval_qp(pb, &L, em, gm, NULL, q))) break;
+      for (int a = 0; a < q->nloc; ++a) b[q->A[a]] += q->W * q->N[a] * fq[k];
+    }
+  }
+  free(q);
+  lay_free(&L);
+  return rc;
+}
+
+int orc_mass_matrix(const orc_problem *pb, const int64_t *row_ptr, const int32_t *col_idx,
+                    double *vals) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  memset(vals, 0, sizeof(double) * row_ptr[L.N]);
+  qpoint *q = (qpoint *)malloc(sizeof(qpoint));
+  int nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0;
+  for (int64_t e = 0; e < L.E && !rc; ++e) {
+    int em[3], gm[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqe && !rc; ++g) {
+      qp_multi(&L, g, gm);
+      if ((rc = eval_qp(pb, &L, em, gm, NULL, q))) break;
+      for (int a = 0; a < q->nloc; ++a)
+        for (int b = 0; b < q->nloc; ++b) {
+          int64_t s = csr_find(row_ptr, col_idx, q->A[a], q->A[b]);
+          if (s < 0) { rc = 3; break; }
+          vals[s] += q->W * q->N[a] * q->N[b];
+        }
+    }
+  }
+  free(q);
+  lay_free(&L);
+  return rc;
+}

@@ -1,0 +1,70 @@
+/*
+ * Plain FP64 CPU oracle for tensor-product NURBS isogeometric assembly (Bratu-type
+ * problems -div(kappa grad u) = lambda exp(u) + f with u = 0 on chosen faces).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code, header, table or helper
+ * with the HIP library; it is written to be checked against the paper by eye:
+ *   - B-splines by the literal Cox-de Boor recursion (Sec. 2.1),
+ *   - tensor product and lexicographic numbering (Sec. 2.2),
+ *   - rational basis and its first derivatives (Sec. 2.3, eq:rational, eq:drational),
+ *   - geometry Jacobian, inverse and spatial gradients (App. A, eq:identity, eq:dspatial),
+ *   - the adjacency stencil of Algorithm 2 (Sec. 2.5),
+ *   - naive per-quadrature-point residual/Jacobian assembly as in Algorithm 3 (Sec. 2.7)
+ *     with the Bratu integrands eq:residual and eq:jacobian (Sec. 3.1),
+ *   - Newton's method with exact (direct banded or tight CG) linear solves.
+ * Every function returns 0 on success and a nonzero code on bad input.
+ */
+#ifndef IGA_ORACLE_H
+#define IGA_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int dim;                   /* 1, 2 or 3 */
+  int degree[3];
+  int nknots[3];
+  const double *knots[3];
+  const double *ctrl;        /* N*dim control points (natural order) or NULL: x = xi */
+  const double *weights;     /* N weights or NULL: non-rational */
+  int nquad[3];              /* 0 => degree+1 Gauss-Legendre points */
+  double lambda;
+  int kappa_mode;            /* 0: kappa = 1, 1: nodal N values, 2: one value per element */
+  const double *kappa;
+  const double *source;      /* N spline coefficients of f, or NULL */
+  unsigned dirichlet_mask;   /* bit 2*axis+side: u = 0 on that face */
+} orc_problem;
+
+int orc_gauss_legendre(int n, double *x, double *w);
+int orc_basis_1d(int p, const double *U, int nk, int i, double xi, double *val, double *der);
+int orc_stencil(int p, const double *U, int nk, int i, int *l, int *r);
+int orc_sizes(const orc_problem *pb, int64_t *ndof, int64_t *nelem, int64_t *nnz);
+int orc_csr_pattern(const orc_problem *pb, int64_t *row_ptr, int32_t *col_idx);
+int orc_residual(const orc_problem *pb, const double *U, double *R);
+int orc_jacobian(const orc_problem *pb, const double *U, const int64_t *row_ptr,
+                 const int32_t *col_idx, double *vals);
+int orc_residual_rows(const orc_problem *pb, const double *U, const int64_t *rows, int64_t nrows,
+                      double *out);
+int orc_jacobian_rows(const orc_problem *pb, const double *U, const int64_t *rows, int64_t nrows,
+                      const int64_t *row_ptr, const int32_t *col_idx, double *out);
+int orc_element_matrix(const orc_problem *pb, const double *U, int64_t elem, double *Ke, double *Re);
+int orc_jacobian_elements(const orc_problem *pb, const double *U, const int64_t *elems, int64_t n,
+                          const int64_t *row_ptr, const int32_t *col_idx, double *vals);
+int orc_spmv(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const double *vals,
+             const double *x, double *y);
+int orc_newton(const orc_problem *pb, double *U, double atol, double rtol, int maxit,
+               int linear_solver, double cg_rtol, double *hist, int *iters);
+int64_t orc_nqp(const orc_problem *pb);
+int orc_qp_data(const orc_problem *pb, const double *U, double *xq, double *Wq, double *uq,
+                double *gradu);
+int orc_load_vector(const orc_problem *pb, const double *fq, double *b);
+int orc_mass_matrix(const orc_problem *pb, const int64_t *row_ptr, const int32_t *col_idx,
+                    double *vals);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
