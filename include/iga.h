@@ -1,0 +1,149 @@
+/*
+ * iga.h -- C ABI of the MI355X (gfx950) isogeometric assembly and Newton-Krylov library.
+ *
+ * Problem class: tensor-product NURBS patches in 2D or 3D, scalar unknown u, Galerkin form of
+ *     -div(kappa grad u) = lambda exp(u) + f,   u = 0 on the faces selected by dirichlet_mask,
+ * i.e. the Bratu problem of the paper's Sec. 3 (eq:strong, eq:dirichlet) with its residual
+ * eq:residual and Jacobian eq:jacobian, generalised by a diffusion coefficient kappa and an
+ * optional source f.  The discretisation follows Sec. 2: B-spline bases from knot vectors
+ * (Sec. 2.1), tensor products with lexicographic numbering A = i0 + n0*(i1 + n1*i2) (Sec. 2.2),
+ * the rational basis of eq:rational, the geometry map and spatial gradients of App. A
+ * (eq:identity, eq:dspatial), Gauss-Legendre quadrature with p+1 points per axis (Sec. 2.9),
+ * the CSR pattern of Algorithm 2 (Sec. 2.5) and assembly as in Algorithm 3 (Sec. 2.7).
+ *
+ * Conventions for every call:
+ *  - Vectors are FP64, contiguous, in the natural (lexicographic) order, and are DEVICE
+ *    pointers owned by the caller.  Host arrays passed to iga_create are copied; the caller
+ *    may free them afterwards.
+ *  - Work is enqueued on the HIP stream given to iga_create and is asynchronous, except
+ *    iga_create, iga_info, iga_element_matrices and iga_newton_solve, which synchronise.
+ *  - Every call returns an iga_status; nothing is thrown and nothing is printed.  On failure
+ *    iga_last_error() returns a message for the calling thread.
+ *  - A handle must not be used from two threads at once.
+ */
+#ifndef IGA_H
+#define IGA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct iga_s *iga_t;
+
+typedef enum {
+  IGA_OK = 0,
+  IGA_EINVAL = 1,        /* invalid argument or problem description */
+  IGA_ENOMEM = 2,        /* device or host allocation failed */
+  IGA_EHIP = 3,          /* a HIP runtime call failed */
+  IGA_ENOCONV = 4,       /* Newton or Krylov did not converge (or produced NaN/Inf) */
+  IGA_EUNSUPPORTED = 5,  /* valid description outside what the GPU kernels implement */
+  IGA_ESTATE = 6         /* call not valid in the handle's current state */
+} iga_status;
+
+typedef enum { IGA_FP64 = 0, IGA_FP32 = 1, IGA_BF16 = 2 } iga_prec;
+
+typedef enum { IGA_KAPPA_ONE = 0, IGA_KAPPA_NODAL = 1, IGA_KAPPA_ELEMENT = 2 } iga_kappa_mode;
+
+/* Jacobian assembly algorithm (iga_set_option(IGA_OPT_JAC_ALGO)):
+ *   ROWGATHER: each workgroup owns a block of row pencils and sums element contributions
+ *              itself; every CSR value is written exactly once (no atomics, deterministic);
+ *   ATOMIC:    element matrices by sum factorisation, scattered with FP64 atomic adds;
+ *   COLOR:     element matrices scattered colour by colour ((p+1)^d colours, no atomics). */
+typedef enum { IGA_JAC_AUTO = 0, IGA_JAC_ROWGATHER = 1, IGA_JAC_ATOMIC = 2, IGA_JAC_COLOR = 3 } iga_jac_algo;
+
+typedef enum {
+  IGA_OPT_JAC_ALGO = 1,      /* iga_jac_algo */
+  IGA_OPT_ROW_BLOCK = 2,     /* row-gather pencil block: (b1 << 8) | b2, 0 = autotuned */
+  IGA_OPT_LAMBDA_BITS = 3    /* replace lambda: value is the IEEE-754 bit pattern of a double */
+} iga_option;
+
+typedef struct {
+  int dim;                       /* 2 or 3 */
+  int degree[3];                 /* p_d, 1..6; the GPU kernels require equal degrees */
+  int nknots[3];
+  const double *knots[3];        /* host; open (p+1 equal end knots), non-decreasing */
+  const double *ctrl;            /* host, N*dim control points, natural order; NULL: x = xi */
+  const double *weights;         /* host, N positive weights; NULL: non-rational */
+  int nquad[3];                  /* 0 or p+1 (Gauss-Legendre points per axis) */
+  double lambda;
+  int kappa_mode;                /* iga_kappa_mode */
+  const double *kappa;           /* host: N nodal values or E element values (natural order) */
+  const double *source;          /* host, N spline coefficients of f, or NULL */
+  unsigned dirichlet_mask;       /* bit 2*axis+side set: u = 0 on that face */
+} iga_desc;
+
+typedef struct {
+  double atol;                   /* stop when ||R||_2 < atol ... */
+  double rtol;                   /* ... or ||R||_2 <= rtol * ||R(U0)||_2 (0 disables) */
+  int max_newton;                /* Newton steps (<= 64) */
+  int max_krylov;                /* CG iterations per Newton step */
+  int matrix_free;               /* 0: assembled CSR Jacobian; 1: iga_apply inside CG */
+  int jac_prec;                  /* iga_prec of the Jacobian values (assembled mode) */
+  double forcing_max;            /* cap of the CG relative tolerance (Eisenstat-Walker); 0: 1e-2 */
+  int check_every;               /* CG iterations between convergence checks; 0: 16 */
+} iga_newton_opts;
+
+typedef struct {
+  int converged;                 /* 1 if the Newton stopping test was met */
+  int newton_iters;
+  int krylov_iters_total;
+  double res_norm0, res_norm;
+  double hist[65];               /* ||R|| before each Newton step and at the end */
+  int krylov_iters[64];
+  double t_total_ms, t_residual_ms, t_jacobian_ms, t_krylov_ms;
+} iga_newton_report;
+
+/* Create a handle: validates the description (open non-decreasing knots, degrees, sizes,
+ * positive weights, det J > 0 at every quadrature point), builds the quadrature rule, the 1D
+ * basis tables, the Algorithm 2 CSR pattern and the geometry data on the device.
+ * Errors: IGA_EINVAL (bad description), IGA_EUNSUPPORTED (unequal degrees, nquad != p+1,
+ * interior knot multiplicity > 1 for the row-gather path is handled by falling back to ATOMIC),
+ * IGA_ENOMEM, IGA_EHIP.  Synchronous.  hip_stream may be NULL (the null stream). */
+iga_status iga_create(const iga_desc *desc, void *hip_stream, iga_t *out);
+iga_status iga_destroy(iga_t h);
+iga_status iga_info(iga_t h, int64_t *ndof, int64_t *nnz, int64_t *nelem);
+iga_status iga_set_option(iga_t h, int key, int64_t value);
+
+/* Copy the CSR pattern (row_ptr: N+1 int64, col_idx: nnz int32, both caller-owned device
+ * buffers).  Columns of a row are ascending; row A holds the tensor product of the per-axis
+ * Algorithm 2 ranges [l_d(i_d), r_d(i_d)]. */
+iga_status iga_csr_pattern(iga_t h, int64_t *row_ptr_dev, int32_t *col_idx_dev);
+
+/* R = R(U) (eq:residual): Dirichlet rows hold R_A = U_A. */
+iga_status iga_assemble_residual(iga_t h, const double *U_dev, double *R_dev);
+
+/* vals = J(U) (eq:jacobian) on the iga_csr_pattern pattern; prec IGA_FP64 writes double,
+ * IGA_FP32 writes float (FP32 element contractions with FP32 accumulation).  Dirichlet rows
+ * are identity rows and Dirichlet columns of the other rows are zero (symmetric elimination).
+ * Every entry is written: no zeroing is needed. */
+iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, int prec);
+
+/* y = J(U) v without forming J (exact linearisation, same Dirichlet convention). */
+iga_status iga_apply(iga_t h, const double *U_dev, const double *v_dev, double *y_dev);
+
+/* y = A x for CSR values on the handle's pattern (prec IGA_FP64: double vals, IGA_FP32: float). */
+iga_status iga_spmv(iga_t h, const void *vals_dev, int prec, const double *x_dev, double *y_dev);
+
+/* Newton's method on R(U) = 0 starting from U (updated in place): each step assembles R and
+ * J (or uses iga_apply) and solves J d = -R by Jacobi-preconditioned CG with an
+ * Eisenstat-Walker forcing term; the residual is always FP64, so an FP32 Jacobian gives an
+ * FP64-accurate fixed point.  Returns IGA_ENOCONV when the test is not met or on NaN/Inf.
+ * opts may be NULL (defaults); report may be NULL.  Synchronous. */
+iga_status iga_newton_solve(iga_t h, double *U_dev, const iga_newton_opts *opts, iga_newton_report *report);
+
+/* Test hook: element matrices K_e (local order a = a0 + P*(a1 + P*a2), row-major K[a*nloc+b])
+ * of the listed elements (host int32 indices, natural element order), without Dirichlet
+ * conditions, computed by the GPU contraction kernels in precision prec; out_host receives
+ * n * nloc * nloc doubles.  Synchronous. */
+iga_status iga_element_matrices(iga_t h, const double *U_dev, const int32_t *elems_host, int n,
+                                int prec, double *out_host);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *iga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

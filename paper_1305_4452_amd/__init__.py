@@ -1,0 +1,280 @@
+"""MI355X isogeometric assembly and Newton-Krylov library: Python binding of libiga.so.
+
+The binding only marshals arguments: every step of assembly, apply and solve runs in the HIP
+kernels of libiga.so.  PyTorch supplies device memory and the stream.  Importing works without
+a GPU (so the ABI can be inspected), but every call that computes needs the built library and a
+GPU, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libiga.so")
+
+IGA_OK, IGA_EINVAL, IGA_ENOMEM, IGA_EHIP, IGA_ENOCONV, IGA_EUNSUPPORTED, IGA_ESTATE = range(7)
+IGA_FP64, IGA_FP32, IGA_BF16 = 0, 1, 2
+IGA_KAPPA_ONE, IGA_KAPPA_NODAL, IGA_KAPPA_ELEMENT = 0, 1, 2
+IGA_JAC_AUTO, IGA_JAC_ROWGATHER, IGA_JAC_ATOMIC, IGA_JAC_COLOR = 0, 1, 2, 3
+IGA_OPT_JAC_ALGO, IGA_OPT_ROW_BLOCK, IGA_OPT_LAMBDA_BITS = 1, 2, 3
+
+_STATUS = {0: "IGA_OK", 1: "IGA_EINVAL", 2: "IGA_ENOMEM", 3: "IGA_EHIP", 4: "IGA_ENOCONV",
+           5: "IGA_EUNSUPPORTED", 6: "IGA_ESTATE"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class iga_desc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("degree", C.c_int * 3),
+        ("nknots", C.c_int * 3),
+        ("knots", _dp * 3),
+        ("ctrl", _dp),
+        ("weights", _dp),
+        ("nquad", C.c_int * 3),
+        ("lam", C.c_double),
+        ("kappa_mode", C.c_int),
+        ("kappa", _dp),
+        ("source", _dp),
+        ("dirichlet_mask", C.c_uint),
+    ]
+
+
+class iga_newton_opts(C.Structure):
+    _fields_ = [
+        ("atol", C.c_double),
+        ("rtol", C.c_double),
+        ("max_newton", C.c_int),
+        ("max_krylov", C.c_int),
+        ("matrix_free", C.c_int),
+        ("jac_prec", C.c_int),
+        ("forcing_max", C.c_double),
+        ("check_every", C.c_int),
+    ]
+
+
+class iga_newton_report(C.Structure):
+    _fields_ = [
+        ("converged", C.c_int),
+        ("newton_iters", C.c_int),
+        ("krylov_iters_total", C.c_int),
+        ("res_norm0", C.c_double),
+        ("res_norm", C.c_double),
+        ("hist", C.c_double * 65),
+        ("krylov_iters", C.c_int * 64),
+        ("t_total_ms", C.c_double),
+        ("t_residual_ms", C.c_double),
+        ("t_jacobian_ms", C.c_double),
+        ("t_krylov_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        k = self.newton_iters
+        return dict(converged=bool(self.converged), newton_iters=k, krylov_iters_total=self.krylov_iters_total,
+                    res_norm0=self.res_norm0, res_norm=self.res_norm, hist=list(self.hist[:k + 1]),
+                    krylov_iters=list(self.krylov_iters[:k]), t_total_ms=self.t_total_ms,
+                    t_residual_ms=self.t_residual_ms, t_jacobian_ms=self.t_jacobian_ms,
+                    t_krylov_ms=self.t_krylov_ms)
+
+
+# name -> (argtypes, restype): mirrors include/iga.h
+_SIGNATURES = {
+    "iga_create": ([C.POINTER(iga_desc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "iga_destroy": ([C.c_void_p], C.c_int),
+    "iga_info": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+    "iga_set_option": ([C.c_void_p, C.c_int, C.c_int64], C.c_int),
+    "iga_csr_pattern": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "iga_assemble_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "iga_assemble_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "iga_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "iga_spmv": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
+    "iga_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_newton_report)],
+                         C.c_int),
+    "iga_element_matrices": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.c_int, _dp], C.c_int),
+    "iga_last_error": ([], C.c_char_p),
+}
+
+_lib = None
+
+
+class IGAError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load():
+    """Load libiga.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1305_4452_amd.build` first")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def _check(st, where):
+    if st != IGA_OK:
+        msg = load().iga_last_error()
+        raise IGAError(st, where, msg.decode() if msg else "")
+
+
+def _dev_ptr(t, dtype, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class IGA:
+    """One problem (handle) bound to the current torch stream at creation."""
+
+    def __init__(self, knots, degree, ctrl=None, weights=None, lam=1.0, kappa_mode=IGA_KAPPA_ONE, kappa=None,
+                 source=None, dirichlet_mask=None, stream=None):
+        import torch
+        L = load()
+        dim = len(knots)
+        self._keep = []
+
+        def arr(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            self._keep.append(a)
+            return a.ctypes.data_as(_dp)
+
+        d = iga_desc()
+        d.dim = dim
+        for a in range(dim):
+            d.degree[a] = int(degree[a])
+            k = np.ascontiguousarray(knots[a], dtype=np.float64)
+            self._keep.append(k)
+            d.nknots[a] = len(k)
+            d.knots[a] = k.ctypes.data_as(_dp)
+            d.nquad[a] = 0
+        d.ctrl = arr(ctrl)
+        d.weights = arr(weights)
+        d.lam = float(lam)
+        d.kappa_mode = int(kappa_mode)
+        d.kappa = arr(kappa)
+        d.source = arr(source)
+        d.dirichlet_mask = (1 << (2 * dim)) - 1 if dirichlet_mask is None else int(dirichlet_mask)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(L.iga_create(C.byref(d), C.c_void_p(stream.cuda_stream), C.byref(h)), "iga_create")
+        self.h = h
+        N, nnz, E = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(L.iga_info(h, C.byref(N), C.byref(nnz), C.byref(E)), "iga_info")
+        self.N, self.nnz, self.E = N.value, nnz.value, E.value
+        self.dim = dim
+        self.p = int(degree[0])
+        self._keep = []
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        p = w.patch
+        args = dict(lam=w.lam, kappa_mode=w.kappa_mode, kappa=w.kappa)
+        args.update(kw)
+        return cls(p.knots, p.degree, p.ctrl, p.weights, **args)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().iga_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- calls -----------------------------------------------------------------------------
+    def set_option(self, key, value):
+        _check(load().iga_set_option(self.h, int(key), int(value)), "iga_set_option")
+
+    def set_lambda(self, lam):
+        bits = int(np.array([lam], dtype=np.float64).view(np.int64)[0])
+        self.set_option(IGA_OPT_LAMBDA_BITS, bits)
+
+    def csr_pattern(self, row_ptr=None, col_idx=None):
+        import torch
+        if row_ptr is None:
+            row_ptr = torch.empty(self.N + 1, dtype=torch.int64, device="cuda")
+            col_idx = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        _check(load().iga_csr_pattern(self.h, _dev_ptr(row_ptr, torch.int64, self.N + 1, "row_ptr"),
+                                      _dev_ptr(col_idx, torch.int32, self.nnz, "col_idx")), "iga_csr_pattern")
+        return row_ptr, col_idx
+
+    def assemble_residual(self, U, R):
+        import torch
+        _check(load().iga_assemble_residual(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
+                                            _dev_ptr(R, torch.float64, self.N, "R")), "iga_assemble_residual")
+        return R
+
+    def assemble_jacobian(self, U, vals, prec=IGA_FP64):
+        import torch
+        vt = torch.float64 if prec == IGA_FP64 else torch.float32
+        _check(load().iga_assemble_jacobian(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
+                                            _dev_ptr(vals, vt, self.nnz, "vals"), int(prec)),
+               "iga_assemble_jacobian")
+        return vals
+
+    def apply(self, U, v, y):
+        import torch
+        _check(load().iga_apply(self.h, _dev_ptr(U, torch.float64, self.N, "U"), _dev_ptr(v, torch.float64, self.N, "v"),
+                                _dev_ptr(y, torch.float64, self.N, "y")), "iga_apply")
+        return y
+
+    def spmv(self, vals, x, y, prec=IGA_FP64):
+        import torch
+        vt = torch.float64 if prec == IGA_FP64 else torch.float32
+        _check(load().iga_spmv(self.h, _dev_ptr(vals, vt, self.nnz, "vals"), int(prec),
+                               _dev_ptr(x, torch.float64, self.N, "x"), _dev_ptr(y, torch.float64, self.N, "y")),
+               "iga_spmv")
+        return y
+
+    def newton_solve(self, U, atol=1e-10, rtol=0.0, max_newton=30, max_krylov=5000, matrix_free=False,
+                     jac_prec=IGA_FP64, forcing_max=1e-2, check_every=16, raise_on_fail=True):
+        import torch
+        o = iga_newton_opts(atol, rtol, max_newton, max_krylov, int(matrix_free), int(jac_prec), forcing_max,
+                            check_every)
+        rep = iga_newton_report()
+        st = load().iga_newton_solve(self.h, _dev_ptr(U, torch.float64, self.N, "U"), C.byref(o), C.byref(rep))
+        if raise_on_fail:
+            _check(st, "iga_newton_solve")
+        out = rep.as_dict()
+        out["status"] = st
+        return out
+
+    def element_matrices(self, U, elems, prec=IGA_FP64):
+        import torch
+        elems = np.ascontiguousarray(elems, dtype=np.int32)
+        nloc = (self.p + 1) ** self.dim
+        out = np.zeros((len(elems), nloc, nloc))
+        _check(load().iga_element_matrices(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
+                                           elems.ctypes.data_as(C.POINTER(C.c_int32)), len(elems), int(prec),
+                                           out.ctypes.data_as(_dp)), "iga_element_matrices")
+        return out

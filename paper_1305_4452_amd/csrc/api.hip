@@ -1,0 +1,286 @@
+// extern "C" entry points of libiga (declared in include/iga.h) and the Newton driver.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "iga_impl.h"
+
+namespace iga {
+iga_status create_impl(const iga_desc *d, void *stream, Handle **out);
+iga_status launch_norm(Handle &h, const double *x, double *out_dev);
+iga_status launch_diag_inv(Handle &h, const void *vals, int prec, double *dinv);
+iga_status launch_axpy(Handle &h, double a, const double *x, double *y);
+iga_status cg_solve(Handle &h, const double *R, double *d, double rtol, int maxit, int check_every,
+                    const void *vals, int prec, bool matrix_free, int *iters_out, double *rel_out);
+
+static iga_status alloc_owned(Handle &h, void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(IGA_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h.owned.push_back(*p);
+  return IGA_OK;
+}
+
+static void pick_block(const Handle &h, int prec, int *b1, int *b2) {
+  if (h.row_b1 > 0 && rowgather_supported(h, prec, h.row_b1, h.row_b2 > 0 ? h.row_b2 : 1)) {
+    *b1 = h.row_b1;
+    *b2 = h.row_b2 > 0 ? h.row_b2 : 1;
+    return;
+  }
+  if (h.pb.dim == 3) {
+    *b1 = 2;
+    *b2 = (h.pb.P <= 4) ? 2 : 1;
+    if (h.pb.table && h.pb.P >= 5) *b1 = 1;
+  } else {
+    *b1 = h.pb.n[1] >= 256 ? 8 : 4;
+    *b2 = 1;
+  }
+}
+
+static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int prec) {
+  int algo = h.jac_algo;
+  int b1 = 0, b2 = 0;
+  pick_block(h, prec, &b1, &b2);
+  if (algo == IGA_JAC_AUTO) algo = rowgather_supported(h, prec, b1, b2) ? IGA_JAC_ROWGATHER : IGA_JAC_ATOMIC;
+  if (algo == IGA_JAC_ROWGATHER) return launch_jac_rowgather(h, U, vals, prec, b1, b2);
+  if (algo == IGA_JAC_ATOMIC) return launch_jac_scatter(h, U, vals, prec, 0);
+  if (algo == IGA_JAC_COLOR) return launch_jac_scatter(h, U, vals, prec, 1);
+  return fail(IGA_EINVAL, "unknown Jacobian algorithm");
+}
+
+static iga_status ensure_newton_ws(Handle &h, bool need_vals, int prec) {
+  iga_status st;
+  const size_t N = (size_t)h.pb.N;
+  if (!h.nw && (st = alloc_owned(h, (void **)&h.nw, 6 * N * sizeof(double)))) return st;
+  if (!h.dinv && (st = alloc_owned(h, (void **)&h.dinv, N * sizeof(double)))) return st;
+  if (!h.scal && (st = alloc_owned(h, (void **)&h.scal, 1100 * sizeof(double)))) return st;
+  if (need_vals && (h.jvals == nullptr || h.jvals_prec != prec)) {
+    size_t bytes = (size_t)h.pb.nnz * (prec == IGA_FP32 ? 4 : 8);
+    if (h.jvals) {
+      for (auto &q : h.owned)
+        if (q == h.jvals) q = nullptr;
+      (void)hipFree(h.jvals);
+      h.jvals = nullptr;
+    }
+    if ((st = alloc_owned(h, &h.jvals, bytes))) return st;
+    h.jvals_prec = prec;
+  }
+  return IGA_OK;
+}
+
+static float ev_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0;
+  return ms;
+}
+
+static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_newton_report *rep) {
+  iga_newton_opts o{};
+  o.atol = 1e-10;
+  o.rtol = 0;
+  o.max_newton = 30;
+  o.max_krylov = 5000;
+  o.matrix_free = 0;
+  o.jac_prec = IGA_FP64;
+  o.forcing_max = 1e-2;
+  o.check_every = 16;
+  if (o_in) o = *o_in;
+  if (o.max_newton < 0 || o.max_newton > 64) return fail(IGA_EINVAL, "max_newton must be in 0..64");
+  if (o.max_krylov < 1) return fail(IGA_EINVAL, "max_krylov must be positive");
+  if (o.jac_prec != IGA_FP64 && o.jac_prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian precision");
+  if (o.forcing_max <= 0) o.forcing_max = 1e-2;
+  if (o.check_every <= 0) o.check_every = 16;
+  if (o.check_every > 1024) o.check_every = 1024;
+  iga_newton_report r{};
+  iga_status st = ensure_newton_ws(h, !o.matrix_free, o.jac_prec);
+  if (st) return st;
+  const int64_t N = h.pb.N;
+  double *R = h.nw, *dvec = h.nw + N;
+  auto t0 = std::chrono::steady_clock::now();
+  hipEvent_t ev[4];
+  for (auto &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(IGA_EHIP, "hipEventCreate");
+  double nr = 0, nr_prev = 0, r0 = -1, eta = o.forcing_max;
+  int k = 0;
+  st = IGA_OK;
+  for (k = 0;; ++k) {
+    hipEventRecord(ev[0], h.stream);
+    if ((st = launch_residual(h, U, R))) break;
+    if ((st = launch_norm(h, R, h.scal))) break;
+    if (hipMemcpyAsync(&nr, h.scal, sizeof(double), hipMemcpyDeviceToHost, h.stream) != hipSuccess ||
+        hipEventRecord(ev[1], h.stream) != hipSuccess || hipStreamSynchronize(h.stream) != hipSuccess) {
+      st = fail(IGA_EHIP, "residual norm");
+      break;
+    }
+    r.t_residual_ms += ev_ms(ev[0], ev[1]);
+    r.hist[k] = nr;
+    if (r0 < 0) r0 = nr;
+    if (!std::isfinite(nr)) { st = fail(IGA_ENOCONV, "residual is not finite"); break; }
+    if (nr < o.atol || (o.rtol > 0 && nr <= o.rtol * r0)) { r.converged = 1; break; }
+    if (k >= o.max_newton) { st = fail(IGA_ENOCONV, "Newton did not converge"); break; }
+    // forcing term (Eisenstat-Walker, second choice) with a floor that avoids over-solving
+    if (k > 0) {
+      double ratio = nr / nr_prev;
+      eta = fmin(o.forcing_max, 0.9 * ratio * ratio);
+    }
+    double target = fmax(o.atol, o.rtol * r0);
+    eta = fmax(eta, 0.1 * target / nr);
+    eta = fmin(eta, o.forcing_max);
+    nr_prev = nr;
+    hipEventRecord(ev[0], h.stream);
+    if (o.matrix_free) {
+      if ((st = launch_linearize(h, U)) || (st = launch_diag_mf(h, h.dinv))) break;
+    } else {
+      if ((st = assemble_jacobian(h, U, h.jvals, o.jac_prec))) break;
+      if ((st = launch_diag_inv(h, h.jvals, o.jac_prec, h.dinv))) break;
+    }
+    hipEventRecord(ev[1], h.stream);
+    int its = 0;
+    double rel = 0;
+    if ((st = cg_solve(h, R, dvec, eta, o.max_krylov, o.check_every, h.jvals, o.jac_prec, o.matrix_free != 0, &its,
+                       &rel)))
+      break;
+    hipEventRecord(ev[2], h.stream);
+    if ((st = launch_axpy(h, 1.0, dvec, U))) break;
+    if (hipStreamSynchronize(h.stream) != hipSuccess) { st = fail(IGA_EHIP, "sync"); break; }
+    r.t_jacobian_ms += ev_ms(ev[0], ev[1]);
+    r.t_krylov_ms += ev_ms(ev[1], ev[2]);
+    r.krylov_iters[k] = its;
+    r.krylov_iters_total += its;
+  }
+  for (auto &e : ev) hipEventDestroy(e);
+  r.newton_iters = k;
+  r.res_norm0 = r0;
+  r.res_norm = nr;
+  r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = r;
+  return st;
+}
+
+}  // namespace iga
+
+using namespace iga;
+
+extern "C" {
+
+iga_status iga_create(const iga_desc *desc, void *hip_stream, iga_t *out) {
+  if (!out) return fail(IGA_EINVAL, "null output handle");
+  *out = nullptr;
+  Handle *h = nullptr;
+  iga_status st = create_impl(desc, hip_stream, &h);
+  if (st) return st;
+  *out = (iga_t)h;
+  set_error("");
+  return IGA_OK;
+}
+
+iga_status iga_destroy(iga_t hh) {
+  if (!hh) return IGA_OK;
+  Handle *h = (Handle *)hh;
+  hipStreamSynchronize(h->stream);
+  for (void *p : h->owned)
+    if (p) hipFree(p);
+  delete h;
+  return IGA_OK;
+}
+
+iga_status iga_info(iga_t hh, int64_t *ndof, int64_t *nnz, int64_t *nelem) {
+  if (!hh) return fail(IGA_EINVAL, "null handle");
+  Handle *h = (Handle *)hh;
+  if (ndof) *ndof = h->pb.N;
+  if (nnz) *nnz = h->pb.nnz;
+  if (nelem) *nelem = h->pb.E;
+  return IGA_OK;
+}
+
+iga_status iga_set_option(iga_t hh, int key, int64_t value) {
+  if (!hh) return fail(IGA_EINVAL, "null handle");
+  Handle *h = (Handle *)hh;
+  switch (key) {
+    case IGA_OPT_JAC_ALGO:
+      if (value < IGA_JAC_AUTO || value > IGA_JAC_COLOR) return fail(IGA_EINVAL, "bad Jacobian algorithm");
+      h->jac_algo = (int)value;
+      return IGA_OK;
+    case IGA_OPT_ROW_BLOCK:
+      h->row_b1 = (int)((value >> 8) & 0xff);
+      h->row_b2 = (int)(value & 0xff);
+      return IGA_OK;
+    case IGA_OPT_LAMBDA_BITS: {
+      double lam;
+      std::memcpy(&lam, &value, sizeof(double));
+      if (!std::isfinite(lam)) return fail(IGA_EINVAL, "lambda must be finite");
+      h->pb.lambda = lam;
+      return IGA_OK;
+    }
+  }
+  return fail(IGA_EINVAL, "unknown option");
+}
+
+iga_status iga_csr_pattern(iga_t hh, int64_t *row_ptr_dev, int32_t *col_idx_dev) {
+  if (!hh || !row_ptr_dev || !col_idx_dev) return fail(IGA_EINVAL, "null argument");
+  Handle *h = (Handle *)hh;
+  IGA_HIP_CHECK(hipMemcpyAsync(row_ptr_dev, h->row_ptr, sizeof(int64_t) * (h->pb.N + 1), hipMemcpyDeviceToDevice,
+                               h->stream));
+  IGA_HIP_CHECK(hipMemcpyAsync(col_idx_dev, h->col_idx, sizeof(int32_t) * h->pb.nnz, hipMemcpyDeviceToDevice,
+                               h->stream));
+  return IGA_OK;
+}
+
+iga_status iga_assemble_residual(iga_t hh, const double *U, double *R) {
+  if (!hh || !U || !R) return fail(IGA_EINVAL, "null argument");
+  return launch_residual(*(Handle *)hh, U, R);
+}
+
+iga_status iga_assemble_jacobian(iga_t hh, const double *U, void *vals, int prec) {
+  if (!hh || !U || !vals) return fail(IGA_EINVAL, "null argument");
+  if (prec != IGA_FP64 && prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian values are FP64 or FP32");
+  return assemble_jacobian(*(Handle *)hh, U, vals, prec);
+}
+
+iga_status iga_apply(iga_t hh, const double *U, const double *v, double *y) {
+  if (!hh || !U || !v || !y) return fail(IGA_EINVAL, "null argument");
+  Handle &h = *(Handle *)hh;
+  iga_status st = launch_linearize(h, U);
+  if (st) return st;
+  return launch_apply(h, v, y);
+}
+
+iga_status iga_spmv(iga_t hh, const void *vals, int prec, const double *x, double *y) {
+  if (!hh || !vals || !x || !y) return fail(IGA_EINVAL, "null argument");
+  if (prec != IGA_FP64 && prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "values are FP64 or FP32");
+  Handle &h = *(Handle *)hh;
+  return launch_spmv(h, vals, prec, x, y, nullptr, h.npartials);
+}
+
+iga_status iga_newton_solve(iga_t hh, double *U, const iga_newton_opts *opts, iga_newton_report *report) {
+  if (!hh || !U) return fail(IGA_EINVAL, "null argument");
+  return newton(*(Handle *)hh, U, opts, report);
+}
+
+iga_status iga_element_matrices(iga_t hh, const double *U, const int32_t *elems, int n, int prec, double *out) {
+  if (!hh || !U || !elems || !out || n < 0) return fail(IGA_EINVAL, "bad argument");
+  if (prec != IGA_FP64 && prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "element matrices in FP64 or FP32");
+  Handle &h = *(Handle *)hh;
+  if (n == 0) return IGA_OK;
+  for (int i = 0; i < n; ++i)
+    if (elems[i] < 0 || elems[i] >= h.pb.E) return fail(IGA_EINVAL, "element index out of range");
+  const int L = ipow(h.pb.P, h.pb.dim);
+  int32_t *d_el = nullptr;
+  double *d_out = nullptr;
+  IGA_HIP_CHECK(hipMalloc(&d_el, sizeof(int32_t) * n));
+  if (hipMalloc(&d_out, sizeof(double) * (size_t)n * L * L) != hipSuccess) {
+    hipFree(d_el);
+    return fail(IGA_ENOMEM, "element matrix buffer");
+  }
+  iga_status st = IGA_OK;
+  if (hipMemcpyAsync(d_el, elems, sizeof(int32_t) * n, hipMemcpyHostToDevice, h.stream) != hipSuccess)
+    st = fail(IGA_EHIP, "copy");
+  if (!st) st = launch_elem_matrices(h, U, d_el, n, prec, d_out);
+  if (!st && hipMemcpyAsync(out, d_out, sizeof(double) * (size_t)n * L * L, hipMemcpyDeviceToHost, h.stream) != hipSuccess)
+    st = fail(IGA_EHIP, "copy back");
+  if (!st && hipStreamSynchronize(h.stream) != hipSuccess) st = fail(IGA_EHIP, "sync");
+  hipFree(d_el);
+  hipFree(d_out);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal definitions shared by the HIP translation units of libiga (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "iga.h"
+
+namespace iga {
+
+constexpr int kMaxP = 7;       // functions per element per axis (degree <= 6)
+constexpr int kWave = 64;      // CDNA wavefront
+
+// Number of per-quadrature-point geometry streams of the table mode.
+//  3D: D'00 D'11 D'22 D'01 D'02 D'12 | g0 g1 g2 | W/w | 1/w     (11)
+//  2D: D'00 D'11 D'01 | g0 g1 | W/w | 1/w                      (7)
+// D' = kappa * W * Jinv Jinv^T / w^2 (parametric-gradient metric with the weight w of the
+// rational basis divided out twice), g = grad_xi(w) / w, W = quadrature weight * det J.
+__host__ __device__ constexpr int geo_streams(int dim) { return dim == 3 ? 11 : 7; }
+
+struct AxisDev {
+  const double *B;     // [ne][Q][P]   B-spline values at the Gauss points of each element
+  const double *dB;    // [ne][Q][P]   d/dxi
+  const double *wq;    // [ne][Q]      Gauss weight * (xi_{s+1} - xi_s) / 2
+  const int *efirst;   // [ne]         index of the first non-zero function of each element
+  const int *stl;      // [n]          Algorithm 2 left index
+  const int *stw;      // [n]          Algorithm 2 width r - l + 1
+};
+
+// Plain-old-data view of a problem passed by value to kernels.
+struct DevProblem {
+  int dim, p, P, Q;
+  int n[3], ne[3];
+  int64_t N, E, nnz;
+  AxisDev ax[3];
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  double lambda;
+  int table;           // 0: identity geometry, kappa one/element (analytic metric); 1: geo table
+  int rational;        // weights present
+  int kappa_mode;
+  const double *kel;   // element kappa (analytic mode, kappa_mode ELEMENT)
+  const double *geo;   // table mode: [E][geo_streams][Q^dim]
+  const double *wts;   // [N] or null
+  const double *src;   // [N] or null
+  unsigned dmask;
+  int simple_knots;    // every element's first function equals its span counter (max continuity)
+};
+
+__host__ __device__ inline int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+__device__ inline bool is_dirichlet_idx(const DevProblem &pb, int i0, int i1, int i2) {
+  unsigned m = pb.dmask;
+  if (((m >> 0) & 1u) && i0 == 0) return true;
+  if (((m >> 1) & 1u) && i0 == pb.n[0] - 1) return true;
+  if (((m >> 2) & 1u) && i1 == 0) return true;
+  if (((m >> 3) & 1u) && i1 == pb.n[1] - 1) return true;
+  if (pb.dim == 3) {
+    if (((m >> 4) & 1u) && i2 == 0) return true;
+    if (((m >> 5) & 1u) && i2 == pb.n[2] - 1) return true;
+  }
+  return false;
+}
+
+__device__ inline bool is_dirichlet(const DevProblem &pb, int64_t A) {
+  int i0 = (int)(A % pb.n[0]);
+  int64_t r = A / pb.n[0];
+  int i1 = (int)(r % pb.n[1]);
+  int i2 = (int)(r / pb.n[1]);
+  return is_dirichlet_idx(pb, i0, i1, i2);
+}
+
+// Offset of column (j0,j1,j2) inside row (i0,i1,i2): the row holds the tensor product of the
+// per-axis stencils, ordered with axis 0 fastest, so no search is needed.
+__device__ inline int64_t csr_slot(const DevProblem &pb, int i0, int i1, int i2, int j0, int j1, int j2) {
+  int64_t A = i0 + (int64_t)pb.n[0] * (i1 + (int64_t)pb.n[1] * i2);
+  int w0 = pb.ax[0].stw[i0], w1 = pb.ax[1].stw[i1];
+  int o0 = j0 - pb.ax[0].stl[i0], o1 = j1 - pb.ax[1].stl[i1];
+  int o2 = pb.dim == 3 ? j2 - pb.ax[2].stl[i2] : 0;
+  return pb.row_ptr[A] + ((int64_t)o2 * w1 + o1) * w0 + o0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Host-side handle
+// ------------------------------------------------------------------------------------------
+struct Handle {
+  DevProblem pb{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // owned device buffers
+  std::vector<void *> owned;
+  int64_t *row_ptr = nullptr;
+  int32_t *col_idx = nullptr;
+  double *geo = nullptr;
+  double *lin = nullptr;          // [E][Q^d] per-point linearisation coefficient (m'')
+  double *partials = nullptr;     // reduction scratch
+  int npartials = 0;
+  // Newton workspace (lazily allocated)
+  double *nw = nullptr;           // 6 * N doubles: R, d, r, z, p, q
+  double *dinv = nullptr;
+  double *scal = nullptr;         // device scalars
+  void *jvals = nullptr;          // Jacobian values owned by Newton
+  int jvals_prec = -1;
+  // options
+  int jac_algo = IGA_JAC_AUTO;
+  int row_b1 = 0, row_b2 = 0;
+  // host copies
+  std::vector<double> hknots[3];
+  int nb_colors = 0;
+};
+
+// Error reporting (thread-local message)
+void set_error(const std::string &msg);
+iga_status fail(iga_status st, const std::string &msg);
+
+#define IGA_HIP_CHECK(expr)                                                          \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess)                                                            \
+      return ::iga::fail(IGA_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// Launchers implemented in the kernel translation units.
+iga_status launch_geometry(Handle &h, const double *ctrl, const double *wts, const double *kappa_nodal,
+                           int *bad_det);
+iga_status launch_pattern(Handle &h);
+iga_status launch_residual(Handle &h, const double *U, double *R);
+iga_status launch_linearize(Handle &h, const double *U);
+iga_status launch_apply(Handle &h, const double *v, double *y);
+iga_status launch_diag_mf(Handle &h, double *diag);
+iga_status launch_elem_matrices(Handle &h, const double *U, const int32_t *elems, int n, int prec,
+                                double *out);
+iga_status launch_jac_scatter(Handle &h, const double *U, void *vals, int prec, int color_mode);
+iga_status launch_jac_rowgather(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
+bool rowgather_supported(const Handle &h, int prec, int b1, int b2);
+iga_status launch_spmv(Handle &h, const void *vals, int prec, const double *x, double *y,
+                       double *partial_dot, int npart);
+iga_status launch_fill(Handle &h, double *x, int64_t n, double v);
+
+}  // namespace iga

@@ -1,0 +1,295 @@
+// Krylov building blocks: CSR SpMV (FP64 or FP32 values, FP64 vectors and accumulation) and
+// Jacobi-preconditioned conjugate gradients whose scalars never leave the device.  Dot products
+// are block partial sums reduced redundantly, in a fixed order, by every block of the consumer
+// kernel, so all blocks see bitwise-identical alpha and beta and the solve is reproducible.
+#include "iga_impl.h"
+
+namespace iga {
+
+constexpr int kVecThreads = 256;
+
+__device__ inline double warp_sum(double v, int width) {
+  for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+  return v;
+}
+
+// block-wide sum; all threads get the result
+__device__ inline double block_sum(double v, double *sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = warp_sum(v, 64);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// sum of n partials, identical in every block
+__device__ inline double reduce_partials(const double *__restrict__ part, int n, double *sh) {
+  double v = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  return block_sum(v, sh);
+}
+
+// y = A x (+ optional partial sums of x.y per block).  LPR lanes cooperate on one row.
+template <typename VT, int LPR>
+__global__ void __launch_bounds__(256) k_spmv(int64_t N, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                              const VT *__restrict__ vals, const double *__restrict__ x,
+                                              double *__restrict__ y, double *__restrict__ part) {
+  __shared__ double sh[8];
+  const int sub = threadIdx.x % LPR;
+  const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LPR;
+  const int64_t ngrp = (gridDim.x * (int64_t)blockDim.x) / LPR;
+  double dot = 0;
+  for (int64_t A = grp; A < N; A += ngrp) {
+    double s = 0;
+    const int64_t b = rp[A], e = rp[A + 1];
+    for (int64_t k = b + sub; k < e; k += LPR) s += (double)vals[k] * x[ci[k]];
+    s = warp_sum(s, LPR);
+    if (sub == 0) {
+      y[A] = s;
+      dot += s * x[A];
+    }
+  }
+  if (part) {
+    double bs = block_sum(dot, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t N, const double *__restrict__ a, const double *__restrict__ b,
+                                                     double *__restrict__ part) {
+  __shared__ double sh[8];
+  double s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x)
+    s += a[i] * b[i];
+  double bs = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_to(const double *__restrict__ part, int n, double *__restrict__ out,
+                                                   int do_sqrt) {
+  __shared__ double sh[8];
+  double s = reduce_partials(part, n, sh);
+  if (threadIdx.x == 0) *out = do_sqrt ? sqrt(s) : s;
+}
+
+// x = 0, r = -R, z = Dinv r, p = z; partial r.z
+__global__ void __launch_bounds__(256) k_cg_init(int64_t N, const double *__restrict__ R, const double *__restrict__ dinv,
+                                                 double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
+                                                 double *__restrict__ p, double *__restrict__ part_rz) {
+  __shared__ double sh[8];
+  double s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x) {
+    double ri = -R[i], zi = dinv[i] * ri;
+    x[i] = 0;
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    s += ri * zi;
+  }
+  double bs = block_sum(s, sh);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = bs;
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; z = Dinv r; partials of r.z (new) and r.r
+__global__ void __launch_bounds__(256) k_cg_xr(int64_t N, const double *__restrict__ part_rz, int n_rz,
+                                               const double *__restrict__ part_pq, int n_pq, double *__restrict__ x,
+                                               double *__restrict__ r, double *__restrict__ z, const double *__restrict__ p,
+                                               const double *__restrict__ q, const double *__restrict__ dinv,
+                                               double *__restrict__ part_rz_new, double *__restrict__ part_rr) {
+  __shared__ double sh[8];
+  const double rz = reduce_partials(part_rz, n_rz, sh);
+  const double pq = reduce_partials(part_pq, n_pq, sh);
+  const double alpha = (pq != 0.0) ? rz / pq : 0.0;
+  double s1 = 0, s2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x) {
+    x[i] += alpha * p[i];
+    double ri = r[i] - alpha * q[i];
+    double zi = dinv[i] * ri;
+    r[i] = ri;
+    z[i] = zi;
+    s1 += ri * zi;
+    s2 += ri * ri;
+  }
+  double b1 = block_sum(s1, sh);
+  double b2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    part_rz_new[blockIdx.x] = b1;
+    part_rr[blockIdx.x] = b2;
+  }
+}
+
+// beta = rz_new / rz; p = z + beta p; block 0 records ||r|| for the host's convergence check
+__global__ void __launch_bounds__(256) k_cg_p(int64_t N, const double *__restrict__ part_rz, const double *__restrict__ part_rz_new,
+                                              const double *__restrict__ part_rr, int n, const double *__restrict__ z,
+                                              double *__restrict__ p, double *__restrict__ rnorm_out) {
+  __shared__ double sh[8];
+  const double rz = reduce_partials(part_rz, n, sh);
+  const double rzn = reduce_partials(part_rz_new, n, sh);
+  const double beta = (rz != 0.0) ? rzn / rz : 0.0;
+  if (blockIdx.x == 0) {
+    double rr = reduce_partials(part_rr, n, sh);
+    if (threadIdx.x == 0) *rnorm_out = sqrt(rr);
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_axpy(int64_t N, double a, const double *__restrict__ x, double *__restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x)
+    y[i] += a * x[i];
+}
+
+template <typename VT>
+__global__ void k_diag_inv(DevProblem pb, const VT *__restrict__ vals, double *__restrict__ dinv) {
+  int64_t A = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (A >= pb.N) return;
+  int i0 = (int)(A % pb.n[0]);
+  int64_t r = A / pb.n[0];
+  int i1 = (int)(r % pb.n[1]);
+  int i2 = (int)(r / pb.n[1]);
+  double d = (double)vals[csr_slot(pb, i0, i1, i2, i0, i1, i2)];
+  dinv[A] = (d != 0.0) ? 1.0 / d : 1.0;
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+int vec_blocks(int64_t N, int maxb) {
+  int64_t b = (N + kVecThreads - 1) / kVecThreads;
+  if (b > maxb) b = maxb;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+iga_status launch_spmv(Handle &h, const void *vals, int prec, const double *x, double *y, double *partial_dot,
+                       int npart) {
+  const int64_t N = h.pb.N;
+  const int lpr = h.pb.dim == 3 ? 64 : 16;
+  int64_t want = (N * lpr + 255) / 256;
+  int blocks = (int)(want < npart ? want : npart);
+  if (blocks < 1) blocks = 1;
+  if (prec == IGA_FP32) {
+    if (lpr == 64)
+      hipLaunchKernelGGL((k_spmv<float, 64>), dim3(blocks), dim3(256), 0, h.stream, N, h.row_ptr, h.col_idx,
+                         (const float *)vals, x, y, partial_dot);
+    else
+      hipLaunchKernelGGL((k_spmv<float, 16>), dim3(blocks), dim3(256), 0, h.stream, N, h.row_ptr, h.col_idx,
+                         (const float *)vals, x, y, partial_dot);
+  } else {
+    if (lpr == 64)
+      hipLaunchKernelGGL((k_spmv<double, 64>), dim3(blocks), dim3(256), 0, h.stream, N, h.row_ptr, h.col_idx,
+                         (const double *)vals, x, y, partial_dot);
+    else
+      hipLaunchKernelGGL((k_spmv<double, 16>), dim3(blocks), dim3(256), 0, h.stream, N, h.row_ptr, h.col_idx,
+                         (const double *)vals, x, y, partial_dot);
+  }
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+int spmv_blocks(const Handle &h, int npart) {
+  const int lpr = h.pb.dim == 3 ? 64 : 16;
+  int64_t want = (h.pb.N * lpr + 255) / 256;
+  int blocks = (int)(want < npart ? want : npart);
+  return blocks < 1 ? 1 : blocks;
+}
+
+iga_status launch_norm(Handle &h, const double *x, double *out_dev) {
+  const int nb = vec_blocks(h.pb.N, h.npartials);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, h.stream, h.pb.N, x, x, h.partials);
+  hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(256), 0, h.stream, (const double *)h.partials, nb, out_dev, 1);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+iga_status launch_diag_inv(Handle &h, const void *vals, int prec, double *dinv) {
+  unsigned nb = (unsigned)((h.pb.N + 255) / 256);
+  if (prec == IGA_FP32)
+    hipLaunchKernelGGL(k_diag_inv<float>, dim3(nb), dim3(256), 0, h.stream, h.pb, (const float *)vals, dinv);
+  else
+    hipLaunchKernelGGL(k_diag_inv<double>, dim3(nb), dim3(256), 0, h.stream, h.pb, (const double *)vals, dinv);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+iga_status launch_axpy(Handle &h, double a, const double *x, double *y) {
+  const int nb = vec_blocks(h.pb.N, 2048);
+  hipLaunchKernelGGL(k_axpy, dim3(nb), dim3(256), 0, h.stream, h.pb.N, a, x, y);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+// CG on J d = -R.  `matvec` is either the assembled SpMV or the matrix-free apply.  The
+// partial-sum buffers rotate so that a consumer never reads a buffer the same launch writes.
+iga_status cg_solve(Handle &h, const double *R, double *d, double rtol, int maxit, int check_every,
+                    const void *vals, int prec, bool matrix_free, int *iters_out, double *rnorm_dev_hist) {
+  const int64_t N = h.pb.N;
+  double *ws = h.nw;            // [R d r z p q] each N
+  double *r = ws + 2 * N, *z = ws + 3 * N, *p = ws + 4 * N, *q = ws + 5 * N;
+  const int nb = vec_blocks(N, h.npartials);
+  double *P0 = h.partials, *P1 = h.partials + h.npartials, *P2 = h.partials + 2 * h.npartials,
+         *P3 = h.partials + 3 * h.npartials;
+  hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(256), 0, h.stream, N, R, h.dinv, d, r, z, p, P0);
+  // ||b|| for the relative test
+  double *sc = h.scal;
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, h.stream, N, R, R, P3);
+  hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(256), 0, h.stream, (const double *)P3, nb, sc, 1);
+  IGA_HIP_CHECK(hipGetLastError());
+  double bnorm = 0;
+  IGA_HIP_CHECK(hipMemcpyAsync(&bnorm, sc, sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  IGA_HIP_CHECK(hipStreamSynchronize(h.stream));
+  if (!(bnorm > 0)) {
+    *iters_out = 0;
+    return IGA_OK;
+  }
+  const double target = rtol * bnorm;
+  double *rz_cur = P0, *rz_new = P1;
+  const int nbs = matrix_free ? nb : spmv_blocks(h, h.npartials);
+  int it = 0;
+  iga_status st;
+  std::vector<double> hist(check_every > 0 ? check_every : 16);
+  const int ce = check_every > 0 ? check_every : 16;
+  while (it < maxit) {
+    int chunk = (maxit - it < ce) ? maxit - it : ce;
+    for (int k = 0; k < chunk; ++k) {
+      // q = J p, partial p.q into P2
+      if (matrix_free) {
+        if ((st = launch_apply(h, p, q))) return st;
+        hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, h.stream, N, (const double *)p, (const double *)q, P2);
+      } else {
+        if ((st = launch_spmv(h, vals, prec, p, q, P2, h.npartials))) return st;
+      }
+      hipLaunchKernelGGL(k_cg_xr, dim3(nb), dim3(256), 0, h.stream, N, (const double *)rz_cur, nb, (const double *)P2,
+                         nbs, d, r, z, (const double *)p, (const double *)q, (const double *)h.dinv, rz_new, P3);
+      hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(256), 0, h.stream, N, (const double *)rz_cur, (const double *)rz_new,
+                         (const double *)P3, nb, (const double *)z, p, sc + 1 + k);
+      double *tmp = rz_cur;
+      rz_cur = rz_new;
+      rz_new = tmp;
+    }
+    IGA_HIP_CHECK(hipGetLastError());
+    IGA_HIP_CHECK(hipMemcpyAsync(hist.data(), sc + 1, sizeof(double) * chunk, hipMemcpyDeviceToHost, h.stream));
+    IGA_HIP_CHECK(hipStreamSynchronize(h.stream));
+    int done = -1;
+    for (int k = 0; k < chunk; ++k) {
+      if (!(hist[k] == hist[k])) { *iters_out = it + k + 1; return fail(IGA_ENOCONV, "CG produced NaN"); }
+      if (done < 0 && hist[k] <= target) done = k;
+    }
+    if (done >= 0) {
+      it += chunk;   // the extra iterations of the chunk only reduce the error further
+      *iters_out = it;
+      if (rnorm_dev_hist) *rnorm_dev_hist = hist[chunk - 1] / bnorm;
+      return IGA_OK;
+    }
+    it += chunk;
+  }
+  *iters_out = it;
+  if (rnorm_dev_hist) *rnorm_dev_hist = hist[0] / bnorm;
+  return IGA_OK;   // inexact Newton tolerates an unconverged inner solve
+}
+
+}  // namespace iga

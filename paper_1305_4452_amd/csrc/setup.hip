@@ -1,0 +1,407 @@
+// Problem set-up: validation, Gauss-Legendre rule, 1D B-spline tables at the Gauss points of
+// every element, the Algorithm 2 adjacency pattern and the per-point geometry table.
+#include <cmath>
+#include <cstring>
+
+#include "iga_impl.h"
+
+namespace iga {
+
+// ------------------------------------------------------------------------------------------
+// Gauss-Legendre nodes/weights on [-1,1] (Sec. 2.9 uses tensor Gauss-Legendre rules):
+// Newton's method on P_n in extended precision, started from Tricomi's asymptotic estimate.
+// ------------------------------------------------------------------------------------------
+static void gauss_legendre(int n, double *x, double *w) {
+  for (int k = 1; k <= n; ++k) {
+    long double th = M_PI * (4.0L * k - 1.0L) / (4.0L * n + 2.0L);
+    long double z = (1.0L - (n - 1.0L) / (8.0L * n * n * n)) * cosl(th);
+    long double dp = 1.0L;
+    for (int it = 0; it < 60; ++it) {
+      long double p0 = 1.0L, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        long double p2 = ((2.0L * j - 1.0L) * z * p1 - (j - 1.0L) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0L; }
+      dp = n * (p0 - z * p1) / (1.0L - z * z);
+      long double step = p1 / dp;
+      z -= step;
+      if (fabsl(step) < 1e-21L) break;
+    }
+    // k-th largest root
+    x[n - k] = (double)z;
+    w[n - k] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
+  }
+  if (n % 2) x[n / 2] = 0.0;
+  for (int k = 0; k < n / 2; ++k) {   // enforce exact symmetry
+    double a = 0.5 * (x[n - 1 - k] - x[k]);
+    x[k] = -a;
+    x[n - 1 - k] = a;
+    double ww = 0.5 * (w[k] + w[n - 1 - k]);
+    w[k] = w[n - 1 - k] = ww;
+  }
+}
+
+// Values of the q+1 B-splines of degree q that are non-zero in span s (functions s-q..s),
+// built up degree by degree: each degree-(k-1) function i feeds the left term of function i
+// and the right term of function i-1, which share the denominator xi_{i+k} - xi_i.
+static void nonzero_basis(const double *U, int s, int q, double xi, double *N) {
+  double tmp[kMaxP + 1];
+  N[0] = 1.0;
+  for (int k = 1; k <= q; ++k) {
+    double prev = 0.0;
+    for (int j = 0; j < k; ++j) {
+      int i = s - k + 1 + j;
+      double t = N[j] / (U[i + k] - U[i]);
+      tmp[j] = prev + (U[i + k] - xi) * t;
+      prev = (xi - U[i]) * t;
+    }
+    tmp[k] = prev;
+    for (int j = 0; j <= k; ++j) N[j] = tmp[j];
+  }
+}
+
+// Values and first derivatives of the p+1 non-zero functions at xi in span s.
+static void basis_and_derivative(const double *U, int s, int p, double xi, double *N, double *dN) {
+  double low[kMaxP + 1];
+  nonzero_basis(U, s, p - 1, xi, low);          // degree p-1: functions s-p+1..s
+  nonzero_basis(U, s, p, xi, N);
+  for (int j = 0; j <= p; ++j) {
+    int m = s - p + j;
+    double d = 0.0;
+    if (j >= 1) d += low[j - 1] / (U[m + p] - U[m]);
+    if (j <= p - 1) d -= low[j] / (U[m + p + 1] - U[m + 1]);
+    dN[j] = p * d;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Device kernels used once at creation
+// ------------------------------------------------------------------------------------------
+
+// One thread per row: columns are the tensor product of the per-axis stencil ranges.
+__global__ void k_pattern(DevProblem pb, int32_t *col_idx) {
+  int64_t A = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (A >= pb.N) return;
+  int i0 = (int)(A % pb.n[0]);
+  int64_t r = A / pb.n[0];
+  int i1 = (int)(r % pb.n[1]);
+  int i2 = (int)(r / pb.n[1]);
+  int l0 = pb.ax[0].stl[i0], w0 = pb.ax[0].stw[i0];
+  int l1 = pb.ax[1].stl[i1], w1 = pb.ax[1].stw[i1];
+  int l2 = 0, w2 = 1;
+  if (pb.dim == 3) { l2 = pb.ax[2].stl[i2]; w2 = pb.ax[2].stw[i2]; }
+  int64_t pos = pb.row_ptr[A];
+  for (int b2 = 0; b2 < w2; ++b2)
+    for (int b1 = 0; b1 < w1; ++b1)
+      for (int b0 = 0; b0 < w0; ++b0)
+        col_idx[pos++] = (int32_t)((l0 + b0) + (int64_t)pb.n[0] * ((l1 + b1) + (int64_t)pb.n[1] * (l2 + b2)));
+}
+
+// Geometry table, one thread per (element, quadrature point); naive sums over the element's
+// functions (runs once).  Homogeneous coordinates: w = sum w_A M_A, X~ = sum w_A x_A M_A, so
+// x = X~/w and dx/dxi = (dX~ - x dw)/w (eq:rational, eq:drational applied to the geometry map
+// of App. A); D = kappa W Jinv Jinv^T with Jinv from eq:identity.
+__global__ void k_geometry(DevProblem pb, const double *__restrict__ ctrl, const double *__restrict__ wts,
+                           const double *__restrict__ kap_nodal, double *__restrict__ geo, int *bad) {
+  const int dim = pb.dim, P = pb.P, Q = pb.Q;
+  const int QD = dim == 3 ? Q * Q * Q : Q * Q;
+  int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= pb.E * QD) return;
+  int64_t e = gid / QD;
+  int q = (int)(gid % QD);
+  int em[3], qm[3] = {q % Q, (q / Q) % Q, dim == 3 ? q / (Q * Q) : 0};
+  em[0] = (int)(e % pb.ne[0]);
+  em[1] = (int)((e / pb.ne[0]) % pb.ne[1]);
+  em[2] = dim == 3 ? (int)(e / ((int64_t)pb.ne[0] * pb.ne[1])) : 0;
+  double w = 0, dw[3] = {0, 0, 0}, X[3] = {0, 0, 0}, dX[3][3] = {{0}}, kt = 0;
+  double W = 1.0;
+  for (int d = 0; d < dim; ++d) W *= pb.ax[d].wq[(size_t)em[d] * Q + qm[d]];
+  const int P2 = dim == 3 ? P : 1;
+  for (int a2 = 0; a2 < P2; ++a2)
+    for (int a1 = 0; a1 < P; ++a1)
+      for (int a0 = 0; a0 < P; ++a0) {
+        int a[3] = {a0, a1, a2};
+        double v = 1.0, g[3] = {1.0, 1.0, 1.0};
+        int64_t A = 0, stride = 1;
+        for (int d = 0; d < dim; ++d) {
+          size_t o = ((size_t)em[d] * Q + qm[d]) * P + a[d];
+          double b = pb.ax[d].B[o], db = pb.ax[d].dB[o];
+          for (int k = 0; k < dim; ++k) g[k] *= (k == d) ? db : b;
+          v *= b;
+          A += stride * (pb.ax[d].efirst[em[d]] + a[d]);
+          stride *= pb.n[d];
+        }
+        double wa = wts ? wts[A] : 1.0;
+        w += wa * v;
+        for (int k = 0; k < dim; ++k) dw[k] += wa * g[k];
+        if (ctrl)
+          for (int i = 0; i < dim; ++i) {
+            double xa = ctrl[A * dim + i] * wa;
+            X[i] += xa * v;
+            for (int k = 0; k < dim; ++k) dX[i][k] += xa * g[k];
+          }
+        if (kap_nodal) kt += wa * kap_nodal[A] * v;
+      }
+  double J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  if (ctrl)
+    for (int i = 0; i < dim; ++i)
+      for (int k = 0; k < dim; ++k) J[i][k] = (dX[i][k] - (X[i] / w) * dw[k]) / w;
+  double det, Ji[3][3];
+  if (dim == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    Ji[0][0] = J[1][1] / det;  Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+  } else {
+    double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    double id = 1.0 / det;
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  }
+  if (!(det > 0.0)) atomicOr(bad, 1);
+  W *= det;
+  double kappa = 1.0;
+  if (pb.kappa_mode == IGA_KAPPA_NODAL) kappa = kt / w;
+  else if (pb.kappa_mode == IGA_KAPPA_ELEMENT) kappa = pb.kel[e];
+  // Ji[alpha][i] = d xi_alpha / d x_i : D_ab = kappa W sum_i Ji[a][i] Ji[b][i]
+  const int NG = geo_streams(dim);
+  double *out = geo + (size_t)e * NG * QD + q;
+  double s = kappa * W / (w * w);
+  auto D = [&](int a, int b) {
+    double r = 0.0;
+    for (int i = 0; i < dim; ++i) r += Ji[a][i] * Ji[b][i];
+    return s * r;
+  };
+  if (dim == 3) {
+    out[0 * QD] = D(0, 0); out[1 * QD] = D(1, 1); out[2 * QD] = D(2, 2);
+    out[3 * QD] = D(0, 1); out[4 * QD] = D(0, 2); out[5 * QD] = D(1, 2);
+    out[6 * QD] = dw[0] / w; out[7 * QD] = dw[1] / w; out[8 * QD] = dw[2] / w;
+    out[9 * QD] = W / w; out[10 * QD] = 1.0 / w;
+  } else {
+    out[0 * QD] = D(0, 0); out[1 * QD] = D(1, 1); out[2 * QD] = D(0, 1);
+    out[3 * QD] = dw[0] / w; out[4 * QD] = dw[1] / w;
+    out[5 * QD] = W / w; out[6 * QD] = 1.0 / w;
+  }
+}
+
+iga_status launch_pattern(Handle &h) {
+  int64_t N = h.pb.N;
+  int blocks = (int)((N + 255) / 256);
+  hipLaunchKernelGGL(k_pattern, dim3(blocks), dim3(256), 0, h.stream, h.pb, h.col_idx);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+iga_status launch_geometry(Handle &h, const double *ctrl, const double *wts, const double *kappa_nodal,
+                           int *bad_det) {
+  const int QD = ipow(h.pb.Q, h.pb.dim);
+  int64_t tot = h.pb.E * QD;
+  int blocks = (int)((tot + 255) / 256);
+  hipLaunchKernelGGL(k_geometry, dim3(blocks), dim3(256), 0, h.stream, h.pb, ctrl, wts, kappa_nodal, h.geo,
+                     bad_det);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Host-side creation
+// ------------------------------------------------------------------------------------------
+thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+iga_status fail(iga_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+template <typename T>
+static iga_status dev_alloc(Handle &h, T **p, size_t count) {
+  void *q = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(IGA_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h.owned.push_back(q);
+  *p = (T *)q;
+  return IGA_OK;
+}
+
+template <typename T>
+static iga_status dev_upload(Handle &h, T **p, const T *src, size_t count) {
+  iga_status st = dev_alloc(h, p, count);
+  if (st) return st;
+  IGA_HIP_CHECK(hipMemcpyAsync(*p, src, count * sizeof(T), hipMemcpyHostToDevice, h.stream));
+  return IGA_OK;
+}
+
+iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
+  if (!d || !out) return fail(IGA_EINVAL, "null descriptor or output");
+  if (d->dim != 2 && d->dim != 3) return fail(IGA_EINVAL, "dim must be 2 or 3");
+  const int dim = d->dim, p = d->degree[0];
+  if (p < 1 || p > kMaxP - 1) return fail(IGA_EINVAL, "degree must be in 1..6");
+  for (int a = 0; a < dim; ++a) {
+    if (d->degree[a] < 1 || d->degree[a] > kMaxP - 1) return fail(IGA_EINVAL, "degree must be in 1..6");
+    if (d->degree[a] != p) return fail(IGA_EUNSUPPORTED, "the GPU kernels need equal degrees on all axes");
+    if (d->nquad[a] != 0 && d->nquad[a] != p + 1)
+      return fail(IGA_EUNSUPPORTED, "the GPU kernels use p+1 Gauss points per axis");
+    if (!d->knots[a] || d->nknots[a] < 2 * p + 2) return fail(IGA_EINVAL, "knot vector too short or NULL");
+    const double *U = d->knots[a];
+    int nk = d->nknots[a];
+    for (int k = 0; k + 1 < nk; ++k)
+      if (!(U[k] <= U[k + 1]) || !std::isfinite(U[k]) || !std::isfinite(U[k + 1]))
+        return fail(IGA_EINVAL, "knot vector must be finite and non-decreasing");
+    for (int k = 0; k < p; ++k)
+      if (U[k] != U[k + 1] || U[nk - 1 - k] != U[nk - 2 - k])
+        return fail(IGA_EINVAL, "knot vector must be open (p+1 equal end knots)");
+    for (int k = p + 1; k + 1 < nk - p - 1; ++k) {
+      int mult = 1;
+      while (k + mult < nk - p - 1 && U[k + mult] == U[k]) ++mult;
+      if (mult > p) return fail(IGA_EINVAL, "interior knot multiplicity must be <= p");
+    }
+  }
+  if (d->kappa_mode < 0 || d->kappa_mode > 2) return fail(IGA_EINVAL, "bad kappa_mode");
+  if (d->kappa_mode != IGA_KAPPA_ONE && !d->kappa) return fail(IGA_EINVAL, "kappa values missing");
+  if (!std::isfinite(d->lambda)) return fail(IGA_EINVAL, "lambda must be finite");
+
+  Handle *h = new Handle();
+  h->stream = (hipStream_t)stream;
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(IGA_EHIP, "hipGetDevice failed"); }
+  DevProblem &pb = h->pb;
+  pb.dim = dim;
+  pb.p = p;
+  pb.P = p + 1;
+  pb.Q = p + 1;
+  pb.lambda = d->lambda;
+  pb.dmask = d->dirichlet_mask & ((1u << (2 * dim)) - 1u);
+  pb.kappa_mode = d->kappa_mode;
+  pb.N = 1;
+  pb.E = 1;
+  pb.simple_knots = 1;
+  iga_status st = IGA_OK;
+  double gx[kMaxP], gw[kMaxP];
+  gauss_legendre(pb.Q, gx, gw);
+  std::vector<int> stl[3], stw[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= dim) { pb.n[a] = 1; pb.ne[a] = 1; continue; }
+    const double *U = d->knots[a];
+    int nk = d->nknots[a];
+    h->hknots[a].assign(U, U + nk);
+    int n = nk - p - 1;
+    std::vector<int> efirst;
+    std::vector<double> B, dB, wq;
+    for (int s = p; s < n; ++s) {
+      if (!(U[s] < U[s + 1])) continue;
+      int e = (int)efirst.size();
+      efirst.push_back(s - p);
+      if (s - p != e) pb.simple_knots = 0;
+      double lo = U[s], hi = U[s + 1];
+      for (int q = 0; q < pb.Q; ++q) {
+        double xi = 0.5 * (lo + hi) + 0.5 * (hi - lo) * gx[q];
+        double N[kMaxP], dN[kMaxP];
+        basis_and_derivative(U, s, p, xi, N, dN);
+        for (int j = 0; j <= p; ++j) { B.push_back(N[j]); dB.push_back(dN[j]); }
+        wq.push_back(gw[q] * 0.5 * (hi - lo));
+      }
+    }
+    pb.n[a] = n;
+    pb.ne[a] = (int)efirst.size();
+    // Algorithm 2 ranges: function j overlaps function i iff their open supports intersect
+    stl[a].resize(n);
+    stw[a].resize(n);
+    for (int i = 0; i < n; ++i) {
+      int l = i, r = i;
+      while (l - 1 >= 0 && U[l - 1 + p + 1] > U[i]) --l;
+      while (r + 1 < n && U[r + 1] < U[i + p + 1]) ++r;
+      stl[a][i] = l;
+      stw[a][i] = r - l + 1;
+    }
+    int *d_ef, *d_stl, *d_stw;
+    double *d_B, *d_dB, *d_wq;
+    if ((st = dev_upload(*h, &d_ef, efirst.data(), efirst.size())) ||
+        (st = dev_upload(*h, &d_B, B.data(), B.size())) || (st = dev_upload(*h, &d_dB, dB.data(), dB.size())) ||
+        (st = dev_upload(*h, &d_wq, wq.data(), wq.size())) ||
+        (st = dev_upload(*h, &d_stl, stl[a].data(), (size_t)n)) ||
+        (st = dev_upload(*h, &d_stw, stw[a].data(), (size_t)n))) {
+      iga_destroy((iga_t)h);
+      return st;
+    }
+    pb.ax[a] = AxisDev{d_B, d_dB, d_wq, d_ef, d_stl, d_stw};
+  }
+  for (int a = 0; a < 3; ++a) { pb.N *= pb.n[a]; pb.E *= pb.ne[a]; }
+  // row pointer: prefix sum of the stencil-width products
+  std::vector<int64_t> rp((size_t)pb.N + 1);
+  rp[0] = 0;
+  for (int64_t A = 0; A < pb.N; ++A) {
+    int i0 = (int)(A % pb.n[0]);
+    int64_t r = A / pb.n[0];
+    int i1 = (int)(r % pb.n[1]);
+    int i2 = (int)(r / pb.n[1]);
+    int64_t w = (int64_t)stw[0][i0] * stw[1][i1] * (dim == 3 ? stw[2][i2] : 1);
+    rp[A + 1] = rp[A] + w;
+  }
+  pb.nnz = rp[pb.N];
+  if (pb.nnz > INT32_MAX * 16LL) { iga_destroy((iga_t)h); return fail(IGA_EUNSUPPORTED, "pattern too large"); }
+  if ((st = dev_upload(*h, &h->row_ptr, rp.data(), rp.size())) ||
+      (st = dev_alloc(*h, &h->col_idx, (size_t)pb.nnz))) {
+    iga_destroy((iga_t)h);
+    return st;
+  }
+  pb.row_ptr = h->row_ptr;
+  pb.col_idx = h->col_idx;
+  if (d->weights)
+    for (int64_t A = 0; A < pb.N; ++A)
+      if (!(d->weights[A] > 0.0) || !std::isfinite(d->weights[A])) {
+        iga_destroy((iga_t)h);
+        return fail(IGA_EINVAL, "weights must be positive and finite");
+      }
+  pb.rational = d->weights != nullptr;
+  pb.table = (d->ctrl != nullptr || d->weights != nullptr || d->kappa_mode == IGA_KAPPA_NODAL) ? 1 : 0;
+  double *d_w = nullptr, *d_ctrl = nullptr, *d_kn = nullptr, *d_kel = nullptr, *d_src = nullptr;
+  if (d->weights && (st = dev_upload(*h, &d_w, d->weights, (size_t)pb.N))) { iga_destroy((iga_t)h); return st; }
+  if (d->kappa_mode == IGA_KAPPA_ELEMENT && (st = dev_upload(*h, &d_kel, d->kappa, (size_t)pb.E))) {
+    iga_destroy((iga_t)h);
+    return st;
+  }
+  if (d->source && (st = dev_upload(*h, &d_src, d->source, (size_t)pb.N))) { iga_destroy((iga_t)h); return st; }
+  pb.wts = d_w;
+  pb.kel = d_kel;
+  pb.src = d_src;
+  if ((st = launch_pattern(*h))) { iga_destroy((iga_t)h); return st; }
+  const int QD = ipow(pb.Q, dim);
+  if ((st = dev_alloc(*h, &h->lin, (size_t)pb.E * QD))) { iga_destroy((iga_t)h); return st; }
+  h->npartials = 4096;
+  if ((st = dev_alloc(*h, &h->partials, (size_t)h->npartials * 4))) { iga_destroy((iga_t)h); return st; }
+  if (pb.table) {
+    if (d->ctrl && (st = dev_upload(*h, &d_ctrl, d->ctrl, (size_t)pb.N * dim))) { iga_destroy((iga_t)h); return st; }
+    if (d->kappa_mode == IGA_KAPPA_NODAL && (st = dev_upload(*h, &d_kn, d->kappa, (size_t)pb.N))) {
+      iga_destroy((iga_t)h);
+      return st;
+    }
+    if ((st = dev_alloc(*h, &h->geo, (size_t)pb.E * QD * geo_streams(dim)))) { iga_destroy((iga_t)h); return st; }
+    pb.geo = h->geo;
+    int *d_bad;
+    if ((st = dev_alloc(*h, &d_bad, 1))) { iga_destroy((iga_t)h); return st; }
+    hipMemsetAsync(d_bad, 0, sizeof(int), h->stream);
+    if ((st = launch_geometry(*h, d_ctrl, d_w, d_kn, d_bad))) { iga_destroy((iga_t)h); return st; }
+    int bad = 0;
+    hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) { iga_destroy((iga_t)h); return fail(IGA_EHIP, "geometry"); }
+    if (bad) { iga_destroy((iga_t)h); return fail(IGA_EINVAL, "det J <= 0 at a quadrature point"); }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) { iga_destroy((iga_t)h); return fail(IGA_EHIP, "setup sync"); }
+  *out = h;
+  return IGA_OK;
+}
+
+}  // namespace iga
+
+extern "C" const char *iga_last_error(void) { return iga::g_err.c_str(); }

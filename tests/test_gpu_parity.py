@@ -1,0 +1,231 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar: norm-wise relative error <= 1e-12 for FP64 residuals, Jacobian values and applies (entries
+of a stiffness row cancel to ~0, so entry-wise relative error is meaningless); the CSR pattern
+must be identical; FP32 element matrices within 1e-5 relative Frobenius error."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1305_4452_amd as iga  # noqa: E402
+
+TOL64 = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def make_case(name):
+    """(patch, lam, kappa_mode, kappa, mask) for named parity cases."""
+    if name == "box2_p2_16":
+        return inputs.unit_box(2, 16, 2), 6.0, 0, None, None
+    if name == "box2_p3_ragged":
+        return inputs.unit_box(2, [9, 5], 3), 3.0, 0, None, None
+    if name == "box2_p4_kel":
+        p = inputs.unit_box(2, [6, 7], 4)
+        return p, 2.0, 2, inputs.uniform(8, 1, 42, 0.5, 2.0), None
+    if name == "box3_p2":
+        return inputs.unit_box(3, [5, 4, 3], 2), 5.0, 0, None, None
+    if name == "box3_p3":
+        return inputs.unit_box(3, 5, 3), 5.0, 0, None, None
+    if name == "box3_p1":
+        return inputs.unit_box(3, 4, 1), 2.0, 0, None, None
+    if name == "box3_p3_mask":
+        return inputs.unit_box(3, [4, 5, 3], 3), 1.0, 0, None, 0b010110
+    if name == "ann2_p2_nodal":
+        p = inputs.quarter_cylinder(6, 2, dim=2)
+        return p, 1.0, 1, np.exp(inputs.grf_rff(p.ctrl, 3, 1)), None
+    if name == "ann2_p3_nodal":
+        p = inputs.quarter_cylinder([5, 7], 3, dim=2)
+        return p, 1.0, 1, np.exp(inputs.grf_rff(p.ctrl, 3, 1)), None
+    if name == "cyl3_p2_nodal":
+        p = inputs.quarter_cylinder([4, 3, 3], 2, dim=3)
+        return p, 1.0, 1, np.exp(inputs.grf_rff(p.ctrl, 3, 1)), None
+    if name == "cyl3_p3_nodal":
+        p = inputs.quarter_cylinder(3, 3, dim=3)
+        return p, 1.0, 1, np.exp(inputs.grf_rff(p.ctrl, 3, 1)), None
+    if name == "box2_p2_c0":
+        kv = inputs.open_uniform_knots(5, 2, cont=0)
+        return inputs.Patch([kv, inputs.open_uniform_knots(4, 2)], [2, 2]), 2.0, 0, None, None
+    if name == "box3_single":
+        return inputs.unit_box(3, 1, 2), 1.0, 0, None, None
+    raise KeyError(name)
+
+
+CASES = ["box2_p2_16", "box2_p3_ragged", "box2_p4_kel", "box3_p1", "box3_p2", "box3_p3", "box3_p3_mask",
+         "ann2_p2_nodal", "ann2_p3_nodal", "cyl3_p2_nodal", "cyl3_p3_nodal", "box2_p2_c0", "box3_single"]
+
+
+def build_pair(name):
+    patch, lam, km, kap, mask = make_case(name)
+    o = oracle.Oracle(patch.knots, patch.degree, patch.ctrl, patch.weights, lam=lam, kappa_mode=km, kappa=kap,
+                      dirichlet_mask=mask)
+    g = iga.IGA(patch.knots, patch.degree, patch.ctrl, patch.weights, lam=lam, kappa_mode=km, kappa=kap,
+                dirichlet_mask=mask)
+    U = inputs.uniform(11, 3, patch.ndof, 0.0, 0.3)
+    return patch, o, g, U
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_pattern_and_residual(name):
+    print(f"[case] pattern+residual {name}", flush=True)
+    patch, o, g, U = build_pair(name)
+    assert (g.N, g.nnz) == (o.N, o.nnz)
+    rp, ci = g.csr_pattern()
+    orp, oci = o.pattern()
+    assert np.array_equal(host(rp), orp) and np.array_equal(host(ci), oci)
+    R = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+    g.assemble_residual(dev(U), R)
+    assert rel(host(R), o.residual(U)) < TOL64
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("algo", [iga.IGA_JAC_ROWGATHER, iga.IGA_JAC_ATOMIC, iga.IGA_JAC_COLOR])
+def test_jacobian_fp64(name, algo):
+    print(f"[case] jacobian {name} algo={algo}", flush=True)
+    patch, o, g, U = build_pair(name)
+    if algo == iga.IGA_JAC_ROWGATHER and name == "box2_p2_c0":
+        pytest.skip("row-gather needs simple interior knots (the library falls back to atomics)")
+    g.set_option(iga.IGA_OPT_JAC_ALGO, algo)
+    vals = torch.full((g.nnz,), np.nan, dtype=torch.float64, device="cuda")
+    g.assemble_jacobian(dev(U), vals)
+    ref = o.jacobian(U)
+    got = host(vals)
+    assert np.all(np.isfinite(got)), "some CSR value was never written"
+    assert rel(got, ref) < TOL64
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_apply_and_spmv(name):
+    print(f"[case] apply {name}", flush=True)
+    patch, o, g, U = build_pair(name)
+    v = inputs.uniform(12, 4, g.N, -1.0, 1.0)
+    y = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+    g.apply(dev(U), dev(v), y)
+    ref = o.jacobian_csr(U) @ v
+    assert rel(host(y), ref) < TOL64
+    vals = torch.zeros(g.nnz, dtype=torch.float64, device="cuda")
+    g.assemble_jacobian(dev(U), vals)
+    y2 = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+    g.spmv(vals, dev(v), y2)
+    assert rel(host(y2), ref) < TOL64
+
+
+@pytest.mark.parametrize("name", ["box2_p2_16", "box2_p4_kel", "box3_p2", "box3_p3", "ann2_p3_nodal", "cyl3_p2_nodal",
+                                  "cyl3_p3_nodal"])
+def test_element_matrices_fp64_fp32(name):
+    print(f"[case] element matrices {name}", flush=True)
+    patch, o, g, U = build_pair(name)
+    els = np.unique(np.linspace(0, g.E - 1, min(g.E, 7)).astype(np.int32))
+    K64 = g.element_matrices(dev(U), els, iga.IGA_FP64)
+    K32 = g.element_matrices(dev(U), els, iga.IGA_FP32)
+    for k, e in enumerate(els):
+        Ko, _ = o.element_matrix(U, int(e))
+        assert rel(K64[k], Ko) < TOL64
+        assert rel(K32[k], Ko) < 1e-5
+
+
+def test_rowgather_bitwise_deterministic():
+    patch, o, g, U = build_pair("box3_p3")
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER)
+    a = torch.zeros(g.nnz, dtype=torch.float64, device="cuda")
+    b = torch.zeros(g.nnz, dtype=torch.float64, device="cuda")
+    g.assemble_jacobian(dev(U), a)
+    g.assemble_jacobian(dev(U), b)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("block", [(1, 1), (2, 1), (2, 2)])
+def test_rowgather_block_shapes(block):
+    patch, o, g, U = build_pair("cyl3_p2_nodal")
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER)
+    g.set_option(iga.IGA_OPT_ROW_BLOCK, (block[0] << 8) | block[1])
+    vals = torch.full((g.nnz,), np.nan, dtype=torch.float64, device="cuda")
+    g.assemble_jacobian(dev(U), vals)
+    assert rel(host(vals), o.jacobian(U)) < TOL64
+
+
+def test_fp32_jacobian_values():
+    patch, o, g, U = build_pair("box3_p3")
+    vals = torch.zeros(g.nnz, dtype=torch.float32, device="cuda")
+    g.assemble_jacobian(dev(U), vals, iga.IGA_FP32)
+    assert rel(host(vals), o.jacobian(U)) < 1e-5
+
+
+def test_newton_small_config_matches_oracle():
+    w = inputs.config_2d_small()
+    o = oracle.Oracle.from_workload(w)
+    Uo, ho, rc = o.newton(w.U0, atol=1e-13)
+    assert rc == 0
+    g = iga.IGA.from_workload(w)
+    U = dev(w.U0)
+    rep = g.newton_solve(U, atol=1e-10)
+    assert rep["converged"] and rep["res_norm"] < 1e-10
+    assert rel(host(U), Uo) < 1e-9
+    # the first residual norm equals the oracle's
+    assert abs(rep["hist"][0] - ho[0]) < 1e-12 * ho[0]
+
+
+@pytest.mark.parametrize("mf", [False, True])
+@pytest.mark.parametrize("prec", [iga.IGA_FP64, iga.IGA_FP32])
+def test_newton_3d_modes(mf, prec):
+    if mf and prec == iga.IGA_FP32:
+        pytest.skip("matrix-free apply is FP64")
+    patch = inputs.unit_box(3, 6, 3)
+    U0 = inputs.initial_guess(patch.shape, 2)
+    o = oracle.Oracle(patch.knots, patch.degree, lam=5.0)
+    Uo, ho, rc = o.newton(U0, atol=1e-14, linear_solver=2, cg_rtol=1e-14)
+    g = iga.IGA(patch.knots, patch.degree, lam=5.0)
+    U = dev(U0)
+    rep = g.newton_solve(U, atol=0.0, rtol=1e-10, matrix_free=mf, jac_prec=prec)
+    assert rep["converged"]
+    assert rep["res_norm"] <= 1e-10 * rep["res_norm0"]
+    assert rel(host(U), Uo) < 1e-8
+
+
+def test_newton_cylinder_nodal_kappa():
+    patch, o, g, U = build_pair("cyl3_p3_nodal")
+    U0 = inputs.initial_guess(patch.shape, 3)
+    Uo, ho, rc = o.newton(U0, atol=1e-14, linear_solver=2, cg_rtol=1e-14)
+    Ud = dev(U0)
+    rep = g.newton_solve(Ud, atol=0.0, rtol=1e-11)
+    assert rep["converged"]
+    assert rel(host(Ud), Uo) < 1e-8
+
+
+def test_invalid_descriptions_rejected():
+    k = inputs.open_uniform_knots(4, 2)
+    with pytest.raises(iga.IGAError) as e:
+        iga.IGA([k, k[::-1].copy()], [2, 2])
+    assert e.value.status == iga.IGA_EINVAL
+    with pytest.raises(iga.IGAError) as e:
+        iga.IGA([k, k], [2, 3])
+    assert e.value.status in (iga.IGA_EINVAL, iga.IGA_EUNSUPPORTED)
+    with pytest.raises(iga.IGAError) as e:
+        iga.IGA([k, k], [2, 2], weights=-np.ones(36))
+    assert e.value.status == iga.IGA_EINVAL
+    # mirrored control net: det J < 0
+    p = inputs.quarter_cylinder(2, 2, dim=2)
+    bad = p.ctrl.copy()
+    bad[:, 0] *= -1
+    with pytest.raises(iga.IGAError) as e:
+        iga.IGA(p.knots, p.degree, bad, p.weights)
+    assert e.value.status == iga.IGA_EINVAL
