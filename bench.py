@@ -1,0 +1,251 @@
+"""Benchmark: Jacobian assembly DOF/s and Newton time to 1e-10 on one MI355X.
+
+Workload: 3D Bratu -Laplace(u) = lambda e^u on the unit cube, lambda = 5, 64^3 elements, p = 3,
+C^2, 4^3 Gauss points (N = 300,763 coefficients, 95,443,993 CSR values), U0 ~ U[0, 0.1) from
+seed 2 with u = 0 on the boundary.  Inputs are synthetic (the problem is defined by formulas).
+
+A timed step is one Jacobian assembly at fixed U: gather, quadrature-point state, integrand,
+sum-factorised contraction, CSR write and Dirichlet rows.  `value` = N / (seconds per step).
+Newton time-to-solution (||R_k|| <= 1e-10 ||R_0||) is reported for the FP64 Jacobian, the FP32
+Jacobian with FP64 residual refinement, and the matrix-free FP64 apply, each against the FP64
+result.  The dominant kernel's roofline figures come from HIP events on the launch stream, and
+the CPU baseline times the FP64 oracle on a bounded sample of elements of the same workload.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (the row-gather kernel runs on the VALU)
+
+
+def rowgather_flops(n: int, p: int, b1: int, b2: int) -> float:
+    """Floating-point operations (2 per multiply-add) of one 3D row-gather launch with the
+    analytic metric (identity geometry, kappa = 1), counted from its loop bounds:
+    u interpolation (3 sum-factorised sweeps), level 1 (axis 2: 3 term-streams), level 2
+    (axis 1: 3 combination-streams), level 3 (axis 0: 2 streams into the register window)."""
+    P = Q = p + 1
+    ne = n - p
+    total = 0.0
+    for I1 in range(0, n, b1):
+        E1lo, E1hi = max(0, I1 - p), min(ne - 1, I1 + b1 - 1)
+        NE1 = E1hi - E1lo + 1
+        for I2 in range(0, n, b2):
+            E2lo, E2hi = max(0, I2 - p), min(ne - 1, I2 + b2 - 1)
+            NE2 = E2hi - E2lo + 1
+            G1, G2, NI1, NI2 = NE1 * Q, NE2 * Q, NE1 + p, NE2 + p
+            interp = (NI2 * NI1 + NI2 * G1 + G2 * G1) * P
+            lvl1 = 0
+            for il in range(b2):
+                i2 = I2 + il
+                if i2 >= n:
+                    continue
+                for o in range(-p, p + 1):
+                    j2 = i2 + o
+                    if not 0 <= j2 < n:
+                        continue
+                    ecount = min(min(i2, j2), E2hi) - max(max(i2, j2) - p, E2lo) + 1
+                    # combos: (DD,VV) 1 term, (VV,DD) 1 term, (VV,VV) 2 terms -> 4 terms
+                    lvl1 += G1 * 4 * max(ecount, 0) * Q * 2       # coef*X*Y: 2 multiply-adds
+            lvl2 = 0
+            for il in range(b1):
+                i1 = I1 + il
+                if i1 >= n:
+                    continue
+                for o in range(-p, p + 1):
+                    j1 = i1 + o
+                    if not 0 <= j1 < n:
+                        continue
+                    ecount = min(min(i1, j1), E1hi) - max(max(i1, j1) - p, E1lo) + 1
+                    lvl2 += 3 * max(ecount, 0) * Q * 2 * sum(
+                        1 for jl in range(b2) if I2 + jl < n for o2 in range(-p, p + 1) if 0 <= I2 + jl + o2 < n)
+            live = sum(1 for a in range(b1) if I1 + a < n for o1 in range(-p, p + 1) if 0 <= I1 + a + o1 < n) * \
+                sum(1 for a in range(b2) if I2 + a < n for o2 in range(-p, p + 1) if 0 <= I2 + a + o2 < n)
+            lvl3 = live * 2 * (P * P + P)          # 2 streams, each P*P multiply-adds + P products
+            total += Q * (interp + lvl1 + lvl2 + lvl3)
+    return 2.0 * total * ne
+
+
+def cpu_baseline(w, n_sample: int, seed: int = 2):
+    import numpy as np
+
+    import inputs
+    import oracle
+    o = oracle.Oracle.from_workload(w)
+    o.pattern()
+    rng_els = (inputs.uniform(seed, 99, n_sample) * o.E).astype(np.int64)
+    vals = np.zeros(o.nnz)
+    t0 = time.perf_counter()
+    o.jacobian_elements(w.U0, rng_els, vals)
+    dt = time.perf_counter() - t0
+    per_elem = dt / n_sample
+    return dict(value=o.N / (per_elem * o.E), unit="DOF/s", cores=1, kind="oracle",
+                sample=f"FP64 oracle Jacobian assembly of {n_sample} seeded random elements of the "
+                       f"{o.E}-element mesh ({dt:.1f} s, single thread), scaled to all elements",
+                seconds_full_assembly_extrapolated=per_elem * o.E)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nel", type=int, default=64)
+    ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=3000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
+                                   "but not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1305_4452_amd as iga
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(3)
+    torch.cuda.set_device(0)
+    w = inputs.config_3d_bratu(nel=args.nel)
+    g = iga.IGA.from_workload(w)
+    N, nnz, E = g.N, g.nnz, g.E
+    U = torch.as_tensor(w.U0, device="cuda")
+    R = torch.zeros(N, dtype=torch.float64, device="cuda")
+    vals = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER)
+    print(f"[bench] workload N={N} nnz={nnz} E={E}; warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        g.assemble_jacobian(U, vals)
+        g.assemble_residual(U, R)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record()
+        g.assemble_jacobian(U, vals)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_step = wall * 1e3 / K
+    jac_ms = float(np.mean(kern_ms))
+    print(f"[bench] jacobian {jac_ms:.3f} ms/launch, wall {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # residual assembly time (reported, not part of the step)
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record()
+    for _ in range(10):
+        g.assemble_residual(U, R)
+    r1.record()
+    torch.cuda.synchronize()
+    res_ms = r0.elapsed_time(r1) / 10
+
+    # FP32 Jacobian values (mixed-precision path)
+    vals32 = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    g.assemble_jacobian(U, vals32, iga.IGA_FP32)
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record()
+    for _ in range(5):
+        g.assemble_jacobian(U, vals32, iga.IGA_FP32)
+    f1.record()
+    torch.cuda.synchronize()
+    jac32_ms = f0.elapsed_time(f1) / 5
+    del vals32
+
+    # SpMV (HBM-bound) time for the report
+    x = torch.rand(N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    g.spmv(vals, x, y)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(10):
+        g.spmv(vals, x, y)
+    s1.record()
+    torch.cuda.synchronize()
+    spmv_ms = s0.elapsed_time(s1) / 10
+    spmv_bytes = 12.0 * nnz + 8.0 * (N + 1) + 16.0 * N + 8.0 * N
+
+    newton = {}
+    if not args.no_newton:
+        Uref = None
+        for name, kw in [("fp64", dict(jac_prec=iga.IGA_FP64)), ("fp32_refined", dict(jac_prec=iga.IGA_FP32)),
+                         ("matrix_free_fp64", dict(matrix_free=True))]:
+            Ux = torch.as_tensor(w.U0, device="cuda").clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rep = g.newton_solve(Ux, atol=0.0, rtol=1e-10, max_krylov=20000, raise_on_fail=False, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            Uh = Ux.cpu().numpy()
+            if Uref is None:
+                Uref = Uh
+            newton[name] = dict(time_s=dt, converged=rep["converged"], newton_iters=rep["newton_iters"],
+                                krylov_iters=rep["krylov_iters_total"], rel_residual=rep["res_norm"] / rep["res_norm0"],
+                                res_norm0=rep["res_norm0"], t_jacobian_ms=rep["t_jacobian_ms"],
+                                t_krylov_ms=rep["t_krylov_ms"], t_residual_ms=rep["t_residual_ms"],
+                                max_rel_diff_vs_fp64=float(np.abs(Uh - Uref).max() / np.abs(Uref).max()))
+            print(f"[bench] newton {name}: {dt:.3f} s, {rep['newton_iters']} steps, "
+                  f"{rep['krylov_iters_total']} CG its", file=sys.stderr, flush=True)
+
+    flops = rowgather_flops(w.patch.shape[0], w.patch.degree[0], 2, 2)
+    achieved = flops / (jac_ms * 1e-3) / 1e12
+    out_bytes = 8.0 * nnz
+    cpu = None
+    if not args.no_cpu:
+        print(f"[bench] cpu baseline: oracle on {args.cpu_sample} elements", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, args.cpu_sample)
+    value = N / (ms_step * 1e-3)
+    line = {
+        "metric": "Jacobian assembly DOF/s + Newton time to 1e-10; mixed/learned vs plain FP64",
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Bratu unit cube lambda=5, {args.nel}^3 elements, p=3 C^2, 4^3 Gauss points, "
+                               "U0~U[0,0.1) seed 2; Jacobian assembly (FP64 row-gather)",
+                   "ndof": N, "nnz": nnz, "nelem": E},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_rowgather3<4,false,2,2,double,double>", "kernel_ms": jac_ms,
+                     "algorithmic_flops": flops, "output_bytes": out_bytes,
+                     "output_hbm_GBs": out_bytes / (jac_ms * 1e-3) / 1e9,
+                     "output_hbm_frac": out_bytes / (jac_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+        "elements_per_s": E / (ms_step * 1e-3),
+        "jacobian_fp32_ms": jac32_ms,
+        "residual_ms": res_ms,
+        "spmv": {"ms": spmv_ms, "GBs": spmv_bytes / (spmv_ms * 1e-3) / 1e9,
+                 "frac": spmv_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "newton": newton,
+        "paper_context": {"explicit_jacobian_s": 15.41, "procs": 16, "hw": "2x Xeon E5-2680 v2",
+                          "dof_per_s": 300763 / 15.41},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -342,3 +342,81 @@ def test_manufactured_solution_convergence_rate(p):
         errs.append(math.sqrt(np.sum(Wq * (uq - us) ** 2)))
     rates = [math.log(errs[i] / errs[i + 1], 2) for i in range(len(errs) - 1)]
     assert rates[-1] > p + 1 - 0.3, (errs, rates)
+
+
+# ------------------------------------------------------------------------------------------
+# Consistency of the oracle's partial entry points with its full assembly
+# ------------------------------------------------------------------------------------------
+
+def _tensor_support_pattern(patch):
+    """Brute force: (A, B) interact iff the open supports overlap on every axis."""
+    dim = patch.dim
+    sup = []
+    for U, p in zip(patch.knots, patch.degree):
+        n = len(U) - p - 1
+        sup.append(np.array([[max(U[i], U[j]) < min(U[i + p + 1], U[j + p + 1]) for j in range(n)]
+                             for i in range(n)]))
+    M = sup[0]
+    for d in range(1, dim):
+        M = np.kron(sup[d], M)
+    return M
+
+
+@pytest.mark.parametrize("kind", ["box2", "box3c1", "c0"])
+def test_csr_pattern_bruteforce(kind):
+    if kind == "box2":
+        patch = inputs.unit_box(2, [4, 3], 3)
+    elif kind == "box3c1":
+        patch = inputs.unit_box(3, [3, 2, 2], 2, cont=0)
+    else:
+        patch = inputs.Patch([inputs.open_uniform_knots(4, 3, cont=1), inputs.open_uniform_knots(3, 2)], [3, 2])
+    o = oracle.Oracle(patch.knots, patch.degree)
+    rp, ci = o.pattern()
+    M = np.zeros((o.N, o.N), dtype=bool)
+    for A in range(o.N):
+        cols = ci[rp[A]:rp[A + 1]]
+        assert np.all(np.diff(cols) > 0)
+        M[A, cols] = True
+    assert np.array_equal(M, _tensor_support_pattern(patch))
+
+
+def test_partial_entry_points_agree_with_full_assembly():
+    patch = inputs.quarter_cylinder([3, 4], 2, dim=2)
+    kap = np.exp(inputs.grf_rff(patch.ctrl, 3, 1))
+    o = oracle.Oracle(patch.knots, patch.degree, patch.ctrl, patch.weights, lam=2.0, kappa_mode=1, kappa=kap)
+    U = inputs.initial_guess(patch.shape, 7, 0, 0.0, 0.4)
+    R, J = o.residual(U), o.jacobian(U)
+    rp, ci = o.pattern()
+    rows = np.array([0, 5, 7, 13, o.N - 1])
+    assert np.allclose(o.residual_rows(U, rows), R[rows], rtol=1e-13, atol=1e-16)
+    JR = o.jacobian_rows(U, rows)
+    ref = np.concatenate([J[rp[r]:rp[r + 1]] for r in rows])
+    assert np.allclose(JR, ref, rtol=1e-13, atol=1e-16)
+    # all element matrices scattered == the Jacobian without Dirichlet rows
+    o0 = oracle.Oracle(patch.knots, patch.degree, patch.ctrl, patch.weights, lam=2.0, kappa_mode=1, kappa=kap,
+                       dirichlet_mask=0)
+    J0 = o0.jacobian(U)
+    v = np.zeros(o0.nnz)
+    o0.jacobian_elements(U, np.arange(o0.E), v)
+    assert np.allclose(v, J0, rtol=1e-13, atol=1e-15)
+    K, Re = o0.element_matrix(U, 4)
+    assert np.allclose(K, K.T, rtol=1e-13, atol=1e-15)
+    # SpMV against scipy
+    x = inputs.uniform(1, 1, o.N, -1, 1)
+    y = np.zeros(o.N)
+    oracle.lib().orc_spmv(o.N, rp.ctypes.data_as(oracle._i64p), ci.ctypes.data_as(oracle._i32p),
+                          J.ctypes.data_as(oracle._dp), x.ctypes.data_as(oracle._dp), y.ctypes.data_as(oracle._dp))
+    assert np.allclose(y, o.jacobian_csr(U) @ x, rtol=1e-14, atol=1e-15)
+
+
+def test_mass_matrix_and_load_vector():
+    patch = inputs.quarter_cylinder(4, 2, dim=2)
+    E = 16
+    o = oracle.Oracle(patch.knots, patch.degree, patch.ctrl, patch.weights, lam=-1.0, kappa_mode=2,
+                      kappa=np.zeros(E), dirichlet_mask=0)
+    M = o.mass_matrix()
+    assert np.allclose(M.toarray(), o.jacobian_csr(np.zeros(o.N)).toarray(), rtol=1e-14, atol=1e-17)
+    xq, Wq, _, _ = o.qp_data()
+    b = o.load_vector(np.ones(len(Wq)))
+    assert np.allclose(b, np.asarray(M.sum(axis=1)).ravel(), rtol=1e-13)
+    assert abs(b.sum() - Wq.sum()) < 1e-13
