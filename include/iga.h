@@ -48,10 +48,16 @@ typedef enum { IGA_KAPPA_ONE = 0, IGA_KAPPA_NODAL = 1, IGA_KAPPA_ELEMENT = 2 } i
 
 /* Jacobian assembly algorithm (iga_set_option(IGA_OPT_JAC_ALGO)):
  *   ROWGATHER: each workgroup owns a block of row pencils and sums element contributions
- *              itself; every CSR value is written exactly once (no atomics, deterministic);
+ *              itself; every CSR value is written exactly once (no atomics, deterministic).
+ *              With identity geometry, no weights and kappa = 1 the stiffness is a Kronecker
+ *              sum of 1D band matrices and only the reaction term is contracted in 3D;
  *   ATOMIC:    element matrices by sum factorisation, scattered with FP64 atomic adds;
- *   COLOR:     element matrices scattered colour by colour ((p+1)^d colours, no atomics). */
-typedef enum { IGA_JAC_AUTO = 0, IGA_JAC_ROWGATHER = 1, IGA_JAC_ATOMIC = 2, IGA_JAC_COLOR = 3 } iga_jac_algo;
+ *   COLOR:     element matrices scattered colour by colour ((p+1)^d colours, no atomics);
+ *   ROWGATHER_GENERAL: the row-gather kernel with every term contracted (never the
+ *              Kronecker-sum shortcut), for comparison. */
+typedef enum {
+  IGA_JAC_AUTO = 0, IGA_JAC_ROWGATHER = 1, IGA_JAC_ATOMIC = 2, IGA_JAC_COLOR = 3, IGA_JAC_ROWGATHER_GENERAL = 4
+} iga_jac_algo;
 
 typedef enum {
   IGA_OPT_JAC_ALGO = 1,      /* iga_jac_algo */

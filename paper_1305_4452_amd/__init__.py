@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libiga.so")
 IGA_OK, IGA_EINVAL, IGA_ENOMEM, IGA_EHIP, IGA_ENOCONV, IGA_EUNSUPPORTED, IGA_ESTATE = range(7)
 IGA_FP64, IGA_FP32, IGA_BF16 = 0, 1, 2
 IGA_KAPPA_ONE, IGA_KAPPA_NODAL, IGA_KAPPA_ELEMENT = 0, 1, 2
-IGA_JAC_AUTO, IGA_JAC_ROWGATHER, IGA_JAC_ATOMIC, IGA_JAC_COLOR = 0, 1, 2, 3
+IGA_JAC_AUTO, IGA_JAC_ROWGATHER, IGA_JAC_ATOMIC, IGA_JAC_COLOR, IGA_JAC_ROWGATHER_GENERAL = 0, 1, 2, 3, 4
 IGA_OPT_JAC_ALGO, IGA_OPT_ROW_BLOCK, IGA_OPT_LAMBDA_BITS = 1, 2, 3
 
 _STATUS = {0: "IGA_OK", 1: "IGA_EINVAL", 2: "IGA_ENOMEM", 3: "IGA_EHIP", 4: "IGA_ENOCONV",

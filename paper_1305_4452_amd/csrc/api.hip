@@ -36,12 +36,27 @@ static void pick_block(const Handle &h, int prec, int *b1, int *b2) {
   }
 }
 
+static void pick_sep_block(const Handle &h, int *b1, int *b2) {
+  if (h.row_b1 > 0 && rgsep_supported(h, h.row_b1, h.row_b2 > 0 ? h.row_b2 : 1)) {
+    *b1 = h.row_b1;
+    *b2 = h.row_b2 > 0 ? h.row_b2 : 1;
+    return;
+  }
+  *b1 = h.pb.P <= 4 ? 4 : 2;
+  *b2 = 2;
+}
+
 static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int prec) {
   int algo = h.jac_algo;
   int b1 = 0, b2 = 0;
+  if (algo == IGA_JAC_AUTO || algo == IGA_JAC_ROWGATHER) {
+    int s1 = 0, s2 = 0;
+    pick_sep_block(h, &s1, &s2);
+    if (rgsep_supported(h, s1, s2)) return launch_jac_rgsep(h, U, vals, prec, s1, s2);
+  }
   pick_block(h, prec, &b1, &b2);
   if (algo == IGA_JAC_AUTO) algo = rowgather_supported(h, prec, b1, b2) ? IGA_JAC_ROWGATHER : IGA_JAC_ATOMIC;
-  if (algo == IGA_JAC_ROWGATHER) return launch_jac_rowgather(h, U, vals, prec, b1, b2);
+  if (algo == IGA_JAC_ROWGATHER || algo == IGA_JAC_ROWGATHER_GENERAL) return launch_jac_rowgather(h, U, vals, prec, b1, b2);
   if (algo == IGA_JAC_ATOMIC) return launch_jac_scatter(h, U, vals, prec, 0);
   if (algo == IGA_JAC_COLOR) return launch_jac_scatter(h, U, vals, prec, 1);
   return fail(IGA_EINVAL, "unknown Jacobian algorithm");
@@ -197,7 +212,7 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
   Handle *h = (Handle *)hh;
   switch (key) {
     case IGA_OPT_JAC_ALGO:
-      if (value < IGA_JAC_AUTO || value > IGA_JAC_COLOR) return fail(IGA_EINVAL, "bad Jacobian algorithm");
+      if (value < IGA_JAC_AUTO || value > IGA_JAC_ROWGATHER_GENERAL) return fail(IGA_EINVAL, "bad Jacobian algorithm");
       h->jac_algo = (int)value;
       return IGA_OK;
     case IGA_OPT_ROW_BLOCK:

@@ -48,6 +48,10 @@ struct DevProblem {
   const double *src;   // [N] or null
   unsigned dmask;
   int simple_knots;    // every element's first function equals its span counter (max continuity)
+  int separable;       // identity geometry, no weights, kappa = 1: stiffness is a Kronecker sum
+  // 1D Galerkin matrices per axis, band storage [n][2p+1] (offset o = j - i + p):
+  //   M_d[i][o] = sum_g w(g) B_i(g) B_j(g),  A_d[i][o] = sum_g w(g) B'_i(g) B'_j(g)
+  const double *sepM[3], *sepA[3];
 };
 
 __host__ __device__ inline int ipow(int b, int e) {
@@ -140,6 +144,8 @@ iga_status launch_elem_matrices(Handle &h, const double *U, const int32_t *elems
 iga_status launch_jac_scatter(Handle &h, const double *U, void *vals, int prec, int color_mode);
 iga_status launch_jac_rowgather(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
 bool rowgather_supported(const Handle &h, int prec, int b1, int b2);
+iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
+bool rgsep_supported(const Handle &h, int b1, int b2);
 iga_status launch_spmv(Handle &h, const void *vals, int prec, const double *x, double *y,
                        double *partial_dot, int npart);
 iga_status launch_fill(Handle &h, double *x, int64_t n, double v);

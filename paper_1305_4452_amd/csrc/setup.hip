@@ -324,6 +324,27 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       stl[a][i] = l;
       stw[a][i] = r - l + 1;
     }
+    // 1D mass and stiffness in band storage (used by the separable Jacobian kernel)
+    const int W = 2 * p + 1;
+    std::vector<double> sM((size_t)n * W, 0.0), sA((size_t)n * W, 0.0);
+    for (size_t e = 0; e < efirst.size(); ++e)
+      for (int q = 0; q < pb.Q; ++q) {
+        const double *Bq = &B[(e * pb.Q + q) * (p + 1)], *dBq = &dB[(e * pb.Q + q) * (p + 1)];
+        double wgt = wq[e * pb.Q + q];
+        for (int ia = 0; ia <= p; ++ia)
+          for (int ib = 0; ib <= p; ++ib) {
+            size_t o = (size_t)(efirst[e] + ia) * W + (ib - ia + p);
+            sM[o] += wgt * Bq[ia] * Bq[ib];
+            sA[o] += wgt * dBq[ia] * dBq[ib];
+          }
+      }
+    double *d_sM, *d_sA;
+    if ((st = dev_upload(*h, &d_sM, sM.data(), sM.size())) || (st = dev_upload(*h, &d_sA, sA.data(), sA.size()))) {
+      iga_destroy((iga_t)h);
+      return st;
+    }
+    pb.sepM[a] = d_sM;
+    pb.sepA[a] = d_sA;
     int *d_ef, *d_stl, *d_stw;
     double *d_B, *d_dB, *d_wq;
     if ((st = dev_upload(*h, &d_ef, efirst.data(), efirst.size())) ||
@@ -365,6 +386,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       }
   pb.rational = d->weights != nullptr;
   pb.table = (d->ctrl != nullptr || d->weights != nullptr || d->kappa_mode == IGA_KAPPA_NODAL) ? 1 : 0;
+  pb.separable = (!pb.table && d->kappa_mode == IGA_KAPPA_ONE) ? 1 : 0;
   double *d_w = nullptr, *d_ctrl = nullptr, *d_kn = nullptr, *d_kel = nullptr, *d_src = nullptr;
   if (d->weights && (st = dev_upload(*h, &d_w, d->weights, (size_t)pb.N))) { iga_destroy((iga_t)h); return st; }
   if (d->kappa_mode == IGA_KAPPA_ELEMENT && (st = dev_upload(*h, &d_kel, d->kappa, (size_t)pb.E))) {

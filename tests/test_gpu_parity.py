@@ -98,11 +98,12 @@ def test_pattern_and_residual(name):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("algo", [iga.IGA_JAC_ROWGATHER, iga.IGA_JAC_ATOMIC, iga.IGA_JAC_COLOR])
+@pytest.mark.parametrize("algo", [iga.IGA_JAC_ROWGATHER, iga.IGA_JAC_ROWGATHER_GENERAL, iga.IGA_JAC_ATOMIC,
+                                  iga.IGA_JAC_COLOR])
 def test_jacobian_fp64(name, algo):
     print(f"[case] jacobian {name} algo={algo}", flush=True)
     patch, o, g, U = build_pair(name)
-    if algo == iga.IGA_JAC_ROWGATHER and name == "box2_p2_c0":
+    if algo in (iga.IGA_JAC_ROWGATHER, iga.IGA_JAC_ROWGATHER_GENERAL) and name == "box2_p2_c0":
         pytest.skip("row-gather needs simple interior knots (the library falls back to atomics)")
     g.set_option(iga.IGA_OPT_JAC_ALGO, algo)
     vals = torch.full((g.nnz,), np.nan, dtype=torch.float64, device="cuda")
@@ -161,6 +162,27 @@ def test_rowgather_block_shapes(block):
     vals = torch.full((g.nnz,), np.nan, dtype=torch.float64, device="cuda")
     g.assemble_jacobian(dev(U), vals)
     assert rel(host(vals), o.jacobian(U)) < TOL64
+
+
+@pytest.mark.parametrize("p,nel,block", [(1, [6, 5, 4], (4, 2)), (2, [5, 6, 3], (4, 2)), (3, [7, 5, 4], (4, 2)),
+                                         (3, [7, 5, 4], (2, 2)), (3, [9, 9, 6], (4, 4)), (3, [9, 10, 5], (8, 2)),
+                                         (4, [4, 5, 3], (2, 2)), (4, [4, 5, 3], (2, 1)), (2, 1, (4, 2))])
+@pytest.mark.parametrize("prec", [iga.IGA_FP64, iga.IGA_FP32])
+def test_separable_rowgather_blocks(p, nel, block, prec):
+    """Kronecker-sum stiffness + contracted reaction term, every compiled block shape."""
+    print(f"[case] separable p={p} nel={nel} block={block} prec={prec}", flush=True)
+    patch = inputs.unit_box(3, nel, p)
+    o = oracle.Oracle(patch.knots, patch.degree, lam=4.0)
+    g = iga.IGA(patch.knots, patch.degree, lam=4.0)
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER)
+    g.set_option(iga.IGA_OPT_ROW_BLOCK, (block[0] << 8) | block[1])
+    U = inputs.uniform(5, 5, g.N, 0.0, 0.5)
+    dt = torch.float64 if prec == iga.IGA_FP64 else torch.float32
+    vals = torch.full((g.nnz,), float("nan"), dtype=dt, device="cuda")
+    g.assemble_jacobian(dev(U), vals, prec)
+    got = host(vals)
+    assert np.all(np.isfinite(got))
+    assert rel(got, o.jacobian(U)) < (TOL64 if prec == iga.IGA_FP64 else 1e-5)
 
 
 def test_fp32_jacobian_values():
