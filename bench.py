@@ -107,6 +107,52 @@ def rgsep_flops(n: int, p: int, b1: int, b2: int) -> float:
     return 2.0 * total * ne + 0.0 * rows_entries
 
 
+def bench_batched(n: int):
+    """The uneven 2D batch: one batched solve (hipGraph-replayed CG chunks, autotuned shapes)
+    against plain per-instance FP64 Newton on the same GPU, both to ||R|| < 1e-10."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1305_4452_amd as iga
+    ws = inputs.batched_instances(n)
+    t = time.perf_counter()
+    b = iga.IGABatch(ws)
+    t_create = time.perf_counter() - t
+    U0 = b.pack([w.U0 for w in ws])
+    U = torch.as_tensor(U0, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    per, summ = b.newton_solve(U, atol=1e-10, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    print(f"[bench] batched {n}: {t_batch:.3f} s", file=sys.stderr, flush=True)
+    sols = b.unpack(U.cpu().numpy())
+    b.close()
+    t_single = 0.0
+    maxdiff = 0.0
+    conv_single = 0
+    for i, w in enumerate(ws):
+        g = iga.IGA.from_workload(w)
+        Ui = torch.as_tensor(w.U0, device="cuda")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rep = g.newton_solve(Ui, atol=1e-10, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t
+        conv_single += int(rep["converged"])
+        ref = Ui.cpu().numpy()
+        maxdiff = max(maxdiff, float(np.abs(sols[i] - ref).max() / max(np.abs(ref).max(), 1e-300)))
+        g.close()
+    print(f"[bench] per-instance {n}: {t_single:.3f} s", file=sys.stderr, flush=True)
+    return dict(instances=n, total_dof=int(b.N), batched_s=t_batch, per_instance_s=t_single,
+                speedup=t_single / t_batch, batched_converged=int(sum(p["converged"] for p in per)),
+                per_instance_converged=conv_single, max_rel_diff=maxdiff, graph_launches=summ["graph_launches"],
+                newton_steps=summ["newton_steps"], tune_ms=summ["t_tune_ms"], create_s=t_create,
+                t_residual_ms=summ["t_residual_ms"], t_jacobian_ms=summ["t_jacobian_ms"],
+                t_krylov_ms=summ["t_krylov_ms"])
+
+
 def cpu_baseline(w, n_sample: int, seed: int = 2):
     import numpy as np
 
@@ -135,6 +181,8 @@ def main():
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-n", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
@@ -248,6 +296,9 @@ def main():
             print(f"[bench] newton {name}: {dt:.3f} s, {rep['newton_iters']} steps, "
                   f"{rep['krylov_iters_total']} CG its", file=sys.stderr, flush=True)
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(args.batch_n)
     flops = rgsep_flops(w.patch.shape[0], w.patch.degree[0], 4, 2)
     achieved = flops / (jac_ms * 1e-3) / 1e12
     out_bytes = 8.0 * nnz
@@ -286,6 +337,7 @@ def main():
         "spmv": {"ms": spmv_ms, "GBs": spmv_bytes / (spmv_ms * 1e-3) / 1e9,
                  "frac": spmv_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "newton": newton,
+        "batched": batched,
         "paper_context": {"explicit_jacobian_s": 15.41, "procs": 16, "hw": "2x Xeon E5-2680 v2",
                           "dof_per_s": 300763 / 15.41},
     }

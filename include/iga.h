@@ -146,6 +146,46 @@ iga_status iga_newton_solve(iga_t h, double *U_dev, const iga_newton_opts *opts,
 iga_status iga_element_matrices(iga_t h, const double *U_dev, const int32_t *elems_host, int n,
                                 int prec, double *out_host);
 
+/* ---- batched solves ------------------------------------------------------------------------
+ * Many independent 2D problems (identity geometry, kappa one or element-wise, simple interior
+ * knots; degrees and sizes may differ) solved together: every kernel of the Newton step covers
+ * all instances in one launch over per-instance work lists, per-instance CG scalars and
+ * convergence decisions stay on the device, and each chunk of CG iterations is one replay of a
+ * captured hipGraph.  Pencil-block and SpMV launch shapes are autotuned per (degree, size
+ * class) when the batch is created.  Callers that need many solves of the same shape (the
+ * batched workload of the spec configuration list, training-data generation) use this
+ * instead of iga_newton_solve per instance. */
+typedef struct iga_batch_s *iga_batch_t;
+
+typedef struct {
+  int converged;
+  int newton_iters;
+  int krylov_iters;
+  double res_norm0, res_norm;
+} iga_batch_item_report;
+
+typedef struct {
+  int all_converged;
+  int newton_steps;              /* Newton steps of the slowest instance */
+  int graph_launches;            /* CG chunk replays in total */
+  int krylov_iters_max;          /* CG iterations run (chunks x chunk length) */
+  double t_total_ms, t_residual_ms, t_jacobian_ms, t_krylov_ms, t_tune_ms;
+} iga_batch_report;
+
+/* n descriptions (host array); copied.  Errors as iga_create, plus IGA_EUNSUPPORTED for 3D,
+ * NURBS geometry or repeated interior knots.  Synchronous. */
+iga_status iga_batch_create(int n, const iga_desc *descs, void *hip_stream, iga_batch_t *out);
+/* Sizes of the concatenated unknown vector; dof_offsets (host, n+1, may be NULL) receives the
+ * offset of each instance's coefficients in the caller's order. */
+iga_status iga_batch_info(iga_batch_t b, int64_t *total_ndof, int64_t *total_nnz, int64_t *dof_offsets);
+/* Newton on every instance; U_dev is the concatenation (device, FP64) in the caller's order,
+ * updated in place.  opts as for iga_newton_solve (matrix_free must be 0); items (host, n, may
+ * be NULL) gets the per-instance result.  Returns IGA_ENOCONV if any instance did not converge.
+ * Synchronous. */
+iga_status iga_batch_newton_solve(iga_batch_t b, double *U_dev, const iga_newton_opts *opts,
+                                  iga_batch_item_report *items, iga_batch_report *report);
+iga_status iga_batch_destroy(iga_batch_t b);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *iga_last_error(void);
 

@@ -81,6 +81,30 @@ class iga_newton_report(C.Structure):
                     t_krylov_ms=self.t_krylov_ms)
 
 
+class iga_batch_item_report(C.Structure):
+    _fields_ = [
+        ("converged", C.c_int),
+        ("newton_iters", C.c_int),
+        ("krylov_iters", C.c_int),
+        ("res_norm0", C.c_double),
+        ("res_norm", C.c_double),
+    ]
+
+
+class iga_batch_report(C.Structure):
+    _fields_ = [
+        ("all_converged", C.c_int),
+        ("newton_steps", C.c_int),
+        ("graph_launches", C.c_int),
+        ("krylov_iters_max", C.c_int),
+        ("t_total_ms", C.c_double),
+        ("t_residual_ms", C.c_double),
+        ("t_jacobian_ms", C.c_double),
+        ("t_krylov_ms", C.c_double),
+        ("t_tune_ms", C.c_double),
+    ]
+
+
 # name -> (argtypes, restype): mirrors include/iga.h
 _SIGNATURES = {
     "iga_create": ([C.POINTER(iga_desc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
@@ -95,6 +119,11 @@ _SIGNATURES = {
     "iga_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_newton_report)],
                          C.c_int),
     "iga_element_matrices": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.c_int, _dp], C.c_int),
+    "iga_batch_create": ([C.c_int, C.POINTER(iga_desc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "iga_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+    "iga_batch_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_batch_item_report),
+                                C.POINTER(iga_batch_report)], C.c_int),
+    "iga_batch_destroy": ([C.c_void_p], C.c_int),
     "iga_last_error": ([], C.c_char_p),
 }
 
@@ -147,6 +176,38 @@ def _dev_ptr(t, dtype, n, name):
     return C.c_void_p(t.data_ptr())
 
 
+def make_desc(keep, knots, degree, ctrl=None, weights=None, lam=1.0, kappa_mode=IGA_KAPPA_ONE, kappa=None,
+              source=None, dirichlet_mask=None, d=None):
+    """Fill an iga_desc; the numpy arrays backing its pointers are appended to `keep`."""
+    dim = len(knots)
+
+    def arr(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(_dp)
+
+    if d is None:
+        d = iga_desc()
+    d.dim = dim
+    for a in range(dim):
+        d.degree[a] = int(degree[a])
+        k = np.ascontiguousarray(knots[a], dtype=np.float64)
+        keep.append(k)
+        d.nknots[a] = len(k)
+        d.knots[a] = k.ctypes.data_as(_dp)
+        d.nquad[a] = 0
+    d.ctrl = arr(ctrl)
+    d.weights = arr(weights)
+    d.lam = float(lam)
+    d.kappa_mode = int(kappa_mode)
+    d.kappa = arr(kappa)
+    d.source = arr(source)
+    d.dirichlet_mask = (1 << (2 * dim)) - 1 if dirichlet_mask is None else int(dirichlet_mask)
+    return d
+
+
 class IGA:
     """One problem (handle) bound to the current torch stream at creation."""
 
@@ -156,30 +217,7 @@ class IGA:
         L = load()
         dim = len(knots)
         self._keep = []
-
-        def arr(a):
-            if a is None:
-                return None
-            a = np.ascontiguousarray(a, dtype=np.float64)
-            self._keep.append(a)
-            return a.ctypes.data_as(_dp)
-
-        d = iga_desc()
-        d.dim = dim
-        for a in range(dim):
-            d.degree[a] = int(degree[a])
-            k = np.ascontiguousarray(knots[a], dtype=np.float64)
-            self._keep.append(k)
-            d.nknots[a] = len(k)
-            d.knots[a] = k.ctypes.data_as(_dp)
-            d.nquad[a] = 0
-        d.ctrl = arr(ctrl)
-        d.weights = arr(weights)
-        d.lam = float(lam)
-        d.kappa_mode = int(kappa_mode)
-        d.kappa = arr(kappa)
-        d.source = arr(source)
-        d.dirichlet_mask = (1 << (2 * dim)) - 1 if dirichlet_mask is None else int(dirichlet_mask)
+        d = make_desc(self._keep, knots, degree, ctrl, weights, lam, kappa_mode, kappa, source, dirichlet_mask)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -278,3 +316,65 @@ class IGA:
                                            elems.ctypes.data_as(C.POINTER(C.c_int32)), len(elems), int(prec),
                                            out.ctypes.data_as(_dp)), "iga_element_matrices")
         return out
+
+
+class IGABatch:
+    """Many independent 2D problems solved together (iga_batch_*)."""
+
+    def __init__(self, workloads, stream=None):
+        import torch
+        L = load()
+        self.n = len(workloads)
+        keep = []
+        descs = (iga_desc * self.n)()
+        for i, w in enumerate(workloads):
+            p = w.patch
+            make_desc(keep, p.knots, p.degree, p.ctrl, p.weights, w.lam, w.kappa_mode, w.kappa, None, None, descs[i])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(L.iga_batch_create(self.n, descs, C.c_void_p(stream.cuda_stream), C.byref(h)), "iga_batch_create")
+        self.h = h
+        tot, nnz = C.c_int64(), C.c_int64()
+        offs = (C.c_int64 * (self.n + 1))()
+        _check(L.iga_batch_info(h, C.byref(tot), C.byref(nnz), offs), "iga_batch_info")
+        self.N, self.nnz = tot.value, nnz.value
+        self.offsets = np.array(offs[:], dtype=np.int64)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().iga_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, arrays):
+        out = np.zeros(self.N)
+        for i, a in enumerate(arrays):
+            out[self.offsets[i]:self.offsets[i + 1]] = a
+        return out
+
+    def unpack(self, x):
+        x = np.asarray(x)
+        return [x[self.offsets[i]:self.offsets[i + 1]] for i in range(self.n)]
+
+    def newton_solve(self, U, atol=1e-10, rtol=0.0, max_newton=30, max_krylov=5000, jac_prec=IGA_FP64,
+                     forcing_max=1e-2, raise_on_fail=True):
+        import torch
+        o = iga_newton_opts(atol, rtol, max_newton, max_krylov, 0, int(jac_prec), forcing_max, 16)
+        items = (iga_batch_item_report * self.n)()
+        rep = iga_batch_report()
+        st = load().iga_batch_newton_solve(self.h, _dev_ptr(U, torch.float64, self.N, "U"), C.byref(o), items,
+                                           C.byref(rep))
+        if raise_on_fail:
+            _check(st, "iga_batch_newton_solve")
+        per = [dict(converged=bool(it.converged), newton_iters=it.newton_iters, krylov_iters=it.krylov_iters,
+                    res_norm0=it.res_norm0, res_norm=it.res_norm) for it in items]
+        summary = {k: getattr(rep, k) for k, _ in iga_batch_report._fields_}
+        summary["status"] = st
+        return per, summary

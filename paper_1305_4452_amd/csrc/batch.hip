@@ -1,0 +1,866 @@
+// Batched Newton-Krylov for many independent 2D problems of different sizes and degrees.
+//
+// Every kernel below covers all instances in one launch: a launch walks a work list of tiles
+// (instance, rows) or (instance, element) / (instance, pencil block) and reads the instance's
+// problem description from a device array.  Per-instance CG scalars never leave the device:
+// each tile writes one partial sum, and every block of an instance reduces that instance's
+// partials in the same order, so all blocks take bitwise-identical alpha/beta and the same
+// converged/not-converged decision without flags or atomics.  One chunk of CG iterations is
+// captured once into a hipGraph and replayed; the host only reads one counter per chunk and
+// one vector of residual norms per Newton step.  Launch shapes (pencils per row-gather block
+// and lanes per SpMV row) are chosen per (degree, size class) by timing the candidates on the
+// device when the batch is created.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+
+#include "iga_impl.h"
+#include "kern_elem.h"
+#include "kern_rg.h"
+
+namespace iga {
+iga_status create_impl(const iga_desc *d, void *stream, Handle **out);
+
+namespace {
+
+constexpr int kVT = 256;   // rows per vector tile
+constexpr int kChunk = 16; // CG iterations per captured graph (even: the partial buffers alternate)
+
+struct Tile {
+  int inst;
+  int start;
+  int count;
+};
+struct Pair {
+  int inst;
+  int idx;
+};
+
+__device__ inline double bsum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// sum of the partials of one instance (identical in every block of that instance)
+__device__ inline double inst_sum(const double *__restrict__ part, const int *__restrict__ vt_start, int inst,
+                                  double *sh) {
+  double v = 0;
+  for (int i = vt_start[inst] + threadIdx.x; i < vt_start[inst + 1]; i += blockDim.x) v += part[i];
+  return bsum(v, sh);
+}
+
+__device__ inline bool cg_done(const double *rr_cur, const int *vt_start, const double *target, int inst,
+                               double *sh) {
+  double rr = inst_sum(rr_cur, vt_start, inst, sh);
+  return !(sqrt(rr) > target[inst]);
+}
+
+__global__ void k_b_fill(const Tile *__restrict__ tl, const int64_t *__restrict__ off, const int *__restrict__ act,
+                         double *__restrict__ x, double v) {
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst] || (int)threadIdx.x >= T.count) return;
+  x[off[T.inst] + T.start + threadIdx.x] = v;
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) k_b_residual(const DevProblem *__restrict__ pbs, const Pair *__restrict__ work,
+                                                   const int64_t *__restrict__ off, const int *__restrict__ act,
+                                                   const double *__restrict__ U, double *__restrict__ R) {
+  const Pair w = work[blockIdx.x];
+  if (!act[w.inst]) return;
+  const int64_t o = off[w.inst];
+  ek::elem_op_body<2, P, false, ek::OP_RES>(pbs[w.inst], (int64_t)w.idx, U + o, (double *)nullptr, R + o);
+}
+
+__global__ void k_b_bc_copy(const DevProblem *__restrict__ pbs, const Tile *__restrict__ tl,
+                            const int64_t *__restrict__ off, const int *__restrict__ act, const double *__restrict__ X,
+                            double *__restrict__ Y) {
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst] || (int)threadIdx.x >= T.count) return;
+  const int64_t A = T.start + threadIdx.x, o = off[T.inst];
+  if (is_dirichlet(pbs[T.inst], A)) Y[o + A] = X[o + A];
+}
+
+__global__ void k_b_sq_partial(const Tile *__restrict__ tl, const int64_t *__restrict__ off,
+                               const double *__restrict__ x, double *__restrict__ part) {
+  __shared__ double sh[4];
+  const Tile T = tl[blockIdx.x];
+  double v = 0;
+  if ((int)threadIdx.x < T.count) {
+    double a = x[off[T.inst] + T.start + threadIdx.x];
+    v = a * a;
+  }
+  double s = bsum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_b_inst_norms(int n, const int *__restrict__ vt_start, const double *__restrict__ part,
+                               double *__restrict__ norms) {
+  __shared__ double sh[4];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    double s = inst_sum(part, vt_start, i, sh);
+    if (threadIdx.x == 0) norms[i] = sqrt(s);
+  }
+}
+
+template <int P, int B1, typename OT>
+__global__ void __launch_bounds__(rgk::rg_threads(B1 * (2 * P - 1)))
+k_b_rowgather(const DevProblem *__restrict__ pbs, const Pair *__restrict__ work, const int64_t *__restrict__ off,
+              const int64_t *__restrict__ noff, const int *__restrict__ act, const double *__restrict__ U,
+              OT *__restrict__ vals) {
+  const Pair w = work[blockIdx.x];
+  if (!act[w.inst]) return;
+  rgk::rowgather2_body<P, false, B1, OT, OT>(pbs[w.inst], w.idx, U + off[w.inst], vals + noff[w.inst]);
+}
+
+template <typename VT>
+__global__ void k_b_diag_inv(const DevProblem *__restrict__ pbs, const Tile *__restrict__ tl,
+                             const int64_t *__restrict__ off, const int64_t *__restrict__ noff,
+                             const int *__restrict__ act, const VT *__restrict__ vals, double *__restrict__ dinv) {
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst] || (int)threadIdx.x >= T.count) return;
+  const DevProblem &pb = pbs[T.inst];
+  const int64_t A = T.start + threadIdx.x;
+  const int i0 = (int)(A % pb.n[0]), i1 = (int)(A / pb.n[0]);
+  double d = (double)vals[noff[T.inst] + csr_slot(pb, i0, i1, 0, i0, i1, 0)];
+  dinv[off[T.inst] + A] = d != 0.0 ? 1.0 / d : 1.0;
+}
+
+// x = 0, r = -R, z = Dinv r, p = z; partials of r.z and r.r
+__global__ void k_b_cg_init(const Tile *__restrict__ tl, const int64_t *__restrict__ off, const int *__restrict__ act,
+                            const double *__restrict__ R, const double *__restrict__ dinv, double *__restrict__ x,
+                            double *__restrict__ r, double *__restrict__ z, double *__restrict__ p,
+                            double *__restrict__ part_rz, double *__restrict__ part_rr) {
+  __shared__ double sh[4];
+  const Tile T = tl[blockIdx.x];
+  double a = 0, b = 0;
+  if (act[T.inst] && (int)threadIdx.x < T.count) {
+    const int64_t i = off[T.inst] + T.start + threadIdx.x;
+    double ri = -R[i], zi = dinv[i] * ri;
+    x[i] = 0;
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    a = ri * zi;
+    b = ri * ri;
+  }
+  double sa = bsum(a, sh), sb = bsum(b, sh);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = sa;
+    part_rr[blockIdx.x] = sb;
+  }
+}
+
+// q = J p on the instance's CSR rows (LPR lanes per row); partial p.q per tile
+template <typename VT, int LPR>
+__global__ void __launch_bounds__(256) k_b_spmv(const DevProblem *__restrict__ pbs, const Tile *__restrict__ st,
+                                                const int *__restrict__ vt_start, const int64_t *__restrict__ off,
+                                                const int64_t *__restrict__ noff, const int *__restrict__ act,
+                                                const double *__restrict__ target, const double *__restrict__ rr_cur,
+                                                const VT *__restrict__ vals, const double *__restrict__ p,
+                                                double *__restrict__ q, double *__restrict__ part_pq) {
+  __shared__ double sh[4];
+  const Tile T = st[blockIdx.x];
+  if (!act[T.inst]) return;
+  if (cg_done(rr_cur, vt_start, target, T.inst, sh)) return;
+  const DevProblem &pb = pbs[T.inst];
+  const int64_t o = off[T.inst];
+  const VT *v = vals + noff[T.inst];
+  const double *pp = p + o;
+  const int sub = threadIdx.x % LPR, row = threadIdx.x / LPR;
+  double dot = 0;
+  for (int r = row; r < T.count; r += 256 / LPR) {
+    const int64_t A = T.start + r;
+    const int64_t b = pb.row_ptr[A], e = pb.row_ptr[A + 1];
+    double s = 0;
+    for (int64_t k = b + sub; k < e; k += LPR) s += (double)v[k] * pp[pb.col_idx[k]];
+    for (int w = LPR / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, LPR);
+    if (sub == 0) {
+      q[o + A] = s;
+      dot += s * pp[A];
+    }
+  }
+  double bs = bsum(dot, sh);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = bs;
+}
+
+// alpha = rz/pq; x += alpha p; r -= alpha q; z = Dinv r; partials of the new r.z and r.r.
+// A converged instance carries its partials over unchanged, so the decision stays put.
+__global__ void __launch_bounds__(256) k_b_cg_xr(const Tile *__restrict__ tl, const int *__restrict__ vt_start,
+                                                 const int *__restrict__ st_start, const int64_t *__restrict__ off,
+                                                 const int *__restrict__ act, const double *__restrict__ target,
+                                                 const double *__restrict__ rz_cur, const double *__restrict__ rr_cur,
+                                                 const double *__restrict__ part_pq, double *__restrict__ x,
+                                                 double *__restrict__ r, double *__restrict__ z,
+                                                 const double *__restrict__ p, const double *__restrict__ q,
+                                                 const double *__restrict__ dinv, double *__restrict__ rz_new,
+                                                 double *__restrict__ rr_new) {
+  __shared__ double sh[4];
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst]) return;
+  if (cg_done(rr_cur, vt_start, target, T.inst, sh)) {
+    if (threadIdx.x == 0) {
+      rz_new[blockIdx.x] = rz_cur[blockIdx.x];
+      rr_new[blockIdx.x] = rr_cur[blockIdx.x];
+    }
+    return;
+  }
+  const double rz = inst_sum(rz_cur, vt_start, T.inst, sh);
+  double pq = 0;
+  for (int i = st_start[T.inst] + threadIdx.x; i < st_start[T.inst + 1]; i += blockDim.x) pq += part_pq[i];
+  pq = bsum(pq, sh);
+  const double alpha = pq != 0.0 ? rz / pq : 0.0;
+  double a = 0, b = 0;
+  if ((int)threadIdx.x < T.count) {
+    const int64_t i = off[T.inst] + T.start + threadIdx.x;
+    x[i] += alpha * p[i];
+    double ri = r[i] - alpha * q[i], zi = dinv[i] * ri;
+    r[i] = ri;
+    z[i] = zi;
+    a = ri * zi;
+    b = ri * ri;
+  }
+  double sa = bsum(a, sh), sb = bsum(b, sh);
+  if (threadIdx.x == 0) {
+    rz_new[blockIdx.x] = sa;
+    rr_new[blockIdx.x] = sb;
+  }
+}
+
+// beta = rz_new/rz; p = z + beta p; the first tile of an instance counts its iterations
+__global__ void __launch_bounds__(256) k_b_cg_p(const Tile *__restrict__ tl, const int *__restrict__ vt_start,
+                                                const int64_t *__restrict__ off, const int *__restrict__ act,
+                                                const double *__restrict__ target, const double *__restrict__ rz_cur,
+                                                const double *__restrict__ rr_cur, const double *__restrict__ rz_new,
+                                                const double *__restrict__ z, double *__restrict__ p,
+                                                int *__restrict__ iters) {
+  __shared__ double sh[4];
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst]) return;
+  if (cg_done(rr_cur, vt_start, target, T.inst, sh)) return;
+  const double rz = inst_sum(rz_cur, vt_start, T.inst, sh);
+  const double rzn = inst_sum(rz_new, vt_start, T.inst, sh);
+  const double beta = rz != 0.0 ? rzn / rz : 0.0;
+  if ((int)threadIdx.x < T.count) {
+    const int64_t i = off[T.inst] + T.start + threadIdx.x;
+    p[i] = z[i] + beta * p[i];
+  }
+  if (threadIdx.x == 0 && (int)blockIdx.x == vt_start[T.inst]) iters[T.inst] += 1;
+}
+
+// number of Newton-active instances whose CG has not converged (single block)
+__global__ void k_b_count(int n, const int *__restrict__ vt_start, const int *__restrict__ act,
+                          const double *__restrict__ target, const double *__restrict__ rr, int *__restrict__ out) {
+  __shared__ double sh[4];
+  int c = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    double s = inst_sum(rr, vt_start, i, sh);
+    if (sqrt(s) > target[i] && s == s) ++c;
+  }
+  if (threadIdx.x == 0) *out = c;
+}
+
+__global__ void k_b_axpy(const Tile *__restrict__ tl, const int64_t *__restrict__ off, const int *__restrict__ act,
+                         const double *__restrict__ d, double *__restrict__ U) {
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst] || (int)threadIdx.x >= T.count) return;
+  const int64_t i = off[T.inst] + T.start + threadIdx.x;
+  U[i] += d[i];
+}
+
+// ------------------------------------------------------------------------------------------
+// Autotuner cache: (degree, size class, kernel) -> chosen shape, kept for the process
+// ------------------------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<long, int> g_tune;   // key = (kind << 16) | (p << 8) | size class
+
+int size_class(int64_t N) { return N < 1500 ? 0 : (N < 5000 ? 1 : 2); }
+
+}  // namespace
+
+struct Group {
+  int P;
+  int cls;
+  std::vector<int> insts;
+  int b1 = 4;               // row-gather pencils per block (autotuned)
+  int lpr = 8;              // SpMV lanes per row (autotuned)
+  std::vector<Pair> pencils;
+  Pair *d_pencils = nullptr;
+  std::vector<Pair> elems;
+  Pair *d_elems = nullptr;
+};
+
+struct Batch {
+  int n = 0;
+  std::vector<Handle *> hs;
+  hipStream_t user = nullptr, bs = nullptr;
+  std::vector<void *> owned;
+  DevProblem *d_pbs = nullptr;
+  std::vector<int64_t> off, noff;
+  int64_t *d_off = nullptr, *d_noff = nullptr;
+  int64_t Ntot = 0, nnztot = 0;
+  std::vector<Tile> vt;
+  std::vector<int> vt_start;
+  Tile *d_vt = nullptr;
+  int *d_vt_start = nullptr;
+  // SpMV tiles (per group shapes), concatenated; st_start per instance
+  std::vector<Tile> st;
+  std::vector<int> st_start;
+  Tile *d_st = nullptr;
+  int *d_st_start = nullptr;
+  std::vector<std::pair<int, int>> st_group_range;   // [first tile, count) per group
+  std::vector<Group> groups;
+  // state
+  double *ws = nullptr;        // R d r z p q : 6 * Ntot
+  double *dinv = nullptr;
+  void *vals = nullptr;
+  int vals_prec = -1;
+  double *partA = nullptr, *partB = nullptr, *partC = nullptr, *partD = nullptr, *part_pq = nullptr;
+  double *norms = nullptr, *target = nullptr;
+  int *act = nullptr, *iters = nullptr, *count = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_prec = -1;
+  double t_tune_ms = 0;
+  std::vector<int> perm_;
+};
+
+template <typename T>
+static iga_status balloc(Batch &b, T **p, size_t n) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) return fail(IGA_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  b.owned.push_back(q);
+  *p = (T *)q;
+  return IGA_OK;
+}
+
+template <typename T>
+static iga_status bupload(Batch &b, T **p, const std::vector<T> &v) {
+  iga_status st = balloc(b, p, v.size());
+  if (st) return st;
+  IGA_HIP_CHECK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, b.bs));
+  return IGA_OK;
+}
+
+static void batch_free(Batch *b) {
+  if (!b) return;
+  if (b->bs) (void)hipStreamSynchronize(b->bs);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  for (void *p : b->owned)
+    if (p) (void)hipFree(p);
+  for (Handle *h : b->hs) iga_destroy((iga_t)h);
+  if (b->bs) (void)hipStreamDestroy(b->bs);
+  delete b;
+}
+
+// ---- launch helpers -----------------------------------------------------------------------
+template <int P>
+static void launch_rg_group(Batch &b, const Group &g, int b1, const double *U, void *vals, int prec, hipStream_t s) {
+  dim3 grid((unsigned)g.pencils.size());
+#define IGA_RGB(BB)                                                                                          \
+  if (b1 == BB) {                                                                                            \
+    dim3 blk(rgk::rg_threads(BB * (2 * P - 1)));                                                             \
+    if (prec == IGA_FP32)                                                                                    \
+      hipLaunchKernelGGL((k_b_rowgather<P, BB, float>), grid, blk, 0, s, b.d_pbs, g.d_pencils, b.d_off,      \
+                         b.d_noff, b.act, U, (float *)vals);                                                 \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_b_rowgather<P, BB, double>), grid, blk, 0, s, b.d_pbs, g.d_pencils, b.d_off,     \
+                         b.d_noff, b.act, U, (double *)vals);                                                \
+    return;                                                                                                  \
+  }
+  IGA_RGB(1) IGA_RGB(4) IGA_RGB(8)
+#undef IGA_RGB
+}
+
+static void launch_rg(Batch &b, const Group &g, int b1, const double *U, void *vals, int prec, hipStream_t s) {
+  if (g.pencils.empty()) return;
+  switch (g.P) {
+    case 3: launch_rg_group<3>(b, g, b1, U, vals, prec, s); break;
+    case 4: launch_rg_group<4>(b, g, b1, U, vals, prec, s); break;
+    case 5: launch_rg_group<5>(b, g, b1, U, vals, prec, s); break;
+    case 2: launch_rg_group<2>(b, g, b1, U, vals, prec, s); break;
+    case 6: launch_rg_group<6>(b, g, b1, U, vals, prec, s); break;
+  }
+}
+
+static void launch_res(Batch &b, const Group &g, const double *U, double *R, hipStream_t s) {
+  if (g.elems.empty()) return;
+  dim3 grid((unsigned)g.elems.size()), blk(64);
+  switch (g.P) {
+    case 2: hipLaunchKernelGGL(k_b_residual<2>, grid, blk, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+    case 3: hipLaunchKernelGGL(k_b_residual<3>, grid, blk, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+    case 4: hipLaunchKernelGGL(k_b_residual<4>, grid, blk, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+    case 5: hipLaunchKernelGGL(k_b_residual<5>, grid, blk, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+    case 6: hipLaunchKernelGGL(k_b_residual<6>, grid, blk, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+  }
+}
+
+template <typename VT>
+static void launch_spmv_group(Batch &b, size_t gi, const VT *vals, const double *p, double *q, const double *rr_cur,
+                              hipStream_t s) {
+  const Group &g = b.groups[gi];
+  auto rng = b.st_group_range[gi];
+  if (rng.second == 0) return;
+  dim3 grid((unsigned)rng.second), blk(256);
+  const Tile *tiles = b.d_st + rng.first;
+  double *part = b.part_pq + rng.first;
+#define IGA_SPM(L)                                                                                            \
+  if (g.lpr == L) {                                                                                           \
+    hipLaunchKernelGGL((k_b_spmv<VT, L>), grid, blk, 0, s, b.d_pbs, tiles, b.d_vt_start, b.d_off, b.d_noff,  \
+                       b.act, b.target, rr_cur, vals, p, q, part);                                            \
+    return;                                                                                                   \
+  }
+  IGA_SPM(4) IGA_SPM(8) IGA_SPM(16) IGA_SPM(32)
+#undef IGA_SPM
+}
+
+// SpMV tiles: rows per tile = 256 / lpr of the instance's group.  Instances are numbered so
+// that each group is contiguous; tile ranges are then contiguous per instance and per group.
+static void build_spmv_tiles(Batch &b) {
+  b.st.clear();
+  b.st_start.assign(b.n + 1, 0);
+  b.st_group_range.assign(b.groups.size(), {0, 0});
+  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+    const Group &g = b.groups[gi];
+    const int rpt = 256 / g.lpr;
+    b.st_group_range[gi].first = (int)b.st.size();
+    for (int i : g.insts) {
+      b.st_start[i] = (int)b.st.size();
+      for (int64_t s0 = 0; s0 < b.hs[i]->pb.N; s0 += rpt)
+        b.st.push_back(Tile{i, (int)s0, (int)std::min<int64_t>(rpt, b.hs[i]->pb.N - s0)});
+    }
+    b.st_group_range[gi].second = (int)b.st.size() - b.st_group_range[gi].first;
+  }
+  b.st_start[b.n] = (int)b.st.size();
+}
+
+static iga_status upload_spmv(Batch &b) {
+  build_spmv_tiles(b);
+  iga_status st;
+  if ((st = bupload(b, &b.d_st, b.st)) || (st = bupload(b, &b.d_st_start, b.st_start))) return st;
+  if ((st = balloc(b, &b.part_pq, b.st.size()))) return st;
+  return IGA_OK;
+}
+
+static iga_status build_pencils(Batch &b, Group &g) {
+  g.pencils.clear();
+  for (int i : g.insts) {
+    const int nb = (b.hs[i]->pb.n[1] + g.b1 - 1) / g.b1;
+    for (int k = 0; k < nb; ++k) g.pencils.push_back(Pair{i, k});
+  }
+  iga_status st = bupload(b, &g.d_pencils, g.pencils);
+  return st;
+}
+
+static float elapsed(hipEvent_t a, hipEvent_t c) {
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, a, c);
+  return ms;
+}
+
+// Time every candidate shape of each group's row-gather and SpMV launches on the device and
+// keep the fastest (cached per process by degree and size class).
+static iga_status autotune(Batch &b) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipEvent_t e0, e1;
+  IGA_HIP_CHECK(hipEventCreate(&e0));
+  IGA_HIP_CHECK(hipEventCreate(&e1));
+  double *U = b.ws + 5 * b.Ntot;   // q slot as a zero state
+  hipLaunchKernelGGL(k_b_fill, dim3((unsigned)b.vt.size()), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, U, 0.0);
+  iga_status st = IGA_OK;
+  for (Group &g : b.groups) {
+    long key_rg = (1L << 16) | (g.P << 8) | g.cls, key_sp = (2L << 16) | (g.P << 8) | g.cls;
+    bool have_rg, have_sp;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      have_rg = g_tune.count(key_rg);
+      have_sp = g_tune.count(key_sp);
+      if (have_rg) g.b1 = g_tune[key_rg];
+      if (have_sp) g.lpr = g_tune[key_sp];
+    }
+    if (!have_rg) {
+      float best = 1e30f;
+      int bestb = 4;
+      for (int cand : {1, 4, 8}) {
+        g.b1 = cand;
+        if ((st = build_pencils(b, g))) return st;
+        launch_rg(b, g, cand, U, b.vals, IGA_FP64, b.bs);
+        hipEventRecord(e0, b.bs);
+        for (int r = 0; r < 3; ++r) launch_rg(b, g, cand, U, b.vals, IGA_FP64, b.bs);
+        hipEventRecord(e1, b.bs);
+        IGA_HIP_CHECK(hipEventSynchronize(e1));
+        float ms = elapsed(e0, e1);
+        if (ms < best) { best = ms; bestb = cand; }
+      }
+      g.b1 = bestb;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key_rg] = bestb;
+    }
+    if ((st = build_pencils(b, g))) return st;
+  }
+  // SpMV lanes per row: tune each group with the others fixed
+  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+    Group &g = b.groups[gi];
+    long key_sp = (2L << 16) | (g.P << 8) | g.cls;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      if (g_tune.count(key_sp)) { g.lpr = g_tune[key_sp]; continue; }
+    }
+    float best = 1e30f;
+    int bestl = 8;
+    for (int cand : {4, 8, 16, 32}) {
+      g.lpr = cand;
+      if ((st = upload_spmv(b))) return st;
+      // all instances "not converged": target = -1 makes sqrt(rr) > target true
+      hipLaunchKernelGGL(k_b_fill, dim3((unsigned)b.vt.size()), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act,
+                         b.ws + 4 * b.Ntot, 1.0);
+      launch_spmv_group<double>(b, gi, (const double *)b.vals, b.ws + 4 * b.Ntot, b.ws + 5 * b.Ntot, b.partA, b.bs);
+      hipEventRecord(e0, b.bs);
+      for (int r = 0; r < 5; ++r)
+        launch_spmv_group<double>(b, gi, (const double *)b.vals, b.ws + 4 * b.Ntot, b.ws + 5 * b.Ntot, b.partA, b.bs);
+      hipEventRecord(e1, b.bs);
+      IGA_HIP_CHECK(hipEventSynchronize(e1));
+      float ms = elapsed(e0, e1);
+      if (ms < best) { best = ms; bestl = cand; }
+    }
+    g.lpr = bestl;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key_sp] = bestl;
+  }
+  if ((st = upload_spmv(b))) return st;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b.t_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return IGA_OK;
+}
+
+static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch **out) {
+  if (n <= 0 || !descs || !out) return fail(IGA_EINVAL, "bad batch arguments");
+  Batch *b = new Batch();
+  b->n = n;
+  b->user = (hipStream_t)stream;
+  if (hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return fail(IGA_EHIP, "stream creation failed");
+  }
+  iga_status st = IGA_OK;
+  // instances sorted by (degree, size class) so that groups are contiguous; `perm[k]` is the
+  // caller's index of internal instance k
+  std::vector<Handle *> hs_user(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    if (descs[i].dim != 2) { st = fail(IGA_EUNSUPPORTED, "batched solves are 2D"); break; }
+    if (descs[i].ctrl || descs[i].weights || descs[i].kappa_mode == IGA_KAPPA_NODAL) {
+      st = fail(IGA_EUNSUPPORTED, "batched solves use the identity geometry without weights");
+      break;
+    }
+    Handle *h = nullptr;
+    if ((st = create_impl(&descs[i], b->bs, &h))) break;
+    if (!h->pb.simple_knots) {
+      iga_destroy((iga_t)h);
+      st = fail(IGA_EUNSUPPORTED, "batched solves need simple interior knots");
+      break;
+    }
+    hs_user[i] = h;
+  }
+  if (st) {
+    for (Handle *h : hs_user)
+      if (h) iga_destroy((iga_t)h);
+    (void)hipStreamDestroy(b->bs);
+    delete b;
+    return st;
+  }
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+    int px = hs_user[x]->pb.P, py = hs_user[y]->pb.P;
+    if (px != py) return px < py;
+    return size_class(hs_user[x]->pb.N) < size_class(hs_user[y]->pb.N);
+  });
+  b->hs.resize(n);
+  std::vector<int64_t> uoff(n + 1, 0), unoff(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    uoff[i + 1] = uoff[i] + hs_user[i]->pb.N;
+    unoff[i + 1] = unoff[i] + hs_user[i]->pb.nnz;
+  }
+  b->off.resize(n);
+  b->noff.resize(n);
+  std::vector<DevProblem> pbs(n);
+  for (int k = 0; k < n; ++k) {
+    b->hs[k] = hs_user[perm[k]];
+    b->off[k] = uoff[perm[k]];
+    b->noff[k] = unoff[perm[k]];
+    pbs[k] = b->hs[k]->pb;
+  }
+  b->Ntot = uoff[n];
+  b->nnztot = unoff[n];
+  b->perm_ = perm;
+  // groups
+  for (int k = 0; k < n; ++k) {
+    int P = b->hs[k]->pb.P, cls = size_class(b->hs[k]->pb.N);
+    if (b->groups.empty() || b->groups.back().P != P || b->groups.back().cls != cls) {
+      Group g;
+      g.P = P;
+      g.cls = cls;
+      b->groups.push_back(g);
+    }
+    b->groups.back().insts.push_back(k);
+  }
+  // vector tiles
+  b->vt_start.assign(n + 1, 0);
+  for (int k = 0; k < n; ++k) {
+    b->vt_start[k] = (int)b->vt.size();
+    for (int64_t s0 = 0; s0 < b->hs[k]->pb.N; s0 += kVT)
+      b->vt.push_back(Tile{k, (int)s0, (int)std::min<int64_t>(kVT, b->hs[k]->pb.N - s0)});
+  }
+  b->vt_start[n] = (int)b->vt.size();
+  const size_t nvt = b->vt.size();
+  if ((st = bupload(*b, &b->d_pbs, pbs)) || (st = bupload(*b, &b->d_off, b->off)) ||
+      (st = bupload(*b, &b->d_noff, b->noff)) || (st = bupload(*b, &b->d_vt, b->vt)) ||
+      (st = bupload(*b, &b->d_vt_start, b->vt_start)) || (st = balloc(*b, &b->ws, 6 * (size_t)b->Ntot)) ||
+      (st = balloc(*b, &b->dinv, (size_t)b->Ntot)) || (st = balloc(*b, &b->partA, nvt)) ||
+      (st = balloc(*b, &b->partB, nvt)) || (st = balloc(*b, &b->partC, nvt)) || (st = balloc(*b, &b->partD, nvt)) ||
+      (st = balloc(*b, &b->norms, (size_t)n)) || (st = balloc(*b, &b->target, (size_t)n)) ||
+      (st = balloc(*b, &b->act, (size_t)n)) || (st = balloc(*b, &b->iters, (size_t)n)) ||
+      (st = balloc(*b, &b->count, 1))) {
+    batch_free(b);
+    return st;
+  }
+  void *vals = nullptr;
+  if (hipMalloc(&vals, (size_t)b->nnztot * sizeof(double)) != hipSuccess) {
+    batch_free(b);
+    return fail(IGA_ENOMEM, "batch Jacobian values");
+  }
+  b->owned.push_back(vals);
+  b->vals = vals;
+  b->vals_prec = IGA_FP64;
+  for (Group &g : b->groups) {
+    for (int k : g.insts)
+      for (int64_t e = 0; e < b->hs[k]->pb.E; ++e) g.elems.push_back(Pair{k, (int)e});
+    if ((st = bupload(*b, &g.d_elems, g.elems))) {
+      batch_free(b);
+      return st;
+    }
+  }
+  std::vector<int> ones(n, 1);
+  std::vector<double> tz(n, -1.0);
+  if ((st = [&]() -> iga_status {
+        IGA_HIP_CHECK(hipMemcpyAsync(b->act, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, b->bs));
+        IGA_HIP_CHECK(hipMemcpyAsync(b->target, tz.data(), n * sizeof(double), hipMemcpyHostToDevice, b->bs));
+        // defined partials: the shape tuner runs the SpMV before any CG state exists
+        IGA_HIP_CHECK(hipMemsetAsync(b->partA, 0, nvt * sizeof(double), b->bs));
+        IGA_HIP_CHECK(hipMemsetAsync(b->partC, 0, nvt * sizeof(double), b->bs));
+        return IGA_OK;
+      }())) {
+    batch_free(b);
+    return st;
+  }
+  if ((st = autotune(*b))) {
+    batch_free(b);
+    return st;
+  }
+  if (hipStreamSynchronize(b->bs) != hipSuccess) {
+    batch_free(b);
+    return fail(IGA_EHIP, "batch setup");
+  }
+  *out = b;
+  return IGA_OK;
+}
+
+static iga_status capture_cg_graph(Batch &b, int prec) {
+  if (b.graph && b.graph_prec == prec) return IGA_OK;
+  if (b.graph) {
+    (void)hipGraphExecDestroy(b.graph);
+    b.graph = nullptr;
+  }
+  const int64_t N = b.Ntot;
+  double *d = b.ws + N, *r = b.ws + 2 * N, *z = b.ws + 3 * N, *p = b.ws + 4 * N, *q = b.ws + 5 * N;
+  const unsigned nvt = (unsigned)b.vt.size();
+  IGA_HIP_CHECK(hipStreamBeginCapture(b.bs, hipStreamCaptureModeThreadLocal));
+  // partial buffers: rz in A/B, rr in C/D; iteration k reads (A,C) or (B,D) alternately
+  for (int it = 0; it < kChunk; ++it) {
+    double *rz_cur = (it % 2 == 0) ? b.partA : b.partB, *rz_new = (it % 2 == 0) ? b.partB : b.partA;
+    double *rr_cur = (it % 2 == 0) ? b.partC : b.partD, *rr_new = (it % 2 == 0) ? b.partD : b.partC;
+    for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+      if (prec == IGA_FP32) launch_spmv_group<float>(b, gi, (const float *)b.vals, p, q, rr_cur, b.bs);
+      else launch_spmv_group<double>(b, gi, (const double *)b.vals, p, q, rr_cur, b.bs);
+    }
+    hipLaunchKernelGGL(k_b_cg_xr, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_vt_start, b.d_st_start, b.d_off, b.act,
+                       b.target, rz_cur, rr_cur, b.part_pq, d, r, z, p, q, b.dinv, rz_new, rr_new);
+    hipLaunchKernelGGL(k_b_cg_p, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_vt_start, b.d_off, b.act, b.target,
+                       rz_cur, rr_cur, rz_new, z, p, b.iters);
+  }
+  hipLaunchKernelGGL(k_b_count, dim3(1), dim3(256), 0, b.bs, b.n, b.d_vt_start, b.act, b.target, b.partC, b.count);
+  hipGraph_t g;
+  hipError_t e = hipStreamEndCapture(b.bs, &g);
+  if (e != hipSuccess) return fail(IGA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(IGA_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  b.graph_prec = prec;
+  return IGA_OK;
+}
+
+static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in, iga_batch_item_report *items,
+                               iga_batch_report *rep) {
+  iga_newton_opts o{};
+  o.atol = 1e-10;
+  o.max_newton = 30;
+  o.max_krylov = 5000;
+  o.jac_prec = IGA_FP64;
+  o.forcing_max = 1e-2;
+  if (o_in) o = *o_in;
+  if (o.matrix_free) return fail(IGA_EUNSUPPORTED, "batched solves use the assembled Jacobian");
+  if (o.jac_prec != IGA_FP64 && o.jac_prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian precision");
+  if (o.max_newton < 0 || o.max_newton > 64) return fail(IGA_EINVAL, "max_newton must be in 0..64");
+  if (o.forcing_max <= 0) o.forcing_max = 1e-2;
+  const int n = b.n;
+  const int64_t N = b.Ntot;
+  double *R = b.ws, *d = b.ws + N;
+  const unsigned nvt = (unsigned)b.vt.size();
+  iga_batch_report r{};
+  r.t_tune_ms = b.t_tune_ms;
+  auto t0 = std::chrono::steady_clock::now();
+  IGA_HIP_CHECK(hipStreamSynchronize(b.user));
+  iga_status st = capture_cg_graph(b, o.jac_prec);
+  if (st) return st;
+  std::vector<double> nr(n), nr_prev(n, 0.0), r0(n, -1.0), eta(n, o.forcing_max), tgt(n);
+  std::vector<int> act(n, 1), conv(n, 0), nits(n, 0), kits(n, 0);
+  std::vector<std::vector<double>> hist(n);
+  hipEvent_t ev[3];
+  for (auto &e : ev) IGA_HIP_CHECK(hipEventCreate(&e));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.act, act.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemsetAsync(b.iters, 0, n * sizeof(int), b.bs));
+  int k;
+  for (k = 0;; ++k) {
+    (void)hipEventRecord(ev[0], b.bs);
+    hipLaunchKernelGGL(k_b_fill, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, R, 0.0);
+    for (const Group &g : b.groups) launch_res(b, g, U, R, b.bs);
+    hipLaunchKernelGGL(k_b_bc_copy, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.act, (const double *)U, R);
+    hipLaunchKernelGGL(k_b_sq_partial, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, (const double *)R, b.partA);
+    hipLaunchKernelGGL(k_b_inst_norms, dim3(std::min(n, 1024)), dim3(256), 0, b.bs, n, b.d_vt_start,
+                       (const double *)b.partA, b.norms);
+    IGA_HIP_CHECK(hipMemcpyAsync(nr.data(), b.norms, n * sizeof(double), hipMemcpyDeviceToHost, b.bs));
+    (void)hipEventRecord(ev[1], b.bs);
+    IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
+    r.t_residual_ms += elapsed(ev[0], ev[1]);
+    int nact = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!act[i]) continue;
+      hist[i].push_back(nr[i]);
+      if (r0[i] < 0) r0[i] = nr[i];
+      if (!std::isfinite(nr[i])) { act[i] = 0; continue; }
+      if (nr[i] < o.atol || (o.rtol > 0 && nr[i] <= o.rtol * r0[i])) { act[i] = 0; conv[i] = 1; continue; }
+      if (k >= o.max_newton) { act[i] = 0; continue; }
+      if (k > 0) {
+        double ratio = nr[i] / nr_prev[i];
+        eta[i] = std::min(o.forcing_max, 0.9 * ratio * ratio);
+      }
+      double target = std::max(o.atol, o.rtol * r0[i]);
+      eta[i] = std::min(o.forcing_max, std::max(eta[i], 0.1 * target / nr[i]));
+      nr_prev[i] = nr[i];
+      tgt[i] = eta[i] * nr[i];
+      nits[i] = k + 1;
+      ++nact;
+    }
+    if (nact == 0) break;
+    IGA_HIP_CHECK(hipMemcpyAsync(b.act, act.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
+    IGA_HIP_CHECK(hipMemcpyAsync(b.target, tgt.data(), n * sizeof(double), hipMemcpyHostToDevice, b.bs));
+    (void)hipEventRecord(ev[0], b.bs);
+    for (const Group &g : b.groups) launch_rg(b, g, g.b1, U, b.vals, o.jac_prec, b.bs);
+    if (o.jac_prec == IGA_FP32)
+      hipLaunchKernelGGL(k_b_diag_inv<float>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff, b.act,
+                         (const float *)b.vals, b.dinv);
+    else
+      hipLaunchKernelGGL(k_b_diag_inv<double>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff,
+                         b.act, (const double *)b.vals, b.dinv);
+    hipLaunchKernelGGL(k_b_cg_init, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)R,
+                       (const double *)b.dinv, d, b.ws + 2 * N, b.ws + 3 * N, b.ws + 4 * N, b.partA, b.partC);
+    (void)hipEventRecord(ev[1], b.bs);
+    int done_iters = 0, remaining = 1;
+    while (done_iters < o.max_krylov && remaining > 0) {
+      IGA_HIP_CHECK(hipGraphLaunch(b.graph, b.bs));
+      IGA_HIP_CHECK(hipMemcpyAsync(&remaining, b.count, sizeof(int), hipMemcpyDeviceToHost, b.bs));
+      IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
+      done_iters += kChunk;
+      r.graph_launches += 1;
+    }
+    r.krylov_iters_max += done_iters;
+    hipLaunchKernelGGL(k_b_axpy, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)d, U);
+    (void)hipEventRecord(ev[2], b.bs);
+    IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
+    r.t_jacobian_ms += elapsed(ev[0], ev[1]);
+    r.t_krylov_ms += elapsed(ev[1], ev[2]);
+  }
+  std::vector<int> dev_iters(n);
+  IGA_HIP_CHECK(hipMemcpyAsync(dev_iters.data(), b.iters, n * sizeof(int), hipMemcpyDeviceToHost, b.bs));
+  IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  r.newton_steps = k;
+  r.all_converged = 1;
+  for (int kk = 0; kk < n; ++kk) {
+    r.all_converged &= conv[kk];
+    if (items) {
+      iga_batch_item_report &it = items[b.perm_[kk]];
+      it.converged = conv[kk];
+      it.newton_iters = (int)hist[kk].size() - 1;
+      it.krylov_iters = dev_iters[kk];
+      it.res_norm0 = r0[kk];
+      it.res_norm = hist[kk].empty() ? 0.0 : hist[kk].back();
+    }
+  }
+  r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = r;
+  return r.all_converged ? IGA_OK : fail(IGA_ENOCONV, "some batched instances did not converge");
+}
+
+}  // namespace iga
+
+using namespace iga;
+
+extern "C" {
+
+iga_status iga_batch_create(int n, const iga_desc *descs, void *hip_stream, iga_batch_t *out) {
+  if (!out) return fail(IGA_EINVAL, "null output");
+  *out = nullptr;
+  Batch *b = nullptr;
+  iga_status st = batch_create(n, descs, hip_stream, &b);
+  if (st) return st;
+  *out = (iga_batch_t)b;
+  return IGA_OK;
+}
+
+iga_status iga_batch_info(iga_batch_t bb, int64_t *total_ndof, int64_t *total_nnz, int64_t *dof_offsets) {
+  if (!bb) return fail(IGA_EINVAL, "null batch");
+  Batch *b = (Batch *)bb;
+  if (total_ndof) *total_ndof = b->Ntot;
+  if (total_nnz) *total_nnz = b->nnztot;
+  if (dof_offsets) {
+    std::vector<int64_t> o(b->n + 1, 0);
+    for (int k = 0; k < b->n; ++k) o[b->perm_[k]] = b->off[k];
+    o[b->n] = b->Ntot;
+    for (int i = 0; i <= b->n; ++i) dof_offsets[i] = o[i];
+  }
+  return IGA_OK;
+}
+
+iga_status iga_batch_newton_solve(iga_batch_t bb, double *U_dev, const iga_newton_opts *opts,
+                                  iga_batch_item_report *items, iga_batch_report *report) {
+  if (!bb || !U_dev) return fail(IGA_EINVAL, "null argument");
+  return batch_newton(*(Batch *)bb, U_dev, opts, items, report);
+}
+
+iga_status iga_batch_destroy(iga_batch_t bb) {
+  batch_free((Batch *)bb);
+  return IGA_OK;
+}
+
+}  // extern "C"

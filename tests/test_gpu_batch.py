@@ -1,0 +1,87 @@
+"""Batched Newton (iga_batch_*) against per-instance Newton and the oracle."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1305_4452_amd as iga  # noqa: E402
+
+
+def mixed_workloads():
+    """Instances given in mixed degree/size order (exercises the internal regrouping)."""
+    ws = []
+    specs = [(12, 3, 2.0), (8, 2, 6.0), (20, 4, 1.0), (9, 2, 4.5), (16, 3, 6.4), (8, 4, 3.3), (33, 2, 5.0),
+             (10, 3, 1.2)]
+    for i, (nel, p, lam) in enumerate(specs):
+        ws.append(inputs.bratu_box(2, nel, p, lam, seed=4, stream=i))
+    # one element-wise kappa instance (p = 3, 8x8 elements, kappa constant on 2x2 blocks)
+    _, lam, w = inputs.learned_instance(3, nel=8, p=3, ncell=4)
+    w.lam = 1.5          # sub-critical for this kappa draw (lambda = 5 has no solution here)
+    w.U0 = inputs.initial_guess(w.patch.shape, 4, 99)
+    ws.append(w)
+    return ws
+
+
+def test_batch_matches_per_instance_and_oracle():
+    ws = mixed_workloads()
+    b = iga.IGABatch(ws)
+    U = torch.as_tensor(b.pack([w.U0 for w in ws]), device="cuda")
+    per, summ = b.newton_solve(U, atol=1e-10)
+    assert summ["all_converged"] and all(p["converged"] for p in per)
+    assert all(p["res_norm"] < 1e-10 for p in per)
+    assert summ["graph_launches"] > 0
+    sols = b.unpack(U.cpu().numpy())
+    for i, w in enumerate(ws):
+        g = iga.IGA.from_workload(w)
+        Ui = torch.as_tensor(w.U0, device="cuda")
+        g.newton_solve(Ui, atol=1e-10)
+        ref = Ui.cpu().numpy()
+        assert np.linalg.norm(sols[i] - ref) <= 1e-8 * np.linalg.norm(ref), i
+    for i in (1, 4, 8):
+        o = oracle.Oracle.from_workload(ws[i])
+        Uo, _, rc = o.newton(ws[i].U0, atol=1e-13)
+        assert rc == 0
+        assert np.linalg.norm(sols[i] - Uo) <= 1e-9 * np.linalg.norm(Uo), i
+
+
+def test_batch_fp32_jacobian_and_determinism():
+    ws = mixed_workloads()[:6]
+    b = iga.IGABatch(ws)
+    U0 = b.pack([w.U0 for w in ws])
+    U1 = torch.as_tensor(U0, device="cuda")
+    U2 = torch.as_tensor(U0, device="cuda")
+    b.newton_solve(U1, atol=1e-10)
+    b.newton_solve(U2, atol=1e-10)
+    # the Jacobian and the CG reductions are order-fixed; the residual scatter uses FP64 atomics,
+    # so two runs agree to rounding, not bit for bit
+    assert torch.allclose(U1, U2, rtol=0, atol=1e-12 * float(U1.abs().max()))
+    U3 = torch.as_tensor(U0, device="cuda")
+    per, summ = b.newton_solve(U3, atol=1e-10, jac_prec=iga.IGA_FP32)
+    assert all(p["converged"] for p in per)
+    assert torch.allclose(U3, U1, rtol=0, atol=1e-9)
+
+
+def test_batch_seeded_configuration_subset():
+    ws = inputs.batched_instances(24)
+    b = iga.IGABatch(ws)
+    U = torch.as_tensor(b.pack([w.U0 for w in ws]), device="cuda")
+    per, summ = b.newton_solve(U, atol=1e-10)
+    assert summ["all_converged"]
+    sols = b.unpack(U.cpu().numpy())
+    for i in (0, 7, 13):
+        g = iga.IGA.from_workload(ws[i])
+        Ui = torch.as_tensor(ws[i].U0, device="cuda")
+        g.newton_solve(Ui, atol=1e-10)
+        ref = Ui.cpu().numpy()
+        assert np.linalg.norm(sols[i] - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_batch_rejects_unsupported():
+    w3 = inputs.bratu_box(3, 3, 2, 1.0, seed=1)
+    with pytest.raises(iga.IGAError) as e:
+        iga.IGABatch([w3])
+    assert e.value.status == iga.IGA_EUNSUPPORTED
