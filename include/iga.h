@@ -186,6 +186,39 @@ iga_status iga_batch_newton_solve(iga_batch_t b, double *U_dev, const iga_newton
                                   iga_batch_item_report *items, iga_batch_report *report);
 iga_status iga_batch_destroy(iga_batch_t b);
 
+/* ---- learned initial guess ---------------------------------------------------------------
+ * A 4-layer convolutional encoder-decoder (conv 3x3 2->64, conv 3x3 stride 2 64->64, then the
+ * per-channel mean over the 16x16 pixels added back as global context, transposed conv 4x4
+ * stride 4 64->64, transposed conv 2x2 64->1; ReLU between layers) mapping
+ * a [2][32][32] input (log kappa on the 32x32 cells, lambda broadcast) to the 65x65 interior
+ * coefficients of the 64x64-element degree-3 problem.  BF16 weights and activations, FP32
+ * accumulation, FP32 master weights, Adam (beta 0.9/0.999, eps 1e-8), mean-squared-error loss.
+ * Parameters are one flat FP32 vector [W0 b0 W1 b1 W2 b2 W3 b3] (W0, W1: [co][ci][ky][kx];
+ * W2, W3: [ci][co][ky][kx]).  Inputs/outputs are caller-owned FP32 device buffers, batch-major. */
+typedef struct igann_s *igann_t;
+int64_t igann_num_params(void);
+/* Allocates weights, optimiser state and activations for batches of up to batch_max. */
+iga_status igann_create(int batch_max, void *hip_stream, igann_t *out);
+/* Host FP32 weights in and out (count must equal igann_num_params()); set also resets Adam. */
+iga_status igann_set_weights(igann_t net, const float *host, int64_t count);
+iga_status igann_get_weights(igann_t net, float *host, int64_t count);
+/* y[B][4225] = net(x[B][2][32][32]). */
+iga_status igann_forward(igann_t net, const float *x_dev, int B, float *y_dev);
+/* In place on y[B][4225]: y = (scale * y + mean) * sample_scale[n] (mean: device [4225], may be
+ * NULL; sample_scale: device [B], may be NULL), then `passes` times the separable [1 2 1]/4
+ * filter along each axis of the 65x65 coefficient grid with zero (the Dirichlet value) outside. */
+iga_status igann_postprocess(igann_t net, float *y_dev, int B, const float *mean_dev, float scale,
+                             const float *sample_scale_dev, int passes);
+/* Loss (mean squared error against t[B][4225]) and its gradient w.r.t. all parameters (host,
+ * igann_num_params() floats; may be NULL) without updating the weights.  Synchronous. */
+iga_status igann_gradients(igann_t net, const float *x_dev, const float *t_dev, int B, float *loss,
+                           float *grad_host);
+/* One Adam step with learning rate lr; *loss (may be NULL) gets the batch loss.  Synchronous
+ * when loss is non-NULL. */
+iga_status igann_train_step(igann_t net, const float *x_dev, const float *t_dev, int B, float lr,
+                            float *loss);
+iga_status igann_destroy(igann_t net);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *iga_last_error(void);
 

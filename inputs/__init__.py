@@ -14,6 +14,7 @@ or torch generator is used, so every draw is reproducible from its definition.
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 
@@ -228,6 +229,29 @@ def grf_rff(points: np.ndarray, seed: int, stream: int, var: float = 0.5, corr: 
     return math.sqrt(2.0 * var / nfeat) * out
 
 
+def grf_grid(n: int, seed: int, stream: int, var: float = 0.5, corr: float = 0.2, h: float | None = None) -> np.ndarray:
+    """Zero-mean field with covariance var*exp(-|x-y|^2/(2 corr^2)) at the centres of an n x n
+    grid of spacing h (default 1/n), by circulant embedding: the grid is embedded in a 2n x 2n
+    periodic grid (period 2 n h, so wrap-around correlation is exp(-(n h)^2/(2 corr^2)), below
+    1e-5 for n h = 1, corr = 0.2), the covariance's eigenvalues are its FFT, and the field is
+    the inverse FFT of sqrt(eigenvalues) times the FFT of white noise.  Returns [n, n] with axis 1
+    varying along x."""
+    h = 1.0 / n if h is None else h
+    m = 2 * n
+    xi = normal(seed, stream, m * m).reshape(m, m)
+    g = np.fft.ifft2(_grf_sqrt_eigs(n, h, var, corr) * np.fft.fft2(xi)).real
+    return g[:n, :n]
+
+
+@functools.lru_cache(maxsize=16)
+def _grf_sqrt_eigs(n: int, h: float, var: float, corr: float) -> np.ndarray:
+    m = 2 * n
+    d = np.minimum(np.arange(m), m - np.arange(m)) * h
+    r2 = d[:, None] ** 2 + d[None, :] ** 2
+    lam = np.fft.fft2(var * np.exp(-r2 / (2.0 * corr * corr))).real
+    return np.sqrt(np.maximum(lam, 0.0))
+
+
 # --------------------------------------------------------------------------------------------
 # Workload recipes (the configurations the tests and the benchmark use)
 # --------------------------------------------------------------------------------------------
@@ -312,11 +336,7 @@ def batched_instances(n: int = 512, seed: int = 4):
 def learned_instance(index: int, seed: int = 5, nel: int = 64, p: int = 3, ncell: int = 32):
     """Instance for the learned-guess workload: log kappa = GRF(0.5, 0.2) at the ncell^2 cell
     centres (kappa constant per cell = (nel/ncell)^2 elements), lambda ~ U[1,6]."""
-    h = 1.0 / ncell
-    c = (np.arange(ncell) + 0.5) * h
-    X, Y = np.meshgrid(c, c, indexing="xy")          # X varies along axis 0 (fastest)
-    pts = np.stack([X.reshape(-1), Y.reshape(-1)], axis=1)
-    logk = grf_rff(pts, seed=seed, stream=2 * index + 10, nfeat=1024).reshape(ncell, ncell)
+    logk = grf_grid(ncell, seed=seed, stream=2 * index + 10)        # [y][x]
     lam = float(uniform(seed, 7, 1, 1.0, 6.0, offset=index)[0])
     r = nel // ncell
     kel = np.exp(np.repeat(np.repeat(logk, r, axis=0), r, axis=1)).reshape(-1)   # element natural order

@@ -124,6 +124,16 @@ _SIGNATURES = {
     "iga_batch_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_batch_item_report),
                                 C.POINTER(iga_batch_report)], C.c_int),
     "iga_batch_destroy": ([C.c_void_p], C.c_int),
+    "igann_num_params": ([], C.c_int64),
+    "igann_create": ([C.c_int, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "igann_set_weights": ([C.c_void_p, C.POINTER(C.c_float), C.c_int64], C.c_int),
+    "igann_get_weights": ([C.c_void_p, C.POINTER(C.c_float), C.c_int64], C.c_int),
+    "igann_forward": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "igann_postprocess": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_float, C.c_void_p, C.c_int], C.c_int),
+    "igann_gradients": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+                        C.c_int),
+    "igann_train_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_float, C.POINTER(C.c_float)], C.c_int),
+    "igann_destroy": ([C.c_void_p], C.c_int),
     "iga_last_error": ([], C.c_char_p),
 }
 
@@ -378,3 +388,76 @@ class IGABatch:
         summary = {k: getattr(rep, k) for k, _ in iga_batch_report._fields_}
         summary["status"] = st
         return per, summary
+
+
+class GuessNet:
+    """Device network of the learned initial guess (igann_*)."""
+
+    def __init__(self, batch_max=256, stream=None):
+        import torch
+        L = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.bmax = batch_max
+        self.nparam = int(L.igann_num_params())
+        h = C.c_void_p()
+        _check(L.igann_create(int(batch_max), C.c_void_p(stream.cuda_stream), C.byref(h)), "igann_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().igann_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(load().igann_set_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size), "igann_set_weights")
+
+    def get_weights(self):
+        w = np.zeros(self.nparam, dtype=np.float32)
+        _check(load().igann_get_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size), "igann_get_weights")
+        return w
+
+    def forward(self, x, y=None):
+        import torch
+        B = x.shape[0]
+        if y is None:
+            y = torch.empty((B, 65 * 65), dtype=torch.float32, device="cuda")
+        _check(load().igann_forward(self.h, _dev_ptr(x, torch.float32, B * 2 * 32 * 32, "x"), B,
+                                    _dev_ptr(y, torch.float32, B * 65 * 65, "y")), "igann_forward")
+        return y
+
+    def postprocess(self, y, mean=None, scale=1.0, sample_scale=None, passes=0):
+        import torch
+        B = y.shape[0]
+        mp = None if mean is None else _dev_ptr(mean, torch.float32, 65 * 65, "mean")
+        sp = None if sample_scale is None else _dev_ptr(sample_scale, torch.float32, B, "sample_scale")
+        _check(load().igann_postprocess(self.h, _dev_ptr(y, torch.float32, B * 65 * 65, "y"), B, mp, float(scale),
+                                        sp, int(passes)), "igann_postprocess")
+        return y
+
+    def gradients(self, x, t):
+        import torch
+        B = x.shape[0]
+        g = np.zeros(self.nparam, dtype=np.float32)
+        loss = C.c_float()
+        _check(load().igann_gradients(self.h, _dev_ptr(x, torch.float32, B * 2 * 32 * 32, "x"),
+                                      _dev_ptr(t, torch.float32, B * 65 * 65, "t"), B, C.byref(loss),
+                                      g.ctypes.data_as(C.POINTER(C.c_float))), "igann_gradients")
+        return loss.value, g
+
+    def train_step(self, x, t, lr, want_loss=True):
+        import torch
+        B = x.shape[0]
+        loss = C.c_float()
+        _check(load().igann_train_step(self.h, _dev_ptr(x, torch.float32, B * 2 * 32 * 32, "x"),
+                                       _dev_ptr(t, torch.float32, B * 65 * 65, "t"), B, float(lr),
+                                       C.byref(loss) if want_loss else None), "igann_train_step")
+        return loss.value if want_loss else None

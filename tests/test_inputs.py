@@ -55,3 +55,13 @@ def test_cylinder_weights_and_sizes():
     for i0 in range(3):
         assert np.allclose(w[0, :, i0], [1.0, math.sqrt(0.5), 1.0], atol=1e-16)
     assert np.allclose(w[:, 0, :], 1.0)
+
+
+def test_grf_grid_statistics():
+    """Circulant-embedding field: variance 0.5 and correlation 0.5 exp(-1/2) at distance 0.2."""
+    fs = np.array([inputs.grf_grid(32, seed=9, stream=s) for s in range(400)])
+    assert abs(fs.var() - 0.5) < 0.05
+    lag = round(0.2 * 32)                       # 0.2 / h cells
+    c = np.mean(fs[:, :, :-lag] * fs[:, :, lag:])
+    assert abs(c - 0.5 * np.exp(-0.5 * (lag / 32 / 0.2) ** 2)) < 0.05
+    assert np.array_equal(inputs.grf_grid(32, 9, 3), inputs.grf_grid(32, 9, 3))
