@@ -204,12 +204,15 @@ iga_status igann_set_weights(igann_t net, const float *host, int64_t count);
 iga_status igann_get_weights(igann_t net, float *host, int64_t count);
 /* y[B][4225] = net(x[B][2][32][32]). */
 iga_status igann_forward(igann_t net, const float *x_dev, int B, float *y_dev);
+/* Loss = mean((y-t)^2) + w * mean((L(y-t))^2) with L the 5-point Laplacian on the 65x65 grid
+ * (zero outside); w = 0 (the default) is the plain mean squared error. */
+iga_status igann_set_loss(igann_t net, float laplacian_weight);
 /* In place on y[B][4225]: y = (scale * y + mean) * sample_scale[n] (mean: device [4225], may be
  * NULL; sample_scale: device [B], may be NULL), then `passes` times the separable [1 2 1]/4
  * filter along each axis of the 65x65 coefficient grid with zero (the Dirichlet value) outside. */
 iga_status igann_postprocess(igann_t net, float *y_dev, int B, const float *mean_dev, float scale,
                              const float *sample_scale_dev, int passes);
-/* Loss (mean squared error against t[B][4225]) and its gradient w.r.t. all parameters (host,
+/* Loss (as set by igann_set_loss, against t[B][4225]) and its gradient w.r.t. all parameters (host,
  * igann_num_params() floats; may be NULL) without updating the weights.  Synchronous. */
 iga_status igann_gradients(igann_t net, const float *x_dev, const float *t_dev, int B, float *loss,
                            float *grad_host);

@@ -111,13 +111,21 @@ def forward(p, x, bf=True):
     return y.reshape(y.shape[0], -1), cache
 
 
-def loss_and_grad(p, x, t, bf=True):
-    """Mean squared error over all outputs and its gradient (flat parameter layout)."""
+def laplacian(e):
+    """5-point Laplacian 4e_ij - e_(i+-1)j - e_i(j+-1) on [B,65,65] with zero outside."""
+    p = np.pad(e, ((0, 0), (1, 1), (1, 1)))
+    return 4 * e - p[:, :-2, 1:-1] - p[:, 2:, 1:-1] - p[:, 1:-1, :-2] - p[:, 1:-1, 2:]
+
+
+def loss_and_grad(p, x, t, bf=True, lap_weight=0.0):
+    """Loss mean((y-t)^2) + w mean((L(y-t))^2) and its gradient (flat parameter layout)."""
     y, c = forward(p, x, bf)
     t = np.asarray(t, dtype=np.float64).reshape(y.shape)
     n = y.size
-    loss = float(np.sum((y - t) ** 2) / n)
-    dy = (2.0 * (y - t) / n).reshape(-1, 1, 65, 65)
+    e = (y - t).reshape(-1, 65, 65)
+    l = laplacian(e)
+    loss = float((np.sum(e ** 2) + lap_weight * np.sum(l ** 2)) / n)
+    dy = ((2.0 * e + lap_weight * 2.0 * laplacian(l)) / n).reshape(-1, 1, 65, 65)
     g = {}
     g["b3"] = np.array([dy.sum()])
     da3, g["W3"] = _convT_back(dy, c["a3"], c["W3"], 2, 1)

@@ -129,6 +129,7 @@ _SIGNATURES = {
     "igann_set_weights": ([C.c_void_p, C.POINTER(C.c_float), C.c_int64], C.c_int),
     "igann_get_weights": ([C.c_void_p, C.POINTER(C.c_float), C.c_int64], C.c_int),
     "igann_forward": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "igann_set_loss": ([C.c_void_p, C.c_float], C.c_int),
     "igann_postprocess": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_float, C.c_void_p, C.c_int], C.c_int),
     "igann_gradients": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_float)],
                         C.c_int),
@@ -433,6 +434,9 @@ class GuessNet:
         _check(load().igann_forward(self.h, _dev_ptr(x, torch.float32, B * 2 * 32 * 32, "x"), B,
                                     _dev_ptr(y, torch.float32, B * 65 * 65, "y")), "igann_forward")
         return y
+
+    def set_loss(self, laplacian_weight):
+        _check(load().igann_set_loss(self.h, float(laplacian_weight)), "igann_set_loss")
 
     def postprocess(self, y, mean=None, scale=1.0, sample_scale=None, passes=0):
         import torch

@@ -167,15 +167,44 @@ __global__ void k_smooth(int B, const float *__restrict__ y, float *__restrict__
   out[i] = 0.25f * l + 0.5f * c + 0.25f * r;
 }
 
-// MSE loss gradient dy = 2 (y - t) / (B * 4225); per-block partial sums of (y - t)^2
-__global__ void k_mse(int B, const float *__restrict__ y, const float *__restrict__ t, float *__restrict__ dy,
-                      float *__restrict__ part) {
+// Loss = mean((y-t)^2) + beta * mean((L e)^2), e = y - t, L the 5-point discrete Laplacian on the
+// 65x65 grid with zero outside (the error vanishes on the Dirichlet coefficients).  The second
+// term weighs rough errors the way the stiffness part of the residual does.
+__device__ inline float lap_at(const float *__restrict__ y, const float *__restrict__ t, long n, int yy, int x) {
+  auto e = [&](int a, int b) -> float {
+    if (a < 0 || a >= H4 || b < 0 || b >= H4) return 0.f;
+    long k = n * H4 * H4 + a * H4 + b;
+    return y[k] - t[k];
+  };
+  return 4.f * e(yy, x) - e(yy - 1, x) - e(yy + 1, x) - e(yy, x - 1) - e(yy, x + 1);
+}
+
+__global__ void k_lap_err(int B, const float *__restrict__ y, const float *__restrict__ t, float *__restrict__ l) {
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)B * H4 * H4) return;
+  int x = i % H4, yy = (i / H4) % H4;
+  long n = i / (H4 * H4);
+  l[i] = lap_at(y, t, n, yy, x);
+}
+
+// dy = 2 e / n + beta * 2 L(l) / n ; per-block partial sums of e^2 + beta l^2
+__global__ void k_mse(int B, const float *__restrict__ y, const float *__restrict__ t, const float *__restrict__ l,
+                      float beta, float *__restrict__ dy, float *__restrict__ part) {
   __shared__ float sh[256];
   long n = (long)B * H4 * H4;
   float acc = 0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    int x = i % H4, yy = (i / H4) % H4;
+    long s0 = (i / (H4 * H4)) * H4 * H4;
     float d = y[i] - t[i];
-    dy[i] = 2.f * d / (float)n;
+    float g = 2.f * d;
+    if (beta != 0.f) {
+      auto L = [&](int a, int b) -> float { return (a < 0 || a >= H4 || b < 0 || b >= H4) ? 0.f : l[s0 + a * H4 + b]; };
+      float lap = 4.f * L(yy, x) - L(yy - 1, x) - L(yy + 1, x) - L(yy, x - 1) - L(yy, x + 1);
+      g += beta * 2.f * lap;
+      acc += beta * l[i] * l[i];
+    }
+    dy[i] = g / (float)n;
     acc += d * d;
   }
   sh[threadIdx.x] = acc;
@@ -358,10 +387,11 @@ struct Net {
   hipStream_t stream = nullptr;
   int bmax = 0;
   long step = 0;
+  float beta = 0.f;           // weight of the Laplacian term of the loss
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *part = nullptr;
   bf16_t *pb = nullptr;
   bf16_t *x = nullptr, *a1 = nullptr, *a2 = nullptr, *a2g = nullptr, *a3 = nullptr;
-  float *y = nullptr, *dy = nullptr, *d3 = nullptr, *dg = nullptr, *d2 = nullptr, *d1 = nullptr;
+  float *y = nullptr, *dy = nullptr, *lap = nullptr, *d3 = nullptr, *dg = nullptr, *d2 = nullptr, *d1 = nullptr;
   std::vector<void *> owned;
 };
 
@@ -403,7 +433,10 @@ static iga_status backward(Net &n, const float *target, int B) {
   hipStream_t s = n.stream;
   const bf16_t *pb = n.pb;
   float *g = n.g;
-  hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, s, B, n.y, target, n.dy, n.part);
+  if (n.beta != 0.f)
+    hipLaunchKernelGGL(k_lap_err, dim3(nblk((long)B * H4 * H4)), dim3(256), 0, s, B, (const float *)n.y, target, n.lap);
+  hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, s, B, (const float *)n.y, target, (const float *)n.lap, n.beta,
+                     n.dy, n.part);
   hipLaunchKernelGGL(k_convT2_bwd_w, dim3(NP_W3), dim3(256), 0, s, B, n.dy, n.a3, g + O_W3, g + O_B3);
   hipLaunchKernelGGL(k_convT2_bwd_data, dim3(nblk((long)B * C * H3 * H3)), dim3(256), 0, s, B, n.dy, pb + O_W3, n.a3,
                      n.d3);
@@ -451,6 +484,7 @@ iga_status igann_create(int batch_max, void *hip_stream, igann_t *out) {
       (st = nalloc(*n, &n->a2, B * C * H2 * H2)) || (st = nalloc(*n, &n->a2g, B * C * H2 * H2)) ||
       (st = nalloc(*n, &n->dg, B * C * H2 * H2)) || (st = nalloc(*n, &n->a3, B * C * H3 * H3)) ||
       (st = nalloc(*n, &n->y, B * H4 * H4)) || (st = nalloc(*n, &n->dy, B * H4 * H4)) ||
+      (st = nalloc(*n, &n->lap, B * H4 * H4)) ||
       (st = nalloc(*n, &n->d3, B * C * H3 * H3)) || (st = nalloc(*n, &n->d2, B * C * H2 * H2)) ||
       (st = nalloc(*n, &n->d1, B * C * H1 * H1))) {
     net_free(n);
@@ -487,6 +521,12 @@ iga_status igann_forward(igann_t nn, const float *x_dev, int B, float *y_dev) {
   iga_status st = forward(n, x_dev, B);
   if (st) return st;
   IGA_HIP_CHECK(hipMemcpyAsync(y_dev, n.y, (size_t)B * H4 * H4 * sizeof(float), hipMemcpyDeviceToDevice, n.stream));
+  return IGA_OK;
+}
+
+iga_status igann_set_loss(igann_t nn, float laplacian_weight) {
+  if (!nn || !(laplacian_weight >= 0.f)) return fail(IGA_EINVAL, "weight must be >= 0");
+  ((Net *)nn)->beta = laplacian_weight;
   return IGA_OK;
 }
 

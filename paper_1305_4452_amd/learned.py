@@ -221,7 +221,10 @@ def evaluate(net, std, test, sols_ref, atol=1e-10, chunk=1000, corrupt=None):
     return summ
 
 
-def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print):
+LAP_WEIGHT = 0.0
+
+
+def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print, lap_weight=LAP_WEIGHT):
     """Generate, train and evaluate; returns a summary dict."""
     t = time.perf_counter()
     tr = instances(range(n_train), log=log)
@@ -238,6 +241,7 @@ def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print):
     std = Standardiser(logk, lam, tgt)
     net = GuessNet(batch_max=max(batch, 256))
     net.set_weights(init_weights())
+    net.set_loss(lap_weight)
     t = time.perf_counter()
     hist = train(net, std.x(logk, lam), std.t(tgt), epochs=epochs, batch=batch, lr=lr, log=log)
     t_train = time.perf_counter() - t
@@ -248,6 +252,7 @@ def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print):
         log("evaluating the learned guess")
     ev = evaluate(net, std, te_k, [sols_te[i] for i in keep_te])
     ev.update(train_instances=len(keep), train_rejected=rej_tr, test_rejected=len(te) - len(keep_te),
-              epochs=epochs, loss_first=hist[0], loss_last=hist[-1], train_s=t_train, datagen_s=t_gen,
+              epochs=epochs, lap_weight=lap_weight, loss_first=hist[0], loss_last=hist[-1], train_s=t_train,
+              datagen_s=t_gen,
               instance_setup_s=t_inst)
     return ev, net, std

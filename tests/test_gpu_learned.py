@@ -26,14 +26,17 @@ def test_forward_and_gradients_match_reference():
     y = net.forward(torch.as_tensor(x, device="cuda")).cpu().numpy()
     yr, _ = nn_ref.forward(w.astype(np.float64), x.astype(np.float64), bf=True)
     assert rel(y, yr) < 2e-3
-    loss, g = net.gradients(torch.as_tensor(x, device="cuda"), torch.as_tensor(t, device="cuda"))
-    lr_, gr = nn_ref.loss_and_grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf=True)
-    assert abs(loss - lr_) < 1e-3 * lr_
-    k = 0
-    for name, shp in nn_ref.SHAPES:
-        n = int(np.prod(shp))
-        assert rel(g[k:k + n], gr[k:k + n]) < 5e-3, name
-        k += n
+    for lw in (0.0, 0.5):
+        net.set_loss(lw)
+        loss, g = net.gradients(torch.as_tensor(x, device="cuda"), torch.as_tensor(t, device="cuda"))
+        lr_, gr = nn_ref.loss_and_grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf=True,
+                                       lap_weight=lw)
+        assert abs(loss - lr_) < 1e-3 * lr_
+        k = 0
+        for name, shp in nn_ref.SHAPES:
+            n = int(np.prod(shp))
+            assert rel(g[k:k + n], gr[k:k + n]) < 5e-3, (lw, name)
+            k += n
     assert np.array_equal(net.get_weights(), w)
 
 

@@ -40,17 +40,18 @@ def test_bf16_rounding_matches_torch():
     assert np.array_equal(nn_ref.bf16(v), ref)
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("w", [0.0, 0.3])
+def test_gradient_matches_central_differences(w):
     p = _params(2, scale=0.7)
     x = inputs.normal(5, 0, 2 * 32 * 32).reshape(1, 2, 32, 32)
     t = inputs.normal(6, 0, 65 * 65).reshape(1, -1)
-    _, g = nn_ref.loss_and_grad(p, x, t, bf=False)
+    _, g = nn_ref.loss_and_grad(p, x, t, bf=False, lap_weight=w)
     idx = np.concatenate([np.arange(0, nn_ref.NPARAM, 4999), [nn_ref.NPARAM - 1, nn_ref.NPARAM - 2]])
     h = 1e-6
     for i in idx:
         e = np.zeros_like(p)
         e[i] = h
-        lp, _ = nn_ref.loss_and_grad(p + e, x, t, bf=False)
-        lm, _ = nn_ref.loss_and_grad(p - e, x, t, bf=False)
+        lp, _ = nn_ref.loss_and_grad(p + e, x, t, bf=False, lap_weight=w)
+        lm, _ = nn_ref.loss_and_grad(p - e, x, t, bf=False, lap_weight=w)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
