@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3000)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run each hot kernel a few times and a 256 MiB device copy (for counter runs), then exit")
     ap.add_argument("--batch-n", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -206,6 +208,22 @@ def main():
     R = torch.zeros(N, dtype=torch.float64, device="cuda")
     vals = torch.empty(nnz, dtype=torch.float64, device="cuda")
     g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_AUTO)
+    if args.kernels_only:
+        for _ in range(3):
+            g.assemble_jacobian(U, vals)
+        for _ in range(3):
+            g.assemble_residual(U, R)
+        x = torch.rand(N, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            g.spmv(vals, x, y)
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "copy_bytes": a.numel() * 8}))
+        return
     print(f"[bench] workload N={N} nnz={nnz} E={E}; warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         g.assemble_jacobian(U, vals)
