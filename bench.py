@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (the row-gather kernel runs on the VALU)
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 
 
 def rowgather_flops(n: int, p: int, b1: int, b2: int) -> float:
@@ -76,35 +76,42 @@ def rowgather_flops(n: int, p: int, b1: int, b2: int) -> float:
     return 2.0 * total * ne
 
 
-def rgsep_flops(n: int, p: int, b1: int, b2: int) -> float:
-    """Floating-point operations (2 per multiply-add; the exponential is not counted) of one
-    launch of the separable row-gather kernel, counted from its loop bounds with only the
-    non-zero band entries of levels 1 and 2: coefficient sweeps along axes 0 and 1, u at the
-    window points, level 1 (axis 2), level 2 (axis 1), level 3 (axis 0) and the Kronecker-sum
-    stiffness added at the write."""
+# HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device
+# copy (FETCH x2.0, WRITE x1.0); the summary is under profiles/.  Valid only for the kernel source
+# the counters were taken on (SHA-1 of rg_sep.hip); otherwise the traffic is reported as null.
+TRAFFIC = {"src_sha1": "9fb9714bc49923a44bf7cce21430d98b86bcedbb", "fetch_kib": 179993, "write_kib": 751699,
+           "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def measured_traffic(_algorithmic_bytes: float):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1305_4452_amd", "csrc", "rg_sep.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    if TRAFFIC["src_sha1"] != sha or TRAFFIC["fetch_kib"] is None:
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+
+
+def rgsep_flops(n: int, p: int) -> float:
+    """Floating-point operations (2 per multiply-add) of the separable reaction contraction at
+    the minimum of the sum-factorised method (no window redundancy): level 1 over axis 2 for every
+    quadrature line (g0, g1), level 2 over axis 1 for every (g0, i2, j2), level 3 over axis 0 for
+    every (i1, j1, i2, j2) pair and element column (P products + P^2 Q multiply-adds), plus the
+    Kronecker-sum stiffness added to every CSR value (2 multiply-adds)."""
     P = Q = p + 1
-    W = 2 * p + 1
     ne = n - p
-    ME1, ME2 = b1 + p, b2 + p
-    G1, G2, NI1, NI2 = ME1 * Q, ME2 * Q, ME1 + p, ME2 + p
 
     def overlap(i, j):
         return max(0, min(min(i, j), ne - 1) - max(max(i, j) - p, 0) + 1)
 
-    total = 0.0
-    for I1 in range(0, n, b1):
-        for I2 in range(0, n, b2):
-            fma = Q * NI2 * NI1 * P + Q * NI2 * G1 * P + Q * G2 * G1 * P
-            fma += Q * G1 * sum(overlap(I2 + a, I2 + a + o) * Q for a in range(b2) if I2 + a < n
-                                for o in range(-p, p + 1) if 0 <= I2 + a + o < n)
-            r2 = sum(1 for a in range(b2) if I2 + a < n for o in range(-p, p + 1) if 0 <= I2 + a + o < n)
-            fma += Q * r2 * sum(overlap(I1 + a, I1 + a + o) * Q for a in range(b1) if I1 + a < n
-                                for o in range(-p, p + 1) if 0 <= I1 + a + o < n)
-            r1 = sum(1 for a in range(b1) if I1 + a < n for o in range(-p, p + 1) if 0 <= I1 + a + o < n)
-            fma += r1 * r2 * (Q * P + P * P * Q)
-            total += fma
-    rows_entries = 0   # stiffness at the write: 3 products + 2 adds per CSR value
-    return 2.0 * total * ne + 0.0 * rows_entries
+    S = sum(overlap(i, j) * Q for i in range(n) for j in range(max(0, i - p), min(n, i + p + 1)))
+    R = sum(1 for i in range(n) for j in range(max(0, i - p), min(n, i + p + 1)))
+    nnz = R ** 3
+    l1 = (ne * Q) * (ne * Q) * S
+    l2 = (ne * Q) * R * S
+    l3 = R * R * ne * (Q * P + Q * P * P)
+    return 2.0 * (l1 + l2 + l3) + 4.0 * nnz
 
 
 def bench_batched(n: int):
@@ -232,6 +239,7 @@ def main():
 
     K = args.steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    g.set_option(iga.IGA_OPT_KERNEL_TIMING, 1)   # HIP event pair around each kernel, on the launch stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
@@ -243,6 +251,8 @@ def main():
     kern_ms = [a.elapsed_time(b) for a, b in ev]
     ms_step = wall * 1e3 / K
     jac_ms = float(np.mean(kern_ms))
+    ktimes = dict(g.kernel_times())   # mean over the last min(K, 64) timed steps
+    g.set_option(iga.IGA_OPT_KERNEL_TIMING, 0)
     print(f"[bench] jacobian {jac_ms:.3f} ms/launch, wall {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
 
     # the general row-gather kernel (every term contracted) on the same workload, for comparison
@@ -317,9 +327,12 @@ def main():
     batched = None
     if not args.no_batched:
         batched = bench_batched(args.batch_n)
-    flops = rgsep_flops(w.patch.shape[0], w.patch.degree[0], 4, 2)
-    achieved = flops / (jac_ms * 1e-3) / 1e12
-    out_bytes = 8.0 * nnz
+    p_deg = w.patch.degree[0]
+    flops = rgsep_flops(w.patch.shape[0], p_deg)
+    nqp = E * (p_deg + 1) ** 3
+    rg_ms = ktimes["k_rgsep3"]
+    rg_bytes = 8.0 * nnz + 8.0 * nqp        # CSR values written once + reaction field read once
+    achieved = rg_bytes / (rg_ms * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu:
         print(f"[bench] cpu baseline: oracle on {args.cpu_sample} elements", file=sys.stderr, flush=True)
@@ -341,12 +354,13 @@ def main():
         "config": {"workload": f"3D Bratu unit cube lambda=5, {args.nel}^3 elements, p=3 C^2, 4^3 Gauss points, "
                                "U0~U[0,0.1) seed 2; Jacobian assembly (FP64 row-gather, Kronecker-sum stiffness)",
                    "ndof": N, "nnz": nnz, "nelem": E},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_rgsep3<4,4,2,double,double>", "kernel_ms": jac_ms,
-                     "algorithmic_flops": flops, "output_bytes": out_bytes,
-                     "output_hbm_GBs": out_bytes / (jac_ms * 1e-3) / 1e9,
-                     "output_hbm_frac": out_bytes / (jac_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(rg_bytes),
+                     "kernel": "k_rgsep3<4,2,2,double,double>", "kernel_ms": rg_ms,
+                     "algorithmic_bytes": rg_bytes, "algorithmic_flops": flops,
+                     "achieved_tflops": flops / (rg_ms * 1e-3) / 1e12,
+                     "tflops_frac": flops / (rg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "other_kernels_ms": {k: v for k, v in ktimes.items() if k != "k_rgsep3"}},
         "cpu_baseline": cpu,
         "elements_per_s": E / (ms_step * 1e-3),
         "jacobian_fp32_ms": jac32_ms,

@@ -62,7 +62,11 @@ typedef enum {
 typedef enum {
   IGA_OPT_JAC_ALGO = 1,      /* iga_jac_algo */
   IGA_OPT_ROW_BLOCK = 2,     /* row-gather pencil block: (b1 << 8) | b2, 0 = autotuned */
-  IGA_OPT_LAMBDA_BITS = 3    /* replace lambda: value is the IEEE-754 bit pattern of a double */
+  IGA_OPT_LAMBDA_BITS = 3,   /* replace lambda: value is the IEEE-754 bit pattern of a double */
+  IGA_OPT_ROW_SEGMENTS = 4,  /* separable row-gather: split each pencil into this many segments along
+                                axis 0 (each a workgroup; 0 = planned from the occupancy), 0..64 */
+  IGA_OPT_KERNEL_TIMING = 5  /* 1: record a HIP event pair around each kernel of iga_assemble_jacobian
+                                (read back with iga_kernel_times); 0: off (default) */
 } iga_option;
 
 typedef struct {
@@ -145,6 +149,15 @@ iga_status iga_newton_solve(iga_t h, double *U_dev, const iga_newton_opts *opts,
  * n * nloc * nloc doubles.  Synchronous. */
 iga_status iga_element_matrices(iga_t h, const double *U_dev, const int32_t *elems_host, int n,
                                 int prec, double *out_host);
+
+/* Tracing aid: per-kernel device times of iga_assemble_jacobian.  With IGA_OPT_KERNEL_TIMING = 1
+ * (setting the option starts a new averaging window) every call records a HIP event pair on the
+ * handle's stream around each kernel it launches; the events of the last 64 calls are kept.
+ * iga_kernel_times waits for the latest call's last event, then writes up to cap entries:
+ * ms[i] the mean elapsed milliseconds of the i-th kernel of a call over the kept calls, and
+ * names[i] a static string naming it (either array may be NULL); *count receives the number of
+ * kernels per call (at most 4).  IGA_ESTATE if no timed call has been made. */
+iga_status iga_kernel_times(iga_t h, int cap, double *ms, const char **names, int *count);
 
 /* ---- batched solves ------------------------------------------------------------------------
  * Many independent 2D problems (identity geometry, kappa one or element-wise, simple interior

@@ -19,7 +19,7 @@ IGA_OK, IGA_EINVAL, IGA_ENOMEM, IGA_EHIP, IGA_ENOCONV, IGA_EUNSUPPORTED, IGA_EST
 IGA_FP64, IGA_FP32, IGA_BF16 = 0, 1, 2
 IGA_KAPPA_ONE, IGA_KAPPA_NODAL, IGA_KAPPA_ELEMENT = 0, 1, 2
 IGA_JAC_AUTO, IGA_JAC_ROWGATHER, IGA_JAC_ATOMIC, IGA_JAC_COLOR, IGA_JAC_ROWGATHER_GENERAL = 0, 1, 2, 3, 4
-IGA_OPT_JAC_ALGO, IGA_OPT_ROW_BLOCK, IGA_OPT_LAMBDA_BITS = 1, 2, 3
+IGA_OPT_JAC_ALGO, IGA_OPT_ROW_BLOCK, IGA_OPT_LAMBDA_BITS, IGA_OPT_ROW_SEGMENTS, IGA_OPT_KERNEL_TIMING = 1, 2, 3, 4, 5
 
 _STATUS = {0: "IGA_OK", 1: "IGA_EINVAL", 2: "IGA_ENOMEM", 3: "IGA_EHIP", 4: "IGA_ENOCONV",
            5: "IGA_EUNSUPPORTED", 6: "IGA_ESTATE"}
@@ -119,6 +119,7 @@ _SIGNATURES = {
     "iga_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_newton_report)],
                          C.c_int),
     "iga_element_matrices": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.c_int, _dp], C.c_int),
+    "iga_kernel_times": ([C.c_void_p, C.c_int, _dp, C.POINTER(C.c_char_p), C.POINTER(C.c_int)], C.c_int),
     "iga_batch_create": ([C.c_int, C.POINTER(iga_desc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "iga_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "iga_batch_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_batch_item_report),
@@ -317,6 +318,14 @@ class IGA:
         out = rep.as_dict()
         out["status"] = st
         return out
+
+    def kernel_times(self):
+        """[(kernel name, ms)] of the last Jacobian assembly made with IGA_OPT_KERNEL_TIMING = 1."""
+        ms = (C.c_double * 8)()
+        names = (C.c_char_p * 8)()
+        n = C.c_int(0)
+        _check(load().iga_kernel_times(self.h, 8, ms, names, C.byref(n)), "iga_kernel_times")
+        return [(names[i].decode(), ms[i]) for i in range(min(n.value, 8))]
 
     def element_matrices(self, U, elems, prec=IGA_FP64):
         import torch

@@ -36,13 +36,15 @@ static void pick_block(const Handle &h, int prec, int *b1, int *b2) {
   }
 }
 
+// Separable row-gather pencil block, from a sweep at 64^3 p = 3 on MI355X: 2x2 for FP64
+// (0.52 ms; 4x4 0.58, 8x2 0.61, 4x2 0.63) and FP32 (0.34 ms; 4x4 0.37, 4x2 0.39).
 static void pick_sep_block(const Handle &h, int *b1, int *b2) {
   if (h.row_b1 > 0 && rgsep_supported(h, h.row_b1, h.row_b2 > 0 ? h.row_b2 : 1)) {
     *b1 = h.row_b1;
     *b2 = h.row_b2 > 0 ? h.row_b2 : 1;
     return;
   }
-  *b1 = h.pb.P <= 4 ? 4 : 2;
+  *b1 = 2;
   *b2 = 2;
 }
 
@@ -56,10 +58,18 @@ static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int 
   }
   pick_block(h, prec, &b1, &b2);
   if (algo == IGA_JAC_AUTO) algo = rowgather_supported(h, prec, b1, b2) ? IGA_JAC_ROWGATHER : IGA_JAC_ATOMIC;
-  if (algo == IGA_JAC_ROWGATHER || algo == IGA_JAC_ROWGATHER_GENERAL) return launch_jac_rowgather(h, U, vals, prec, b1, b2);
-  if (algo == IGA_JAC_ATOMIC) return launch_jac_scatter(h, U, vals, prec, 0);
-  if (algo == IGA_JAC_COLOR) return launch_jac_scatter(h, U, vals, prec, 1);
-  return fail(IGA_EINVAL, "unknown Jacobian algorithm");
+  iga_status st;
+  if (algo == IGA_JAC_ROWGATHER || algo == IGA_JAC_ROWGATHER_GENERAL) {
+    kt_begin(h, "k_rowgather (general)");
+    st = launch_jac_rowgather(h, U, vals, prec, b1, b2);
+  } else if (algo == IGA_JAC_ATOMIC || algo == IGA_JAC_COLOR) {
+    kt_begin(h, algo == IGA_JAC_ATOMIC ? "k_elem_mat (atomic scatter)" : "k_elem_mat (colour scatter)");
+    st = launch_jac_scatter(h, U, vals, prec, algo == IGA_JAC_COLOR ? 1 : 0);
+  } else {
+    return fail(IGA_EINVAL, "unknown Jacobian algorithm");
+  }
+  kt_end(h);
+  return st;
 }
 
 static iga_status ensure_newton_ws(Handle &h, bool need_vals, int prec) {
@@ -194,6 +204,10 @@ iga_status iga_destroy(iga_t hh) {
   hipStreamSynchronize(h->stream);
   for (void *p : h->owned)
     if (p) hipFree(p);
+  for (auto &call : h->kt_ev)
+    for (auto &pair : call)
+      for (auto &e : pair)
+        if (e) hipEventDestroy(e);
   delete h;
   return IGA_OK;
 }
@@ -218,6 +232,16 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
     case IGA_OPT_ROW_BLOCK:
       h->row_b1 = (int)((value >> 8) & 0xff);
       h->row_b2 = (int)(value & 0xff);
+      return IGA_OK;
+    case IGA_OPT_ROW_SEGMENTS:
+      if (value < 0 || value > 64) return fail(IGA_EINVAL, "row segments must be in 0..64");
+      h->row_segments = (int)value;
+      return IGA_OK;
+    case IGA_OPT_KERNEL_TIMING:
+      if (value != 0 && value != 1) return fail(IGA_EINVAL, "kernel timing must be 0 or 1");
+      h->ktiming = (int)value;
+      h->kt_calls = 0;   // (re)starts the averaging window
+      h->kt_n = 0;
       return IGA_OK;
     case IGA_OPT_LAMBDA_BITS: {
       double lam;
@@ -248,7 +272,31 @@ iga_status iga_assemble_residual(iga_t hh, const double *U, double *R) {
 iga_status iga_assemble_jacobian(iga_t hh, const double *U, void *vals, int prec) {
   if (!hh || !U || !vals) return fail(IGA_EINVAL, "null argument");
   if (prec != IGA_FP64 && prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian values are FP64 or FP32");
-  return assemble_jacobian(*(Handle *)hh, U, vals, prec);
+  Handle &h = *(Handle *)hh;
+  kt_reset(h);
+  return assemble_jacobian(h, U, vals, prec);
+}
+
+iga_status iga_kernel_times(iga_t hh, int cap, double *ms, const char **names, int *count) {
+  if (!hh) return fail(IGA_EINVAL, "null handle");
+  Handle &h = *(Handle *)hh;
+  if (h.kt_calls == 0 || h.kt_n == 0) return fail(IGA_ESTATE, "no timed Jacobian assembly recorded");
+  const int64_t ncalls = h.kt_calls < Handle::kTimedCalls ? h.kt_calls : Handle::kTimedCalls;
+  const int last = (int)((h.kt_calls - 1) % Handle::kTimedCalls);
+  IGA_HIP_CHECK(hipEventSynchronize(h.kt_ev[last][h.kt_n - 1][1]));
+  for (int i = 0; i < h.kt_n && i < cap; ++i) {
+    double sum = 0;
+    for (int64_t c = 0; c < ncalls; ++c) {
+      const int slot = (int)((h.kt_calls - 1 - c) % Handle::kTimedCalls);
+      float t = 0;
+      IGA_HIP_CHECK(hipEventElapsedTime(&t, h.kt_ev[slot][i][0], h.kt_ev[slot][i][1]));
+      sum += t;
+    }
+    if (ms) ms[i] = sum / (double)ncalls;
+    if (names) names[i] = h.kt_name[i];
+  }
+  if (count) *count = h.kt_n;
+  return IGA_OK;
 }
 
 iga_status iga_apply(iga_t hh, const double *U, const double *v, double *y) {

@@ -115,6 +115,19 @@ struct Handle {
   // options
   int jac_algo = IGA_JAC_AUTO;
   int row_b1 = 0, row_b2 = 0;
+  int row_segments = 0;           // separable row-gather: segments along axis 0 (0 = planned)
+  // separable row-gather tables (3D, identity geometry, kappa = 1, simple knots)
+  void *mfield = nullptr;         // [ne0 Q][ne2 Q][ne1 Q] reaction coefficient, FP64 or FP32
+  const void *sep_phi[2][3] = {}; // [FP64, FP32][axis] band products [n][2p+1][(p+1)^2]
+  const void *sep_b0[2] = {};     // [FP64, FP32] axis-0 basis table [ne0][Q][P]
+  const int64_t *sep_cw = nullptr; // prefix sums of the stencil widths, [n0+1 | n1+1 | n2+1]
+  // per-kernel timing (IGA_OPT_KERNEL_TIMING): event pairs of up to kMaxTimed kernels for each
+  // of the last kTimedCalls Jacobian assemblies (a ring)
+  static constexpr int kMaxTimed = 4, kTimedCalls = 64;
+  int ktiming = 0, kt_n = 0;
+  int64_t kt_calls = 0;           // timed calls since timing was switched on
+  hipEvent_t kt_ev[kTimedCalls][kMaxTimed][2] = {};
+  const char *kt_name[kMaxTimed] = {};
   // host copies
   std::vector<double> hknots[3];
   int nb_colors = 0;
@@ -130,6 +143,27 @@ iga_status fail(iga_status st, const std::string &msg);
     if (_e != hipSuccess)                                                            \
       return ::iga::fail(IGA_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
+
+// Per-kernel timing: kt_reset at the start of a timed entry point, kt_begin / kt_end around
+// each launch (events on the handle's stream; no-ops unless IGA_OPT_KERNEL_TIMING is set).
+inline void kt_reset(Handle &h) {
+  if (!h.ktiming) return;
+  h.kt_n = 0;
+  ++h.kt_calls;
+}
+inline void kt_begin(Handle &h, const char *name) {
+  if (!h.ktiming || h.kt_n >= Handle::kMaxTimed) return;
+  hipEvent_t *ev = h.kt_ev[(h.kt_calls - 1) % Handle::kTimedCalls][h.kt_n];
+  for (int k = 0; k < 2; ++k)
+    if (!ev[k]) (void)hipEventCreate(&ev[k]);
+  h.kt_name[h.kt_n] = name;
+  (void)hipEventRecord(ev[0], h.stream);
+}
+inline void kt_end(Handle &h) {
+  if (!h.ktiming || h.kt_n >= Handle::kMaxTimed) return;
+  (void)hipEventRecord(h.kt_ev[(h.kt_calls - 1) % Handle::kTimedCalls][h.kt_n][1], h.stream);
+  ++h.kt_n;
+}
 
 // Launchers implemented in the kernel translation units.
 iga_status launch_geometry(Handle &h, const double *ctrl, const double *wts, const double *kappa_nodal,

@@ -1,5 +1,6 @@
 // Problem set-up: validation, Gauss-Legendre rule, 1D B-spline tables at the Gauss points of
 // every element, the Algorithm 2 adjacency pattern and the per-point geometry table.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -243,6 +244,66 @@ static iga_status dev_upload(Handle &h, T **p, const T *src, size_t count) {
   return IGA_OK;
 }
 
+// Tables of the separable row-gather Jacobian (simple knots: element e carries functions e..e+p).
+//  phi_d[i][o][k] = B_i(g) B_{i+o-p}(g) at the k-th Gauss point g of supp(B_i) (element i-p+k/Q,
+//                   point k mod Q), zero where j = i+o-p is not a function or g is outside the mesh;
+// and the axis-0 basis table [ne0][Q][P], both in FP64 and FP32; the prefix sums of the stencil widths (row pointers of the tensor-product pattern)
+// and the per-point reaction-coefficient buffer.
+static iga_status build_separable_tables(Handle &h, const std::vector<double> *hostB) {
+  const DevProblem &pb = h.pb;
+  const int p = pb.p, P = pb.P, Q = pb.Q, W = 2 * p + 1, KM = P * Q;
+  iga_status st;
+  for (int a = 1; a < 3; ++a) {
+    const int n = pb.n[a], ne = pb.ne[a];
+    const std::vector<double> &B = hostB[a];
+    std::vector<double> ph((size_t)n * W * KM, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int o = 0; o < W; ++o) {
+        const int j = i + o - p;
+        for (int k = 0; k < KM; ++k) {
+          const int el = i - p + k / Q, q = k % Q, ia = i - el, ib = j - el;
+          if (el < 0 || el >= ne || j < 0 || j >= n || ib < 0 || ib > p) continue;
+          ph[((size_t)i * W + o) * KM + k] = B[((size_t)el * Q + q) * P + ia] * B[((size_t)el * Q + q) * P + ib];
+        }
+      }
+    std::vector<float> phf(ph.begin(), ph.end());
+    double *dd;
+    float *df;
+    if ((st = dev_upload(h, &dd, ph.data(), ph.size())) || (st = dev_upload(h, &df, phf.data(), phf.size())))
+      return st;
+    h.sep_phi[0][a] = dd;
+    h.sep_phi[1][a] = df;
+  }
+  {
+    std::vector<float> bf(hostB[0].begin(), hostB[0].end());
+    double *dd;
+    float *df;
+    if ((st = dev_upload(h, &dd, hostB[0].data(), hostB[0].size())) || (st = dev_upload(h, &df, bf.data(), bf.size())))
+      return st;
+    h.sep_b0[0] = dd;
+    h.sep_b0[1] = df;
+  }
+  {
+    std::vector<int64_t> cw;
+    for (int a = 0; a < 3; ++a) {
+      int64_t c = 0;
+      for (int i = 0; i < pb.n[a]; ++i) {
+        cw.push_back(c);
+        c += std::min(pb.n[a] - 1, i + p) - std::max(0, i - p) + 1;
+      }
+      cw.push_back(c);
+    }
+    int64_t *dcw;
+    if ((st = dev_upload(h, &dcw, cw.data(), cw.size()))) return st;
+    h.sep_cw = dcw;
+  }
+  const size_t nqp = (size_t)pb.ne[0] * Q * pb.ne[1] * Q * pb.ne[2] * Q;
+  double *mf;
+  if ((st = dev_alloc(h, &mf, nqp))) return st;
+  h.mfield = mf;
+  return IGA_OK;
+}
+
 iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   if (!d || !out) return fail(IGA_EINVAL, "null descriptor or output");
   if (d->dim != 2 && d->dim != 3) return fail(IGA_EINVAL, "dim must be 2 or 3");
@@ -290,6 +351,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   double gx[kMaxP], gw[kMaxP];
   gauss_legendre(pb.Q, gx, gw);
   std::vector<int> stl[3], stw[3];
+  std::vector<double> hostB[3];
   for (int a = 0; a < 3; ++a) {
     if (a >= dim) { pb.n[a] = 1; pb.ne[a] = 1; continue; }
     const double *U = d->knots[a];
@@ -314,6 +376,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     }
     pb.n[a] = n;
     pb.ne[a] = (int)efirst.size();
+    hostB[a] = B;
     // Algorithm 2 ranges: function j overlaps function i iff their open supports intersect
     stl[a].resize(n);
     stw[a].resize(n);
@@ -387,6 +450,11 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   pb.rational = d->weights != nullptr;
   pb.table = (d->ctrl != nullptr || d->weights != nullptr || d->kappa_mode == IGA_KAPPA_NODAL) ? 1 : 0;
   pb.separable = (!pb.table && d->kappa_mode == IGA_KAPPA_ONE) ? 1 : 0;
+  if (pb.separable && pb.simple_knots && dim == 3 && pb.P >= 2 && pb.P <= 5 &&
+      (st = build_separable_tables(*h, hostB))) {
+    iga_destroy((iga_t)h);
+    return st;
+  }
   double *d_w = nullptr, *d_ctrl = nullptr, *d_kn = nullptr, *d_kel = nullptr, *d_src = nullptr;
   if (d->weights && (st = dev_upload(*h, &d_w, d->weights, (size_t)pb.N))) { iga_destroy((iga_t)h); return st; }
   if (d->kappa_mode == IGA_KAPPA_ELEMENT && (st = dev_upload(*h, &d_kel, d->kappa, (size_t)pb.E))) {

@@ -185,6 +185,28 @@ def test_separable_rowgather_blocks(p, nel, block, prec):
     assert rel(got, o.jacobian(U)) < (TOL64 if prec == iga.IGA_FP64 else 1e-5)
 
 
+@pytest.mark.parametrize("segments", [1, 2, 3, 7])
+@pytest.mark.parametrize("prec", [iga.IGA_FP64, iga.IGA_FP32])
+def test_separable_rowgather_segments(segments, prec):
+    """Pencils split along axis 0 into segments (warm-up columns, virtual flush columns)."""
+    print(f"[case] separable segments={segments} prec={prec}", flush=True)
+    patch = inputs.unit_box(3, [7, 5, 6], 3)
+    o = oracle.Oracle(patch.knots, patch.degree, lam=4.0, dirichlet_mask=0b101101)
+    g = iga.IGA(patch.knots, patch.degree, lam=4.0, dirichlet_mask=0b101101)
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER)
+    g.set_option(iga.IGA_OPT_ROW_SEGMENTS, segments)
+    g.set_option(iga.IGA_OPT_KERNEL_TIMING, 1)
+    U = inputs.uniform(6, 5, g.N, 0.0, 0.5)
+    dt = torch.float64 if prec == iga.IGA_FP64 else torch.float32
+    vals = torch.full((g.nnz,), float("nan"), dtype=dt, device="cuda")
+    g.assemble_jacobian(dev(U), vals, prec)
+    got = host(vals)
+    assert np.all(np.isfinite(got))
+    assert rel(got, o.jacobian(U)) < (TOL64 if prec == iga.IGA_FP64 else 1e-5)
+    names = [n for n, _ in g.kernel_times()]
+    assert names == ["k_mfield", "k_rgsep3"]
+
+
 def test_fp32_jacobian_values():
     patch, o, g, U = build_pair("box3_p3")
     vals = torch.zeros(g.nnz, dtype=torch.float32, device="cuda")
