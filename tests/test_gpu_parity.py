@@ -185,6 +185,29 @@ def test_separable_rowgather_blocks(p, nel, block, prec):
     assert rel(got, o.jacobian(U)) < (TOL64 if prec == iga.IGA_FP64 else 1e-5)
 
 
+@pytest.mark.parametrize("dim,nel,p", [(3, [12, 11, 10], 3), (3, [9, 8, 7], 2), (3, [6, 5, 7], 4), (2, [40, 33], 3),
+                                       (3, [3, 2, 2], 1), (2, [7, 9], 2)])
+@pytest.mark.parametrize("prec", [iga.IGA_FP64, iga.IGA_FP32])
+def test_spmv_tensor_product_pattern(dim, nel, p, prec):
+    """Index-free SpMV on random values of the oracle's CSR pattern vs a plain CSR product."""
+    print(f"[case] spmv dim={dim} nel={nel} p={p} prec={prec}", flush=True)
+    patch = inputs.unit_box(dim, nel, p)
+    o = oracle.Oracle(patch.knots, patch.degree, lam=1.0)
+    g = iga.IGA(patch.knots, patch.degree, lam=1.0)
+    orp, oci = o.pattern()
+    vals = inputs.uniform(21, 1, len(oci), -1.0, 1.0)
+    if prec == iga.IGA_FP32:
+        vals = vals.astype(np.float32).astype(np.float64)   # the device sees the same FP32 values
+    x = inputs.uniform(21, 2, g.N, -1.0, 1.0)
+    ref = np.zeros(g.N)
+    for A in range(g.N):
+        ref[A] = np.dot(vals[orp[A]:orp[A + 1]], x[oci[orp[A]:orp[A + 1]]])
+    dt = torch.float64 if prec == iga.IGA_FP64 else torch.float32
+    y = torch.full((g.N,), float("nan"), dtype=torch.float64, device="cuda")
+    g.spmv(torch.as_tensor(vals, dtype=dt, device="cuda"), dev(x), y, prec)
+    assert rel(host(y), ref) < TOL64
+
+
 @pytest.mark.parametrize("segments", [1, 2, 3, 7])
 @pytest.mark.parametrize("prec", [iga.IGA_FP64, iga.IGA_FP32])
 def test_separable_rowgather_segments(segments, prec):
