@@ -300,7 +300,7 @@ def main():
     s1.record()
     torch.cuda.synchronize()
     spmv_ms = s0.elapsed_time(s1) / 10
-    spmv_bytes = 12.0 * nnz + 8.0 * (N + 1) + 16.0 * N + 8.0 * N
+    spmv_bytes = 8.0 * nnz + 8.0 * (N + 1) + 16.0 * N + 8.0 * N   # values, row pointers, x (+x[A]), y
 
     newton = {}
     if not args.no_newton:
