@@ -65,9 +65,19 @@ typedef enum {
   IGA_OPT_LAMBDA_BITS = 3,   /* replace lambda: value is the IEEE-754 bit pattern of a double */
   IGA_OPT_ROW_SEGMENTS = 4,  /* separable row-gather: split each pencil into this many segments along
                                 axis 0 (each a workgroup; 0 = planned from the occupancy), 0..64 */
-  IGA_OPT_KERNEL_TIMING = 5  /* 1: record a HIP event pair around each kernel of iga_assemble_jacobian
+  IGA_OPT_KERNEL_TIMING = 5, /* 1: record a HIP event pair around each kernel of iga_assemble_jacobian
                                 (read back with iga_kernel_times); 0: off (default) */
+  IGA_OPT_PRECOND = 6        /* CG preconditioner of iga_newton_solve: iga_precond */
 } iga_option;
+
+/* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):
+ *   AUTO:   FDM when the problem is separable (identity geometry, no weights, kappa = 1, at most
+ *           240 non-Dirichlet coefficients per axis), Jacobi otherwise;
+ *   JACOBI: the inverse diagonal of the Jacobian;
+ *   FDM:    fast diagonalisation of K + c M, K the Kronecker-sum stiffness and M the mass matrix
+ *           of the tensor-product basis (Sec. 2.1 tensor-product structure), c = -lambda times the
+ *           integral-weighted mean of e^U at each Newton step; IGA_EUNSUPPORTED if not separable. */
+typedef enum { IGA_PRECOND_AUTO = 0, IGA_PRECOND_JACOBI = 1, IGA_PRECOND_FDM = 2 } iga_precond;
 
 typedef struct {
   int dim;                       /* 2 or 3 */
@@ -92,7 +102,8 @@ typedef struct {
   int matrix_free;               /* 0: assembled CSR Jacobian; 1: iga_apply inside CG */
   int jac_prec;                  /* iga_prec of the Jacobian values (assembled mode) */
   double forcing_max;            /* cap of the CG relative tolerance (Eisenstat-Walker); 0: 1e-2 */
-  int check_every;               /* CG iterations between convergence checks; 0: 16 */
+  int check_every;               /* CG iterations between convergence checks; 0: automatic (4 with the
+                                    fast-diagonalisation preconditioner, 16 with Jacobi) */
 } iga_newton_opts;
 
 typedef struct {

@@ -20,6 +20,8 @@ IGA_FP64, IGA_FP32, IGA_BF16 = 0, 1, 2
 IGA_KAPPA_ONE, IGA_KAPPA_NODAL, IGA_KAPPA_ELEMENT = 0, 1, 2
 IGA_JAC_AUTO, IGA_JAC_ROWGATHER, IGA_JAC_ATOMIC, IGA_JAC_COLOR, IGA_JAC_ROWGATHER_GENERAL = 0, 1, 2, 3, 4
 IGA_OPT_JAC_ALGO, IGA_OPT_ROW_BLOCK, IGA_OPT_LAMBDA_BITS, IGA_OPT_ROW_SEGMENTS, IGA_OPT_KERNEL_TIMING = 1, 2, 3, 4, 5
+IGA_OPT_PRECOND = 6
+IGA_PRECOND_AUTO, IGA_PRECOND_JACOBI, IGA_PRECOND_FDM = 0, 1, 2
 
 _STATUS = {0: "IGA_OK", 1: "IGA_EINVAL", 2: "IGA_ENOMEM", 3: "IGA_EHIP", 4: "IGA_ENOCONV",
            5: "IGA_EUNSUPPORTED", 6: "IGA_ESTATE"}
@@ -307,7 +309,7 @@ class IGA:
         return y
 
     def newton_solve(self, U, atol=1e-10, rtol=0.0, max_newton=30, max_krylov=5000, matrix_free=False,
-                     jac_prec=IGA_FP64, forcing_max=1e-2, check_every=16, raise_on_fail=True):
+                     jac_prec=IGA_FP64, forcing_max=1e-2, check_every=0, raise_on_fail=True):
         import torch
         o = iga_newton_opts(atol, rtol, max_newton, max_krylov, int(matrix_free), int(jac_prec), forcing_max,
                             check_every)

@@ -11,7 +11,7 @@ iga_status launch_norm(Handle &h, const double *x, double *out_dev);
 iga_status launch_diag_inv(Handle &h, const void *vals, int prec, double *dinv);
 iga_status launch_axpy(Handle &h, double a, const double *x, double *y);
 iga_status cg_solve(Handle &h, const double *R, double *d, double rtol, int maxit, int check_every,
-                    const void *vals, int prec, bool matrix_free, int *iters_out, double *rel_out);
+                    const void *vals, int prec, bool matrix_free, bool fdm, int *iters_out, double *rel_out);
 
 static iga_status alloc_owned(Handle &h, void **p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
@@ -78,6 +78,7 @@ static iga_status ensure_newton_ws(Handle &h, bool need_vals, int prec) {
   if (!h.nw && (st = alloc_owned(h, (void **)&h.nw, 6 * N * sizeof(double)))) return st;
   if (!h.dinv && (st = alloc_owned(h, (void **)&h.dinv, N * sizeof(double)))) return st;
   if (!h.scal && (st = alloc_owned(h, (void **)&h.scal, 1100 * sizeof(double)))) return st;
+  if (h.fdm.ok && !h.fdm_w && (st = alloc_owned(h, (void **)&h.fdm_w, 2 * N * sizeof(double)))) return st;
   if (need_vals && (h.jvals == nullptr || h.jvals_prec != prec)) {
     size_t bytes = (size_t)h.pb.nnz * (prec == IGA_FP32 ? 4 : 8);
     if (h.jvals) {
@@ -107,13 +108,20 @@ static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_
   o.matrix_free = 0;
   o.jac_prec = IGA_FP64;
   o.forcing_max = 1e-2;
-  o.check_every = 16;
+  o.check_every = 0;
   if (o_in) o = *o_in;
   if (o.max_newton < 0 || o.max_newton > 64) return fail(IGA_EINVAL, "max_newton must be in 0..64");
   if (o.max_krylov < 1) return fail(IGA_EINVAL, "max_krylov must be positive");
   if (o.jac_prec != IGA_FP64 && o.jac_prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian precision");
   if (o.forcing_max <= 0) o.forcing_max = 1e-2;
-  if (o.check_every <= 0) o.check_every = 16;
+  if (h.precond != IGA_PRECOND_JACOBI) {
+    iga_status sf = ensure_fdm(h);
+    if (sf) return sf;
+  }
+  const bool fdm = h.precond != IGA_PRECOND_JACOBI && h.fdm.ok;
+  if (h.precond == IGA_PRECOND_FDM && !fdm)
+    return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs a separable problem with at most 240 unknowns per axis");
+  if (o.check_every <= 0) o.check_every = fdm ? 4 : 16;
   if (o.check_every > 1024) o.check_every = 1024;
   iga_newton_report r{};
   iga_status st = ensure_newton_ws(h, !o.matrix_free, o.jac_prec);
@@ -153,16 +161,18 @@ static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_
     nr_prev = nr;
     hipEventRecord(ev[0], h.stream);
     if (o.matrix_free) {
-      if ((st = launch_linearize(h, U)) || (st = launch_diag_mf(h, h.dinv))) break;
+      if ((st = launch_linearize(h, U))) break;
+      if (!fdm && (st = launch_diag_mf(h, h.dinv))) break;
     } else {
       if ((st = assemble_jacobian(h, U, h.jvals, o.jac_prec))) break;
-      if ((st = launch_diag_inv(h, h.jvals, o.jac_prec, h.dinv))) break;
+      if (!fdm && (st = launch_diag_inv(h, h.jvals, o.jac_prec, h.dinv))) break;
     }
+    if (fdm && (st = launch_fdm_shift(h, U))) break;
     hipEventRecord(ev[1], h.stream);
     int its = 0;
     double rel = 0;
-    if ((st = cg_solve(h, R, dvec, eta, o.max_krylov, o.check_every, h.jvals, o.jac_prec, o.matrix_free != 0, &its,
-                       &rel)))
+    if ((st = cg_solve(h, R, dvec, eta, o.max_krylov, o.check_every, h.jvals, o.jac_prec, o.matrix_free != 0, fdm,
+                       &its, &rel)))
       break;
     hipEventRecord(ev[2], h.stream);
     if ((st = launch_axpy(h, 1.0, dvec, U))) break;
@@ -193,6 +203,11 @@ iga_status iga_create(const iga_desc *desc, void *hip_stream, iga_t *out) {
   Handle *h = nullptr;
   iga_status st = create_impl(desc, hip_stream, &h);
   if (st) return st;
+  // the preconditioner's 1D eigendecompositions are set-up work, like the pattern
+  if ((st = ensure_fdm(*h))) {
+    iga_destroy((iga_t)h);
+    return st;
+  }
   *out = (iga_t)h;
   set_error("");
   return IGA_OK;
@@ -242,6 +257,12 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
       h->ktiming = (int)value;
       h->kt_calls = 0;   // (re)starts the averaging window
       h->kt_n = 0;
+      return IGA_OK;
+    case IGA_OPT_PRECOND:
+      if (value < IGA_PRECOND_AUTO || value > IGA_PRECOND_FDM) return fail(IGA_EINVAL, "bad preconditioner");
+      if (value == IGA_PRECOND_FDM && !fdm_possible(*h))
+        return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs a separable problem with at most 240 unknowns per axis");
+      h->precond = (int)value;
       return IGA_OK;
     case IGA_OPT_LAMBDA_BITS: {
       double lam;

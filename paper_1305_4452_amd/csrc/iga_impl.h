@@ -91,6 +91,17 @@ __device__ inline int64_t csr_slot(const DevProblem &pb, int i0, int i1, int i2,
   return pb.row_ptr[A] + ((int64_t)o2 * w1 + o1) * w0 + o0;
 }
 
+// Fast-diagonalisation preconditioner data (see precond.hip): per axis the non-Dirichlet index
+// range [lo, lo + m), the forward / backward transforms V^T and V (m x m, row-major), the
+// generalised eigenvalues and the 1D basis integrals (row sums of the mass matrix).
+constexpr int kFdmMax = 240;
+struct FdmData {
+  int ok;
+  int lo[3], m[3];
+  const double *Tf[3], *Tb[3], *mu[3], *rs[3];
+  double mu_min;
+};
+
 // ------------------------------------------------------------------------------------------
 // Host-side handle
 // ------------------------------------------------------------------------------------------
@@ -121,6 +132,14 @@ struct Handle {
   const void *sep_phi[2][3] = {}; // [FP64, FP32][axis] band products [n][2p+1][(p+1)^2]
   const void *sep_b0[2] = {};     // [FP64, FP32] axis-0 basis table [ne0][Q][P]
   const int64_t *sep_cw = nullptr; // prefix sums of the stencil widths, [n0+1 | n1+1 | n2+1]
+  // fast-diagonalisation preconditioner (built at creation when the problem is separable)
+  FdmData fdm{};
+  double *fdm_part = nullptr;     // 2 x 256 shift partial sums
+  double *fdm_shift = nullptr;    // device scalar c
+  double *fdm_w = nullptr;        // 2 x N scratch of the transforms (lazily, with the Newton workspace)
+  int precond = IGA_PRECOND_AUTO;
+  int fdm_tried = 0;              // build attempted (lazily, by the first Newton solve that uses it)
+  std::vector<double> hsepM[3], hsepA[3];   // host copies of the 1D band matrices
   // per-kernel timing (IGA_OPT_KERNEL_TIMING): event pairs of up to kMaxTimed kernels for each
   // of the last kTimedCalls Jacobian assemblies (a ring)
   static constexpr int kMaxTimed = 4, kTimedCalls = 64;
@@ -164,6 +183,12 @@ inline void kt_end(Handle &h) {
   (void)hipEventRecord(h.kt_ev[(h.kt_calls - 1) % Handle::kTimedCalls][h.kt_n][1], h.stream);
   ++h.kt_n;
 }
+
+iga_status upload_owned(Handle &h, double **dst, const double *src, size_t count);
+bool fdm_possible(const Handle &h);
+iga_status ensure_fdm(Handle &h);   // builds on first use; h.fdm.ok tells whether it succeeded
+iga_status launch_fdm_shift(Handle &h, const double *U);
+iga_status launch_fdm_apply(Handle &h, const double *r, double *z, double *w1, double *w2);
 
 // Launchers implemented in the kernel translation units.
 iga_status launch_geometry(Handle &h, const double *ctrl, const double *wts, const double *kappa_nodal,

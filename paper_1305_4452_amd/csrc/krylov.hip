@@ -164,12 +164,30 @@ __global__ void __launch_bounds__(256) k_cg_init(int64_t N, const double *__rest
   __shared__ double sh[8];
   double s = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x) {
-    double ri = -R[i], zi = dinv[i] * ri;
+    double ri = -R[i];
     x[i] = 0;
     r[i] = ri;
-    z[i] = zi;
-    p[i] = zi;
-    s += ri * zi;
+    if (dinv) {   // Jacobi; otherwise z and p come from the separate preconditioner
+      double zi = dinv[i] * ri;
+      z[i] = zi;
+      p[i] = zi;
+      s += ri * zi;
+    }
+  }
+  if (dinv) {
+    double bs = block_sum(s, sh);
+    if (threadIdx.x == 0) part_rz[blockIdx.x] = bs;
+  }
+}
+
+// p = z; partial r.z (first iteration with a separate preconditioner)
+__global__ void __launch_bounds__(256) k_cg_pz(int64_t N, const double *__restrict__ r, const double *__restrict__ z,
+                                               double *__restrict__ p, double *__restrict__ part_rz) {
+  __shared__ double sh[8];
+  double s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x) {
+    p[i] = z[i];
+    s += r[i] * z[i];
   }
   double bs = block_sum(s, sh);
   if (threadIdx.x == 0) part_rz[blockIdx.x] = bs;
@@ -189,16 +207,18 @@ __global__ void __launch_bounds__(256) k_cg_xr(int64_t N, const double *__restri
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += gridDim.x * (int64_t)blockDim.x) {
     x[i] += alpha * p[i];
     double ri = r[i] - alpha * q[i];
-    double zi = dinv[i] * ri;
     r[i] = ri;
-    z[i] = zi;
-    s1 += ri * zi;
+    if (dinv) {
+      double zi = dinv[i] * ri;
+      z[i] = zi;
+      s1 += ri * zi;
+    }
     s2 += ri * ri;
   }
   double b1 = block_sum(s1, sh);
   double b2 = block_sum(s2, sh);
   if (threadIdx.x == 0) {
-    part_rz_new[blockIdx.x] = b1;
+    if (dinv) part_rz_new[blockIdx.x] = b1;
     part_rr[blockIdx.x] = b2;
   }
 }
@@ -326,14 +346,21 @@ iga_status launch_axpy(Handle &h, double a, const double *x, double *y) {
 // CG on J d = -R.  `matvec` is either the assembled SpMV or the matrix-free apply.  The
 // partial-sum buffers rotate so that a consumer never reads a buffer the same launch writes.
 iga_status cg_solve(Handle &h, const double *R, double *d, double rtol, int maxit, int check_every,
-                    const void *vals, int prec, bool matrix_free, int *iters_out, double *rnorm_dev_hist) {
+                    const void *vals, int prec, bool matrix_free, bool fdm, int *iters_out, double *rnorm_dev_hist) {
   const int64_t N = h.pb.N;
   double *ws = h.nw;            // [R d r z p q] each N
   double *r = ws + 2 * N, *z = ws + 3 * N, *p = ws + 4 * N, *q = ws + 5 * N;
   const int nb = vec_blocks(N, h.npartials);
   double *P0 = h.partials, *P1 = h.partials + h.npartials, *P2 = h.partials + 2 * h.npartials,
          *P3 = h.partials + 3 * h.npartials;
-  hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(256), 0, h.stream, N, R, h.dinv, d, r, z, p, P0);
+  const double *dinv = fdm ? nullptr : h.dinv;
+  double *w1 = h.fdm_w, *w2 = h.fdm_w + N;
+  iga_status st;
+  hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(256), 0, h.stream, N, R, dinv, d, r, z, p, P0);
+  if (fdm) {
+    if ((st = launch_fdm_apply(h, r, z, w1, w2))) return st;
+    hipLaunchKernelGGL(k_cg_pz, dim3(nb), dim3(256), 0, h.stream, N, (const double *)r, (const double *)z, p, P0);
+  }
   // ||b|| for the relative test
   double *sc = h.scal;
   hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, h.stream, N, R, R, P3);
@@ -350,7 +377,6 @@ iga_status cg_solve(Handle &h, const double *R, double *d, double rtol, int maxi
   double *rz_cur = P0, *rz_new = P1;
   const int nbs = matrix_free ? nb : spmv_blocks(h, h.npartials);
   int it = 0;
-  iga_status st;
   std::vector<double> hist(check_every > 0 ? check_every : 16);
   const int ce = check_every > 0 ? check_every : 16;
   while (it < maxit) {
@@ -364,7 +390,12 @@ iga_status cg_solve(Handle &h, const double *R, double *d, double rtol, int maxi
         if ((st = launch_spmv(h, vals, prec, p, q, P2, h.npartials))) return st;
       }
       hipLaunchKernelGGL(k_cg_xr, dim3(nb), dim3(256), 0, h.stream, N, (const double *)rz_cur, nb, (const double *)P2,
-                         nbs, d, r, z, (const double *)p, (const double *)q, (const double *)h.dinv, rz_new, P3);
+                         nbs, d, r, z, (const double *)p, (const double *)q, dinv, rz_new, P3);
+      if (fdm) {
+        if ((st = launch_fdm_apply(h, r, z, w1, w2))) return st;
+        hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, h.stream, N, (const double *)r, (const double *)z,
+                           rz_new);
+      }
       hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(256), 0, h.stream, N, (const double *)rz_cur, (const double *)rz_new,
                          (const double *)P3, nb, (const double *)z, p, sc + 1 + k);
       double *tmp = rz_cur;

@@ -1,0 +1,414 @@
+// Fast-diagonalisation preconditioner for the separable case (identity geometry, no weights,
+// kappa = 1).  There the stiffness restricted to the non-Dirichlet coefficients is the Kronecker
+// sum K = A0 (x) M1 (x) M2 + M0 (x) A1 (x) M2 + M0 (x) M1 (x) A2 of the 1D stiffness and mass
+// matrices of each axis, and the reaction part of eq:jacobian is close to a multiple of the mass
+// matrix M = M0 (x) M1 (x) M2, because e^u varies little.  With the 1D generalised eigenpairs
+// A_d V_d = M_d V_d diag(mu_d), V_d^T M_d V_d = I (Lynch, Rice and Thomas's fast diagonalisation),
+//
+//   (K + c M)^{-1} = (V0 (x) V1 (x) V2) diag(1 / (mu0 + mu1 + mu2 + c)) (V0 (x) V1 (x) V2)^T,
+//
+// applied as three dense 1D transforms along the axes, a scaling and three more transforms.
+// c = -lambda * (integral-weighted mean of e^U) is set before each linear solve.  Dirichlet rows
+// are identity rows, so z = r there.
+#include <cmath>
+#include <vector>
+
+#include "iga_impl.h"
+
+namespace iga {
+
+// ---------------------------------------------------------------------------------------------
+// Host: generalised symmetric eigenproblem A v = mu M v (dense, row-major, FP64).
+// M = L L^T by Cholesky; C = L^{-1} A L^{-T} is symmetric; cyclic Jacobi rotations give
+// C = Q diag(mu) Q^T; V = L^{-T} Q.
+// ---------------------------------------------------------------------------------------------
+static bool cholesky_lower(std::vector<double> &a, int n) {
+  for (int j = 0; j < n; ++j) {
+    double d = a[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= a[(size_t)j * n + k] * a[(size_t)j * n + k];
+    if (!(d > 0)) return false;
+    d = std::sqrt(d);
+    a[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = a[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
+      a[(size_t)i * n + j] = s / d;
+    }
+    for (int k = j + 1; k < n; ++k) a[(size_t)j * n + k] = 0.0;
+  }
+  return true;
+}
+
+// symmetric C (overwritten) -> eigenvalues mu, eigenvectors in the columns of Q
+static void jacobi_eigen(std::vector<double> &C, int n, std::vector<double> &mu, std::vector<double> &Q) {
+  Q.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  auto at = [&](int i, int j) -> double & { return C[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, diag = 0;
+    for (int i = 0; i < n; ++i) {
+      diag += at(i, i) * at(i, i);
+      for (int j = i + 1; j < n; ++j) off += at(i, j) * at(i, j);
+    }
+    if (off <= 1e-30 * diag) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = at(p, q);
+        if (std::fabs(apq) <= 1e-300) continue;
+        // rotation in the (p, q) plane that zeroes C[p][q]: tan(phi) = t
+        const double theta = (at(q, q) - at(p, p)) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double ckp = at(k, p), ckq = at(k, q);
+          at(k, p) = c * ckp - s * ckq;
+          at(k, q) = s * ckp + c * ckq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double cpk = at(p, k), cqk = at(q, k);
+          at(p, k) = c * cpk - s * cqk;
+          at(q, k) = s * cpk + c * cqk;
+        }
+        at(p, q) = at(q, p) = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double qkp = Q[(size_t)k * n + p], qkq = Q[(size_t)k * n + q];
+          Q[(size_t)k * n + p] = c * qkp - s * qkq;
+          Q[(size_t)k * n + q] = s * qkp + c * qkq;
+        }
+      }
+  }
+  mu.resize(n);
+  for (int i = 0; i < n; ++i) mu[i] = at(i, i);
+}
+
+// A, M dense symmetric (n x n); on success V (row-major, V[k*n+i] = component k of vector i)
+// and mu.  The factorisation is checked: V^T M V = I and V^T A V = diag(mu) to 1e-9 relative.
+static bool gen_eigen(const std::vector<double> &A, const std::vector<double> &M, int n, std::vector<double> &V,
+                      std::vector<double> &mu) {
+  std::vector<double> L = M;
+  if (!cholesky_lower(L, n)) return false;
+  // C = L^{-1} A L^{-T}: solve L X = A (forward), then C^T = L^{-1} X^T
+  std::vector<double> X = A;
+  for (int col = 0; col < n; ++col)
+    for (int i = 0; i < n; ++i) {
+      double s = X[(size_t)i * n + col];
+      for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * X[(size_t)k * n + col];
+      X[(size_t)i * n + col] = s / L[(size_t)i * n + i];
+    }
+  std::vector<double> C((size_t)n * n);
+  for (int row = 0; row < n; ++row)   // C[row][:] = L^{-1} (X[row][:])^T  (X = L^{-1} A, C = X L^{-T})
+    for (int i = 0; i < n; ++i) {
+      double s = X[(size_t)row * n + i];
+      for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * C[(size_t)row * n + k];
+      C[(size_t)row * n + i] = s / L[(size_t)i * n + i];
+    }
+  for (int i = 0; i < n; ++i)   // symmetrise against rounding
+    for (int j = i + 1; j < n; ++j) C[(size_t)i * n + j] = C[(size_t)j * n + i] = 0.5 * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
+  std::vector<double> Q;
+  jacobi_eigen(C, n, mu, Q);
+  // V = L^{-T} Q: back substitution with L^T, column by column
+  V.assign((size_t)n * n, 0.0);
+  for (int col = 0; col < n; ++col)
+    for (int i = n - 1; i >= 0; --i) {
+      double s = Q[(size_t)i * n + col];
+      for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * V[(size_t)k * n + col];
+      V[(size_t)i * n + col] = s / L[(size_t)i * n + i];
+    }
+  // check
+  double amax = 0, err_m = 0, err_a = 0;
+  for (double v : mu) amax = std::fmax(amax, std::fabs(v));
+  std::vector<double> MV((size_t)n * n), AV((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int col = 0; col < n; ++col) {
+      double sm = 0, sa = 0;
+      for (int k = 0; k < n; ++k) {
+        sm += M[(size_t)i * n + k] * V[(size_t)k * n + col];
+        sa += A[(size_t)i * n + k] * V[(size_t)k * n + col];
+      }
+      MV[(size_t)i * n + col] = sm;
+      AV[(size_t)i * n + col] = sa;
+    }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      double sm = 0, sa = 0;
+      for (int k = 0; k < n; ++k) {
+        sm += V[(size_t)k * n + a] * MV[(size_t)k * n + b];
+        sa += V[(size_t)k * n + a] * AV[(size_t)k * n + b];
+      }
+      err_m = std::fmax(err_m, std::fabs(sm - (a == b ? 1.0 : 0.0)));
+      err_a = std::fmax(err_a, std::fabs(sa - (a == b ? mu[a] : 0.0)));
+    }
+  return err_m < 1e-9 && err_a < 1e-9 * std::fmax(amax, 1.0);
+}
+
+static void fdm_ranges(const DevProblem &pb, int *lo, int *m) {
+  for (int d = 0; d < 3; ++d) {
+    if (d >= pb.dim) {
+      lo[d] = 0;
+      m[d] = 1;
+      continue;
+    }
+    lo[d] = ((pb.dmask >> (2 * d)) & 1u) ? 1 : 0;
+    m[d] = pb.n[d] - (((pb.dmask >> (2 * d + 1)) & 1u) ? 1 : 0) - lo[d];
+  }
+}
+
+bool fdm_possible(const Handle &h) {
+  if (!h.pb.separable) return false;
+  int lo[3], m[3];
+  fdm_ranges(h.pb, lo, m);
+  for (int d = 0; d < h.pb.dim; ++d)
+    if (m[d] < 1 || m[d] > kFdmMax) return false;
+  return true;
+}
+
+static iga_status build_fdm(Handle &h) {
+  const std::vector<double> *bandM = h.hsepM, *bandA = h.hsepA;
+  const DevProblem &pb = h.pb;
+  const int p = pb.p, W = 2 * p + 1;
+  FdmData f{};
+  double mu_min = 0, mins[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    if (d >= pb.dim) {
+      f.lo[d] = 0;
+      f.m[d] = 1;
+      continue;
+    }
+    const int n = pb.n[d];
+    int los[3], ms[3];
+    fdm_ranges(pb, los, ms);
+    const int lo = los[d], m = ms[d], hi = lo + m;
+    if (m < 1 || m > kFdmMax) return IGA_OK;   // not applicable: Jacobi stays in use
+    std::vector<double> A((size_t)m * m, 0.0), M((size_t)m * m, 0.0), rs(n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int o = 0; o < W; ++o) {
+        const int j = i + o - p;
+        if (j < 0 || j >= n) continue;
+        rs[i] += bandM[d][(size_t)i * W + o];
+        if (i < lo || i >= hi || j < lo || j >= hi) continue;
+        A[(size_t)(i - lo) * m + (j - lo)] = bandA[d][(size_t)i * W + o];
+        M[(size_t)(i - lo) * m + (j - lo)] = bandM[d][(size_t)i * W + o];
+      }
+    // an axis with the same 1D problem as an earlier one reuses its decomposition
+    int same = -1;
+    for (int e = 0; e < d && same < 0; ++e)
+      if (f.lo[e] == lo && f.m[e] == m && pb.n[e] == n && bandM[e] == bandM[d] && bandA[e] == bandA[d]) same = e;
+    if (same >= 0) {
+      f.Tf[d] = f.Tf[same];
+      f.Tb[d] = f.Tb[same];
+      f.mu[d] = f.mu[same];
+      f.rs[d] = f.rs[same];
+      f.lo[d] = lo;
+      f.m[d] = m;
+      mu_min += mins[same];
+      mins[d] = mins[same];
+      continue;
+    }
+    std::vector<double> V, mu;
+    if (!gen_eigen(A, M, m, V, mu)) return IGA_OK;   // fall back to Jacobi
+    // device copies: T_fwd = V^T (row i = vector i), T_bwd = V (row k = components k)
+    std::vector<double> Tf((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < m; ++k) Tf[(size_t)i * m + k] = V[(size_t)k * m + i];
+    iga_status st;
+    double *dTf, *dTb, *dmu, *drs;
+    if ((st = upload_owned(h, &dTf, Tf.data(), Tf.size())) || (st = upload_owned(h, &dTb, V.data(), V.size())) ||
+        (st = upload_owned(h, &dmu, mu.data(), mu.size())) || (st = upload_owned(h, &drs, rs.data(), rs.size())))
+      return st;
+    f.Tf[d] = dTf;
+    f.Tb[d] = dTb;
+    f.mu[d] = dmu;
+    f.rs[d] = drs;
+    f.lo[d] = lo;
+    f.m[d] = m;
+    double mn = mu[0];
+    for (double v : mu) mn = std::fmin(mn, v);
+    mu_min += mn;
+    mins[d] = mn;
+  }
+  f.mu_min = mu_min;
+  double *part, *shift;
+  iga_status st;
+  if ((st = upload_owned(h, &part, std::vector<double>(512, 0.0).data(), 512)) ||
+      (st = upload_owned(h, &shift, std::vector<double>(1, 0.0).data(), 1)))
+    return st;
+  h.fdm_part = part;
+  h.fdm_shift = shift;
+  f.ok = 1;
+  h.fdm = f;
+  return IGA_OK;
+}
+
+iga_status ensure_fdm(Handle &h) {
+  if (h.fdm_tried) return IGA_OK;
+  h.fdm_tried = 1;
+  if (!fdm_possible(h)) return IGA_OK;
+  return build_fdm(h);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Device
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int kTC = 16;   // columns per block of a 1D transform
+
+struct BoxView {
+  int64_t off, s0, s1, s2;   // element (i0,i1,i2) of the box at off + i0 s0 + i1 s1 + i2 s2
+};
+
+// out(.., i, ..) = sum_k T[i m + k] in(.., k, ..) along axis AX of the box m0 x m1 x m2; the
+// other two axes form the columns, kTC columns per block, staged in LDS.  With mu != null the
+// result is divided by mu0[i0] + mu1[i1] + mu2[i2] + shift.
+template <int AX>
+__global__ void __launch_bounds__(256) k_fdm_axis(const double *__restrict__ in, BoxView vi, double *__restrict__ out,
+                                                  BoxView vo, const double *__restrict__ T, int m0, int m1, int m2,
+                                                  const double *__restrict__ mu0, const double *__restrict__ mu1,
+                                                  const double *__restrict__ mu2, const double *__restrict__ shift) {
+  extern __shared__ double lds[];
+  const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
+  const int ca = AX == 0 ? m1 : m0;                       // faster column axis extent
+  const int ncol = AX == 0 ? m1 * m2 : (AX == 1 ? m0 * m2 : m0 * m1);
+  double *x = lds, *y = lds + (size_t)m * (kTC + 1);     // [m][kTC+1] each
+  const int c0 = blockIdx.x * kTC, t = threadIdx.x;
+  auto coords = [&](int k, int c, int &i0, int &i1, int &i2) {
+    const int a = c % ca, b = c / ca;
+    if (AX == 0) { i0 = k; i1 = a; i2 = b; }
+    else if (AX == 1) { i0 = a; i1 = k; i2 = b; }
+    else { i0 = a; i1 = b; i2 = k; }
+  };
+  // load: axis 0 walks k fastest (contiguous), the others walk the columns (i0) fastest
+  for (int e = t; e < m * kTC; e += 256) {
+    const int k = AX == 0 ? e % m : e / kTC, cl = AX == 0 ? e / m : e % kTC, c = c0 + cl;
+    double v = 0;
+    if (c < ncol) {
+      int i0, i1, i2;
+      coords(k, c, i0, i1, i2);
+      v = in[vi.off + i0 * vi.s0 + i1 * vi.s1 + i2 * vi.s2];
+    }
+    x[(size_t)k * (kTC + 1) + cl] = v;
+  }
+  __syncthreads();
+  const int cl = t % kTC, g = t / kTC;
+  for (int i = g; i < m; i += 256 / kTC) {
+    const double *Ti = T + (size_t)i * m;
+    double s = 0;
+    for (int k = 0; k < m; ++k) s += Ti[k] * x[(size_t)k * (kTC + 1) + cl];
+    y[(size_t)i * (kTC + 1) + cl] = s;
+  }
+  __syncthreads();
+  const double c_shift = mu0 ? *shift : 0.0;
+  for (int e = t; e < m * kTC; e += 256) {
+    const int i = AX == 0 ? e % m : e / kTC, cl2 = AX == 0 ? e / m : e % kTC, c = c0 + cl2;
+    if (c >= ncol) continue;
+    int i0, i1, i2;
+    coords(i, c, i0, i1, i2);
+    double v = y[(size_t)i * (kTC + 1) + cl2];
+    if (mu0) v /= mu0[i0] + mu1[i1] + (mu2 ? mu2[i2] : 0.0) + c_shift;
+    out[vo.off + i0 * vo.s0 + i1 * vo.s1 + i2 * vo.s2] = v;
+  }
+}
+
+__global__ void k_copy(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += gridDim.x * (int64_t)blockDim.x) b[i] = a[i];
+}
+
+// partial sums of w_A e^{U_A} and w_A with w_A = prod_d (integral of B_{i_d}) (a lumped mass)
+__global__ void __launch_bounds__(256) k_fdm_shift_partial(DevProblem pb, FdmData f, const double *__restrict__ U,
+                                                           double *__restrict__ part) {
+  __shared__ double sh[2][8];
+  double s1 = 0, s2 = 0;
+  for (int64_t A = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; A < pb.N; A += gridDim.x * (int64_t)blockDim.x) {
+    const int i0 = (int)(A % pb.n[0]);
+    const int64_t r = A / pb.n[0];
+    const int i1 = (int)(r % pb.n[1]), i2 = (int)(r / pb.n[1]);
+    double w = f.rs[0][i0] * f.rs[1][i1];
+    if (pb.dim == 3) w *= f.rs[2][i2];
+    s1 += w * exp(U[A]);
+    s2 += w;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = s1;
+    sh[1][threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      a += sh[0][i];
+      b += sh[1][i];
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// shift = max(-lambda * sum1 / sum2, -0.9 mu_min): K + shift M stays positive definite
+__global__ void k_fdm_shift_final(const double *__restrict__ part, int nb, double lam, double mu_min,
+                                  double *__restrict__ shift) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0, b = 0;
+  for (int i = 0; i < nb; ++i) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  double c = (b > 0) ? -lam * a / b : 0.0;
+  *shift = fmax(c, -0.9 * mu_min);
+}
+
+template <int AX>
+void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView vo, const double *T, const int *m,
+                 const double *mu0, const double *mu1, const double *mu2, const double *shift) {
+  const int mm = m[AX];
+  const int ncol = AX == 0 ? m[1] * m[2] : (AX == 1 ? m[0] * m[2] : m[0] * m[1]);
+  const size_t lds = 2 * (size_t)mm * (kTC + 1) * sizeof(double);
+  hipLaunchKernelGGL((k_fdm_axis<AX>), dim3((unsigned)((ncol + kTC - 1) / kTC)), dim3(256), lds, h.stream, in, vi, out,
+                     vo, T, m[0], m[1], m[2], mu0, mu1, mu2, shift);
+}
+
+}  // namespace
+
+iga_status launch_fdm_shift(Handle &h, const double *U) {
+  const int nb = 256;
+  hipLaunchKernelGGL(k_fdm_shift_partial, dim3(nb), dim3(256), 0, h.stream, h.pb, h.fdm, U, h.fdm_part);
+  hipLaunchKernelGGL(k_fdm_shift_final, dim3(1), dim3(64), 0, h.stream, (const double *)h.fdm_part, nb, h.pb.lambda,
+                     h.fdm.mu_min, h.fdm_shift);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+// z = (K + shift M)^{-1} r on the non-Dirichlet coefficients, z = r on the Dirichlet ones.
+// w1, w2: scratch of m0 m1 m2 doubles each.
+iga_status launch_fdm_apply(Handle &h, const double *r, double *z, double *w1, double *w2) {
+  const FdmData &f = h.fdm;
+  const int dim = h.pb.dim;
+  const int64_t n0 = h.pb.n[0], n1 = h.pb.n[1];
+  const int *m = f.m;
+  const BoxView full{f.lo[0] + n0 * (f.lo[1] + n1 * (int64_t)f.lo[2]), 1, n0, n0 * n1};
+  const BoxView box{0, 1, m[0], (int64_t)m[0] * m[1]};
+  const int64_t N = h.pb.N;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((N + 255) / 256 < 2048 ? (N + 255) / 256 : 2048)), dim3(256), 0, h.stream,
+                     N, r, z);
+  const double *mu2 = dim == 3 ? f.mu[2] : nullptr;
+  if (dim == 3) {
+    launch_axis<0>(h, r, full, w1, box, f.Tf[0], m, nullptr, nullptr, nullptr, nullptr);
+    launch_axis<1>(h, w1, box, w2, box, f.Tf[1], m, nullptr, nullptr, nullptr, nullptr);
+    launch_axis<2>(h, w2, box, w1, box, f.Tf[2], m, f.mu[0], f.mu[1], mu2, h.fdm_shift);
+    launch_axis<2>(h, w1, box, w2, box, f.Tb[2], m, nullptr, nullptr, nullptr, nullptr);
+    launch_axis<1>(h, w2, box, w1, box, f.Tb[1], m, nullptr, nullptr, nullptr, nullptr);
+    launch_axis<0>(h, w1, box, z, full, f.Tb[0], m, nullptr, nullptr, nullptr, nullptr);
+  } else {
+    launch_axis<0>(h, r, full, w1, box, f.Tf[0], m, nullptr, nullptr, nullptr, nullptr);
+    launch_axis<1>(h, w1, box, w2, box, f.Tf[1], m, f.mu[0], f.mu[1], nullptr, h.fdm_shift);
+    launch_axis<1>(h, w2, box, w1, box, f.Tb[1], m, nullptr, nullptr, nullptr, nullptr);
+    launch_axis<0>(h, w1, box, z, full, f.Tb[0], m, nullptr, nullptr, nullptr, nullptr);
+  }
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+}  // namespace iga

@@ -304,6 +304,10 @@ static iga_status build_separable_tables(Handle &h, const std::vector<double> *h
   return IGA_OK;
 }
 
+iga_status upload_owned(Handle &h, double **dst, const double *src, size_t count) {
+  return dev_upload(h, dst, src, count);
+}
+
 iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   if (!d || !out) return fail(IGA_EINVAL, "null descriptor or output");
   if (d->dim != 2 && d->dim != 3) return fail(IGA_EINVAL, "dim must be 2 or 3");
@@ -351,7 +355,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   double gx[kMaxP], gw[kMaxP];
   gauss_legendre(pb.Q, gx, gw);
   std::vector<int> stl[3], stw[3];
-  std::vector<double> hostB[3];
+  std::vector<double> hostB[3], hostSM[3], hostSA[3];
   for (int a = 0; a < 3; ++a) {
     if (a >= dim) { pb.n[a] = 1; pb.ne[a] = 1; continue; }
     const double *U = d->knots[a];
@@ -408,6 +412,8 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     }
     pb.sepM[a] = d_sM;
     pb.sepA[a] = d_sA;
+    hostSM[a] = sM;
+    hostSA[a] = sA;
     int *d_ef, *d_stl, *d_stw;
     double *d_B, *d_dB, *d_wq;
     if ((st = dev_upload(*h, &d_ef, efirst.data(), efirst.size())) ||
@@ -455,6 +461,11 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     iga_destroy((iga_t)h);
     return st;
   }
+  if (pb.separable)
+    for (int a = 0; a < dim; ++a) {
+      h->hsepM[a] = hostSM[a];
+      h->hsepA[a] = hostSA[a];
+    }
   double *d_w = nullptr, *d_ctrl = nullptr, *d_kn = nullptr, *d_kel = nullptr, *d_src = nullptr;
   if (d->weights && (st = dev_upload(*h, &d_w, d->weights, (size_t)pb.N))) { iga_destroy((iga_t)h); return st; }
   if (d->kappa_mode == IGA_KAPPA_ELEMENT && (st = dev_upload(*h, &d_kel, d->kappa, (size_t)pb.E))) {
