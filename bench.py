@@ -136,28 +136,89 @@ def bench_batched(n: int):
     print(f"[bench] batched {n}: {t_batch:.3f} s", file=sys.stderr, flush=True)
     sols = b.unpack(U.cpu().numpy())
     b.close()
-    t_single = 0.0
+    # per-instance FP64 Newton, once with the batched solver's Jacobi-CG (same algorithm) and once
+    # with the single-problem default (fast-diagonalisation preconditioner for these separable squares)
+    t_single = {iga.IGA_PRECOND_JACOBI: 0.0, iga.IGA_PRECOND_AUTO: 0.0}
     maxdiff = 0.0
     conv_single = 0
-    for i, w in enumerate(ws):
-        g = iga.IGA.from_workload(w)
-        Ui = torch.as_tensor(w.U0, device="cuda")
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        rep = g.newton_solve(Ui, atol=1e-10, raise_on_fail=False)
-        torch.cuda.synchronize()
-        t_single += time.perf_counter() - t
-        conv_single += int(rep["converged"])
-        ref = Ui.cpu().numpy()
-        maxdiff = max(maxdiff, float(np.abs(sols[i] - ref).max() / max(np.abs(ref).max(), 1e-300)))
-        g.close()
-    print(f"[bench] per-instance {n}: {t_single:.3f} s", file=sys.stderr, flush=True)
-    return dict(instances=n, total_dof=int(b.N), batched_s=t_batch, per_instance_s=t_single,
-                speedup=t_single / t_batch, batched_converged=int(sum(p["converged"] for p in per)),
+    for pre in t_single:
+        for i, w in enumerate(ws):
+            g = iga.IGA.from_workload(w)
+            g.set_option(iga.IGA_OPT_PRECOND, pre)
+            Ui = torch.as_tensor(w.U0, device="cuda")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rep = g.newton_solve(Ui, atol=1e-10, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t_single[pre] += time.perf_counter() - t
+            if pre == iga.IGA_PRECOND_JACOBI:
+                conv_single += int(rep["converged"])
+                ref = Ui.cpu().numpy()
+                maxdiff = max(maxdiff, float(np.abs(sols[i] - ref).max() / max(np.abs(ref).max(), 1e-300)))
+            g.close()
+    t_jac, t_def = t_single[iga.IGA_PRECOND_JACOBI], t_single[iga.IGA_PRECOND_AUTO]
+    print(f"[bench] per-instance {n}: {t_jac:.3f} s (Jacobi-CG), {t_def:.3f} s (default preconditioner)",
+          file=sys.stderr, flush=True)
+    return dict(instances=n, total_dof=int(b.N), batched_s=t_batch, per_instance_s=t_jac,
+                per_instance_default_precond_s=t_def, speedup=t_jac / t_batch,
+                speedup_vs_default_precond=t_def / t_batch, batched_converged=int(sum(p["converged"] for p in per)),
                 per_instance_converged=conv_single, max_rel_diff=maxdiff, graph_launches=summ["graph_launches"],
                 newton_steps=summ["newton_steps"], tune_ms=summ["t_tune_ms"], create_s=t_create,
                 t_residual_ms=summ["t_residual_ms"], t_jacobian_ms=summ["t_jacobian_ms"],
                 t_krylov_ms=summ["t_krylov_ms"])
+
+
+def bench_cylinder(nel: int, degrees):
+    """Nonlinear diffusion on the thick quarter cylinder (exact NURBS, kappa = exp(GRF) at the
+    control points): Jacobian assembly (general row-gather, FP64 and FP32 values) and Newton to
+    ||R_k|| <= 1e-10 ||R_0|| with the FP64 and the FP32-refined Jacobian."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1305_4452_amd as iga
+    out = {}
+    for p in degrees:
+        w = inputs.config_cylinder(nel=nel, p=p)
+        t = time.perf_counter()
+        g = iga.IGA.from_workload(w)
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - t
+        U = torch.as_tensor(w.U0, device="cuda")
+        res = dict(ndof=g.N, nnz=g.nnz, nelem=g.E, create_s=t_create)
+        for prec, dt, key in [(iga.IGA_FP64, torch.float64, "jacobian_fp64_ms"), (iga.IGA_FP32, torch.float32,
+                                                                                 "jacobian_fp32_ms")]:
+            vals = torch.empty(g.nnz, dtype=dt, device="cuda")
+            g.assemble_jacobian(U, vals, prec)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                g.assemble_jacobian(U, vals, prec)
+            b.record()
+            torch.cuda.synchronize()
+            res[key] = a.elapsed_time(b) / 3
+            del vals
+        res["jacobian_fp64_dof_per_s"] = g.N / (res["jacobian_fp64_ms"] * 1e-3)
+        Uref = None
+        for name, kw in [("newton_fp64", dict(jac_prec=iga.IGA_FP64)), ("newton_fp32_refined", dict(jac_prec=iga.IGA_FP32))]:
+            Ux = torch.as_tensor(w.U0, device="cuda").clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rep = g.newton_solve(Ux, atol=0.0, rtol=1e-10, max_krylov=20000, raise_on_fail=False, **kw)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t
+            Uh = Ux.cpu().numpy()
+            if Uref is None:
+                Uref = Uh
+            res[name] = dict(time_s=dt_s, converged=rep["converged"], newton_iters=rep["newton_iters"],
+                             krylov_iters=rep["krylov_iters_total"], rel_residual=rep["res_norm"] / rep["res_norm0"],
+                             max_rel_diff_vs_fp64=float(np.abs(Uh - Uref).max() / np.abs(Uref).max()))
+        print(f"[bench] cylinder {nel}^3 p={p}: J {res['jacobian_fp64_ms']:.2f} ms, Newton "
+              f"{res['newton_fp64']['time_s']:.3f} s / {res['newton_fp32_refined']['time_s']:.3f} s",
+              file=sys.stderr, flush=True)
+        out[f"p{p}"] = res
+        g.close()
+    return out
 
 
 def cpu_baseline(w, n_sample: int, seed: int = 2):
@@ -192,6 +253,11 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="run each hot kernel a few times and a 256 MiB device copy (for counter runs), then exit")
     ap.add_argument("--batch-n", type=int, default=512)
+    ap.add_argument("--no-cylinder", action="store_true")
+    ap.add_argument("--learned-train", type=int, default=2000, help="0 skips the learned-guess section")
+    ap.add_argument("--learned-test", type=int, default=300)
+    ap.add_argument("--learned-epochs", type=int, default=12)
+    ap.add_argument("--cyl-nel", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
@@ -327,6 +393,18 @@ def main():
     batched = None
     if not args.no_batched:
         batched = bench_batched(args.batch_n)
+    cylinder = None
+    if not args.no_cylinder:
+        cylinder = bench_cylinder(args.cyl_nel, (2, 3, 4))
+    learned = None
+    if args.learned_train > 0:
+        from paper_1305_4452_amd import learned as lg
+        print(f"[bench] learned guess (reduced: {args.learned_train} train / {args.learned_test} test)",
+              file=sys.stderr, flush=True)
+        learned, _, _ = lg.run(n_train=args.learned_train, n_test=args.learned_test, epochs=args.learned_epochs,
+                               log=None)
+        learned["note"] = ("reduced run for the default bench; the 20,000 / 2,000-instance, 40-epoch run is "
+                           "`python -m paper_1305_4452_amd.learned` (summary under profiles/)")
     p_deg = w.patch.degree[0]
     flops = rgsep_flops(w.patch.shape[0], p_deg)
     nqp = E * (p_deg + 1) ** 3
@@ -370,6 +448,8 @@ def main():
                  "frac": spmv_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "newton": newton,
         "batched": batched,
+        "cylinder": cylinder,
+        "learned_guess": learned,
         "paper_context": {"explicit_jacobian_s": 15.41, "procs": 16, "hw": "2x Xeon E5-2680 v2",
                           "dof_per_s": 300763 / 15.41},
     }

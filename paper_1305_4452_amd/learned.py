@@ -256,3 +256,17 @@ def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print, la
               datagen_s=t_gen,
               instance_setup_s=t_inst)
     return ev, net, std
+
+
+if __name__ == "__main__":
+    # python -m paper_1305_4452_amd.learned [n_train n_test epochs]: the learned-guess workload
+    # (defaults: 20,000 training and 2,000 held-out instances, 40 epochs); prints the summary
+    import json
+    import sys
+
+    args = [int(a) for a in sys.argv[1:4]]
+    n_train, n_test, epochs = (args + [20000, 2000, 40][len(args):])[:3]
+    t0 = time.perf_counter()
+    summary, _, _ = run(n_train=n_train, n_test=n_test, epochs=epochs, log=lambda m: print(m, flush=True))
+    summary["total_s"] = time.perf_counter() - t0
+    print(json.dumps(summary), flush=True)
