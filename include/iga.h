@@ -71,12 +71,14 @@ typedef enum {
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):
- *   AUTO:   FDM when the problem is separable (identity geometry, no weights, kappa = 1, at most
- *           240 non-Dirichlet coefficients per axis), Jacobi otherwise;
+ *   AUTO:   FDM when every axis has at most 240 non-Dirichlet coefficients, Jacobi otherwise;
  *   JACOBI: the inverse diagonal of the Jacobian;
- *   FDM:    fast diagonalisation of K + c M, K the Kronecker-sum stiffness and M the mass matrix
- *           of the tensor-product basis (Sec. 2.1 tensor-product structure), c = -lambda times the
- *           integral-weighted mean of e^U at each Newton step; IGA_EUNSUPPORTED if not separable. */
+ *   FDM:    fast diagonalisation of a0 A0(x)M1(x)M2 + a1 M0(x)A1(x)M2 + a2 M0(x)M1(x)A2 + c M, the
+ *           parametric 1D stiffness / mass matrices of the tensor-product B-spline basis (Sec. 2.1),
+ *           a_d the quadrature average of kappa W (J^-1 J^-T)_dd per unit parametric volume (1 for
+ *           x = xi, kappa = 1, where this is the exact stiffness), c = -lambda times the
+ *           integral-weighted mean of e^U times the mean det J, set at each Newton step;
+ *           IGA_EUNSUPPORTED if an axis is larger. */
 typedef enum { IGA_PRECOND_AUTO = 0, IGA_PRECOND_JACOBI = 1, IGA_PRECOND_FDM = 2 } iga_precond;
 
 typedef struct {

@@ -93,13 +93,15 @@ __device__ inline int64_t csr_slot(const DevProblem &pb, int i0, int i1, int i2,
 
 // Fast-diagonalisation preconditioner data (see precond.hip): per axis the non-Dirichlet index
 // range [lo, lo + m), the forward / backward transforms V^T and V (m x m, row-major), the
-// generalised eigenvalues and the 1D basis integrals (row sums of the mass matrix).
+// generalised eigenvalues times the axis coefficient a_d, and the 1D basis integrals (row sums
+// of the mass matrix).
 constexpr int kFdmMax = 240;
 struct FdmData {
   int ok;
   int lo[3], m[3];
   const double *Tf[3], *Tb[3], *mu[3], *rs[3];
   double mu_min;
+  double mscale;   // mass scale of the shift (mean det J per unit parametric volume; 1 for x = xi)
 };
 
 // ------------------------------------------------------------------------------------------

@@ -10,6 +10,13 @@
 // applied as three dense 1D transforms along the axes, a scaling and three more transforms.
 // c = -lambda * (integral-weighted mean of e^U) is set before each linear solve.  Dirichlet rows
 // are identity rows, so z = r there.
+//
+// For mapped (NURBS) geometry or variable kappa the Jacobian is spectrally equivalent to the
+// parametric Kronecker sum with per-axis coefficients, a0 A0 (x) M1 (x) M2 + a1 M0 (x) A1 (x) M2 +
+// a2 M0 (x) M1 (x) A2, where a_d is the quadrature average of the metric diagonal kappa W
+// (J^-1 J^-T)_dd per unit parametric volume, and the mass shift is scaled by the mean det J; the
+// same eigenvectors apply with eigenvalues a0 mu0 + a1 mu1 + a2 mu2.  Only the rate of CG depends
+// on how good this approximation is, not the converged answer.
 #include <cmath>
 #include <vector>
 
@@ -154,12 +161,78 @@ static void fdm_ranges(const DevProblem &pb, int *lo, int *m) {
 }
 
 bool fdm_possible(const Handle &h) {
-  if (!h.pb.separable) return false;
+  if (h.hsepM[0].empty()) return false;
   int lo[3], m[3];
   fdm_ranges(h.pb, lo, m);
   for (int d = 0; d < h.pb.dim; ++d)
     if (m[d] < 1 || m[d] > kFdmMax) return false;
   return true;
+}
+
+// per-axis averages a_d and the mass scale: sums over all Gauss points of the metric diagonal,
+// of the mass coefficient and of the parametric weight (one partial set per block)
+__global__ void __launch_bounds__(256) k_fdm_coef_sums(DevProblem pb, double *__restrict__ part) {
+  __shared__ double sh[5][4];
+  const int Q = pb.Q, dim = pb.dim, L = dim == 3 ? Q * Q * Q : Q * Q, NG = geo_streams(dim);
+  double s[5] = {0, 0, 0, 0, 0};
+  for (int64_t e = blockIdx.x; e < pb.E; e += gridDim.x) {
+    const int e0 = (int)(e % pb.ne[0]);
+    const int64_t r = e / pb.ne[0];
+    const int e1 = (int)(r % pb.ne[1]), e2 = (int)(r / pb.ne[1]);
+    const double kap = (!pb.table && pb.kappa_mode == IGA_KAPPA_ELEMENT) ? pb.kel[e] : 1.0;
+    for (int q = threadIdx.x; q < L; q += blockDim.x) {
+      const int q0 = q % Q, q1 = (q / Q) % Q, q2 = dim == 3 ? q / (Q * Q) : 0;
+      double wpar = pb.ax[0].wq[(size_t)e0 * Q + q0] * pb.ax[1].wq[(size_t)e1 * Q + q1];
+      if (dim == 3) wpar *= pb.ax[2].wq[(size_t)e2 * Q + q2];
+      if (pb.table) {
+        const double *G = pb.geo + (size_t)e * NG * L + q;
+        s[0] += G[0];
+        s[1] += G[L];
+        if (dim == 3) s[2] += G[2 * L];
+        s[3] += G[(NG - 2) * L] * G[(NG - 1) * L];   // (W / w) (1 / w): the coefficient of M_A M_B
+      } else {
+        s[0] += kap * wpar;
+        s[1] += kap * wpar;
+        if (dim == 3) s[2] += kap * wpar;
+        s[3] += wpar;
+      }
+      s[4] += wpar;
+    }
+  }
+  for (int k = 0; k < 5; ++k) {
+    double v = s[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double v = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) v += sh[threadIdx.x][i];
+    part[blockIdx.x * 5 + threadIdx.x] = v;
+  }
+}
+
+static iga_status fdm_coefficients(Handle &h, double a[3], double *mscale) {
+  a[0] = a[1] = a[2] = 1.0;
+  *mscale = 1.0;
+  if (h.pb.separable) return IGA_OK;
+  const int nb = 256;
+  double *part = nullptr;
+  IGA_HIP_CHECK(hipMalloc(&part, nb * 5 * sizeof(double)));
+  hipLaunchKernelGGL(k_fdm_coef_sums, dim3(nb), dim3(256), 0, h.stream, h.pb, part);
+  std::vector<double> hp(nb * 5);
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h.stream);
+  hipError_t e3 = hipStreamSynchronize(h.stream);
+  (void)hipFree(part);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(IGA_EHIP, "preconditioner coefficients");
+  double sum[5] = {0, 0, 0, 0, 0};
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < 5; ++k) sum[k] += hp[b * 5 + k];
+  if (!(sum[4] > 0)) return IGA_OK;
+  for (int d = 0; d < h.pb.dim; ++d) a[d] = sum[d] / sum[4];
+  *mscale = sum[3] / sum[4];
+  return IGA_OK;
 }
 
 static iga_status build_fdm(Handle &h) {
@@ -168,6 +241,15 @@ static iga_status build_fdm(Handle &h) {
   const int p = pb.p, W = 2 * p + 1;
   FdmData f{};
   double mu_min = 0, mins[3] = {0, 0, 0};
+  double acoef[3], mscale;
+  {
+    iga_status sc = fdm_coefficients(h, acoef, &mscale);
+    if (sc) return sc;
+    for (int d = 0; d < pb.dim; ++d)
+      if (!(acoef[d] > 0) || !std::isfinite(acoef[d])) return IGA_OK;   // Jacobi stays in use
+  }
+  f.mscale = mscale;
+  std::vector<double> hostV[3], hostMu[3];   // unscaled decompositions, for axis reuse
   for (int d = 0; d < 3; ++d) {
     if (d >= pb.dim) {
       f.lo[d] = 0;
@@ -193,19 +275,32 @@ static iga_status build_fdm(Handle &h) {
     int same = -1;
     for (int e = 0; e < d && same < 0; ++e)
       if (f.lo[e] == lo && f.m[e] == m && pb.n[e] == n && bandM[e] == bandM[d] && bandA[e] == bandA[d]) same = e;
+    std::vector<double> V, mu;
     if (same >= 0) {
+      V = hostV[same];
+      mu = hostMu[same];
+    } else if (!gen_eigen(A, M, m, V, mu)) {
+      return IGA_OK;   // fall back to Jacobi
+    }
+    hostV[d] = V;
+    hostMu[d] = mu;
+    if (same >= 0) {
+      std::vector<double> smu(mu);
+      for (double &v : smu) v *= acoef[d];
+      double *dmu;
+      iga_status st;
+      if ((st = upload_owned(h, &dmu, smu.data(), smu.size()))) return st;
       f.Tf[d] = f.Tf[same];
       f.Tb[d] = f.Tb[same];
-      f.mu[d] = f.mu[same];
+      f.mu[d] = dmu;
       f.rs[d] = f.rs[same];
       f.lo[d] = lo;
       f.m[d] = m;
-      mu_min += mins[same];
-      mins[d] = mins[same];
+      mins[d] = mins[same] / acoef[same] * acoef[d];
+      mu_min += mins[d];
       continue;
     }
-    std::vector<double> V, mu;
-    if (!gen_eigen(A, M, m, V, mu)) return IGA_OK;   // fall back to Jacobi
+    for (double &v : mu) v *= acoef[d];
     // device copies: T_fwd = V^T (row i = vector i), T_bwd = V (row k = components k)
     std::vector<double> Tf((size_t)m * m);
     for (int i = 0; i < m; ++i)
@@ -347,8 +442,8 @@ __global__ void __launch_bounds__(256) k_fdm_shift_partial(DevProblem pb, FdmDat
   }
 }
 
-// shift = max(-lambda * sum1 / sum2, -0.9 mu_min): K + shift M stays positive definite
-__global__ void k_fdm_shift_final(const double *__restrict__ part, int nb, double lam, double mu_min,
+// shift = max(-lambda mscale sum1 / sum2, -0.9 mu_min): K + shift M stays positive definite
+__global__ void k_fdm_shift_final(const double *__restrict__ part, int nb, double lam, double mscale, double mu_min,
                                   double *__restrict__ shift) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double a = 0, b = 0;
@@ -356,7 +451,7 @@ __global__ void k_fdm_shift_final(const double *__restrict__ part, int nb, doubl
     a += part[2 * i];
     b += part[2 * i + 1];
   }
-  double c = (b > 0) ? -lam * a / b : 0.0;
+  double c = (b > 0) ? -lam * mscale * a / b : 0.0;
   *shift = fmax(c, -0.9 * mu_min);
 }
 
@@ -376,7 +471,7 @@ iga_status launch_fdm_shift(Handle &h, const double *U) {
   const int nb = 256;
   hipLaunchKernelGGL(k_fdm_shift_partial, dim3(nb), dim3(256), 0, h.stream, h.pb, h.fdm, U, h.fdm_part);
   hipLaunchKernelGGL(k_fdm_shift_final, dim3(1), dim3(64), 0, h.stream, (const double *)h.fdm_part, nb, h.pb.lambda,
-                     h.fdm.mu_min, h.fdm_shift);
+                     h.fdm.mscale, h.fdm.mu_min, h.fdm_shift);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
 }

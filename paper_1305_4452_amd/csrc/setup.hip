@@ -461,11 +461,10 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     iga_destroy((iga_t)h);
     return st;
   }
-  if (pb.separable)
-    for (int a = 0; a < dim; ++a) {
-      h->hsepM[a] = hostSM[a];
-      h->hsepA[a] = hostSA[a];
-    }
+  for (int a = 0; a < dim; ++a) {
+    h->hsepM[a] = hostSM[a];
+    h->hsepA[a] = hostSA[a];
+  }
   double *d_w = nullptr, *d_ctrl = nullptr, *d_kn = nullptr, *d_kel = nullptr, *d_src = nullptr;
   if (d->weights && (st = dev_upload(*h, &d_w, d->weights, (size_t)pb.N))) { iga_destroy((iga_t)h); return st; }
   if (d->kappa_mode == IGA_KAPPA_ELEMENT && (st = dev_upload(*h, &d_kel, d->kappa, (size_t)pb.E))) {
