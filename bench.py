@@ -200,7 +200,8 @@ def bench_cylinder(nel: int, degrees):
             del vals
         res["jacobian_fp64_dof_per_s"] = g.N / (res["jacobian_fp64_ms"] * 1e-3)
         Uref = None
-        for name, kw in [("newton_fp64", dict(jac_prec=iga.IGA_FP64)), ("newton_fp32_refined", dict(jac_prec=iga.IGA_FP32))]:
+        for name, kw in [("newton_fp64", dict(jac_prec=iga.IGA_FP64)), ("newton_fp32_refined", dict(jac_prec=iga.IGA_FP32)),
+                         ("newton_matrix_free_fp64", dict(matrix_free=True))]:
             Ux = torch.as_tensor(w.U0, device="cuda").clone()
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -213,9 +214,9 @@ def bench_cylinder(nel: int, degrees):
             res[name] = dict(time_s=dt_s, converged=rep["converged"], newton_iters=rep["newton_iters"],
                              krylov_iters=rep["krylov_iters_total"], rel_residual=rep["res_norm"] / rep["res_norm0"],
                              max_rel_diff_vs_fp64=float(np.abs(Uh - Uref).max() / np.abs(Uref).max()))
-        print(f"[bench] cylinder {nel}^3 p={p}: J {res['jacobian_fp64_ms']:.2f} ms, Newton "
-              f"{res['newton_fp64']['time_s']:.3f} s / {res['newton_fp32_refined']['time_s']:.3f} s",
-              file=sys.stderr, flush=True)
+        print(f"[bench] cylinder {nel}^3 p={p}: J {res['jacobian_fp64_ms']:.2f} ms, Newton FP64 / FP32-refined / "
+              f"matrix-free {res['newton_fp64']['time_s']:.3f} / {res['newton_fp32_refined']['time_s']:.3f} / "
+              f"{res['newton_matrix_free_fp64']['time_s']:.3f} s", file=sys.stderr, flush=True)
         out[f"p{p}"] = res
         g.close()
     return out
