@@ -178,9 +178,11 @@ iga_status iga_kernel_times(iga_t h, int cap, double *ms, const char **names, in
  * all instances in one launch over per-instance work lists, per-instance CG scalars and
  * convergence decisions stay on the device, and each chunk of CG iterations is one replay of a
  * captured hipGraph.  Pencil-block and SpMV launch shapes are autotuned per (degree, size
- * class) when the batch is created.  Callers that need many solves of the same shape (the
- * batched workload of the spec configuration list, training-data generation) use this
- * instead of iga_newton_solve per instance. */
+ * class) when the batch is created.  The CG preconditioner is the fast diagonalisation of each
+ * instance (two 1D eigendecompositions per distinct 1D problem, computed at creation) when every
+ * axis of every instance has at most 136 free coefficients, Jacobi otherwise.  Callers that need
+ * many solves of small 2D problems (parameter sweeps, training-data generation) use this instead
+ * of iga_newton_solve per instance. */
 typedef struct iga_batch_s *iga_batch_t;
 
 typedef struct {
@@ -205,11 +207,16 @@ iga_status iga_batch_create(int n, const iga_desc *descs, void *hip_stream, iga_
  * offset of each instance's coefficients in the caller's order. */
 iga_status iga_batch_info(iga_batch_t b, int64_t *total_ndof, int64_t *total_nnz, int64_t *dof_offsets);
 /* Newton on every instance; U_dev is the concatenation (device, FP64) in the caller's order,
- * updated in place.  opts as for iga_newton_solve (matrix_free must be 0); items (host, n, may
+ * updated in place.  opts as for iga_newton_solve (matrix_free must be 0; check_every, rounded up
+ * to even, is the CG chunk of one graph replay, 0: 8 with fast diagonalisation, 16 with Jacobi); items (host, n, may
  * be NULL) gets the per-instance result.  Returns IGA_ENOCONV if any instance did not converge.
  * Synchronous. */
 iga_status iga_batch_newton_solve(iga_batch_t b, double *U_dev, const iga_newton_opts *opts,
                                   iga_batch_item_report *items, iga_batch_report *report);
+/* key IGA_OPT_PRECOND only: IGA_PRECOND_AUTO (fast diagonalisation when built, the default),
+ * IGA_PRECOND_JACOBI, or IGA_PRECOND_FDM (IGA_EUNSUPPORTED when it was not built).  Takes effect
+ * at the next iga_batch_newton_solve. */
+iga_status iga_batch_set_option(iga_batch_t b, int key, int64_t value);
 iga_status iga_batch_destroy(iga_batch_t b);
 
 /* ---- learned initial guess ---------------------------------------------------------------

@@ -126,6 +126,7 @@ _SIGNATURES = {
     "iga_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "iga_batch_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_batch_item_report),
                                 C.POINTER(iga_batch_report)], C.c_int),
+    "iga_batch_set_option": ([C.c_void_p, C.c_int, C.c_int64], C.c_int),
     "iga_batch_destroy": ([C.c_void_p], C.c_int),
     "igann_num_params": ([], C.c_int64),
     "igann_create": ([C.c_int, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
@@ -385,10 +386,13 @@ class IGABatch:
         x = np.asarray(x)
         return [x[self.offsets[i]:self.offsets[i + 1]] for i in range(self.n)]
 
+    def set_option(self, key, value):
+        _check(load().iga_batch_set_option(self.h, int(key), int(value)), "iga_batch_set_option")
+
     def newton_solve(self, U, atol=1e-10, rtol=0.0, max_newton=30, max_krylov=5000, jac_prec=IGA_FP64,
-                     forcing_max=1e-2, raise_on_fail=True):
+                     forcing_max=1e-2, raise_on_fail=True, check_every=0):
         import torch
-        o = iga_newton_opts(atol, rtol, max_newton, max_krylov, 0, int(jac_prec), forcing_max, 16)
+        o = iga_newton_opts(atol, rtol, max_newton, max_krylov, 0, int(jac_prec), forcing_max, int(check_every))
         items = (iga_batch_item_report * self.n)()
         rep = iga_batch_report()
         st = load().iga_batch_newton_solve(self.h, _dev_ptr(U, torch.float64, self.N, "U"), C.byref(o), items,

@@ -15,6 +15,9 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <atomic>
+#include <thread>
+#include <vector>
 
 #include "iga_impl.h"
 #include "kern_elem.h"
@@ -26,7 +29,8 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out);
 namespace {
 
 constexpr int kVT = 256;   // rows per vector tile
-constexpr int kChunk = 16; // CG iterations per captured graph (even: the partial buffers alternate)
+// CG iterations per captured graph with each preconditioner (even: the partial buffers alternate)
+constexpr int kChunkJacobi = 16, kChunkFdm = 8;
 
 struct Tile {
   int inst;
@@ -144,12 +148,15 @@ __global__ void k_b_cg_init(const Tile *__restrict__ tl, const int64_t *__restri
   double a = 0, b = 0;
   if (act[T.inst] && (int)threadIdx.x < T.count) {
     const int64_t i = off[T.inst] + T.start + threadIdx.x;
-    double ri = -R[i], zi = dinv[i] * ri;
+    double ri = -R[i];
     x[i] = 0;
     r[i] = ri;
-    z[i] = zi;
-    p[i] = zi;
-    a = ri * zi;
+    if (dinv) {   // Jacobi; otherwise z, p and r.z come from the preconditioner step
+      const double zi = dinv[i] * ri;
+      z[i] = zi;
+      p[i] = zi;
+      a = ri * zi;
+    }
     b = ri * ri;
   }
   double sa = bsum(a, sh), sb = bsum(b, sh);
@@ -222,15 +229,18 @@ __global__ void __launch_bounds__(256) k_b_cg_xr(const Tile *__restrict__ tl, co
   if ((int)threadIdx.x < T.count) {
     const int64_t i = off[T.inst] + T.start + threadIdx.x;
     x[i] += alpha * p[i];
-    double ri = r[i] - alpha * q[i], zi = dinv[i] * ri;
+    double ri = r[i] - alpha * q[i];
     r[i] = ri;
-    z[i] = zi;
-    a = ri * zi;
+    if (dinv) {
+      const double zi = dinv[i] * ri;
+      z[i] = zi;
+      a = ri * zi;
+    }
     b = ri * ri;
   }
   double sa = bsum(a, sh), sb = bsum(b, sh);
   if (threadIdx.x == 0) {
-    rz_new[blockIdx.x] = sa;
+    if (dinv) rz_new[blockIdx.x] = sa;
     rr_new[blockIdx.x] = sb;
   }
 }
@@ -275,6 +285,147 @@ __global__ void k_b_axpy(const Tile *__restrict__ tl, const int64_t *__restrict_
   if (!act[T.inst] || (int)threadIdx.x >= T.count) return;
   const int64_t i = off[T.inst] + T.start + threadIdx.x;
   U[i] += d[i];
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched fast-diagonalisation preconditioner.  Per instance (2D) z = (a0 A0 (x) M1 + a1 M0 (x) A1
+// + c M)^{-1} r on the non-Dirichlet box, z = r elsewhere (the single-problem preconditioner of
+// precond.hip, one box per instance): two 1D transforms, a scaling, two inverse transforms.
+// A block handles kBfTC columns of one instance; instances whose CG has converged are skipped.
+// ------------------------------------------------------------------------------------------
+constexpr int kBfMax = 136, kBfTC = 16;
+struct BfInst {
+  int m0, m1, lo0, lo1, n0;
+  int64_t tf0, tb0, tf1, tb1;   // V^T / V of each axis in the pool
+  int64_t mu0, mu1;             // eigenvalues times the axis coefficient, in the pool
+  int64_t rs0, rs1;             // 1D basis integrals, in the pool
+  int64_t box;                  // offset of the m0 x m1 box in the scratch vectors
+  double mu_min;
+};
+
+// shift c_k = max(-lambda_k * (integral-weighted mean of e^U), -0.9 min eigenvalue), per instance
+__global__ void __launch_bounds__(256) k_bf_shift(const DevProblem *__restrict__ pbs, const BfInst *__restrict__ bf,
+                                                  const double *__restrict__ pool, const int64_t *__restrict__ off,
+                                                  const int *__restrict__ act, const double *__restrict__ U,
+                                                  double *__restrict__ shift) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
+  if (!act[k]) return;
+  const DevProblem &pb = pbs[k];
+  const BfInst B = bf[k];
+  double s1 = 0, s2 = 0;
+  for (int64_t A = threadIdx.x; A < pb.N; A += blockDim.x) {
+    const int i0 = (int)(A % pb.n[0]), i1 = (int)(A / pb.n[0]);
+    const double w = pool[B.rs0 + i0] * pool[B.rs1 + i1];
+    s1 += w * exp(U[off[k] + A]);
+    s2 += w;
+  }
+  s1 = bsum(s1, sh);
+  s2 = bsum(s2, sh);
+  if (threadIdx.x == 0) {
+    const double c = s2 > 0 ? -pb.lambda * s1 / s2 : 0.0;
+    shift[k] = fmax(c, -0.9 * B.mu_min);
+  }
+}
+
+template <int AX>
+__global__ void __launch_bounds__(256) k_bf_axis(const Pair *__restrict__ work, const BfInst *__restrict__ bf,
+                                                 const double *__restrict__ pool, const int64_t *__restrict__ off,
+                                                 const int *__restrict__ act, const int *__restrict__ vt_start,
+                                                 const double *__restrict__ target, const double *__restrict__ rr_cur,
+                                                 const double *__restrict__ in, int in_full, double *__restrict__ out,
+                                                 int out_full, int fwd, int scale, const double *__restrict__ shift) {
+  __shared__ double x[kBfMax][kBfTC + 1], y[kBfMax][kBfTC + 1];
+  __shared__ double sh[4];
+  const Pair w = work[blockIdx.x];
+  const int k = w.inst;
+  if (!act[k]) return;
+  if (rr_cur && cg_done(rr_cur, vt_start, target, k, sh)) return;
+  const BfInst B = bf[k];
+  const int m = AX == 0 ? B.m0 : B.m1, ncol = AX == 0 ? B.m1 : B.m0;
+  const double *T = pool + (AX == 0 ? (fwd ? B.tf0 : B.tb0) : (fwd ? B.tf1 : B.tb1));
+  const int c0 = w.idx, t = threadIdx.x;
+  auto addr = [&](int full, int i0, int i1) -> int64_t {
+    return full ? off[k] + (B.lo0 + i0) + (int64_t)B.n0 * (B.lo1 + i1) : B.box + i0 + (int64_t)B.m0 * i1;
+  };
+  // axis 0 walks the contracted index (contiguous) fastest, axis 1 the columns (i0)
+  for (int e = t; e < m * kBfTC; e += 256) {
+    const int kk = AX == 0 ? e % m : e / kBfTC, cl = AX == 0 ? e / m : e % kBfTC, c = c0 + cl;
+    double v = 0;
+    if (c < ncol) v = AX == 0 ? in[addr(in_full, kk, c)] : in[addr(in_full, c, kk)];
+    x[kk][cl] = v;
+  }
+  __syncthreads();
+  const int cl = t % kBfTC, g = t / kBfTC;
+  for (int i = g; i < m; i += 256 / kBfTC) {
+    const double *Ti = T + (size_t)i * m;
+    double acc = 0;
+    for (int kk = 0; kk < m; ++kk) acc += Ti[kk] * x[kk][cl];
+    y[i][cl] = acc;
+  }
+  __syncthreads();
+  const double c_shift = scale ? shift[k] : 0.0;
+  for (int e = t; e < m * kBfTC; e += 256) {
+    const int i = AX == 0 ? e % m : e / kBfTC, cl2 = AX == 0 ? e / m : e % kBfTC, c = c0 + cl2;
+    if (c >= ncol) continue;
+    const int i0 = AX == 0 ? i : c, i1 = AX == 0 ? c : i;
+    double v = y[i][cl2];
+    if (scale) v /= pool[B.mu0 + i0] + pool[B.mu1 + i1] + c_shift;
+    out[addr(out_full, i0, i1)] = v;
+  }
+}
+
+// z = r (the Dirichlet rows keep it; the transforms overwrite the box)
+__global__ void k_b_copy_pc(const Tile *__restrict__ tl, const int *__restrict__ vt_start, const int64_t *__restrict__ off,
+                            const int *__restrict__ act, const double *__restrict__ target,
+                            const double *__restrict__ rr_cur, const double *__restrict__ r, double *__restrict__ z) {
+  __shared__ double sh[4];
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst]) return;
+  if (rr_cur && cg_done(rr_cur, vt_start, target, T.inst, sh)) return;
+  if ((int)threadIdx.x < T.count) {
+    const int64_t i = off[T.inst] + T.start + threadIdx.x;
+    z[i] = r[i];
+  }
+}
+
+// partial r.z per tile; a converged instance carries its partials over
+__global__ void __launch_bounds__(256) k_b_rz(const Tile *__restrict__ tl, const int *__restrict__ vt_start,
+                                              const int64_t *__restrict__ off, const int *__restrict__ act,
+                                              const double *__restrict__ target, const double *__restrict__ rr_cur,
+                                              const double *__restrict__ rz_cur, const double *__restrict__ r,
+                                              const double *__restrict__ z, double *__restrict__ rz_new) {
+  __shared__ double sh[4];
+  const Tile T = tl[blockIdx.x];
+  if (!act[T.inst]) return;
+  if (cg_done(rr_cur, vt_start, target, T.inst, sh)) {
+    if (threadIdx.x == 0) rz_new[blockIdx.x] = rz_cur[blockIdx.x];
+    return;
+  }
+  double a = 0;
+  if ((int)threadIdx.x < T.count) {
+    const int64_t i = off[T.inst] + T.start + threadIdx.x;
+    a = r[i] * z[i];
+  }
+  const double sa = bsum(a, sh);
+  if (threadIdx.x == 0) rz_new[blockIdx.x] = sa;
+}
+
+// p = z; partial r.z (first CG iteration)
+__global__ void __launch_bounds__(256) k_b_pz(const Tile *__restrict__ tl, const int64_t *__restrict__ off,
+                                              const int *__restrict__ act, const double *__restrict__ r,
+                                              const double *__restrict__ z, double *__restrict__ p,
+                                              double *__restrict__ part_rz) {
+  __shared__ double sh[4];
+  const Tile T = tl[blockIdx.x];
+  double a = 0;
+  if (act[T.inst] && (int)threadIdx.x < T.count) {
+    const int64_t i = off[T.inst] + T.start + threadIdx.x;
+    p[i] = z[i];
+    a = r[i] * z[i];
+  }
+  const double sa = bsum(a, sh);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = sa;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -328,7 +479,16 @@ struct Batch {
   double *norms = nullptr, *target = nullptr;
   int *act = nullptr, *iters = nullptr, *count = nullptr;
   hipGraphExec_t graph = nullptr;
-  int graph_prec = -1;
+  // batched fast-diagonalisation preconditioner (bf_on: every instance has one)
+  bool bf_on = false;
+  int precond = IGA_PRECOND_AUTO;   // iga_precond chosen by the caller
+  BfInst *d_bf = nullptr;
+  double *bf_pool = nullptr, *bf_shift = nullptr, *bf_w = nullptr;
+  std::vector<Pair> bf_w0, bf_w1;
+  Pair *d_bf_w0 = nullptr, *d_bf_w1 = nullptr;
+  int64_t bf_box_total = 0;
+  int graph_prec = -1, graph_chunk = 0;
+  bool graph_fdm = false;
   double t_tune_ms = 0;
   std::vector<int> perm_;
 };
@@ -543,6 +703,149 @@ static iga_status autotune(Batch &b) {
   return IGA_OK;
 }
 
+// Fast-diagonalisation data of every instance: one generalised eigendecomposition per distinct
+// 1D problem (knots, degree, Dirichlet range), computed on host threads; instances scale the
+// eigenvalues by their axis coefficient (the mean kappa for element-wise kappa).  Leaves
+// bf_on false (Jacobi) if an axis is longer than kBfMax or a decomposition fails.
+static iga_status build_bfdm(Batch &b, const iga_desc *descs) {
+  const int n = b.n;
+  struct Prob {
+    int n, p, lo, m;
+    const std::vector<double> *bm, *ba;
+  };
+  std::map<std::vector<double>, int> keymap;
+  std::vector<Prob> probs;
+  std::vector<int> key(2 * n), lo(2 * n), mm(2 * n);
+  for (int k = 0; k < n; ++k) {
+    const Handle &h = *b.hs[k];
+    const DevProblem &pb = h.pb;
+    for (int d = 0; d < 2; ++d) {
+      const int nn = pb.n[d];
+      const int l = ((pb.dmask >> (2 * d)) & 1u) ? 1 : 0;
+      const int m = nn - (((pb.dmask >> (2 * d + 1)) & 1u) ? 1 : 0) - l;
+      if (m < 1 || m > kBfMax || h.hsepM[d].empty()) return IGA_OK;
+      std::vector<double> sig = {(double)nn, (double)pb.p, (double)l, (double)m};
+      sig.insert(sig.end(), h.hsepM[d].begin(), h.hsepM[d].end());
+      sig.insert(sig.end(), h.hsepA[d].begin(), h.hsepA[d].end());
+      auto it = keymap.find(sig);
+      int id;
+      if (it == keymap.end()) {
+        id = (int)probs.size();
+        keymap.emplace(std::move(sig), id);
+        probs.push_back(Prob{nn, pb.p, l, m, &h.hsepM[d], &h.hsepA[d]});
+      } else {
+        id = it->second;
+      }
+      key[2 * k + d] = id;
+      lo[2 * k + d] = l;
+      mm[2 * k + d] = m;
+    }
+  }
+  const int np = (int)probs.size();
+  std::vector<std::vector<double>> V(np), mu(np), rs(np);
+  std::vector<char> ok(np, 0);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    for (int j; (j = next++) < np;) {
+      const Prob &q = probs[j];
+      const int W = 2 * q.p + 1, m = q.m;
+      std::vector<double> A((size_t)m * m, 0.0), M((size_t)m * m, 0.0), r(q.n, 0.0);
+      for (int i = 0; i < q.n; ++i)
+        for (int o = 0; o < W; ++o) {
+          const int jj = i + o - q.p;
+          if (jj < 0 || jj >= q.n) continue;
+          r[i] += (*q.bm)[(size_t)i * W + o];
+          if (i < q.lo || i >= q.lo + m || jj < q.lo || jj >= q.lo + m) continue;
+          A[(size_t)(i - q.lo) * m + (jj - q.lo)] = (*q.ba)[(size_t)i * W + o];
+          M[(size_t)(i - q.lo) * m + (jj - q.lo)] = (*q.bm)[(size_t)i * W + o];
+        }
+      rs[j] = r;
+      ok[j] = gen_eigen(A, M, m, V[j], mu[j]) ? 1 : 0;
+    }
+  };
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nth = (int)std::min<unsigned>(8u, hw > 0 ? hw : 1u);
+  std::vector<std::thread> th;
+  for (int i = 1; i < nth; ++i) th.emplace_back(worker);
+  worker();
+  for (auto &t : th) t.join();
+  for (int j = 0; j < np; ++j)
+    if (!ok[j]) return IGA_OK;
+  std::vector<double> pool;
+  std::vector<int64_t> otf(np), otb(np), ors(np);
+  for (int j = 0; j < np; ++j) {
+    const int m = probs[j].m;
+    otf[j] = (int64_t)pool.size();
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < m; ++k) pool.push_back(V[j][(size_t)k * m + i]);   // V^T
+    otb[j] = (int64_t)pool.size();
+    pool.insert(pool.end(), V[j].begin(), V[j].end());                      // V
+    ors[j] = (int64_t)pool.size();
+    pool.insert(pool.end(), rs[j].begin(), rs[j].end());
+  }
+  std::vector<BfInst> bf(n);
+  int64_t box = 0;
+  for (int k = 0; k < n; ++k) {
+    const DevProblem &pb = b.hs[k]->pb;
+    const iga_desc &dk = descs[b.perm_[k]];
+    double a = 1.0;
+    if (dk.kappa_mode == IGA_KAPPA_ELEMENT && dk.kappa) {
+      double s = 0;
+      for (int64_t e = 0; e < pb.E; ++e) s += dk.kappa[e];
+      a = s / (double)pb.E;
+      if (!(a > 0) || !std::isfinite(a)) return IGA_OK;
+    }
+    BfInst B{};
+    const int j0 = key[2 * k], j1 = key[2 * k + 1];
+    B.m0 = mm[2 * k];
+    B.m1 = mm[2 * k + 1];
+    B.lo0 = lo[2 * k];
+    B.lo1 = lo[2 * k + 1];
+    B.n0 = pb.n[0];
+    B.tf0 = otf[j0];
+    B.tb0 = otb[j0];
+    B.tf1 = otf[j1];
+    B.tb1 = otb[j1];
+    B.rs0 = ors[j0];
+    B.rs1 = ors[j1];
+    double mn0 = mu[j0][0], mn1 = mu[j1][0];
+    B.mu0 = (int64_t)pool.size();
+    for (double v : mu[j0]) { pool.push_back(a * v); mn0 = std::min(mn0, v); }
+    B.mu1 = (int64_t)pool.size();
+    for (double v : mu[j1]) { pool.push_back(a * v); mn1 = std::min(mn1, v); }
+    B.mu_min = a * (mn0 + mn1);
+    B.box = box;
+    box += (int64_t)B.m0 * B.m1;
+    bf[k] = B;
+    for (int c = 0; c < B.m1; c += kBfTC) b.bf_w0.push_back(Pair{k, c});
+    for (int c = 0; c < B.m0; c += kBfTC) b.bf_w1.push_back(Pair{k, c});
+  }
+  iga_status st;
+  if ((st = bupload(b, &b.d_bf, bf)) || (st = bupload(b, &b.bf_pool, pool)) || (st = bupload(b, &b.d_bf_w0, b.bf_w0)) ||
+      (st = bupload(b, &b.d_bf_w1, b.bf_w1)) || (st = balloc(b, &b.bf_shift, (size_t)n)) ||
+      (st = balloc(b, &b.bf_w, 2 * (size_t)box)))
+    return st;
+  b.bf_box_total = box;
+  b.bf_on = true;
+  return IGA_OK;
+}
+
+// z = P^{-1} r for every active instance (skipping those whose CG has converged when rr_cur is given)
+static void launch_bf_apply(Batch &b, const double *r, double *z, const double *rr_cur, hipStream_t s) {
+  double *w1 = b.bf_w, *w2 = b.bf_w + b.bf_box_total;
+  const unsigned nvt = (unsigned)b.vt.size(), n0 = (unsigned)b.bf_w0.size(), n1 = (unsigned)b.bf_w1.size();
+  hipLaunchKernelGGL(k_b_copy_pc, dim3(nvt), dim3(kVT), 0, s, b.d_vt, b.d_vt_start, b.d_off, b.act, b.target, rr_cur, r,
+                     z);
+  hipLaunchKernelGGL(k_bf_axis<0>, dim3(n0), dim3(256), 0, s, b.d_bf_w0, b.d_bf, b.bf_pool, b.d_off, b.act,
+                     b.d_vt_start, b.target, rr_cur, r, 1, w1, 0, 1, 0, b.bf_shift);
+  hipLaunchKernelGGL(k_bf_axis<1>, dim3(n1), dim3(256), 0, s, b.d_bf_w1, b.d_bf, b.bf_pool, b.d_off, b.act,
+                     b.d_vt_start, b.target, rr_cur, (const double *)w1, 0, w2, 0, 1, 1, b.bf_shift);
+  hipLaunchKernelGGL(k_bf_axis<1>, dim3(n1), dim3(256), 0, s, b.d_bf_w1, b.d_bf, b.bf_pool, b.d_off, b.act,
+                     b.d_vt_start, b.target, rr_cur, (const double *)w2, 0, w1, 0, 0, 0, b.bf_shift);
+  hipLaunchKernelGGL(k_bf_axis<0>, dim3(n0), dim3(256), 0, s, b.d_bf_w0, b.d_bf, b.bf_pool, b.d_off, b.act,
+                     b.d_vt_start, b.target, rr_cur, (const double *)w1, 0, z, 1, 0, 0, b.bf_shift);
+}
+
 static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch **out) {
   if (n <= 0 || !descs || !out) return fail(IGA_EINVAL, "bad batch arguments");
   Batch *b = new Batch();
@@ -663,6 +966,10 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
     batch_free(b);
     return st;
   }
+  if ((st = build_bfdm(*b, descs))) {
+    batch_free(b);
+    return st;
+  }
   if ((st = autotune(*b))) {
     batch_free(b);
     return st;
@@ -675,8 +982,8 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
   return IGA_OK;
 }
 
-static iga_status capture_cg_graph(Batch &b, int prec) {
-  if (b.graph && b.graph_prec == prec) return IGA_OK;
+static iga_status capture_cg_graph(Batch &b, int prec, int chunk, bool fdm) {
+  if (b.graph && b.graph_prec == prec && b.graph_chunk == chunk && b.graph_fdm == fdm) return IGA_OK;
   if (b.graph) {
     (void)hipGraphExecDestroy(b.graph);
     b.graph = nullptr;
@@ -686,7 +993,7 @@ static iga_status capture_cg_graph(Batch &b, int prec) {
   const unsigned nvt = (unsigned)b.vt.size();
   IGA_HIP_CHECK(hipStreamBeginCapture(b.bs, hipStreamCaptureModeThreadLocal));
   // partial buffers: rz in A/B, rr in C/D; iteration k reads (A,C) or (B,D) alternately
-  for (int it = 0; it < kChunk; ++it) {
+  for (int it = 0; it < chunk; ++it) {
     double *rz_cur = (it % 2 == 0) ? b.partA : b.partB, *rz_new = (it % 2 == 0) ? b.partB : b.partA;
     double *rr_cur = (it % 2 == 0) ? b.partC : b.partD, *rr_new = (it % 2 == 0) ? b.partD : b.partC;
     for (size_t gi = 0; gi < b.groups.size(); ++gi) {
@@ -694,7 +1001,13 @@ static iga_status capture_cg_graph(Batch &b, int prec) {
       else launch_spmv_group<double>(b, gi, (const double *)b.vals, p, q, rr_cur, b.bs);
     }
     hipLaunchKernelGGL(k_b_cg_xr, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_vt_start, b.d_st_start, b.d_off, b.act,
-                       b.target, rz_cur, rr_cur, b.part_pq, d, r, z, p, q, b.dinv, rz_new, rr_new);
+                       b.target, rz_cur, rr_cur, b.part_pq, d, r, z, p, q, fdm ? nullptr : b.dinv, rz_new,
+                       rr_new);
+    if (fdm) {
+      launch_bf_apply(b, r, z, rr_cur, b.bs);
+      hipLaunchKernelGGL(k_b_rz, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_vt_start, b.d_off, b.act, b.target, rr_cur,
+                         rz_cur, (const double *)r, (const double *)z, rz_new);
+    }
     hipLaunchKernelGGL(k_b_cg_p, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_vt_start, b.d_off, b.act, b.target,
                        rz_cur, rr_cur, rz_new, z, p, b.iters);
   }
@@ -706,6 +1019,8 @@ static iga_status capture_cg_graph(Batch &b, int prec) {
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(IGA_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
   b.graph_prec = prec;
+  b.graph_chunk = chunk;
+  b.graph_fdm = fdm;
   return IGA_OK;
 }
 
@@ -730,7 +1045,9 @@ static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in,
   r.t_tune_ms = b.t_tune_ms;
   auto t0 = std::chrono::steady_clock::now();
   IGA_HIP_CHECK(hipStreamSynchronize(b.user));
-  iga_status st = capture_cg_graph(b, o.jac_prec);
+  const bool fdm = b.bf_on && b.precond != IGA_PRECOND_JACOBI;
+  const int chunk = o.check_every > 0 ? std::min(64, (o.check_every + 1) & ~1) : (fdm ? kChunkFdm : kChunkJacobi);
+  iga_status st = capture_cg_graph(b, o.jac_prec, chunk, fdm);
   if (st) return st;
   std::vector<double> nr(n), nr_prev(n, 0.0), r0(n, -1.0), eta(n, o.forcing_max), tgt(n);
   std::vector<int> act(n, 1), conv(n, 0), nits(n, 0), kits(n, 0);
@@ -776,21 +1093,31 @@ static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in,
     IGA_HIP_CHECK(hipMemcpyAsync(b.target, tgt.data(), n * sizeof(double), hipMemcpyHostToDevice, b.bs));
     (void)hipEventRecord(ev[0], b.bs);
     for (const Group &g : b.groups) launch_rg(b, g, g.b1, U, b.vals, o.jac_prec, b.bs);
-    if (o.jac_prec == IGA_FP32)
+    if (fdm) {
+      hipLaunchKernelGGL(k_bf_shift, dim3((unsigned)n), dim3(256), 0, b.bs, b.d_pbs, b.d_bf, (const double *)b.bf_pool,
+                         b.d_off, b.act, (const double *)U, b.bf_shift);
+    } else if (o.jac_prec == IGA_FP32) {
       hipLaunchKernelGGL(k_b_diag_inv<float>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff, b.act,
                          (const float *)b.vals, b.dinv);
-    else
+    } else {
       hipLaunchKernelGGL(k_b_diag_inv<double>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff,
                          b.act, (const double *)b.vals, b.dinv);
+    }
     hipLaunchKernelGGL(k_b_cg_init, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)R,
-                       (const double *)b.dinv, d, b.ws + 2 * N, b.ws + 3 * N, b.ws + 4 * N, b.partA, b.partC);
+                       fdm ? nullptr : (const double *)b.dinv, d, b.ws + 2 * N, b.ws + 3 * N, b.ws + 4 * N,
+                       b.partA, b.partC);
+    if (fdm) {
+      launch_bf_apply(b, b.ws + 2 * N, b.ws + 3 * N, nullptr, b.bs);
+      hipLaunchKernelGGL(k_b_pz, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)(b.ws + 2 * N),
+                         (const double *)(b.ws + 3 * N), b.ws + 4 * N, b.partA);
+    }
     (void)hipEventRecord(ev[1], b.bs);
     int done_iters = 0, remaining = 1;
     while (done_iters < o.max_krylov && remaining > 0) {
       IGA_HIP_CHECK(hipGraphLaunch(b.graph, b.bs));
       IGA_HIP_CHECK(hipMemcpyAsync(&remaining, b.count, sizeof(int), hipMemcpyDeviceToHost, b.bs));
       IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
-      done_iters += kChunk;
+      done_iters += chunk;
       r.graph_launches += 1;
     }
     r.krylov_iters_max += done_iters;
@@ -856,6 +1183,17 @@ iga_status iga_batch_newton_solve(iga_batch_t bb, double *U_dev, const iga_newto
                                   iga_batch_item_report *items, iga_batch_report *report) {
   if (!bb || !U_dev) return fail(IGA_EINVAL, "null argument");
   return batch_newton(*(Batch *)bb, U_dev, opts, items, report);
+}
+
+iga_status iga_batch_set_option(iga_batch_t bb, int key, int64_t value) {
+  if (!bb) return fail(IGA_EINVAL, "null batch");
+  Batch *b = (Batch *)bb;
+  if (key != IGA_OPT_PRECOND) return fail(IGA_EINVAL, "batched solves take IGA_OPT_PRECOND only");
+  if (value < IGA_PRECOND_AUTO || value > IGA_PRECOND_FDM) return fail(IGA_EINVAL, "bad preconditioner");
+  if (value == IGA_PRECOND_FDM && !b->bf_on)
+    return fail(IGA_EUNSUPPORTED, "fast diagonalisation needs every axis of every instance within 136 coefficients");
+  b->precond = (int)value;
+  return IGA_OK;
 }
 
 iga_status iga_batch_destroy(iga_batch_t bb) {

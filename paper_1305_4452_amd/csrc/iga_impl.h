@@ -186,6 +186,10 @@ inline void kt_end(Handle &h) {
   ++h.kt_n;
 }
 
+// A v = mu M v for dense symmetric A, M (n x n, row-major): V (column i = vector i, V^T M V = I)
+// and mu; false if M is not positive definite or the factorisation fails its check.
+bool gen_eigen(const std::vector<double> &A, const std::vector<double> &M, int n, std::vector<double> &V,
+               std::vector<double> &mu);
 iga_status upload_owned(Handle &h, double **dst, const double *src, size_t count);
 bool fdm_possible(const Handle &h);
 iga_status ensure_fdm(Handle &h);   // builds on first use; h.fdm.ok tells whether it succeeded

@@ -90,8 +90,8 @@ static void jacobi_eigen(std::vector<double> &C, int n, std::vector<double> &mu,
 
 // A, M dense symmetric (n x n); on success V (row-major, V[k*n+i] = component k of vector i)
 // and mu.  The factorisation is checked: V^T M V = I and V^T A V = diag(mu) to 1e-9 relative.
-static bool gen_eigen(const std::vector<double> &A, const std::vector<double> &M, int n, std::vector<double> &V,
-                      std::vector<double> &mu) {
+bool gen_eigen(const std::vector<double> &A, const std::vector<double> &M, int n, std::vector<double> &V,
+               std::vector<double> &mu) {
   std::vector<double> L = M;
   if (!cholesky_lower(L, n)) return false;
   // C = L^{-1} A L^{-T}: solve L X = A (forward), then C^T = L^{-1} X^T
