@@ -58,6 +58,7 @@ static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int 
     int s1 = 0, s2 = 0;
     pick_sep_block(h, &s1, &s2);
     if (rgsep_supported(h, s1, s2)) return launch_jac_rgsep(h, U, vals, prec, s1, s2);
+    if (rgt2_supported(h.pb) && h.row_b1 == 0) return launch_jac_rgt2(h, U, vals, prec);
   }
   pick_block(h, prec, &b1, &b2);
   if (algo == IGA_JAC_AUTO) algo = rowgather_supported(h, prec, b1, b2) ? IGA_JAC_ROWGATHER : IGA_JAC_ATOMIC;

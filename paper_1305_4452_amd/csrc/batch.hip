@@ -22,6 +22,7 @@
 #include "iga_impl.h"
 #include "kern_elem.h"
 #include "kern_rg.h"
+#include "kern_rgt2.h"
 
 namespace iga {
 iga_status create_impl(const iga_desc *d, void *stream, Handle **out);
@@ -123,6 +124,17 @@ k_b_rowgather(const DevProblem *__restrict__ pbs, const Pair *__restrict__ work,
   const Pair w = work[blockIdx.x];
   if (!act[w.inst]) return;
   rgk::rowgather2_body<P, false, B1, OT, OT>(pbs[w.inst], w.idx, U + off[w.inst], vals + noff[w.inst]);
+}
+
+template <int P, typename OT>
+__global__ void __launch_bounds__(rgt::kThreads)
+k_b_rgt2(const DevProblem *__restrict__ pbs, const Pair *__restrict__ work, const int64_t *__restrict__ off,
+         const int64_t *__restrict__ noff, const int *__restrict__ act, const double *__restrict__ U,
+         OT *__restrict__ vals) {
+  __shared__ __align__(16) char lds[rgt::Lds2<P, OT, OT>::total];
+  const Pair w = work[blockIdx.x];
+  if (!act[w.inst]) return;
+  rgt::rgt2_body<P, OT, OT>(pbs[w.inst], w.idx, U + off[w.inst], vals + noff[w.inst], lds);
 }
 
 template <typename VT>
@@ -442,10 +454,12 @@ struct Group {
   int P;
   int cls;
   std::vector<int> insts;
-  int b1 = 4;               // row-gather pencils per block (autotuned)
+  int b1 = 4;               // row-gather pencils per block, 0: tiled kernel (autotuned)
   int lpr = 8;              // SpMV lanes per row (autotuned)
   std::vector<Pair> pencils;
   Pair *d_pencils = nullptr;
+  std::vector<Pair> tiles;   // (instance, tile) of the tiled row-gather
+  Pair *d_tiles = nullptr;
   std::vector<Pair> elems;
   Pair *d_elems = nullptr;
 };
@@ -524,7 +538,24 @@ static void batch_free(Batch *b) {
 
 // ---- launch helpers -----------------------------------------------------------------------
 template <int P>
+static void launch_rgt_group(Batch &b, const Group &g, const double *U, void *vals, int prec, hipStream_t s) {
+  if constexpr (P >= 2 && P <= 5) {
+    dim3 grid((unsigned)g.tiles.size()), blk(rgt::kThreads);
+    if (prec == IGA_FP32)
+      hipLaunchKernelGGL((k_b_rgt2<P, float>), grid, blk, 0, s, b.d_pbs, g.d_tiles, b.d_off, b.d_noff, b.act, U,
+                         (float *)vals);
+    else
+      hipLaunchKernelGGL((k_b_rgt2<P, double>), grid, blk, 0, s, b.d_pbs, g.d_tiles, b.d_off, b.d_noff, b.act, U,
+                         (double *)vals);
+  }
+}
+
+template <int P>
 static void launch_rg_group(Batch &b, const Group &g, int b1, const double *U, void *vals, int prec, hipStream_t s) {
+  if (b1 == 0) {
+    if (!g.tiles.empty()) launch_rgt_group<P>(b, g, U, vals, prec, s);
+    return;
+  }
   dim3 grid((unsigned)g.pencils.size());
 #define IGA_RGB(BB)                                                                                          \
   if (b1 == BB) {                                                                                            \
@@ -542,7 +573,7 @@ static void launch_rg_group(Batch &b, const Group &g, int b1, const double *U, v
 }
 
 static void launch_rg(Batch &b, const Group &g, int b1, const double *U, void *vals, int prec, hipStream_t s) {
-  if (g.pencils.empty()) return;
+  if (b1 != 0 && g.pencils.empty()) return;
   switch (g.P) {
     case 3: launch_rg_group<3>(b, g, b1, U, vals, prec, s); break;
     case 4: launch_rg_group<4>(b, g, b1, U, vals, prec, s); break;
@@ -611,6 +642,33 @@ static iga_status upload_spmv(Batch &b) {
   return IGA_OK;
 }
 
+// tiles of the tiled row-gather (degrees 1..4 with element-wise or unit kappa; every batched
+// instance has the identity geometry and simple knots)
+static bool tiles_supported(const Batch &b, const Group &g) {
+  if (g.P < 2 || g.P > 5) return false;
+  for (int i : g.insts)
+    if (!rgt2_supported(b.hs[i]->pb)) return false;
+  return true;
+}
+
+static iga_status build_tiles(Batch &b, Group &g) {
+  g.tiles.clear();
+  int T0 = 0, B1 = 0;
+  switch (g.P) {
+    case 2: T0 = rgt::Shape2<2>::T0; B1 = rgt::Shape2<2>::B1; break;
+    case 3: T0 = rgt::Shape2<3>::T0; B1 = rgt::Shape2<3>::B1; break;
+    case 4: T0 = rgt::Shape2<4>::T0; B1 = rgt::Shape2<4>::B1; break;
+    case 5: T0 = rgt::Shape2<5>::T0; B1 = rgt::Shape2<5>::B1; break;
+    default: return IGA_OK;
+  }
+  for (int i : g.insts) {
+    const DevProblem &pb = b.hs[i]->pb;
+    const int nt = rgt::rgt2_tiles_0(pb.n[0], T0) * ((pb.n[1] + B1 - 1) / B1);
+    for (int k = 0; k < nt; ++k) g.tiles.push_back(Pair{i, k});
+  }
+  return bupload(b, &g.d_tiles, g.tiles);
+}
+
 static iga_status build_pencils(Batch &b, Group &g) {
   g.pencils.clear();
   for (int i : g.insts) {
@@ -647,12 +705,16 @@ static iga_status autotune(Batch &b) {
       if (have_rg) g.b1 = g_tune[key_rg];
       if (have_sp) g.lpr = g_tune[key_sp];
     }
+    const bool tiles = tiles_supported(b, g);
+    if (tiles && (st = build_tiles(b, g))) return st;
+    if (have_rg && g.b1 == 0 && !tiles) have_rg = false;
     if (!have_rg) {
       float best = 1e30f;
       int bestb = 4;
-      for (int cand : {1, 4, 8}) {
+      for (int cand : {0, 1, 4, 8}) {
+        if (cand == 0 && !tiles) continue;
         g.b1 = cand;
-        if ((st = build_pencils(b, g))) return st;
+        if (cand > 0 && (st = build_pencils(b, g))) return st;
         launch_rg(b, g, cand, U, b.vals, IGA_FP64, b.bs);
         hipEventRecord(e0, b.bs);
         for (int r = 0; r < 3; ++r) launch_rg(b, g, cand, U, b.vals, IGA_FP64, b.bs);
@@ -665,7 +727,7 @@ static iga_status autotune(Batch &b) {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune[key_rg] = bestb;
     }
-    if ((st = build_pencils(b, g))) return st;
+    if (g.b1 > 0 && (st = build_pencils(b, g))) return st;
   }
   // SpMV lanes per row: tune each group with the others fixed
   for (size_t gi = 0; gi < b.groups.size(); ++gi) {

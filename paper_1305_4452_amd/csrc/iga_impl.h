@@ -52,6 +52,8 @@ struct DevProblem {
   // 1D Galerkin matrices per axis, band storage [n][2p+1] (offset o = j - i + p):
   //   M_d[i][o] = sum_g w(g) B_i(g) B_j(g),  A_d[i][o] = sum_g w(g) B'_i(g) B'_j(g)
   const double *sepM[3], *sepA[3];
+  // the same per element: elM_d[e][a][b] = sum_q w(q) B_a(q) B_b(q) over element e (local a, b < P)
+  const double *elM[3], *elA[3];
 };
 
 __host__ __device__ inline int ipow(int b, int e) {
@@ -210,6 +212,8 @@ iga_status launch_jac_scatter(Handle &h, const double *U, void *vals, int prec, 
 iga_status launch_jac_rowgather(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
 bool rowgather_supported(const Handle &h, int prec, int b1, int b2);
 iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
+bool rgt2_supported(const DevProblem &pb);
+iga_status launch_jac_rgt2(Handle &h, const double *U, void *vals, int prec);
 bool rgsep_supported(const Handle &h, int b1, int b2);
 iga_status launch_spmv(Handle &h, const void *vals, int prec, const double *x, double *y,
                        double *partial_dot, int npart);

@@ -1,0 +1,253 @@
+// Tiled 2D row-gather Jacobian for the analytic metric (identity geometry, no weights, kappa one or
+// element-wise, every interior knot simple).  Shared by the single-problem and batched launchers.
+//
+// A workgroup owns a tile of T0 x B1 rows (i0 along axis 0, i1 along axis 1).  With
+// c = kappa_e W and m = -lambda W e^u at the Gauss points (the Jacobian of the weak form, Sec. 3),
+//   J[i][j] = sum_e kappa_e (A0_e M1_e + M0_e A1_e)[i][j]  +  sum_g m(g) N_i(g) N_j(g),
+// where A_e / M_e are the 1D element stiffness / mass matrices; the first part is a sum of products
+// of 1D element matrices (the global 1D band matrices when kappa = 1) and only the reaction part
+// is contracted over Gauss points, by sum factorisation:
+//   a. u at the tile's Gauss points (two 1D contractions of the coefficients), m into LDS;
+//   b. level 1 (axis 1): Sm[i1, o1][g0] = sum_{g1} m(g0, g1) N_i1(g1) N_j1(g1)   (one wave per i1,
+//      one lane per g0: the axis-1 basis values are wave-uniform);
+//   c. level 2 (axis 0): J[(i0, i1)][(j0, j1)] += sum_{g0} Sm[i1, o1][g0] N_i0(g0) N_j0(g0) plus the
+//      stiffness, one wave per row i0 and one lane per (i1, o1) pair; rows are staged in LDS in
+//      CSR order;
+//   d. the staged rows are written out, consecutive lanes on consecutive CSR slots.
+// Dirichlet rows become identity rows and Dirichlet columns zero, as in every assembly path.
+#pragma once
+
+#include "iga_impl.h"
+
+namespace iga {
+namespace rgt {
+
+constexpr int kThreads = 256;
+
+// Tile shape per P = p + 1: B1 * (2p + 1) <= 64 (one lane per pair) and (T0 + p) * Q <= 64 (one
+// lane per Gauss point along axis 0).
+template <int P>
+struct Shape2;
+template <>
+struct Shape2<2> { static constexpr int B1 = 21, T0 = 24; };
+template <>
+struct Shape2<3> { static constexpr int B1 = 12, T0 = 19; };
+template <>
+struct Shape2<4> { static constexpr int B1 = 9, T0 = 12; };
+template <>
+struct Shape2<5> { static constexpr int B1 = 7, T0 = 8; };
+
+constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+template <int P, typename CT, typename OT>
+struct Lds2 {
+  static constexpr int p = P - 1, Q = P, W = 2 * p + 1;
+  static constexpr int B1 = Shape2<P>::B1, T0 = Shape2<P>::T0;
+  static constexpr int NPAIR = B1 * W;
+  static constexpr int G0M = (T0 + p) * Q, G1M = (B1 + p) * Q;
+  static constexpr int SP = G0M + 1;   // odd pitch of Sm rows (lanes = pairs read one column)
+  static constexpr int NI0M = T0 + 2 * p, NI1M = B1 + 2 * p;
+  static constexpr size_t bytes_m = align16((size_t)G1M * G0M * sizeof(CT));
+  static constexpr size_t bytes_stage = align16((size_t)T0 * B1 * W * W * sizeof(OT));
+  // region A: m at the Gauss points, then (after level 1) the staged rows
+  static constexpr size_t bytes_a = bytes_m > bytes_stage ? bytes_m : bytes_stage;
+  static constexpr size_t bytes_s = align16((size_t)NPAIR * SP * sizeof(CT));
+  static constexpr size_t bytes_uv = align16((size_t)(NI0M * NI1M + NI1M * G0M) * sizeof(double));
+  // region B: coefficients and their axis-0 contraction (phase a), then Sm
+  static constexpr size_t bytes_b = bytes_s > bytes_uv ? bytes_s : bytes_uv;
+  static constexpr size_t bytes_k = align16((size_t)(T0 + p) * (B1 + p) * sizeof(double));
+  static constexpr size_t total = bytes_a + bytes_b + bytes_k;
+  static_assert(NPAIR <= 64, "one lane per (i1, o1) pair");
+};
+
+// number of tiles of one problem
+__host__ __device__ inline int rgt2_tiles_0(int n0, int T0) { return (n0 + T0 - 1) / T0; }
+
+template <int P, typename CT, typename OT>
+__device__ inline void rgt2_body(const DevProblem &pb, const int tile, const double *__restrict__ U,
+                                 OT *__restrict__ vals, char *__restrict__ lds) {
+  using L = Lds2<P, CT, OT>;
+  constexpr int p = L::p, Q = L::Q, W = L::W, B1 = L::B1, T0 = L::T0;
+  constexpr int NW = kThreads / 64;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1];
+  const int nt0 = rgt2_tiles_0(n0, T0);
+  const int I0 = (tile % nt0) * T0, I1 = (tile / nt0) * B1;
+  const int E0lo = max(0, I0 - p), E0hi = min(ne0 - 1, I0 + T0 - 1);
+  const int E1lo = max(0, I1 - p), E1hi = min(ne1 - 1, I1 + B1 - 1);
+  const int NE0 = E0hi - E0lo + 1, NE1 = E1hi - E1lo + 1;
+  const int G0 = NE0 * Q, G1 = NE1 * Q, NI0 = NE0 + p, NI1 = NE1 + p;
+  CT *mQ = (CT *)lds;                                   // [G1M][G0M]
+  OT *stage = (OT *)lds;                                // [B1][T0][W * W], after level 1
+  CT *Sm = (CT *)(lds + L::bytes_a);                    // [NPAIR][SP]
+  double *sU = (double *)(lds + L::bytes_a);            // [NI1M][NI0M], phase a only
+  double *V = sU + L::NI0M * L::NI1M;                   // [NI1M][G0M], phase a only
+  double *kt = (double *)(lds + L::bytes_a + L::bytes_b);   // [NE0][NE1] element kappa
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const double *__restrict__ B0 = pb.ax[0].B;
+  const double *__restrict__ B1t = pb.ax[1].B;
+  const bool kel = pb.kappa_mode == IGA_KAPPA_ELEMENT;
+
+  // ---- a. u and m at the tile's Gauss points -------------------------------------------
+  for (int i = t; i < NI0 * NI1; i += kThreads) {
+    const int k0 = i % NI0, k1 = i / NI0;
+    sU[k1 * L::NI0M + k0] = U[(E0lo + k0) + (int64_t)n0 * (E1lo + k1)];
+  }
+  if (kel)
+    for (int i = t; i < NE0 * NE1; i += kThreads) {
+      const int el0 = i % NE0, el1 = i / NE0;
+      kt[el0 * NE1 + el1] = pb.kel[(E0lo + el0) + (int64_t)ne0 * (E1lo + el1)];
+    }
+  __syncthreads();
+  for (int i = t; i < NI1 * G0; i += kThreads) {
+    const int g0 = i % G0, k1 = i / G0, el0 = g0 / Q, q0 = g0 % Q;
+    const double *Bq = B0 + ((size_t)(E0lo + el0) * Q + q0) * P;
+    double s = 0;
+#pragma unroll
+    for (int a0 = 0; a0 < P; ++a0) s += Bq[a0] * sU[k1 * L::NI0M + el0 + a0];
+    V[k1 * L::G0M + g0] = s;
+  }
+  __syncthreads();
+  {
+    const double lam = pb.lambda;
+    const double *wq0 = pb.ax[0].wq + (size_t)E0lo * Q, *wq1 = pb.ax[1].wq + (size_t)E1lo * Q;
+    for (int i = t; i < G1 * G0; i += kThreads) {
+      const int g0 = i % G0, g1 = i / G0, el1 = g1 / Q, q1 = g1 % Q;
+      const double *Bq = B1t + ((size_t)(E1lo + el1) * Q + q1) * P;
+      double u = 0;
+#pragma unroll
+      for (int a1 = 0; a1 < P; ++a1) u += Bq[a1] * V[(el1 + a1) * L::G0M + g0];
+      mQ[g1 * L::G0M + g0] = (CT)(-lam * wq0[g0] * wq1[g1] * exp(u));
+    }
+  }
+  __syncthreads();
+
+  // ---- b. level 1: contract axis 1 (wave = i1, lane = g0) ------------------------------
+  for (int i1l = wave; i1l < B1; i1l += NW) {
+    const int i1 = I1 + i1l;
+    if (i1 >= n1) break;
+    for (int gb = 0; gb < G0; gb += 64) {
+      const int g0 = gb + lane;
+      const bool ok = g0 < G0;
+      CT sm[W];
+#pragma unroll
+      for (int o = 0; o < W; ++o) sm[o] = 0;
+#pragma unroll
+      for (int a1 = 0; a1 <= p; ++a1) {
+        const int e1 = i1 - a1;
+        if (e1 < 0 || e1 >= ne1) continue;
+        const int el1 = e1 - E1lo;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) {
+          const double *Bq = B1t + ((size_t)e1 * Q + q1) * P;
+          const CT m = ok ? mQ[(el1 * Q + q1) * L::G0M + g0] : CT(0);
+          const CT mb = m * (CT)Bq[a1];
+#pragma unroll
+          for (int b1 = 0; b1 <= p; ++b1) sm[b1 - a1 + p] += mb * (CT)Bq[b1];
+        }
+      }
+      if (ok)
+#pragma unroll
+        for (int o = 0; o < W; ++o) Sm[(i1l * W + o) * L::SP + g0] = sm[o];
+    }
+  }
+  __syncthreads();
+
+  // ---- c. level 2: contract axis 0 (wave = i0, lane = (i1, o1)) plus the stiffness -----
+  {
+    const int pair = lane;
+    const int i1l = pair / W, o1 = pair % W - p;
+    const int i1 = I1 + i1l, j1 = i1 + o1;
+    const bool live = pair < L::NPAIR && i1 < n1 && j1 >= 0 && j1 < n1;
+    // axis-1 factors of the stiffness, fixed per lane
+    CT sM1 = 0, sA1 = 0;
+    CT M1s[P], A1s[P];
+#pragma unroll
+    for (int a1 = 0; a1 < P; ++a1) { M1s[a1] = 0; A1s[a1] = 0; }
+    if (live) {
+      if (!kel) {
+        sM1 = (CT)pb.sepM[1][(size_t)i1 * W + (o1 + p)];
+        sA1 = (CT)pb.sepA[1][(size_t)i1 * W + (o1 + p)];
+      } else {
+#pragma unroll
+        for (int a1 = 0; a1 < P; ++a1) {
+          const int e1 = i1 - a1, b1 = j1 - e1;
+          if (e1 >= 0 && e1 < ne1 && b1 >= 0 && b1 <= p) {
+            M1s[a1] = (CT)pb.elM[1][((size_t)e1 * P + a1) * P + b1];
+            A1s[a1] = (CT)pb.elA[1][((size_t)e1 * P + a1) * P + b1];
+          }
+        }
+      }
+    }
+    const int l1 = max(0, i1 - p);
+    for (int i0l = wave; i0l < T0; i0l += NW) {
+      const int i0 = I0 + i0l;
+      if (i0 >= n0) break;
+      CT out[W];
+      if (!kel) {
+        const double *M0r = pb.sepM[0] + (size_t)i0 * W, *A0r = pb.sepA[0] + (size_t)i0 * W;
+#pragma unroll
+        for (int o = 0; o < W; ++o) out[o] = (CT)A0r[o] * sM1 + (CT)M0r[o] * sA1;
+      } else {
+#pragma unroll
+        for (int o = 0; o < W; ++o) out[o] = 0;
+      }
+#pragma unroll
+      for (int a0 = 0; a0 <= p; ++a0) {
+        const int e0 = i0 - a0;
+        if (e0 < 0 || e0 >= ne0) continue;
+        const int el0 = e0 - E0lo;
+        if (kel) {
+          CT kM = 0, kA = 0;
+#pragma unroll
+          for (int a1 = 0; a1 < P; ++a1) {
+            const int el1 = min(max(i1 - a1 - E1lo, 0), NE1 - 1);
+            const CT k = (CT)kt[el0 * NE1 + el1];
+            kM += k * M1s[a1];
+            kA += k * A1s[a1];
+          }
+          const double *eM = pb.elM[0] + ((size_t)e0 * P + a0) * P, *eA = pb.elA[0] + ((size_t)e0 * P + a0) * P;
+#pragma unroll
+          for (int b0 = 0; b0 <= p; ++b0) out[b0 - a0 + p] += (CT)eA[b0] * kM + (CT)eM[b0] * kA;
+        }
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+          const double *Bq = B0 + ((size_t)e0 * Q + q0) * P;
+          const CT s = live ? Sm[pair * L::SP + el0 * Q + q0] : CT(0);
+          const CT xb = s * (CT)Bq[a0];
+#pragma unroll
+          for (int b0 = 0; b0 <= p; ++b0) out[b0 - a0 + p] += xb * (CT)Bq[b0];
+        }
+      }
+      if (live) {
+        const bool rowDir = is_dirichlet_idx(pb, i0, i1, 0);
+        const int l0 = max(0, i0 - p), w0 = min(n0 - 1, i0 + p) - l0 + 1;
+        OT *srow = stage + ((size_t)i1l * T0 + i0l) * (W * W) + (size_t)(j1 - l1) * w0;
+#pragma unroll
+        for (int o = 0; o < W; ++o) {
+          const int j0 = i0 + o - p;
+          if (j0 < 0 || j0 >= n0) continue;
+          double v;
+          if (rowDir) v = (j0 == i0 && j1 == i1) ? 1.0 : 0.0;
+          else if (is_dirichlet_idx(pb, j0, j1, 0)) v = 0.0;
+          else v = (double)out[o];
+          srow[j0 - l0] = (OT)v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- d. staged rows to the CSR values (rows of one i1 are consecutive in CSR) ---------
+  for (int i = t; i < B1 * T0 * W * W; i += kThreads) {
+    const int k = i % (W * W), r = i / (W * W), i0l = r % T0, i1l = r / T0;
+    const int i0 = I0 + i0l, i1 = I1 + i1l;
+    if (i0 >= n0 || i1 >= n1) continue;
+    const int w0 = min(n0 - 1, i0 + p) - max(0, i0 - p) + 1, w1 = min(n1 - 1, i1 + p) - max(0, i1 - p) + 1;
+    if (k >= w0 * w1) continue;
+    vals[pb.row_ptr[i0 + (int64_t)n0 * i1] + k] = stage[(size_t)r * (W * W) + k];
+  }
+}
+
+}  // namespace rgt
+}  // namespace iga

@@ -1,0 +1,47 @@
+// Tiled 2D row-gather Jacobian (single problem): one workgroup per T0 x B1 tile of rows; the body
+// is shared with the batched solver.
+#include "kern_rgt2.h"
+
+namespace iga {
+namespace {
+
+template <int P, typename OT>
+__global__ void __launch_bounds__(rgt::kThreads) k_rgt2(DevProblem pb, const double *__restrict__ U,
+                                                        OT *__restrict__ vals) {
+  __shared__ __align__(16) char lds[rgt::Lds2<P, OT, OT>::total];
+  rgt::rgt2_body<P, OT, OT>(pb, (int)blockIdx.x, U, vals, lds);
+}
+
+template <int P>
+iga_status run_rgt2(Handle &h, const double *U, void *vals, int prec) {
+  using S = rgt::Shape2<P>;
+  const unsigned nb = (unsigned)(rgt::rgt2_tiles_0(h.pb.n[0], S::T0) * ((h.pb.n[1] + S::B1 - 1) / S::B1));
+  kt_begin(h, "k_rgt2");
+  if (prec == IGA_FP32)
+    hipLaunchKernelGGL((k_rgt2<P, float>), dim3(nb), dim3(rgt::kThreads), 0, h.stream, h.pb, U, (float *)vals);
+  else
+    hipLaunchKernelGGL((k_rgt2<P, double>), dim3(nb), dim3(rgt::kThreads), 0, h.stream, h.pb, U, (double *)vals);
+  kt_end(h);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+}  // namespace
+
+bool rgt2_supported(const DevProblem &pb) {
+  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && pb.P >= 2 && pb.P <= 5 &&
+         (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
+}
+
+iga_status launch_jac_rgt2(Handle &h, const double *U, void *vals, int prec) {
+  if (!rgt2_supported(h.pb)) return fail(IGA_EUNSUPPORTED, "tiled 2D row-gather configuration");
+  switch (h.pb.P) {
+    case 2: return run_rgt2<2>(h, U, vals, prec);
+    case 3: return run_rgt2<3>(h, U, vals, prec);
+    case 4: return run_rgt2<4>(h, U, vals, prec);
+    case 5: return run_rgt2<5>(h, U, vals, prec);
+  }
+  return fail(IGA_EUNSUPPORTED, "tiled 2D row-gather degree");
+}
+
+}  // namespace iga

@@ -393,7 +393,9 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     }
     // 1D mass and stiffness in band storage (used by the separable Jacobian kernel)
     const int W = 2 * p + 1;
+    const int P1 = p + 1;
     std::vector<double> sM((size_t)n * W, 0.0), sA((size_t)n * W, 0.0);
+    std::vector<double> eM(efirst.size() * P1 * P1, 0.0), eA(efirst.size() * P1 * P1, 0.0);
     for (size_t e = 0; e < efirst.size(); ++e)
       for (int q = 0; q < pb.Q; ++q) {
         const double *Bq = &B[(e * pb.Q + q) * (p + 1)], *dBq = &dB[(e * pb.Q + q) * (p + 1)];
@@ -401,17 +403,23 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
         for (int ia = 0; ia <= p; ++ia)
           for (int ib = 0; ib <= p; ++ib) {
             size_t o = (size_t)(efirst[e] + ia) * W + (ib - ia + p);
-            sM[o] += wgt * Bq[ia] * Bq[ib];
-            sA[o] += wgt * dBq[ia] * dBq[ib];
+            const double m = wgt * Bq[ia] * Bq[ib], k = wgt * dBq[ia] * dBq[ib];
+            sM[o] += m;
+            sA[o] += k;
+            eM[(e * P1 + ia) * P1 + ib] += m;
+            eA[(e * P1 + ia) * P1 + ib] += k;
           }
       }
-    double *d_sM, *d_sA;
-    if ((st = dev_upload(*h, &d_sM, sM.data(), sM.size())) || (st = dev_upload(*h, &d_sA, sA.data(), sA.size()))) {
+    double *d_sM, *d_sA, *d_eM, *d_eA;
+    if ((st = dev_upload(*h, &d_sM, sM.data(), sM.size())) || (st = dev_upload(*h, &d_sA, sA.data(), sA.size())) ||
+        (st = dev_upload(*h, &d_eM, eM.data(), eM.size())) || (st = dev_upload(*h, &d_eA, eA.data(), eA.size()))) {
       iga_destroy((iga_t)h);
       return st;
     }
     pb.sepM[a] = d_sM;
     pb.sepA[a] = d_sA;
+    pb.elM[a] = d_eM;
+    pb.elA[a] = d_eA;
     hostSM[a] = sM;
     hostSA[a] = sA;
     int *d_ef, *d_stl, *d_stw;

@@ -230,6 +230,30 @@ def test_separable_rowgather_segments(segments, prec):
     assert names == ["k_mfield", "k_rgsep3"]
 
 
+@pytest.mark.parametrize("p,nel,km,mask", [(1, [50, 23], 0, None), (2, [40, 27], 2, None), (3, [25, 20], 0, 0b0110),
+                                           (4, [13, 17], 2, 0b1001), (4, [3, 2], 0, None), (2, 1, 0, None),
+                                           (3, [30, 4], 2, 0b0011)])
+@pytest.mark.parametrize("prec", [iga.IGA_FP64, iga.IGA_FP32])
+def test_tiled_rowgather_2d(p, nel, km, mask, prec):
+    """The tiled 2D row-gather (default for 2D with the identity map): several tiles per axis with
+    ragged last tiles, unit and element-wise kappa, partial Dirichlet masks, single-element meshes."""
+    print(f"[case] tiled 2D row-gather p={p} nel={nel} kappa={km} mask={mask} prec={prec}", flush=True)
+    patch = inputs.unit_box(2, nel, p)
+    ne = [n - p for n in patch.shape]
+    kap = inputs.uniform(9, 1, ne[0] * ne[1], 0.5, 2.0) if km == 2 else None
+    o = oracle.Oracle(patch.knots, patch.degree, None, None, lam=4.0, kappa_mode=km, kappa=kap, dirichlet_mask=mask)
+    g = iga.IGA(patch.knots, patch.degree, None, None, lam=4.0, kappa_mode=km, kappa=kap, dirichlet_mask=mask)
+    g.set_option(iga.IGA_OPT_KERNEL_TIMING, 1)
+    U = inputs.uniform(11, 3, patch.ndof, 0.0, 0.3)
+    dt = torch.float64 if prec == iga.IGA_FP64 else torch.float32
+    vals = torch.full((g.nnz,), np.nan, dtype=dt, device="cuda")
+    g.assemble_jacobian(dev(U), vals, prec)
+    got = host(vals)
+    assert np.all(np.isfinite(got)), "some CSR value was never written"
+    assert rel(got, o.jacobian(U)) < (TOL64 if prec == iga.IGA_FP64 else 1e-5)
+    assert [n for n, _ in g.kernel_times()] == ["k_rgt2"]
+
+
 def test_fp32_jacobian_values():
     patch, o, g, U = build_pair("box3_p3")
     vals = torch.zeros(g.nnz, dtype=torch.float32, device="cuda")
