@@ -22,6 +22,7 @@
 #include "iga_impl.h"
 #include "kern_elem.h"
 #include "kern_rg.h"
+#include "kern_res2.h"
 #include "kern_rgt2.h"
 
 namespace iga {
@@ -124,6 +125,18 @@ k_b_rowgather(const DevProblem *__restrict__ pbs, const Pair *__restrict__ work,
   const Pair w = work[blockIdx.x];
   if (!act[w.inst]) return;
   rgk::rowgather2_body<P, false, B1, OT, OT>(pbs[w.inst], w.idx, U + off[w.inst], vals + noff[w.inst]);
+}
+
+template <int P>
+__global__ void __launch_bounds__(rst::kThreads) k_b_res2(const DevProblem *__restrict__ pbs,
+                                                          const Pair *__restrict__ work,
+                                                          const int64_t *__restrict__ off,
+                                                          const int *__restrict__ act, const double *__restrict__ U,
+                                                          double *__restrict__ R) {
+  __shared__ double lds[rst::Res2<P>::total / sizeof(double)];
+  const Pair w = work[blockIdx.x];
+  if (!act[w.inst]) return;
+  rst::res2_body<P>(pbs[w.inst], w.idx, U + off[w.inst], R + off[w.inst], lds);
 }
 
 template <int P, typename OT>
@@ -279,16 +292,26 @@ __global__ void __launch_bounds__(256) k_b_cg_p(const Tile *__restrict__ tl, con
 }
 
 // number of Newton-active instances whose CG has not converged (single block)
-__global__ void k_b_count(int n, const int *__restrict__ vt_start, const int *__restrict__ act,
-                          const double *__restrict__ target, const double *__restrict__ rr, int *__restrict__ out) {
+// flags[i] = 1 if instance i is active and its CG has not converged (one wave per instance)
+__global__ void __launch_bounds__(256) k_b_flags(int n, const int *__restrict__ vt_start, const int *__restrict__ act,
+                                                 const double *__restrict__ target, const double *__restrict__ rr,
+                                                 int *__restrict__ flags) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;
+  double v = 0;
+  if (act[i])
+    for (int k = vt_start[i] + lane; k < vt_start[i + 1]; k += 64) v += rr[k];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) flags[i] = (act[i] && sqrt(v) > target[i] && v == v) ? 1 : 0;
+}
+
+// number of instances whose CG still runs
+__global__ void __launch_bounds__(256) k_b_count(int n, const int *__restrict__ flags, int *__restrict__ out) {
   __shared__ double sh[4];
-  int c = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!act[i]) continue;
-    double s = inst_sum(rr, vt_start, i, sh);
-    if (sqrt(s) > target[i] && s == s) ++c;
-  }
-  if (threadIdx.x == 0) *out = c;
+  double c = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c += flags[i];
+  c = bsum(c, sh);
+  if (threadIdx.x == 0) *out = (int)c;
 }
 
 __global__ void k_b_axpy(const Tile *__restrict__ tl, const int64_t *__restrict__ off, const int *__restrict__ act,
@@ -460,8 +483,9 @@ struct Group {
   Pair *d_pencils = nullptr;
   std::vector<Pair> tiles;   // (instance, tile) of the tiled row-gather
   Pair *d_tiles = nullptr;
-  std::vector<Pair> elems;
+  std::vector<Pair> elems;   // (instance, element), or (instance, element tile) when res_tiles
   Pair *d_elems = nullptr;
+  bool res_tiles = false;
 };
 
 struct Batch {
@@ -491,7 +515,7 @@ struct Batch {
   int vals_prec = -1;
   double *partA = nullptr, *partB = nullptr, *partC = nullptr, *partD = nullptr, *part_pq = nullptr;
   double *norms = nullptr, *target = nullptr;
-  int *act = nullptr, *iters = nullptr, *count = nullptr;
+  int *act = nullptr, *iters = nullptr, *count = nullptr, *flags = nullptr;
   hipGraphExec_t graph = nullptr;
   // batched fast-diagonalisation preconditioner (bf_on: every instance has one)
   bool bf_on = false;
@@ -586,6 +610,16 @@ static void launch_rg(Batch &b, const Group &g, int b1, const double *U, void *v
 static void launch_res(Batch &b, const Group &g, const double *U, double *R, hipStream_t s) {
   if (g.elems.empty()) return;
   dim3 grid((unsigned)g.elems.size()), blk(64);
+  if (g.res_tiles) {
+    dim3 bt(rst::kThreads);
+    switch (g.P) {
+      case 2: hipLaunchKernelGGL(k_b_res2<2>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+      case 3: hipLaunchKernelGGL(k_b_res2<3>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+      case 4: hipLaunchKernelGGL(k_b_res2<4>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+      case 5: hipLaunchKernelGGL(k_b_res2<5>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+    }
+    return;
+  }
   switch (g.P) {
     case 2: hipLaunchKernelGGL(k_b_residual<2>, grid, blk, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
     case 3: hipLaunchKernelGGL(k_b_residual<3>, grid, blk, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
@@ -995,7 +1029,7 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
       (st = balloc(*b, &b->partB, nvt)) || (st = balloc(*b, &b->partC, nvt)) || (st = balloc(*b, &b->partD, nvt)) ||
       (st = balloc(*b, &b->norms, (size_t)n)) || (st = balloc(*b, &b->target, (size_t)n)) ||
       (st = balloc(*b, &b->act, (size_t)n)) || (st = balloc(*b, &b->iters, (size_t)n)) ||
-      (st = balloc(*b, &b->count, 1))) {
+      (st = balloc(*b, &b->count, 1)) || (st = balloc(*b, &b->flags, (size_t)n))) {
     batch_free(b);
     return st;
   }
@@ -1008,8 +1042,20 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
   b->vals = vals;
   b->vals_prec = IGA_FP64;
   for (Group &g : b->groups) {
-    for (int k : g.insts)
-      for (int64_t e = 0; e < b->hs[k]->pb.E; ++e) g.elems.push_back(Pair{k, (int)e});
+    g.res_tiles = g.P >= 2 && g.P <= 5;
+    for (int k : g.insts) g.res_tiles = g.res_tiles && res2_supported(b->hs[k]->pb);
+    int TE = 0;
+    switch (g.P) {
+      case 2: TE = rst::Res2<2>::TE; break;
+      case 3: TE = rst::Res2<3>::TE; break;
+      case 4: TE = rst::Res2<4>::TE; break;
+      case 5: TE = rst::Res2<5>::TE; break;
+    }
+    for (int k : g.insts) {
+      const DevProblem &pk = b->hs[k]->pb;
+      const int64_t cnt = g.res_tiles ? rst::res2_tiles(pk.ne[0], pk.ne[1], TE) : pk.E;
+      for (int64_t e = 0; e < cnt; ++e) g.elems.push_back(Pair{k, (int)e});
+    }
     if ((st = bupload(*b, &g.d_elems, g.elems))) {
       batch_free(b);
       return st;
@@ -1073,7 +1119,9 @@ static iga_status capture_cg_graph(Batch &b, int prec, int chunk, bool fdm) {
     hipLaunchKernelGGL(k_b_cg_p, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_vt_start, b.d_off, b.act, b.target,
                        rz_cur, rr_cur, rz_new, z, p, b.iters);
   }
-  hipLaunchKernelGGL(k_b_count, dim3(1), dim3(256), 0, b.bs, b.n, b.d_vt_start, b.act, b.target, b.partC, b.count);
+  hipLaunchKernelGGL(k_b_flags, dim3((unsigned)((b.n + 3) / 4)), dim3(256), 0, b.bs, b.n, b.d_vt_start, b.act,
+                     b.target, b.partC, b.flags);
+  hipLaunchKernelGGL(k_b_count, dim3(1), dim3(256), 0, b.bs, b.n, (const int *)b.flags, b.count);
   hipGraph_t g;
   hipError_t e = hipStreamEndCapture(b.bs, &g);
   if (e != hipSuccess) return fail(IGA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));

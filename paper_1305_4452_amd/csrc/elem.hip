@@ -460,7 +460,9 @@ iga_status launch_fill(Handle &h, double *x, int64_t n, double v) {
 iga_status launch_residual(Handle &h, const double *U, double *R) {
   iga_status st = launch_fill(h, R, h.pb.N, 0.0);
   if (st) return st;
-  if ((st = dispatch_dpt<RunRes>(h, U, R))) return st;
+  if (res2_supported(h.pb)) st = launch_res2(h, U, R);
+  else st = dispatch_dpt<RunRes>(h, U, R);
+  if (st) return st;
   hipLaunchKernelGGL(k_bc_copy, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb, U, R);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;

@@ -213,6 +213,8 @@ iga_status launch_jac_rowgather(Handle &h, const double *U, void *vals, int prec
 bool rowgather_supported(const Handle &h, int prec, int b1, int b2);
 iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
 bool rgt2_supported(const DevProblem &pb);
+bool res2_supported(const DevProblem &pb);
+iga_status launch_res2(Handle &h, const double *U, double *R);
 iga_status launch_jac_rgt2(Handle &h, const double *U, void *vals, int prec);
 bool rgsep_supported(const Handle &h, int b1, int b2);
 iga_status launch_spmv(Handle &h, const void *vals, int prec, const double *x, double *y,

@@ -1,0 +1,144 @@
+// Tiled 2D residual for the analytic metric (identity geometry, no weights, kappa one or
+// element-wise; every interior knot simple, so element e carries functions e .. e + p).  Shared
+// by the single-problem and batched launchers.
+//
+// A workgroup owns TE x TE elements.  The weak-form residual of Sec. 3,
+//   R_A = sum_g [ kappa W grad N_A . grad u  -  W N_A (lambda e^u + f) ],
+// is evaluated by sum factorisation over the whole tile: the coefficients of the tile's
+// (TE + p)^2 functions are contracted to u, du/dxi0, du/dxi1 (and f) at its (TE Q)^2 Gauss
+// points, the point integrands are formed, and the transposed contractions give the tile's
+// contribution to each of those functions, added to R with one FP64 atomic per function (the
+// functions on the tile border are shared with neighbouring tiles).  R must be zeroed before and
+// the Dirichlet rows set afterwards, as for the element-by-element kernel.
+#pragma once
+
+#include "iga_impl.h"
+
+namespace iga {
+namespace rst {
+
+constexpr int kThreads = 256;
+
+// elements per tile side: TE * Q = 40 Gauss points per axis
+template <int P>
+struct Res2 {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TE = 40 / Q;
+  static constexpr int NI = TE + p, G = TE * Q;
+  // doubles: sU, sF [NI][NI]; V, D, VF [NI][G]; F0, F1, S [G][G]
+  static constexpr int n_u = NI * NI, n_v = NI * G, n_f = G * G;
+  static constexpr size_t total = (size_t)(2 * n_u + 3 * n_v + 3 * n_f) * sizeof(double);
+};
+
+__host__ __device__ inline int res2_tiles(int ne0, int ne1, int TE) {
+  return ((ne0 + TE - 1) / TE) * ((ne1 + TE - 1) / TE);
+}
+
+template <int P>
+__device__ inline void res2_body(const DevProblem &pb, const int tile, const double *__restrict__ U,
+                                 double *__restrict__ R, double *__restrict__ lds) {
+  using S_ = Res2<P>;
+  constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G;
+  const int n0 = pb.n[0], ne0 = pb.ne[0], ne1 = pb.ne[1];
+  const int nt0 = (ne0 + TE - 1) / TE;
+  const int E0 = (tile % nt0) * TE, E1 = (tile / nt0) * TE;
+  const int NE0 = min(TE, ne0 - E0), NE1 = min(TE, ne1 - E1);
+  const int G0 = NE0 * Q, G1 = NE1 * Q;
+  // the tile's functions: f0 .. f0 + NI0 - 1 along axis 0 (likewise axis 1)
+  const int f0 = E0, f1 = E1, NI0 = NE0 + p, NI1 = NE1 + p;
+  double *sU = lds, *sF = sU + S_::n_u;
+  double *V = sF + S_::n_u, *D = V + S_::n_v, *VF = D + S_::n_v;
+  double *F0 = VF + S_::n_v, *F1 = F0 + S_::n_f, *Sg = F1 + S_::n_f;
+  double *Ya = V, *Yb = D;   // reused once the point integrands are formed
+  const int t = threadIdx.x;
+  const bool src = pb.src != nullptr;
+  const bool kel = pb.kappa_mode == IGA_KAPPA_ELEMENT;
+
+  for (int i = t; i < NI0 * NI1; i += kThreads) {
+    const int k0 = i % NI0, k1 = i / NI0;
+    const int64_t A = (f0 + k0) + (int64_t)n0 * (f1 + k1);
+    sU[k1 * NI + k0] = U[A];
+    if (src) sF[k1 * NI + k0] = pb.src[A];
+  }
+  __syncthreads();
+  // axis 0: coefficients -> (value, derivative) at the Gauss points, per function row k1
+  for (int i = t; i < NI1 * G0; i += kThreads) {
+    const int g0 = i % G0, k1 = i / G0, el0 = g0 / Q, q0 = g0 % Q;
+    const size_t o = ((size_t)(E0 + el0) * Q + q0) * P;
+    double v = 0, d = 0, vf = 0;
+#pragma unroll
+    for (int a0 = 0; a0 < P; ++a0) {
+      const double c = sU[k1 * NI + el0 + a0];
+      v += pb.ax[0].B[o + a0] * c;
+      d += pb.ax[0].dB[o + a0] * c;
+      if (src) vf += pb.ax[0].B[o + a0] * sF[k1 * NI + el0 + a0];
+    }
+    V[k1 * G + g0] = v;
+    D[k1 * G + g0] = d;
+    VF[k1 * G + g0] = vf;
+  }
+  __syncthreads();
+  // axis 1 and the point integrands
+  {
+    const double lam = pb.lambda;
+    for (int i = t; i < G1 * G0; i += kThreads) {
+      const int g0 = i % G0, g1 = i / G0, el1 = g1 / Q, q1 = g1 % Q, el0 = g0 / Q;
+      const size_t o = ((size_t)(E1 + el1) * Q + q1) * P;
+      double u = 0, u0 = 0, u1 = 0, f = 0;
+#pragma unroll
+      for (int a1 = 0; a1 < P; ++a1) {
+        const double b = pb.ax[1].B[o + a1], db = pb.ax[1].dB[o + a1];
+        const int r = (el1 + a1) * G + g0;
+        u += b * V[r];
+        u0 += b * D[r];
+        u1 += db * V[r];
+        f += b * VF[r];
+      }
+      const double W = pb.ax[0].wq[(size_t)E0 * Q + g0] * pb.ax[1].wq[(size_t)(E1 + el1) * Q + q1];
+      const double kw = (kel ? pb.kel[(E0 + el0) + (int64_t)ne0 * (E1 + el1)] : 1.0) * W;
+      F0[g1 * G + g0] = kw * u0;
+      F1[g1 * G + g0] = kw * u1;
+      Sg[g1 * G + g0] = -W * (lam * exp(u) + (src ? f : 0.0));
+    }
+  }
+  __syncthreads();
+  // transposed axis 1: Ya[k1][g0] = sum F0 N_k1, Yb[k1][g0] = sum F1 N'_k1 + S N_k1
+  for (int i = t; i < NI1 * G0; i += kThreads) {
+    const int g0 = i % G0, k1 = i / G0;
+    double ya = 0, yb = 0;
+    for (int el1 = 0; el1 < NE1; ++el1) {
+      const int a1 = k1 - el1;
+      if (a1 < 0 || a1 > p) continue;
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1) {
+        const size_t o = ((size_t)(E1 + el1) * Q + q1) * P + a1;
+        const int r = (el1 * Q + q1) * G + g0;
+        const double b = pb.ax[1].B[o];
+        ya += F0[r] * b;
+        yb += F1[r] * pb.ax[1].dB[o] + Sg[r] * b;
+      }
+    }
+    Ya[k1 * G + g0] = ya;
+    Yb[k1 * G + g0] = yb;
+  }
+  __syncthreads();
+  // transposed axis 0 and the scatter of the tile's contributions
+  for (int i = t; i < NI0 * NI1; i += kThreads) {
+    const int k0 = i % NI0, k1 = i / NI0;
+    double r = 0;
+    for (int el0 = 0; el0 < NE0; ++el0) {
+      const int a0 = k0 - el0;
+      if (a0 < 0 || a0 > p) continue;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) {
+        const size_t o = ((size_t)(E0 + el0) * Q + q0) * P + a0;
+        const int g0 = el0 * Q + q0;
+        r += Ya[k1 * G + g0] * pb.ax[0].dB[o] + Yb[k1 * G + g0] * pb.ax[0].B[o];
+      }
+    }
+    atomicAdd(&R[(f0 + k0) + (int64_t)n0 * (f1 + k1)], r);
+  }
+}
+
+}  // namespace rst
+}  // namespace iga

@@ -1,5 +1,7 @@
-// Tiled 2D row-gather Jacobian (single problem): one workgroup per T0 x B1 tile of rows; the body
-// is shared with the batched solver.
+// Tiled 2D kernels (single problem): the row-gather Jacobian, one workgroup per T0 x B1 tile of
+// rows, and the residual, one workgroup per TE x TE tile of elements; the bodies are shared with
+// the batched solver.
+#include "kern_res2.h"
 #include "kern_rgt2.h"
 
 namespace iga {
@@ -26,7 +28,37 @@ iga_status run_rgt2(Handle &h, const double *U, void *vals, int prec) {
   return IGA_OK;
 }
 
+template <int P>
+__global__ void __launch_bounds__(rst::kThreads) k_res2(DevProblem pb, const double *__restrict__ U,
+                                                        double *__restrict__ R) {
+  __shared__ double lds[rst::Res2<P>::total / sizeof(double)];
+  rst::res2_body<P>(pb, (int)blockIdx.x, U, R, lds);
+}
+
+template <int P>
+iga_status run_res2(Handle &h, const double *U, double *R) {
+  const unsigned nb = (unsigned)rst::res2_tiles(h.pb.ne[0], h.pb.ne[1], rst::Res2<P>::TE);
+  hipLaunchKernelGGL(k_res2<P>, dim3(nb), dim3(rst::kThreads), 0, h.stream, h.pb, U, R);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
 }  // namespace
+
+bool res2_supported(const DevProblem &pb) {
+  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && pb.P >= 2 && pb.P <= 5 &&
+         (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
+}
+
+iga_status launch_res2(Handle &h, const double *U, double *R) {
+  switch (h.pb.P) {
+    case 2: return run_res2<2>(h, U, R);
+    case 3: return run_res2<3>(h, U, R);
+    case 4: return run_res2<4>(h, U, R);
+    case 5: return run_res2<5>(h, U, R);
+  }
+  return fail(IGA_EUNSUPPORTED, "tiled 2D residual degree");
+}
 
 bool rgt2_supported(const DevProblem &pb) {
   return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && pb.P >= 2 && pb.P <= 5 &&

@@ -254,6 +254,29 @@ def test_tiled_rowgather_2d(p, nel, km, mask, prec):
     assert [n for n, _ in g.kernel_times()] == ["k_rgt2"]
 
 
+@pytest.mark.parametrize("p,nel,km,mask,src", [(1, [45, 23], 0, None, True), (2, [30, 27], 2, None, False),
+                                               (3, [25, 14], 0, 0b0110, True), (4, [17, 9], 2, 0b1001, True),
+                                               (4, [3, 2], 0, None, False), (2, 1, 0, None, True)])
+def test_tiled_residual_2d(p, nel, km, mask, src):
+    """The tiled 2D residual (default for 2D with the identity map): several element tiles per axis
+    with ragged last tiles, unit and element-wise kappa, a source term and partial Dirichlet masks."""
+    print(f"[case] tiled 2D residual p={p} nel={nel} kappa={km} mask={mask} src={src}", flush=True)
+    patch = inputs.unit_box(2, nel, p)
+    ne = [n - p for n in patch.shape]
+    kap = inputs.uniform(9, 1, ne[0] * ne[1], 0.5, 2.0) if km == 2 else None
+    f = inputs.uniform(9, 2, patch.ndof, -1.0, 1.0) if src else None
+    o = oracle.Oracle(patch.knots, patch.degree, None, None, lam=4.0, kappa_mode=km, kappa=kap, source=f,
+                      dirichlet_mask=mask)
+    g = iga.IGA(patch.knots, patch.degree, None, None, lam=4.0, kappa_mode=km, kappa=kap, source=f,
+                dirichlet_mask=mask)
+    U = inputs.uniform(11, 3, patch.ndof, 0.0, 0.3)
+    R = torch.full((g.N,), np.nan, dtype=torch.float64, device="cuda")
+    g.assemble_residual(dev(U), R)
+    got = host(R)
+    assert np.all(np.isfinite(got))
+    assert rel(got, o.residual(U)) < TOL64
+
+
 def test_fp32_jacobian_values():
     patch, o, g, U = build_pair("box3_p3")
     vals = torch.zeros(g.nnz, dtype=torch.float32, device="cuda")
