@@ -208,12 +208,22 @@ __global__ void __launch_bounds__(256) k_b_spmv(const DevProblem *__restrict__ p
   const VT *v = vals + noff[T.inst];
   const double *pp = p + o;
   const int sub = threadIdx.x % LPR, row = threadIdx.x / LPR;
+  const int n0 = pb.n[0], n1 = pb.n[1], deg = pb.p;
   double dot = 0;
   for (int r = row; r < T.count; r += 256 / LPR) {
     const int64_t A = T.start + r;
-    const int64_t b = pb.row_ptr[A], e = pb.row_ptr[A + 1];
+    // tensor-product pattern (simple knots): row (i0, i1) couples (l0 .. l0 + w0 - 1) x
+    // (l1 .. l1 + w1 - 1), stored with axis 0 fastest, so no column indices are read
+    const int i0 = (int)(A % n0), i1 = (int)(A / n0);
+    const int l0 = max(0, i0 - deg), w0 = min(n0 - 1, i0 + deg) - l0 + 1;
+    const int l1 = max(0, i1 - deg), w1 = min(n1 - 1, i1 + deg) - l1 + 1;
+    const int64_t b = pb.row_ptr[A];
+    const double *xb = pp + l0 + (int64_t)n0 * l1;
     double s = 0;
-    for (int64_t k = b + sub; k < e; k += LPR) s += (double)v[k] * pp[pb.col_idx[k]];
+    for (int k = sub; k < w0 * w1; k += LPR) {
+      const int o1 = k / w0, o0 = k - o1 * w0;
+      s += (double)v[b + k] * xb[o0 + (int64_t)n0 * o1];
+    }
     for (int w = LPR / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, LPR);
     if (sub == 0) {
       q[o + A] = s;
@@ -742,13 +752,15 @@ static iga_status autotune(Batch &b) {
     const bool tiles = tiles_supported(b, g);
     if (tiles && (st = build_tiles(b, g))) return st;
     if (have_rg && g.b1 == 0 && !tiles) have_rg = false;
-    if (!have_rg) {
+    if (!have_rg && tiles) {
+      // the tiled kernel wherever it applies (several times faster than any pencil shape)
+      g.b1 = 0;
+    } else if (!have_rg) {
       float best = 1e30f;
       int bestb = 4;
-      for (int cand : {0, 1, 4, 8}) {
-        if (cand == 0 && !tiles) continue;
+      for (int cand : {1, 4, 8}) {
         g.b1 = cand;
-        if (cand > 0 && (st = build_pencils(b, g))) return st;
+        if ((st = build_pencils(b, g))) return st;
         launch_rg(b, g, cand, U, b.vals, IGA_FP64, b.bs);
         hipEventRecord(e0, b.bs);
         for (int r = 0; r < 3; ++r) launch_rg(b, g, cand, U, b.vals, IGA_FP64, b.bs);
