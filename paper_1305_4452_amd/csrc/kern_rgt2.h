@@ -11,9 +11,8 @@
 //   b. level 1 (axis 1): Sm[i1, o1][g0] = sum_{g1} m(g0, g1) N_i1(g1) N_j1(g1)   (one wave per i1,
 //      one lane per g0: the axis-1 basis values are wave-uniform);
 //   c. level 2 (axis 0): J[(i0, i1)][(j0, j1)] += sum_{g0} Sm[i1, o1][g0] N_i0(g0) N_j0(g0) plus the
-//      stiffness, one wave per row i0 and one lane per (i1, o1) pair; rows are staged in LDS in
-//      CSR order;
-//   d. the staged rows are written out, consecutive lanes on consecutive CSR slots.
+//      stiffness, one wave per row i0 and one lane per (i1, o1) pair; each lane stores its run of
+//      2p + 1 consecutive CSR values (the lanes of one i1 together cover the whole row).
 // Dirichlet rows become identity rows and Dirichlet columns zero, as in every assembly path.
 #pragma once
 
@@ -47,10 +46,8 @@ struct Lds2 {
   static constexpr int G0M = (T0 + p) * Q, G1M = (B1 + p) * Q;
   static constexpr int SP = G0M + 1;   // odd pitch of Sm rows (lanes = pairs read one column)
   static constexpr int NI0M = T0 + 2 * p, NI1M = B1 + 2 * p;
-  static constexpr size_t bytes_m = align16((size_t)G1M * G0M * sizeof(CT));
-  static constexpr size_t bytes_stage = align16((size_t)T0 * B1 * W * W * sizeof(OT));
-  // region A: m at the Gauss points, then (after level 1) the staged rows
-  static constexpr size_t bytes_a = bytes_m > bytes_stage ? bytes_m : bytes_stage;
+  // region A: m at the Gauss points
+  static constexpr size_t bytes_a = align16((size_t)G1M * G0M * sizeof(CT));
   static constexpr size_t bytes_s = align16((size_t)NPAIR * SP * sizeof(CT));
   static constexpr size_t bytes_uv = align16((size_t)(NI0M * NI1M + NI1M * G0M) * sizeof(double));
   // region B: coefficients and their axis-0 contraction (phase a), then Sm
@@ -77,7 +74,6 @@ __device__ inline void rgt2_body(const DevProblem &pb, const int tile, const dou
   const int NE0 = E0hi - E0lo + 1, NE1 = E1hi - E1lo + 1;
   const int G0 = NE0 * Q, G1 = NE1 * Q, NI0 = NE0 + p, NI1 = NE1 + p;
   CT *mQ = (CT *)lds;                                   // [G1M][G0M]
-  OT *stage = (OT *)lds;                                // [B1][T0][W * W], after level 1
   CT *Sm = (CT *)(lds + L::bytes_a);                    // [NPAIR][SP]
   double *sU = (double *)(lds + L::bytes_a);            // [NI1M][NI0M], phase a only
   double *V = sU + L::NI0M * L::NI1M;                   // [NI1M][G0M], phase a only
@@ -222,7 +218,8 @@ __device__ inline void rgt2_body(const DevProblem &pb, const int tile, const dou
       if (live) {
         const bool rowDir = is_dirichlet_idx(pb, i0, i1, 0);
         const int l0 = max(0, i0 - p), w0 = min(n0 - 1, i0 + p) - l0 + 1;
-        OT *srow = stage + ((size_t)i1l * T0 + i0l) * (W * W) + (size_t)(j1 - l1) * w0;
+        // CSR row (i0, i1): columns (j0, j1) with j1 - l1 major, j0 - l0 minor
+        OT *srow = vals + pb.row_ptr[i0 + (int64_t)n0 * i1] + (size_t)(j1 - l1) * w0;
 #pragma unroll
         for (int o = 0; o < W; ++o) {
           const int j0 = i0 + o - p;
@@ -235,17 +232,6 @@ __device__ inline void rgt2_body(const DevProblem &pb, const int tile, const dou
         }
       }
     }
-  }
-  __syncthreads();
-
-  // ---- d. staged rows to the CSR values (rows of one i1 are consecutive in CSR) ---------
-  for (int i = t; i < B1 * T0 * W * W; i += kThreads) {
-    const int k = i % (W * W), r = i / (W * W), i0l = r % T0, i1l = r / T0;
-    const int i0 = I0 + i0l, i1 = I1 + i1l;
-    if (i0 >= n0 || i1 >= n1) continue;
-    const int w0 = min(n0 - 1, i0 + p) - max(0, i0 - p) + 1, w1 = min(n1 - 1, i1 + p) - max(0, i1 - p) + 1;
-    if (k >= w0 * w1) continue;
-    vals[pb.row_ptr[i0 + (int64_t)n0 * i1] + k] = stage[(size_t)r * (W * W) + k];
   }
 }
 
