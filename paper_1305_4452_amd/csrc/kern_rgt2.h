@@ -95,25 +95,39 @@ __device__ inline void rgt2_body(const DevProblem &pb, const int tile, const dou
       kt[el0 * NE1 + el1] = pb.kel[(E0lo + el0) + (int64_t)ne0 * (E1lo + el1)];
     }
   __syncthreads();
-  for (int i = t; i < NI1 * G0; i += kThreads) {
-    const int g0 = i % G0, k1 = i / G0, el0 = g0 / Q, q0 = g0 % Q;
-    const double *Bq = B0 + ((size_t)(E0lo + el0) * Q + q0) * P;
-    double s = 0;
+  // one lane per axis-0 Gauss point (its basis values in registers), waves walk axis 1 (the
+  // axis-1 basis values and weights are wave-uniform)
+  for (int gb = 0; gb < G0; gb += 64) {
+    const int g0 = gb + lane;
+    const bool ok = g0 < G0;
+    const int el0 = ok ? g0 / Q : 0;
+    double b0[P];
+    const double *Bq0 = B0 + ((size_t)(E0lo + el0) * Q + (ok ? g0 % Q : 0)) * P;
 #pragma unroll
-    for (int a0 = 0; a0 < P; ++a0) s += Bq[a0] * sU[k1 * L::NI0M + el0 + a0];
-    V[k1 * L::G0M + g0] = s;
+    for (int a0 = 0; a0 < P; ++a0) b0[a0] = Bq0[a0];
+    for (int k1 = wave; k1 < NI1; k1 += NW) {
+      double s = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < P; ++a0) s += b0[a0] * sU[k1 * L::NI0M + el0 + a0];
+      if (ok) V[k1 * L::G0M + g0] = s;
+    }
   }
   __syncthreads();
   {
     const double lam = pb.lambda;
     const double *wq0 = pb.ax[0].wq + (size_t)E0lo * Q, *wq1 = pb.ax[1].wq + (size_t)E1lo * Q;
-    for (int i = t; i < G1 * G0; i += kThreads) {
-      const int g0 = i % G0, g1 = i / G0, el1 = g1 / Q, q1 = g1 % Q;
-      const double *Bq = B1t + ((size_t)(E1lo + el1) * Q + q1) * P;
-      double u = 0;
+    for (int gb = 0; gb < G0; gb += 64) {
+      const int g0 = gb + lane;
+      const bool ok = g0 < G0;
+      const double w0 = ok ? -lam * wq0[g0] : 0.0;
+      for (int g1 = wave; g1 < G1; g1 += NW) {
+        const int el1 = g1 / Q;
+        const double *Bq = B1t + ((size_t)E1lo * Q + g1) * P;
+        double u = 0;
 #pragma unroll
-      for (int a1 = 0; a1 < P; ++a1) u += Bq[a1] * V[(el1 + a1) * L::G0M + g0];
-      mQ[g1 * L::G0M + g0] = (CT)(-lam * wq0[g0] * wq1[g1] * exp(u));
+        for (int a1 = 0; a1 < P; ++a1) u += Bq[a1] * V[(el1 + a1) * L::G0M + (ok ? g0 : 0)];
+        if (ok) mQ[g1 * L::G0M + g0] = (CT)(w0 * wq1[g1] * exp(u));
+      }
     }
   }
   __syncthreads();
@@ -175,7 +189,13 @@ __device__ inline void rgt2_body(const DevProblem &pb, const int tile, const dou
         }
       }
     }
-    const int l1 = max(0, i1 - p);
+    const int l1 = max(0, i1 - p), w1 = min(n1 - 1, i1 + p) - l1 + 1;
+    // CSR rows (I0 .. I0 + T0 - 1, i1) are consecutive: row (i0, i1) starts w1 * (sum of the
+    // axis-0 widths of rows I0 .. i0 - 1) after row (I0, i1)
+    const int64_t rp0 = live ? pb.row_ptr[I0 + (int64_t)n0 * i1] : 0;
+    const unsigned dm = pb.dmask;
+    const bool dirI1 = (((dm >> 2) & 1u) && i1 == 0) || (((dm >> 3) & 1u) && i1 == n1 - 1);
+    const bool dirJ1 = (((dm >> 2) & 1u) && j1 == 0) || (((dm >> 3) & 1u) && j1 == n1 - 1);
     for (int i0l = wave; i0l < T0; i0l += NW) {
       const int i0 = I0 + i0l;
       if (i0 >= n0) break;
@@ -215,20 +235,23 @@ __device__ inline void rgt2_body(const DevProblem &pb, const int tile, const dou
           for (int b0 = 0; b0 <= p; ++b0) out[b0 - a0 + p] += xb * (CT)Bq[b0];
         }
       }
+      int pre = 0;   // wave-uniform
+      for (int i = I0; i < i0; ++i) pre += min(n0 - 1, i + p) - max(0, i - p) + 1;
       if (live) {
-        const bool rowDir = is_dirichlet_idx(pb, i0, i1, 0);
+        const bool dir0i = ((dm & 1u) && i0 == 0) || (((dm >> 1) & 1u) && i0 == n0 - 1);
+        const bool rowDir = dir0i || dirI1;
         const int l0 = max(0, i0 - p), w0 = min(n0 - 1, i0 + p) - l0 + 1;
         // CSR row (i0, i1): columns (j0, j1) with j1 - l1 major, j0 - l0 minor
-        OT *srow = vals + pb.row_ptr[i0 + (int64_t)n0 * i1] + (size_t)(j1 - l1) * w0;
+        OT *srow = vals + rp0 + (int64_t)w1 * pre + (j1 - l1) * w0 - l0;
 #pragma unroll
         for (int o = 0; o < W; ++o) {
           const int j0 = i0 + o - p;
           if (j0 < 0 || j0 >= n0) continue;
-          double v;
-          if (rowDir) v = (j0 == i0 && j1 == i1) ? 1.0 : 0.0;
-          else if (is_dirichlet_idx(pb, j0, j1, 0)) v = 0.0;
-          else v = (double)out[o];
-          srow[j0 - l0] = (OT)v;
+          const bool dir0j = ((dm & 1u) && j0 == 0) || (((dm >> 1) & 1u) && j0 == n0 - 1);
+          double v = (double)out[o];
+          if (rowDir) v = (o == p && o1 == 0) ? 1.0 : 0.0;
+          else if (dir0j || dirJ1) v = 0.0;
+          srow[j0] = (OT)v;
         }
       }
     }
