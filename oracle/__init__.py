@@ -63,6 +63,7 @@ def lib():
             "orc_csr_pattern": [P, _i64p, _i32p],
             "orc_residual": [P, _dp, _dp],
             "orc_jacobian": [P, _dp, _i64p, _i32p, _dp],
+            "orc_jacobian_nd": [P, _dp, _i64p, _i32p, C.c_double, _dp],
             "orc_residual_rows": [P, _dp, _i64p, C.c_int64, _dp],
             "orc_jacobian_rows": [P, _dp, _i64p, C.c_int64, _i64p, _i32p, _dp],
             "orc_element_matrix": [P, _dp, C.c_int64, _dp, _dp],
@@ -160,6 +161,16 @@ class Oracle:
         v = np.zeros(self.nnz)
         self._chk(lib().orc_jacobian(C.byref(self.pb), _ptr(U), _ptr(rp, _i64p), _ptr(ci, _i32p), _ptr(v)),
                   "jacobian")
+        return v
+
+    def jacobian_nd(self, U, eta=0.0):
+        """Local numerical-differentiation Jacobian (Sec. 2.8, eq:fdjac), CSR values; eta <= 0
+        selects the default step factor sqrt(machine epsilon)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        rp, ci = self.pattern()
+        v = np.zeros(self.nnz)
+        self._chk(lib().orc_jacobian_nd(C.byref(self.pb), _ptr(U), _ptr(rp, _i64p), _ptr(ci, _i32p), float(eta),
+                                        _ptr(v)), "jacobian_nd")
         return v
 
     def jacobian_csr(self, U):

@@ -458,6 +458,81 @@ int orc_jacobian(const orc_problem *pb, const double *U, const int64_t *row_ptr,
   return rc;
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Local numerical differentiation (Sec. 2.8, eq:fdjac): at each quadrature point q of     */
+/* element e, column k of dF_q/dU_e is (F_q(U_e + delta e_k) - F_q(U_e)) / delta, where     */
+/* F_q[a] is the point's contribution to the element residual and                           */
+/* delta = eta sqrt(1 + ||U_e||_2); eta <= 0 selects the default sqrt(machine epsilon).     */
+/* The element matrices are summed into the CSR values, then the Dirichlet rows and columns  */
+/* are treated as for the explicit Jacobian.                                                */
+/* ------------------------------------------------------------------------------------ */
+static void state_at(const qpoint *q, const double *Ue, qpoint *out) {
+  *out = *q;
+  out->u = 0.0;
+  out->gu[0] = out->gu[1] = out->gu[2] = 0.0;
+  for (int a = 0; a < q->nloc; ++a) {
+    out->u += Ue[a] * q->N[a];
+    for (int i = 0; i < 3; ++i) out->gu[i] += Ue[a] * q->dN[a][i];
+  }
+}
+
+int orc_jacobian_nd(const orc_problem *pb, const double *U, const int64_t *row_ptr,
+                    const int32_t *col_idx, double eta, double *vals) {
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  if (!(eta > 0.0)) eta = sqrt(2.220446049250313e-16);
+  memset(vals, 0, sizeof(double) * row_ptr[L.N]);
+  qpoint *q = (qpoint *)malloc(3 * sizeof(qpoint));
+  qpoint *qb = q + 1, *qk = q + 2;
+  double *Ue = (double *)malloc(sizeof(double) * ORC_MAXLOC);
+  double *F0 = (double *)malloc(sizeof(double) * ORC_MAXLOC);
+  double *Ke = (double *)malloc(sizeof(double) * ORC_MAXLOC * ORC_MAXLOC);
+  int nqe = L.nq[0] * L.nq[1] * L.nq[2], rc = 0;
+  for (int64_t e = 0; e < L.E && !rc; ++e) {
+    int em[3], gm[3];
+    elem_multi(&L, e, em);
+    int nloc = 0;
+    memset(Ke, 0, sizeof(double) * ORC_MAXLOC * ORC_MAXLOC);
+    double delta = 0.0;
+    for (int g = 0; g < nqe && !rc; ++g) {
+      qp_multi(&L, g, gm);
+      if ((rc = eval_qp(pb, &L, em, gm, U, q))) break;
+      nloc = q->nloc;
+      if (g == 0) {
+        double nrm = 0.0;
+        for (int a = 0; a < nloc; ++a) {
+          Ue[a] = U[q->A[a]];
+          nrm += Ue[a] * Ue[a];
+        }
+        delta = eta * sqrt(1.0 + sqrt(nrm));
+      }
+      state_at(q, Ue, qb);
+      for (int a = 0; a < nloc; ++a) F0[a] = res_term(pb, qb, a);
+      for (int k = 0; k < nloc; ++k) {
+        double keep = Ue[k];
+        Ue[k] = keep + delta;
+        state_at(q, Ue, qk);
+        Ue[k] = keep;
+        for (int a = 0; a < nloc; ++a) Ke[a * nloc + k] += (res_term(pb, qk, a) - F0[a]) / delta;
+      }
+    }
+    for (int a = 0; a < nloc && !rc; ++a)
+      for (int k = 0; k < nloc; ++k) {
+        int64_t s = csr_find(row_ptr, col_idx, q->A[a], q->A[k]);
+        if (s < 0) { rc = 3; break; }
+        vals[s] += Ke[a * nloc + k];
+      }
+  }
+  if (!rc)
+    for (int64_t A = 0; A < L.N; ++A) jac_bc_rows(pb, &L, row_ptr, col_idx, vals, A, NULL);
+  free(Ke);
+  free(F0);
+  free(Ue);
+  free(q);
+  lay_free(&L);
+  return rc;
+}
+
 /* elements of one axis whose span contains function i */
 static int elems_of_fn(const layout *L, int d, int i, int *out) {
   int c = 0;

@@ -12,6 +12,7 @@
  *   - the adjacency stencil of Algorithm 2 (Sec. 2.5),
  *   - naive per-quadrature-point residual/Jacobian assembly as in Algorithm 3 (Sec. 2.7)
  *     with the Bratu integrands eq:residual and eq:jacobian (Sec. 3.1),
+ *   - the local numerical-differentiation Jacobian of Sec. 2.8 (eq:fdjac),
  *   - Newton's method with exact (direct banded or tight CG) linear solves.
  * Every function returns 0 on success and a nonzero code on bad input.
  */
@@ -46,6 +47,9 @@ int orc_csr_pattern(const orc_problem *pb, int64_t *row_ptr, int32_t *col_idx);
 int orc_residual(const orc_problem *pb, const double *U, double *R);
 int orc_jacobian(const orc_problem *pb, const double *U, const int64_t *row_ptr,
                  const int32_t *col_idx, double *vals);
+/* Local numerical-differentiation Jacobian (Sec. 2.8, eq:fdjac); eta <= 0: sqrt(epsilon). */
+int orc_jacobian_nd(const orc_problem *pb, const double *U, const int64_t *row_ptr,
+                    const int32_t *col_idx, double eta, double *vals);
 int orc_residual_rows(const orc_problem *pb, const double *U, const int64_t *rows, int64_t nrows,
                       double *out);
 int orc_jacobian_rows(const orc_problem *pb, const double *U, const int64_t *rows, int64_t nrows,
