@@ -54,9 +54,14 @@ typedef enum { IGA_KAPPA_ONE = 0, IGA_KAPPA_NODAL = 1, IGA_KAPPA_ELEMENT = 2 } i
  *   ATOMIC:    element matrices by sum factorisation, scattered with FP64 atomic adds;
  *   COLOR:     element matrices scattered colour by colour ((p+1)^d colours, no atomics);
  *   ROWGATHER_GENERAL: the row-gather kernel with every term contracted (never the
- *              Kronecker-sum shortcut), for comparison. */
+ *              Kronecker-sum shortcut), for comparison;
+ *   LOCAL_ND:  local numerical differentiation (Sec. 2.8, eq:fdjac): column k of each element
+ *              matrix is sum_q (F_q(U_e + delta e_k) - F_q(U_e)) / delta with
+ *              delta = eta sqrt(1 + ||U_e||_2), eta = sqrt(DBL_EPSILON); an approximation of the
+ *              same matrix (relative error ~1e-8), added with FP64 atomics (p <= 4 in 3D). */
 typedef enum {
-  IGA_JAC_AUTO = 0, IGA_JAC_ROWGATHER = 1, IGA_JAC_ATOMIC = 2, IGA_JAC_COLOR = 3, IGA_JAC_ROWGATHER_GENERAL = 4
+  IGA_JAC_AUTO = 0, IGA_JAC_ROWGATHER = 1, IGA_JAC_ATOMIC = 2, IGA_JAC_COLOR = 3, IGA_JAC_ROWGATHER_GENERAL = 4,
+  IGA_JAC_LOCAL_ND = 5
 } iga_jac_algo;
 
 typedef enum {

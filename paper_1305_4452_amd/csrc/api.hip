@@ -66,6 +66,9 @@ static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int 
   if (algo == IGA_JAC_ROWGATHER || algo == IGA_JAC_ROWGATHER_GENERAL) {
     kt_begin(h, "k_rowgather (general)");
     st = launch_jac_rowgather(h, U, vals, prec, b1, b2);
+  } else if (algo == IGA_JAC_LOCAL_ND) {
+    kt_begin(h, "k_elem_nd (local numerical differentiation)");
+    st = launch_jac_nd(h, U, vals, prec);
   } else if (algo == IGA_JAC_ATOMIC || algo == IGA_JAC_COLOR) {
     kt_begin(h, algo == IGA_JAC_ATOMIC ? "k_elem_mat (atomic scatter)" : "k_elem_mat (colour scatter)");
     st = launch_jac_scatter(h, U, vals, prec, algo == IGA_JAC_COLOR ? 1 : 0);
@@ -245,7 +248,7 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
   Handle *h = (Handle *)hh;
   switch (key) {
     case IGA_OPT_JAC_ALGO:
-      if (value < IGA_JAC_AUTO || value > IGA_JAC_ROWGATHER_GENERAL) return fail(IGA_EINVAL, "bad Jacobian algorithm");
+      if (value < IGA_JAC_AUTO || value > IGA_JAC_LOCAL_ND) return fail(IGA_EINVAL, "bad Jacobian algorithm");
       h->jac_algo = (int)value;
       return IGA_OK;
     case IGA_OPT_ROW_BLOCK:

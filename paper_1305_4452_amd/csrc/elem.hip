@@ -269,6 +269,215 @@ __global__ void __launch_bounds__(256) k_elem_mat(DevProblem pb, const double *_
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Local numerical differentiation (Sec. 2.8, eq:fdjac).  Column k of element e's matrix is
+// sum_q (F_q(U_e + delta e_k) - F_q(U_e)) / delta with delta = eta sqrt(1 + ||U_e||_2), where
+// F_q is the point's contribution to the element residual (the integrand of eq:residual tested
+// with every local function).  The difference is taken on the point flux and source before the
+// test functions are applied (the same sum in exact arithmetic); the perturbed state is
+// u + delta N_k (its exponential from the base point's, exp_near), and the column is contracted
+// by the transposed sum factorisation of the residual
+// kernel.  One workgroup per element, four columns in flight (one wave each); the columns are
+// added into the CSR values with FP64 atomics (FP32 values: FP32 atomics of the FP64 result).
+// ------------------------------------------------------------------------------------------
+// exp(arg) from exp(arg0): the perturbed exponent differs by x = arg - arg0, exactly
+// representable, |x| <~ 1e-7 here, so e^x = 1 + x + x^2/2 + x^3/6 to within x^4/24; a larger x
+// (huge ||U_e||) takes the library exp
+__device__ inline double exp_near(double arg, double arg0, double e0) {
+  const double x = arg - arg0;
+  if (fabs(x) > 1e-3) return exp(arg);
+  return e0 + e0 * (x * (1.0 + x * (0.5 + x * (1.0 / 6.0))));
+}
+
+// point flux F and source term S of eq:residual at state (val, gu); with arg0 / e0 given, the
+// exponential is formed from the base point's (exp_near)
+template <int DIM, bool TABLE>
+__device__ inline void nd_point(const DevProblem &pb, int64_t e, int q, int L, const double *sW0, const double *sW1,
+                                const double *sW2, double kap_e, double val, const double gu[3], double f,
+                                double Fv[3], double &Sv, bool near = false, double arg0 = 0.0, double e0 = 0.0,
+                                double *arg_out = nullptr) {
+  const double lam = pb.lambda;
+  const bool src = pb.src != nullptr;
+  if constexpr (!TABLE) {
+    const int Q = pb.Q;
+    const int q0 = q % Q, q1 = (q / Q) % Q, q2 = DIM == 3 ? q / (Q * Q) : 0;
+    const double W = sW0[q0] * sW1[q1] * (DIM == 3 ? sW2[q2] : 1.0);
+    const double kw = kap_e * W;
+    for (int k = 0; k < DIM; ++k) Fv[k] = kw * gu[k];
+    if (arg_out) *arg_out = val;
+    Sv = -W * (lam * (near ? exp_near(val, arg0, e0) : exp(val)) + (src ? f : 0.0));
+  } else {
+    constexpr int NG = geo_streams(DIM);
+    const double *G = pb.geo + (size_t)e * NG * L + q;
+    double Dm[3][3], g[3] = {0, 0, 0}, Wow, iw;
+    if (DIM == 3) {
+      Dm[0][0] = G[0]; Dm[1][1] = G[L]; Dm[2][2] = G[2 * L];
+      Dm[0][1] = Dm[1][0] = G[3 * L]; Dm[0][2] = Dm[2][0] = G[4 * L]; Dm[1][2] = Dm[2][1] = G[5 * L];
+      g[0] = G[6 * L]; g[1] = G[7 * L]; g[2] = G[8 * L];
+      Wow = G[9 * L]; iw = G[10 * L];
+    } else {
+      Dm[0][0] = G[0]; Dm[1][1] = G[L]; Dm[0][1] = Dm[1][0] = G[2 * L];
+      g[0] = G[3 * L]; g[1] = G[4 * L];
+      Wow = G[5 * L]; iw = G[6 * L];
+    }
+    double gv[3];
+    for (int k = 0; k < DIM; ++k) gv[k] = gu[k] - val * g[k];
+    double gF = 0;
+    for (int k = 0; k < DIM; ++k) {
+      double s = 0;
+      for (int m = 0; m < DIM; ++m) s += Dm[k][m] * gv[m];
+      Fv[k] = s;
+      gF += g[k] * s;
+    }
+    const double arg = val * iw;
+    if (arg_out) *arg_out = arg;
+    Sv = -Wow * (lam * (near ? exp_near(arg, arg0, e0) : exp(arg)) + (src ? f * iw : 0.0)) - gF;
+  }
+}
+
+template <int DIM, int P, bool TABLE>
+__global__ void __launch_bounds__(256) k_elem_nd(DevProblem pb, const double *__restrict__ U, double eta,
+                                                 void *__restrict__ vals, int f32) {
+  constexpr int L = Shp<DIM, P>::L, PP = P * P;
+  constexpr int NGRP = 4;   // columns in flight, one wave each
+  __shared__ double sB[3][PP], sD[3][PP], sW[3][P];
+  __shared__ double c[L], cf[L], su[L], sg[3][L], sfq[L], Fb[3][L], Sb[L], sA[L], sE[L];
+  __shared__ double buf[NGRP][7][L];
+  __shared__ double sh[4];
+  const int t = threadIdx.x, grp = t >> 6, lane = t & 63;
+  const int64_t e = blockIdx.x;
+  int em[3], f[3];
+  elem_coords(pb, e, em);
+  for (int d = 0; d < DIM; ++d) {
+    const double *B = pb.ax[d].B + (size_t)em[d] * PP, *D = pb.ax[d].dB + (size_t)em[d] * PP;
+    for (int i = t; i < PP; i += 256) { sB[d][i] = B[i]; sD[d][i] = D[i]; }
+    if (t < P) sW[d][t] = pb.ax[d].wq[(size_t)em[d] * P + t];
+    f[d] = pb.ax[d].efirst[em[d]];
+  }
+  if (DIM == 2) f[2] = 0;
+  const bool src = pb.src != nullptr;
+  double nrm = 0;
+  for (int a = t; a < L; a += 256) {
+    const int64_t A = local_to_global<DIM, P>(pb, f, a);
+    const double wa = (TABLE && pb.rational) ? pb.wts[A] : 1.0;
+    const double x = U[A];
+    nrm += x * x;
+    c[a] = x * wa;
+    cf[a] = src ? pb.src[A] * wa : 0.0;
+  }
+  for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o, 64);
+  if (lane == 0) sh[grp] = nrm;
+  __syncthreads();
+  const double delta = eta * sqrt(1.0 + sqrt(sh[0] + sh[1] + sh[2] + sh[3]));
+  // state at the points: value and parametric gradient of the (homogeneous) field, source
+  double *y0 = buf[0][0], *y1 = buf[0][1], *y2 = buf[0][2], *y3 = buf[0][3], *y4 = buf[0][4], *y5 = buf[0][5];
+  if constexpr (DIM == 3) {
+    fwd<PP, 1, P>(c, y0, sB[0], t, 256);
+    fwd<PP, 1, P>(c, y1, sD[0], t, 256);
+    fwd<PP, 1, P>(cf, y5, sB[0], t, 256);
+    __syncthreads();
+    fwd<P, P, P>(y0, y2, sB[1], t, 256);
+    fwd<P, P, P>(y1, y3, sB[1], t, 256);
+    fwd<P, P, P>(y0, y4, sD[1], t, 256);
+    fwd<P, P, P>(y5, buf[1][0], sB[1], t, 256);
+    __syncthreads();
+    fwd<1, PP, P>(y2, su, sB[2], t, 256);
+    fwd<1, PP, P>(y3, sg[0], sB[2], t, 256);
+    fwd<1, PP, P>(y4, sg[1], sB[2], t, 256);
+    fwd<1, PP, P>(y2, sg[2], sD[2], t, 256);
+    fwd<1, PP, P>(buf[1][0], sfq, sB[2], t, 256);
+  } else {
+    fwd<P, 1, P>(c, y0, sB[0], t, 256);
+    fwd<P, 1, P>(c, y1, sD[0], t, 256);
+    fwd<P, 1, P>(cf, y5, sB[0], t, 256);
+    __syncthreads();
+    fwd<1, P, P>(y0, su, sB[1], t, 256);
+    fwd<1, P, P>(y1, sg[0], sB[1], t, 256);
+    fwd<1, P, P>(y0, sg[1], sD[1], t, 256);
+    fwd<1, P, P>(y5, sfq, sB[1], t, 256);
+  }
+  __syncthreads();
+  const double kap_e = (!TABLE && pb.kappa_mode == IGA_KAPPA_ELEMENT) ? pb.kel[e] : 1.0;
+  for (int q = t; q < L; q += 256) {
+    double gq[3] = {sg[0][q], sg[1][q], DIM == 3 ? sg[2][q] : 0.0}, Fv[3] = {0, 0, 0}, Sv = 0, arg = 0;
+    nd_point<DIM, TABLE>(pb, e, q, L, sW[0], sW[1], sW[2], kap_e, su[q], gq, sfq[q], Fv, Sv, false, 0.0, 0.0, &arg);
+    for (int k = 0; k < DIM; ++k) Fb[k][q] = Fv[k];
+    Sb[q] = Sv;
+    sA[q] = arg;
+    sE[q] = exp(arg);
+  }
+  __syncthreads();
+  for (int kb = 0; kb < L; kb += NGRP) {
+    const int k = kb + grp;
+    const bool ok = k < L;
+    double *dF0 = buf[grp][0], *dF1 = buf[grp][1], *dF2 = buf[grp][2], *dS = buf[grp][3];
+    if (ok) {
+      const int k0 = k % P, k1 = (k / P) % P, k2 = DIM == 3 ? k / PP : 0;
+      const int64_t Ak = local_to_global<DIM, P>(pb, f, k);
+      const double dc = delta * ((TABLE && pb.rational) ? pb.wts[Ak] : 1.0);
+      for (int q = lane; q < L; q += 64) {
+        const int q0 = q % P, q1 = (q / P) % P, q2 = DIM == 3 ? q / PP : 0;
+        const double b0 = sB[0][q0 * P + k0], b1 = sB[1][q1 * P + k1], b2 = DIM == 3 ? sB[2][q2 * P + k2] : 1.0;
+        const double d0 = sD[0][q0 * P + k0], d1 = sD[1][q1 * P + k1], d2 = DIM == 3 ? sD[2][q2 * P + k2] : 0.0;
+        double gq[3] = {sg[0][q] + dc * d0 * b1 * b2, sg[1][q] + dc * b0 * d1 * b2,
+                        DIM == 3 ? sg[2][q] + dc * b0 * b1 * d2 : 0.0};
+        double Fv[3] = {0, 0, 0}, Sv = 0;
+        nd_point<DIM, TABLE>(pb, e, q, L, sW[0], sW[1], sW[2], kap_e, su[q] + dc * b0 * b1 * b2, gq, sfq[q], Fv,
+                             Sv, true, sA[q], sE[q]);
+        dF0[q] = (Fv[0] - Fb[0][q]) / delta;
+        dF1[q] = (Fv[1] - Fb[1][q]) / delta;
+        if (DIM == 3) dF2[q] = (Fv[2] - Fb[2][q]) / delta;
+        dS[q] = (Sv - Sb[q]) / delta;
+      }
+    }
+    __syncthreads();
+    double *Re;
+    if constexpr (DIM == 3) {
+      double *Sa = buf[grp][4], *S0 = buf[grp][5], *S1 = buf[grp][6];
+      if (ok) {
+        bwd2<1, PP, P>(dF2, sD[2], dS, sB[2], Sa, lane, 64);
+        bwd2<1, PP, P>(dF0, sB[2], (const double *)nullptr, sB[2], S0, lane, 64);
+        bwd2<1, PP, P>(dF1, sB[2], (const double *)nullptr, sB[2], S1, lane, 64);
+      }
+      __syncthreads();
+      double *VB = buf[grp][0], *V0 = buf[grp][1];
+      if (ok) {
+        bwd2<P, P, P>(S1, sD[1], Sa, sB[1], VB, lane, 64);
+        bwd2<P, P, P>(S0, sB[1], (const double *)nullptr, sB[1], V0, lane, 64);
+      }
+      __syncthreads();
+      Re = buf[grp][2];
+      if (ok) bwd2<PP, 1, P>(V0, sD[0], VB, sB[0], Re, lane, 64);
+    } else {
+      double *Sa = buf[grp][4], *S0 = buf[grp][5];
+      if (ok) {
+        bwd2<1, P, P>(dF1, sD[1], dS, sB[1], Sa, lane, 64);
+        bwd2<1, P, P>(dF0, sB[1], (const double *)nullptr, sB[1], S0, lane, 64);
+      }
+      __syncthreads();
+      Re = buf[grp][2];
+      if (ok) bwd2<P, 1, P>(S0, sD[0], Sa, sB[0], Re, lane, 64);
+    }
+    __syncthreads();
+    if (ok) {
+      const int k0 = k % P, k1 = (k / P) % P, k2 = DIM == 3 ? k / PP : 0;
+      const int j0 = f[0] + k0, j1 = f[1] + k1, j2 = f[2] + k2;
+      const bool colDir = is_dirichlet_idx(pb, j0, j1, j2);
+      for (int a = lane; a < L; a += 64) {
+        const int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / PP : 0;
+        const int i0 = f[0] + a0, i1 = f[1] + a1, i2 = f[2] + a2;
+        if (colDir || is_dirichlet_idx(pb, i0, i1, i2)) continue;
+        double v = Re[a];
+        if (TABLE && pb.rational) v *= pb.wts[local_to_global<DIM, P>(pb, f, a)];
+        const int64_t slot = csr_slot(pb, i0, i1, i2, j0, j1, j2);
+        if (f32) atomicAdd(&((float *)vals)[slot], (float)v);
+        else atomicAdd(&((double *)vals)[slot], v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Dirichlet rows of an assembled Jacobian become identity rows (entries were never written).
 template <typename VT>
 __global__ void k_bc_diag(DevProblem pb, VT *vals) {
@@ -446,6 +655,18 @@ struct RunElemMat {
   }
 };
 
+template <int D, int P, bool T>
+struct RunElemND {
+  static void run(const Handle &h, const double *U, double eta, void *vals, int f32) {
+    if constexpr (D == 3 && P > 5) {
+      return;
+    } else {
+      hipLaunchKernelGGL((k_elem_nd<D, P, T>), dim3((unsigned)h.pb.E), dim3(256), 0, h.stream, h.pb, U, eta, vals,
+                         f32);
+    }
+  }
+};
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -528,6 +749,28 @@ iga_status launch_jac_scatter(Handle &h, const double *U, void *vals, int prec, 
     }
   }
   if (prec == IGA_FP32)
+    hipLaunchKernelGGL(k_bc_diag<float>, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb, (float *)vals);
+  else
+    hipLaunchKernelGGL(k_bc_diag<double>, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb,
+                       (double *)vals);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+// Jacobian by local numerical differentiation: zero the values, add every element's difference
+// columns, then the identity Dirichlet rows.
+iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec) {
+  if (h.pb.dim == 3 && h.pb.P > 5) return fail(IGA_EUNSUPPORTED, "local numerical differentiation needs p <= 4 in 3D");
+  const int64_t nnz = h.pb.nnz;
+  const int f32 = prec == IGA_FP32 ? 1 : 0;
+  if (f32)
+    hipLaunchKernelGGL(k_fill_f, dim3(blocks_for(nnz, 256)), dim3(256), 0, h.stream, (float *)vals, nnz, 0.0f);
+  else
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(nnz, 256)), dim3(256), 0, h.stream, (double *)vals, nnz, 0.0);
+  // eta = sqrt(machine epsilon), the default of Sec. 2.8
+  iga_status st = dispatch_dpt<RunElemND>(h, U, 1.4901161193847656e-08, vals, f32);
+  if (st) return st;
+  if (f32)
     hipLaunchKernelGGL(k_bc_diag<float>, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb, (float *)vals);
   else
     hipLaunchKernelGGL(k_bc_diag<double>, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb,

@@ -212,6 +212,7 @@ iga_status launch_jac_scatter(Handle &h, const double *U, void *vals, int prec, 
 iga_status launch_jac_rowgather(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
 bool rowgather_supported(const Handle &h, int prec, int b1, int b2);
 iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
+iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec);
 bool rgt2_supported(const DevProblem &pb);
 bool res2_supported(const DevProblem &pb);
 iga_status launch_res2(Handle &h, const double *U, double *R);
