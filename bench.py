@@ -322,16 +322,36 @@ def main():
     g.set_option(iga.IGA_OPT_KERNEL_TIMING, 0)
     print(f"[bench] jacobian {jac_ms:.3f} ms/launch, wall {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # the general row-gather kernel (every term contracted) on the same workload, for comparison
-    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER_GENERAL)
-    g.assemble_jacobian(U, vals)
-    q0e, q1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    q0e.record()
-    for _ in range(3):
+    # other Jacobian algorithms on the same workload, for comparison: the general row-gather
+    # (every term contracted), element matrices with atomic scatter, and the local
+    # numerical-differentiation Jacobian of Sec. 2.8 (element columns by differences, atomic scatter)
+    def time_algo(algo, reps=3):
+        g.set_option(iga.IGA_OPT_JAC_ALGO, algo)
         g.assemble_jacobian(U, vals)
-    q1e.record()
-    torch.cuda.synchronize()
-    jac_general_ms = q0e.elapsed_time(q1e) / 3
+        q0e, q1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        q0e.record()
+        for _ in range(reps):
+            g.assemble_jacobian(U, vals)
+        q1e.record()
+        torch.cuda.synchronize()
+        return q0e.elapsed_time(q1e) / reps
+
+    jac_general_ms = time_algo(iga.IGA_JAC_ROWGATHER_GENERAL)
+    jac_atomic_ms = time_algo(iga.IGA_JAC_ATOMIC)
+    exact_vals = vals.clone()
+    jac_nd_ms = time_algo(iga.IGA_JAC_LOCAL_ND)
+    nd_rel = float((vals - exact_vals).norm() / exact_vals.norm())
+    del exact_vals
+    local_nd = {
+        "ms": jac_nd_ms,
+        "vs_explicit_rowgather": jac_nd_ms / jac_ms,
+        "vs_explicit_element_atomic": jac_nd_ms / jac_atomic_ms,
+        "rel_diff_vs_explicit": nd_rel,
+        "paper_ratio_local_nd_vs_explicit_64cube_p3": 64.93 / 15.41,
+    }
+    print(f"[bench] local ND jacobian {jac_nd_ms:.2f} ms ({local_nd['vs_explicit_rowgather']:.1f}x row-gather, "
+          f"{local_nd['vs_explicit_element_atomic']:.2f}x element+atomic), rel diff {nd_rel:.1e}",
+          file=sys.stderr, flush=True)
     g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_AUTO)
     g.assemble_jacobian(U, vals)
 
@@ -444,6 +464,8 @@ def main():
         "elements_per_s": E / (ms_step * 1e-3),
         "jacobian_fp32_ms": jac32_ms,
         "jacobian_general_rowgather_ms": jac_general_ms,
+        "jacobian_element_atomic_ms": jac_atomic_ms,
+        "jacobian_local_nd": local_nd,
         "residual_ms": res_ms,
         "spmv": {"ms": spmv_ms, "GBs": spmv_bytes / (spmv_ms * 1e-3) / 1e9,
                  "frac": spmv_bytes / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

@@ -58,7 +58,8 @@ typedef enum { IGA_KAPPA_ONE = 0, IGA_KAPPA_NODAL = 1, IGA_KAPPA_ELEMENT = 2 } i
  *   LOCAL_ND:  local numerical differentiation (Sec. 2.8, eq:fdjac): column k of each element
  *              matrix is sum_q (F_q(U_e + delta e_k) - F_q(U_e)) / delta with
  *              delta = eta sqrt(1 + ||U_e||_2), eta = sqrt(DBL_EPSILON); an approximation of the
- *              same matrix (relative error ~1e-8), added with FP64 atomics (p <= 4 in 3D). */
+ *              same matrix (relative error ~1e-8), added colour by colour or with FP64 atomics
+ *              (IGA_OPT_ND_SCATTER; p <= 4 in 3D). */
 typedef enum {
   IGA_JAC_AUTO = 0, IGA_JAC_ROWGATHER = 1, IGA_JAC_ATOMIC = 2, IGA_JAC_COLOR = 3, IGA_JAC_ROWGATHER_GENERAL = 4,
   IGA_JAC_LOCAL_ND = 5
@@ -72,7 +73,10 @@ typedef enum {
                                 axis 0 (each a workgroup; 0 = planned from the occupancy), 0..64 */
   IGA_OPT_KERNEL_TIMING = 5, /* 1: record a HIP event pair around each kernel of iga_assemble_jacobian
                                 (read back with iga_kernel_times); 0: off (default) */
-  IGA_OPT_PRECOND = 6        /* CG preconditioner of iga_newton_solve: iga_precond */
+  IGA_OPT_PRECOND = 6,       /* CG preconditioner of iga_newton_solve: iga_precond */
+  IGA_OPT_ND_SCATTER = 7     /* IGA_JAC_LOCAL_ND: 0 FP64 atomics in one launch (default), 1 colour
+                                by colour with plain adds ((p+1)^d launches, no two workgroups of a
+                                launch share a value) */
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):

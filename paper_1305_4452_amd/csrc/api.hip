@@ -68,7 +68,7 @@ static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int 
     st = launch_jac_rowgather(h, U, vals, prec, b1, b2);
   } else if (algo == IGA_JAC_LOCAL_ND) {
     kt_begin(h, "k_elem_nd (local numerical differentiation)");
-    st = launch_jac_nd(h, U, vals, prec);
+    st = launch_jac_nd(h, U, vals, prec, h.nd_color);
   } else if (algo == IGA_JAC_ATOMIC || algo == IGA_JAC_COLOR) {
     kt_begin(h, algo == IGA_JAC_ATOMIC ? "k_elem_mat (atomic scatter)" : "k_elem_mat (colour scatter)");
     st = launch_jac_scatter(h, U, vals, prec, algo == IGA_JAC_COLOR ? 1 : 0);
@@ -264,6 +264,10 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
       h->ktiming = (int)value;
       h->kt_calls = 0;   // (re)starts the averaging window
       h->kt_n = 0;
+      return IGA_OK;
+    case IGA_OPT_ND_SCATTER:
+      if (value != 0 && value != 1) return fail(IGA_EINVAL, "IGA_OPT_ND_SCATTER is 0 or 1");
+      h->nd_color = (int)value;
       return IGA_OK;
     case IGA_OPT_PRECOND:
       if (value < IGA_PRECOND_AUTO || value > IGA_PRECOND_FDM) return fail(IGA_EINVAL, "bad preconditioner");

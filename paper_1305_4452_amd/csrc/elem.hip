@@ -277,8 +277,10 @@ __global__ void __launch_bounds__(256) k_elem_mat(DevProblem pb, const double *_
 // test functions are applied (the same sum in exact arithmetic); the perturbed state is
 // u + delta N_k (its exponential from the base point's, exp_near), and the column is contracted
 // by the transposed sum factorisation of the residual
-// kernel.  One workgroup per element, four columns in flight (one wave each); the columns are
-// added into the CSR values with FP64 atomics (FP32 values: FP32 atomics of the FP64 result).
+// kernel.  One workgroup per element, four columns in flight (one wave each).  Columns are kept
+// in LDS in chunks of KC and each chunk is added into the CSR values with FP64 atomics (FP32
+// values: FP32 atomics of the FP64 result) in one pass, so the workgroup barriers inside the
+// column loop never wait for outstanding atomics.
 // ------------------------------------------------------------------------------------------
 // exp(arg) from exp(arg0): the perturbed exponent differs by x = arg - arg0, exactly
 // representable, |x| <~ 1e-7 here, so e^x = 1 + x + x^2/2 + x^3/6 to within x^4/24; a larger x
@@ -337,15 +339,29 @@ __device__ inline void nd_point(const DevProblem &pb, int64_t e, int q, int L, c
 
 template <int DIM, int P, bool TABLE>
 __global__ void __launch_bounds__(256) k_elem_nd(DevProblem pb, const double *__restrict__ U, double eta,
-                                                 void *__restrict__ vals, int f32) {
+                                                 void *__restrict__ vals, int f32, int color) {
   constexpr int L = Shp<DIM, P>::L, PP = P * P;
   constexpr int NGRP = 4;   // columns in flight, one wave each
+  constexpr int L4 = (L + 3) / 4 * 4, KCM = (4096 / L) / 4 * 4;
+  constexpr int KC = L4 < KCM ? L4 : KCM;   // columns per LDS chunk (multiple of 4)
+  __shared__ double Ke[L * KC];
   __shared__ double sB[3][PP], sD[3][PP], sW[3][P];
   __shared__ double c[L], cf[L], su[L], sg[3][L], sfq[L], Fb[3][L], Sb[L], sA[L], sE[L];
   __shared__ double buf[NGRP][7][L];
   __shared__ double sh[4];
   const int t = threadIdx.x, grp = t >> 6, lane = t & 63;
-  const int64_t e = blockIdx.x;
+  int64_t e = blockIdx.x;
+  if (color >= 0) {
+    // colour (c0, c1, c2), c_d < P: elements (c0 + P k0, c1 + P k1, c2 + P k2) share no function
+    const int c0 = color % P, c1 = (color / P) % P, c2 = color / PP;
+    const int k0n = (pb.ne[0] - c0 + P - 1) / P, k1n = (pb.ne[1] - c1 + P - 1) / P;
+    const int64_t kk = blockIdx.x;
+    const int k0 = (int)(kk % k0n);
+    const int64_t r = kk / k0n;
+    const int e0 = c0 + P * k0, e1 = c1 + P * (int)(r % k1n), e2 = DIM == 3 ? c2 + P * (int)(r / k1n) : 0;
+    if (e0 >= pb.ne[0] || e1 >= pb.ne[1] || (DIM == 3 && e2 >= pb.ne[2])) return;
+    e = e0 + (int64_t)pb.ne[0] * (e1 + (int64_t)pb.ne[1] * e2);
+  }
   int em[3], f[3];
   elem_coords(pb, e, em);
   for (int d = 0; d < DIM; ++d) {
@@ -407,9 +423,11 @@ __global__ void __launch_bounds__(256) k_elem_nd(DevProblem pb, const double *__
     sE[q] = exp(arg);
   }
   __syncthreads();
-  for (int kb = 0; kb < L; kb += NGRP) {
+  for (int cs = 0; cs < L; cs += KC) {
+  const int ce = min(L, cs + KC);
+  for (int kb = cs; kb < ce; kb += NGRP) {
     const int k = kb + grp;
-    const bool ok = k < L;
+    const bool ok = k < ce;
     double *dF0 = buf[grp][0], *dF1 = buf[grp][1], *dF2 = buf[grp][2], *dS = buf[grp][3];
     if (ok) {
       const int k0 = k % P, k1 = (k / P) % P, k2 = DIM == 3 ? k / PP : 0;
@@ -459,22 +477,32 @@ __global__ void __launch_bounds__(256) k_elem_nd(DevProblem pb, const double *__
       if (ok) bwd2<P, 1, P>(S0, sD[0], Sa, sB[0], Re, lane, 64);
     }
     __syncthreads();
-    if (ok) {
-      const int k0 = k % P, k1 = (k / P) % P, k2 = DIM == 3 ? k / PP : 0;
-      const int j0 = f[0] + k0, j1 = f[1] + k1, j2 = f[2] + k2;
-      const bool colDir = is_dirichlet_idx(pb, j0, j1, j2);
-      for (int a = lane; a < L; a += 64) {
-        const int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / PP : 0;
-        const int i0 = f[0] + a0, i1 = f[1] + a1, i2 = f[2] + a2;
-        if (colDir || is_dirichlet_idx(pb, i0, i1, i2)) continue;
-        double v = Re[a];
-        if (TABLE && pb.rational) v *= pb.wts[local_to_global<DIM, P>(pb, f, a)];
-        const int64_t slot = csr_slot(pb, i0, i1, i2, j0, j1, j2);
-        if (f32) atomicAdd(&((float *)vals)[slot], (float)v);
-        else atomicAdd(&((double *)vals)[slot], v);
-      }
-    }
+    if (ok)
+      for (int a = lane; a < L; a += 64) Ke[a * KC + (k - cs)] = Re[a];
     __syncthreads();
+  }
+  // add the chunk's columns: consecutive threads on consecutive columns of one row
+  const int nc = ce - cs;
+  for (int i = t; i < L * nc; i += 256) {
+    const int a = i / nc, k = cs + i % nc;
+    const int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / PP : 0;
+    const int k0 = k % P, k1 = (k / P) % P, k2 = DIM == 3 ? k / PP : 0;
+    const int i0 = f[0] + a0, i1 = f[1] + a1, i2 = f[2] + a2;
+    const int j0 = f[0] + k0, j1 = f[1] + k1, j2 = f[2] + k2;
+    if (is_dirichlet_idx(pb, i0, i1, i2) || is_dirichlet_idx(pb, j0, j1, j2)) continue;
+    double v = Ke[a * KC + (k - cs)];
+    if (TABLE && pb.rational) v *= pb.wts[local_to_global<DIM, P>(pb, f, a)];
+    const int64_t slot = csr_slot(pb, i0, i1, i2, j0, j1, j2);
+    if (color >= 0) {
+      // no other workgroup of this launch touches the slot
+      if (f32) ((float *)vals)[slot] += (float)v;
+      else ((double *)vals)[slot] += v;
+    } else {
+      if (f32) atomicAdd(&((float *)vals)[slot], (float)v);
+      else atomicAdd(&((double *)vals)[slot], v);
+    }
+  }
+  if (ce < L) __syncthreads();
   }
 }
 
@@ -657,12 +685,11 @@ struct RunElemMat {
 
 template <int D, int P, bool T>
 struct RunElemND {
-  static void run(const Handle &h, const double *U, double eta, void *vals, int f32) {
+  static void run(const Handle &h, const double *U, double eta, void *vals, int f32, int color, unsigned nblk) {
     if constexpr (D == 3 && P > 5) {
       return;
     } else {
-      hipLaunchKernelGGL((k_elem_nd<D, P, T>), dim3((unsigned)h.pb.E), dim3(256), 0, h.stream, h.pb, U, eta, vals,
-                         f32);
+      hipLaunchKernelGGL((k_elem_nd<D, P, T>), dim3(nblk), dim3(256), 0, h.stream, h.pb, U, eta, vals, f32, color);
     }
   }
 };
@@ -759,7 +786,7 @@ iga_status launch_jac_scatter(Handle &h, const double *U, void *vals, int prec, 
 
 // Jacobian by local numerical differentiation: zero the values, add every element's difference
 // columns, then the identity Dirichlet rows.
-iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec) {
+iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec, int color_mode) {
   if (h.pb.dim == 3 && h.pb.P > 5) return fail(IGA_EUNSUPPORTED, "local numerical differentiation needs p <= 4 in 3D");
   const int64_t nnz = h.pb.nnz;
   const int f32 = prec == IGA_FP32 ? 1 : 0;
@@ -768,8 +795,20 @@ iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec) {
   else
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(nnz, 256)), dim3(256), 0, h.stream, (double *)vals, nnz, 0.0);
   // eta = sqrt(machine epsilon), the default of Sec. 2.8
-  iga_status st = dispatch_dpt<RunElemND>(h, U, 1.4901161193847656e-08, vals, f32);
-  if (st) return st;
+  const double eta = 1.4901161193847656e-08;
+  iga_status st;
+  if (!color_mode) {
+    if ((st = dispatch_dpt<RunElemND>(h, U, eta, vals, f32, -1, (unsigned)h.pb.E))) return st;
+  } else {
+    const int P = h.pb.P, ncol = ipow(P, h.pb.dim);
+    for (int c = 0; c < ncol; ++c) {
+      const int c0 = c % P, c1 = (c / P) % P, c2 = c / (P * P);
+      const int64_t k0 = (h.pb.ne[0] - c0 + P - 1) / P, k1 = (h.pb.ne[1] - c1 + P - 1) / P;
+      const int64_t k2 = h.pb.dim == 3 ? (h.pb.ne[2] - c2 + P - 1) / P : 1;
+      if (k0 <= 0 || k1 <= 0 || k2 <= 0) continue;
+      if ((st = dispatch_dpt<RunElemND>(h, U, eta, vals, f32, c, (unsigned)(k0 * k1 * k2)))) return st;
+    }
+  }
   if (f32)
     hipLaunchKernelGGL(k_bc_diag<float>, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb, (float *)vals);
   else

@@ -129,6 +129,7 @@ struct Handle {
   int jvals_prec = -1;
   // options
   int jac_algo = IGA_JAC_AUTO;
+  int nd_color = 0;   // local-ND scatter: 0 atomics (default), 1 colour-ordered plain adds
   int row_b1 = 0, row_b2 = 0;
   int row_segments = 0;           // separable row-gather: segments along axis 0 (0 = planned)
   // separable row-gather tables (3D, identity geometry, kappa = 1, simple knots)
@@ -212,7 +213,7 @@ iga_status launch_jac_scatter(Handle &h, const double *U, void *vals, int prec, 
 iga_status launch_jac_rowgather(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
 bool rowgather_supported(const Handle &h, int prec, int b1, int b2);
 iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
-iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec);
+iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec, int color_mode);
 bool rgt2_supported(const DevProblem &pb);
 bool res2_supported(const DevProblem &pb);
 iga_status launch_res2(Handle &h, const double *U, double *R);

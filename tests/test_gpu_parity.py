@@ -285,12 +285,15 @@ def test_jacobian_local_nd(name):
     print(f"[case] local-ND jacobian {name}", flush=True)
     patch, o, g, U = build_pair(name)
     g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_LOCAL_ND)
-    vals = torch.full((g.nnz,), np.nan, dtype=torch.float64, device="cuda")
-    g.assemble_jacobian(dev(U), vals)
-    got = host(vals)
-    assert np.all(np.isfinite(got)), "some CSR value was never written"
-    assert rel(got, o.jacobian_nd(U)) < 1e-7
-    assert rel(got, o.jacobian(U)) < 1e-7
+    ref_nd, ref = o.jacobian_nd(U), o.jacobian(U)
+    for scatter in (1, 0):
+        g.set_option(iga.IGA_OPT_ND_SCATTER, scatter)
+        vals = torch.full((g.nnz,), np.nan, dtype=torch.float64, device="cuda")
+        g.assemble_jacobian(dev(U), vals)
+        got = host(vals)
+        assert np.all(np.isfinite(got)), "some CSR value was never written"
+        assert rel(got, ref_nd) < 1e-7
+        assert rel(got, ref) < 1e-7
     v32 = torch.full((g.nnz,), np.nan, dtype=torch.float32, device="cuda")
     g.assemble_jacobian(dev(U), v32, iga.IGA_FP32)
     assert rel(host(v32), o.jacobian(U)) < 1e-5
