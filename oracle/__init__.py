@@ -40,6 +40,7 @@ class Problem(C.Structure):
         ("kappa", C.POINTER(C.c_double)),
         ("source", C.POINTER(C.c_double)),
         ("dirichlet_mask", C.c_uint),
+        ("periodic", C.c_int * 3),
     ]
 
 
@@ -57,6 +58,7 @@ def lib():
         P = C.POINTER(Problem)
         sig = {
             "orc_gauss_legendre": [C.c_int, _dp, _dp],
+            "orc_unclamp": [C.c_int, C.c_int, C.c_int, _dp],
             "orc_basis_1d": [C.c_int, _dp, C.c_int, C.c_int, C.c_double, _dp, _dp],
             "orc_stencil": [C.c_int, _dp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)],
             "orc_sizes": [P, _i64p, _i64p, _i64p],
@@ -94,7 +96,9 @@ class Oracle:
     that back its pointers alive."""
 
     def __init__(self, knots, degree, ctrl=None, weights=None, lam=1.0, kappa_mode=0, kappa=None,
-                 source=None, dirichlet_mask=None, nquad=None):
+                 source=None, dirichlet_mask=None, nquad=None, periodic=None):
+        """periodic: per axis None (open) or the continuity k across the seam (Sec. 2.4); the
+        default Dirichlet mask then leaves the periodic axes' faces free."""
         dim = len(knots)
         self.dim = dim
         self._keep = []
@@ -121,7 +125,12 @@ class Oracle:
         pb.kappa_mode = int(kappa_mode)
         pb.kappa = keep(kappa)
         pb.source = keep(source)
-        pb.dirichlet_mask = (1 << (2 * dim)) - 1 if dirichlet_mask is None else int(dirichlet_mask)
+        per = [None] * 3 if periodic is None else list(periodic) + [None] * (3 - len(periodic))
+        for d in range(3):
+            pb.periodic[d] = 0 if per[d] is None else int(per[d]) + 1
+        if dirichlet_mask is None:
+            dirichlet_mask = sum(3 << (2 * d) for d in range(dim) if per[d] is None)
+        pb.dirichlet_mask = int(dirichlet_mask)
         self.pb = pb
         N, E, nnz = C.c_int64(), C.c_int64(), C.c_int64()
         rc = lib().orc_sizes(C.byref(pb), C.byref(N), C.byref(E), C.byref(nnz))
@@ -270,3 +279,12 @@ def stencil(p, U, i):
     if lib().orc_stencil(p, _ptr(U), len(U), i, C.byref(l), C.byref(r)):
         raise ValueError("bad index")
     return l.value, r.value
+
+
+def unclamp(U, p, k):
+    """Knot vector unclamped for C^k periodicity (Sec. 2.4, eq:unclamp-left/right)."""
+    U = np.array(U, dtype=np.float64, copy=True)
+    n = len(U) - p - 2
+    if lib().orc_unclamp(n, p, k, _ptr(U)):
+        raise ValueError("bad continuity")
+    return U

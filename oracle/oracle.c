@@ -116,12 +116,63 @@ typedef struct {
   int dim;
   int p[3], n[3], nq[3], ne[3];
   int *span[3];            /* span index s of each element: functions s-p..s are nonzero */
+  int per[3];              /* periodic axis: continuity k + 1 across the seam; 0: not periodic */
+  const double *kn[3];     /* knots in use (the unclamped copy on a periodic axis) */
+  double *ukn[3];          /* owned unclamped copy, or NULL */
   double gx[3][ORC_MAXQ], gw[3][ORC_MAXQ];
   int64_t N, E;
 } layout;
 
 static void lay_free(layout *L) {
-  for (int d = 0; d < 3; ++d) free(L->span[d]);
+  for (int d = 0; d < 3; ++d) {
+    free(L->span[d]);
+    free(L->ukn[d]);
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Periodicity (Sec. 2.4): unclamp an open knot vector for C^k continuity across the seam  */
+/* by redefining k+1 knots at each end (eq:unclamp-left, eq:unclamp-right), in place.       */
+/* n is the index of the last basis function of the open vector (m = n + p + 1).           */
+/* ------------------------------------------------------------------------------------ */
+int orc_unclamp(int n, int p, int k, double *U) {
+  if (k < 0 || k > p - 1 || n < p) return 1;
+  int m = n + p + 1;
+  for (int i = 0; i <= k; ++i) U[k - i] = U[p] - U[n + 1] + U[n - i];
+  for (int i = 0; i <= k; ++i) U[m - k + i] = U[n + 1] - U[p] + U[p + i + 1];
+  return 0;
+}
+
+/* eq:map-wrap: global index of a basis function on a periodic axis with nper functions */
+static int wrap(int i, int nper) {
+  int q = (int)floor((double)i / (double)nper);
+  return i - nper * q;
+}
+
+/* global index of local function a (0..p) of the element with span s along axis d */
+static int fn_index(const layout *L, int d, int s, int a) {
+  int i = s - L->p[d] + a;
+  return L->per[d] ? wrap(i, L->n[d]) : i;
+}
+
+/* sorted distinct functions sharing an element with function i along axis d */
+static int axis_neighbors(const layout *L, int d, int i, int *out) {
+  int c = 0;
+  for (int e = 0; e < L->ne[d]; ++e) {
+    int s = L->span[d][e], has = 0;
+    for (int a = 0; a <= L->p[d]; ++a) has |= fn_index(L, d, s, a) == i;
+    if (!has) continue;
+    for (int b = 0; b <= L->p[d]; ++b) {
+      int j = fn_index(L, d, s, b), k = 0;
+      while (k < c && out[k] != j) ++k;
+      if (k == c) out[c++] = j;
+    }
+  }
+  for (int x = 1; x < c; ++x)     /* insertion sort */
+    for (int y = x; y > 0 && out[y - 1] > out[y]; --y) {
+      int t = out[y]; out[y] = out[y - 1]; out[y - 1] = t;
+    }
+  return c;
 }
 
 static int lay_init(const orc_problem *pb, layout *L) {
@@ -146,6 +197,20 @@ static int lay_init(const orc_problem *pb, layout *L) {
       if (U[k] != U[k + 1] || U[nk - 1 - k] != U[nk - 2 - k]) { lay_free(L); return 1; }
     L->p[d] = p;
     L->n[d] = nk - p - 1;
+    L->kn[d] = U;
+    L->per[d] = pb->periodic[d];
+    if (L->per[d]) {
+      int k = L->per[d] - 1;
+      /* the seam must not be a Dirichlet face, and n - k >= 2p + 1 keeps the wrapped stencil distinct */
+      if (k < 0 || k > p - 1 || ((pb->dirichlet_mask >> (2 * d)) & 3u) || L->n[d] - 1 - k < 2 * p + 1) {
+        lay_free(L);
+        return 1;
+      }
+      L->ukn[d] = (double *)malloc(sizeof(double) * nk);
+      memcpy(L->ukn[d], U, sizeof(double) * nk);
+      orc_unclamp(L->n[d] - 1, p, k, L->ukn[d]);
+      L->kn[d] = L->ukn[d];
+    }
     L->nq[d] = pb->nquad[d] > 0 ? pb->nquad[d] : p + 1;
     if (L->nq[d] > ORC_MAXQ) { lay_free(L); return 1; }
     orc_gauss_legendre(L->nq[d], L->gx[d], L->gw[d]);
@@ -155,6 +220,7 @@ static int lay_init(const orc_problem *pb, layout *L) {
       if (U[s] < U[s + 1]) L->span[d][ne++] = s;
     if (ne == 0) { lay_free(L); return 1; }
     L->ne[d] = ne;
+    if (L->per[d]) L->n[d] -= L->per[d];   /* n - k distinct functions (n: index of the last) */
   }
   for (int d = 0; d < 3; ++d) { L->N *= L->n[d]; L->E *= L->ne[d]; }
   if (pb->weights)
@@ -195,7 +261,7 @@ static int eval_qp(const orc_problem *pb, const layout *L, const int e[3], const
   double B[3][ORC_MAXP], dB[3][ORC_MAXP], wq = 1.0;
   for (int d = 0; d < 3; ++d) {
     if (d >= dim) { B[d][0] = 1.0; dB[d][0] = 0.0; continue; }
-    const double *K = pb->knots[d];
+    const double *K = L->kn[d];
     int s = L->span[d][e[d]], p = L->p[d];
     double a = K[s], b = K[s + 1];
     double xi = 0.5 * ((a + b) + (b - a) * L->gx[d][g[d]]);
@@ -211,9 +277,9 @@ static int eval_qp(const orc_problem *pb, const layout *L, const int e[3], const
     for (int a1 = 0; a1 < P1; ++a1)
       for (int a0 = 0; a0 < P0; ++a0) {
         int a = a0 + P0 * (a1 + P1 * a2);
-        int64_t i0 = L->span[0][e[0]] - L->p[0] + a0;
-        int64_t i1 = L->span[1][e[1]] - L->p[1] + a1;
-        int64_t i2 = L->span[2][e[2]] - L->p[2] + a2;
+        int64_t i0 = fn_index(L, 0, L->span[0][e[0]], a0);
+        int64_t i1 = fn_index(L, 1, L->span[1][e[1]], a1);
+        int64_t i2 = fn_index(L, 2, L->span[2][e[2]], a2);
         q->A[a] = i0 + (int64_t)L->n[0] * (i1 + (int64_t)L->n[1] * i2);
         M[a] = B[0][a0] * B[1][a1] * B[2][a2];
         dM[a][0] = dB[0][a0] * B[1][a1] * B[2][a2];
@@ -254,7 +320,7 @@ static int eval_qp(const orc_problem *pb, const layout *L, const int e[3], const
       }
   } else {
     for (int d = 0; d < dim; ++d) {
-      const double *K = pb->knots[d];
+      const double *K = L->kn[d];
       int s = L->span[d][e[d]];
       xi_phys[d] = 0.5 * ((K[s] + K[s + 1]) + (K[s + 1] - K[s]) * L->gx[d][g[d]]);
     }
@@ -338,9 +404,14 @@ int orc_sizes(const orc_problem *pb, int64_t *ndof, int64_t *nelem, int64_t *nnz
     int64_t i[3] = {A % L.n[0], (A / L.n[0]) % L.n[1], A / ((int64_t)L.n[0] * L.n[1])};
     int64_t w = 1;
     for (int d = 0; d < pb->dim; ++d) {
-      int l, r;
-      orc_stencil(L.p[d], pb->knots[d], pb->nknots[d], (int)i[d], &l, &r);
-      w *= (r - l + 1);
+      if (L.per[d]) {
+        int nb[2 * ORC_MAXP + 8];
+        w *= axis_neighbors(&L, d, (int)i[d], nb);
+      } else {
+        int l, r;
+        orc_stencil(L.p[d], pb->knots[d], pb->nknots[d], (int)i[d], &l, &r);
+        w *= (r - l + 1);
+      }
     }
     cnt += w;
   }
@@ -358,13 +429,23 @@ int orc_csr_pattern(const orc_problem *pb, int64_t *row_ptr, int32_t *col_idx) {
   row_ptr[0] = 0;
   for (int64_t A = 0; A < L.N; ++A) {
     int64_t i[3] = {A % L.n[0], (A / L.n[0]) % L.n[1], A / ((int64_t)L.n[0] * L.n[1])};
-    int l[3] = {0, 0, 0}, r[3] = {0, 0, 0};
-    for (int d = 0; d < pb->dim; ++d)
-      orc_stencil(L.p[d], pb->knots[d], pb->nknots[d], (int)i[d], &l[d], &r[d]);
-    for (int j2 = l[2]; j2 <= r[2]; ++j2)
-      for (int j1 = l[1]; j1 <= r[1]; ++j1)
-        for (int j0 = l[0]; j0 <= r[0]; ++j0)
-          col_idx[pos++] = (int32_t)(j0 + (int64_t)L.n[0] * (j1 + (int64_t)L.n[1] * j2));
+    /* per axis, the sorted functions sharing an element with i[d] (Algorithm 2 on an open axis) */
+    int nb[3][2 * ORC_MAXP + 8], c[3] = {1, 1, 1};
+    nb[1][0] = nb[2][0] = 0;
+    for (int d = 0; d < pb->dim; ++d) {
+      if (L.per[d]) {
+        c[d] = axis_neighbors(&L, d, (int)i[d], nb[d]);
+      } else {
+        int l, r;
+        orc_stencil(L.p[d], pb->knots[d], pb->nknots[d], (int)i[d], &l, &r);
+        c[d] = r - l + 1;
+        for (int j = l; j <= r; ++j) nb[d][j - l] = j;
+      }
+    }
+    for (int x2 = 0; x2 < c[2]; ++x2)
+      for (int x1 = 0; x1 < c[1]; ++x1)
+        for (int x0 = 0; x0 < c[0]; ++x0)
+          col_idx[pos++] = (int32_t)(nb[0][x0] + (int64_t)L.n[0] * (nb[1][x1] + (int64_t)L.n[1] * nb[2][x2]));
     row_ptr[A + 1] = pos;
   }
   lay_free(&L);
@@ -537,8 +618,9 @@ int orc_jacobian_nd(const orc_problem *pb, const double *U, const int64_t *row_p
 static int elems_of_fn(const layout *L, int d, int i, int *out) {
   int c = 0;
   for (int e = 0; e < L->ne[d]; ++e) {
-    int s = L->span[d][e];
-    if (s - L->p[d] <= i && i <= s) out[c++] = e;
+    int s = L->span[d][e], has = 0;
+    for (int a = 0; a <= L->p[d]; ++a) has |= fn_index(L, d, s, a) == i;
+    if (has) out[c++] = e;
   }
   return c;
 }

@@ -10,6 +10,7 @@
  *   - rational basis and its first derivatives (Sec. 2.3, eq:rational, eq:drational),
  *   - geometry Jacobian, inverse and spatial gradients (App. A, eq:identity, eq:dspatial),
  *   - the adjacency stencil of Algorithm 2 (Sec. 2.5),
+ *   - periodic axes by unclamping (Sec. 2.4, eq:unclamp-left/right) and index wrapping (eq:map-wrap),
  *   - naive per-quadrature-point residual/Jacobian assembly as in Algorithm 3 (Sec. 2.7)
  *     with the Bratu integrands eq:residual and eq:jacobian (Sec. 3.1),
  *   - the local numerical-differentiation Jacobian of Sec. 2.8 (eq:fdjac),
@@ -37,9 +38,14 @@ typedef struct {
   const double *kappa;
   const double *source;      /* N spline coefficients of f, or NULL */
   unsigned dirichlet_mask;   /* bit 2*axis+side: u = 0 on that face */
+  int periodic[3];           /* 0: open axis; k + 1: periodic with C^k across the seam (Sec. 2.4):
+                                the open knots given are unclamped and n - k functions remain,
+                                n being the index of the last open function */
 } orc_problem;
 
 int orc_gauss_legendre(int n, double *x, double *w);
+/* eq:unclamp-left / eq:unclamp-right in place; n = index of the last basis function */
+int orc_unclamp(int n, int p, int k, double *U);
 int orc_basis_1d(int p, const double *U, int nk, int i, double xi, double *val, double *der);
 int orc_stencil(int p, const double *U, int nk, int i, int *l, int *r);
 int orc_sizes(const orc_problem *pb, int64_t *ndof, int64_t *nelem, int64_t *nnz);
