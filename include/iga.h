@@ -103,6 +103,14 @@ typedef struct {
   const double *kappa;           /* host: N nodal values or E element values (natural order) */
   const double *source;          /* host, N spline coefficients of f, or NULL */
   unsigned dirichlet_mask;       /* bit 2*axis+side set: u = 0 on that face */
+  int periodic[3];               /* 0: open axis; k + 1: periodic with C^k continuity across the seam
+                                    (Sec. 2.4).  The open knots given are unclamped by
+                                    eq:unclamp-left/right and functions are wrapped by eq:map-wrap,
+                                    leaving n - k per axis (n: index of the last open function;
+                                    at least 2p+1 must remain).  Needs x = xi, no weights, kappa one or
+                                    element-wise, no Dirichlet face on that axis; the assembly then
+                                    uses element kernels (IGA_JAC_ATOMIC or IGA_JAC_LOCAL_ND), CSR
+                                    SpMV with column indices and Jacobi-CG. */
 } iga_desc;
 
 typedef struct {

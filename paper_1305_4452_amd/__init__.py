@@ -44,6 +44,7 @@ class iga_desc(C.Structure):
         ("kappa", _dp),
         ("source", _dp),
         ("dirichlet_mask", C.c_uint),
+        ("periodic", C.c_int * 3),
     ]
 
 
@@ -193,8 +194,10 @@ def _dev_ptr(t, dtype, n, name):
 
 
 def make_desc(keep, knots, degree, ctrl=None, weights=None, lam=1.0, kappa_mode=IGA_KAPPA_ONE, kappa=None,
-              source=None, dirichlet_mask=None, d=None):
-    """Fill an iga_desc; the numpy arrays backing its pointers are appended to `keep`."""
+              source=None, dirichlet_mask=None, d=None, periodic=None):
+    """Fill an iga_desc; the numpy arrays backing its pointers are appended to `keep`.  periodic:
+    per axis None (open) or the continuity k across the seam; the default Dirichlet mask then
+    leaves the periodic axes' faces free."""
     dim = len(knots)
 
     def arr(a):
@@ -220,7 +223,12 @@ def make_desc(keep, knots, degree, ctrl=None, weights=None, lam=1.0, kappa_mode=
     d.kappa_mode = int(kappa_mode)
     d.kappa = arr(kappa)
     d.source = arr(source)
-    d.dirichlet_mask = (1 << (2 * dim)) - 1 if dirichlet_mask is None else int(dirichlet_mask)
+    per = [None] * 3 if periodic is None else list(periodic) + [None] * (3 - len(periodic))
+    for a in range(3):
+        d.periodic[a] = 0 if per[a] is None else int(per[a]) + 1
+    if dirichlet_mask is None:
+        dirichlet_mask = sum(3 << (2 * a) for a in range(dim) if per[a] is None)
+    d.dirichlet_mask = int(dirichlet_mask)
     return d
 
 
@@ -228,12 +236,13 @@ class IGA:
     """One problem (handle) bound to the current torch stream at creation."""
 
     def __init__(self, knots, degree, ctrl=None, weights=None, lam=1.0, kappa_mode=IGA_KAPPA_ONE, kappa=None,
-                 source=None, dirichlet_mask=None, stream=None):
+                 source=None, dirichlet_mask=None, stream=None, periodic=None):
         import torch
         L = load()
         dim = len(knots)
         self._keep = []
-        d = make_desc(self._keep, knots, degree, ctrl, weights, lam, kappa_mode, kappa, source, dirichlet_mask)
+        d = make_desc(self._keep, knots, degree, ctrl, weights, lam, kappa_mode, kappa, source, dirichlet_mask,
+                      periodic=periodic)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

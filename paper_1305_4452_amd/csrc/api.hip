@@ -68,7 +68,10 @@ static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int 
     st = launch_jac_rowgather(h, U, vals, prec, b1, b2);
   } else if (algo == IGA_JAC_LOCAL_ND) {
     kt_begin(h, "k_elem_nd (local numerical differentiation)");
-    st = launch_jac_nd(h, U, vals, prec, h.nd_color);
+    // colours assume no function is shared across the ends of an axis
+    st = launch_jac_nd(h, U, vals, prec, h.pb.periodic ? 0 : h.nd_color);
+  } else if (algo == IGA_JAC_COLOR && h.pb.periodic) {
+    return fail(IGA_EUNSUPPORTED, "colour scatter needs open axes (elements share functions across the seam)");
   } else if (algo == IGA_JAC_ATOMIC || algo == IGA_JAC_COLOR) {
     kt_begin(h, algo == IGA_JAC_ATOMIC ? "k_elem_mat (atomic scatter)" : "k_elem_mat (colour scatter)");
     st = launch_jac_scatter(h, U, vals, prec, algo == IGA_JAC_COLOR ? 1 : 0);

@@ -969,6 +969,10 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
   std::vector<Handle *> hs_user(n, nullptr);
   for (int i = 0; i < n; ++i) {
     if (descs[i].dim != 2) { st = fail(IGA_EUNSUPPORTED, "batched solves are 2D"); break; }
+    if (descs[i].periodic[0] || descs[i].periodic[1] || descs[i].periodic[2]) {
+      st = fail(IGA_EUNSUPPORTED, "batched solves use open axes");
+      break;
+    }
     if (descs[i].ctrl || descs[i].weights || descs[i].kappa_mode == IGA_KAPPA_NODAL) {
       st = fail(IGA_EUNSUPPORTED, "batched solves use the identity geometry without weights");
       break;

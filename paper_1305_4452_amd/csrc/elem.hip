@@ -255,8 +255,8 @@ __global__ void __launch_bounds__(256) k_elem_mat(DevProblem pb, const double *_
     }
     int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / PP : 0;
     int b0 = b % P, b1 = (b / P) % P, b2 = DIM == 3 ? b / PP : 0;
-    int i0 = f[0] + a0, i1 = f[1] + a1, i2 = f[2] + a2;
-    int j0 = f[0] + b0, j1 = f[1] + b1, j2 = f[2] + b2;
+    int i0 = wrap_fn(pb.ax[0], f[0] + a0), i1 = wrap_fn(pb.ax[1], f[1] + a1), i2 = DIM == 3 ? wrap_fn(pb.ax[2], f[2] + a2) : 0;
+    int j0 = wrap_fn(pb.ax[0], f[0] + b0), j1 = wrap_fn(pb.ax[1], f[1] + b1), j2 = DIM == 3 ? wrap_fn(pb.ax[2], f[2] + b2) : 0;
     if (is_dirichlet_idx(pb, i0, i1, i2) || is_dirichlet_idx(pb, j0, j1, j2)) continue;
     int64_t slot = csr_slot(pb, i0, i1, i2, j0, j1, j2);
     if (MODE == EM_ATOMIC) {
@@ -487,8 +487,10 @@ __global__ void __launch_bounds__(256) k_elem_nd(DevProblem pb, const double *__
     const int a = i / nc, k = cs + i % nc;
     const int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / PP : 0;
     const int k0 = k % P, k1 = (k / P) % P, k2 = DIM == 3 ? k / PP : 0;
-    const int i0 = f[0] + a0, i1 = f[1] + a1, i2 = f[2] + a2;
-    const int j0 = f[0] + k0, j1 = f[1] + k1, j2 = f[2] + k2;
+    const int i0 = wrap_fn(pb.ax[0], f[0] + a0), i1 = wrap_fn(pb.ax[1], f[1] + a1);
+    const int i2 = DIM == 3 ? wrap_fn(pb.ax[2], f[2] + a2) : 0;
+    const int j0 = wrap_fn(pb.ax[0], f[0] + k0), j1 = wrap_fn(pb.ax[1], f[1] + k1);
+    const int j2 = DIM == 3 ? wrap_fn(pb.ax[2], f[2] + k2) : 0;
     if (is_dirichlet_idx(pb, i0, i1, i2) || is_dirichlet_idx(pb, j0, j1, j2)) continue;
     double v = Ke[a * KC + (k - cs)];
     if (TABLE && pb.rational) v *= pb.wts[local_to_global<DIM, P>(pb, f, a)];

@@ -28,7 +28,12 @@ struct AxisDev {
   const int *efirst;   // [ne]         index of the first non-zero function of each element
   const int *stl;      // [n]          Algorithm 2 left index
   const int *stw;      // [n]          Algorithm 2 width r - l + 1
+  int nper;            // periodic axis: its number of functions (indices wrap); 0 on an open axis
+  const int *nbr;      // periodic axis: [n][2p+1] sorted functions sharing an element with each one
 };
+
+// eq:map-wrap for the local-to-global index of an element function (i < 2 nper here)
+__host__ __device__ inline int wrap_fn(const AxisDev &ax, int i) { return (ax.nper && i >= ax.nper) ? i - ax.nper : i; }
 
 // Plain-old-data view of a problem passed by value to kernels.
 struct DevProblem {
@@ -49,6 +54,7 @@ struct DevProblem {
   unsigned dmask;
   int simple_knots;    // every element's first function equals its span counter (max continuity)
   int separable;       // identity geometry, no weights, kappa = 1: stiffness is a Kronecker sum
+  int periodic;        // some axis is periodic (element kernels and CSR SpMV only)
   // 1D Galerkin matrices per axis, band storage [n][2p+1] (offset o = j - i + p):
   //   M_d[i][o] = sum_g w(g) B_i(g) B_j(g),  A_d[i][o] = sum_g w(g) B'_i(g) B'_j(g)
   const double *sepM[3], *sepA[3];
@@ -85,11 +91,21 @@ __device__ inline bool is_dirichlet(const DevProblem &pb, int64_t A) {
 
 // Offset of column (j0,j1,j2) inside row (i0,i1,i2): the row holds the tensor product of the
 // per-axis stencils, ordered with axis 0 fastest, so no search is needed.
+// position of column j in row i's list along one axis (a periodic axis searches its sorted list)
+__device__ inline int axis_rank(const AxisDev &ax, int W, int i, int j) {
+  if (!ax.nper) return j - ax.stl[i];
+  const int *l = ax.nbr + (size_t)i * W;
+  int r = 0;
+  while (r < W - 1 && l[r] != j) ++r;
+  return r;
+}
+
 __device__ inline int64_t csr_slot(const DevProblem &pb, int i0, int i1, int i2, int j0, int j1, int j2) {
   int64_t A = i0 + (int64_t)pb.n[0] * (i1 + (int64_t)pb.n[1] * i2);
+  const int W = 2 * pb.p + 1;
   int w0 = pb.ax[0].stw[i0], w1 = pb.ax[1].stw[i1];
-  int o0 = j0 - pb.ax[0].stl[i0], o1 = j1 - pb.ax[1].stl[i1];
-  int o2 = pb.dim == 3 ? j2 - pb.ax[2].stl[i2] : 0;
+  int o0 = axis_rank(pb.ax[0], W, i0, j0), o1 = axis_rank(pb.ax[1], W, i1, j1);
+  int o2 = pb.dim == 3 ? axis_rank(pb.ax[2], W, i2, j2) : 0;
   return pb.row_ptr[A] + ((int64_t)o2 * w1 + o1) * w0 + o0;
 }
 

@@ -22,7 +22,8 @@ __device__ inline void elem_coords(const DevProblem &pb, int64_t e, int em[3]) {
 template <int DIM, int P>
 __device__ inline int64_t local_to_global(const DevProblem &pb, const int f[3], int a) {
   int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / (P * P) : 0;
-  int64_t A = (f[0] + a0) + (int64_t)pb.n[0] * ((f[1] + a1) + (int64_t)pb.n[1] * (DIM == 3 ? f[2] + a2 : 0));
+  int64_t A = wrap_fn(pb.ax[0], f[0] + a0) +
+              (int64_t)pb.n[0] * (wrap_fn(pb.ax[1], f[1] + a1) + (int64_t)pb.n[1] * (DIM == 3 ? wrap_fn(pb.ax[2], f[2] + a2) : 0));
   return A;
 }
 

@@ -272,8 +272,9 @@ iga_status launch_spmv(Handle &h, const void *vals, int prec, const double *x, d
                        int npart) {
   const int64_t N = h.pb.N;
   const int blocks = spmv_blocks(h, npart);
-  if (N < INT32_MAX / 2 && (int64_t)h.pb.n[0] * h.pb.n[1] * h.pb.n[2] < INT32_MAX && 2 * h.pb.p + 1 < 16) {
-    // tensor-product pattern: values only; NV = loads per lane for the longest row, (2p+1)^dim / 64
+  if (N < INT32_MAX / 2 && (int64_t)h.pb.n[0] * h.pb.n[1] * h.pb.n[2] < INT32_MAX && 2 * h.pb.p + 1 < 16 &&
+      !h.pb.periodic) {
+    // tensor-product pattern (contiguous column ranges per axis): values only; NV = loads per lane for the longest row, (2p+1)^dim / 64
     static const int nv3[7] = {0, 1, 2, 6, 12, 21, 35}, nv2[7] = {0, 1, 1, 1, 2, 2, 3};
     const int nv = h.pb.dim == 3 ? nv3[h.pb.p] : nv2[h.pb.p];
 #define IGA_SPMV_TP(D, NVV)                                                                                  \

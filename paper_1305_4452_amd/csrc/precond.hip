@@ -161,7 +161,7 @@ static void fdm_ranges(const DevProblem &pb, int *lo, int *m) {
 }
 
 bool fdm_possible(const Handle &h) {
-  if (h.hsepM[0].empty()) return false;
+  if (h.hsepM[0].empty() || h.pb.periodic) return false;
   int lo[3], m[3];
   fdm_ranges(h.pb, lo, m);
   for (int d = 0; d < h.pb.dim; ++d)

@@ -46,7 +46,7 @@ iga_status run_res2(Handle &h, const double *U, double *R) {
 }  // namespace
 
 bool res2_supported(const DevProblem &pb) {
-  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && pb.P >= 2 && pb.P <= 5 &&
+  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && !pb.periodic && pb.P >= 2 && pb.P <= 5 &&
          (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
 }
 
@@ -61,7 +61,7 @@ iga_status launch_res2(Handle &h, const double *U, double *R) {
 }
 
 bool rgt2_supported(const DevProblem &pb) {
-  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && pb.P >= 2 && pb.P <= 5 &&
+  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && !pb.periodic && pb.P >= 2 && pb.P <= 5 &&
          (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
 }
 

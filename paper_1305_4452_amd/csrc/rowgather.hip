@@ -337,7 +337,7 @@ iga_status pick2(const Handle &h, const double *U, void *vals, int prec, int b1)
 
 bool rowgather_supported(const Handle &h, int prec, int b1, int b2) {
   (void)prec;
-  if (!h.pb.simple_knots) return false;
+  if (!h.pb.simple_knots || h.pb.periodic) return false;
   if (h.pb.dim == 3) {
     if (h.pb.P < 2 || h.pb.P > 5) return false;
     if (b1 == 1 && b2 == 1) return true;

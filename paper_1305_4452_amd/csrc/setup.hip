@@ -89,15 +89,19 @@ __global__ void k_pattern(DevProblem pb, int32_t *col_idx) {
   int64_t r = A / pb.n[0];
   int i1 = (int)(r % pb.n[1]);
   int i2 = (int)(r / pb.n[1]);
+  const int W = 2 * pb.p + 1;
   int l0 = pb.ax[0].stl[i0], w0 = pb.ax[0].stw[i0];
   int l1 = pb.ax[1].stl[i1], w1 = pb.ax[1].stw[i1];
   int l2 = 0, w2 = 1;
   if (pb.dim == 3) { l2 = pb.ax[2].stl[i2]; w2 = pb.ax[2].stw[i2]; }
+  // column b of row i along an axis: l + b, or the b-th entry of a periodic axis' sorted list
+  auto col = [&](int d, int i, int l, int b) { return pb.ax[d].nper ? pb.ax[d].nbr[(size_t)i * W + b] : l + b; };
   int64_t pos = pb.row_ptr[A];
   for (int b2 = 0; b2 < w2; ++b2)
     for (int b1 = 0; b1 < w1; ++b1)
       for (int b0 = 0; b0 < w0; ++b0)
-        col_idx[pos++] = (int32_t)((l0 + b0) + (int64_t)pb.n[0] * ((l1 + b1) + (int64_t)pb.n[1] * (l2 + b2)));
+        col_idx[pos++] = (int32_t)(col(0, i0, l0, b0) +
+                                   (int64_t)pb.n[0] * (col(1, i1, l1, b1) + (int64_t)pb.n[1] * (pb.dim == 3 ? col(2, i2, l2, b2) : 0)));
 }
 
 // Geometry table, one thread per (element, quadrature point); naive sums over the element's
@@ -333,6 +337,20 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       if (mult > p) return fail(IGA_EINVAL, "interior knot multiplicity must be <= p");
     }
   }
+  bool any_periodic = false;
+  for (int a = 0; a < dim; ++a) {
+    const int pr = d->periodic[a];
+    if (pr == 0) continue;
+    any_periodic = true;
+    if (pr < 1 || pr > p) return fail(IGA_EINVAL, "periodic[axis] must be 0 or k + 1 with 0 <= k <= p - 1");
+    if ((d->dirichlet_mask >> (2 * a)) & 3u) return fail(IGA_EINVAL, "a periodic axis has no Dirichlet faces");
+    if (d->nknots[a] - p - 2 - (pr - 1) < 2 * p + 1)
+      return fail(IGA_EINVAL, "a periodic axis needs at least 2p+1 functions after wrapping");
+  }
+  for (int a = dim; a < 3; ++a)
+    if (d->periodic[a] != 0) return fail(IGA_EINVAL, "periodic set on an axis beyond dim");
+  if (any_periodic && (d->ctrl || d->weights || d->kappa_mode == IGA_KAPPA_NODAL))
+    return fail(IGA_EUNSUPPORTED, "periodic axes need x = xi, no weights and kappa one or element-wise");
   if (d->kappa_mode < 0 || d->kappa_mode > 2) return fail(IGA_EINVAL, "bad kappa_mode");
   if (d->kappa_mode != IGA_KAPPA_ONE && !d->kappa) return fail(IGA_EINVAL, "kappa values missing");
   if (!std::isfinite(d->lambda)) return fail(IGA_EINVAL, "lambda must be finite");
@@ -356,11 +374,21 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   gauss_legendre(pb.Q, gx, gw);
   std::vector<int> stl[3], stw[3];
   std::vector<double> hostB[3], hostSM[3], hostSA[3];
+  std::vector<int> nbr[3];
   for (int a = 0; a < 3; ++a) {
     if (a >= dim) { pb.n[a] = 1; pb.ne[a] = 1; continue; }
-    const double *U = d->knots[a];
     int nk = d->nknots[a];
-    h->hknots[a].assign(U, U + nk);
+    h->hknots[a].assign(d->knots[a], d->knots[a] + nk);
+    const int kper = d->periodic[a] - 1;   // -1: open axis
+    if (kper >= 0) {
+      // unclamp for C^k across the seam (eq:unclamp-left / eq:unclamp-right); the domain
+      // [U_p, U_{n+1}] and its spans are unchanged, only the end knots move
+      std::vector<double> &K = h->hknots[a];
+      const int nl = nk - p - 2, m = nk - 1;   // index of the last function, of the last knot
+      for (int i = 0; i <= kper; ++i) K[kper - i] = K[p] - K[nl + 1] + K[nl - i];
+      for (int i = 0; i <= kper; ++i) K[m - kper + i] = K[nl + 1] - K[p] + K[p + i + 1];
+    }
+    const double *U = h->hknots[a].data();
     int n = nk - p - 1;
     std::vector<int> efirst;
     std::vector<double> B, dB, wq;
@@ -378,21 +406,40 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
         wq.push_back(gw[q] * 0.5 * (hi - lo));
       }
     }
+    const int nopen = n;
+    if (kper >= 0) n = nopen - 1 - kper;   // eq:map-wrap leaves n - k functions
     pb.n[a] = n;
     pb.ne[a] = (int)efirst.size();
     hostB[a] = B;
-    // Algorithm 2 ranges: function j overlaps function i iff their open supports intersect
+    const int W = 2 * p + 1;
     stl[a].resize(n);
     stw[a].resize(n);
-    for (int i = 0; i < n; ++i) {
-      int l = i, r = i;
-      while (l - 1 >= 0 && U[l - 1 + p + 1] > U[i]) --l;
-      while (r + 1 < n && U[r + 1] < U[i + p + 1]) ++r;
-      stl[a][i] = l;
-      stw[a][i] = r - l + 1;
+    if (kper < 0) {
+      // Algorithm 2 ranges: function j overlaps function i iff their open supports intersect
+      for (int i = 0; i < n; ++i) {
+        int l = i, r = i;
+        while (l - 1 >= 0 && U[l - 1 + p + 1] > U[i]) --l;
+        while (r + 1 < n && U[r + 1] < U[i + p + 1]) ++r;
+        stl[a][i] = l;
+        stw[a][i] = r - l + 1;
+      }
+    } else {
+      // periodic axis: the wrapped functions sharing an element with i, sorted
+      std::vector<std::vector<int>> sets(n);
+      for (size_t e = 0; e < efirst.size(); ++e)
+        for (int ia = 0; ia <= p; ++ia)
+          for (int ib = 0; ib <= p; ++ib) sets[(efirst[e] + ia) % n].push_back((efirst[e] + ib) % n);
+      nbr[a].assign((size_t)n * W, -1);
+      for (int i = 0; i < n; ++i) {
+        std::sort(sets[i].begin(), sets[i].end());
+        sets[i].erase(std::unique(sets[i].begin(), sets[i].end()), sets[i].end());
+        stl[a][i] = sets[i][0];
+        stw[a][i] = (int)sets[i].size();
+        for (size_t r = 0; r < sets[i].size(); ++r) nbr[a][(size_t)i * W + r] = sets[i][r];
+      }
     }
-    // 1D mass and stiffness in band storage (used by the separable Jacobian kernel)
-    const int W = 2 * p + 1;
+    // 1D mass and stiffness in band storage (row i, offset o: column i + o - p, wrapped on a
+    // periodic axis), used by the separable kernels and the fast-diagonalisation set-up
     const int P1 = p + 1;
     std::vector<double> sM((size_t)n * W, 0.0), sA((size_t)n * W, 0.0);
     std::vector<double> eM(efirst.size() * P1 * P1, 0.0), eA(efirst.size() * P1 * P1, 0.0);
@@ -402,7 +449,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
         double wgt = wq[e * pb.Q + q];
         for (int ia = 0; ia <= p; ++ia)
           for (int ib = 0; ib <= p; ++ib) {
-            size_t o = (size_t)(efirst[e] + ia) * W + (ib - ia + p);
+            size_t o = (size_t)((efirst[e] + ia) % n) * W + (ib - ia + p);
             const double m = wgt * Bq[ia] * Bq[ib], k = wgt * dBq[ia] * dBq[ib];
             sM[o] += m;
             sA[o] += k;
@@ -432,7 +479,17 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       iga_destroy((iga_t)h);
       return st;
     }
-    pb.ax[a] = AxisDev{d_B, d_dB, d_wq, d_ef, d_stl, d_stw};
+    pb.ax[a] = AxisDev{d_B, d_dB, d_wq, d_ef, d_stl, d_stw, 0, nullptr};
+    if (kper >= 0) {
+      int *d_nbr;
+      if ((st = dev_upload(*h, &d_nbr, nbr[a].data(), nbr[a].size()))) {
+        iga_destroy((iga_t)h);
+        return st;
+      }
+      pb.ax[a].nper = n;
+      pb.ax[a].nbr = d_nbr;
+      pb.periodic = 1;
+    }
   }
   for (int a = 0; a < 3; ++a) { pb.N *= pb.n[a]; pb.E *= pb.ne[a]; }
   // row pointer: prefix sum of the stencil-width products
@@ -463,7 +520,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       }
   pb.rational = d->weights != nullptr;
   pb.table = (d->ctrl != nullptr || d->weights != nullptr || d->kappa_mode == IGA_KAPPA_NODAL) ? 1 : 0;
-  pb.separable = (!pb.table && d->kappa_mode == IGA_KAPPA_ONE) ? 1 : 0;
+  pb.separable = (!pb.table && d->kappa_mode == IGA_KAPPA_ONE && !pb.periodic) ? 1 : 0;
   if (pb.separable && pb.simple_knots && dim == 3 && pb.P >= 2 && pb.P <= 5 &&
       (st = build_separable_tables(*h, hostB))) {
     iga_destroy((iga_t)h);

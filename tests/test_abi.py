@@ -33,6 +33,6 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header_sizes():
-    # iga_desc: 4 + 12 + 12 (+4 pad) + 24 + 8 + 8 + 12 (+4) + 8 + 4 (+4) + 8 + 8 + 4 (+4) = 128 bytes
-    assert ctypes.sizeof(iga.iga_desc) == 128
+    # iga_desc: 4 + 12 + 12 (+4 pad) + 24 + 8 + 8 + 12 (+4) + 8 + 4 (+4) + 8 + 8 + 4 + 12 (+4) = 136 bytes
+    assert ctypes.sizeof(iga.iga_desc) == 136
     assert ctypes.sizeof(iga.iga_newton_opts) == 48
