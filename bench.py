@@ -168,6 +168,44 @@ def bench_batched(n: int):
                 t_krylov_ms=summ["t_krylov_ms"])
 
 
+def bench_periodic(nel: int = 64, p: int = 3):
+    """3D Bratu on the unit cube with x periodic (C^(p-1) across the seam, Sec. 2.4) and u = 0 on the
+    y and z faces, lambda = 5, the C2 mesh otherwise: residual, Jacobian (element matrices, atomic
+    scatter, the path periodic axes use) and Newton to ||R_k|| <= 1e-10 ||R_0|| with Jacobi-CG."""
+    import torch
+
+    import inputs
+    import paper_1305_4452_amd as iga
+    patch = inputs.unit_box(3, nel, p)
+    per = [p - 1, None, None]
+    g = iga.IGA(patch.knots, patch.degree, lam=5.0, periodic=per)
+    U = torch.as_tensor(inputs.uniform(2, 0, g.N, 0.0, 0.1), device="cuda")
+    res = dict(ndof=g.N, nnz=g.nnz, nelem=g.E, workload=f"3D Bratu {nel}^3 p={p}, x periodic C^{p - 1}, lambda=5")
+    R = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+    vals = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+    for key, fn in [("residual_ms", lambda: g.assemble_residual(U, R)), ("jacobian_ms", lambda: g.assemble_jacobian(U, vals))]:
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        res[key] = a.elapsed_time(b) / 3
+    del vals
+    Ux = U.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rep = g.newton_solve(Ux, atol=0.0, rtol=1e-10, max_krylov=20000, raise_on_fail=False)
+    torch.cuda.synchronize()
+    res["newton"] = dict(time_s=time.perf_counter() - t, converged=bool(rep["converged"]),
+                         newton_iters=rep["newton_iters"], krylov_iters=rep["krylov_iters_total"],
+                         rel_residual=rep["res_norm"] / rep["res_norm0"] if rep["res_norm0"] else 0.0)
+    print(f"[bench] periodic {nel}^3 p={p}: residual {res['residual_ms']:.2f} ms, jacobian {res['jacobian_ms']:.2f} ms, "
+          f"newton {res['newton']['time_s']:.3f} s ({res['newton']['krylov_iters']} CG its)", file=sys.stderr, flush=True)
+    return res
+
+
 def bench_cylinder(nel: int, degrees):
     """Nonlinear diffusion on the thick quarter cylinder (exact NURBS, kappa = exp(GRF) at the
     control points): Jacobian assembly (general row-gather, FP64 and FP32 values) and Newton to
@@ -255,6 +293,7 @@ def main():
                     help="run each hot kernel a few times and a 256 MiB device copy (for counter runs), then exit")
     ap.add_argument("--batch-n", type=int, default=512)
     ap.add_argument("--no-cylinder", action="store_true")
+    ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--learned-train", type=int, default=2000, help="0 skips the learned-guess section")
     ap.add_argument("--learned-test", type=int, default=300)
     ap.add_argument("--learned-epochs", type=int, default=12)
@@ -417,6 +456,9 @@ def main():
     cylinder = None
     if not args.no_cylinder:
         cylinder = bench_cylinder(args.cyl_nel, (2, 3, 4))
+    periodic = None
+    if not args.no_periodic:
+        periodic = bench_periodic()
     learned = None
     if args.learned_train > 0:
         from paper_1305_4452_amd import learned as lg
@@ -472,6 +514,7 @@ def main():
         "newton": newton,
         "batched": batched,
         "cylinder": cylinder,
+        "periodic": periodic,
         "learned_guess": learned,
         "paper_context": {"explicit_jacobian_s": 15.41, "procs": 16, "hw": "2x Xeon E5-2680 v2",
                           "dof_per_s": 300763 / 15.41},

@@ -275,7 +275,7 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
     case IGA_OPT_PRECOND:
       if (value < IGA_PRECOND_AUTO || value > IGA_PRECOND_FDM) return fail(IGA_EINVAL, "bad preconditioner");
       if (value == IGA_PRECOND_FDM && !fdm_possible(*h))
-        return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs at most 240 unknowns per axis");
+        return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs at most 240 unknowns per axis and a Dirichlet face");
       h->precond = (int)value;
       return IGA_OK;
     case IGA_OPT_LAMBDA_BITS: {

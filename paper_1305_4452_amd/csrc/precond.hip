@@ -161,7 +161,9 @@ static void fdm_ranges(const DevProblem &pb, int *lo, int *m) {
 }
 
 bool fdm_possible(const Handle &h) {
-  if (h.hsepM[0].empty() || h.pb.periodic) return false;
+  if (h.hsepM[0].empty()) return false;
+  // with every axis periodic and no Dirichlet face the stiffness has the constants in its kernel
+  if (h.pb.periodic && h.pb.dmask == 0) return false;
   int lo[3], m[3];
   fdm_ranges(h.pb, lo, m);
   for (int d = 0; d < h.pb.dim; ++d)
@@ -262,19 +264,23 @@ static iga_status build_fdm(Handle &h) {
     const int lo = los[d], m = ms[d], hi = lo + m;
     if (m < 1 || m > kFdmMax) return IGA_OK;   // not applicable: Jacobi stays in use
     std::vector<double> A((size_t)m * m, 0.0), M((size_t)m * m, 0.0), rs(n, 0.0);
+    const bool per = pb.ax[d].nper != 0;   // periodic axis: band columns wrap (eq:map-wrap)
     for (int i = 0; i < n; ++i)
       for (int o = 0; o < W; ++o) {
-        const int j = i + o - p;
+        int j = i + o - p;
+        if (per) j = (j + n) % n;
         if (j < 0 || j >= n) continue;
         rs[i] += bandM[d][(size_t)i * W + o];
         if (i < lo || i >= hi || j < lo || j >= hi) continue;
-        A[(size_t)(i - lo) * m + (j - lo)] = bandA[d][(size_t)i * W + o];
-        M[(size_t)(i - lo) * m + (j - lo)] = bandM[d][(size_t)i * W + o];
+        A[(size_t)(i - lo) * m + (j - lo)] += bandA[d][(size_t)i * W + o];
+        M[(size_t)(i - lo) * m + (j - lo)] += bandM[d][(size_t)i * W + o];
       }
     // an axis with the same 1D problem as an earlier one reuses its decomposition
     int same = -1;
     for (int e = 0; e < d && same < 0; ++e)
-      if (f.lo[e] == lo && f.m[e] == m && pb.n[e] == n && bandM[e] == bandM[d] && bandA[e] == bandA[d]) same = e;
+      if (f.lo[e] == lo && f.m[e] == m && pb.n[e] == n && pb.ax[e].nper == pb.ax[d].nper && bandM[e] == bandM[d] &&
+          bandA[e] == bandA[d])
+        same = e;
     std::vector<double> V, mu;
     if (same >= 0) {
       V = hostV[same];
