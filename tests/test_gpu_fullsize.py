@@ -1,0 +1,151 @@
+"""Parity at the benchmark's full sizes, in the launch configurations bench.py times, on outputs the
+oracle computes row by row from the same seeded inputs.
+
+* 3D Bratu 64^3, p = 3 (the benchmark workload): the whole CSR pattern, and sampled rows of the
+  residual, the Jacobian (the default separable row-gather, FP64 and FP32 values, and the local
+  numerical-differentiation Jacobian), the index-free SpMV and the matrix-free apply.
+* The quarter cylinder 48^3, p = 2, 3, 4 (general row-gather, NURBS geometry, nodal kappa): sampled
+  residual and Jacobian rows.
+* 64^3, p = 3 with x periodic: the whole pattern and sampled rows.
+* The 512 uneven 2D instances solved as one batch: sampled instances against the oracle's Newton.
+
+Sampled rows cover every face, edge and corner class (the Dirichlet rows, the rows next to them and
+interior rows) plus random rows.  Bars as in the other parity tests: identical pattern, 1e-12 relative
+(norm over the sampled entries) for FP64 values, 1e-5 for FP32 values, 1e-7 for the local
+numerical-differentiation Jacobian against the exact one, 1e-9 for batched solutions."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1305_4452_amd as iga  # noqa: E402
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def sample_rows(shape, n_random, seed):
+    """Rows of every boundary class of a tensor grid (indices 0, 1, 2, middle, n-3, n-2, n-1 per
+    axis, all combinations) plus random rows; natural order, axis 0 fastest."""
+    picks = [sorted({0, 1, 2, n // 2, n - 3, n - 2, n - 1}) for n in shape]
+    grid = np.stack(np.meshgrid(*picks, indexing="ij"), -1).reshape(-1, len(shape))
+    rng = np.random.default_rng(seed)
+    rnd = np.stack([rng.integers(0, n, n_random) for n in shape], -1)
+    ids = np.concatenate([grid, rnd])
+    strides = np.cumprod([1] + list(shape[:-1]))
+    return np.unique((ids * strides).sum(axis=1)).astype(np.int64)
+
+
+def gather_rows(vals, rp, rows):
+    return np.concatenate([vals[rp[r]:rp[r + 1]] for r in rows])
+
+
+def check_pattern(g, o):
+    rp, ci = g.csr_pattern()
+    orp, oci = o.pattern()
+    assert np.array_equal(host(rp), orp)
+    assert np.array_equal(host(ci), oci)
+    return orp, oci
+
+
+def test_bratu3d_64_p3_benchmark_workload():
+    print("[case] full size: 3D Bratu 64^3 p=3", flush=True)
+    w = inputs.config_3d_bratu()
+    g = iga.IGA.from_workload(w)
+    o = oracle.Oracle.from_workload(w)
+    orp, oci = check_pattern(g, o)
+    rows = sample_rows(w.patch.shape, 120, 1)
+    U = torch.as_tensor(w.U0, device="cuda")
+    R = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    g.assemble_residual(U, R)
+    assert rel(host(R)[rows], o.residual_rows(w.U0, rows)) < 1e-12
+    ref = o.jacobian_rows(w.U0, rows, orp, oci)
+    vals = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+    g.assemble_jacobian(U, vals)                      # default: the separable row-gather
+    v64 = host(vals)
+    assert rel(gather_rows(v64, orp, rows), ref) < 1e-12
+    vals32 = torch.empty(g.nnz, dtype=torch.float32, device="cuda")
+    g.assemble_jacobian(U, vals32, iga.IGA_FP32)
+    assert rel(gather_rows(host(vals32), orp, rows), ref) < 1e-5
+    del vals32
+    # SpMV and the matrix-free apply on a seeded vector: rows of the oracle's own values times x
+    x = inputs.uniform(12, 7, g.N, -1.0, 1.0)
+    yref = np.array([np.dot(o.jacobian_rows(w.U0, [r], orp, oci), x[oci[orp[r]:orp[r + 1]]]) for r in rows[:60]])
+    y = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    g.spmv(vals, torch.as_tensor(x, device="cuda"), y)
+    assert rel(host(y)[rows[:60]], yref) < 1e-12
+    g.apply(U, torch.as_tensor(x, device="cuda"), y)
+    assert rel(host(y)[rows[:60]], yref) < 1e-12
+    # local numerical differentiation on the same workload
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_LOCAL_ND)
+    g.assemble_jacobian(U, vals)
+    assert rel(gather_rows(host(vals), orp, rows[:40]), o.jacobian_rows(w.U0, rows[:40], orp, oci)) < 1e-7
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_quarter_cylinder_48_benchmark_workload(p):
+    print(f"[case] full size: quarter cylinder 48^3 p={p}", flush=True)
+    w = inputs.config_cylinder(nel=48, p=p)
+    g = iga.IGA.from_workload(w)
+    o = oracle.Oracle.from_workload(w)
+    orp, oci = check_pattern(g, o)
+    rows = sample_rows(w.patch.shape, 40, 2 + p)
+    U = torch.as_tensor(w.U0, device="cuda")
+    R = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    g.assemble_residual(U, R)
+    assert rel(host(R)[rows], o.residual_rows(w.U0, rows)) < 1e-12
+    vals = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+    g.assemble_jacobian(U, vals)
+    assert rel(gather_rows(host(vals), orp, rows), o.jacobian_rows(w.U0, rows, orp, oci)) < 1e-12
+
+
+def test_periodic_64_p3_benchmark_workload():
+    print("[case] full size: 64^3 p=3, x periodic", flush=True)
+    p = 3
+    patch = inputs.unit_box(3, 64, p)
+    per = [p - 1, None, None]
+    g = iga.IGA(patch.knots, patch.degree, lam=5.0, periodic=per)
+    o = oracle.Oracle(patch.knots, patch.degree, lam=5.0, periodic=per)
+    orp, oci = check_pattern(g, o)
+    U0 = inputs.uniform(2, 0, g.N, 0.0, 0.1)
+    shape = [64 + p - 1 - (p - 1), 64 + p, 64 + p]
+    assert int(np.prod(shape)) == g.N
+    rows = sample_rows(shape, 60, 9)
+    U = torch.as_tensor(U0, device="cuda")
+    R = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    g.assemble_residual(U, R)
+    assert rel(host(R)[rows], o.residual_rows(U0, rows)) < 1e-12
+    vals = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+    g.assemble_jacobian(U, vals)
+    assert rel(gather_rows(host(vals), orp, rows), o.jacobian_rows(U0, rows, orp, oci)) < 1e-12
+
+
+def test_batched_512_benchmark_workload():
+    print("[case] full size: 512 batched 2D instances", flush=True)
+    ws = inputs.batched_instances(512)
+    b = iga.IGABatch(ws)
+    U = torch.as_tensor(b.pack([w.U0 for w in ws]), device="cuda")
+    # the benchmark stops at ||R|| < 1e-10; a tighter stop makes the solution error (||J^-1|| ||R||,
+    # up to ~2e-9 relative on the stiffest small instances at 1e-10) small against the bar
+    per, summ = b.newton_solve(U, atol=1e-12)
+    assert summ["all_converged"]
+    sols = b.unpack(host(U))
+    sizes = np.array([w.patch.ndof for w in ws])
+    order = np.argsort(sizes)
+    picks = list(order[:5]) + [int(order[len(order) // 4])]
+    for i in picks:
+        oi = oracle.Oracle.from_workload(ws[i])
+        ref, _, rc = oi.newton(ws[i].U0, atol=1e-13)
+        assert rc == 0
+        assert rel(sols[i], ref) < 1e-9, i
