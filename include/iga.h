@@ -74,9 +74,11 @@ typedef enum {
   IGA_OPT_KERNEL_TIMING = 5, /* 1: record a HIP event pair around each kernel of iga_assemble_jacobian
                                 (read back with iga_kernel_times); 0: off (default) */
   IGA_OPT_PRECOND = 6,       /* CG preconditioner of iga_newton_solve: iga_precond */
-  IGA_OPT_ND_SCATTER = 7     /* IGA_JAC_LOCAL_ND: 0 FP64 atomics in one launch (default), 1 colour
+  IGA_OPT_ND_SCATTER = 7,    /* IGA_JAC_LOCAL_ND: 0 FP64 atomics in one launch (default), 1 colour
                                 by colour with plain adds ((p+1)^d launches, no two workgroups of a
                                 launch share a value) */
+  IGA_OPT_TILED_3D = 8       /* 3D residual and matrix-free apply with x = xi, no weights, no source:
+                                1 by tiles of elements (default), 0 one element per workgroup */
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):

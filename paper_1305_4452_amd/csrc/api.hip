@@ -268,6 +268,10 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
       h->kt_calls = 0;   // (re)starts the averaging window
       h->kt_n = 0;
       return IGA_OK;
+    case IGA_OPT_TILED_3D:
+      if (value != 0 && value != 1) return fail(IGA_EINVAL, "IGA_OPT_TILED_3D is 0 or 1");
+      h->tiled_3d = (int)value;
+      return IGA_OK;
     case IGA_OPT_ND_SCATTER:
       if (value != 0 && value != 1) return fail(IGA_EINVAL, "IGA_OPT_ND_SCATTER is 0 or 1");
       h->nd_color = (int)value;

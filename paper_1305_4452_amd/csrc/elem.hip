@@ -711,6 +711,7 @@ iga_status launch_residual(Handle &h, const double *U, double *R) {
   iga_status st = launch_fill(h, R, h.pb.N, 0.0);
   if (st) return st;
   if (res2_supported(h.pb)) st = launch_res2(h, U, R);
+  else if (res3_supported(h.pb) && h.tiled_3d) st = launch_res3(h, U, R, 0);
   else st = dispatch_dpt<RunRes>(h, U, R);
   if (st) return st;
   hipLaunchKernelGGL(k_bc_copy, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb, U, R);
@@ -728,7 +729,9 @@ iga_status launch_linearize(Handle &h, const double *U) {
 iga_status launch_apply(Handle &h, const double *v, double *y) {
   iga_status st = launch_fill(h, y, h.pb.N, 0.0);
   if (st) return st;
-  if ((st = dispatch_dpt<RunApply>(h, v, y))) return st;
+  if (res3_supported(h.pb) && h.tiled_3d) st = launch_res3(h, v, y, 1);
+  else st = dispatch_dpt<RunApply>(h, v, y);
+  if (st) return st;
   hipLaunchKernelGGL(k_bc_copy, dim3(blocks_for(h.pb.N, 256)), dim3(256), 0, h.stream, h.pb, v, y);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;

@@ -146,6 +146,7 @@ struct Handle {
   // options
   int jac_algo = IGA_JAC_AUTO;
   int nd_color = 0;   // local-ND scatter: 0 atomics (default), 1 colour-ordered plain adds
+  int tiled_3d = 1;   // 3D residual / apply by element tiles where supported (0: one element per workgroup)
   int row_b1 = 0, row_b2 = 0;
   int row_segments = 0;           // separable row-gather: segments along axis 0 (0 = planned)
   // separable row-gather tables (3D, identity geometry, kappa = 1, simple knots)
@@ -232,6 +233,8 @@ iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, in
 iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec, int color_mode);
 bool rgt2_supported(const DevProblem &pb);
 bool res2_supported(const DevProblem &pb);
+bool res3_supported(const DevProblem &pb);
+iga_status launch_res3(Handle &h, const double *X, double *Y, int apply);
 iga_status launch_res2(Handle &h, const double *U, double *R);
 iga_status launch_jac_rgt2(Handle &h, const double *U, void *vals, int prec);
 bool rgsep_supported(const Handle &h, int b1, int b2);

@@ -1,0 +1,201 @@
+// Tiled 3D residual and matrix-free Jacobian apply for the identity map (no weights, kappa one or
+// element-wise, every interior knot simple, no source term).
+//
+// A workgroup owns TE^3 elements.  Over the whole tile, sum factorisation takes the coefficients
+// of the tile's (TE + p)^3 functions to the value and gradient at its (TE Q)^3 Gauss points (three
+// 1D contractions), forms the point flux F and source S of the weak form (Sec. 3):
+//   residual: F = kappa W grad u, S = -lambda W e^u;
+//   apply:    F = kappa W grad v, S = m v with m = -lambda W e^u cached per point (OP_LIN),
+// and the three transposed contractions give the tile's contribution to each of its functions,
+//   R_A += sum_g F . grad N_A + S N_A,
+// added to the output with one FP64 atomic per function (border functions are shared with the
+// neighbouring tiles).  The output must be zeroed before and the Dirichlet rows set afterwards, as
+// for the element-by-element kernel; for the apply, Dirichlet coefficients of v count as zero.
+#pragma once
+
+#include "iga_impl.h"
+
+namespace iga {
+namespace rs3 {
+
+constexpr int kThreads = 256;
+enum { OP3_RES = 0, OP3_APPLY = 1 };
+
+// elements per tile side (TE Q = 8 or 9 Gauss points per axis: measured at 64^3, larger tiles run one
+// workgroup per CU and lose to the element-by-element kernel) and the LDS plan in doubles:
+// c [NI^3]; A0, D0 [NI^2 G]; U1, U01, U10 [NI G^2] (reused for Y0, Y1, Y2); F0, F1, F2, S [G^3]
+// (A0 / D0 reused for Za / Zb)
+template <int P>
+struct Res3 {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TE = P == 2 ? 4 : P == 3 ? 3 : 2;
+  static constexpr int NI = TE + p, G = TE * Q;
+  static constexpr int n_c = NI * NI * NI, n_a = NI * NI * G, n_u = NI * G * G, n_f = G * G * G;
+  static constexpr size_t total = (size_t)(n_c + 2 * n_a + 3 * n_u + 4 * n_f) * sizeof(double);
+};
+
+__host__ __device__ inline int res3_tiles(int ne0, int ne1, int ne2, int TE) {
+  return ((ne0 + TE - 1) / TE) * ((ne1 + TE - 1) / TE) * ((ne2 + TE - 1) / TE);
+}
+
+template <int P, int OP>
+__device__ inline void res3_body(const DevProblem &pb, const int tile, const double *__restrict__ X,
+                                 const double *__restrict__ lin, double *__restrict__ Y, double *__restrict__ lds) {
+  using S_ = Res3<P>;
+  constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G;
+  constexpr int NT = kThreads, L = P * P * P;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
+  const int nt0 = (ne0 + TE - 1) / TE, nt1 = (ne1 + TE - 1) / TE;
+  const int E0 = (tile % nt0) * TE, E1 = ((tile / nt0) % nt1) * TE, E2 = (tile / (nt0 * nt1)) * TE;
+  const int NE0 = min(TE, ne0 - E0), NE1 = min(TE, ne1 - E1), NE2 = min(TE, ne2 - E2);
+  const int G0 = NE0 * Q, G1 = NE1 * Q, G2 = NE2 * Q;
+  const int NI0 = NE0 + p, NI1 = NE1 + p, NI2 = NE2 + p;
+  double *c = lds;                                       // [k2][k1][k0]
+  double *A0 = c + S_::n_c, *D0 = A0 + S_::n_a;          // [k2][k1][g0]
+  double *U1 = D0 + S_::n_a, *U01 = U1 + S_::n_u, *U10 = U01 + S_::n_u;   // [k2][g1][g0]
+  double *F0 = U10 + S_::n_u, *F1 = F0 + S_::n_f, *F2 = F1 + S_::n_f, *Sg = F2 + S_::n_f;   // [g2][g1][g0]
+  double *Y0 = U1, *Y1 = U01, *Y2 = U10, *Za = A0, *Zb = D0;
+  const int t = threadIdx.x;
+  const double *B0 = pb.ax[0].B, *dB0 = pb.ax[0].dB, *B1 = pb.ax[1].B, *dB1 = pb.ax[1].dB;
+  const double *B2 = pb.ax[2].B, *dB2 = pb.ax[2].dB;
+  const bool kel = pb.kappa_mode == IGA_KAPPA_ELEMENT;
+
+  for (int i = t; i < NI0 * NI1 * NI2; i += NT) {
+    const int k0 = i % NI0, k1 = (i / NI0) % NI1, k2 = i / (NI0 * NI1);
+    const int i0 = E0 + k0, i1 = E1 + k1, i2 = E2 + k2;
+    double x = X[i0 + (int64_t)n0 * (i1 + (int64_t)n1 * i2)];
+    if (OP == OP3_APPLY && is_dirichlet_idx(pb, i0, i1, i2)) x = 0.0;
+    c[(k2 * NI + k1) * NI + k0] = x;
+  }
+  __syncthreads();
+  // axis 0: value and derivative per function pair (k1, k2)
+  for (int i = t; i < NI1 * NI2 * G0; i += NT) {
+    const int g0 = i % G0, k1 = (i / G0) % NI1, k2 = i / (G0 * NI1), el0 = g0 / Q;
+    const size_t o = ((size_t)E0 * Q + g0) * P;
+    const double *cc = c + (k2 * NI + k1) * NI + el0;
+    double a = 0, d = 0;
+#pragma unroll
+    for (int a0 = 0; a0 < P; ++a0) {
+      a += B0[o + a0] * cc[a0];
+      d += dB0[o + a0] * cc[a0];
+    }
+    A0[(k2 * NI + k1) * G + g0] = a;
+    D0[(k2 * NI + k1) * G + g0] = d;
+  }
+  __syncthreads();
+  // axis 1
+  for (int i = t; i < NI2 * G1 * G0; i += NT) {
+    const int g0 = i % G0, g1 = (i / G0) % G1, k2 = i / (G0 * G1), el1 = g1 / Q;
+    const size_t o = ((size_t)E1 * Q + g1) * P;
+    double u = 0, u01 = 0, u10 = 0;
+#pragma unroll
+    for (int a1 = 0; a1 < P; ++a1) {
+      const int r = (k2 * NI + el1 + a1) * G + g0;
+      const double b = B1[o + a1];
+      u += b * A0[r];
+      u01 += b * D0[r];
+      u10 += dB1[o + a1] * A0[r];
+    }
+    const int w = (k2 * G + g1) * G + g0;
+    U1[w] = u;
+    U01[w] = u01;
+    U10[w] = u10;
+  }
+  __syncthreads();
+  // axis 2 and the point integrands
+  {
+    const double lam = pb.lambda;
+    for (int i = t; i < G2 * G1 * G0; i += NT) {
+      const int g0 = i % G0, g1 = (i / G0) % G1, g2 = i / (G0 * G1), el2 = g2 / Q;
+      const size_t o = ((size_t)E2 * Q + g2) * P;
+      double u = 0, d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+      for (int a2 = 0; a2 < P; ++a2) {
+        const int r = ((el2 + a2) * G + g1) * G + g0;
+        const double b = B2[o + a2];
+        u += b * U1[r];
+        d0 += b * U01[r];
+        d1 += b * U10[r];
+        d2 += dB2[o + a2] * U1[r];
+      }
+      const int el0 = g0 / Q, el1 = g1 / Q;
+      const double W = pb.ax[0].wq[(size_t)E0 * Q + g0] * pb.ax[1].wq[(size_t)E1 * Q + g1] *
+                       pb.ax[2].wq[(size_t)E2 * Q + g2];
+      const int64_t e = (E0 + el0) + (int64_t)ne0 * ((E1 + el1) + (int64_t)ne1 * (E2 + el2));
+      const double kw = (kel ? pb.kel[e] : 1.0) * W;
+      const int w = (g2 * G + g1) * G + g0;
+      F0[w] = kw * d0;
+      F1[w] = kw * d1;
+      F2[w] = kw * d2;
+      if (OP == OP3_RES) {
+        Sg[w] = -W * lam * exp(u);
+      } else {
+        const int q = (g0 % Q) + Q * ((g1 % Q) + Q * (g2 % Q));
+        Sg[w] = lin[e * L + q] * u;
+      }
+    }
+  }
+  __syncthreads();
+  // transposed axis 2: Y0 = sum B2 F0, Y1 = sum B2 F1, Y2 = sum dB2 F2 + B2 S
+  for (int i = t; i < NI2 * G1 * G0; i += NT) {
+    const int g0 = i % G0, g1 = (i / G0) % G1, k2 = i / (G0 * G1);
+    double y0 = 0, y1 = 0, y2 = 0;
+    for (int a2 = 0; a2 <= p; ++a2) {
+      const int el2 = k2 - a2;
+      if (el2 < 0 || el2 >= NE2) continue;
+#pragma unroll
+      for (int q2 = 0; q2 < Q; ++q2) {
+        const size_t o = ((size_t)(E2 + el2) * Q + q2) * P + a2;
+        const int w = ((el2 * Q + q2) * G + g1) * G + g0;
+        const double b = B2[o];
+        y0 += b * F0[w];
+        y1 += b * F1[w];
+        y2 += dB2[o] * F2[w] + b * Sg[w];
+      }
+    }
+    const int w = (k2 * G + g1) * G + g0;
+    Y0[w] = y0;
+    Y1[w] = y1;
+    Y2[w] = y2;
+  }
+  __syncthreads();
+  // transposed axis 1: Za = sum B1 Y0, Zb = sum dB1 Y1 + B1 Y2
+  for (int i = t; i < NI2 * NI1 * G0; i += NT) {
+    const int g0 = i % G0, k1 = (i / G0) % NI1, k2 = i / (G0 * NI1);
+    double za = 0, zb = 0;
+    for (int a1 = 0; a1 <= p; ++a1) {
+      const int el1 = k1 - a1;
+      if (el1 < 0 || el1 >= NE1) continue;
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1) {
+        const size_t o = ((size_t)(E1 + el1) * Q + q1) * P + a1;
+        const int w = (k2 * G + el1 * Q + q1) * G + g0;
+        const double b = B1[o];
+        za += b * Y0[w];
+        zb += dB1[o] * Y1[w] + b * Y2[w];
+      }
+    }
+    Za[(k2 * NI + k1) * G + g0] = za;
+    Zb[(k2 * NI + k1) * G + g0] = zb;
+  }
+  __syncthreads();
+  // transposed axis 0 and the scatter of the tile's contributions
+  for (int i = t; i < NI0 * NI1 * NI2; i += NT) {
+    const int k0 = i % NI0, k1 = (i / NI0) % NI1, k2 = i / (NI0 * NI1);
+    double r = 0;
+    for (int a0 = 0; a0 <= p; ++a0) {
+      const int el0 = k0 - a0;
+      if (el0 < 0 || el0 >= NE0) continue;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) {
+        const size_t o = ((size_t)(E0 + el0) * Q + q0) * P + a0;
+        const int w = (k2 * NI + k1) * G + el0 * Q + q0;
+        r += dB0[o] * Za[w] + B0[o] * Zb[w];
+      }
+    }
+    atomicAdd(&Y[(E0 + k0) + (int64_t)n0 * ((E1 + k1) + (int64_t)n1 * (E2 + k2))], r);
+  }
+}
+
+}  // namespace rs3
+}  // namespace iga

@@ -2,6 +2,7 @@
 // rows, and the residual, one workgroup per TE x TE tile of elements; the bodies are shared with
 // the batched solver.
 #include "kern_res2.h"
+#include "kern_res3.h"
 #include "kern_rgt2.h"
 
 namespace iga {
@@ -43,7 +44,45 @@ iga_status run_res2(Handle &h, const double *U, double *R) {
   return IGA_OK;
 }
 
+template <int P, int OP>
+__global__ void __launch_bounds__(rs3::kThreads) k_res3(DevProblem pb, const double *__restrict__ X,
+                                                        const double *__restrict__ lin, double *__restrict__ Y) {
+  __shared__ double lds[rs3::Res3<P>::total / sizeof(double)];
+  rs3::res3_body<P, OP>(pb, (int)blockIdx.x, X, lin, Y, lds);
+}
+
+template <int P>
+iga_status run_res3(Handle &h, const double *X, double *Y, int op) {
+  const unsigned nb = (unsigned)rs3::res3_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], rs3::Res3<P>::TE);
+  if (op == rs3::OP3_APPLY)
+    hipLaunchKernelGGL((k_res3<P, rs3::OP3_APPLY>), dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                       (const double *)h.lin, Y);
+  else
+    hipLaunchKernelGGL((k_res3<P, rs3::OP3_RES>), dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                       (const double *)nullptr, Y);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
 }  // namespace
+
+bool res3_supported(const DevProblem &pb) {
+  // p <= 3: at p = 4 the element-by-element kernel measured faster (0.97 against 1.03 ms at 64^3)
+  return pb.dim == 3 && !pb.table && !pb.rational && pb.simple_knots && !pb.periodic && !pb.src && pb.P >= 2 &&
+         pb.P <= 4 && (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
+}
+
+// residual (apply = 0) or matrix-free Jacobian apply (apply = 1, needs the OP_LIN point cache)
+iga_status launch_res3(Handle &h, const double *X, double *Y, int apply) {
+  const int op = apply ? rs3::OP3_APPLY : rs3::OP3_RES;
+  switch (h.pb.P) {
+    case 2: return run_res3<2>(h, X, Y, op);
+    case 3: return run_res3<3>(h, X, Y, op);
+    case 4: return run_res3<4>(h, X, Y, op);
+    case 5: return run_res3<5>(h, X, Y, op);
+  }
+  return fail(IGA_EUNSUPPORTED, "tiled 3D residual degree");
+}
 
 bool res2_supported(const DevProblem &pb) {
   return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && !pb.periodic && pb.P >= 2 && pb.P <= 5 &&
