@@ -193,16 +193,18 @@ def bench_periodic(nel: int = 64, p: int = 3):
         torch.cuda.synchronize()
         res[key] = a.elapsed_time(b) / 3
     del vals
-    Ux = U.clone()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    rep = g.newton_solve(Ux, atol=0.0, rtol=1e-10, max_krylov=20000, raise_on_fail=False)
-    torch.cuda.synchronize()
-    res["newton"] = dict(time_s=time.perf_counter() - t, converged=bool(rep["converged"]),
-                         newton_iters=rep["newton_iters"], krylov_iters=rep["krylov_iters_total"],
-                         rel_residual=rep["res_norm"] / rep["res_norm0"] if rep["res_norm0"] else 0.0)
+    for key, mf in (("newton", False), ("newton_matrix_free", True)):
+        Ux = U.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rep = g.newton_solve(Ux, atol=0.0, rtol=1e-10, max_krylov=20000, matrix_free=mf, raise_on_fail=False)
+        torch.cuda.synchronize()
+        res[key] = dict(time_s=time.perf_counter() - t, converged=bool(rep["converged"]),
+                        newton_iters=rep["newton_iters"], krylov_iters=rep["krylov_iters_total"],
+                        rel_residual=rep["res_norm"] / rep["res_norm0"] if rep["res_norm0"] else 0.0)
     print(f"[bench] periodic {nel}^3 p={p}: residual {res['residual_ms']:.2f} ms, jacobian {res['jacobian_ms']:.2f} ms, "
-          f"newton {res['newton']['time_s']:.3f} s ({res['newton']['krylov_iters']} CG its)", file=sys.stderr, flush=True)
+          f"newton {res['newton']['time_s']:.3f} s ({res['newton']['krylov_iters']} CG its), matrix-free "
+          f"{res['newton_matrix_free']['time_s']:.3f} s", file=sys.stderr, flush=True)
     return res
 
 

@@ -1,6 +1,6 @@
 // Tiled 2D residual for the analytic metric (identity geometry, no weights, kappa one or
-// element-wise; every interior knot simple, so element e carries functions e .. e + p).  Shared
-// by the single-problem and batched launchers.
+// element-wise; every interior knot simple, so element e carries functions e .. e + p, wrapped on a
+// periodic axis).  Shared by the single-problem and batched launchers.
 //
 // A workgroup owns TE x TE elements.  The weak-form residual of Sec. 3,
 //   R_A = sum_g [ kappa W grad N_A . grad u  -  W N_A (lambda e^u + f) ],
@@ -56,7 +56,7 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
 
   for (int i = t; i < NI0 * NI1; i += kThreads) {
     const int k0 = i % NI0, k1 = i / NI0;
-    const int64_t A = (f0 + k0) + (int64_t)n0 * (f1 + k1);
+    const int64_t A = wrap_fn(pb.ax[0], f0 + k0) + (int64_t)n0 * wrap_fn(pb.ax[1], f1 + k1);   // eq:map-wrap
     sU[k1 * NI + k0] = U[A];
     if (src) sF[k1 * NI + k0] = pb.src[A];
   }
@@ -136,7 +136,7 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
         r += Ya[k1 * G + g0] * pb.ax[0].dB[o] + Yb[k1 * G + g0] * pb.ax[0].B[o];
       }
     }
-    atomicAdd(&R[(f0 + k0) + (int64_t)n0 * (f1 + k1)], r);
+    atomicAdd(&R[wrap_fn(pb.ax[0], f0 + k0) + (int64_t)n0 * wrap_fn(pb.ax[1], f1 + k1)], r);
   }
 }
 

@@ -1,5 +1,5 @@
 // Tiled 3D residual and matrix-free Jacobian apply for the identity map (no weights, kappa one or
-// element-wise, every interior knot simple, no source term).
+// element-wise, every interior knot simple, no source term; periodic axes wrap their indices).
 //
 // A workgroup owns TE^3 elements.  Over the whole tile, sum factorisation takes the coefficients
 // of the tile's (TE + p)^3 functions to the value and gradient at its (TE Q)^3 Gauss points (three
@@ -62,7 +62,8 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
 
   for (int i = t; i < NI0 * NI1 * NI2; i += NT) {
     const int k0 = i % NI0, k1 = (i / NI0) % NI1, k2 = i / (NI0 * NI1);
-    const int i0 = E0 + k0, i1 = E1 + k1, i2 = E2 + k2;
+    // functions past the end of a periodic axis wrap (eq:map-wrap)
+    const int i0 = wrap_fn(pb.ax[0], E0 + k0), i1 = wrap_fn(pb.ax[1], E1 + k1), i2 = wrap_fn(pb.ax[2], E2 + k2);
     double x = X[i0 + (int64_t)n0 * (i1 + (int64_t)n1 * i2)];
     if (OP == OP3_APPLY && is_dirichlet_idx(pb, i0, i1, i2)) x = 0.0;
     c[(k2 * NI + k1) * NI + k0] = x;
@@ -193,7 +194,9 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
         r += dB0[o] * Za[w] + B0[o] * Zb[w];
       }
     }
-    atomicAdd(&Y[(E0 + k0) + (int64_t)n0 * ((E1 + k1) + (int64_t)n1 * (E2 + k2))], r);
+    atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
+                 (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], E2 + k2))],
+              r);
   }
 }
 

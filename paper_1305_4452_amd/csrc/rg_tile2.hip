@@ -68,8 +68,8 @@ iga_status run_res3(Handle &h, const double *X, double *Y, int op) {
 
 bool res3_supported(const DevProblem &pb) {
   // p <= 3: at p = 4 the element-by-element kernel measured faster (0.97 against 1.03 ms at 64^3)
-  return pb.dim == 3 && !pb.table && !pb.rational && pb.simple_knots && !pb.periodic && !pb.src && pb.P >= 2 &&
-         pb.P <= 4 && (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
+  return pb.dim == 3 && !pb.table && !pb.rational && pb.simple_knots && !pb.src && pb.P >= 2 && pb.P <= 4 &&
+         (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
 }
 
 // residual (apply = 0) or matrix-free Jacobian apply (apply = 1, needs the OP_LIN point cache)
@@ -85,7 +85,7 @@ iga_status launch_res3(Handle &h, const double *X, double *Y, int apply) {
 }
 
 bool res2_supported(const DevProblem &pb) {
-  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && !pb.periodic && pb.P >= 2 && pb.P <= 5 &&
+  return pb.dim == 2 && !pb.table && !pb.rational && pb.simple_knots && pb.P >= 2 && pb.P <= 5 &&
          (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
 }
 

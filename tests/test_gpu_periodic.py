@@ -22,6 +22,8 @@ CASES = {
     "per2_p2_full": (2, [8, 9], 2, [1, 0], 1.0, False),
     "per3_p2_xz": (3, [7, 6, 7], 2, [1, None, 0], 2.5, False),   # y-only Dirichlet: 1D-like fold near 3.5
     "per3_p3_c2_x": (3, [8, 5, 6], 3, [2, None, None], 3.0, False),
+    # three functions per periodic axis: a residual tile covers the axis and wraps onto itself
+    "per3_p1_tiny": (3, [3, 3, 5], 1, [0, 0, None], 1.0, False),
 }
 
 
