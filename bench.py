@@ -332,6 +332,8 @@ def main():
         y = torch.empty_like(x)
         for _ in range(3):
             g.spmv(vals, x, y)
+        for _ in range(3):
+            g.apply(U, x, y)
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
         b = torch.empty_like(a)
         for _ in range(3):
