@@ -24,26 +24,30 @@ enum { OP3_RES = 0, OP3_APPLY = 1 };
 // elements per tile side (TE Q = 8 or 9 Gauss points per axis: measured at 64^3, larger tiles run one
 // workgroup per CU and lose to the element-by-element kernel) and the LDS plan in doubles:
 // c [NI^3]; A0, D0 [NI^2 G]; U1, U01, U10 [NI G^2] (reused for Y0, Y1, Y2); F0, F1, F2, S [G^3]
-// (A0 / D0 reused for Za / Zb)
+// (A0 / D0 reused for Za / Zb); the tile's basis values and derivatives [axis][B|dB][G][P] and
+// quadrature weights [axis][G].
 template <int P>
 struct Res3 {
   static constexpr int p = P - 1, Q = P;
   static constexpr int TE = P == 2 ? 4 : P == 3 ? 3 : 2;
   static constexpr int NI = TE + p, G = TE * Q;
   static constexpr int n_c = NI * NI * NI, n_a = NI * NI * G, n_u = NI * G * G, n_f = G * G * G;
-  static constexpr size_t total = (size_t)(n_c + 2 * n_a + 3 * n_u + 4 * n_f) * sizeof(double);
+  static constexpr int n_b = 6 * G * P + 3 * G;
+  static constexpr size_t total = (size_t)(n_c + 2 * n_a + 3 * n_u + 4 * n_f + n_b) * sizeof(double);
 };
 
 __host__ __device__ inline int res3_tiles(int ne0, int ne1, int ne2, int TE) {
   return ((ne0 + TE - 1) / TE) * ((ne1 + TE - 1) / TE) * ((ne2 + TE - 1) / TE);
 }
 
+// Every stage runs over the full tile extents (compile-time strides); a tile cut by the end of the
+// mesh skips the entries past its NE_d elements.
 template <int P, int OP>
 __device__ inline void res3_body(const DevProblem &pb, const int tile, const double *__restrict__ X,
                                  const double *__restrict__ lin, double *__restrict__ Y, double *__restrict__ lds) {
   using S_ = Res3<P>;
   constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G;
-  constexpr int NT = kThreads, L = P * P * P;
+  constexpr int NT = kThreads, L = P * P * P, GP = G * P;
   const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
   const int nt0 = (ne0 + TE - 1) / TE, nt1 = (ne1 + TE - 1) / TE;
   const int E0 = (tile % nt0) * TE, E1 = ((tile / nt0) % nt1) * TE, E2 = (tile / (nt0 * nt1)) * TE;
@@ -55,143 +59,159 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
   double *U1 = D0 + S_::n_a, *U01 = U1 + S_::n_u, *U10 = U01 + S_::n_u;   // [k2][g1][g0]
   double *F0 = U10 + S_::n_u, *F1 = F0 + S_::n_f, *F2 = F1 + S_::n_f, *Sg = F2 + S_::n_f;   // [g2][g1][g0]
   double *Y0 = U1, *Y1 = U01, *Y2 = U10, *Za = A0, *Zb = D0;
+  double *sB = Sg + S_::n_f, *sW = sB + 6 * GP;
+  const double *B0 = sB, *dB0 = sB + GP, *B1 = sB + 2 * GP, *dB1 = sB + 3 * GP, *B2 = sB + 4 * GP,
+               *dB2 = sB + 5 * GP;
+  const double *W0 = sW, *W1 = sW + G, *W2 = sW + 2 * G;
   const int t = threadIdx.x;
-  const double *B0 = pb.ax[0].B, *dB0 = pb.ax[0].dB, *B1 = pb.ax[1].B, *dB1 = pb.ax[1].dB;
-  const double *B2 = pb.ax[2].B, *dB2 = pb.ax[2].dB;
   const bool kel = pb.kappa_mode == IGA_KAPPA_ELEMENT;
 
-  for (int i = t; i < NI0 * NI1 * NI2; i += NT) {
-    const int k0 = i % NI0, k1 = (i / NI0) % NI1, k2 = i / (NI0 * NI1);
+  // the tile's rows of the basis tables (point g of axis d is global point E_d Q + g)
+  auto stage_axis = [&](const AxisDev &ax, int E, int Gd, double *dst, double *wdst) {
+    for (int i = t; i < GP; i += NT) {
+      if (i / P < Gd) {
+        dst[i] = ax.B[(size_t)E * Q * P + i];
+        dst[GP + i] = ax.dB[(size_t)E * Q * P + i];
+      }
+    }
+    for (int i = t; i < G; i += NT)
+      if (i < Gd) wdst[i] = ax.wq[(size_t)E * Q + i];
+  };
+  stage_axis(pb.ax[0], E0, G0, sB, sW);
+  stage_axis(pb.ax[1], E1, G1, sB + 2 * GP, sW + G);
+  stage_axis(pb.ax[2], E2, G2, sB + 4 * GP, sW + 2 * G);
+  for (int i = t; i < NI * NI * NI; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
     // functions past the end of a periodic axis wrap (eq:map-wrap)
     const int i0 = wrap_fn(pb.ax[0], E0 + k0), i1 = wrap_fn(pb.ax[1], E1 + k1), i2 = wrap_fn(pb.ax[2], E2 + k2);
     double x = X[i0 + (int64_t)n0 * (i1 + (int64_t)n1 * i2)];
     if (OP == OP3_APPLY && is_dirichlet_idx(pb, i0, i1, i2)) x = 0.0;
-    c[(k2 * NI + k1) * NI + k0] = x;
+    c[i] = x;
   }
   __syncthreads();
   // axis 0: value and derivative per function pair (k1, k2)
-  for (int i = t; i < NI1 * NI2 * G0; i += NT) {
-    const int g0 = i % G0, k1 = (i / G0) % NI1, k2 = i / (G0 * NI1), el0 = g0 / Q;
-    const size_t o = ((size_t)E0 * Q + g0) * P;
+  for (int i = t; i < NI * NI * G; i += NT) {
+    const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), el0 = g0 / Q;
+    if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
     const double *cc = c + (k2 * NI + k1) * NI + el0;
     double a = 0, d = 0;
 #pragma unroll
     for (int a0 = 0; a0 < P; ++a0) {
-      a += B0[o + a0] * cc[a0];
-      d += dB0[o + a0] * cc[a0];
+      a += B0[g0 * P + a0] * cc[a0];
+      d += dB0[g0 * P + a0] * cc[a0];
     }
-    A0[(k2 * NI + k1) * G + g0] = a;
-    D0[(k2 * NI + k1) * G + g0] = d;
+    A0[i] = a;
+    D0[i] = d;
   }
   __syncthreads();
   // axis 1
-  for (int i = t; i < NI2 * G1 * G0; i += NT) {
-    const int g0 = i % G0, g1 = (i / G0) % G1, k2 = i / (G0 * G1), el1 = g1 / Q;
-    const size_t o = ((size_t)E1 * Q + g1) * P;
+  for (int i = t; i < NI * G * G; i += NT) {
+    const int g0 = i % G, g1 = (i / G) % G, k2 = i / (G * G), el1 = g1 / Q;
+    if (g0 >= G0 || g1 >= G1 || k2 >= NI2) continue;
     double u = 0, u01 = 0, u10 = 0;
 #pragma unroll
     for (int a1 = 0; a1 < P; ++a1) {
       const int r = (k2 * NI + el1 + a1) * G + g0;
-      const double b = B1[o + a1];
+      const double b = B1[g1 * P + a1];
       u += b * A0[r];
       u01 += b * D0[r];
-      u10 += dB1[o + a1] * A0[r];
+      u10 += dB1[g1 * P + a1] * A0[r];
     }
-    const int w = (k2 * G + g1) * G + g0;
-    U1[w] = u;
-    U01[w] = u01;
-    U10[w] = u10;
+    U1[i] = u;
+    U01[i] = u01;
+    U10[i] = u10;
   }
   __syncthreads();
   // axis 2 and the point integrands
   {
     const double lam = pb.lambda;
-    for (int i = t; i < G2 * G1 * G0; i += NT) {
-      const int g0 = i % G0, g1 = (i / G0) % G1, g2 = i / (G0 * G1), el2 = g2 / Q;
-      const size_t o = ((size_t)E2 * Q + g2) * P;
+    for (int i = t; i < G * G * G; i += NT) {
+      const int g0 = i % G, g1 = (i / G) % G, g2 = i / (G * G), el2 = g2 / Q;
+      if (g0 >= G0 || g1 >= G1 || g2 >= G2) continue;
       double u = 0, d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
       for (int a2 = 0; a2 < P; ++a2) {
         const int r = ((el2 + a2) * G + g1) * G + g0;
-        const double b = B2[o + a2];
+        const double b = B2[g2 * P + a2];
         u += b * U1[r];
         d0 += b * U01[r];
         d1 += b * U10[r];
-        d2 += dB2[o + a2] * U1[r];
+        d2 += dB2[g2 * P + a2] * U1[r];
       }
       const int el0 = g0 / Q, el1 = g1 / Q;
-      const double W = pb.ax[0].wq[(size_t)E0 * Q + g0] * pb.ax[1].wq[(size_t)E1 * Q + g1] *
-                       pb.ax[2].wq[(size_t)E2 * Q + g2];
+      const double W = W0[g0] * W1[g1] * W2[g2];
       const int64_t e = (E0 + el0) + (int64_t)ne0 * ((E1 + el1) + (int64_t)ne1 * (E2 + el2));
       const double kw = (kel ? pb.kel[e] : 1.0) * W;
-      const int w = (g2 * G + g1) * G + g0;
-      F0[w] = kw * d0;
-      F1[w] = kw * d1;
-      F2[w] = kw * d2;
+      F0[i] = kw * d0;
+      F1[i] = kw * d1;
+      F2[i] = kw * d2;
       if (OP == OP3_RES) {
-        Sg[w] = -W * lam * exp(u);
+        Sg[i] = -W * lam * exp(u);
       } else {
         const int q = (g0 % Q) + Q * ((g1 % Q) + Q * (g2 % Q));
-        Sg[w] = lin[e * L + q] * u;
+        Sg[i] = lin[e * L + q] * u;
       }
     }
   }
   __syncthreads();
   // transposed axis 2: Y0 = sum B2 F0, Y1 = sum B2 F1, Y2 = sum dB2 F2 + B2 S
-  for (int i = t; i < NI2 * G1 * G0; i += NT) {
-    const int g0 = i % G0, g1 = (i / G0) % G1, k2 = i / (G0 * G1);
+  for (int i = t; i < NI * G * G; i += NT) {
+    const int g0 = i % G, g1 = (i / G) % G, k2 = i / (G * G);
+    if (g0 >= G0 || g1 >= G1 || k2 >= NI2) continue;
     double y0 = 0, y1 = 0, y2 = 0;
+#pragma unroll
     for (int a2 = 0; a2 <= p; ++a2) {
       const int el2 = k2 - a2;
       if (el2 < 0 || el2 >= NE2) continue;
 #pragma unroll
       for (int q2 = 0; q2 < Q; ++q2) {
-        const size_t o = ((size_t)(E2 + el2) * Q + q2) * P + a2;
-        const int w = ((el2 * Q + q2) * G + g1) * G + g0;
-        const double b = B2[o];
+        const int g2 = el2 * Q + q2, w = (g2 * G + g1) * G + g0;
+        const double b = B2[g2 * P + a2];
         y0 += b * F0[w];
         y1 += b * F1[w];
-        y2 += dB2[o] * F2[w] + b * Sg[w];
+        y2 += dB2[g2 * P + a2] * F2[w] + b * Sg[w];
       }
     }
-    const int w = (k2 * G + g1) * G + g0;
-    Y0[w] = y0;
-    Y1[w] = y1;
-    Y2[w] = y2;
+    Y0[i] = y0;
+    Y1[i] = y1;
+    Y2[i] = y2;
   }
   __syncthreads();
   // transposed axis 1: Za = sum B1 Y0, Zb = sum dB1 Y1 + B1 Y2
-  for (int i = t; i < NI2 * NI1 * G0; i += NT) {
-    const int g0 = i % G0, k1 = (i / G0) % NI1, k2 = i / (G0 * NI1);
+  for (int i = t; i < NI * NI * G; i += NT) {
+    const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI);
+    if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
     double za = 0, zb = 0;
+#pragma unroll
     for (int a1 = 0; a1 <= p; ++a1) {
       const int el1 = k1 - a1;
       if (el1 < 0 || el1 >= NE1) continue;
 #pragma unroll
       for (int q1 = 0; q1 < Q; ++q1) {
-        const size_t o = ((size_t)(E1 + el1) * Q + q1) * P + a1;
-        const int w = (k2 * G + el1 * Q + q1) * G + g0;
-        const double b = B1[o];
+        const int g1 = el1 * Q + q1, w = (k2 * G + g1) * G + g0;
+        const double b = B1[g1 * P + a1];
         za += b * Y0[w];
-        zb += dB1[o] * Y1[w] + b * Y2[w];
+        zb += dB1[g1 * P + a1] * Y1[w] + b * Y2[w];
       }
     }
-    Za[(k2 * NI + k1) * G + g0] = za;
-    Zb[(k2 * NI + k1) * G + g0] = zb;
+    Za[i] = za;
+    Zb[i] = zb;
   }
   __syncthreads();
   // transposed axis 0 and the scatter of the tile's contributions
-  for (int i = t; i < NI0 * NI1 * NI2; i += NT) {
-    const int k0 = i % NI0, k1 = (i / NI0) % NI1, k2 = i / (NI0 * NI1);
+  for (int i = t; i < NI * NI * NI; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
     double r = 0;
+#pragma unroll
     for (int a0 = 0; a0 <= p; ++a0) {
       const int el0 = k0 - a0;
       if (el0 < 0 || el0 >= NE0) continue;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) {
-        const size_t o = ((size_t)(E0 + el0) * Q + q0) * P + a0;
-        const int w = (k2 * NI + k1) * G + el0 * Q + q0;
-        r += dB0[o] * Za[w] + B0[o] * Zb[w];
+        const int g0 = el0 * Q + q0, w = (k2 * NI + k1) * G + g0;
+        r += dB0[g0 * P + a0] * Za[w] + B0[g0 * P + a0] * Zb[w];
       }
     }
     atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
