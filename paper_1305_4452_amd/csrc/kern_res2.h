@@ -25,10 +25,15 @@ struct Res2 {
   static constexpr int p = P - 1, Q = P;
   static constexpr int TE = 40 / Q;
   static constexpr int NI = TE + p, G = TE * Q;
-  // doubles: sU, sF [NI][NI]; V, D, VF [NI][G]; F0, F1, S [G][G]
-  static constexpr int n_u = NI * NI, n_v = NI * G, n_f = G * G;
-  static constexpr size_t total = (size_t)(2 * n_u + 3 * n_v + 3 * n_f) * sizeof(double);
+  // doubles: sU, sF [NI][NI]; V, D, VF [NI][G]; F0, F1, S [G][G]; the tile's basis values and
+  // derivatives [axis][B|dB][G][P] and quadrature weights [axis][G]
+  static constexpr int n_u = NI * NI, n_v = NI * G, n_f = G * G, n_b = 4 * G * P + 2 * G;
+  static constexpr size_t total = (size_t)(2 * n_u + 3 * n_v + 3 * n_f + n_b) * sizeof(double);
 };
+
+// i / d for 0 <= i < 2^16 and 1 <= d <= 64 from inv = 1/d in FP32: (i + 1/2) / d lies at least 1/(2d)
+// from an integer, and the two roundings move it by less than 2^16 * 2^-23 / d, so the truncation is exact.
+__device__ inline int small_div(int i, float inv) { return (int)(((float)i + 0.5f) * inv); }
 
 __host__ __device__ inline int res2_tiles(int ne0, int ne1, int TE) {
   return ((ne0 + TE - 1) / TE) * ((ne1 + TE - 1) / TE);
@@ -50,12 +55,27 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
   double *V = sF + S_::n_u, *D = V + S_::n_v, *VF = D + S_::n_v;
   double *F0 = VF + S_::n_v, *F1 = F0 + S_::n_f, *Sg = F1 + S_::n_f;
   double *Ya = V, *Yb = D;   // reused once the point integrands are formed
+  constexpr int GP = G * P;
+  double *sB = Sg + S_::n_f, *sW = sB + 4 * GP;
+  const double *B0 = sB, *dB0 = sB + GP, *B1 = sB + 2 * GP, *dB1 = sB + 3 * GP, *W0 = sW, *W1 = sW + G;
   const int t = threadIdx.x;
   const bool src = pb.src != nullptr;
   const bool kel = pb.kappa_mode == IGA_KAPPA_ELEMENT;
+  const float iNI0 = 1.0f / NI0, iG0 = 1.0f / G0;
 
+  // the tile's rows of the basis tables (point g of axis d is global point E_d Q + g)
+  for (int i = t; i < G0 * P; i += kThreads) {
+    sB[i] = pb.ax[0].B[(size_t)E0 * Q * P + i];
+    sB[GP + i] = pb.ax[0].dB[(size_t)E0 * Q * P + i];
+  }
+  for (int i = t; i < G1 * P; i += kThreads) {
+    sB[2 * GP + i] = pb.ax[1].B[(size_t)E1 * Q * P + i];
+    sB[3 * GP + i] = pb.ax[1].dB[(size_t)E1 * Q * P + i];
+  }
+  for (int i = t; i < G0; i += kThreads) sW[i] = pb.ax[0].wq[(size_t)E0 * Q + i];
+  for (int i = t; i < G1; i += kThreads) sW[G + i] = pb.ax[1].wq[(size_t)E1 * Q + i];
   for (int i = t; i < NI0 * NI1; i += kThreads) {
-    const int k0 = i % NI0, k1 = i / NI0;
+    const int k1 = small_div(i, iNI0), k0 = i - k1 * NI0;
     const int64_t A = wrap_fn(pb.ax[0], f0 + k0) + (int64_t)n0 * wrap_fn(pb.ax[1], f1 + k1);   // eq:map-wrap
     sU[k1 * NI + k0] = U[A];
     if (src) sF[k1 * NI + k0] = pb.src[A];
@@ -63,15 +83,14 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
   __syncthreads();
   // axis 0: coefficients -> (value, derivative) at the Gauss points, per function row k1
   for (int i = t; i < NI1 * G0; i += kThreads) {
-    const int g0 = i % G0, k1 = i / G0, el0 = g0 / Q, q0 = g0 % Q;
-    const size_t o = ((size_t)(E0 + el0) * Q + q0) * P;
+    const int k1 = small_div(i, iG0), g0 = i - k1 * G0, el0 = g0 / Q;
     double v = 0, d = 0, vf = 0;
 #pragma unroll
     for (int a0 = 0; a0 < P; ++a0) {
       const double c = sU[k1 * NI + el0 + a0];
-      v += pb.ax[0].B[o + a0] * c;
-      d += pb.ax[0].dB[o + a0] * c;
-      if (src) vf += pb.ax[0].B[o + a0] * sF[k1 * NI + el0 + a0];
+      v += B0[g0 * P + a0] * c;
+      d += dB0[g0 * P + a0] * c;
+      if (src) vf += B0[g0 * P + a0] * sF[k1 * NI + el0 + a0];
     }
     V[k1 * G + g0] = v;
     D[k1 * G + g0] = d;
@@ -82,19 +101,18 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
   {
     const double lam = pb.lambda;
     for (int i = t; i < G1 * G0; i += kThreads) {
-      const int g0 = i % G0, g1 = i / G0, el1 = g1 / Q, q1 = g1 % Q, el0 = g0 / Q;
-      const size_t o = ((size_t)(E1 + el1) * Q + q1) * P;
+      const int g1 = small_div(i, iG0), g0 = i - g1 * G0, el1 = g1 / Q, el0 = g0 / Q;
       double u = 0, u0 = 0, u1 = 0, f = 0;
 #pragma unroll
       for (int a1 = 0; a1 < P; ++a1) {
-        const double b = pb.ax[1].B[o + a1], db = pb.ax[1].dB[o + a1];
+        const double b = B1[g1 * P + a1], db = dB1[g1 * P + a1];
         const int r = (el1 + a1) * G + g0;
         u += b * V[r];
         u0 += b * D[r];
         u1 += db * V[r];
         f += b * VF[r];
       }
-      const double W = pb.ax[0].wq[(size_t)E0 * Q + g0] * pb.ax[1].wq[(size_t)(E1 + el1) * Q + q1];
+      const double W = W0[g0] * W1[g1];
       const double kw = (kel ? pb.kel[(E0 + el0) + (int64_t)ne0 * (E1 + el1)] : 1.0) * W;
       F0[g1 * G + g0] = kw * u0;
       F1[g1 * G + g0] = kw * u1;
@@ -104,18 +122,18 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
   __syncthreads();
   // transposed axis 1: Ya[k1][g0] = sum F0 N_k1, Yb[k1][g0] = sum F1 N'_k1 + S N_k1
   for (int i = t; i < NI1 * G0; i += kThreads) {
-    const int g0 = i % G0, k1 = i / G0;
+    const int k1 = small_div(i, iG0), g0 = i - k1 * G0;
     double ya = 0, yb = 0;
-    for (int el1 = 0; el1 < NE1; ++el1) {
-      const int a1 = k1 - el1;
-      if (a1 < 0 || a1 > p) continue;
+#pragma unroll
+    for (int a1 = 0; a1 <= p; ++a1) {
+      const int el1 = k1 - a1;
+      if (el1 < 0 || el1 >= NE1) continue;
 #pragma unroll
       for (int q1 = 0; q1 < Q; ++q1) {
-        const size_t o = ((size_t)(E1 + el1) * Q + q1) * P + a1;
-        const int r = (el1 * Q + q1) * G + g0;
-        const double b = pb.ax[1].B[o];
+        const int g1 = el1 * Q + q1, r = g1 * G + g0;
+        const double b = B1[g1 * P + a1];
         ya += F0[r] * b;
-        yb += F1[r] * pb.ax[1].dB[o] + Sg[r] * b;
+        yb += F1[r] * dB1[g1 * P + a1] + Sg[r] * b;
       }
     }
     Ya[k1 * G + g0] = ya;
@@ -124,16 +142,16 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
   __syncthreads();
   // transposed axis 0 and the scatter of the tile's contributions
   for (int i = t; i < NI0 * NI1; i += kThreads) {
-    const int k0 = i % NI0, k1 = i / NI0;
+    const int k1 = small_div(i, iNI0), k0 = i - k1 * NI0;
     double r = 0;
-    for (int el0 = 0; el0 < NE0; ++el0) {
-      const int a0 = k0 - el0;
-      if (a0 < 0 || a0 > p) continue;
+#pragma unroll
+    for (int a0 = 0; a0 <= p; ++a0) {
+      const int el0 = k0 - a0;
+      if (el0 < 0 || el0 >= NE0) continue;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) {
-        const size_t o = ((size_t)(E0 + el0) * Q + q0) * P + a0;
         const int g0 = el0 * Q + q0;
-        r += Ya[k1 * G + g0] * pb.ax[0].dB[o] + Yb[k1 * G + g0] * pb.ax[0].B[o];
+        r += Ya[k1 * G + g0] * dB0[g0 * P + a0] + Yb[k1 * G + g0] * B0[g0 * P + a0];
       }
     }
     atomicAdd(&R[wrap_fn(pb.ax[0], f0 + k0) + (int64_t)n0 * wrap_fn(pb.ax[1], f1 + k1)], r);
