@@ -720,7 +720,7 @@ iga_status launch_residual(Handle &h, const double *U, double *R) {
 }
 
 iga_status launch_linearize(Handle &h, const double *U) {
-  iga_status st = dispatch_dpt<RunLin>(h, U);
+  iga_status st = (res3_supported(h.pb) && h.tiled_3d) ? launch_res3(h, U, h.lin, 2) : dispatch_dpt<RunLin>(h, U);
   if (st) return st;
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;

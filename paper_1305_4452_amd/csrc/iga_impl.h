@@ -234,7 +234,7 @@ iga_status launch_jac_nd(Handle &h, const double *U, void *vals, int prec, int c
 bool rgt2_supported(const DevProblem &pb);
 bool res2_supported(const DevProblem &pb);
 bool res3_supported(const DevProblem &pb);
-iga_status launch_res3(Handle &h, const double *X, double *Y, int apply);
+iga_status launch_res3(Handle &h, const double *X, double *Y, int op);
 iga_status launch_res2(Handle &h, const double *U, double *R);
 iga_status launch_jac_rgt2(Handle &h, const double *U, void *vals, int prec);
 bool rgsep_supported(const Handle &h, int b1, int b2);

@@ -5,12 +5,14 @@
 // of the tile's (TE + p)^3 functions to the value and gradient at its (TE Q)^3 Gauss points (three
 // 1D contractions), forms the point flux F and source S of the weak form (Sec. 3):
 //   residual: F = kappa W grad u, S = -lambda W e^u;
-//   apply:    F = kappa W grad v, S = m v with m = -lambda W e^u cached per point (OP_LIN),
+//   apply:    F = kappa W grad v, S = m v with m = -lambda W e^u cached per point,
 // and the three transposed contractions give the tile's contribution to each of its functions,
 //   R_A += sum_g F . grad N_A + S N_A,
 // added to the output with one FP64 atomic per function (border functions are shared with the
 // neighbouring tiles).  The output must be zeroed before and the Dirichlet rows set afterwards, as
 // for the element-by-element kernel; for the apply, Dirichlet coefficients of v count as zero.
+// The linearisation (OP3_LIN) stops after the forward contractions of u (values only) and writes
+// m = -lambda W e^u at every Gauss point, layout [element][q0 + Q (q1 + Q q2)], into Y.
 #pragma once
 
 #include "iga_impl.h"
@@ -19,7 +21,7 @@ namespace iga {
 namespace rs3 {
 
 constexpr int kThreads = 256;
-enum { OP3_RES = 0, OP3_APPLY = 1 };
+enum { OP3_RES = 0, OP3_APPLY = 1, OP3_LIN = 2 };
 
 // elements per tile side (TE Q = 8 or 9 Gauss points per axis: measured at 64^3, larger tiles run one
 // workgroup per CU and lose to the element-by-element kernel) and the LDS plan in doubles:
@@ -48,6 +50,7 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
   using S_ = Res3<P>;
   constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G;
   constexpr int NT = kThreads, L = P * P * P, GP = G * P;
+  constexpr bool LIN = OP == OP3_LIN;
   const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
   const int nt0 = (ne0 + TE - 1) / TE, nt1 = (ne1 + TE - 1) / TE;
   const int E0 = (tile % nt0) * TE, E1 = ((tile / nt0) % nt1) * TE, E2 = (tile / (nt0 * nt1)) * TE;
@@ -99,10 +102,10 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
 #pragma unroll
     for (int a0 = 0; a0 < P; ++a0) {
       a += B0[g0 * P + a0] * cc[a0];
-      d += dB0[g0 * P + a0] * cc[a0];
+      if constexpr (!LIN) d += dB0[g0 * P + a0] * cc[a0];
     }
     A0[i] = a;
-    D0[i] = d;
+    if constexpr (!LIN) D0[i] = d;
   }
   __syncthreads();
   // axis 1
@@ -115,12 +118,16 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
       const int r = (k2 * NI + el1 + a1) * G + g0;
       const double b = B1[g1 * P + a1];
       u += b * A0[r];
-      u01 += b * D0[r];
-      u10 += dB1[g1 * P + a1] * A0[r];
+      if constexpr (!LIN) {
+        u01 += b * D0[r];
+        u10 += dB1[g1 * P + a1] * A0[r];
+      }
     }
     U1[i] = u;
-    U01[i] = u01;
-    U10[i] = u10;
+    if constexpr (!LIN) {
+      U01[i] = u01;
+      U10[i] = u10;
+    }
   }
   __syncthreads();
   // axis 2 and the point integrands
@@ -135,13 +142,20 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
         const int r = ((el2 + a2) * G + g1) * G + g0;
         const double b = B2[g2 * P + a2];
         u += b * U1[r];
-        d0 += b * U01[r];
-        d1 += b * U10[r];
-        d2 += dB2[g2 * P + a2] * U1[r];
+        if constexpr (!LIN) {
+          d0 += b * U01[r];
+          d1 += b * U10[r];
+          d2 += dB2[g2 * P + a2] * U1[r];
+        }
       }
       const int el0 = g0 / Q, el1 = g1 / Q;
       const double W = W0[g0] * W1[g1] * W2[g2];
       const int64_t e = (E0 + el0) + (int64_t)ne0 * ((E1 + el1) + (int64_t)ne1 * (E2 + el2));
+      if constexpr (LIN) {
+        const int q = (g0 % Q) + Q * ((g1 % Q) + Q * (g2 % Q));
+        Y[e * L + q] = -lam * W * exp(u);
+        continue;
+      }
       const double kw = (kel ? pb.kel[e] : 1.0) * W;
       F0[i] = kw * d0;
       F1[i] = kw * d1;
@@ -154,6 +168,7 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
       }
     }
   }
+  if constexpr (LIN) return;
   __syncthreads();
   // transposed axis 2: Y0 = sum B2 F0, Y1 = sum B2 F1, Y2 = sum dB2 F2 + B2 S
   for (int i = t; i < NI * G * G; i += NT) {

@@ -57,6 +57,9 @@ iga_status run_res3(Handle &h, const double *X, double *Y, int op) {
   if (op == rs3::OP3_APPLY)
     hipLaunchKernelGGL((k_res3<P, rs3::OP3_APPLY>), dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
                        (const double *)h.lin, Y);
+  else if (op == rs3::OP3_LIN)
+    hipLaunchKernelGGL((k_res3<P, rs3::OP3_LIN>), dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                       (const double *)nullptr, Y);
   else
     hipLaunchKernelGGL((k_res3<P, rs3::OP3_RES>), dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
                        (const double *)nullptr, Y);
@@ -72,9 +75,10 @@ bool res3_supported(const DevProblem &pb) {
          (pb.kappa_mode == IGA_KAPPA_ONE || pb.kappa_mode == IGA_KAPPA_ELEMENT);
 }
 
-// residual (apply = 0) or matrix-free Jacobian apply (apply = 1, needs the OP_LIN point cache)
-iga_status launch_res3(Handle &h, const double *X, double *Y, int apply) {
-  const int op = apply ? rs3::OP3_APPLY : rs3::OP3_RES;
+// residual (op = 0), matrix-free Jacobian apply (op = 1, needs the point cache of the linearisation) or
+// the linearisation itself (op = 2: X = U, Y = the point cache)
+iga_status launch_res3(Handle &h, const double *X, double *Y, int op) {
+  if (op < rs3::OP3_RES || op > rs3::OP3_LIN) return fail(IGA_EINVAL, "tiled 3D operation");
   switch (h.pb.P) {
     case 2: return run_res3<2>(h, X, Y, op);
     case 3: return run_res3<3>(h, X, Y, op);
