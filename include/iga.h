@@ -186,9 +186,10 @@ iga_status iga_element_matrices(iga_t h, const double *U_dev, const int32_t *ele
  * (setting the option starts a new averaging window) every call records a HIP event pair on the
  * handle's stream around each kernel it launches; the events of the last 64 calls are kept.
  * iga_kernel_times waits for the latest call's last event, then writes up to cap entries:
- * ms[i] the mean elapsed milliseconds of the i-th kernel of a call over the kept calls, and
- * names[i] a static string naming it (either array may be NULL); *count receives the number of
- * kernels per call (at most 4).  IGA_ESTATE if no timed call has been made. */
+ * ms[i] the mean elapsed milliseconds of the latest call's i-th kernel over the kept calls that
+ * launched the same kernel in that position (calls made with another algorithm are left out),
+ * and names[i] a static string naming it (either array may be NULL); *count receives the number
+ * of kernels of the latest call (at most 4).  IGA_ESTATE if no timed call has been made. */
 iga_status iga_kernel_times(iga_t h, int cap, double *ms, const char **names, int *count);
 
 /* ---- batched solves ------------------------------------------------------------------------

@@ -324,15 +324,20 @@ iga_status iga_kernel_times(iga_t hh, int cap, double *ms, const char **names, i
   const int last = (int)((h.kt_calls - 1) % Handle::kTimedCalls);
   IGA_HIP_CHECK(hipEventSynchronize(h.kt_ev[last][h.kt_n - 1][1]));
   for (int i = 0; i < h.kt_n && i < cap; ++i) {
+    // kernel i of the latest call, averaged over the kept calls that timed the same kernel there
+    // (calls made with another algorithm launch other kernels)
     double sum = 0;
+    int64_t used = 0;
     for (int64_t c = 0; c < ncalls; ++c) {
       const int slot = (int)((h.kt_calls - 1 - c) % Handle::kTimedCalls);
+      if (h.kt_cnt[slot] <= i || h.kt_name[slot][i] != h.kt_name[last][i]) continue;
       float t = 0;
       IGA_HIP_CHECK(hipEventElapsedTime(&t, h.kt_ev[slot][i][0], h.kt_ev[slot][i][1]));
       sum += t;
+      ++used;
     }
-    if (ms) ms[i] = sum / (double)ncalls;
-    if (names) names[i] = h.kt_name[i];
+    if (ms) ms[i] = sum / (double)used;
+    if (names) names[i] = h.kt_name[last][i];
   }
   if (count) *count = h.kt_n;
   return IGA_OK;

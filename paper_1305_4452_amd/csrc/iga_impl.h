@@ -168,7 +168,8 @@ struct Handle {
   int ktiming = 0, kt_n = 0;
   int64_t kt_calls = 0;           // timed calls since timing was switched on
   hipEvent_t kt_ev[kTimedCalls][kMaxTimed][2] = {};
-  const char *kt_name[kMaxTimed] = {};
+  const char *kt_name[kTimedCalls][kMaxTimed] = {};   // per kept call: the kernel each event pair timed
+  int kt_cnt[kTimedCalls] = {};                        // per kept call: timed kernels
   // host copies
   std::vector<double> hknots[3];
   int nb_colors = 0;
@@ -191,19 +192,22 @@ inline void kt_reset(Handle &h) {
   if (!h.ktiming) return;
   h.kt_n = 0;
   ++h.kt_calls;
+  h.kt_cnt[(h.kt_calls - 1) % Handle::kTimedCalls] = 0;
 }
 inline void kt_begin(Handle &h, const char *name) {
   if (!h.ktiming || h.kt_n >= Handle::kMaxTimed) return;
-  hipEvent_t *ev = h.kt_ev[(h.kt_calls - 1) % Handle::kTimedCalls][h.kt_n];
+  const int slot = (int)((h.kt_calls - 1) % Handle::kTimedCalls);
+  hipEvent_t *ev = h.kt_ev[slot][h.kt_n];
   for (int k = 0; k < 2; ++k)
     if (!ev[k]) (void)hipEventCreate(&ev[k]);
-  h.kt_name[h.kt_n] = name;
+  h.kt_name[slot][h.kt_n] = name;
   (void)hipEventRecord(ev[0], h.stream);
 }
 inline void kt_end(Handle &h) {
   if (!h.ktiming || h.kt_n >= Handle::kMaxTimed) return;
-  (void)hipEventRecord(h.kt_ev[(h.kt_calls - 1) % Handle::kTimedCalls][h.kt_n][1], h.stream);
-  ++h.kt_n;
+  const int slot = (int)((h.kt_calls - 1) % Handle::kTimedCalls);
+  (void)hipEventRecord(h.kt_ev[slot][h.kt_n][1], h.stream);
+  h.kt_cnt[slot] = ++h.kt_n;
 }
 
 // A v = mu M v for dense symmetric A, M (n x n, row-major): V (column i = vector i, V^T M V = I)

@@ -230,6 +230,32 @@ def test_separable_rowgather_segments(segments, prec):
     assert names == ["k_mfield", "k_rgsep3"]
 
 
+def test_kernel_times_across_algorithm_changes():
+    """Per-kernel timing while the Jacobian algorithm changes between calls: each reported kernel is
+    averaged only over the calls that launched it in that position (calls of the other algorithm
+    launch other kernels, or fewer)."""
+    print("[case] kernel timing across algorithm changes", flush=True)
+    patch = inputs.unit_box(3, [6, 5, 4], 3)
+    g = iga.IGA(patch.knots, patch.degree, lam=4.0)
+    g.set_option(iga.IGA_OPT_KERNEL_TIMING, 1)
+    U = dev(inputs.uniform(6, 9, g.N, 0.0, 0.5))
+    vals = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER_GENERAL)
+    g.assemble_jacobian(U, vals)
+    general = [n for n, _ in g.kernel_times()]
+    assert len(general) == 1
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER)
+    for _ in range(3):
+        g.assemble_jacobian(U, vals)
+    kt = g.kernel_times()
+    assert [n for n, _ in kt] == ["k_mfield", "k_rgsep3"]
+    assert all(ms > 0 and np.isfinite(ms) for _, ms in kt)
+    g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_ROWGATHER_GENERAL)
+    g.assemble_jacobian(U, vals)
+    kt = g.kernel_times()
+    assert [n for n, _ in kt] == general and kt[0][1] > 0
+
+
 @pytest.mark.parametrize("p,nel,km,mask", [(1, [50, 23], 0, None), (2, [40, 27], 2, None), (3, [25, 20], 0, 0b0110),
                                            (4, [13, 17], 2, 0b1001), (4, [3, 2], 0, None), (2, 1, 0, None),
                                            (3, [30, 4], 2, 0b0011)])
