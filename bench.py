@@ -80,7 +80,7 @@ def rowgather_flops(n: int, p: int, b1: int, b2: int) -> float:
 # WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device
 # copy (FETCH x2.0, WRITE x1.0); the summary is under profiles/.  Valid only for the kernel source
 # the counters were taken on (SHA-1 of rg_sep.hip); otherwise the traffic is reported as null.
-TRAFFIC = {"src_sha1": "9fb9714bc49923a44bf7cce21430d98b86bcedbb", "fetch_kib": 179993, "write_kib": 751699,
+TRAFFIC = {"src_sha1": "5c1a4a8b9052f0d4749c3ee335f5eb976dca5de8", "fetch_kib": 130399, "write_kib": 813166,
            "fetch_scale": 2.0, "write_scale": 1.0}
 
 

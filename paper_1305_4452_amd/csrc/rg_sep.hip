@@ -240,16 +240,18 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
         woff[j] = (int)(((size_t)q0 * GG2 + (size_t)(W2lo * Q + g2l)) * GG1 + (size_t)(W1lo * Q + g1l));
     }
   }
+  // every lane loads (points outside the mesh read the column's first point and are zeroed when
+  // stored), so no register is written while a load into it may still be in flight
   auto load_win = [&](int e0) {
     const CT *base = mf + (size_t)e0 * Q * GG2 * GG1;
 #pragma unroll
-    for (int j = 0; j < NLD; ++j) pre[j] = woff[j] >= 0 ? base[woff[j]] : (CT)0;
+    for (int j = 0; j < NLD; ++j) pre[j] = base[woff[j] >= 0 ? woff[j] : 0];
   };
   auto store_win = [&]() {
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
       const int i = t + j * NT;
-      if (i < NWIN) (&mw[0][0][0])[i] = pre[j];
+      if (i < NWIN) (&mw[0][0][0])[i] = woff[j] >= 0 ? pre[j] : (CT)0;
     }
   };
 
@@ -280,7 +282,8 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
     for (int r = wv; r < NROW; r += NT / 64) {
       const int len = rlen[r];
       const int64_t start = rstart[r];
-      for (int loc = lane; loc < len; loc += 64) vals[start + loc] = stage[r][loc];
+      // streamed once: non-temporal, so the values do not displace the m windows in L2
+      for (int loc = lane; loc < len; loc += 64) __builtin_nontemporal_store(stage[r][loc], &vals[start + loc]);
     }
   };
 
