@@ -233,6 +233,15 @@ iga_status iga_batch_info(iga_batch_t b, int64_t *total_ndof, int64_t *total_nnz
  * Synchronous. */
 iga_status iga_batch_newton_solve(iga_batch_t b, double *U_dev, const iga_newton_opts *opts,
                                   iga_batch_item_report *items, iga_batch_report *report);
+/* Error estimate of a state, per instance: ||P^{-1} R(U)||_2, with R the residual of eq:residual
+ * (Dirichlet rows U_A) and P the fast-diagonalisation operator with its reaction shift taken at U,
+ * i.e. the first Newton correction as the preconditioner approximates it (close to ||U - U*|| for
+ * U near the solution U*; no solve).  It judges an initial guess by its error where the residual
+ * norm would mostly weigh the guess's high-frequency error.  U_dev as for iga_batch_newton_solve
+ * (read only); est_host (host, n) gets the estimates in the caller's order.  IGA_EUNSUPPORTED when
+ * the fast-diagonalisation data was not built (an axis longer than 136 coefficients).  Uses the
+ * solve workspace; synchronous. */
+iga_status iga_batch_error_estimates(iga_batch_t b, const double *U_dev, double *est_host);
 /* key IGA_OPT_PRECOND only: IGA_PRECOND_AUTO (fast diagonalisation when built, the default),
  * IGA_PRECOND_JACOBI, or IGA_PRECOND_FDM (IGA_EUNSUPPORTED when it was not built).  Takes effect
  * at the next iga_batch_newton_solve. */

@@ -130,6 +130,7 @@ _SIGNATURES = {
     "iga_batch_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_batch_item_report),
                                 C.POINTER(iga_batch_report)], C.c_int),
     "iga_batch_set_option": ([C.c_void_p, C.c_int, C.c_int64], C.c_int),
+    "iga_batch_error_estimates": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "iga_batch_destroy": ([C.c_void_p], C.c_int),
     "igann_num_params": ([], C.c_int64),
     "igann_create": ([C.c_int, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
@@ -399,6 +400,15 @@ class IGABatch:
 
     def set_option(self, key, value):
         _check(load().iga_batch_set_option(self.h, int(key), int(value)), "iga_batch_set_option")
+
+    def error_estimates(self, U):
+        """Per instance ||P^{-1} R(U)||_2 (iga_batch_error_estimates): the first Newton correction as the
+        fast-diagonalisation preconditioner approximates it."""
+        import torch
+        est = (C.c_double * self.n)()
+        _check(load().iga_batch_error_estimates(self.h, _dev_ptr(U, torch.float64, self.N, "U"), est),
+               "iga_batch_error_estimates")
+        return np.array(est[:], dtype=np.float64)
 
     def newton_solve(self, U, atol=1e-10, rtol=0.0, max_newton=30, max_krylov=5000, jac_prec=IGA_FP64,
                      forcing_max=1e-2, raise_on_fail=True, check_every=0):

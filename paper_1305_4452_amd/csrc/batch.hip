@@ -1275,6 +1275,39 @@ static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in,
   return r.all_converged ? IGA_OK : fail(IGA_ENOCONV, "some batched instances did not converge");
 }
 
+// Per instance, ||P^{-1} R(U)||_2 with P the fast-diagonalisation operator whose reaction shift is
+// taken at U: the first Newton correction as the preconditioner approximates it, an estimate of
+// ||U - U*|| that needs no solve.  Used to judge an initial guess: its residual norm is dominated
+// by the high-frequency part of its error, which the stiffness amplifies, while this estimate weighs
+// every frequency of the error alike (exactly so where P is the exact Jacobian).  est_host gets one
+// value per instance in the caller's order.  Uses the residual and correction slots of the solve
+// workspace; runs on the batch stream after the caller's stream, and returns once done.
+static iga_status batch_error_estimates(Batch &b, const double *U, double *est_host) {
+  if (!b.bf_on) return fail(IGA_EUNSUPPORTED, "error estimates need the fast-diagonalisation preconditioner");
+  const int n = b.n;
+  const int64_t N = b.Ntot;
+  double *R = b.ws, *z = b.ws + N;
+  const unsigned nvt = (unsigned)b.vt.size();
+  IGA_HIP_CHECK(hipStreamSynchronize(b.user));
+  std::vector<int> act(n, 1);
+  std::vector<double> nr(n);
+  IGA_HIP_CHECK(hipMemcpyAsync(b.act, act.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
+  hipLaunchKernelGGL(k_b_fill, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, R, 0.0);
+  for (const Group &g : b.groups) launch_res(b, g, U, R, b.bs);
+  hipLaunchKernelGGL(k_b_bc_copy, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.act, U, R);
+  hipLaunchKernelGGL(k_bf_shift, dim3((unsigned)n), dim3(256), 0, b.bs, b.d_pbs, b.d_bf, (const double *)b.bf_pool,
+                     b.d_off, b.act, U, b.bf_shift);
+  launch_bf_apply(b, R, z, nullptr, b.bs);
+  hipLaunchKernelGGL(k_b_sq_partial, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, (const double *)z, b.partA);
+  hipLaunchKernelGGL(k_b_inst_norms, dim3(std::min(n, 1024)), dim3(256), 0, b.bs, n, b.d_vt_start,
+                     (const double *)b.partA, b.norms);
+  IGA_HIP_CHECK(hipGetLastError());
+  IGA_HIP_CHECK(hipMemcpyAsync(nr.data(), b.norms, n * sizeof(double), hipMemcpyDeviceToHost, b.bs));
+  IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
+  for (int k = 0; k < n; ++k) est_host[b.perm_[k]] = nr[k];
+  return IGA_OK;
+}
+
 }  // namespace iga
 
 using namespace iga;
@@ -1309,6 +1342,11 @@ iga_status iga_batch_newton_solve(iga_batch_t bb, double *U_dev, const iga_newto
                                   iga_batch_item_report *items, iga_batch_report *report) {
   if (!bb || !U_dev) return fail(IGA_EINVAL, "null argument");
   return batch_newton(*(Batch *)bb, U_dev, opts, items, report);
+}
+
+iga_status iga_batch_error_estimates(iga_batch_t bb, const double *U_dev, double *est_host) {
+  if (!bb || !U_dev || !est_host) return fail(IGA_EINVAL, "null argument");
+  return batch_error_estimates(*(Batch *)bb, U_dev, est_host);
 }
 
 iga_status iga_batch_set_option(iga_batch_t bb, int key, int64_t value) {

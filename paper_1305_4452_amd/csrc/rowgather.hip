@@ -44,9 +44,15 @@ k_rowgather3(DevProblem pb, const double *__restrict__ U, OT *__restrict__ vals)
 
   __shared__ CT tX1[2][ME1][Q][P], tX2[2][ME2][Q][P];  // [val/der][elem][q][a]
   __shared__ double tW1[ME1][Q], tW2[ME2][Q];
-  __shared__ double tB1d[ME1][Q][P], tB2d[ME2][Q][P];  // FP64 values for interpolation
+  // FP64 basis values for the interpolation of u: with FP64 contractions they are the value tables
+  // themselves, so the copies (and their LDS) exist only for FP32 contractions
+  constexpr bool F64 = std::is_same<CT, double>::value;
+  __shared__ double tB1c[F64 ? 1 : ME1][Q][P], tB2c[F64 ? 1 : ME2][Q][P];
   __shared__ CT tX0[2][Q][P];
-  __shared__ double tB0d[Q][P], tW0[Q];
+  __shared__ double tB0c[F64 ? 1 : Q][P], tW0[Q];
+  const auto tB1d = [&](int el, int q, int a) -> double { return F64 ? (double)tX1[0][el][q][a] : tB1c[el][q][a]; };
+  const auto tB2d = [&](int el, int q, int a) -> double { return F64 ? (double)tX2[0][el][q][a] : tB2c[el][q][a]; };
+  const auto tB0d = [&](int q, int a) -> double { return F64 ? (double)tX0[0][q][a] : tB0c[q][a]; };
   __shared__ double sU[P][MI2][MI1];
   __shared__ double V0[MI2][MI1];
   __shared__ double V1[MI2][MG1];
@@ -90,7 +96,7 @@ k_rowgather3(DevProblem pb, const double *__restrict__ U, OT *__restrict__ vals)
     size_t o = (size_t)e1 * Q * P + r;
     (&tX1[0][0][0][0])[i] = (CT)pb.ax[1].B[o];
     (&tX1[1][0][0][0])[i] = (CT)pb.ax[1].dB[o];
-    (&tB1d[0][0][0])[i] = pb.ax[1].B[o];
+    if constexpr (!F64) (&tB1c[0][0][0])[i] = pb.ax[1].B[o];
   }
   for (int i = t; i < ME2 * Q * P; i += NT) {
     int el = i / (Q * P), r = i % (Q * P);
@@ -98,7 +104,7 @@ k_rowgather3(DevProblem pb, const double *__restrict__ U, OT *__restrict__ vals)
     size_t o = (size_t)e2 * Q * P + r;
     (&tX2[0][0][0][0])[i] = (CT)pb.ax[2].B[o];
     (&tX2[1][0][0][0])[i] = (CT)pb.ax[2].dB[o];
-    (&tB2d[0][0][0])[i] = pb.ax[2].B[o];
+    if constexpr (!F64) (&tB2c[0][0][0])[i] = pb.ax[2].B[o];
   }
   for (int i = t; i < ME1 * Q; i += NT) {
     int e1 = min(E1lo + i / Q, pb.ne[1] - 1);
@@ -133,7 +139,7 @@ k_rowgather3(DevProblem pb, const double *__restrict__ U, OT *__restrict__ vals)
       size_t o = (size_t)e0 * Q * P + i;
       (&tX0[0][0][0])[i] = (CT)pb.ax[0].B[o];
       (&tX0[1][0][0])[i] = (CT)pb.ax[0].dB[o];
-      (&tB0d[0][0])[i] = pb.ax[0].B[o];
+      if constexpr (!F64) (&tB0c[0][0])[i] = pb.ax[0].B[o];
     }
     if (t < Q) tW0[t] = pb.ax[0].wq[(size_t)e0 * Q + t];
     // coefficient block U[e0 + a0, E1lo + k1, E2lo + k2] (weighted for rational bases)
@@ -151,7 +157,7 @@ k_rowgather3(DevProblem pb, const double *__restrict__ U, OT *__restrict__ vals)
         int k1 = i % NI1, k2 = i / NI1;
         double s = 0;
 #pragma unroll
-        for (int a0 = 0; a0 < P; ++a0) s += tB0d[q0][a0] * sU[a0][k2][k1];
+        for (int a0 = 0; a0 < P; ++a0) s += tB0d(q0, a0) * sU[a0][k2][k1];
         V0[k2][k1] = s;
       }
       __syncthreads();
@@ -159,7 +165,7 @@ k_rowgather3(DevProblem pb, const double *__restrict__ U, OT *__restrict__ vals)
         int g1 = i % G1, k2 = i / G1, el = g1 / Q, q1 = g1 % Q;
         double s = 0;
 #pragma unroll
-        for (int a1 = 0; a1 < P; ++a1) s += tB1d[el][q1][a1] * V0[k2][el + a1];
+        for (int a1 = 0; a1 < P; ++a1) s += tB1d(el, q1, a1) * V0[k2][el + a1];
         V1[k2][g1] = s;
       }
       __syncthreads();
@@ -167,7 +173,7 @@ k_rowgather3(DevProblem pb, const double *__restrict__ U, OT *__restrict__ vals)
         int g1 = i % G1, g2 = i / G1, el1 = g1 / Q, q1 = g1 % Q, el2 = g2 / Q, q2 = g2 % Q;
         double ut = 0;
 #pragma unroll
-        for (int a2 = 0; a2 < P; ++a2) ut += tB2d[el2][q2][a2] * V1[el2 + a2][g1];
+        for (int a2 = 0; a2 < P; ++a2) ut += tB2d(el2, q2, a2) * V1[el2 + a2][g1];
         int64_t e = e0 + (int64_t)pb.ne[0] * ((E1lo + el1) + (int64_t)pb.ne[1] * (E2lo + el2));
         double W = tW0[q0] * tW1[el1][q1] * tW2[el2][q2];
         double kap = (!TABLE && pb.kappa_mode == IGA_KAPPA_ELEMENT) ? pb.kel[e] : 1.0;

@@ -5,9 +5,10 @@ Pipeline (every numerical step runs in libiga's HIP kernels; this module only or
   2. targets: plain Newton solutions from the zero guess by the batched solver; instances where
      it fails (no solution near the fold for that kappa) are rejected and counted;
   3. training: the device network (igann_*) on standardised inputs and targets with Adam;
-  4. use: guess = network output (interior coefficients, zero boundary); if ||R(guess)|| is
-     larger than ||R(0)|| the zero guess is used instead, and plain Newton from the zero guess
-     is the judge of the converged answer.
+  4. use: guess = network output (interior coefficients, zero boundary); if its error estimate
+     ||P^{-1} R(guess)|| (P the fast-diagonalisation preconditioner, iga_batch_error_estimates)
+     is larger than that of the zero guess, the zero guess is used instead, and plain Newton from
+     the zero guess is the judge of the converged answer.
 """
 from __future__ import annotations
 
@@ -173,12 +174,24 @@ def _residual_norms(b, starts):
     return np.array([p["res_norm0"] for p in per]), time.perf_counter() - t
 
 
+def _error_estimates(b, starts):
+    """||P^{-1} R(U)|| of every start (the fast-diagonalisation estimate of its error)."""
+    import torch
+    U = torch.as_tensor(b.pack(starts), device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    est = b.error_estimates(U)
+    return est, time.perf_counter() - t
+
+
 def evaluate(net, std, test, sols_ref, atol=1e-10, chunk=1000, corrupt=None):
     """Newton from the zero guess, from the raw learned guess, and from the learned guess with
-    the residual check (fall back to zero when ||R(guess)|| > ||R(0)||), all on the same
-    instances and to the same absolute tolerance.  A run counts as wrong when it does not
-    converge or lands on a different solution than Newton from zero (e.g. the upper Bratu
-    branch).  `corrupt(guesses)` (tests only) perturbs the guesses to exercise the fallback."""
+    the check (fall back to zero when the guess's error estimate ||P^{-1} R(guess)|| exceeds
+    that of the zero guess, or is not finite), all on the same instances and to the same absolute
+    tolerance.  A run counts as wrong when it does not converge or lands on a different solution
+    than Newton from zero (e.g. the upper Bratu branch).  `fallbacks_residual_norm` counts the
+    guesses the plain residual-norm test ||R(guess)|| > ||R(0)|| would have rejected.
+    `corrupt(guesses)` (tests only) perturbs the guesses to exercise the fallback."""
     import torch
     ws = [w for _, _, w in test]
     torch.cuda.synchronize()
@@ -191,16 +204,19 @@ def evaluate(net, std, test, sols_ref, atol=1e-10, chunk=1000, corrupt=None):
     Ug = [full_from_interior(g) for g in guesses]
     res = {"zero": dict(iters=[], time=0.0, wrong=0), "learned_raw": dict(iters=[], time=t_infer, wrong=0),
            "learned_checked": dict(iters=[], time=t_infer, wrong=0)}
-    fallbacks = 0
+    fallbacks = fallbacks_res = 0
     for s in range(0, len(ws), chunk):
         part = ws[s:s + chunk]
         zeros = [np.zeros_like(u) for u in Ug[s:s + chunk]]
         raw = [np.nan_to_num(u, nan=0.0, posinf=0.0, neginf=0.0) for u in Ug[s:s + chunk]]
         b = IGABatch(part)                 # set-up (untimed), shared by every start
-        rg, t1 = _residual_norms(b, Ug[s:s + chunk])
-        rz, t2 = _residual_norms(b, zeros)
+        rg, _ = _residual_norms(b, Ug[s:s + chunk])
+        rz, _ = _residual_norms(b, zeros)
+        fallbacks_res += int((~np.isfinite(rg) | (rg > rz)).sum())
+        eg, t1 = _error_estimates(b, Ug[s:s + chunk])
+        ez, t2 = _error_estimates(b, zeros)
         t_check = t1 + t2
-        bad = ~np.isfinite(rg) | (rg > rz)
+        bad = ~np.isfinite(eg) | (eg > ez)
         fallbacks += int(bad.sum())
         checked = [zeros[i] if bad[i] else Ug[s + i] for i in range(len(part))]
         for key, starts, extra in (("zero", zeros, 0.0), ("learned_raw", raw, 0.0), ("learned_checked", checked, t_check)):
@@ -213,7 +229,7 @@ def evaluate(net, std, test, sols_ref, atol=1e-10, chunk=1000, corrupt=None):
                 r["wrong"] += int(not ok)
                 r["iters"].append(per[i]["newton_iters"])
         b.close()
-    summ = dict(instances=len(ws), inference_s=t_infer, fallbacks=fallbacks,
+    summ = dict(instances=len(ws), inference_s=t_infer, fallbacks=fallbacks, fallbacks_residual_norm=fallbacks_res,
                 guess_rel_error_mean=float(np.mean([np.linalg.norm(full_from_interior(g) - u) / np.linalg.norm(u)
                                                     for g, u in zip(guesses, sols_ref)])))
     for key, r in res.items():

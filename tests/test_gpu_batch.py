@@ -119,3 +119,43 @@ def test_batch_fdm_unavailable_for_long_axes():
     U = torch.as_tensor(b.pack([w.U0 for w in ws]), device="cuda")
     per, summ = b.newton_solve(U, atol=1e-10)
     assert summ["all_converged"]
+
+
+def _interior(shape, u):
+    """u with the entries of the Dirichlet faces (every face of the unit box) set to zero."""
+    g = np.array(u, dtype=np.float64).reshape(shape[::-1])
+    g[0, :] = g[-1, :] = 0.0
+    g[:, 0] = g[:, -1] = 0.0
+    return g.ravel()
+
+
+def test_batch_error_estimates_exact_for_the_linear_problem():
+    """With lambda = 0 and kappa = 1 the fast-diagonalisation operator is the Jacobian itself and
+    R(U) = J U, so ||P^{-1} R(U)|| equals ||U|| for any U that vanishes on the Dirichlet faces."""
+    print("[case] batched error estimates, linear problem", flush=True)
+    ws = [inputs.bratu_box(2, nel, p, 0.0, seed=7, stream=i) for i, (nel, p) in enumerate([(12, 2), (20, 3), (9, 4),
+                                                                                          (31, 2)])]
+    b = iga.IGABatch(ws)
+    us = [_interior(w.patch.shape, inputs.uniform(40 + i, 0, w.patch.ndof, -1.0, 1.0)) for i, w in enumerate(ws)]
+    est = b.error_estimates(torch.as_tensor(b.pack(us), device="cuda"))
+    ref = np.array([np.linalg.norm(u) for u in us])
+    assert np.allclose(est, ref, rtol=1e-10, atol=0.0), (est, ref)
+    b.close()
+
+
+def test_batch_error_estimates_track_the_error():
+    """At the converged solution the estimate is at rounding level; from the zero guess (error
+    ||U*||) it is within a factor two of ||U*||, for every instance of the mixed batch."""
+    print("[case] batched error estimates, Bratu and kappa instances", flush=True)
+    ws = mixed_workloads()
+    b = iga.IGABatch(ws)
+    U = torch.as_tensor(b.pack([np.zeros(w.patch.ndof) for w in ws]), device="cuda")
+    est0 = b.error_estimates(U)
+    per, summ = b.newton_solve(U, atol=1e-12)
+    assert summ["all_converged"]
+    sols = b.unpack(U.cpu().numpy())
+    nrm = np.array([np.linalg.norm(s) for s in sols])
+    assert np.all(est0 > 0.5 * nrm) and np.all(est0 < 2.0 * nrm), (est0, nrm)
+    est1 = b.error_estimates(U)
+    assert np.all(est1 < 1e-8 * nrm), (est1, nrm)
+    b.close()
