@@ -76,6 +76,9 @@ def lib():
             "orc_qp_data": [P, _dp, _dp, _dp, _dp, _dp],
             "orc_load_vector": [P, _dp, _dp],
             "orc_mass_matrix": [P, _i64p, _i32p, _dp],
+            "orc_basis_1d_d2": [C.c_int, _dp, C.c_int, C.c_int, C.c_double, _dp],
+            "orc_basis_hessian": [P, C.c_int64, _dp, _i64p, _dp, _dp, _dp, _dp],
+            "orc_biharmonic_residual": [P, _dp, _dp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -157,6 +160,30 @@ class Oracle:
             self._chk(lib().orc_csr_pattern(C.byref(self.pb), _ptr(rp, _i64p), _ptr(ci, _i32p)), "pattern")
             self._pattern = (rp, ci)
         return self._pattern
+
+    def basis_hessian(self, elem, t):
+        """Local functions of element `elem` at local coordinates t in [-1,1]^dim: global indices,
+        values, spatial gradients [nloc, 3], spatial Hessians [nloc, 3, 3] (eq:ddrational,
+        eq:ddimap, eq:ddspatial) and the point x [3]."""
+        nloc = int(np.prod([self.pb.degree[d] + 1 for d in range(self.dim)]))
+        tt = np.zeros(3)
+        tv = np.atleast_1d(np.asarray(t, dtype=np.float64))
+        tt[:len(tv)] = tv
+        A = np.zeros(nloc, dtype=np.int64)
+        N = np.zeros(nloc)
+        dN = np.zeros(nloc * 3)
+        d2N = np.zeros(nloc * 9)
+        x = np.zeros(3)
+        self._chk(lib().orc_basis_hessian(C.byref(self.pb), int(elem), _ptr(tt), _ptr(A, _i64p), _ptr(N), _ptr(dN),
+                                          _ptr(d2N), _ptr(x)), "basis_hessian")
+        return A, N, dN.reshape(nloc, 3), d2N.reshape(nloc, 3, 3), x
+
+    def biharmonic_residual(self, U):
+        """R_A = sum_e sum_q W (Lap N_A)(Lap u_h) for every function (no boundary rows)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        R = np.zeros(self.N)
+        self._chk(lib().orc_biharmonic_residual(C.byref(self.pb), _ptr(U), _ptr(R)), "biharmonic_residual")
+        return R
 
     def residual(self, U):
         U = np.ascontiguousarray(U, dtype=np.float64)

@@ -84,6 +84,24 @@ static double cdb_der(const double *U, int nk, int i, int p, double xi) {
   return d;
 }
 
+/* Second derivative: the same derivative formula applied once more, to the first derivatives of
+ * the two degree p-1 functions. */
+static double cdb_der2(const double *U, int nk, int i, int p, double xi) {
+  if (p <= 1) return 0.0;
+  double a = U[i + p] - U[i];
+  double b = U[i + p + 1] - U[i + 1];
+  double d = 0.0;
+  if (a != 0.0) d += p / a * cdb_der(U, nk, i, p - 1, xi);
+  if (b != 0.0) d -= p / b * cdb_der(U, nk, i + 1, p - 1, xi);
+  return d;
+}
+
+int orc_basis_1d_d2(int p, const double *U, int nk, int i, double xi, double *d2) {
+  if (p < 0 || !U || !d2 || i < 0 || i + p + 1 >= nk) return 1;
+  *d2 = cdb_der2(U, nk, i, p, xi);
+  return 0;
+}
+
 int orc_basis_1d(int p, const double *U, int nk, int i, double xi, double *val, double *der) {
   if (p < 0 || !U || i < 0 || i + p + 1 >= nk) return 1;
   if (val) *val = cdb(U, nk, i, p, xi);
@@ -968,4 +986,234 @@ int orc_mass_matrix(const orc_problem *pb, const int64_t *row_ptr, const int32_t
   free(q);
   lay_free(&L);
   return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Second spatial derivatives (Sec. 2.3 eq:ddrational; App. A eq:identity, eq:ddimap,     */
+/* eq:ddspatial) at local coordinates t in [-1,1]^dim of one element, and the fourth-order */
+/* operator R_A = sum_e sum_q W (Lap N_A)(Lap u_h) built from them.                        */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+  int nloc;
+  int64_t A[ORC_MAXLOC];
+  double N[ORC_MAXLOC], dN[ORC_MAXLOC][3], d2N[ORC_MAXLOC][3][3];   /* spatial */
+  double x[3];
+  double detJ;      /* det of the map xi -> x (the parametric span factors excluded) */
+  double span;      /* product of the span factors (xi_{s+1} - xi_s) / 2 */
+} hpoint;
+
+static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], const double t[3], hpoint *h) {
+  const int dim = L->dim;
+  double B[3][ORC_MAXP], dB[3][ORC_MAXP], d2B[3][ORC_MAXP];
+  h->span = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    if (d >= dim) { B[d][0] = 1.0; dB[d][0] = 0.0; d2B[d][0] = 0.0; continue; }
+    const double *K = L->kn[d];
+    int s = L->span[d][e[d]], p = L->p[d];
+    double a = K[s], b = K[s + 1];
+    double xi = 0.5 * ((a + b) + (b - a) * t[d]);
+    h->span *= 0.5 * (b - a);
+    for (int k = 0; k <= p; ++k) {
+      orc_basis_1d(p, K, pb->nknots[d], s - p + k, xi, &B[d][k], &dB[d][k]);
+      orc_basis_1d_d2(p, K, pb->nknots[d], s - p + k, xi, &d2B[d][k]);
+    }
+  }
+  const int P0 = L->p[0] + 1, P1 = L->p[1] + 1, P2 = L->p[2] + 1, nloc = P0 * P1 * P2;
+  h->nloc = nloc;
+  static double M[ORC_MAXLOC], dM[ORC_MAXLOC][3], d2M[ORC_MAXLOC][3][3];
+  static double Np[ORC_MAXLOC], dNp[ORC_MAXLOC][3], d2Np[ORC_MAXLOC][3][3];
+  for (int a2 = 0; a2 < P2; ++a2)
+    for (int a1 = 0; a1 < P1; ++a1)
+      for (int a0 = 0; a0 < P0; ++a0) {
+        int a = a0 + P0 * (a1 + P1 * a2), ai[3] = {a0, a1, a2};
+        int64_t i0 = fn_index(L, 0, L->span[0][e[0]], a0);
+        int64_t i1 = fn_index(L, 1, L->span[1][e[1]], a1);
+        int64_t i2 = fn_index(L, 2, L->span[2][e[2]], a2);
+        h->A[a] = i0 + (int64_t)L->n[0] * (i1 + (int64_t)L->n[1] * i2);
+        /* tensor product (Sec. 2.2): differentiate the factor of each axis named by the index */
+        for (int al = 0; al < 3; ++al) {
+          double v = 1.0;
+          for (int d = 0; d < 3; ++d) v *= (d == al) ? dB[d][ai[d]] : B[d][ai[d]];
+          dM[a][al] = v;
+          for (int be = 0; be < 3; ++be) {
+            double w2 = 1.0;
+            for (int d = 0; d < 3; ++d) {
+              int order = (d == al) + (d == be);
+              w2 *= order == 0 ? B[d][ai[d]] : order == 1 ? dB[d][ai[d]] : d2B[d][ai[d]];
+            }
+            d2M[a][al][be] = w2;
+          }
+        }
+        M[a] = B[0][a0] * B[1][a1] * B[2][a2];
+      }
+  /* rational basis and its first and second parametric derivatives (eq:rational, eq:drational,
+   * eq:ddrational); without weights N_A = M_A */
+  if (pb->weights) {
+    double w = 0.0, dw[3] = {0, 0, 0}, d2w[3][3] = {{0}};
+    for (int a = 0; a < nloc; ++a) {
+      double wa = pb->weights[h->A[a]];
+      w += wa * M[a];
+      for (int al = 0; al < 3; ++al) {
+        dw[al] += wa * dM[a][al];
+        for (int be = 0; be < 3; ++be) d2w[al][be] += wa * d2M[a][al][be];
+      }
+    }
+    for (int a = 0; a < nloc; ++a) {
+      double wa = pb->weights[h->A[a]];
+      Np[a] = wa * M[a] / w;
+      for (int al = 0; al < 3; ++al) dNp[a][al] = (wa * dM[a][al] - Np[a] * dw[al]) / w;
+      for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be)
+          d2Np[a][al][be] = (wa * d2M[a][al][be] - Np[a] * d2w[al][be]) / w
+                            - (dNp[a][be] * dw[al] + dNp[a][al] * dw[be]) / w;
+    }
+  } else {
+    for (int a = 0; a < nloc; ++a) {
+      Np[a] = M[a];
+      for (int al = 0; al < 3; ++al) {
+        dNp[a][al] = dM[a][al];
+        for (int be = 0; be < 3; ++be) d2Np[a][al][be] = d2M[a][al][be];
+      }
+    }
+  }
+  /* geometry and its parametric derivatives (App. A): x_{i,alpha}, x_{i,alpha beta} */
+  double J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, H[3][3][3] = {{{0}}};
+  for (int i = 0; i < 3; ++i) h->x[i] = 0.0;
+  if (pb->ctrl) {
+    for (int i = 0; i < dim; ++i)
+      for (int al = 0; al < dim; ++al) J[i][al] = 0.0;
+    for (int a = 0; a < nloc; ++a)
+      for (int i = 0; i < dim; ++i) {
+        double xa = pb->ctrl[h->A[a] * dim + i];
+        h->x[i] += xa * Np[a];
+        for (int al = 0; al < dim; ++al) {
+          J[i][al] += xa * dNp[a][al];
+          for (int be = 0; be < dim; ++be) H[i][al][be] += xa * d2Np[a][al][be];
+        }
+      }
+  } else {
+    for (int d = 0; d < dim; ++d) {
+      const double *K = L->kn[d];
+      int sp = L->span[d][e[d]];
+      h->x[d] = 0.5 * ((K[sp] + K[sp + 1]) + (K[sp + 1] - K[sp]) * t[d]);
+    }
+  }
+  /* first derivatives of the inverse map from eq:identity (matrix inverse, by cofactors) */
+  double det, Ji[3][3] = {{0}};
+  if (dim == 1) {
+    det = J[0][0];
+    Ji[0][0] = 1.0 / det;
+  } else if (dim == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    Ji[0][0] = J[1][1] / det;  Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+  } else {
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+        - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+        + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        /* cofactor of J[c][r], over det: (J^-1)[r][c] */
+        int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+        Ji[r][c] = (J[r1][c1] * J[r2][c2] - J[r1][c2] * J[r2][c1]) / det;
+      }
+  }
+  if (!(det > 0.0)) return 2;
+  h->detJ = det;
+  /* eq:ddimap, with the sign that differentiating eq:identity gives:
+   * xi_{alpha,ij} = - xi_{alpha,m} x_{m,eps mu} xi_{eps,i} xi_{mu,j} */
+  double X2[3][3][3] = {{{0}}};   /* [alpha][i][j] */
+  for (int al = 0; al < dim; ++al)
+    for (int i = 0; i < dim; ++i)
+      for (int j = 0; j < dim; ++j) {
+        double sum = 0.0;
+        for (int m = 0; m < dim; ++m)
+          for (int ep = 0; ep < dim; ++ep)
+            for (int mu = 0; mu < dim; ++mu) sum += Ji[al][m] * H[m][ep][mu] * Ji[ep][i] * Ji[mu][j];
+        X2[al][i][j] = -sum;
+      }
+  /* eq:dspatial and eq:ddspatial */
+  for (int a = 0; a < nloc; ++a) {
+    h->N[a] = Np[a];
+    for (int i = 0; i < 3; ++i) {
+      double g = 0.0;
+      if (i < dim)
+        for (int al = 0; al < dim; ++al) g += dNp[a][al] * Ji[al][i];
+      h->dN[a][i] = g;
+      for (int j = 0; j < 3; ++j) {
+        double v = 0.0;
+        if (i < dim && j < dim) {
+          for (int al = 0; al < dim; ++al)
+            for (int be = 0; be < dim; ++be) v += d2Np[a][al][be] * Ji[al][i] * Ji[be][j];
+          for (int al = 0; al < dim; ++al) v += dNp[a][al] * X2[al][i][j];
+        }
+        h->d2N[a][i][j] = v;
+      }
+    }
+  }
+  return 0;
+}
+
+int orc_basis_hessian(const orc_problem *pb, int64_t elem, const double *t, int64_t *A, double *N,
+                      double *dN, double *d2N, double *x) {
+  layout L;
+  if (!pb || !t || lay_init(pb, &L)) return 1;
+  int64_t ne = (int64_t)L.ne[0] * L.ne[1] * L.ne[2];
+  if (elem < 0 || elem >= ne) { lay_free(&L); return 1; }
+  int em[3];
+  elem_multi(&L, elem, em);
+  static hpoint h;
+  double tt[3] = {t[0], L.dim > 1 ? t[1] : 0.0, L.dim > 2 ? t[2] : 0.0};
+  int rc = eval_hess(pb, &L, em, tt, &h);
+  if (!rc) {
+    for (int a = 0; a < h.nloc; ++a) {
+      if (A) A[a] = h.A[a];
+      if (N) N[a] = h.N[a];
+      for (int i = 0; i < 3; ++i) {
+        if (dN) dN[a * 3 + i] = h.dN[a][i];
+        for (int j = 0; j < 3; ++j)
+          if (d2N) d2N[(a * 3 + i) * 3 + j] = h.d2N[a][i][j];
+      }
+    }
+    if (x) for (int i = 0; i < 3; ++i) x[i] = h.x[i];
+  }
+  lay_free(&L);
+  return rc;
+}
+
+/* R_A = sum over elements and Gauss points of W (Lap N_A)(Lap u_h), Lap the spatial Laplacian
+ * (trace of eq:ddspatial), W = Gauss weights * span factors * det J; all functions, no boundary
+ * rows: the fourth-order operator of a primal biharmonic / Cahn-Hilliard-type weak form. */
+int orc_biharmonic_residual(const orc_problem *pb, const double *U, double *R) {
+  layout L;
+  if (!pb || !U || !R || lay_init(pb, &L)) return 1;
+  int64_t N = (int64_t)L.n[0] * L.n[1] * L.n[2], ne = (int64_t)L.ne[0] * L.ne[1] * L.ne[2];
+  for (int64_t A = 0; A < N; ++A) R[A] = 0.0;
+  int nqt = L.nq[0] * L.nq[1] * L.nq[2];
+  static hpoint h;
+  static double lap[ORC_MAXLOC];
+  for (int64_t e = 0; e < ne; ++e) {
+    int em[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqt; ++g) {
+      int gm[3];
+      qp_multi(&L, g, gm);
+      double t[3], wq = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        t[d] = d < L.dim ? L.gx[d][gm[d]] : 0.0;
+        if (d < L.dim) wq *= L.gw[d][gm[d]];
+      }
+      int rc = eval_hess(pb, &L, em, t, &h);
+      if (rc) { lay_free(&L); return rc; }
+      double W = wq * h.span * h.detJ, lu = 0.0;
+      for (int a = 0; a < h.nloc; ++a) {
+        lap[a] = 0.0;
+        for (int i = 0; i < L.dim; ++i) lap[a] += h.d2N[a][i][i];
+        lu += U[h.A[a]] * lap[a];
+      }
+      for (int a = 0; a < h.nloc; ++a) R[h.A[a]] += W * lap[a] * lu;
+    }
+  }
+  lay_free(&L);
+  return 0;
 }

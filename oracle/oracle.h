@@ -9,6 +9,9 @@
  *   - tensor product and lexicographic numbering (Sec. 2.2),
  *   - rational basis and its first derivatives (Sec. 2.3, eq:rational, eq:drational),
  *   - geometry Jacobian, inverse and spatial gradients (App. A, eq:identity, eq:dspatial),
+ *   - second derivatives: of B-splines (the derivative formula applied twice), rational
+ *     (eq:ddrational), of the inverse map (eq:ddimap) and spatial (eq:ddspatial), and the
+ *     fourth-order operator sum W (Lap N_A)(Lap u_h) built from them,
  *   - the adjacency stencil of Algorithm 2 (Sec. 2.5),
  *   - periodic axes by unclamping (Sec. 2.4, eq:unclamp-left/right) and index wrapping (eq:map-wrap),
  *   - naive per-quadrature-point residual/Jacobian assembly as in Algorithm 3 (Sec. 2.7)
@@ -47,6 +50,8 @@ int orc_gauss_legendre(int n, double *x, double *w);
 /* eq:unclamp-left / eq:unclamp-right in place; n = index of the last basis function */
 int orc_unclamp(int n, int p, int k, double *U);
 int orc_basis_1d(int p, const double *U, int nk, int i, double xi, double *val, double *der);
+/* second derivative of B_{i,p} at xi (the derivative formula of Sec. 2.1 applied twice) */
+int orc_basis_1d_d2(int p, const double *U, int nk, int i, double xi, double *d2);
 int orc_stencil(int p, const double *U, int nk, int i, int *l, int *r);
 int orc_sizes(const orc_problem *pb, int64_t *ndof, int64_t *nelem, int64_t *nnz);
 int orc_csr_pattern(const orc_problem *pb, int64_t *row_ptr, int32_t *col_idx);
@@ -73,6 +78,14 @@ int orc_qp_data(const orc_problem *pb, const double *U, double *xq, double *Wq, 
 int orc_load_vector(const orc_problem *pb, const double *fq, double *b);
 int orc_mass_matrix(const orc_problem *pb, const int64_t *row_ptr, const int32_t *col_idx,
                     double *vals);
+/* At local coordinates t in [-1,1]^dim of element elem: the nloc = prod(p_d+1) local functions'
+ * global indices A, values N, spatial gradients dN [nloc][3] and spatial Hessians d2N [nloc][3][3]
+ * (eq:ddrational, eq:ddimap read with the sign that differentiating eq:identity gives,
+ * eq:ddspatial), and the point x [3].  Any output may be NULL. */
+int orc_basis_hessian(const orc_problem *pb, int64_t elem, const double *t, int64_t *A, double *N,
+                      double *dN, double *d2N, double *x);
+/* R_A = sum_e sum_q W (Lap N_A)(Lap u_h) over every function (no boundary rows). */
+int orc_biharmonic_residual(const orc_problem *pb, const double *U, double *R);
 
 #ifdef __cplusplus
 }
