@@ -208,6 +208,32 @@ def bench_periodic(nel: int = 64, p: int = 3):
     return res
 
 
+def bench_fourth_order():
+    """The fourth-order operator sum W (Lap N_A)(Lap u_h) from second spatial derivatives
+    (iga_biharmonic_residual) on the thick quarter cylinder 48^3, p = 2 (exact NURBS) and the unit
+    cube 64^3, p = 3, on a seeded vector."""
+    import torch
+
+    import inputs
+    import paper_1305_4452_amd as iga
+    out = {}
+    for key, patch in [("cylinder_48_p2", inputs.quarter_cylinder(48, 2, dim=3)), ("cube_64_p3", inputs.unit_box(3, 64, 3))]:
+        g = iga.IGA(patch.knots, patch.degree, ctrl=patch.ctrl, weights=patch.weights)
+        U = torch.as_tensor(inputs.uniform(3, 0, g.N, -1.0, 1.0), device="cuda")
+        R = torch.empty_like(U)
+        g.biharmonic_residual(U, R)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            g.biharmonic_residual(U, R)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 3
+        out[key] = dict(ndof=g.N, nelem=g.E, ms=ms, elements_per_s=g.E / (ms * 1e-3))
+        print(f"[bench] fourth-order operator {key}: {ms:.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_cylinder(nel: int, degrees):
     """Nonlinear diffusion on the thick quarter cylinder (exact NURBS, kappa = exp(GRF) at the
     control points): Jacobian assembly (general row-gather, FP64 and FP32 values) and Newton to
@@ -296,6 +322,7 @@ def main():
     ap.add_argument("--batch-n", type=int, default=512)
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-periodic", action="store_true")
+    ap.add_argument("--no-fourth-order", action="store_true")
     ap.add_argument("--learned-train", type=int, default=2000, help="0 skips the learned-guess section")
     ap.add_argument("--learned-test", type=int, default=300)
     ap.add_argument("--learned-epochs", type=int, default=12)
@@ -463,6 +490,9 @@ def main():
     periodic = None
     if not args.no_periodic:
         periodic = bench_periodic()
+    fourth = None
+    if not args.no_fourth_order:
+        fourth = bench_fourth_order()
     learned = None
     if args.learned_train > 0:
         from paper_1305_4452_amd import learned as lg
@@ -519,6 +549,7 @@ def main():
         "batched": batched,
         "cylinder": cylinder,
         "periodic": periodic,
+        "fourth_order_operator": fourth,
         "learned_guess": learned,
         "paper_context": {"explicit_jacobian_s": 15.41, "procs": 16, "hw": "2x Xeon E5-2680 v2",
                           "dof_per_s": 300763 / 15.41},

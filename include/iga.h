@@ -162,6 +162,17 @@ iga_status iga_assemble_residual(iga_t h, const double *U_dev, double *R_dev);
  * Every entry is written: no zeroing is needed. */
 iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, int prec);
 
+/* Fourth-order operator from second spatial derivatives: R_A = sum_e sum_q W (Lap N_A)(Lap u_h)
+ * for every function A (no Dirichlet rows), W the Gauss weight times the span factors and det J,
+ * Lap N_A the trace of eq:ddspatial with the rational second derivatives of eq:ddrational and
+ * the inverse-map derivatives of eq:ddimap (read with the minus sign that differentiating
+ * eq:identity gives).  This is the principal part of a primal biharmonic / Cahn-Hilliard weak
+ * form (the Cahn-Hilliard example).  U_dev, R_dev: N doubles on the device, natural order; R is
+ * overwritten.
+ * Needs p >= 2; p <= 6 in 2D and p <= 3 in 3D (IGA_EUNSUPPORTED otherwise).  Asynchronous on
+ * the handle's stream. */
+iga_status iga_biharmonic_residual(iga_t h, const double *U_dev, double *R_dev);
+
 /* y = J(U) v without forming J (exact linearisation, same Dirichlet convention). */
 iga_status iga_apply(iga_t h, const double *U_dev, const double *v_dev, double *y_dev);
 

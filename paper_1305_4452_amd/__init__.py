@@ -118,6 +118,7 @@ _SIGNATURES = {
     "iga_set_option": ([C.c_void_p, C.c_int, C.c_int64], C.c_int),
     "iga_csr_pattern": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_assemble_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "iga_biharmonic_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_assemble_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "iga_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_spmv": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
@@ -297,6 +298,13 @@ class IGA:
         import torch
         _check(load().iga_assemble_residual(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
                                             _dev_ptr(R, torch.float64, self.N, "R")), "iga_assemble_residual")
+        return R
+
+    def biharmonic_residual(self, U, R):
+        """R_A = sum W (Lap N_A)(Lap u_h) over every function (iga_biharmonic_residual)."""
+        import torch
+        _check(load().iga_biharmonic_residual(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
+                                              _dev_ptr(R, torch.float64, self.N, "R")), "iga_biharmonic_residual")
         return R
 
     def assemble_jacobian(self, U, vals, prec=IGA_FP64):

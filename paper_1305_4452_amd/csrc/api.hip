@@ -308,6 +308,11 @@ iga_status iga_assemble_residual(iga_t hh, const double *U, double *R) {
   return launch_residual(*(Handle *)hh, U, R);
 }
 
+iga_status iga_biharmonic_residual(iga_t hh, const double *U, double *R) {
+  if (!hh || !U || !R) return fail(IGA_EINVAL, "null argument");
+  return launch_biharmonic(*(Handle *)hh, U, R);
+}
+
 iga_status iga_assemble_jacobian(iga_t hh, const double *U, void *vals, int prec) {
   if (!hh || !U || !vals) return fail(IGA_EINVAL, "null argument");
   if (prec != IGA_FP64 && prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian values are FP64 or FP32");

@@ -1,0 +1,208 @@
+// Fourth-order operator from second spatial derivatives (Sec. 2.3 eq:ddrational; App. A
+// eq:identity, eq:ddimap, eq:ddspatial):
+//
+//   R_A = sum_e sum_q W (Lap N_A)(Lap u_h),   Lap u_h = sum_B U_B Lap N_B,
+//
+// W = Gauss weight x span factors x det J, over every function (no boundary rows): the principal
+// part of a primal biharmonic / Cahn-Hilliard weak form.
+//
+// One 64-lane workgroup per element, one lane per Gauss point (Q^d <= 64).  A lane forms at its
+// point, from the element's 1D value / first / second derivative tables staged in LDS:
+//   * the weight w and its parametric derivatives (rational bases);
+//   * the map's parametric derivatives x_{i,alpha} and x_{i,alpha beta} from the control points,
+//     its inverse xi_{alpha,i} (eq:identity) and xi_{alpha,ij} = -xi_{alpha,m} x_{m,eps mu}
+//     xi_{eps,i} xi_{mu,j} (eq:ddimap, with the sign that differentiating eq:identity gives);
+//   * Lap N_A = N_{A,alpha beta} xi_{alpha,i} xi_{beta,i} + N_{A,alpha} xi_{alpha,ii} for every
+//     local function (eq:ddspatial, traced), kept in LDS, and W Lap u_h.
+// The element's contributions sum_q Lap N_A(q) W Lap u_h(q) are added with one FP64 atomic per
+// local function.  Without control points x = xi (the inverse map is the identity).
+#include "iga_impl.h"
+
+namespace iga {
+namespace {
+
+constexpr int hpow(int b, int e) { return e == 0 ? 1 : b * hpow(b, e - 1); }
+
+template <int DIM, int P>
+__global__ void __launch_bounds__(64) k_biharmonic(DevProblem pb, const double *__restrict__ U,
+                                                   double *__restrict__ R) {
+  constexpr int Q = P, L = hpow(P, DIM), QD = hpow(Q, DIM);
+  static_assert(QD <= 64 && L <= 64, "one lane per Gauss point and per local function");
+  __shared__ double tb[3][3][Q][P];   // [axis][value | d/dxi | d2/dxi2][q][a]
+  __shared__ double tw[3][Q];
+  __shared__ double sU[L], sW[L], sX[L][3];
+  __shared__ int64_t sA[L];
+  __shared__ double sLap[L][QD + 1];
+  __shared__ double sLu[QD];
+  const int t = threadIdx.x;
+  const int64_t e = blockIdx.x;
+  int em[3] = {(int)(e % pb.ne[0]), (int)((e / pb.ne[0]) % pb.ne[1]), (int)(e / ((int64_t)pb.ne[0] * pb.ne[1]))};
+  for (int d = 0; d < 3; ++d) {
+    for (int i = t; i < 3 * Q * P; i += 64) {
+      const int kind = i / (Q * P), r = i % (Q * P);
+      double v = (kind == 0 && r % P == 0) ? 1.0 : 0.0;   // axes beyond dim: the constant function
+      if (d < DIM) {
+        const size_t o = (size_t)em[d] * Q * P + r;
+        v = kind == 0 ? pb.ax[d].B[o] : kind == 1 ? pb.ax[d].dB[o] : pb.ax[d].d2B[o];
+      }
+      (&tb[d][0][0][0])[i] = v;
+    }
+    if (t < Q) tw[d][t] = d < DIM ? pb.ax[d].wq[(size_t)em[d] * Q + t] : (t == 0 ? 1.0 : 0.0);
+  }
+  for (int a = t; a < L; a += 64) {
+    const int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / (P * P) : 0;
+    const int i0 = wrap_fn(pb.ax[0], pb.ax[0].efirst[em[0]] + a0);
+    const int i1 = wrap_fn(pb.ax[1], pb.ax[1].efirst[em[1]] + a1);
+    const int i2 = DIM == 3 ? wrap_fn(pb.ax[2], pb.ax[2].efirst[em[2]] + a2) : 0;
+    const int64_t A = i0 + (int64_t)pb.n[0] * (i1 + (int64_t)pb.n[1] * i2);
+    sA[a] = A;
+    sU[a] = U[A];
+    sW[a] = pb.wts ? pb.wts[A] : 1.0;
+    for (int i = 0; i < 3; ++i) sX[a][i] = (pb.ctrl && i < DIM) ? pb.ctrl[A * DIM + i] : 0.0;
+  }
+  __syncthreads();
+
+  if (t < QD) {
+    const int qi[3] = {t % Q, (t / Q) % Q, DIM == 3 ? t / (Q * Q) : 0};
+    // tensor-product value, first and second parametric derivatives of local function a
+    auto tens = [&](int a, double &m, double *dm, double (*d2m)[3]) {
+      const int ai[3] = {a % P, (a / P) % P, DIM == 3 ? a / (P * P) : 0};
+      double v[3][3];   // [axis][order]
+      for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < 3; ++k) v[d][k] = (d < DIM || k == 0) ? tb[d][k][qi[d]][ai[d]] : 0.0;
+      m = v[0][0] * v[1][0] * v[2][0];
+      for (int al = 0; al < 3; ++al) {
+        double s = 1.0;
+        for (int d = 0; d < 3; ++d) s *= v[d][d == al ? 1 : 0];
+        dm[al] = s;
+        for (int be = 0; be < 3; ++be) {
+          double s2 = 1.0;
+          for (int d = 0; d < 3; ++d) s2 *= v[d][(d == al) + (d == be)];
+          d2m[al][be] = s2;
+        }
+      }
+    };
+    // weight function and its derivatives (eq:rational)
+    double w = 1.0, dw[3] = {0, 0, 0}, d2w[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (pb.wts) {
+      w = 0.0;
+      for (int a = 0; a < L; ++a) {
+        double m, dm[3], d2m[3][3];
+        tens(a, m, dm, d2m);
+        w += sW[a] * m;
+        for (int al = 0; al < 3; ++al) {
+          dw[al] += sW[a] * dm[al];
+          for (int be = 0; be < 3; ++be) d2w[al][be] += sW[a] * d2m[al][be];
+        }
+      }
+    }
+    // rational value, first and second parametric derivatives (eq:rational, eq:drational,
+    // eq:ddrational)
+    auto rat = [&](int a, double &n, double *dn, double (*d2n)[3]) {
+      double m, dm[3], d2m[3][3];
+      tens(a, m, dm, d2m);
+      const double wa = sW[a];
+      n = wa * m / w;
+      for (int al = 0; al < 3; ++al) dn[al] = (wa * dm[al] - n * dw[al]) / w;
+      for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be)
+          d2n[al][be] = (wa * d2m[al][be] - n * d2w[al][be]) / w - (dn[be] * dw[al] + dn[al] * dw[be]) / w;
+    };
+    // the map's parametric derivatives, its inverse (eq:identity) and eq:ddimap
+    double J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, H[3][3][3] = {};
+    if (pb.ctrl) {
+      for (int i = 0; i < DIM; ++i)
+        for (int al = 0; al < DIM; ++al) J[i][al] = 0.0;
+      for (int a = 0; a < L; ++a) {
+        double n, dn[3], d2n[3][3];
+        rat(a, n, dn, d2n);
+        for (int i = 0; i < DIM; ++i)
+          for (int al = 0; al < DIM; ++al) {
+            J[i][al] += sX[a][i] * dn[al];
+            for (int be = 0; be < DIM; ++be) H[i][al][be] += sX[a][i] * d2n[al][be];
+          }
+      }
+    }
+    double det, Ji[3][3] = {};
+    if (DIM == 2) {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      Ji[0][0] = J[1][1] / det;
+      Ji[0][1] = -J[0][1] / det;
+      Ji[1][0] = -J[1][0] / det;
+      Ji[1][1] = J[0][0] / det;
+    } else {
+      det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+          Ji[r][c] = (J[r1][c1] * J[r2][c2] - J[r1][c2] * J[r2][c1]) / det;
+        }
+    }
+    // only the trace over i is needed: G[al][be] = sum_i xi_{al,i} xi_{be,i} and
+    // h[al] = xi_{al,ii} = - xi_{al,m} x_{m,eps mu} G[eps][mu]
+    double G[3][3] = {}, hv[3] = {};
+    for (int al = 0; al < DIM; ++al)
+      for (int be = 0; be < DIM; ++be)
+        for (int i = 0; i < DIM; ++i) G[al][be] += Ji[al][i] * Ji[be][i];
+    for (int al = 0; al < DIM; ++al) {
+      double s = 0.0;
+      for (int m = 0; m < DIM; ++m)
+        for (int ep = 0; ep < DIM; ++ep)
+          for (int mu = 0; mu < DIM; ++mu) s += Ji[al][m] * H[m][ep][mu] * G[ep][mu];
+      hv[al] = -s;
+    }
+    double lu = 0.0;
+    for (int a = 0; a < L; ++a) {
+      double n, dn[3], d2n[3][3];
+      rat(a, n, dn, d2n);
+      double lap = 0.0;
+      for (int al = 0; al < DIM; ++al) {
+        lap += dn[al] * hv[al];
+        for (int be = 0; be < DIM; ++be) lap += d2n[al][be] * G[al][be];
+      }
+      sLap[a][t] = lap;
+      lu += sU[a] * lap;
+    }
+    sLu[t] = tw[0][qi[0]] * tw[1][qi[1]] * tw[2][qi[2]] * det * lu;
+  }
+  __syncthreads();
+  for (int a = t; a < L; a += 64) {
+    double r = 0.0;
+    for (int q = 0; q < QD; ++q) r += sLap[a][q] * sLu[q];
+    atomicAdd(&R[sA[a]], r);
+  }
+}
+
+template <int DIM, int P>
+iga_status run_bih(Handle &h, const double *U, double *R) {
+  hipLaunchKernelGGL((k_biharmonic<DIM, P>), dim3((unsigned)h.pb.E), dim3(64), 0, h.stream, h.pb, U, R);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+}  // namespace
+
+iga_status launch_biharmonic(Handle &h, const double *U, double *R) {
+  const int p = h.pb.p;
+  if (p < 2) return fail(IGA_EUNSUPPORTED, "the fourth-order operator needs p >= 2");
+  iga_status st = launch_fill(h, R, h.pb.N, 0.0);
+  if (st) return st;
+  if (h.pb.dim == 2) {
+    switch (p) {
+      case 2: return run_bih<2, 3>(h, U, R);
+      case 3: return run_bih<2, 4>(h, U, R);
+      case 4: return run_bih<2, 5>(h, U, R);
+      case 5: return run_bih<2, 6>(h, U, R);
+      case 6: return run_bih<2, 7>(h, U, R);
+    }
+  } else {
+    switch (p) {
+      case 2: return run_bih<3, 3>(h, U, R);
+      case 3: return run_bih<3, 4>(h, U, R);
+    }
+  }
+  return fail(IGA_EUNSUPPORTED, "the fourth-order operator supports p <= 6 in 2D and p <= 3 in 3D");
+}
+
+}  // namespace iga

@@ -30,6 +30,7 @@ struct AxisDev {
   const int *stw;      // [n]          Algorithm 2 width r - l + 1
   int nper;            // periodic axis: its number of functions (indices wrap); 0 on an open axis
   const int *nbr;      // periodic axis: [n][2p+1] sorted functions sharing an element with each one
+  const double *d2B;   // [ne][Q][P]   d2/dxi2 (the fourth-order operator)
 };
 
 // eq:map-wrap for the local-to-global index of an element function (i < 2 nper here)
@@ -50,6 +51,7 @@ struct DevProblem {
   const double *kel;   // element kappa (analytic mode, kappa_mode ELEMENT)
   const double *geo;   // table mode: [E][geo_streams][Q^dim]
   const double *wts;   // [N] or null
+  const double *ctrl;  // [N][dim] control points (kept when given) or null: x = xi
   const double *src;   // [N] or null
   unsigned dmask;
   int simple_knots;    // every element's first function equals its span counter (max continuity)
@@ -226,6 +228,7 @@ iga_status launch_geometry(Handle &h, const double *ctrl, const double *wts, con
 iga_status launch_pattern(Handle &h);
 iga_status launch_residual(Handle &h, const double *U, double *R);
 iga_status launch_linearize(Handle &h, const double *U);
+iga_status launch_biharmonic(Handle &h, const double *U, double *R);
 iga_status launch_apply(Handle &h, const double *v, double *y);
 iga_status launch_diag_mf(Handle &h, double *diag);
 iga_status launch_elem_matrices(Handle &h, const double *U, const int32_t *elems, int n, int prec,

@@ -77,6 +77,22 @@ static void basis_and_derivative(const double *U, int s, int p, double xi, doubl
   }
 }
 
+// Second derivatives of the p+1 non-zero functions on span s: the derivative formula applied to
+// the first derivatives of the degree p-1 functions (zero for p = 1).
+static void basis_second_derivative(const double *U, int s, int p, double xi, double *d2N) {
+  double low[kMaxP + 1] = {0}, dlow[kMaxP + 1] = {0};
+  if (p >= 2) basis_and_derivative(U, s, p - 1, xi, low, dlow);
+  for (int j = 0; j <= p; ++j) {
+    int m = s - p + j;
+    double d = 0.0;
+    if (p >= 2) {
+      if (j >= 1) d += dlow[j - 1] / (U[m + p] - U[m]);
+      if (j <= p - 1) d -= dlow[j] / (U[m + p + 1] - U[m + 1]);
+    }
+    d2N[j] = p * d;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Device kernels used once at creation
 // ------------------------------------------------------------------------------------------
@@ -391,7 +407,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     const double *U = h->hknots[a].data();
     int n = nk - p - 1;
     std::vector<int> efirst;
-    std::vector<double> B, dB, wq;
+    std::vector<double> B, dB, d2B, wq;
     for (int s = p; s < n; ++s) {
       if (!(U[s] < U[s + 1])) continue;
       int e = (int)efirst.size();
@@ -401,8 +417,10 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       for (int q = 0; q < pb.Q; ++q) {
         double xi = 0.5 * (lo + hi) + 0.5 * (hi - lo) * gx[q];
         double N[kMaxP], dN[kMaxP];
+        double d2N[kMaxP];
         basis_and_derivative(U, s, p, xi, N, dN);
-        for (int j = 0; j <= p; ++j) { B.push_back(N[j]); dB.push_back(dN[j]); }
+        basis_second_derivative(U, s, p, xi, d2N);
+        for (int j = 0; j <= p; ++j) { B.push_back(N[j]); dB.push_back(dN[j]); d2B.push_back(d2N[j]); }
         wq.push_back(gw[q] * 0.5 * (hi - lo));
       }
     }
@@ -479,7 +497,12 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       iga_destroy((iga_t)h);
       return st;
     }
-    pb.ax[a] = AxisDev{d_B, d_dB, d_wq, d_ef, d_stl, d_stw, 0, nullptr};
+    double *d_d2B;
+    if ((st = dev_upload(*h, &d_d2B, d2B.data(), d2B.size()))) {
+      iga_destroy((iga_t)h);
+      return st;
+    }
+    pb.ax[a] = AxisDev{d_B, d_dB, d_wq, d_ef, d_stl, d_stw, 0, nullptr, d_d2B};
     if (kper >= 0) {
       int *d_nbr;
       if ((st = dev_upload(*h, &d_nbr, nbr[a].data(), nbr[a].size()))) {
@@ -547,6 +570,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   if ((st = dev_alloc(*h, &h->partials, (size_t)h->npartials * 4))) { iga_destroy((iga_t)h); return st; }
   if (pb.table) {
     if (d->ctrl && (st = dev_upload(*h, &d_ctrl, d->ctrl, (size_t)pb.N * dim))) { iga_destroy((iga_t)h); return st; }
+    pb.ctrl = d_ctrl;
     if (d->kappa_mode == IGA_KAPPA_NODAL && (st = dev_upload(*h, &d_kn, d->kappa, (size_t)pb.N))) {
       iga_destroy((iga_t)h);
       return st;
