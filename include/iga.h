@@ -78,7 +78,8 @@ typedef enum {
                                 by colour with plain adds ((p+1)^d launches, no two workgroups of a
                                 launch share a value) */
   IGA_OPT_TILED_3D = 8       /* 3D residual and matrix-free apply with x = xi, no weights, no source:
-                                1 by tiles of elements (default), 0 one element per workgroup */
+                                1 by tiles of elements (default), 0 one element per workgroup; also the
+                                fourth-order operator on x = xi without weights */
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):
@@ -169,8 +170,8 @@ iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, i
  * eq:identity gives).  This is the principal part of a primal biharmonic / Cahn-Hilliard weak
  * form (the Cahn-Hilliard example).  U_dev, R_dev: N doubles on the device, natural order; R is
  * overwritten.
- * Needs p >= 2; p <= 6 in 2D and p <= 3 in 3D (IGA_EUNSUPPORTED otherwise).  Asynchronous on
- * the handle's stream. */
+ * Needs p >= 2; p <= 6 in 2D and p <= 3 in 3D, p <= 4 in 3D on x = xi without weights
+ * (IGA_EUNSUPPORTED otherwise).  Asynchronous on the handle's stream. */
 iga_status iga_biharmonic_residual(iga_t h, const double *U_dev, double *R_dev);
 
 /* y = J(U) v without forming J (exact linearisation, same Dirichlet convention). */

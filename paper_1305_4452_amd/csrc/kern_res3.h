@@ -235,5 +235,153 @@ __device__ inline void res3_body(const DevProblem &pb, const int tile, const dou
   }
 }
 
+// Fourth-order operator on x = xi without weights (tiles as above): R_A = sum_q W (Lap N_A)(Lap u_h)
+// with Lap N_A = N''_{a0} N_{a1} N_{a2} + N_{a0} N''_{a1} N_{a2} + N_{a0} N_{a1} N''_{a2}.  Forward:
+// axis 0 gives B.c and B''.c, axis 1 the three products needed, axis 2 the Laplacian at every
+// point, S = W Lap u_h; transposed: axis 2 gives B.S and B''.S, axis 1 the two sums that axis 0
+// closes with B'' and B.  One FP64 atomic per tile function; the output must be zeroed before.
+template <int P>
+__device__ inline void bih3_body(const DevProblem &pb, const int tile, const double *__restrict__ X,
+                                 double *__restrict__ Y, double *__restrict__ lds) {
+  using S_ = Res3<P>;
+  constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G;
+  constexpr int NT = kThreads, GP = G * P;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
+  const int nt0 = (ne0 + TE - 1) / TE, nt1 = (ne1 + TE - 1) / TE;
+  const int E0 = (tile % nt0) * TE, E1 = ((tile / nt0) % nt1) * TE, E2 = (tile / (nt0 * nt1)) * TE;
+  const int NE0 = min(TE, ne0 - E0), NE1 = min(TE, ne1 - E1), NE2 = min(TE, ne2 - E2);
+  const int G0 = NE0 * Q, G1 = NE1 * Q, G2 = NE2 * Q;
+  const int NI0 = NE0 + p, NI1 = NE1 + p, NI2 = NE2 + p;
+  double *c = lds;                                       // [k2][k1][k0]
+  double *A0 = c + S_::n_c, *D0 = A0 + S_::n_a;          // [k2][k1][g0]: B.c, B''.c along axis 0
+  double *V1 = D0 + S_::n_a, *W1 = V1 + S_::n_u, *X1 = W1 + S_::n_u;   // [k2][g1][g0]
+  double *Sg = X1 + S_::n_u;                             // [g2][g1][g0]
+  double *YB = V1, *YD = W1, *Z1 = A0, *Z2 = D0;
+  double *sB = Sg + 4 * S_::n_f, *sW = sB + 6 * GP;      // the residual's table slots: [axis][B|B''][G][P]
+  const double *B0 = sB, *C0 = sB + GP, *B1 = sB + 2 * GP, *C1 = sB + 3 * GP, *B2 = sB + 4 * GP,
+               *C2 = sB + 5 * GP;
+  const double *Wq0 = sW, *Wq1 = sW + G, *Wq2 = sW + 2 * G;
+  const int t = threadIdx.x;
+
+  auto stage_axis = [&](const AxisDev &ax, int E, int Gd, double *dst, double *wdst) {
+    for (int i = t; i < GP; i += NT) {
+      if (i / P < Gd) {
+        dst[i] = ax.B[(size_t)E * Q * P + i];
+        dst[GP + i] = ax.d2B[(size_t)E * Q * P + i];
+      }
+    }
+    for (int i = t; i < G; i += NT)
+      if (i < Gd) wdst[i] = ax.wq[(size_t)E * Q + i];
+  };
+  stage_axis(pb.ax[0], E0, G0, sB, sW);
+  stage_axis(pb.ax[1], E1, G1, sB + 2 * GP, sW + G);
+  stage_axis(pb.ax[2], E2, G2, sB + 4 * GP, sW + 2 * G);
+  for (int i = t; i < NI * NI * NI; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+    const int i0 = wrap_fn(pb.ax[0], E0 + k0), i1 = wrap_fn(pb.ax[1], E1 + k1), i2 = wrap_fn(pb.ax[2], E2 + k2);
+    c[i] = X[i0 + (int64_t)n0 * (i1 + (int64_t)n1 * i2)];
+  }
+  __syncthreads();
+  for (int i = t; i < NI * NI * G; i += NT) {
+    const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), el0 = g0 / Q;
+    if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+    const double *cc = c + (k2 * NI + k1) * NI + el0;
+    double a = 0, d = 0;
+#pragma unroll
+    for (int a0 = 0; a0 < P; ++a0) {
+      a += B0[g0 * P + a0] * cc[a0];
+      d += C0[g0 * P + a0] * cc[a0];
+    }
+    A0[i] = a;
+    D0[i] = d;
+  }
+  __syncthreads();
+  for (int i = t; i < NI * G * G; i += NT) {
+    const int g0 = i % G, g1 = (i / G) % G, k2 = i / (G * G), el1 = g1 / Q;
+    if (g0 >= G0 || g1 >= G1 || k2 >= NI2) continue;
+    double v = 0, w = 0, x = 0;
+#pragma unroll
+    for (int a1 = 0; a1 < P; ++a1) {
+      const int r = (k2 * NI + el1 + a1) * G + g0;
+      v += B1[g1 * P + a1] * A0[r];
+      w += C1[g1 * P + a1] * A0[r];
+      x += B1[g1 * P + a1] * D0[r];
+    }
+    V1[i] = v;    // B B
+    W1[i] = w;    // B B''  (second derivative along axis 1)
+    X1[i] = x;    // B'' B  (second derivative along axis 0)
+  }
+  __syncthreads();
+  for (int i = t; i < G * G * G; i += NT) {
+    const int g0 = i % G, g1 = (i / G) % G, g2 = i / (G * G), el2 = g2 / Q;
+    if (g0 >= G0 || g1 >= G1 || g2 >= G2) continue;
+    double lap = 0;
+#pragma unroll
+    for (int a2 = 0; a2 < P; ++a2) {
+      const int r = ((el2 + a2) * G + g1) * G + g0;
+      lap += B2[g2 * P + a2] * (X1[r] + W1[r]) + C2[g2 * P + a2] * V1[r];
+    }
+    Sg[i] = Wq0[g0] * Wq1[g1] * Wq2[g2] * lap;
+  }
+  __syncthreads();
+  for (int i = t; i < NI * G * G; i += NT) {
+    const int g0 = i % G, g1 = (i / G) % G, k2 = i / (G * G);
+    if (g0 >= G0 || g1 >= G1 || k2 >= NI2) continue;
+    double yb = 0, yd = 0;
+#pragma unroll
+    for (int a2 = 0; a2 <= p; ++a2) {
+      const int el2 = k2 - a2;
+      if (el2 < 0 || el2 >= NE2) continue;
+#pragma unroll
+      for (int q2 = 0; q2 < Q; ++q2) {
+        const int g2 = el2 * Q + q2, w = (g2 * G + g1) * G + g0;
+        yb += B2[g2 * P + a2] * Sg[w];
+        yd += C2[g2 * P + a2] * Sg[w];
+      }
+    }
+    YB[i] = yb;
+    YD[i] = yd;
+  }
+  __syncthreads();
+  for (int i = t; i < NI * NI * G; i += NT) {
+    const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI);
+    if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+    double z1 = 0, z2 = 0;
+#pragma unroll
+    for (int a1 = 0; a1 <= p; ++a1) {
+      const int el1 = k1 - a1;
+      if (el1 < 0 || el1 >= NE1) continue;
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1) {
+        const int g1 = el1 * Q + q1, w = (k2 * G + g1) * G + g0;
+        z1 += B1[g1 * P + a1] * YB[w];
+        z2 += C1[g1 * P + a1] * YB[w] + B1[g1 * P + a1] * YD[w];
+      }
+    }
+    Z1[i] = z1;
+    Z2[i] = z2;
+  }
+  __syncthreads();
+  for (int i = t; i < NI * NI * NI; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+    double r = 0;
+#pragma unroll
+    for (int a0 = 0; a0 <= p; ++a0) {
+      const int el0 = k0 - a0;
+      if (el0 < 0 || el0 >= NE0) continue;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) {
+        const int g0 = el0 * Q + q0, w = (k2 * NI + k1) * G + g0;
+        r += C0[g0 * P + a0] * Z1[w] + B0[g0 * P + a0] * Z2[w];
+      }
+    }
+    atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
+                 (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], E2 + k2))],
+              r);
+  }
+}
+
 }  // namespace rs3
 }  // namespace iga

@@ -32,16 +32,25 @@ CASES = {
     "cylinder_p2": lambda: (inputs.quarter_cylinder([3, 4, 2], 2, dim=3), True, None),
     "cylinder_p3": lambda: (inputs.quarter_cylinder([2, 3, 2], 3, dim=3), True, None),
     "box2_p3_periodic_x": lambda: (inputs.unit_box(2, [7, 5], 3), False, [2, None]),
+    "box3_p3_ragged_tiles": lambda: (inputs.unit_box(3, [7, 5, 6], 3), False, None),
+    "box3_p4": lambda: (inputs.unit_box(3, [3, 4, 2], 4), False, None),
+    "box3_p2_periodic_y": lambda: (inputs.unit_box(3, [5, 7, 4], 2), False, [None, 1, None]),
 }
 
 
+@pytest.mark.parametrize("tiled", [1, 0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_biharmonic_operator_matches_oracle(name):
-    print(f"[case] fourth-order operator {name}", flush=True)
+def test_biharmonic_operator_matches_oracle(name, tiled):
+    """tiled = 1: on x = xi without weights in 3D the sum-factorised tile kernel runs (the default);
+    tiled = 0 keeps one element per workgroup (which has no 3D p = 4)."""
+    print(f"[case] fourth-order operator {name} tiled={tiled}", flush=True)
     patch, mapped, per = CASES[name]()
+    if not tiled and len(patch.knots) == 3 and patch.degree[0] > 3:
+        pytest.skip("one element per workgroup covers p <= 3 in 3D")
     ctrl = patch.ctrl if mapped is True else None
     weights = patch.weights if mapped else None
     g = iga.IGA(patch.knots, patch.degree, ctrl=ctrl, weights=weights, periodic=per)
+    g.set_option(iga.IGA_OPT_TILED_3D, tiled)
     o = oracle.Oracle(patch.knots, patch.degree, ctrl=ctrl, weights=weights, periodic=per)
     assert g.N == o.N
     for stream in range(2):
@@ -68,8 +77,8 @@ def test_biharmonic_operator_is_zero_for_linear_functions_of_x():
 
 
 def test_biharmonic_operator_rejects_unsupported_degrees():
-    for patch in (inputs.unit_box(2, 4, 1), inputs.unit_box(3, 2, 4)):
-        g = iga.IGA(patch.knots, patch.degree)
+    for patch in (inputs.unit_box(2, 4, 1), inputs.quarter_cylinder(2, 4, dim=3), inputs.unit_box(3, 2, 5)):
+        g = iga.IGA(patch.knots, patch.degree, ctrl=patch.ctrl, weights=patch.weights)
         x = torch.zeros(g.N, dtype=torch.float64, device="cuda")
         with pytest.raises(iga.IGAError) as ei:
             g.biharmonic_residual(x, torch.empty_like(x))
