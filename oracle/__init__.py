@@ -79,6 +79,9 @@ def lib():
             "orc_basis_1d_d2": [C.c_int, _dp, C.c_int, C.c_int, C.c_double, _dp],
             "orc_basis_hessian": [P, C.c_int64, _dp, _i64p, _dp, _dp, _dp, _dp],
             "orc_biharmonic_residual": [P, _dp, _dp],
+            "orc_gen_alpha_params": [C.c_double, _dp, _dp, _dp],
+            "orc_gen_alpha_step": [P, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int, _dp, _dp,
+                                   C.POINTER(C.c_int)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -88,6 +91,14 @@ def lib():
         L.orc_nqp.restype = C.c_int64
         _lib = L
     return _lib
+
+
+def gen_alpha_params(rho):
+    """(alpha_m, alpha_f, gamma) of generalized-alpha from the spectral radius at infinity."""
+    am, af, g = C.c_double(), C.c_double(), C.c_double()
+    if lib().orc_gen_alpha_params(float(rho), C.byref(am), C.byref(af), C.byref(g)):
+        raise ValueError("rho must be in [0, 1]")
+    return am.value, af.value, g.value
 
 
 def _ptr(a, t=_dp):
@@ -184,6 +195,16 @@ class Oracle:
         R = np.zeros(self.N)
         self._chk(lib().orc_biharmonic_residual(C.byref(self.pb), _ptr(U), _ptr(R)), "biharmonic_residual")
         return R
+
+    def gen_alpha_step(self, U0, V0, dt, rho, atol=1e-12, maxit=30):
+        """One generalized-alpha step (eq:ga) of M0 Udot + R(U) = 0: returns (U1, V1, Newton iterations)."""
+        U0 = np.ascontiguousarray(U0, dtype=np.float64)
+        V0 = np.ascontiguousarray(V0, dtype=np.float64)
+        U1, V1 = np.zeros(self.N), np.zeros(self.N)
+        it = C.c_int(0)
+        self._chk(lib().orc_gen_alpha_step(C.byref(self.pb), _ptr(U0), _ptr(V0), float(dt), float(rho), float(atol),
+                                           int(maxit), _ptr(U1), _ptr(V1), C.byref(it)), "gen_alpha_step")
+        return U1, V1, it.value
 
     def residual(self, U):
         U = np.ascontiguousarray(U, dtype=np.float64)

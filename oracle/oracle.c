@@ -786,6 +786,7 @@ static int banded_solve(int64_t N, const int64_t *rp, const int32_t *ci, const d
       if (d > bw) bw = d;
     }
   int64_t W = 2 * bw + 1;
+  if (N <= 0 || N > INT64_MAX / W) return 2;
   double *band = (double *)calloc((size_t)(N * W), sizeof(double));
   if (!band) return 2;
 #define BAND(i, j) band[(i) * W + ((j) - (i) + bw)]
@@ -1216,4 +1217,73 @@ int orc_biharmonic_residual(const orc_problem *pb, const double *U, double *R) {
   }
   lay_free(&L);
   return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Generalized-alpha time stepping (eq:ga) for first-order systems R(Udot, U) = 0         */
+/* ------------------------------------------------------------------------------------ */
+int orc_gen_alpha_params(double rho, double *am, double *af, double *gamma) {
+  if (!(rho >= 0.0 && rho <= 1.0) || !am || !af || !gamma) return 1;
+  *am = 0.5 * (3.0 - rho) / (1.0 + rho);
+  *af = 1.0 / (1.0 + rho);
+  *gamma = 0.5 + *am - *af;
+  return 0;
+}
+
+/* One step for R(Udot, U) = M0 Udot + R_B(U): R_B the residual of eq:residual (Dirichlet rows U_A),
+ * M0 the mass matrix with the rows and columns of Dirichlet functions removed.  Unknown Udot_{n+1},
+ * by Newton on G = M0 Udot_{n+am} + R_B(U_{n+af}) (eq:ga), dG/dUdot_{n+1} = am M0 + af gamma dt
+ * J(U_{n+af}), each linear system solved exactly (banded LU in 2D, CG to 1e-14 in 3D); starts from
+ * Udot_{n+1} = Udot_n (zero on Dirichlet functions); stops when ||G||_2 < atol. */
+int orc_gen_alpha_step(const orc_problem *pb, const double *U0, const double *V0, double dt, double rho,
+                       double atol, int maxit, double *U1, double *V1, int *iters) {
+  double am, af, gm;
+  if (!pb || !U0 || !V0 || !U1 || !V1 || !(dt > 0.0) || orc_gen_alpha_params(rho, &am, &af, &gm)) return 1;
+  layout L;
+  if (lay_init(pb, &L)) return 1;
+  int64_t N = L.N, nnz;
+  orc_sizes(pb, NULL, NULL, &nnz);
+  int64_t *rp = (int64_t *)malloc(sizeof(int64_t) * (N + 1));
+  int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * nnz);
+  double *Mv = (double *)malloc(sizeof(double) * nnz), *Jv = (double *)malloc(sizeof(double) * nnz);
+  double *Ua = (double *)malloc(sizeof(double) * N), *Va = (double *)malloc(sizeof(double) * N);
+  double *G = (double *)malloc(sizeof(double) * N), *d = (double *)malloc(sizeof(double) * N);
+  char *dir = (char *)malloc((size_t)N);
+  orc_csr_pattern(pb, rp, ci);
+  int rc = orc_mass_matrix(pb, rp, ci, Mv);
+  for (int64_t A = 0; A < N; ++A) dir[A] = (char)is_dirichlet(pb, &L, A);
+  for (int64_t A = 0; A < N; ++A)
+    for (int64_t k = rp[A]; k < rp[A + 1]; ++k)
+      if (dir[A] || dir[ci[k]]) Mv[k] = 0.0;
+  for (int64_t A = 0; A < N; ++A) V1[A] = dir[A] ? 0.0 : V0[A];
+  int k = 0;
+  if (!rc) rc = 4;
+  for (k = 0; k <= maxit && rc != 0 && rc != 2 && rc != 5; ++k) {
+    for (int64_t A = 0; A < N; ++A) {
+      Ua[A] = U0[A] + af * dt * (gm * V1[A] + (1.0 - gm) * V0[A]);
+      Va[A] = V0[A] + am * (V1[A] - V0[A]);
+    }
+    if (orc_residual(pb, Ua, G)) { rc = 2; break; }
+    double nr = 0.0;
+    for (int64_t A = 0; A < N; ++A) {
+      double s = 0.0;
+      for (int64_t q = rp[A]; q < rp[A + 1]; ++q) s += Mv[q] * Va[ci[q]];
+      G[A] += s;
+      nr += G[A] * G[A];
+    }
+    if (!(nr == nr)) { rc = 4; break; }
+    if (sqrt(nr) < atol) { rc = 0; break; }
+    if (k == maxit) break;
+    if (orc_jacobian(pb, Ua, rp, ci, Jv)) { rc = 2; break; }
+    for (int64_t q = 0; q < nnz; ++q) Jv[q] = am * Mv[q] + af * gm * dt * Jv[q];
+    for (int64_t A = 0; A < N; ++A) G[A] = -G[A];
+    int lrc = (pb->dim <= 2 && N <= 200000) ? banded_solve(N, rp, ci, Jv, G, d) : cg_solve(N, rp, ci, Jv, G, d, 1e-14, 20000);
+    if (lrc) { rc = 5; break; }
+    for (int64_t A = 0; A < N; ++A) V1[A] += d[A];
+  }
+  for (int64_t A = 0; A < N; ++A) U1[A] = U0[A] + dt * (gm * V1[A] + (1.0 - gm) * V0[A]);
+  if (iters) *iters = k;
+  free(rp); free(ci); free(Mv); free(Jv); free(Ua); free(Va); free(G); free(d); free(dir);
+  lay_free(&L);
+  return rc;
 }

@@ -12,6 +12,7 @@
  *   - second derivatives: of B-splines (the derivative formula applied twice), rational
  *     (eq:ddrational), of the inverse map (eq:ddimap) and spatial (eq:ddspatial), and the
  *     fourth-order operator sum W (Lap N_A)(Lap u_h) built from them,
+ *   - generalized-alpha time stepping (eq:ga) of M Udot + R(U) = 0 with Newton on Udot_{n+1},
  *   - the adjacency stencil of Algorithm 2 (Sec. 2.5),
  *   - periodic axes by unclamping (Sec. 2.4, eq:unclamp-left/right) and index wrapping (eq:map-wrap),
  *   - naive per-quadrature-point residual/Jacobian assembly as in Algorithm 3 (Sec. 2.7)
@@ -86,6 +87,13 @@ int orc_basis_hessian(const orc_problem *pb, int64_t elem, const double *t, int6
                       double *dN, double *d2N, double *x);
 /* R_A = sum_e sum_q W (Lap N_A)(Lap u_h) over every function (no boundary rows). */
 int orc_biharmonic_residual(const orc_problem *pb, const double *U, double *R);
+/* Generalized-alpha parameters from the spectral radius at infinity rho in [0, 1] (after eq:ga). */
+int orc_gen_alpha_params(double rho, double *am, double *af, double *gamma);
+/* One generalized-alpha step (eq:ga) of M0 Udot + R(U) = 0 (M0: mass matrix without Dirichlet rows and
+ * columns; R: eq:residual with its Dirichlet rows).  U0, V0: state and rate at t_n; U1, V1 at t_n + dt.
+ * Newton on Udot_{n+1} from Udot_n to ||G||_2 < atol, exact linear solves.  Returns 0 when converged. */
+int orc_gen_alpha_step(const orc_problem *pb, const double *U0, const double *V0, double dt, double rho,
+                       double atol, int maxit, double *U1, double *V1, int *iters);
 
 #ifdef __cplusplus
 }
