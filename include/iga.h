@@ -163,6 +163,19 @@ iga_status iga_assemble_residual(iga_t h, const double *U_dev, double *R_dev);
  * Every entry is written: no zeroing is needed. */
 iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, int prec);
 
+/* One generalized-alpha step (eq:ga, parameters from rho_inf in [0, 1] by the formulas after it)
+ * of the first-order system M0 Udot + R(U) = 0: R the residual of eq:residual (Dirichlet rows
+ * U_A), M0 the mass matrix without Dirichlet rows and columns.  U0_dev, V0_dev: state and rate at
+ * t_n; U1_dev, V1_dev (outputs, not aliasing the inputs): at t_n + dt.  Newton on Udot_{n+1} from
+ * Udot_n, each step solving (am M0 + af gamma dt J(U_{n+af})) d = -G with Jacobi-CG on the
+ * assembled FP64 Jacobian's pattern; stops when ||G||_2 < opts->atol (or the rtol test).  opts as
+ * for iga_newton_solve (matrix_free must be 0, jac_prec FP64; NULL: defaults); report may be NULL.
+ * The mass matrix is assembled at the first call and kept.  IGA_ENOCONV if Newton did not
+ * converge.  Synchronous. */
+iga_status iga_gen_alpha_step(iga_t h, const double *U0_dev, const double *V0_dev, double dt, double rho_inf,
+                              const iga_newton_opts *opts, double *U1_dev, double *V1_dev,
+                              iga_newton_report *report);
+
 /* Fourth-order operator from second spatial derivatives: R_A = sum_e sum_q W (Lap N_A)(Lap u_h)
  * for every function A (no Dirichlet rows), W the Gauss weight times the span factors and det J,
  * Lap N_A the trace of eq:ddspatial with the rational second derivatives of eq:ddrational and

@@ -119,6 +119,8 @@ _SIGNATURES = {
     "iga_csr_pattern": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_assemble_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_biharmonic_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "iga_gen_alpha_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.POINTER(iga_newton_opts),
+                            C.c_void_p, C.c_void_p, C.POINTER(iga_newton_report)], C.c_int),
     "iga_assemble_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "iga_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_spmv": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
@@ -299,6 +301,18 @@ class IGA:
         _check(load().iga_assemble_residual(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
                                             _dev_ptr(R, torch.float64, self.N, "R")), "iga_assemble_residual")
         return R
+
+    def gen_alpha_step(self, U0, V0, dt, rho_inf, U1, V1, atol=1e-10, max_newton=30, max_krylov=5000):
+        """One generalized-alpha step of M0 Udot + R(U) = 0 (iga_gen_alpha_step); returns the report."""
+        import torch
+        o = iga_newton_opts(atol, 0.0, max_newton, max_krylov, 0, IGA_FP64, 1e-2, 0)
+        rep = iga_newton_report()
+        _check(load().iga_gen_alpha_step(self.h, _dev_ptr(U0, torch.float64, self.N, "U0"),
+                                         _dev_ptr(V0, torch.float64, self.N, "V0"), float(dt), float(rho_inf),
+                                         C.byref(o), _dev_ptr(U1, torch.float64, self.N, "U1"),
+                                         _dev_ptr(V1, torch.float64, self.N, "V1"), C.byref(rep)), "iga_gen_alpha_step")
+        return dict(converged=bool(rep.converged), newton_iters=rep.newton_iters,
+                    krylov_iters_total=rep.krylov_iters_total, res_norm=rep.res_norm)
 
     def biharmonic_residual(self, U, R):
         """R_A = sum W (Lap N_A)(Lap u_h) over every function (iga_biharmonic_residual)."""

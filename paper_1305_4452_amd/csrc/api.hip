@@ -201,6 +201,131 @@ static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_
   return st;
 }
 
+// ------------------------------------------------------------------------------------------
+// Generalized-alpha time stepping (eq:ga) of M0 Udot + R(U) = 0, R the residual of eq:residual
+// (Dirichlet rows U_A) and M0 the mass matrix without Dirichlet rows and columns.
+// ------------------------------------------------------------------------------------------
+static unsigned ga_blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// U_{n+af} = U0 + c1 V1 + c0 V0, Udot_{n+am} = (1 - am) V0 + am V1
+__global__ void k_ga_stage(int64_t n, const double *__restrict__ U0, const double *__restrict__ V0,
+                           const double *__restrict__ V1, double c1, double c0, double am, double *__restrict__ Ua,
+                           double *__restrict__ Va) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Ua[i] = U0[i] + c1 * V1[i] + c0 * V0[i];
+  Va[i] = (1.0 - am) * V0[i] + am * V1[i];
+}
+
+// y = a x + b y over n values
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+// M0 = J(0; lambda = -1) - J(0; lambda = 0): the reaction term -lambda W e^u N_A N_B at u = 0 and
+// lambda = -1 is the mass matrix, the stiffness cancels, and the Dirichlet identity rows of the
+// two Jacobians cancel too (their columns are zero in both)
+static iga_status ensure_mass(Handle &h) {
+  if (h.massv) return IGA_OK;
+  const int64_t N = h.pb.N, nnz = h.pb.nnz;
+  iga_status st;
+  double *mv = nullptr;
+  if ((st = alloc_owned(h, (void **)&mv, (size_t)nnz * sizeof(double)))) return st;
+  if ((st = ensure_newton_ws(h, true, IGA_FP64))) return st;
+  double *zero = h.nw + 2 * N;
+  if ((st = launch_fill(h, zero, N, 0.0))) return st;
+  const double lam = h.pb.lambda;
+  h.pb.lambda = -1.0;
+  st = assemble_jacobian(h, zero, mv, IGA_FP64);
+  h.pb.lambda = 0.0;
+  if (!st) st = assemble_jacobian(h, zero, h.jvals, IGA_FP64);
+  h.pb.lambda = lam;
+  if (st) return st;
+  hipLaunchKernelGGL(k_axpby, dim3(ga_blocks(nnz)), dim3(256), 0, h.stream, nnz, -1.0, (const double *)h.jvals,
+                     1.0, mv);
+  IGA_HIP_CHECK(hipGetLastError());
+  h.massv = mv;
+  return IGA_OK;
+}
+
+static iga_status gen_alpha_step(Handle &h, const double *U0, const double *V0, double dt, double rho,
+                                 const iga_newton_opts *o_in, double *U1, double *V1, iga_newton_report *rep) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(IGA_EINVAL, "dt must be positive");
+  if (!(rho >= 0.0 && rho <= 1.0)) return fail(IGA_EINVAL, "rho_inf must be in [0, 1]");
+  iga_newton_opts o{};
+  o.atol = 1e-10;
+  o.max_newton = 30;
+  o.max_krylov = 5000;
+  o.jac_prec = IGA_FP64;
+  o.forcing_max = 1e-2;
+  if (o_in) o = *o_in;
+  if (o.matrix_free || o.jac_prec != IGA_FP64) return fail(IGA_EUNSUPPORTED, "generalized-alpha uses the assembled FP64 Jacobian");
+  if (o.max_newton < 0 || o.max_newton > 64) return fail(IGA_EINVAL, "max_newton must be in 0..64");
+  if (o.max_krylov < 1) return fail(IGA_EINVAL, "max_krylov must be positive");
+  if (o.forcing_max <= 0) o.forcing_max = 1e-2;
+  if (o.check_every <= 0) o.check_every = 16;
+  // parameters from the spectral radius at infinity (after eq:ga)
+  const double am = 0.5 * (3.0 - rho) / (1.0 + rho), af = 1.0 / (1.0 + rho), gm = 0.5 + am - af;
+  iga_status st = ensure_mass(h);
+  if (st) return st;
+  const int64_t N = h.pb.N, nnz = h.pb.nnz;
+  if (!h.gaw && (st = alloc_owned(h, (void **)&h.gaw, (size_t)3 * N * sizeof(double)))) return st;
+  double *G = h.nw, *dvec = h.nw + N, *Ua = h.gaw, *Va = h.gaw + N, *MV = h.gaw + 2 * N;
+  const unsigned nb = (unsigned)ga_blocks(N);
+  iga_newton_report r{};
+  auto t0 = std::chrono::steady_clock::now();
+  // start from Udot_{n+1} = Udot_n
+  IGA_HIP_CHECK(hipMemcpyAsync(V1, V0, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+  double nr = 0, r0 = -1;
+  int k;
+  for (k = 0;; ++k) {
+    hipLaunchKernelGGL(k_ga_stage, dim3(nb), dim3(256), 0, h.stream, N, U0, V0, (const double *)V1, af * dt * gm,
+                       af * dt * (1.0 - gm), am, Ua, Va);
+    IGA_HIP_CHECK(hipGetLastError());
+    if ((st = launch_residual(h, Ua, G))) break;
+    if ((st = launch_spmv(h, h.massv, IGA_FP64, Va, MV, nullptr, h.npartials))) break;
+    if ((st = launch_axpy(h, 1.0, MV, G))) break;
+    if ((st = launch_norm(h, G, h.scal))) break;
+    if (hipMemcpyAsync(&nr, h.scal, sizeof(double), hipMemcpyDeviceToHost, h.stream) != hipSuccess ||
+        hipStreamSynchronize(h.stream) != hipSuccess) {
+      st = fail(IGA_EHIP, "stage residual norm");
+      break;
+    }
+    r.hist[k] = nr;
+    if (r0 < 0) r0 = nr;
+    if (!std::isfinite(nr)) { st = fail(IGA_ENOCONV, "stage residual is not finite"); break; }
+    if (nr < o.atol || (o.rtol > 0 && nr <= o.rtol * r0)) { r.converged = 1; break; }
+    if (k >= o.max_newton) { st = fail(IGA_ENOCONV, "generalized-alpha Newton did not converge"); break; }
+    // dG/dUdot_{n+1} = am M0 + af gamma dt J(U_{n+af}) on the Jacobian's CSR pattern
+    if ((st = assemble_jacobian(h, Ua, h.jvals, IGA_FP64))) break;
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)ga_blocks(nnz)), dim3(256), 0, h.stream, nnz, am,
+                       (const double *)h.massv, af * gm * dt, (double *)h.jvals);
+    IGA_HIP_CHECK(hipGetLastError());
+    if ((st = launch_diag_inv(h, h.jvals, IGA_FP64, h.dinv))) break;
+    const double eta = fmin(o.forcing_max, fmax(1e-12, 0.1 * o.atol / nr));
+    int its = 0;
+    double rel = 0;
+    if ((st = cg_solve(h, G, dvec, eta, o.max_krylov, o.check_every, h.jvals, IGA_FP64, false, false, &its, &rel)))
+      break;
+    if ((st = launch_axpy(h, 1.0, dvec, V1))) break;
+    r.krylov_iters[k] = its;
+    r.krylov_iters_total += its;
+  }
+  if (!st) {
+    // U_{n+1} = U_n + dt (gamma Udot_{n+1} + (1 - gamma) Udot_n)
+    IGA_HIP_CHECK(hipMemcpyAsync(U1, U0, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+    if (!(st = launch_axpy(h, dt * gm, V1, U1))) st = launch_axpy(h, dt * (1.0 - gm), V0, U1);
+    if (!st && hipStreamSynchronize(h.stream) != hipSuccess) st = fail(IGA_EHIP, "sync");
+  }
+  r.newton_iters = k;
+  r.res_norm0 = r0;
+  r.res_norm = nr;
+  r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = r;
+  return st;
+}
+
 }  // namespace iga
 
 using namespace iga;
@@ -306,6 +431,13 @@ iga_status iga_csr_pattern(iga_t hh, int64_t *row_ptr_dev, int32_t *col_idx_dev)
 iga_status iga_assemble_residual(iga_t hh, const double *U, double *R) {
   if (!hh || !U || !R) return fail(IGA_EINVAL, "null argument");
   return launch_residual(*(Handle *)hh, U, R);
+}
+
+iga_status iga_gen_alpha_step(iga_t hh, const double *U0, const double *V0, double dt, double rho_inf,
+                              const iga_newton_opts *opts, double *U1, double *V1, iga_newton_report *report) {
+  if (!hh || !U0 || !V0 || !U1 || !V1) return fail(IGA_EINVAL, "null argument");
+  if (U1 == U0 || U1 == V0 || V1 == U0 || V1 == V0 || U1 == V1) return fail(IGA_EINVAL, "outputs must not alias inputs");
+  return gen_alpha_step(*(Handle *)hh, U0, V0, dt, rho_inf, opts, U1, V1, report);
 }
 
 iga_status iga_biharmonic_residual(iga_t hh, const double *U, double *R) {

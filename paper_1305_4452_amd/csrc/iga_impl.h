@@ -145,6 +145,10 @@ struct Handle {
   double *scal = nullptr;         // device scalars
   void *jvals = nullptr;          // Jacobian values owned by Newton
   int jvals_prec = -1;
+  // generalized-alpha (lazily allocated): mass matrix without Dirichlet rows and columns (CSR
+  // values), and the stage vectors U_{n+af}, Udot_{n+am} and a product
+  double *massv = nullptr;
+  double *gaw = nullptr;          // 3 * N doubles
   // options
   int jac_algo = IGA_JAC_AUTO;
   int nd_color = 0;   // local-ND scatter: 0 atomics (default), 1 colour-ordered plain adds
