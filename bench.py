@@ -234,6 +234,38 @@ def bench_fourth_order():
     return out
 
 
+def bench_gen_alpha(nsteps: int = 5):
+    """Generalized-alpha steps (eq:ga, rho_inf = 0.5, dt = 1e-3) of the transient Bratu problem
+    M0 Udot + R(U) = 0 on the C2 mesh (64^3, p = 3, lambda = 5) from the seeded C2 start and zero rate;
+    the first step (which also assembles the mass matrix) is untimed."""
+    import torch
+
+    import inputs
+    import paper_1305_4452_amd as iga
+    w = inputs.config_3d_bratu()
+    g = iga.IGA.from_workload(w)
+    U = torch.as_tensor(w.U0, device="cuda")
+    V = torch.zeros_like(U)
+    U1, V1 = torch.empty_like(U), torch.empty_like(U)
+    g.gen_alpha_step(U, V, 1e-3, 0.5, U1, V1, atol=1e-10)
+    U, V, U1, V1 = U1, V1, U, V
+    torch.cuda.synchronize()
+    newton = krylov = 0
+    t = time.perf_counter()
+    for _ in range(nsteps):
+        rep = g.gen_alpha_step(U, V, 1e-3, 0.5, U1, V1, atol=1e-10)
+        newton += rep["newton_iters"]
+        krylov += rep["krylov_iters_total"]
+        U, V, U1, V1 = U1, V1, U, V
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t) / nsteps
+    res = dict(workload="3D Bratu 64^3 p=3, lambda=5, rho_inf=0.5, dt=1e-3", ms_per_step=dt_s * 1e3,
+               newton_iters_per_step=newton / nsteps, cg_iters_per_step=krylov / nsteps)
+    print(f"[bench] generalized-alpha 64^3 p=3: {dt_s * 1e3:.2f} ms/step ({newton / nsteps:.1f} Newton, "
+          f"{krylov / nsteps:.1f} CG its per step)", file=sys.stderr, flush=True)
+    return res
+
+
 def bench_cylinder(nel: int, degrees):
     """Nonlinear diffusion on the thick quarter cylinder (exact NURBS, kappa = exp(GRF) at the
     control points): Jacobian assembly (general row-gather, FP64 and FP32 values) and Newton to
@@ -323,6 +355,7 @@ def main():
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--no-fourth-order", action="store_true")
+    ap.add_argument("--no-gen-alpha", action="store_true")
     ap.add_argument("--learned-train", type=int, default=2000, help="0 skips the learned-guess section")
     ap.add_argument("--learned-test", type=int, default=300)
     ap.add_argument("--learned-epochs", type=int, default=12)
@@ -493,6 +526,9 @@ def main():
     fourth = None
     if not args.no_fourth_order:
         fourth = bench_fourth_order()
+    gen_alpha = None
+    if not args.no_gen_alpha:
+        gen_alpha = bench_gen_alpha()
     learned = None
     if args.learned_train > 0:
         from paper_1305_4452_amd import learned as lg
@@ -550,6 +586,7 @@ def main():
         "cylinder": cylinder,
         "periodic": periodic,
         "fourth_order_operator": fourth,
+        "generalized_alpha": gen_alpha,
         "learned_guess": learned,
         "paper_context": {"explicit_jacobian_s": 15.41, "procs": 16, "hw": "2x Xeon E5-2680 v2",
                           "dof_per_s": 300763 / 15.41},

@@ -167,8 +167,10 @@ iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, i
  * of the first-order system M0 Udot + R(U) = 0: R the residual of eq:residual (Dirichlet rows
  * U_A), M0 the mass matrix without Dirichlet rows and columns.  U0_dev, V0_dev: state and rate at
  * t_n; U1_dev, V1_dev (outputs, not aliasing the inputs): at t_n + dt.  Newton on Udot_{n+1} from
- * Udot_n, each step solving (am M0 + af gamma dt J(U_{n+af})) d = -G with Jacobi-CG on the
- * assembled FP64 Jacobian's pattern; stops when ||G||_2 < opts->atol (or the rtol test).  opts as
+ * Udot_n, each step solving (am M0 + af gamma dt J(U_{n+af})) d = -G by CG on the assembled FP64
+ * Jacobian's pattern, preconditioned by fast diagonalisation of K + (am/(af gamma dt) - lambda
+ * mean(e^u)) M where it is built (IGA_OPT_PRECOND as for Newton), Jacobi otherwise; stops when
+ * ||G||_2 < opts->atol (or the rtol test).  opts as
  * for iga_newton_solve (matrix_free must be 0, jac_prec FP64; NULL: defaults); report may be NULL.
  * The mass matrix is assembled at the first call and kept.  IGA_ENOCONV if Newton did not
  * converge.  Synchronous. */

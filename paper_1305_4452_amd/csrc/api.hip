@@ -264,11 +264,14 @@ static iga_status gen_alpha_step(Handle &h, const double *U0, const double *V0, 
   if (o.max_newton < 0 || o.max_newton > 64) return fail(IGA_EINVAL, "max_newton must be in 0..64");
   if (o.max_krylov < 1) return fail(IGA_EINVAL, "max_krylov must be positive");
   if (o.forcing_max <= 0) o.forcing_max = 1e-2;
-  if (o.check_every <= 0) o.check_every = 16;
   // parameters from the spectral radius at infinity (after eq:ga)
   const double am = 0.5 * (3.0 - rho) / (1.0 + rho), af = 1.0 / (1.0 + rho), gm = 0.5 + am - af;
-  iga_status st = ensure_mass(h);
-  if (st) return st;
+  // fast diagonalisation of K + (am / (af gamma dt) - lambda mean(e^u)) M when it is built (the
+  // step's operator divided by af gamma dt), Jacobi otherwise
+  iga_status st = IGA_OK;
+  if (h.precond != IGA_PRECOND_JACOBI && (st = ensure_fdm(h))) return st;
+  const bool fdm = h.precond != IGA_PRECOND_JACOBI && h.fdm.ok;
+  if ((st = ensure_mass(h)) || (st = ensure_newton_ws(h, true, IGA_FP64))) return st;
   const int64_t N = h.pb.N, nnz = h.pb.nnz;
   if (!h.gaw && (st = alloc_owned(h, (void **)&h.gaw, (size_t)3 * N * sizeof(double)))) return st;
   double *G = h.nw, *dvec = h.nw + N, *Ua = h.gaw, *Va = h.gaw + N, *MV = h.gaw + 2 * N;
@@ -302,11 +305,16 @@ static iga_status gen_alpha_step(Handle &h, const double *U0, const double *V0, 
     hipLaunchKernelGGL(k_axpby, dim3((unsigned)ga_blocks(nnz)), dim3(256), 0, h.stream, nnz, am,
                        (const double *)h.massv, af * gm * dt, (double *)h.jvals);
     IGA_HIP_CHECK(hipGetLastError());
-    if ((st = launch_diag_inv(h, h.jvals, IGA_FP64, h.dinv))) break;
+    if (fdm) {
+      if ((st = launch_fdm_shift(h, Ua, am / (af * gm * dt)))) break;
+    } else if ((st = launch_diag_inv(h, h.jvals, IGA_FP64, h.dinv))) {
+      break;
+    }
     const double eta = fmin(o.forcing_max, fmax(1e-12, 0.1 * o.atol / nr));
     int its = 0;
     double rel = 0;
-    if ((st = cg_solve(h, G, dvec, eta, o.max_krylov, o.check_every, h.jvals, IGA_FP64, false, false, &its, &rel)))
+    if ((st = cg_solve(h, G, dvec, eta, o.max_krylov, o.check_every > 0 ? o.check_every : (fdm ? 4 : 16), h.jvals,
+                       IGA_FP64, false, fdm, &its, &rel)))
       break;
     if ((st = launch_axpy(h, 1.0, dvec, V1))) break;
     r.krylov_iters[k] = its;

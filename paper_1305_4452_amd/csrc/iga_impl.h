@@ -223,7 +223,9 @@ bool gen_eigen(const std::vector<double> &A, const std::vector<double> &M, int n
 iga_status upload_owned(Handle &h, double **dst, const double *src, size_t count);
 bool fdm_possible(const Handle &h);
 iga_status ensure_fdm(Handle &h);   // builds on first use; h.fdm.ok tells whether it succeeded
-iga_status launch_fdm_shift(Handle &h, const double *U);
+// shift of K + shift M for the Jacobian at U (-lambda times the weighted mean of e^U), plus
+// mass_coef for operators with an added mass term (generalized-alpha: am / (af gamma dt))
+iga_status launch_fdm_shift(Handle &h, const double *U, double mass_coef = 0.0);
 iga_status launch_fdm_apply(Handle &h, const double *r, double *z, double *w1, double *w2);
 
 // Launchers implemented in the kernel translation units.

@@ -450,14 +450,14 @@ __global__ void __launch_bounds__(256) k_fdm_shift_partial(DevProblem pb, FdmDat
 
 // shift = max(-lambda mscale sum1 / sum2, -0.9 mu_min): K + shift M stays positive definite
 __global__ void k_fdm_shift_final(const double *__restrict__ part, int nb, double lam, double mscale, double mu_min,
-                                  double *__restrict__ shift) {
+                                  double add, double *__restrict__ shift) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double a = 0, b = 0;
   for (int i = 0; i < nb; ++i) {
     a += part[2 * i];
     b += part[2 * i + 1];
   }
-  double c = (b > 0) ? -lam * mscale * a / b : 0.0;
+  double c = ((b > 0) ? -lam * mscale * a / b : 0.0) + add;
   *shift = fmax(c, -0.9 * mu_min);
 }
 
@@ -473,11 +473,11 @@ void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView v
 
 }  // namespace
 
-iga_status launch_fdm_shift(Handle &h, const double *U) {
+iga_status launch_fdm_shift(Handle &h, const double *U, double mass_coef) {
   const int nb = 256;
   hipLaunchKernelGGL(k_fdm_shift_partial, dim3(nb), dim3(256), 0, h.stream, h.pb, h.fdm, U, h.fdm_part);
   hipLaunchKernelGGL(k_fdm_shift_final, dim3(1), dim3(64), 0, h.stream, (const double *)h.fdm_part, nb, h.pb.lambda,
-                     h.fdm.mscale, h.fdm.mu_min, h.fdm_shift);
+                     h.fdm.mscale, h.fdm.mu_min, h.fdm.mscale * mass_coef, h.fdm_shift);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
 }
