@@ -80,6 +80,7 @@ def lib():
             "orc_basis_hessian": [P, C.c_int64, _dp, _i64p, _dp, _dp, _dp, _dp],
             "orc_biharmonic_residual": [P, _dp, _dp],
             "orc_gen_alpha_params": [C.c_double, _dp, _dp, _dp],
+            "orc_cahn_hilliard_residual": [P, _dp, _dp, C.c_double, C.c_double, _dp],
             "orc_gen_alpha_step": [P, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int, _dp, _dp,
                                    C.POINTER(C.c_int)],
         }
@@ -194,6 +195,15 @@ class Oracle:
         U = np.ascontiguousarray(U, dtype=np.float64)
         R = np.zeros(self.N)
         self._chk(lib().orc_biharmonic_residual(C.byref(self.pb), _ptr(U), _ptr(R)), "biharmonic_residual")
+        return R
+
+    def cahn_hilliard_residual(self, Cv, Cd, theta, lam):
+        """Cahn-Hilliard residual (primal weak form, D = 1) for coefficients C of c and Cdot of its rate."""
+        Cv = np.ascontiguousarray(Cv, dtype=np.float64)
+        Cd = np.ascontiguousarray(Cd, dtype=np.float64)
+        R = np.zeros(self.N)
+        self._chk(lib().orc_cahn_hilliard_residual(C.byref(self.pb), _ptr(Cv), _ptr(Cd), float(theta), float(lam),
+                                                   _ptr(R)), "cahn_hilliard_residual")
         return R
 
     def gen_alpha_step(self, U0, V0, dt, rho, atol=1e-12, maxit=30):

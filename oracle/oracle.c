@@ -1287,3 +1287,53 @@ int orc_gen_alpha_step(const orc_problem *pb, const double *U0, const double *V0
   lay_free(&L);
   return rc;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Cahn-Hilliard residual (the paper's strong form, D = 1), primal weak form:            */
+/*   R_A = sum_e sum_q W [ N_A cdot + M mu' grad N_A . grad c                             */
+/*                         + lam (M Lap N_A + M' grad c . grad N_A) Lap c ]               */
+/* M = c (1 - c), M' = 1 - 2c, mu' = 1 / (2 theta c (1 - c)) - 2 (derivative of the       */
+/* chemical potential); boundary terms dropped (periodic axes, or the natural conditions).*/
+/* ------------------------------------------------------------------------------------ */
+int orc_cahn_hilliard_residual(const orc_problem *pb, const double *Cv, const double *Cd, double theta,
+                               double lam, double *R) {
+  layout L;
+  if (!pb || !Cv || !Cd || !R || !(theta > 0.0) || lay_init(pb, &L)) return 1;
+  int64_t N = (int64_t)L.n[0] * L.n[1] * L.n[2], ne = (int64_t)L.ne[0] * L.ne[1] * L.ne[2];
+  for (int64_t A = 0; A < N; ++A) R[A] = 0.0;
+  int nqt = L.nq[0] * L.nq[1] * L.nq[2];
+  static hpoint h;
+  static double lap[ORC_MAXLOC];
+  for (int64_t e = 0; e < ne; ++e) {
+    int em[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqt; ++g) {
+      int gm[3];
+      qp_multi(&L, g, gm);
+      double t[3], wq = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        t[d] = d < L.dim ? L.gx[d][gm[d]] : 0.0;
+        if (d < L.dim) wq *= L.gw[d][gm[d]];
+      }
+      int rc = eval_hess(pb, &L, em, t, &h);
+      if (rc) { lay_free(&L); return rc; }
+      double W = wq * h.span * h.detJ, c = 0.0, cd = 0.0, gc[3] = {0, 0, 0}, lc = 0.0;
+      for (int a = 0; a < h.nloc; ++a) {
+        lap[a] = 0.0;
+        for (int i = 0; i < L.dim; ++i) lap[a] += h.d2N[a][i][i];
+        c += Cv[h.A[a]] * h.N[a];
+        cd += Cd[h.A[a]] * h.N[a];
+        for (int i = 0; i < 3; ++i) gc[i] += Cv[h.A[a]] * h.dN[a][i];
+        lc += Cv[h.A[a]] * lap[a];
+      }
+      double M = c * (1.0 - c), dM = 1.0 - 2.0 * c, dmu = 1.0 / (2.0 * theta * c * (1.0 - c)) - 2.0;
+      for (int a = 0; a < h.nloc; ++a) {
+        double gg = 0.0;
+        for (int i = 0; i < 3; ++i) gg += h.dN[a][i] * gc[i];
+        R[h.A[a]] += W * (h.N[a] * cd + M * dmu * gg + lam * (M * lap[a] + dM * gg) * lc);
+      }
+    }
+  }
+  lay_free(&L);
+  return 0;
+}

@@ -13,6 +13,7 @@
  *     (eq:ddrational), of the inverse map (eq:ddimap) and spatial (eq:ddspatial), and the
  *     fourth-order operator sum W (Lap N_A)(Lap u_h) built from them,
  *   - generalized-alpha time stepping (eq:ga) of M Udot + R(U) = 0 with Newton on Udot_{n+1},
+ *   - the Cahn-Hilliard residual (primal weak form of the paper's strong form),
  *   - the adjacency stencil of Algorithm 2 (Sec. 2.5),
  *   - periodic axes by unclamping (Sec. 2.4, eq:unclamp-left/right) and index wrapping (eq:map-wrap),
  *   - naive per-quadrature-point residual/Jacobian assembly as in Algorithm 3 (Sec. 2.7)
@@ -87,6 +88,11 @@ int orc_basis_hessian(const orc_problem *pb, int64_t elem, const double *t, int6
                       double *dN, double *d2N, double *x);
 /* R_A = sum_e sum_q W (Lap N_A)(Lap u_h) over every function (no boundary rows). */
 int orc_biharmonic_residual(const orc_problem *pb, const double *U, double *R);
+/* Cahn-Hilliard residual of the paper's strong form (D = 1) in primal weak form: R_A = sum W [N_A cdot
+ * + M mu' grad N_A . grad c + lam (M Lap N_A + M' grad c . grad N_A) Lap c], M = c(1-c), M' = 1-2c,
+ * mu' = 1/(2 theta c(1-c)) - 2; C, Cdot: coefficients of c and its rate; no boundary terms. */
+int orc_cahn_hilliard_residual(const orc_problem *pb, const double *C, const double *Cdot, double theta,
+                               double lam, double *R);
 /* Generalized-alpha parameters from the spectral radius at infinity rho in [0, 1] (after eq:ga). */
 int orc_gen_alpha_params(double rho, double *am, double *af, double *gamma);
 /* One generalized-alpha step (eq:ga) of M0 Udot + R(U) = 0 (M0: mass matrix without Dirichlet rows and

@@ -1,0 +1,89 @@
+"""Pins of the oracle's Cahn-Hilliard residual (the paper's strong form with D = 1, primal weak form
+obtained by integrating by parts twice; periodic axes as in the paper's example):
+
+* a uniform state: R = M_mass Cdot exactly (every gradient and Laplacian vanishes);
+* conservation on a fully periodic patch: sum_A R_A = integral of cdot = sum_B Cdot_B int N_B;
+* linearisation about c = 1/2: for c = 1/2 + d phi, R(Cdot = 0)/d tends to
+  (1/(2 theta) - 1/2) K phi + (lam/4) B phi with an O(d^2) error, K the stiffness (the Jacobian at
+  lambda = 0, pinned elsewhere) and B the pinned fourth-order operator: this ties the mobility,
+  the chemical-potential derivative and both lam terms to independently checked pieces."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+
+def periodic_patch(dim, p):
+    nel = [8, 7, 7][:dim]
+    patch = inputs.unit_box(dim, nel, p)
+    per = [p - 1] * dim
+    return patch, per
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (2, 3), (3, 2)])
+def test_uniform_state_gives_the_mass_term(dim, p):
+    patch, per = periodic_patch(dim, p)
+    o = oracle.Oracle(patch.knots, patch.degree, periodic=per)
+    rng = np.random.default_rng(dim + p)
+    Cd = rng.uniform(-1, 1, o.N)
+    R = o.cahn_hilliard_residual(np.full(o.N, 0.3), Cd, 0.7, 0.01)
+    ref = o.mass_matrix() @ Cd
+    assert np.abs(R - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (3, 2)])
+def test_conservation_on_a_periodic_patch(dim, p):
+    patch, per = periodic_patch(dim, p)
+    o = oracle.Oracle(patch.knots, patch.degree, periodic=per)
+    rng = np.random.default_rng(11)
+    C = rng.uniform(0.2, 0.8, o.N)
+    Cd = rng.uniform(-1, 1, o.N)
+    R = o.cahn_hilliard_residual(C, Cd, 0.667, 0.02)
+    integ = np.asarray(o.mass_matrix().sum(axis=0)).ravel()      # int N_B over the periodic domain
+    assert abs(R.sum() - integ @ Cd) < 1e-12 * np.abs(R).sum()
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (2, 3), (3, 2)])
+def test_linearisation_about_one_half(dim, p):
+    patch, per = periodic_patch(dim, p)
+    o = oracle.Oracle(patch.knots, patch.degree, periodic=per, lam=0.0)
+    rng = np.random.default_rng(5 * dim + p)
+    phi = rng.uniform(-1, 1, o.N)
+    theta, lam = 0.8, 0.05
+    K = o.jacobian_csr(np.zeros(o.N))
+    ref = (1.0 / (2 * theta) - 0.5) * (K @ phi) + lam / 4.0 * o.biharmonic_residual(phi)
+    errs = []
+    for d in (1e-3, 5e-4):
+        R = o.cahn_hilliard_residual(0.5 + d * phi, np.zeros(o.N), theta, lam) / d
+        errs.append(np.linalg.norm(R - ref) / np.linalg.norm(ref))
+    assert errs[0] < 1e-4 and 3.0 < errs[0] / errs[1] < 5.0, errs      # O(d^2)
+
+
+def polar_quadratic(U, p):
+    n = len(U) - p - 1
+    return np.array([sum(U[i + 1 + j] * U[i + 1 + k] for j in range(p) for k in range(j + 1, p)) * 2.0 / (p * (p - 1))
+                     for i in range(n)])
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (2, 3), (3, 2)])
+def test_fourth_order_term_vanishes_for_a_constant_laplacian(dim, p):
+    """lam (M Lap N_A + M' grad c . grad N_A) Lap c = lam div(M grad N_A) Lap c; for c = 0.3 + s |x|^2
+    (Lap c = 2 dim s) its integral is a boundary term, zero for every function that vanishes with its
+    gradient on the boundary: the lam-part of R (R at lam = 1 minus R at lam = 0) is zero there."""
+    patch = inputs.unit_box(dim, [6, 7, 5][:dim], p)
+    o = oracle.Oracle(patch.knots, patch.degree)
+    q = [polar_quadratic(K, p) for K in patch.knots]
+    n = [len(c) for c in q]
+    C = 0.3 * np.ones(o.N)
+    for ax in range(dim):
+        shape = [1] * dim
+        shape[dim - 1 - ax] = n[ax]
+        C = C + 0.1 * np.broadcast_to(q[ax].reshape(shape), tuple(n[::-1])).ravel()
+    Z = np.zeros(o.N)
+    lam_part = o.cahn_hilliard_residual(C, Z, 0.7, 1.0) - o.cahn_hilliard_residual(C, Z, 0.7, 0.0)
+    idx = np.stack(np.unravel_index(np.arange(o.N), tuple(n[::-1]))[::-1], -1)
+    interior = np.all((idx >= 2) & (idx <= np.array(n) - 3), axis=1)
+    assert interior.sum() > 0
+    scale = np.abs(lam_part).max()
+    assert np.abs(lam_part[interior]).max() < 1e-11 * scale, np.abs(lam_part[interior]).max() / scale
