@@ -163,6 +163,17 @@ iga_status iga_assemble_residual(iga_t h, const double *U_dev, double *R_dev);
  * Every entry is written: no zeroing is needed. */
 iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, int prec);
 
+/* Cahn-Hilliard residual (the Cahn-Hilliard example: the paper's strong form with D = 1, in the
+ * primal weak form obtained by integrating by parts twice, boundary terms dropped as on periodic
+ * axes): R_A = sum_e sum_q W [N_A cdot + (M mu' + lambda_ch M' Lap c) grad N_A . grad c
+ * + lambda_ch M Lap c Lap N_A], M = c(1-c), M' = 1-2c, mu' = 1/(2 theta c(1-c)) - 2.  C_dev, Cdot_dev:
+ * coefficients of c and of its rate (N doubles, device); R_dev overwritten, every function (no
+ * Dirichlet rows).  c must lie in (0, 1) at the Gauss points.  Needs x = xi without weights, p >= 2,
+ * p <= 6 in 2D and p <= 3 in 3D (IGA_EUNSUPPORTED otherwise); theta > 0 (IGA_EINVAL).
+ * Asynchronous on the handle's stream. */
+iga_status iga_cahn_hilliard_residual(iga_t h, const double *C_dev, const double *Cdot_dev, double theta,
+                                      double lambda_ch, double *R_dev);
+
 /* One generalized-alpha step (eq:ga, parameters from rho_inf in [0, 1] by the formulas after it)
  * of the first-order system M0 Udot + R(U) = 0: R the residual of eq:residual (Dirichlet rows
  * U_A), M0 the mass matrix without Dirichlet rows and columns.  U0_dev, V0_dev: state and rate at

@@ -119,6 +119,7 @@ _SIGNATURES = {
     "iga_csr_pattern": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_assemble_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_biharmonic_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "iga_cahn_hilliard_residual": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p], C.c_int),
     "iga_gen_alpha_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.POINTER(iga_newton_opts),
                             C.c_void_p, C.c_void_p, C.POINTER(iga_newton_report)], C.c_int),
     "iga_assemble_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
@@ -313,6 +314,14 @@ class IGA:
                                          _dev_ptr(V1, torch.float64, self.N, "V1"), C.byref(rep)), "iga_gen_alpha_step")
         return dict(converged=bool(rep.converged), newton_iters=rep.newton_iters,
                     krylov_iters_total=rep.krylov_iters_total, res_norm=rep.res_norm)
+
+    def cahn_hilliard_residual(self, Cv, Cd, theta, lam, R):
+        """Cahn-Hilliard residual for coefficients Cv of c and Cd of its rate (iga_cahn_hilliard_residual)."""
+        import torch
+        _check(load().iga_cahn_hilliard_residual(self.h, _dev_ptr(Cv, torch.float64, self.N, "C"),
+                                                 _dev_ptr(Cd, torch.float64, self.N, "Cdot"), float(theta), float(lam),
+                                                 _dev_ptr(R, torch.float64, self.N, "R")), "iga_cahn_hilliard_residual")
+        return R
 
     def biharmonic_residual(self, U, R):
         """R_A = sum W (Lap N_A)(Lap u_h) over every function (iga_biharmonic_residual)."""

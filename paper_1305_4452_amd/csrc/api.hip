@@ -448,6 +448,12 @@ iga_status iga_gen_alpha_step(iga_t hh, const double *U0, const double *V0, doub
   return gen_alpha_step(*(Handle *)hh, U0, V0, dt, rho_inf, opts, U1, V1, report);
 }
 
+iga_status iga_cahn_hilliard_residual(iga_t hh, const double *C, const double *Cdot, double theta, double lambda_ch,
+                                      double *R) {
+  if (!hh || !C || !Cdot || !R) return fail(IGA_EINVAL, "null argument");
+  return launch_cahn_hilliard(*(Handle *)hh, C, Cdot, theta, lambda_ch, R);
+}
+
 iga_status iga_biharmonic_residual(iga_t hh, const double *U, double *R) {
   if (!hh || !U || !R) return fail(IGA_EINVAL, "null argument");
   return launch_biharmonic(*(Handle *)hh, U, R);

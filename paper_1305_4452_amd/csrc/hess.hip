@@ -178,6 +178,104 @@ __global__ void __launch_bounds__(64) k_biharmonic(DevProblem pb, const double *
   }
 }
 
+// Cahn-Hilliard residual on x = xi without weights (periodic axes wrap): with M = c (1 - c),
+// M' = 1 - 2c and mu' = 1 / (2 theta c (1 - c)) - 2,
+//   R_A = sum_e sum_q W [N_A cdot + (M mu' + lam M' Lap c) grad N_A . grad c + lam M Lap c Lap N_A],
+// the primal weak form of the paper's strong form (D = 1; the lam terms are
+// lam div(M grad N_A) Lap c).  One 64-lane workgroup per element, one lane per Gauss point: the lane
+// forms c, cdot, grad c and Lap c, then its point's contribution to every local function (kept in
+// LDS); one FP64 atomic per local function.
+template <int DIM, int P>
+__global__ void __launch_bounds__(64) k_cahn_hilliard(DevProblem pb, const double *__restrict__ Cv,
+                                                      const double *__restrict__ Cd, double theta, double lam,
+                                                      double *__restrict__ R) {
+  constexpr int Q = P, L = hpow(P, DIM), QD = hpow(Q, DIM);
+  static_assert(QD <= 64 && L <= 64, "one lane per Gauss point and per local function");
+  __shared__ double tb[3][3][Q][P];   // [axis][value | d/dxi | d2/dxi2][q][a]
+  __shared__ double tw[3][Q];
+  __shared__ double sC[L], sCd[L];
+  __shared__ int64_t sA[L];
+  __shared__ double sR[L][QD + 1];
+  const int t = threadIdx.x;
+  const int64_t e = blockIdx.x;
+  int em[3] = {(int)(e % pb.ne[0]), (int)((e / pb.ne[0]) % pb.ne[1]), (int)(e / ((int64_t)pb.ne[0] * pb.ne[1]))};
+  for (int d = 0; d < 3; ++d) {
+    for (int i = t; i < 3 * Q * P; i += 64) {
+      const int kind = i / (Q * P), r = i % (Q * P);
+      double v = (kind == 0 && r % P == 0) ? 1.0 : 0.0;
+      if (d < DIM) {
+        const size_t o = (size_t)em[d] * Q * P + r;
+        v = kind == 0 ? pb.ax[d].B[o] : kind == 1 ? pb.ax[d].dB[o] : pb.ax[d].d2B[o];
+      }
+      (&tb[d][0][0][0])[i] = v;
+    }
+    if (t < Q) tw[d][t] = d < DIM ? pb.ax[d].wq[(size_t)em[d] * Q + t] : (t == 0 ? 1.0 : 0.0);
+  }
+  for (int a = t; a < L; a += 64) {
+    const int a0 = a % P, a1 = (a / P) % P, a2 = DIM == 3 ? a / (P * P) : 0;
+    const int i0 = wrap_fn(pb.ax[0], pb.ax[0].efirst[em[0]] + a0);
+    const int i1 = wrap_fn(pb.ax[1], pb.ax[1].efirst[em[1]] + a1);
+    const int i2 = DIM == 3 ? wrap_fn(pb.ax[2], pb.ax[2].efirst[em[2]] + a2) : 0;
+    const int64_t A = i0 + (int64_t)pb.n[0] * (i1 + (int64_t)pb.n[1] * i2);
+    sA[a] = A;
+    sC[a] = Cv[A];
+    sCd[a] = Cd[A];
+  }
+  __syncthreads();
+  if (t < QD) {
+    const int qi[3] = {t % Q, (t / Q) % Q, DIM == 3 ? t / (Q * Q) : 0};
+    // value, gradient and Laplacian of local function a at this point
+    auto fn = [&](int a, double &n, double *g, double &lap) {
+      const int ai[3] = {a % P, (a / P) % P, DIM == 3 ? a / (P * P) : 0};
+      double v[3][3];
+      for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < 3; ++k) v[d][k] = (d < DIM || k == 0) ? tb[d][k][qi[d]][ai[d]] : 0.0;
+      n = v[0][0] * v[1][0] * v[2][0];
+      lap = 0.0;
+      for (int al = 0; al < 3; ++al) {
+        double s = 1.0, s2 = 1.0;
+        for (int d = 0; d < 3; ++d) {
+          s *= v[d][d == al ? 1 : 0];
+          s2 *= v[d][d == al ? 2 : 0];
+        }
+        g[al] = s;
+        if (al < DIM) lap += s2;
+      }
+    };
+    double c = 0, cd = 0, gc[3] = {0, 0, 0}, lc = 0;
+    for (int a = 0; a < L; ++a) {
+      double n, g[3], lap;
+      fn(a, n, g, lap);
+      c += sC[a] * n;
+      cd += sCd[a] * n;
+      for (int i = 0; i < 3; ++i) gc[i] += sC[a] * g[i];
+      lc += sC[a] * lap;
+    }
+    const double W = tw[0][qi[0]] * tw[1][qi[1]] * tw[2][qi[2]];
+    const double M = c * (1.0 - c), dM = 1.0 - 2.0 * c, dmu = 1.0 / (2.0 * theta * c * (1.0 - c)) - 2.0;
+    const double s0 = W * cd, sg = W * (M * dmu + lam * dM * lc), s2 = W * lam * M * lc;
+    for (int a = 0; a < L; ++a) {
+      double n, g[3], lap;
+      fn(a, n, g, lap);
+      sR[a][t] = n * s0 + sg * (g[0] * gc[0] + g[1] * gc[1] + g[2] * gc[2]) + s2 * lap;
+    }
+  }
+  __syncthreads();
+  for (int a = t; a < L; a += 64) {
+    double r = 0.0;
+    for (int q = 0; q < QD; ++q) r += sR[a][q];
+    atomicAdd(&R[sA[a]], r);
+  }
+}
+
+template <int DIM, int P>
+iga_status run_ch(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R) {
+  hipLaunchKernelGGL((k_cahn_hilliard<DIM, P>), dim3((unsigned)h.pb.E), dim3(64), 0, h.stream, h.pb, C, Cd, theta,
+                     lam, R);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
 template <int P>
 __global__ void __launch_bounds__(rs3::kThreads) k_bih3(DevProblem pb, const double *__restrict__ U,
                                                         double *__restrict__ R) {
@@ -201,6 +299,30 @@ iga_status run_bih(Handle &h, const double *U, double *R) {
 }
 
 }  // namespace
+
+iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R) {
+  const int p = h.pb.p;
+  if (h.pb.ctrl || h.pb.wts) return fail(IGA_EUNSUPPORTED, "the Cahn-Hilliard residual needs x = xi without weights");
+  if (!(theta > 0.0) || !std::isfinite(theta) || !std::isfinite(lam)) return fail(IGA_EINVAL, "theta must be positive");
+  if (p < 2) return fail(IGA_EUNSUPPORTED, "the Cahn-Hilliard residual needs p >= 2");
+  iga_status st = launch_fill(h, R, h.pb.N, 0.0);
+  if (st) return st;
+  if (h.pb.dim == 2) {
+    switch (p) {
+      case 2: return run_ch<2, 3>(h, C, Cd, theta, lam, R);
+      case 3: return run_ch<2, 4>(h, C, Cd, theta, lam, R);
+      case 4: return run_ch<2, 5>(h, C, Cd, theta, lam, R);
+      case 5: return run_ch<2, 6>(h, C, Cd, theta, lam, R);
+      case 6: return run_ch<2, 7>(h, C, Cd, theta, lam, R);
+    }
+  } else {
+    switch (p) {
+      case 2: return run_ch<3, 3>(h, C, Cd, theta, lam, R);
+      case 3: return run_ch<3, 4>(h, C, Cd, theta, lam, R);
+    }
+  }
+  return fail(IGA_EUNSUPPORTED, "the Cahn-Hilliard residual supports p <= 6 in 2D and p <= 3 in 3D");
+}
 
 iga_status launch_biharmonic(Handle &h, const double *U, double *R) {
   const int p = h.pb.p;

@@ -1,0 +1,59 @@
+"""The Cahn-Hilliard residual (iga_cahn_hilliard_residual) against the oracle's on the same seeded
+coefficients: periodic and open axes, 2D and 3D, C^1 quadratics (the paper's example) and cubics.
+Bar: 1e-11 relative."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1305_4452_amd as iga  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = {
+    "periodic2_p2": (2, [8, 7], 2, True),
+    "periodic2_p3": (2, [8, 9], 3, True),
+    "open2_p2": (2, [6, 5], 2, False),
+    "open2_p5": (2, [3, 4], 5, False),
+    "periodic3_p2": (3, [8, 7, 7], 2, True),
+    "open3_p3": (3, [3, 4, 2], 3, False),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cahn_hilliard_residual_matches_oracle(name):
+    print(f"[case] Cahn-Hilliard residual {name}", flush=True)
+    dim, nel, p, periodic = CASES[name]
+    patch = inputs.unit_box(dim, nel, p)
+    per = [p - 1] * dim if periodic else None
+    g = iga.IGA(patch.knots, patch.degree, periodic=per)
+    o = oracle.Oracle(patch.knots, patch.degree, periodic=per)
+    assert g.N == o.N
+    for stream, (theta, lam) in enumerate([(0.667, 0.01), (1.5, 0.2)]):
+        C = inputs.uniform(23, 2 * stream, g.N, 0.2, 0.8)
+        Cd = inputs.uniform(23, 2 * stream + 1, g.N, -1.0, 1.0)
+        R = torch.full((g.N,), float("nan"), dtype=torch.float64, device="cuda")
+        g.cahn_hilliard_residual(torch.as_tensor(C, device="cuda"), torch.as_tensor(Cd, device="cuda"), theta, lam, R)
+        torch.cuda.synchronize()
+        got = R.cpu().numpy()
+        assert np.all(np.isfinite(got))
+        assert rel(got, o.cahn_hilliard_residual(C, Cd, theta, lam)) < 1e-11
+
+
+def test_cahn_hilliard_residual_rejections():
+    cases = [(inputs.quarter_cylinder(3, 2, dim=2), 0.7, iga.IGA_EUNSUPPORTED),
+             (inputs.unit_box(2, 4, 1), 0.7, iga.IGA_EUNSUPPORTED),
+             (inputs.unit_box(2, 4, 2), 0.0, iga.IGA_EINVAL)]
+    for patch, theta, status in cases:
+        g = iga.IGA(patch.knots, patch.degree, ctrl=patch.ctrl, weights=patch.weights)
+        x = torch.full((g.N,), 0.5, dtype=torch.float64, device="cuda")
+        with pytest.raises(iga.IGAError) as ei:
+            g.cahn_hilliard_residual(x, x, theta, 0.1, torch.empty_like(x))
+        assert ei.value.status == status
