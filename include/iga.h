@@ -174,6 +174,19 @@ iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, i
 iga_status iga_cahn_hilliard_residual(iga_t h, const double *C_dev, const double *Cdot_dev, double theta,
                                       double lambda_ch, double *R_dev);
 
+/* One generalized-alpha step (eq:ga) of the Cahn-Hilliard system R_CH(cdot, c) = 0 (the residual of
+ * iga_cahn_hilliard_residual; theta, lambda_ch as there).  C0_dev, V0_dev: c and its rate at t_n;
+ * C1_dev, V1_dev (outputs, not aliasing the inputs): at t_n + dt.  Newton on cdot_{n+1} from
+ * cdot_n; each linear system by BiCGStab (the Jacobian is not symmetric) on Jacobian-vector products
+ * by a forward difference of the residual (the matrix-free approach of Sec. 2.8), step
+ * sqrt(eps) (1 + ||c_{n+af}||) / ||x||; stops when ||G||_2 < opts->atol.  opts: atol, rtol,
+ * max_newton, max_krylov (BiCGStab iterations per Newton step), forcing_max; NULL: defaults.
+ * Same geometry limits as iga_cahn_hilliard_residual.  IGA_ENOCONV if Newton or BiCGStab fails.
+ * Synchronous. */
+iga_status iga_ch_gen_alpha_step(iga_t h, const double *C0_dev, const double *V0_dev, double dt, double rho_inf,
+                                 double theta, double lambda_ch, const iga_newton_opts *opts, double *C1_dev,
+                                 double *V1_dev, iga_newton_report *report);
+
 /* One generalized-alpha step (eq:ga, parameters from rho_inf in [0, 1] by the formulas after it)
  * of the first-order system M0 Udot + R(U) = 0: R the residual of eq:residual (Dirichlet rows
  * U_A), M0 the mass matrix without Dirichlet rows and columns.  U0_dev, V0_dev: state and rate at

@@ -206,6 +206,35 @@ class Oracle:
                                                    _ptr(R)), "cahn_hilliard_residual")
         return R
 
+    def ch_gen_alpha_step(self, C0, V0, dt, rho, theta, lam, atol=1e-12, maxit=30):
+        """One generalized-alpha step (eq:ga) of the Cahn-Hilliard system R_CH(cdot, c) = 0: Newton on
+        cdot_{n+1} from cdot_n with a dense Jacobian of G by central differences (columns), linear
+        systems by LU; returns (C1, V1, Newton iterations).  Small problems only."""
+        am, af, gm = gen_alpha_params(rho)
+        C0 = np.asarray(C0, dtype=np.float64)
+        V0 = np.asarray(V0, dtype=np.float64)
+        V1 = V0.copy()
+
+        def G(V):
+            Ca = C0 + af * dt * (gm * V + (1.0 - gm) * V0)
+            Va = V0 + am * (V - V0)
+            return self.cahn_hilliard_residual(Ca, Va, theta, lam)
+
+        for k in range(maxit + 1):
+            g = G(V1)
+            if np.linalg.norm(g) < atol:
+                return C0 + dt * (gm * V1 + (1.0 - gm) * V0), V1, k
+            if k == maxit:
+                break
+            J = np.empty((self.N, self.N))
+            for j in range(self.N):
+                h = 1e-6 * (1.0 + abs(V1[j]))
+                e = np.zeros(self.N)
+                e[j] = h
+                J[:, j] = (G(V1 + e) - G(V1 - e)) / (2.0 * h)
+            V1 = V1 - np.linalg.solve(J, g)
+        raise RuntimeError("oracle Cahn-Hilliard generalized-alpha Newton did not converge")
+
     def gen_alpha_step(self, U0, V0, dt, rho, atol=1e-12, maxit=30):
         """One generalized-alpha step (eq:ga) of M0 Udot + R(U) = 0: returns (U1, V1, Newton iterations)."""
         U0 = np.ascontiguousarray(U0, dtype=np.float64)

@@ -120,6 +120,8 @@ _SIGNATURES = {
     "iga_assemble_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_biharmonic_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_cahn_hilliard_residual": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p], C.c_int),
+    "iga_ch_gen_alpha_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
+                               C.POINTER(iga_newton_opts), C.c_void_p, C.c_void_p, C.POINTER(iga_newton_report)], C.c_int),
     "iga_gen_alpha_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.POINTER(iga_newton_opts),
                             C.c_void_p, C.c_void_p, C.POINTER(iga_newton_report)], C.c_int),
     "iga_assemble_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
@@ -312,6 +314,20 @@ class IGA:
                                          _dev_ptr(V0, torch.float64, self.N, "V0"), float(dt), float(rho_inf),
                                          C.byref(o), _dev_ptr(U1, torch.float64, self.N, "U1"),
                                          _dev_ptr(V1, torch.float64, self.N, "V1"), C.byref(rep)), "iga_gen_alpha_step")
+        return dict(converged=bool(rep.converged), newton_iters=rep.newton_iters,
+                    krylov_iters_total=rep.krylov_iters_total, res_norm=rep.res_norm)
+
+    def ch_gen_alpha_step(self, C0, V0, dt, rho_inf, theta, lam, C1, V1, atol=1e-10, max_newton=30, max_krylov=2000):
+        """One generalized-alpha step of the Cahn-Hilliard system (iga_ch_gen_alpha_step); returns the report."""
+        import torch
+        o = iga_newton_opts(atol, 0.0, max_newton, max_krylov, 0, IGA_FP64, 1e-2, 0)
+        rep = iga_newton_report()
+        _check(load().iga_ch_gen_alpha_step(self.h, _dev_ptr(C0, torch.float64, self.N, "C0"),
+                                            _dev_ptr(V0, torch.float64, self.N, "V0"), float(dt), float(rho_inf),
+                                            float(theta), float(lam), C.byref(o),
+                                            _dev_ptr(C1, torch.float64, self.N, "C1"),
+                                            _dev_ptr(V1, torch.float64, self.N, "V1"), C.byref(rep)),
+               "iga_ch_gen_alpha_step")
         return dict(converged=bool(rep.converged), newton_iters=rep.newton_iters,
                     krylov_iters_total=rep.krylov_iters_total, res_norm=rep.res_norm)
 

@@ -10,6 +10,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out);
 iga_status launch_norm(Handle &h, const double *x, double *out_dev);
 iga_status launch_diag_inv(Handle &h, const void *vals, int prec, double *dinv);
 iga_status launch_axpy(Handle &h, double a, const double *x, double *y);
+iga_status launch_dot(Handle &h, const double *x, const double *y, double *out_dev);
 iga_status cg_solve(Handle &h, const double *R, double *d, double rtol, int maxit, int check_every,
                     const void *vals, int prec, bool matrix_free, bool fdm, int *iters_out, double *rel_out);
 
@@ -334,6 +335,150 @@ static iga_status gen_alpha_step(Handle &h, const double *U0, const double *V0, 
   return st;
 }
 
+// ------------------------------------------------------------------------------------------
+// Generalized-alpha step of the Cahn-Hilliard system R_CH(cdot, c) = 0 (the Cahn-Hilliard residual
+// is linear in cdot): Newton on cdot_{n+1}, each linear system solved by BiCGStab (the Jacobian is
+// not symmetric) with Jacobian-vector products by a forward difference of the residual along the
+// stage direction (the matrix-free approach of Sec. 2.8): J x ~ (G(V1 + eps x) - G(V1)) / eps with
+// eps = sqrt(eps_machine) (1 + ||c_{n+af}||) / ||x||.
+// ------------------------------------------------------------------------------------------
+// o1 = a1 + s1 x, o2 = a2 + s2 x
+__global__ void k_lin2(int64_t n, const double *__restrict__ a1, double s1, const double *__restrict__ a2, double s2,
+                       const double *__restrict__ x, double *__restrict__ o1, double *__restrict__ o2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  o1[i] = a1[i] + s1 * x[i];
+  o2[i] = a2[i] + s2 * x[i];
+}
+
+static iga_status host_scalar(Handle &h, const double *dev, double *out) {
+  if (hipMemcpyAsync(out, dev, sizeof(double), hipMemcpyDeviceToHost, h.stream) != hipSuccess ||
+      hipStreamSynchronize(h.stream) != hipSuccess)
+    return fail(IGA_EHIP, "scalar read-back");
+  return IGA_OK;
+}
+
+static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V0, double dt, double rho,
+                                    double theta, double lam, const iga_newton_opts *o_in, double *C1, double *V1,
+                                    iga_newton_report *rep) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(IGA_EINVAL, "dt must be positive");
+  if (!(rho >= 0.0 && rho <= 1.0)) return fail(IGA_EINVAL, "rho_inf must be in [0, 1]");
+  iga_newton_opts o{};
+  o.atol = 1e-10;
+  o.max_newton = 30;
+  o.max_krylov = 2000;
+  o.forcing_max = 1e-2;
+  if (o_in) o = *o_in;
+  if (o.max_newton < 0 || o.max_newton > 64) return fail(IGA_EINVAL, "max_newton must be in 0..64");
+  if (o.max_krylov < 1) return fail(IGA_EINVAL, "max_krylov must be positive");
+  if (o.forcing_max <= 0) o.forcing_max = 1e-2;
+  const double am = 0.5 * (3.0 - rho) / (1.0 + rho), af = 1.0 / (1.0 + rho), gm = 0.5 + am - af;
+  iga_status st;
+  if ((st = ensure_newton_ws(h, false, IGA_FP64))) return st;
+  const int64_t N = h.pb.N;
+  if (!h.chw && (st = alloc_owned(h, (void **)&h.chw, (size_t)13 * N * sizeof(double)))) return st;
+  double *Ca = h.chw, *Va = Ca + N, *G = Va + N, *Gp = G + N, *tC = Gp + N, *tV = tC + N;
+  double *x = tV + N, *r = x + N, *rh = r + N, *p = rh + N, *v = p + N, *sv = v + N;
+  double *t = sv + N;
+  const unsigned nb = ga_blocks(N);
+  iga_newton_report rr{};
+  auto t0 = std::chrono::steady_clock::now();
+  IGA_HIP_CHECK(hipMemcpyAsync(V1, V0, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+  double ca_norm = 0;
+  // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV)
+  auto apply = [&](const double *y, double *out) -> iga_status {
+    iga_status s2;
+    double yn = 0;
+    if ((s2 = launch_norm(h, y, h.scal)) || (s2 = host_scalar(h, h.scal, &yn))) return s2;
+    if (yn == 0.0) return launch_fill(h, out, N, 0.0);
+    const double eps = 1.4901161193847656e-8 * (1.0 + ca_norm) / yn;
+    hipLaunchKernelGGL(k_lin2, dim3(nb), dim3(256), 0, h.stream, N, (const double *)Ca, eps * af * gm * dt,
+                       (const double *)Va, eps * am, y, tC, tV);
+    if ((s2 = launch_cahn_hilliard(h, tC, tV, theta, lam, Gp))) return s2;
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -1.0 / eps, (const double *)G, 0.0, out);
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0 / eps, (const double *)Gp, 1.0, out);
+    IGA_HIP_CHECK(hipGetLastError());
+    return IGA_OK;
+  };
+  auto dot = [&](const double *a, const double *b, double *out) -> iga_status {
+    iga_status s2 = launch_dot(h, a, b, h.scal);
+    return s2 ? s2 : host_scalar(h, h.scal, out);
+  };
+  double nr = 0, r0 = -1;
+  int k;
+  st = IGA_OK;
+  for (k = 0;; ++k) {
+    hipLaunchKernelGGL(k_ga_stage, dim3(nb), dim3(256), 0, h.stream, N, C0, V0, (const double *)V1, af * dt * gm,
+                       af * dt * (1.0 - gm), am, Ca, Va);
+    IGA_HIP_CHECK(hipGetLastError());
+    if ((st = launch_cahn_hilliard(h, Ca, Va, theta, lam, G))) break;
+    if ((st = launch_norm(h, G, h.scal)) || (st = host_scalar(h, h.scal, &nr))) break;
+    rr.hist[k] = nr;
+    if (r0 < 0) r0 = nr;
+    if (!std::isfinite(nr)) { st = fail(IGA_ENOCONV, "stage residual is not finite"); break; }
+    if (nr < o.atol || (o.rtol > 0 && nr <= o.rtol * r0)) { rr.converged = 1; break; }
+    if (k >= o.max_newton) { st = fail(IGA_ENOCONV, "Cahn-Hilliard Newton did not converge"); break; }
+    if ((st = launch_norm(h, Ca, h.scal)) || (st = host_scalar(h, h.scal, &ca_norm))) break;
+    // BiCGStab on A x = -G from x = 0
+    const double tol = fmin(o.forcing_max, fmax(1e-12, 0.1 * o.atol / nr)) * nr;
+    if ((st = launch_fill(h, x, N, 0.0)) || (st = launch_fill(h, p, N, 0.0)) || (st = launch_fill(h, v, N, 0.0))) break;
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -1.0, (const double *)G, 0.0, r);
+    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, 0.0, rh);
+    double rho_old = 1, alpha = 1, omega = 1, res = nr;
+    int it;
+    for (it = 0; it < o.max_krylov && res > tol; ++it) {
+      double rho_k;
+      if ((st = dot(rh, r, &rho_k))) break;
+      if (rho_k == 0.0) { st = fail(IGA_ENOCONV, "BiCGStab breakdown"); break; }
+      const double beta = (rho_k / rho_old) * (alpha / omega);
+      // p = r + beta (p - omega v)
+      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -omega, (const double *)v, 1.0, p);
+      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, beta, p);
+      if ((st = apply(p, v))) break;
+      double rhv;
+      if ((st = dot(rh, v, &rhv))) break;
+      alpha = rho_k / rhv;
+      // s = r - alpha v
+      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, 0.0, sv);
+      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -alpha, (const double *)v, 1.0, sv);
+      double sn;
+      if ((st = launch_norm(h, sv, h.scal)) || (st = host_scalar(h, h.scal, &sn))) break;
+      if (sn <= tol) {
+        if ((st = launch_axpy(h, alpha, p, x))) break;
+        res = sn;
+        ++it;
+        break;
+      }
+      if ((st = apply(sv, t))) break;
+      double ts, tt;
+      if ((st = dot(t, sv, &ts)) || (st = dot(t, t, &tt))) break;
+      omega = ts / tt;
+      if ((st = launch_axpy(h, alpha, p, x)) || (st = launch_axpy(h, omega, sv, x))) break;
+      // r = s - omega t
+      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)sv, 0.0, r);
+      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -omega, (const double *)t, 1.0, r);
+      if ((st = launch_norm(h, r, h.scal)) || (st = host_scalar(h, h.scal, &res))) break;
+      rho_old = rho_k;
+    }
+    if (st) break;
+    if (res > tol) { st = fail(IGA_ENOCONV, "BiCGStab did not reach its tolerance"); break; }
+    if ((st = launch_axpy(h, 1.0, x, V1))) break;
+    if (k < 64) rr.krylov_iters[k] = it;
+    rr.krylov_iters_total += it;
+  }
+  if (!st) {
+    IGA_HIP_CHECK(hipMemcpyAsync(C1, C0, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+    if (!(st = launch_axpy(h, dt * gm, V1, C1))) st = launch_axpy(h, dt * (1.0 - gm), V0, C1);
+    if (!st && hipStreamSynchronize(h.stream) != hipSuccess) st = fail(IGA_EHIP, "sync");
+  }
+  rr.newton_iters = k;
+  rr.res_norm0 = r0;
+  rr.res_norm = nr;
+  rr.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = rr;
+  return st;
+}
+
 }  // namespace iga
 
 using namespace iga;
@@ -446,6 +591,14 @@ iga_status iga_gen_alpha_step(iga_t hh, const double *U0, const double *V0, doub
   if (!hh || !U0 || !V0 || !U1 || !V1) return fail(IGA_EINVAL, "null argument");
   if (U1 == U0 || U1 == V0 || V1 == U0 || V1 == V0 || U1 == V1) return fail(IGA_EINVAL, "outputs must not alias inputs");
   return gen_alpha_step(*(Handle *)hh, U0, V0, dt, rho_inf, opts, U1, V1, report);
+}
+
+iga_status iga_ch_gen_alpha_step(iga_t hh, const double *C0, const double *V0, double dt, double rho_inf,
+                                 double theta, double lambda_ch, const iga_newton_opts *opts, double *C1, double *V1,
+                                 iga_newton_report *report) {
+  if (!hh || !C0 || !V0 || !C1 || !V1) return fail(IGA_EINVAL, "null argument");
+  if (C1 == C0 || C1 == V0 || V1 == C0 || V1 == V0 || C1 == V1) return fail(IGA_EINVAL, "outputs must not alias inputs");
+  return ch_gen_alpha_step(*(Handle *)hh, C0, V0, dt, rho_inf, theta, lambda_ch, opts, C1, V1, report);
 }
 
 iga_status iga_cahn_hilliard_residual(iga_t hh, const double *C, const double *Cdot, double theta, double lambda_ch,

@@ -149,6 +149,7 @@ struct Handle {
   // values), and the stage vectors U_{n+af}, Udot_{n+am} and a product
   double *massv = nullptr;
   double *gaw = nullptr;          // 3 * N doubles
+  double *chw = nullptr;          // Cahn-Hilliard generalized-alpha: 13 * N doubles
   // options
   int jac_algo = IGA_JAC_AUTO;
   int nd_color = 0;   // local-ND scatter: 0 atomics (default), 1 colour-ordered plain adds

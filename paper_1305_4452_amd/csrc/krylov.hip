@@ -327,6 +327,14 @@ iga_status launch_norm(Handle &h, const double *x, double *out_dev) {
   return IGA_OK;
 }
 
+iga_status launch_dot(Handle &h, const double *x, const double *y, double *out_dev) {
+  const int nb = vec_blocks(h.pb.N, h.npartials);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, h.stream, h.pb.N, x, y, h.partials);
+  hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(256), 0, h.stream, (const double *)h.partials, nb, out_dev, 0);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
 iga_status launch_diag_inv(Handle &h, const void *vals, int prec, double *dinv) {
   unsigned nb = (unsigned)((h.pb.N + 255) / 256);
   if (prec == IGA_FP32)

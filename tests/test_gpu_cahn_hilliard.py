@@ -57,3 +57,29 @@ def test_cahn_hilliard_residual_rejections():
         with pytest.raises(iga.IGAError) as ei:
             g.cahn_hilliard_residual(x, x, theta, 0.1, torch.empty_like(x))
         assert ei.value.status == status
+
+
+@pytest.mark.parametrize("name,dim,nel,p,rho,nsteps", [("periodic2_p2", 2, [8, 7], 2, 0.5, 2),
+                                                       ("periodic2_p3", 2, [8, 7], 3, 1.0, 2),
+                                                       ("periodic3_p2", 3, [5, 5, 5], 2, 0.5, 1)])
+def test_cahn_hilliard_generalized_alpha_matches_oracle(name, dim, nel, p, rho, nsteps):
+    """Steps of iga_ch_gen_alpha_step against the oracle's (both Newton to ||G|| < 1e-12; the GPU
+    with BiCGStab on difference Jacobian-vector products, the oracle with a dense difference Jacobian)."""
+    print(f"[case] Cahn-Hilliard generalized-alpha {name}", flush=True)
+    patch = inputs.unit_box(dim, nel, p)
+    per = [p - 1] * dim
+    g = iga.IGA(patch.knots, patch.degree, periodic=per)
+    o = oracle.Oracle(patch.knots, patch.degree, periodic=per)
+    C = 0.5 + 0.05 * inputs.uniform(41, 0, g.N, -1.0, 1.0)
+    V = np.zeros(g.N)
+    Cg, Vg = torch.as_tensor(C, device="cuda"), torch.as_tensor(V, device="cuda")
+    dt, theta, lam = 2e-3, 1.5, 0.01
+    for step in range(nsteps):
+        C1g, V1g = torch.empty_like(Cg), torch.empty_like(Vg)
+        rep = g.ch_gen_alpha_step(Cg, Vg, dt, rho, theta, lam, C1g, V1g, atol=1e-12)
+        assert rep["converged"]
+        C, V, _ = o.ch_gen_alpha_step(C, V, dt, rho, theta, lam, atol=1e-12)
+        torch.cuda.synchronize()
+        assert rel(C1g.cpu().numpy(), C) < 1e-10, step
+        assert rel(V1g.cpu().numpy(), V) < 1e-7, step
+        Cg, Vg = C1g, V1g

@@ -87,3 +87,18 @@ def test_fourth_order_term_vanishes_for_a_constant_laplacian(dim, p):
     assert interior.sum() > 0
     scale = np.abs(lam_part).max()
     assert np.abs(lam_part[interior]).max() < 1e-11 * scale, np.abs(lam_part[interior]).max() / scale
+
+
+def test_generalized_alpha_step_conserves_mass_and_keeps_uniform_states():
+    """With every axis periodic the residual's rows sum to the integral of cdot, so a step that starts
+    from a zero-mean rate keeps the integral of c; a uniform state at rest stays put."""
+    patch, per = periodic_patch(2, 2)
+    o = oracle.Oracle(patch.knots, patch.degree, periodic=per)
+    m = np.asarray(o.mass_matrix().sum(axis=0)).ravel()
+    C0 = 0.5 + 0.05 * np.random.default_rng(2).uniform(-1, 1, o.N)
+    C1, V1, it = o.ch_gen_alpha_step(C0, np.zeros(o.N), 1e-3, 0.5, 1.5, 0.01)
+    assert it >= 1
+    assert abs(m @ C1 - m @ C0) < 1e-12 * abs(m @ C0)
+    assert abs(m @ V1) < 1e-9 * np.abs(V1).max() * m.sum()
+    Cu, Vu, _ = o.ch_gen_alpha_step(np.full(o.N, 0.4), np.zeros(o.N), 1e-3, 0.5, 1.5, 0.01)
+    assert np.abs(Cu - 0.4).max() < 1e-14 and np.abs(Vu).max() < 1e-12
