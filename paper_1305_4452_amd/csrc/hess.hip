@@ -277,6 +277,22 @@ iga_status run_ch(Handle &h, const double *C, const double *Cd, double theta, do
 }
 
 template <int P>
+__global__ void __launch_bounds__(rs3::kThreads) k_ch3(DevProblem pb, const double *__restrict__ C,
+                                                       const double *__restrict__ Cd, double theta, double lam,
+                                                       double *__restrict__ R) {
+  __shared__ double lds[rs3::Ch3<P>::total / sizeof(double)];
+  rs3::ch3_body<P>(pb, (int)blockIdx.x, C, Cd, theta, lam, R, lds);
+}
+
+template <int P>
+iga_status run_ch3(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R) {
+  const unsigned nb = (unsigned)rs3::res3_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], rs3::Ch3<P>::TE);
+  hipLaunchKernelGGL(k_ch3<P>, dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, C, Cd, theta, lam, R);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+template <int P>
 __global__ void __launch_bounds__(rs3::kThreads) k_bih3(DevProblem pb, const double *__restrict__ U,
                                                         double *__restrict__ R) {
   __shared__ double lds[rs3::Res3<P>::total / sizeof(double)];
@@ -307,6 +323,12 @@ iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, do
   if (p < 2) return fail(IGA_EUNSUPPORTED, "the Cahn-Hilliard residual needs p >= 2");
   iga_status st = launch_fill(h, R, h.pb.N, 0.0);
   if (st) return st;
+  // 3D with simple knots: tiles with sum factorisation (IGA_OPT_TILED_3D = 0 keeps one element per
+  // workgroup, for comparison)
+  if (h.pb.dim == 3 && h.pb.simple_knots && h.tiled_3d) {
+    if (p == 2) return run_ch3<3>(h, C, Cd, theta, lam, R);
+    if (p == 3) return run_ch3<4>(h, C, Cd, theta, lam, R);
+  }
   if (h.pb.dim == 2) {
     switch (p) {
       case 2: return run_ch<2, 3>(h, C, Cd, theta, lam, R);

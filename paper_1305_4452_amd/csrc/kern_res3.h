@@ -383,5 +383,216 @@ __device__ inline void bih3_body(const DevProblem &pb, const int tile, const dou
   }
 }
 
+// Cahn-Hilliard residual on x = xi without weights, by the tiles above (see the element kernel for the
+// form): forward, axis 0 gives B.c, B'.c, B''.c and B.cdot, axis 1 the six products that c, its
+// gradient, its Laplacian and cdot need, axis 2 those at every point; the point terms are
+// S0 = W cdot, F = W (M mu' + lam M' Lap c) grad c and S2 = W lam M Lap c; transposed, the terms
+// B0 B1 (B2 S0 + B2' F2 + B2'' S2) + B0' B1 B2 F0 + B0 B1' B2 F1 + (B0'' B1 + B0 B1'') B2 S2 are
+// contracted axis by axis.  One FP64 atomic per tile function; the output must be zeroed before.
+template <int P>
+struct Ch3 {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TE = P == 2 ? 4 : P == 3 ? 3 : 2;
+  static constexpr int NI = TE + p, G = TE * Q, GP = G * P;
+  static constexpr int n_c = NI * NI * NI, n_a = NI * NI * G, n_u = NI * G * G, n_f = G * G * G;
+  static constexpr int n_b = 9 * GP + 3 * G;
+  static constexpr size_t total = (size_t)(2 * n_c + 4 * n_a + 6 * n_u + 5 * n_f + n_b) * sizeof(double);
+};
+
+template <int P>
+__device__ inline void ch3_body(const DevProblem &pb, const int tile, const double *__restrict__ Cv,
+                                const double *__restrict__ Cd, double theta, double lam, double *__restrict__ Y,
+                                double *__restrict__ lds) {
+  using S_ = Ch3<P>;
+  constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G, GP = S_::GP;
+  constexpr int NT = kThreads;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
+  const int nt0 = (ne0 + TE - 1) / TE, nt1 = (ne1 + TE - 1) / TE;
+  const int E0 = (tile % nt0) * TE, E1 = ((tile / nt0) % nt1) * TE, E2 = (tile / (nt0 * nt1)) * TE;
+  const int NE0 = min(TE, ne0 - E0), NE1 = min(TE, ne1 - E1), NE2 = min(TE, ne2 - E2);
+  const int G0 = NE0 * Q, G1 = NE1 * Q, G2 = NE2 * Q;
+  const int NI0 = NE0 + p, NI1 = NE1 + p, NI2 = NE2 + p;
+  double *c = lds, *cd = c + S_::n_c;                                      // [k2][k1][k0]
+  double *aB = cd + S_::n_c, *aD = aB + S_::n_a, *aE = aD + S_::n_a, *aR = aE + S_::n_a;   // [k2][k1][g0]
+  double *bBB = aR + S_::n_a, *bDB = bBB + S_::n_u, *bBE = bDB + S_::n_u;   // [k2][g1][g0]
+  double *bEB = bBE + S_::n_u, *bBD = bEB + S_::n_u, *bRB = bBD + S_::n_u;
+  double *F0 = bRB + S_::n_u, *F1 = F0 + S_::n_f, *F2 = F1 + S_::n_f, *S0 = F2 + S_::n_f, *S2 = S0 + S_::n_f;
+  double *tb = S2 + S_::n_f, *tw = tb + 9 * GP;                             // [axis][B|B'|B''][G][P], [axis][G]
+  // transposed stage arrays reuse the forward ones
+  double *Ybb = bBB, *Yf0 = bDB, *Yf1 = bBE, *Ys = bEB;                    // [k2][g1][g0]
+  double *Zb = aB, *Zd = aD, *Ze = aE;                                      // [k2][k1][g0]
+  const int t = threadIdx.x;
+  auto T = [&](int d, int kind) { return tb + (d * 3 + kind) * GP; };
+  const int Ed[3] = {E0, E1, E2}, Gd[3] = {G0, G1, G2};
+  for (int d = 0; d < 3; ++d) {
+    const AxisDev &ax = pb.ax[d];
+    for (int i = t; i < GP; i += NT) {
+      if (i / P < Gd[d]) {
+        const size_t o = (size_t)Ed[d] * Q * P + i;
+        T(d, 0)[i] = ax.B[o];
+        T(d, 1)[i] = ax.dB[o];
+        T(d, 2)[i] = ax.d2B[o];
+      }
+    }
+    for (int i = t; i < G; i += NT)
+      if (i < Gd[d]) tw[d * G + i] = ax.wq[(size_t)Ed[d] * Q + i];
+  }
+  for (int i = t; i < NI * NI * NI; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+    const int64_t A = wrap_fn(pb.ax[0], E0 + k0) +
+                      (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], E2 + k2));
+    c[i] = Cv[A];
+    cd[i] = Cd[A];
+  }
+  __syncthreads();
+  {
+    const double *B = T(0, 0), *D = T(0, 1), *E = T(0, 2);
+    for (int i = t; i < NI * NI * G; i += NT) {
+      const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), el0 = g0 / Q;
+      if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+      const int o = (k2 * NI + k1) * NI + el0;
+      double vb = 0, vd = 0, ve = 0, vr = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < P; ++a0) {
+        vb += B[g0 * P + a0] * c[o + a0];
+        vd += D[g0 * P + a0] * c[o + a0];
+        ve += E[g0 * P + a0] * c[o + a0];
+        vr += B[g0 * P + a0] * cd[o + a0];
+      }
+      aB[i] = vb;
+      aD[i] = vd;
+      aE[i] = ve;
+      aR[i] = vr;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = T(1, 0), *D = T(1, 1), *E = T(1, 2);
+    for (int i = t; i < NI * G * G; i += NT) {
+      const int g0 = i % G, g1 = (i / G) % G, k2 = i / (G * G), el1 = g1 / Q;
+      if (g0 >= G0 || g1 >= G1 || k2 >= NI2) continue;
+      double bb = 0, db = 0, be = 0, eb = 0, bd = 0, rb = 0;
+#pragma unroll
+      for (int a1 = 0; a1 < P; ++a1) {
+        const int r = (k2 * NI + el1 + a1) * G + g0;
+        const double b = B[g1 * P + a1];
+        bb += b * aB[r];
+        db += b * aD[r];               // d/dxi0
+        be += E[g1 * P + a1] * aB[r];  // d2/dxi1^2
+        eb += b * aE[r];               // d2/dxi0^2
+        bd += D[g1 * P + a1] * aB[r];  // d/dxi1
+        rb += b * aR[r];               // rate
+      }
+      bBB[i] = bb;
+      bDB[i] = db;
+      bBE[i] = be;
+      bEB[i] = eb;
+      bBD[i] = bd;
+      bRB[i] = rb;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = T(2, 0), *D = T(2, 1), *E = T(2, 2);
+    for (int i = t; i < G * G * G; i += NT) {
+      const int g0 = i % G, g1 = (i / G) % G, g2 = i / (G * G), el2 = g2 / Q;
+      if (g0 >= G0 || g1 >= G1 || g2 >= G2) continue;
+      double cv = 0, c0 = 0, c1 = 0, c2 = 0, lc = 0, cr = 0;
+#pragma unroll
+      for (int a2 = 0; a2 < P; ++a2) {
+        const int r = ((el2 + a2) * G + g1) * G + g0;
+        const double b = B[g2 * P + a2];
+        cv += b * bBB[r];
+        c0 += b * bDB[r];
+        c1 += b * bBD[r];
+        c2 += D[g2 * P + a2] * bBB[r];
+        lc += b * (bEB[r] + bBE[r]) + E[g2 * P + a2] * bBB[r];
+        cr += b * bRB[r];
+      }
+      const double W = tw[g0] * tw[G + g1] * tw[2 * G + g2];
+      const double M = cv * (1.0 - cv), dM = 1.0 - 2.0 * cv, dmu = 1.0 / (2.0 * theta * cv * (1.0 - cv)) - 2.0;
+      const double sg = W * (M * dmu + lam * dM * lc);
+      F0[i] = sg * c0;
+      F1[i] = sg * c1;
+      F2[i] = sg * c2;
+      S0[i] = W * cr;
+      S2[i] = W * lam * M * lc;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = T(2, 0), *D = T(2, 1), *E = T(2, 2);
+    for (int i = t; i < NI * G * G; i += NT) {
+      const int g0 = i % G, g1 = (i / G) % G, k2 = i / (G * G);
+      if (g0 >= G0 || g1 >= G1 || k2 >= NI2) continue;
+      double ybb = 0, yf0 = 0, yf1 = 0, ys = 0;
+#pragma unroll
+      for (int a2 = 0; a2 <= p; ++a2) {
+        const int el2 = k2 - a2;
+        if (el2 < 0 || el2 >= NE2) continue;
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) {
+          const int g2 = el2 * Q + q2, w = (g2 * G + g1) * G + g0, o = g2 * P + a2;
+          ybb += B[o] * S0[w] + D[o] * F2[w] + E[o] * S2[w];
+          yf0 += B[o] * F0[w];
+          yf1 += B[o] * F1[w];
+          ys += B[o] * S2[w];
+        }
+      }
+      Ybb[i] = ybb;
+      Yf0[i] = yf0;
+      Yf1[i] = yf1;
+      Ys[i] = ys;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = T(1, 0), *D = T(1, 1), *E = T(1, 2);
+    for (int i = t; i < NI * NI * G; i += NT) {
+      const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI);
+      if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+      double zb = 0, zd = 0, ze = 0;
+#pragma unroll
+      for (int a1 = 0; a1 <= p; ++a1) {
+        const int el1 = k1 - a1;
+        if (el1 < 0 || el1 >= NE1) continue;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) {
+          const int g1 = el1 * Q + q1, w = (k2 * G + g1) * G + g0, o = g1 * P + a1;
+          zb += B[o] * Ybb[w] + D[o] * Yf1[w] + E[o] * Ys[w];
+          zd += B[o] * Yf0[w];
+          ze += B[o] * Ys[w];
+        }
+      }
+      Zb[i] = zb;
+      Zd[i] = zd;
+      Ze[i] = ze;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = T(0, 0), *D = T(0, 1), *E = T(0, 2);
+    for (int i = t; i < NI * NI * NI; i += NT) {
+      const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+      if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+      double r = 0;
+#pragma unroll
+      for (int a0 = 0; a0 <= p; ++a0) {
+        const int el0 = k0 - a0;
+        if (el0 < 0 || el0 >= NE0) continue;
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+          const int g0 = el0 * Q + q0, w = (k2 * NI + k1) * G + g0, o = g0 * P + a0;
+          r += B[o] * Zb[w] + D[o] * Zd[w] + E[o] * Ze[w];
+        }
+      }
+      atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
+                   (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], E2 + k2))],
+                r);
+    }
+  }
+}
+
 }  // namespace rs3
 }  // namespace iga

@@ -24,16 +24,24 @@ CASES = {
     "open2_p5": (2, [3, 4], 5, False),
     "periodic3_p2": (3, [8, 7, 7], 2, True),
     "open3_p3": (3, [3, 4, 2], 3, False),
+    "open3_p2_tiles": (3, [9, 5, 6], 2, False),
+    "periodic3_p3_tiles": (3, [7, 8, 7], 3, True),
 }
 
 
+@pytest.mark.parametrize("tiled", [1, 0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_cahn_hilliard_residual_matches_oracle(name):
-    print(f"[case] Cahn-Hilliard residual {name}", flush=True)
+def test_cahn_hilliard_residual_matches_oracle(name, tiled):
+    """3D runs both on tiles with sum factorisation (several tiles, ragged at the far ends) and one
+    element per workgroup; 2D has the element kernel only."""
     dim, nel, p, periodic = CASES[name]
+    if dim == 2 and not tiled:
+        pytest.skip("2D has one kernel")
+    print(f"[case] Cahn-Hilliard residual {name} tiled={tiled}", flush=True)
     patch = inputs.unit_box(dim, nel, p)
     per = [p - 1] * dim if periodic else None
     g = iga.IGA(patch.knots, patch.degree, periodic=per)
+    g.set_option(iga.IGA_OPT_TILED_3D, tiled)
     o = oracle.Oracle(patch.knots, patch.degree, periodic=per)
     assert g.N == o.N
     for stream, (theta, lam) in enumerate([(0.667, 0.01), (1.5, 0.2)]):
