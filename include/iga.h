@@ -79,8 +79,8 @@ typedef enum {
                                 launch share a value) */
   IGA_OPT_TILED_3D = 8       /* 3D residual and matrix-free apply with x = xi, no weights, no source:
                                 1 by tiles of elements (default), 0 one element per workgroup; also the
-                                fourth-order operator and the Cahn-Hilliard residual on x = xi without
-                                weights */
+                                3D fourth-order operator on x = xi without weights, and the 2D and 3D
+                                Cahn-Hilliard residual */
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):

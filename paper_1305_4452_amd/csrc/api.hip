@@ -351,8 +351,8 @@ __global__ void k_lin2(int64_t n, const double *__restrict__ a1, double s1, cons
   o2[i] = a2[i] + s2 * x[i];
 }
 
-static iga_status host_scalar(Handle &h, const double *dev, double *out) {
-  if (hipMemcpyAsync(out, dev, sizeof(double), hipMemcpyDeviceToHost, h.stream) != hipSuccess ||
+static iga_status host_scalar(Handle &h, const double *dev, double *out, int n = 1) {
+  if (hipMemcpyAsync(out, dev, n * sizeof(double), hipMemcpyDeviceToHost, h.stream) != hipSuccess ||
       hipStreamSynchronize(h.stream) != hipSuccess)
     return fail(IGA_EHIP, "scalar read-back");
   return IGA_OK;
@@ -385,11 +385,11 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
   auto t0 = std::chrono::steady_clock::now();
   IGA_HIP_CHECK(hipMemcpyAsync(V1, V0, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
   double ca_norm = 0;
-  // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV)
-  auto apply = [&](const double *y, double *out) -> iga_status {
+  // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV); yn = ||y||
+  // when known, negative otherwise
+  auto apply = [&](const double *y, double *out, double yn) -> iga_status {
     iga_status s2;
-    double yn = 0;
-    if ((s2 = launch_norm(h, y, h.scal)) || (s2 = host_scalar(h, h.scal, &yn))) return s2;
+    if (yn < 0 && ((s2 = launch_norm(h, y, h.scal)) || (s2 = host_scalar(h, h.scal, &yn)))) return s2;
     if (yn == 0.0) return launch_fill(h, out, N, 0.0);
     const double eps = 1.4901161193847656e-8 * (1.0 + ca_norm) / yn;
     hipLaunchKernelGGL(k_lin2, dim3(nb), dim3(256), 0, h.stream, N, (const double *)Ca, eps * af * gm * dt,
@@ -424,17 +424,15 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
     if ((st = launch_fill(h, x, N, 0.0)) || (st = launch_fill(h, p, N, 0.0)) || (st = launch_fill(h, v, N, 0.0))) break;
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -1.0, (const double *)G, 0.0, r);
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, 0.0, rh);
-    double rho_old = 1, alpha = 1, omega = 1, res = nr;
+    double rho_old = 1, alpha = 1, omega = 1, res = nr, rho_k = nr * nr;   // (rh, r) with rh = r = -G
     int it;
     for (it = 0; it < o.max_krylov && res > tol; ++it) {
-      double rho_k;
-      if ((st = dot(rh, r, &rho_k))) break;
       if (rho_k == 0.0) { st = fail(IGA_ENOCONV, "BiCGStab breakdown"); break; }
       const double beta = (rho_k / rho_old) * (alpha / omega);
       // p = r + beta (p - omega v)
       hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -omega, (const double *)v, 1.0, p);
       hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, beta, p);
-      if ((st = apply(p, v))) break;
+      if ((st = apply(p, v, -1.0))) break;
       double rhv;
       if ((st = dot(rh, v, &rhv))) break;
       alpha = rho_k / rhv;
@@ -449,16 +447,24 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
         ++it;
         break;
       }
-      if ((st = apply(sv, t))) break;
-      double ts, tt;
-      if ((st = dot(t, sv, &ts)) || (st = dot(t, t, &tt))) break;
-      omega = ts / tt;
+      if ((st = apply(sv, t, sn))) break;
+      double tst[2];
+      if ((st = launch_dot(h, t, sv, h.scal)) || (st = launch_dot(h, t, t, h.scal + 1)) ||
+          (st = host_scalar(h, h.scal, tst, 2)))
+        break;
+      omega = tst[0] / tst[1];
       if ((st = launch_axpy(h, alpha, p, x)) || (st = launch_axpy(h, omega, sv, x))) break;
       // r = s - omega t
       hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)sv, 0.0, r);
       hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -omega, (const double *)t, 1.0, r);
-      if ((st = launch_norm(h, r, h.scal)) || (st = host_scalar(h, h.scal, &res))) break;
+      // ||r|| and the next (rh, r) in one read-back
+      double rr2[2];
+      if ((st = launch_norm(h, r, h.scal)) || (st = launch_dot(h, rh, r, h.scal + 1)) ||
+          (st = host_scalar(h, h.scal, rr2, 2)))
+        break;
+      res = rr2[0];
       rho_old = rho_k;
+      rho_k = rr2[1];
     }
     if (st) break;
     if (res > tol) { st = fail(IGA_ENOCONV, "BiCGStab did not reach its tolerance"); break; }

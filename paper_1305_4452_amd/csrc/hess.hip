@@ -20,6 +20,7 @@
 // On x = xi without weights in 3D the Laplacian factorises axis by axis and the operator runs by
 // tiles of elements with sum factorisation instead (bih3_body, the residual's tiles and LDS plan).
 #include "iga_impl.h"
+#include "kern_res2.h"
 #include "kern_res3.h"
 
 namespace iga {
@@ -277,6 +278,22 @@ iga_status run_ch(Handle &h, const double *C, const double *Cd, double theta, do
 }
 
 template <int P>
+__global__ void __launch_bounds__(rst::kThreads) k_ch2(DevProblem pb, const double *__restrict__ C,
+                                                       const double *__restrict__ Cd, double theta, double lam,
+                                                       double *__restrict__ R) {
+  __shared__ double lds[rst::Ch2<P>::total / sizeof(double)];
+  rst::ch2_body<P>(pb, (int)blockIdx.x, C, Cd, theta, lam, R, lds);
+}
+
+template <int P>
+iga_status run_ch2(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R) {
+  const unsigned nb = (unsigned)rst::res2_tiles(h.pb.ne[0], h.pb.ne[1], rst::Ch2<P>::TE);
+  hipLaunchKernelGGL(k_ch2<P>, dim3(nb), dim3(rst::kThreads), 0, h.stream, h.pb, C, Cd, theta, lam, R);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+template <int P>
 __global__ void __launch_bounds__(rs3::kThreads) k_ch3(DevProblem pb, const double *__restrict__ C,
                                                        const double *__restrict__ Cd, double theta, double lam,
                                                        double *__restrict__ R) {
@@ -323,11 +340,21 @@ iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, do
   if (p < 2) return fail(IGA_EUNSUPPORTED, "the Cahn-Hilliard residual needs p >= 2");
   iga_status st = launch_fill(h, R, h.pb.N, 0.0);
   if (st) return st;
-  // 3D with simple knots: tiles with sum factorisation (IGA_OPT_TILED_3D = 0 keeps one element per
-  // workgroup, for comparison)
-  if (h.pb.dim == 3 && h.pb.simple_knots && h.tiled_3d) {
-    if (p == 2) return run_ch3<3>(h, C, Cd, theta, lam, R);
-    if (p == 3) return run_ch3<4>(h, C, Cd, theta, lam, R);
+  // simple knots: tiles with sum factorisation (IGA_OPT_TILED_3D = 0 keeps one element per workgroup,
+  // for comparison)
+  if (h.pb.simple_knots && h.tiled_3d) {
+    if (h.pb.dim == 3) {
+      if (p == 2) return run_ch3<3>(h, C, Cd, theta, lam, R);
+      if (p == 3) return run_ch3<4>(h, C, Cd, theta, lam, R);
+    } else {
+      switch (p) {
+        case 2: return run_ch2<3>(h, C, Cd, theta, lam, R);
+        case 3: return run_ch2<4>(h, C, Cd, theta, lam, R);
+        case 4: return run_ch2<5>(h, C, Cd, theta, lam, R);
+        case 5: return run_ch2<6>(h, C, Cd, theta, lam, R);
+        case 6: return run_ch2<7>(h, C, Cd, theta, lam, R);
+      }
+    }
   }
   if (h.pb.dim == 2) {
     switch (p) {

@@ -158,5 +158,149 @@ __device__ inline void res2_body(const DevProblem &pb, const int tile, const dou
   }
 }
 
+// Cahn-Hilliard residual on x = xi without weights by 2D tiles (the form of the element kernel):
+// forward, axis 0 gives B.c, B'.c, B''.c and B.cdot per function row, axis 1 the value, gradient,
+// Laplacian and rate at every point; the point terms are S0 = W cdot, F = W (M mu' + lam M' Lap c)
+// grad c and S2 = W lam M Lap c; transposed, B0 (B1 S0 + B1' F1 + B1'' S2) + B0' B1 F0 + B0'' B1 S2
+// is contracted axis by axis.  Tiles of about 24 Gauss points per side keep four workgroups or more
+// per CU on a 256^2 mesh.  One FP64 atomic per tile function; the output must be zeroed before.
+template <int P>
+struct Ch2 {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TE = 24 / Q > 2 ? 24 / Q : 2;
+  static constexpr int NI = TE + p, G = TE * Q, GP = G * P;
+  static constexpr int n_c = NI * NI, n_a = NI * G, n_f = G * G, n_b = 6 * GP + 2 * G;
+  static constexpr size_t total = (size_t)(2 * n_c + 4 * n_a + 4 * n_f + n_b) * sizeof(double);
+};
+
+template <int P>
+__device__ inline void ch2_body(const DevProblem &pb, const int tile, const double *__restrict__ Cv,
+                                const double *__restrict__ Cd, double theta, double lam, double *__restrict__ Y,
+                                double *__restrict__ lds) {
+  using S_ = Ch2<P>;
+  constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G, GP = S_::GP;
+  const int n0 = pb.n[0], ne0 = pb.ne[0], ne1 = pb.ne[1];
+  const int nt0 = (ne0 + TE - 1) / TE;
+  const int E0 = (tile % nt0) * TE, E1 = (tile / nt0) * TE;
+  const int NE0 = min(TE, ne0 - E0), NE1 = min(TE, ne1 - E1);
+  const int G0 = NE0 * Q, G1 = NE1 * Q, NI0 = NE0 + p, NI1 = NE1 + p;
+  double *c = lds, *cd = c + S_::n_c;                                                    // [k1][k0]
+  double *aB = cd + S_::n_c, *aD = aB + S_::n_a, *aE = aD + S_::n_a, *aR = aE + S_::n_a;  // [k1][g0]
+  double *F0 = aR + S_::n_a, *F1 = F0 + S_::n_f, *S0 = F1 + S_::n_f, *S2 = S0 + S_::n_f;  // [g1][g0]
+  double *tb = S2 + S_::n_f, *tw = tb + 6 * GP;   // [axis][B|B'|B''][G][P], [axis][G]
+  double *Zb = aB, *Zd = aD, *Ze = aE;            // [k1][g0], once the point terms are formed
+  const int t = threadIdx.x;
+  const int Ed[2] = {E0, E1}, Gd[2] = {G0, G1};
+  for (int d = 0; d < 2; ++d) {
+    const AxisDev &ax = pb.ax[d];
+    double *T = tb + d * 3 * GP;
+    for (int i = t; i < Gd[d] * P; i += kThreads) {
+      const size_t o = (size_t)Ed[d] * Q * P + i;
+      T[i] = ax.B[o];
+      T[GP + i] = ax.dB[o];
+      T[2 * GP + i] = ax.d2B[o];
+    }
+    for (int i = t; i < Gd[d]; i += kThreads) tw[d * G + i] = ax.wq[(size_t)Ed[d] * Q + i];
+  }
+  for (int i = t; i < NI * NI; i += kThreads) {
+    const int k0 = i % NI, k1 = i / NI;
+    if (k0 >= NI0 || k1 >= NI1) continue;
+    const int64_t A = wrap_fn(pb.ax[0], E0 + k0) + (int64_t)n0 * wrap_fn(pb.ax[1], E1 + k1);   // eq:map-wrap
+    c[i] = Cv[A];
+    cd[i] = Cd[A];
+  }
+  __syncthreads();
+  {
+    const double *B = tb, *D = tb + GP, *E = tb + 2 * GP;
+    for (int i = t; i < NI * G; i += kThreads) {
+      const int g0 = i % G, k1 = i / G, el0 = g0 / Q;
+      if (g0 >= G0 || k1 >= NI1) continue;
+      const int o = k1 * NI + el0;
+      double vb = 0, vd = 0, ve = 0, vr = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < P; ++a0) {
+        vb += B[g0 * P + a0] * c[o + a0];
+        vd += D[g0 * P + a0] * c[o + a0];
+        ve += E[g0 * P + a0] * c[o + a0];
+        vr += B[g0 * P + a0] * cd[o + a0];
+      }
+      aB[i] = vb;
+      aD[i] = vd;
+      aE[i] = ve;
+      aR[i] = vr;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = tb + 3 * GP, *D = tb + 4 * GP, *E = tb + 5 * GP;
+    for (int i = t; i < G * G; i += kThreads) {
+      const int g0 = i % G, g1 = i / G, el1 = g1 / Q;
+      if (g0 >= G0 || g1 >= G1) continue;
+      double cv = 0, c0 = 0, c1 = 0, lc = 0, cr = 0;
+#pragma unroll
+      for (int a1 = 0; a1 < P; ++a1) {
+        const int r = (el1 + a1) * G + g0, o = g1 * P + a1;
+        const double b = B[o];
+        cv += b * aB[r];
+        c0 += b * aD[r];
+        c1 += D[o] * aB[r];
+        lc += b * aE[r] + E[o] * aB[r];
+        cr += b * aR[r];
+      }
+      const double W = tw[g0] * tw[G + g1];
+      const double M = cv * (1.0 - cv), dM = 1.0 - 2.0 * cv, dmu = 1.0 / (2.0 * theta * cv * (1.0 - cv)) - 2.0;
+      const double sg = W * (M * dmu + lam * dM * lc);
+      F0[i] = sg * c0;
+      F1[i] = sg * c1;
+      S0[i] = W * cr;
+      S2[i] = W * lam * M * lc;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = tb + 3 * GP, *D = tb + 4 * GP, *E = tb + 5 * GP;
+    for (int i = t; i < NI * G; i += kThreads) {
+      const int g0 = i % G, k1 = i / G;
+      if (g0 >= G0 || k1 >= NI1) continue;
+      double zb = 0, zd = 0, ze = 0;
+#pragma unroll
+      for (int a1 = 0; a1 <= p; ++a1) {
+        const int el1 = k1 - a1;
+        if (el1 < 0 || el1 >= NE1) continue;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) {
+          const int g1 = el1 * Q + q1, w = g1 * G + g0, o = g1 * P + a1;
+          zb += B[o] * S0[w] + D[o] * F1[w] + E[o] * S2[w];
+          zd += B[o] * F0[w];
+          ze += B[o] * S2[w];
+        }
+      }
+      Zb[i] = zb;
+      Zd[i] = zd;
+      Ze[i] = ze;
+    }
+  }
+  __syncthreads();
+  {
+    const double *B = tb, *D = tb + GP, *E = tb + 2 * GP;
+    for (int i = t; i < NI * NI; i += kThreads) {
+      const int k0 = i % NI, k1 = i / NI;
+      if (k0 >= NI0 || k1 >= NI1) continue;
+      double r = 0;
+#pragma unroll
+      for (int a0 = 0; a0 <= p; ++a0) {
+        const int el0 = k0 - a0;
+        if (el0 < 0 || el0 >= NE0) continue;
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+          const int g0 = el0 * Q + q0, w = k1 * G + g0, o = g0 * P + a0;
+          r += B[o] * Zb[w] + D[o] * Zd[w] + E[o] * Ze[w];
+        }
+      }
+      atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) + (int64_t)n0 * wrap_fn(pb.ax[1], E1 + k1)], r);
+    }
+  }
+}
+
 }  // namespace rst
 }  // namespace iga
