@@ -181,7 +181,9 @@ iga_status iga_cahn_hilliard_residual(iga_t h, const double *C_dev, const double
  * cdot_n; each linear system by BiCGStab (the Jacobian is not symmetric) on Jacobian-vector products
  * by a forward difference of the residual (the matrix-free approach of Sec. 2.8), step
  * sqrt(eps) (1 + ||c_{n+af}||) / ||x||; stops when ||G||_2 < opts->atol.  opts: atol, rtol,
- * max_newton, max_krylov (BiCGStab iterations per Newton step), forcing_max; NULL: defaults.
+ * max_newton, max_krylov (BiCGStab iterations per Newton step), forcing_max; NULL: defaults.  BiCGStab
+ * keeps its scalars on the device and the host tests its residual norm every 4 iterations; the report
+ * counts the iterations that changed the iterate.
  * Same geometry limits as iga_cahn_hilliard_residual.  IGA_ENOCONV if Newton or BiCGStab fails.
  * Synchronous. */
 iga_status iga_ch_gen_alpha_step(iga_t h, const double *C0_dev, const double *V0_dev, double dt, double rho_inf,

@@ -342,13 +342,74 @@ static iga_status gen_alpha_step(Handle &h, const double *U0, const double *V0, 
 // stage direction (the matrix-free approach of Sec. 2.8): J x ~ (G(V1 + eps x) - G(V1)) / eps with
 // eps = sqrt(eps_machine) (1 + ||c_{n+af}||) / ||x||.
 // ------------------------------------------------------------------------------------------
-// o1 = a1 + s1 x, o2 = a2 + s2 x
-__global__ void k_lin2(int64_t n, const double *__restrict__ a1, double s1, const double *__restrict__ a2, double s2,
-                       const double *__restrict__ x, double *__restrict__ o1, double *__restrict__ o2) {
+
+// BiCGStab scalars kept on the device, in the handle's scalar block: the residual norm, the count of
+// iterations taken, rho = (rh, r) and the rest of the recurrence.  Every update kernel is a no-op once
+// the residual norm is at or below tol, so the host reads the norm back only every few iterations.
+enum { kRes = 8, kIts, kRho, kRhoOld, kAlpha, kOmega, kRhv, kTs, kTt, kYn, kSn };
+
+__global__ void k_bcg_init(double *S, double res) {
+  S[kRes] = res;
+  S[kIts] = 0;
+  S[kRhoOld] = 1;
+  S[kAlpha] = 1;
+  S[kOmega] = 1;
+}
+
+// p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega)
+__global__ void k_bcg_p(int64_t n, const double *__restrict__ r, const double *__restrict__ v, double *__restrict__ p,
+                        const double *__restrict__ S, double tol) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || S[kRes] <= tol) return;
+  const double beta = (S[kRho] / S[kRhoOld]) * (S[kAlpha] / S[kOmega]);
+  p[i] = r[i] + beta * (p[i] - S[kOmega] * v[i]);
+}
+
+// s = r - alpha v, alpha = rho / (rh, v)
+__global__ void k_bcg_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v, double *__restrict__ s,
+                        double *__restrict__ S, double tol) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || S[kRes] <= tol) return;
+  const double alpha = S[kRho] / S[kRhv];
+  s[i] = r[i] - alpha * v[i];
+  if (i == 0) S[kAlpha] = alpha;   // no lane of this launch reads it
+}
+
+// x += alpha p + omega s, r = s - omega t, omega = (t, s) / (t, t) (0 when t = 0, i.e. s = 0)
+__global__ void k_bcg_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ s,
+                         const double *__restrict__ t, double *__restrict__ x, double *__restrict__ r,
+                         double *__restrict__ S, double tol) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || S[kRes] <= tol) return;
+  const double tt = S[kTt], om = tt > 0 ? S[kTs] / tt : 0.0, al = S[kAlpha];
+  x[i] += al * p[i] + om * s[i];
+  r[i] = s[i] - om * t[i];
+  if (i == 0) {   // no lane of this launch reads these
+    S[kOmega] = om;
+    S[kRhoOld] = S[kRho];
+    S[kIts] += 1.0;
+  }
+}
+
+// the perturbed stage along x with step K / ||x|| (||x|| = *yn on the device; 0 leaves the stage as is):
+// o1 = a1 + (c1 / yn) x, o2 = a2 + (c2 / yn) x
+__global__ void k_lin2_dev(int64_t n, const double *__restrict__ a1, double c1, const double *__restrict__ a2, double c2,
+                           const double *__restrict__ x, const double *__restrict__ yn, double *__restrict__ o1,
+                           double *__restrict__ o2) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  o1[i] = a1[i] + s1 * x[i];
-  o2[i] = a2[i] + s2 * x[i];
+  const double y = *yn, s = y > 0 ? 1.0 / y : 0.0;
+  o1[i] = a1[i] + (c1 * s) * x[i];
+  o2[i] = a2[i] + (c2 * s) * x[i];
+}
+
+// out = (Gp - G) / eps, eps = K / yn (0 when yn = 0)
+__global__ void k_diffq(int64_t n, const double *__restrict__ G, const double *__restrict__ Gp, double K,
+                        const double *__restrict__ yn, double *__restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double y = *yn;
+  out[i] = y > 0 ? (Gp[i] - G[i]) * (y / K) : 0.0;
 }
 
 static iga_status host_scalar(Handle &h, const double *dev, double *out, int n = 1) {
@@ -385,25 +446,20 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
   auto t0 = std::chrono::steady_clock::now();
   IGA_HIP_CHECK(hipMemcpyAsync(V1, V0, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
   double ca_norm = 0;
-  // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV); yn = ||y||
-  // when known, negative otherwise
-  auto apply = [&](const double *y, double *out, double yn) -> iga_status {
+  // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV), step
+  // sqrt(eps_machine) (1 + ||c_{n+af}||) / ||y|| with ||y|| = *yn on the device
+  double K = 0;
+  auto apply = [&](const double *y, double *out, const double *yn) -> iga_status {
     iga_status s2;
-    if (yn < 0 && ((s2 = launch_norm(h, y, h.scal)) || (s2 = host_scalar(h, h.scal, &yn)))) return s2;
-    if (yn == 0.0) return launch_fill(h, out, N, 0.0);
-    const double eps = 1.4901161193847656e-8 * (1.0 + ca_norm) / yn;
-    hipLaunchKernelGGL(k_lin2, dim3(nb), dim3(256), 0, h.stream, N, (const double *)Ca, eps * af * gm * dt,
-                       (const double *)Va, eps * am, y, tC, tV);
+    hipLaunchKernelGGL(k_lin2_dev, dim3(nb), dim3(256), 0, h.stream, N, (const double *)Ca, K * af * gm * dt,
+                       (const double *)Va, K * am, y, yn, tC, tV);
     if ((s2 = launch_cahn_hilliard(h, tC, tV, theta, lam, Gp))) return s2;
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -1.0 / eps, (const double *)G, 0.0, out);
-    hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0 / eps, (const double *)Gp, 1.0, out);
+    hipLaunchKernelGGL(k_diffq, dim3(nb), dim3(256), 0, h.stream, N, (const double *)G, (const double *)Gp, K, yn, out);
     IGA_HIP_CHECK(hipGetLastError());
     return IGA_OK;
   };
-  auto dot = [&](const double *a, const double *b, double *out) -> iga_status {
-    iga_status s2 = launch_dot(h, a, b, h.scal);
-    return s2 ? s2 : host_scalar(h, h.scal, out);
-  };
+  double *S = h.scal;
+  constexpr int kCheck = 4;   // iterations between read-backs of the residual norm
   double nr = 0, r0 = -1;
   int k;
   st = IGA_OK;
@@ -424,50 +480,34 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
     if ((st = launch_fill(h, x, N, 0.0)) || (st = launch_fill(h, p, N, 0.0)) || (st = launch_fill(h, v, N, 0.0))) break;
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -1.0, (const double *)G, 0.0, r);
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, 0.0, rh);
-    double rho_old = 1, alpha = 1, omega = 1, res = nr, rho_k = nr * nr;   // (rh, r) with rh = r = -G
-    int it;
-    for (it = 0; it < o.max_krylov && res > tol; ++it) {
-      if (rho_k == 0.0) { st = fail(IGA_ENOCONV, "BiCGStab breakdown"); break; }
-      const double beta = (rho_k / rho_old) * (alpha / omega);
-      // p = r + beta (p - omega v)
-      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -omega, (const double *)v, 1.0, p);
-      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, beta, p);
-      if ((st = apply(p, v, -1.0))) break;
-      double rhv;
-      if ((st = dot(rh, v, &rhv))) break;
-      alpha = rho_k / rhv;
-      // s = r - alpha v
-      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, 0.0, sv);
-      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -alpha, (const double *)v, 1.0, sv);
-      double sn;
-      if ((st = launch_norm(h, sv, h.scal)) || (st = host_scalar(h, h.scal, &sn))) break;
-      if (sn <= tol) {
-        if ((st = launch_axpy(h, alpha, p, x))) break;
-        res = sn;
-        ++it;
-        break;
+    K = 1.4901161193847656e-8 * (1.0 + ca_norm);
+    hipLaunchKernelGGL(k_bcg_init, dim3(1), dim3(1), 0, h.stream, S, nr);
+    if ((st = launch_dot(h, rh, r, S + kRho))) break;
+    double chk[3] = {nr, 0, 0};   // residual norm, iterations taken, rho
+    for (int launched = 0; launched < o.max_krylov;) {
+      for (int j = 0; j < kCheck && launched < o.max_krylov; ++j, ++launched) {
+        hipLaunchKernelGGL(k_bcg_p, dim3(nb), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, p,
+                           (const double *)S, tol);
+        if ((st = launch_norm(h, p, S + kYn)) || (st = apply(p, v, S + kYn)) || (st = launch_dot(h, rh, v, S + kRhv)))
+          break;
+        hipLaunchKernelGGL(k_bcg_s, dim3(nb), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, sv, S,
+                           tol);
+        if ((st = launch_norm(h, sv, S + kSn)) || (st = apply(sv, t, S + kSn)) || (st = launch_dot(h, t, sv, S + kTs)) ||
+            (st = launch_dot(h, t, t, S + kTt)))
+          break;
+        hipLaunchKernelGGL(k_bcg_xr, dim3(nb), dim3(256), 0, h.stream, N, (const double *)p, (const double *)sv,
+                           (const double *)t, x, r, S, tol);
+        if ((st = launch_norm(h, r, S + kRes)) || (st = launch_dot(h, rh, r, S + kRho))) break;
       }
-      if ((st = apply(sv, t, sn))) break;
-      double tst[2];
-      if ((st = launch_dot(h, t, sv, h.scal)) || (st = launch_dot(h, t, t, h.scal + 1)) ||
-          (st = host_scalar(h, h.scal, tst, 2)))
-        break;
-      omega = tst[0] / tst[1];
-      if ((st = launch_axpy(h, alpha, p, x)) || (st = launch_axpy(h, omega, sv, x))) break;
-      // r = s - omega t
-      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)sv, 0.0, r);
-      hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -omega, (const double *)t, 1.0, r);
-      // ||r|| and the next (rh, r) in one read-back
-      double rr2[2];
-      if ((st = launch_norm(h, r, h.scal)) || (st = launch_dot(h, rh, r, h.scal + 1)) ||
-          (st = host_scalar(h, h.scal, rr2, 2)))
-        break;
-      res = rr2[0];
-      rho_old = rho_k;
-      rho_k = rr2[1];
+      if (st) break;
+      IGA_HIP_CHECK(hipGetLastError());
+      if ((st = host_scalar(h, S + kRes, chk, 3))) break;
+      if (!std::isfinite(chk[0]) || chk[0] <= tol) break;
+      if (chk[2] == 0.0) { st = fail(IGA_ENOCONV, "BiCGStab breakdown"); break; }
     }
     if (st) break;
-    if (res > tol) { st = fail(IGA_ENOCONV, "BiCGStab did not reach its tolerance"); break; }
+    const int it = (int)chk[1];
+    if (!(chk[0] <= tol)) { st = fail(IGA_ENOCONV, "BiCGStab did not reach its tolerance"); break; }
     if ((st = launch_axpy(h, 1.0, x, V1))) break;
     if (k < 64) rr.krylov_iters[k] = it;
     rr.krylov_iters_total += it;

@@ -92,3 +92,20 @@ def test_cahn_hilliard_generalized_alpha_matches_oracle(name, dim, nel, p, rho, 
         assert rel(C1g.cpu().numpy(), C) < 1e-10, step
         assert rel(V1g.cpu().numpy(), V) < 1e-7, step
         Cg, Vg = C1g, V1g
+
+
+def test_cahn_hilliard_generalized_alpha_reports_krylov_failure():
+    """BiCGStab capped at one iteration cannot reach the first Newton step's tolerance: IGA_ENOCONV,
+    and the same handle then takes a normal step (the device-side BiCGStab state is reset per solve)."""
+    print("[case] Cahn-Hilliard generalized-alpha with max_krylov = 1", flush=True)
+    patch = inputs.unit_box(2, [8, 7], 2)
+    g = iga.IGA(patch.knots, patch.degree, periodic=[1, 1])
+    C = torch.as_tensor(0.5 + 0.05 * inputs.uniform(41, 0, g.N, -1.0, 1.0), device="cuda")
+    V = torch.zeros_like(C)
+    C1, V1 = torch.empty_like(C), torch.empty_like(C)
+    with pytest.raises(iga.IGAError) as ei:
+        g.ch_gen_alpha_step(C, V, 2e-3, 0.5, 1.5, 0.01, C1, V1, atol=1e-12, max_krylov=1)
+    assert ei.value.status == iga.IGA_ENOCONV
+    rep = g.ch_gen_alpha_step(C, V, 2e-3, 0.5, 1.5, 0.01, C1, V1, atol=1e-12)
+    assert rep["converged"] and rep["krylov_iters_total"] >= rep["newton_iters"] >= 1
+    assert np.isclose(C1.sum().item(), C.sum().item(), rtol=0, atol=1e-10)   # periodic: the mean is conserved
