@@ -56,8 +56,8 @@ __global__ void __launch_bounds__(256) k_mfield(DevProblem pb, const double *__r
   const int e1s = blockIdx.x * C1, e2 = blockIdx.y, e0 = blockIdx.z;
   const int n0 = pb.n[0], n1 = pb.n[1], ne1 = pb.ne[1], ne2 = pb.ne[2];
   const int nc = min(C1, ne1 - e1s), nk = nc + p;
-  for (int i = t; i < P * P * nk; i += 256) {
-    const int k1 = i % nk, a0 = (i / nk) % P, a2 = i / (nk * P);
+  for (int i = t; i < P * P * nk; i += 256) {   // a0 fastest: runs of P consecutive coefficients of U
+    const int a0 = i % P, k1 = (i / P) % nk, a2 = i / (nk * P);
     sU[a2][a0][k1] = U[(e0 + a0) + (int64_t)n0 * ((e1s + k1) + (int64_t)n1 * (e2 + a2))];
   }
   if (t < Q * P) {
