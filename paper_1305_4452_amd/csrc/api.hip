@@ -392,15 +392,16 @@ __global__ void k_bcg_xr(int64_t n, const double *__restrict__ p, const double *
 }
 
 // the perturbed stage along x with step K / ||x|| (||x|| = *yn on the device; 0 leaves the stage as is):
-// o1 = a1 + (c1 / yn) x, o2 = a2 + (c2 / yn) x
+// o1 = a1 + (c1 / yn) x, o2 = a2 + (c2 / yn) x; z = 0 (the residual of the stage is added into it)
 __global__ void k_lin2_dev(int64_t n, const double *__restrict__ a1, double c1, const double *__restrict__ a2, double c2,
                            const double *__restrict__ x, const double *__restrict__ yn, double *__restrict__ o1,
-                           double *__restrict__ o2) {
+                           double *__restrict__ o2, double *__restrict__ z) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double y = *yn, s = y > 0 ? 1.0 / y : 0.0;
   o1[i] = a1[i] + (c1 * s) * x[i];
   o2[i] = a2[i] + (c2 * s) * x[i];
+  z[i] = 0.0;
 }
 
 // out = (Gp - G) / eps, eps = K / yn (0 when yn = 0)
@@ -452,8 +453,8 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
   auto apply = [&](const double *y, double *out, const double *yn) -> iga_status {
     iga_status s2;
     hipLaunchKernelGGL(k_lin2_dev, dim3(nb), dim3(256), 0, h.stream, N, (const double *)Ca, K * af * gm * dt,
-                       (const double *)Va, K * am, y, yn, tC, tV);
-    if ((s2 = launch_cahn_hilliard(h, tC, tV, theta, lam, Gp))) return s2;
+                       (const double *)Va, K * am, y, yn, tC, tV, Gp);
+    if ((s2 = launch_cahn_hilliard(h, tC, tV, theta, lam, Gp, false))) return s2;
     hipLaunchKernelGGL(k_diffq, dim3(nb), dim3(256), 0, h.stream, N, (const double *)G, (const double *)Gp, K, yn, out);
     IGA_HIP_CHECK(hipGetLastError());
     return IGA_OK;

@@ -333,12 +333,13 @@ iga_status run_bih(Handle &h, const double *U, double *R) {
 
 }  // namespace
 
-iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R) {
+iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R,
+                                bool zero_out) {
   const int p = h.pb.p;
   if (h.pb.ctrl || h.pb.wts) return fail(IGA_EUNSUPPORTED, "the Cahn-Hilliard residual needs x = xi without weights");
   if (!(theta > 0.0) || !std::isfinite(theta) || !std::isfinite(lam)) return fail(IGA_EINVAL, "theta must be positive");
   if (p < 2) return fail(IGA_EUNSUPPORTED, "the Cahn-Hilliard residual needs p >= 2");
-  iga_status st = launch_fill(h, R, h.pb.N, 0.0);
+  iga_status st = zero_out ? launch_fill(h, R, h.pb.N, 0.0) : IGA_OK;
   if (st) return st;
   // simple knots: tiles with sum factorisation (IGA_OPT_TILED_3D = 0 keeps one element per workgroup,
   // for comparison)

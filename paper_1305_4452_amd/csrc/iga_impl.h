@@ -236,7 +236,9 @@ iga_status launch_pattern(Handle &h);
 iga_status launch_residual(Handle &h, const double *U, double *R);
 iga_status launch_linearize(Handle &h, const double *U);
 iga_status launch_biharmonic(Handle &h, const double *U, double *R);
-iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R);
+// zero_out = false: R is already zero (the kernels add into it)
+iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R,
+                                bool zero_out = true);
 iga_status launch_apply(Handle &h, const double *v, double *y);
 iga_status launch_diag_mf(Handle &h, double *diag);
 iga_status launch_elem_matrices(Handle &h, const double *U, const int32_t *elems, int n, int prec,
