@@ -109,3 +109,30 @@ def test_cahn_hilliard_generalized_alpha_reports_krylov_failure():
     rep = g.ch_gen_alpha_step(C, V, 2e-3, 0.5, 1.5, 0.01, C1, V1, atol=1e-12)
     assert rep["converged"] and rep["krylov_iters_total"] >= rep["newton_iters"] >= 1
     assert np.isclose(C1.sum().item(), C.sum().item(), rtol=0, atol=1e-10)   # periodic: the mean is conserved
+
+
+@pytest.mark.parametrize("dim,nel", [(3, 256), (2, 256)])
+def test_cahn_hilliard_residual_full_size_properties(dim, nel):
+    """The residual at the benchmark's sizes and launch configuration (C^1 quadratics, every axis
+    periodic, tiles), by properties that hold at any size.  Uniform knots give every function the
+    same integral 1/nel^dim.  (1) c and cdot uniform: the gradient and Laplacian terms vanish and
+    R_A = cdot / nel^dim.  (2) seeded c, cdot: the functions sum to one, so their gradients and
+    Laplacians sum to zero and sum_A R_A = sum_B cdot_B / nel^dim."""
+    print(f"[case] Cahn-Hilliard residual full size {dim}D {nel}^{dim}", flush=True)
+    patch = inputs.unit_box(dim, nel, 2)
+    g = iga.IGA(patch.knots, patch.degree, periodic=[1] * dim)
+    assert g.N == nel ** dim
+    vol = 1.0 / nel ** dim
+    R = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    C = torch.full((g.N,), 0.5, dtype=torch.float64, device="cuda")
+    Cd = torch.full((g.N,), 0.3, dtype=torch.float64, device="cuda")
+    g.cahn_hilliard_residual(C, Cd, 1.5, 1.0 / nel ** 2, R)
+    torch.cuda.synchronize()
+    assert torch.max(torch.abs(R - 0.3 * vol)).item() < 1e-9 * 0.3 * vol
+    C = torch.as_tensor(inputs.uniform(29, 0, g.N, 0.45, 0.55), device="cuda")
+    Cd = torch.as_tensor(inputs.uniform(29, 1, g.N, -1.0, 1.0), device="cuda")
+    g.cahn_hilliard_residual(C, Cd, 1.5, 1.0 / nel ** 2, R)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(R).all())
+    total, scale = R.sum().item(), R.abs().sum().item()
+    assert abs(total - Cd.sum().item() * vol) < 1e-11 * scale
