@@ -356,38 +356,80 @@ __global__ void k_bcg_init(double *S, double res) {
   S[kOmega] = 1;
 }
 
-// p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega)
-__global__ void k_bcg_p(int64_t n, const double *__restrict__ r, const double *__restrict__ v, double *__restrict__ p,
-                        const double *__restrict__ S, double tol) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n || S[kRes] <= tol) return;
-  const double beta = (S[kRho] / S[kRhoOld]) * (S[kAlpha] / S[kOmega]);
-  p[i] = r[i] + beta * (p[i] - S[kOmega] * v[i]);
+// Grid-stride update kernels that also leave one partial sum per block of the reductions the next
+// step needs (reduced by launch_reduce, in a fixed order).
+// p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega); partials of ||p||^2
+__global__ void __launch_bounds__(256) k_bcg_p(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+                                               double *__restrict__ p, const double *__restrict__ S, double tol,
+                                               double *__restrict__ part) {
+  __shared__ double sh[4];
+  const bool live = !(S[kRes] <= tol);
+  const double beta = (S[kRho] / S[kRhoOld]) * (S[kAlpha] / S[kOmega]), om = S[kOmega];
+  double acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double pi = p[i];
+    if (live) {
+      pi = r[i] + beta * (pi - om * v[i]);
+      p[i] = pi;
+    }
+    acc += pi * pi;
+  }
+  const double b = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
-// s = r - alpha v, alpha = rho / (rh, v)
-__global__ void k_bcg_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v, double *__restrict__ s,
-                        double *__restrict__ S, double tol) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n || S[kRes] <= tol) return;
+// s = r - alpha v, alpha = rho / (rh, v); partials of ||s||^2
+__global__ void __launch_bounds__(256) k_bcg_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+                                               double *__restrict__ s, double *__restrict__ S, double tol,
+                                               double *__restrict__ part) {
+  __shared__ double sh[4];
+  const bool live = !(S[kRes] <= tol);
   const double alpha = S[kRho] / S[kRhv];
-  s[i] = r[i] - alpha * v[i];
-  if (i == 0) S[kAlpha] = alpha;   // no lane of this launch reads it
+  double acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double si = s[i];
+    if (live) {
+      si = r[i] - alpha * v[i];
+      s[i] = si;
+    }
+    acc += si * si;
+  }
+  const double b = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = b;
+    if (blockIdx.x == 0 && live) S[kAlpha] = alpha;   // no lane of this launch reads it
+  }
 }
 
-// x += alpha p + omega s, r = s - omega t, omega = (t, s) / (t, t) (0 when t = 0, i.e. s = 0)
-__global__ void k_bcg_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ s,
-                         const double *__restrict__ t, double *__restrict__ x, double *__restrict__ r,
-                         double *__restrict__ S, double tol) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n || S[kRes] <= tol) return;
+// x += alpha p + omega s, r = s - omega t, omega = (t, s) / (t, t) (0 when t = 0, i.e. s = 0);
+// partials of ||r||^2 and (rh, r)
+__global__ void __launch_bounds__(256) k_bcg_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ s,
+                                                const double *__restrict__ t, const double *__restrict__ rh,
+                                                double *__restrict__ x, double *__restrict__ r, double *__restrict__ S,
+                                                double tol, double *__restrict__ part, double *__restrict__ part2) {
+  __shared__ double sh[4];
+  const bool live = !(S[kRes] <= tol);
   const double tt = S[kTt], om = tt > 0 ? S[kTs] / tt : 0.0, al = S[kAlpha];
-  x[i] += al * p[i] + om * s[i];
-  r[i] = s[i] - om * t[i];
-  if (i == 0) {   // no lane of this launch reads these
-    S[kOmega] = om;
-    S[kRhoOld] = S[kRho];
-    S[kIts] += 1.0;
+  double a1 = 0, a2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double ri = r[i];
+    if (live) {
+      x[i] += al * p[i] + om * s[i];
+      ri = s[i] - om * t[i];
+      r[i] = ri;
+    }
+    a1 += ri * ri;
+    a2 += rh[i] * ri;
+  }
+  const double b1 = block_sum(a1, sh), b2 = block_sum(a2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = b1;
+    part2[blockIdx.x] = b2;
+    if (blockIdx.x == 0 && live) {   // no lane of this launch reads these
+      S[kOmega] = om;
+      S[kRhoOld] = S[kRho];
+      S[kIts] += 1.0;
+    }
   }
 }
 
@@ -404,13 +446,26 @@ __global__ void k_lin2_dev(int64_t n, const double *__restrict__ a1, double c1, 
   z[i] = 0.0;
 }
 
-// out = (Gp - G) / eps, eps = K / yn (0 when yn = 0)
-__global__ void k_diffq(int64_t n, const double *__restrict__ G, const double *__restrict__ Gp, double K,
-                        const double *__restrict__ yn, double *__restrict__ out) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double y = *yn;
-  out[i] = y > 0 ? (Gp[i] - G[i]) * (y / K) : 0.0;
+// out = (Gp - G) / eps, eps = K / yn (0 when yn = 0); partials of (a, out) and, with part2, of (out, out)
+__global__ void __launch_bounds__(256) k_diffq(int64_t n, const double *__restrict__ G, const double *__restrict__ Gp,
+                                               double K, const double *__restrict__ yn, double *__restrict__ out,
+                                               const double *__restrict__ a, double *__restrict__ part,
+                                               double *__restrict__ part2) {
+  __shared__ double sh[4];
+  const double y = *yn, f = y > 0 ? y / K : 0.0;
+  double a1 = 0, a2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double o = y > 0 ? (Gp[i] - G[i]) * f : 0.0;
+    out[i] = o;
+    a1 += a[i] * o;
+    a2 += o * o;
+  }
+  const double b1 = block_sum(a1, sh);
+  const double b2 = part2 ? block_sum(a2, sh) : 0.0;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = b1;
+    if (part2) part2[blockIdx.x] = b2;
+  }
 }
 
 static iga_status host_scalar(Handle &h, const double *dev, double *out, int n = 1) {
@@ -450,12 +505,16 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
   // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV), step
   // sqrt(eps_machine) (1 + ||c_{n+af}||) / ||y|| with ||y|| = *yn on the device
   double K = 0;
-  auto apply = [&](const double *y, double *out, const double *yn) -> iga_status {
+  // with the partials of (a, out) in P1 and, when both is set, of (out, out) in P2
+  const int nbv = vec_blocks(N, h.npartials);
+  double *P1 = h.partials, *P2 = h.partials + h.npartials;
+  auto apply = [&](const double *y, double *out, const double *yn, const double *a, bool both) -> iga_status {
     iga_status s2;
     hipLaunchKernelGGL(k_lin2_dev, dim3(nb), dim3(256), 0, h.stream, N, (const double *)Ca, K * af * gm * dt,
                        (const double *)Va, K * am, y, yn, tC, tV, Gp);
     if ((s2 = launch_cahn_hilliard(h, tC, tV, theta, lam, Gp, false))) return s2;
-    hipLaunchKernelGGL(k_diffq, dim3(nb), dim3(256), 0, h.stream, N, (const double *)G, (const double *)Gp, K, yn, out);
+    hipLaunchKernelGGL(k_diffq, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)G, (const double *)Gp, K, yn, out,
+                       a, P1, both ? P2 : nullptr);
     IGA_HIP_CHECK(hipGetLastError());
     return IGA_OK;
   };
@@ -487,18 +546,19 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
     double chk[3] = {nr, 0, 0};   // residual norm, iterations taken, rho
     for (int launched = 0; launched < o.max_krylov;) {
       for (int j = 0; j < kCheck && launched < o.max_krylov; ++j, ++launched) {
-        hipLaunchKernelGGL(k_bcg_p, dim3(nb), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, p,
-                           (const double *)S, tol);
-        if ((st = launch_norm(h, p, S + kYn)) || (st = apply(p, v, S + kYn)) || (st = launch_dot(h, rh, v, S + kRhv)))
+        hipLaunchKernelGGL(k_bcg_p, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, p,
+                           (const double *)S, tol, P1);
+        if ((st = launch_reduce(h, P1, nbv, S + kYn, 1)) || (st = apply(p, v, S + kYn, rh, false)) ||
+            (st = launch_reduce(h, P1, nbv, S + kRhv, 0)))
           break;
-        hipLaunchKernelGGL(k_bcg_s, dim3(nb), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, sv, S,
-                           tol);
-        if ((st = launch_norm(h, sv, S + kSn)) || (st = apply(sv, t, S + kSn)) || (st = launch_dot(h, t, sv, S + kTs)) ||
-            (st = launch_dot(h, t, t, S + kTt)))
+        hipLaunchKernelGGL(k_bcg_s, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, sv, S,
+                           tol, P1);
+        if ((st = launch_reduce(h, P1, nbv, S + kSn, 1)) || (st = apply(sv, t, S + kSn, sv, true)) ||
+            (st = launch_reduce(h, P1, nbv, S + kTs, 0)) || (st = launch_reduce(h, P2, nbv, S + kTt, 0)))
           break;
-        hipLaunchKernelGGL(k_bcg_xr, dim3(nb), dim3(256), 0, h.stream, N, (const double *)p, (const double *)sv,
-                           (const double *)t, x, r, S, tol);
-        if ((st = launch_norm(h, r, S + kRes)) || (st = launch_dot(h, rh, r, S + kRho))) break;
+        hipLaunchKernelGGL(k_bcg_xr, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)p, (const double *)sv,
+                           (const double *)t, (const double *)rh, x, r, S, tol, P1, P2);
+        if ((st = launch_reduce(h, P1, nbv, S + kRes, 1)) || (st = launch_reduce(h, P2, nbv, S + kRho, 0))) break;
       }
       if (st) break;
       IGA_HIP_CHECK(hipGetLastError());

@@ -236,6 +236,30 @@ iga_status launch_pattern(Handle &h);
 iga_status launch_residual(Handle &h, const double *U, double *R);
 iga_status launch_linearize(Handle &h, const double *U);
 iga_status launch_biharmonic(Handle &h, const double *U, double *R);
+// sum over `width` lanes of a wavefront (all of them get it)
+__device__ inline double warp_sum(double v, int width) {
+  for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+  return v;
+}
+
+// block-wide sum of a 64-lane-multiple block, sh[blockDim.x / 64] in LDS; all threads get the result
+__device__ inline double block_sum(double v, double *sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = warp_sum(v, 64);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// blocks for a grid-stride vector kernel with at most maxb partial sums; *out = sum of n partials
+// (square root when do_sqrt)
+int vec_blocks(int64_t N, int maxb);
+iga_status launch_reduce(Handle &h, const double *part, int n, double *out, int do_sqrt);
+
 // zero_out = false: R is already zero (the kernels add into it)
 iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R,
                                 bool zero_out = true);

@@ -8,23 +8,6 @@ namespace iga {
 
 constexpr int kVecThreads = 256;
 
-__device__ inline double warp_sum(double v, int width) {
-  for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
-  return v;
-}
-
-// block-wide sum; all threads get the result
-__device__ inline double block_sum(double v, double *sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = warp_sum(v, 64);
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double s = 0;
-  for (int i = 0; i < nw; ++i) s += sh[i];
-  __syncthreads();
-  return s;
-}
 
 // sum of n partials, identical in every block
 __device__ inline double reduce_partials(const double *__restrict__ part, int n, double *sh) {
@@ -323,6 +306,12 @@ iga_status launch_norm(Handle &h, const double *x, double *out_dev) {
   const int nb = vec_blocks(h.pb.N, h.npartials);
   hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, h.stream, h.pb.N, x, x, h.partials);
   hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(256), 0, h.stream, (const double *)h.partials, nb, out_dev, 1);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
+iga_status launch_reduce(Handle &h, const double *part, int n, double *out, int do_sqrt) {
+  hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(256), 0, h.stream, part, n, out, do_sqrt);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
 }
