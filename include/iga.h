@@ -164,6 +164,22 @@ iga_status iga_assemble_residual(iga_t h, const double *U_dev, double *R_dev);
  * Every entry is written: no zeroing is needed. */
 iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, int prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): iga_assemble_jacobian without any allocation and without
+ * the handle's reaction-field buffer.  Same arguments, values and errors as iga_assemble_jacobian
+ * (the handle itself is created beforehand by iga_create, which allocates).  On the separable
+ * row-gather path (3D, x = xi, no weights, kappa = 1, simple knots) the per-point reaction field
+ * -lambda W e^u the kernels pass between them lives in a static device array of 64 MiB per GPU,
+ * part of the library's code object and held until the process ends: at most 64 MiB /
+ * sizeof(value) quadrature points (FP64: 8,388,608, e.g. 50^3 elements at p = 3; FP32: 16,777,216,
+ * i.e. 64^3 at p = 3); a larger mesh is refused with IGA_EINVAL and a message naming both sizes.
+ * The 2D tiled and general row-gather paths use no scratch memory and run as in
+ * iga_assemble_jacobian; the element-matrix and local-ND algorithms (IGA_OPT_JAC_ALGO) are refused
+ * with IGA_EUNSUPPORTED.  Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other handles, other host threads) race and must be serialised by the caller.
+ * No kernel-timing events are recorded.  Asynchronous on the handle's stream. */
+iga_status iga_assemble_jacobian_noalloc(iga_t h, const double *U_dev, void *vals_dev, int prec);
+
 /* Cahn-Hilliard residual (the Cahn-Hilliard example: the paper's strong form with D = 1, in the
  * primal weak form obtained by integrating by parts twice, boundary terms dropped as on periodic
  * axes): R_A = sum_e sum_q W [N_A cdot + (M mu' + lambda_ch M' Lap c) grad N_A . grad c

@@ -125,6 +125,7 @@ _SIGNATURES = {
     "iga_gen_alpha_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.POINTER(iga_newton_opts),
                             C.c_void_p, C.c_void_p, C.POINTER(iga_newton_report)], C.c_int),
     "iga_assemble_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "iga_assemble_jacobian_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "iga_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_spmv": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
     "iga_newton_solve": ([C.c_void_p, C.c_void_p, C.POINTER(iga_newton_opts), C.POINTER(iga_newton_report)],
@@ -352,6 +353,15 @@ class IGA:
         _check(load().iga_assemble_jacobian(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
                                             _dev_ptr(vals, vt, self.nnz, "vals"), int(prec)),
                "iga_assemble_jacobian")
+        return vals
+
+    def assemble_jacobian_noalloc(self, U, vals, prec=IGA_FP64):
+        """iga_assemble_jacobian_noalloc: the same values without any allocation (static scratch)."""
+        import torch
+        vt = torch.float64 if prec == IGA_FP64 else torch.float32
+        _check(load().iga_assemble_jacobian_noalloc(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
+                                                    _dev_ptr(vals, vt, self.nnz, "vals"), int(prec)),
+               "iga_assemble_jacobian_noalloc")
         return vals
 
     def apply(self, U, v, y):

@@ -727,6 +727,26 @@ iga_status iga_assemble_jacobian(iga_t hh, const double *U, void *vals, int prec
   return assemble_jacobian(h, U, vals, prec);
 }
 
+iga_status iga_assemble_jacobian_noalloc(iga_t hh, const double *U, void *vals, int prec) {
+  if (!hh || !U || !vals) return fail(IGA_EINVAL, "null argument");
+  if (prec != IGA_FP64 && prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian values are FP64 or FP32");
+  Handle &h = *(Handle *)hh;
+  const int algo = h.jac_algo;
+  if (algo == IGA_JAC_AUTO || algo == IGA_JAC_ROWGATHER) {
+    int s1 = 0, s2 = 0;
+    pick_sep_block(h, &s1, &s2);
+    if (rgsep_supported(h, s1, s2)) return launch_jac_rgsep_scratch(h, U, vals, prec, s1, s2);
+    if (rgt2_supported(h.pb) && h.row_b1 == 0) return launch_jac_rgt2(h, U, vals, prec);
+  }
+  if (algo == IGA_JAC_AUTO || algo == IGA_JAC_ROWGATHER || algo == IGA_JAC_ROWGATHER_GENERAL) {
+    int b1 = 0, b2 = 0;
+    pick_block(h, prec, &b1, &b2);
+    if (rowgather_supported(h, prec, b1, b2)) return launch_jac_rowgather(h, U, vals, prec, b1, b2);
+  }
+  return fail(IGA_EUNSUPPORTED, "the allocation-free Jacobian covers the row-gather paths only (element-matrix "
+                                "and local-ND assembly keep a per-point cache in the handle)");
+}
+
 iga_status iga_kernel_times(iga_t hh, int cap, double *ms, const char **names, int *count) {
   if (!hh) return fail(IGA_EINVAL, "null handle");
   Handle &h = *(Handle *)hh;

@@ -279,6 +279,11 @@ iga_status launch_res3(Handle &h, const double *X, double *Y, int op);
 iga_status launch_res2(Handle &h, const double *U, double *R);
 iga_status launch_jac_rgt2(Handle &h, const double *U, void *vals, int prec);
 bool rgsep_supported(const Handle &h, int b1, int b2);
+// allocation-free Jacobian: the separable path with its reaction field in a static per-device array
+#define NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+iga_status noalloc_scratch_init(int device);
+size_t rgsep_field_bytes(const Handle &h, int prec);
+iga_status launch_jac_rgsep_scratch(Handle &h, const double *U, void *vals, int prec, int b1, int b2);
 iga_status launch_spmv(Handle &h, const void *vals, int prec, const double *x, double *y,
                        double *partial_dot, int npart);
 iga_status launch_fill(Handle &h, double *x, int64_t n, double v);

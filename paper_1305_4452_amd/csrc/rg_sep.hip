@@ -24,6 +24,7 @@
 // window, the axis-0 basis values, the 1D matrix rows and the row pointer, computed from
 // per-axis prefix sums of the stencil widths) is loaded one column ahead, so no global-memory
 // round trip sits on a column's critical path.
+#include <mutex>
 #include <utility>
 
 #include "iga_impl.h"
@@ -435,34 +436,64 @@ SepPlan plan_sep3(const Handle &h) {
   return pl;
 }
 
+// mf: the reaction field (the handle's, or the static scratch of the allocation-free entry point);
+// timed: record the kernel-timing events (never for the allocation-free entry point)
 template <int P, int B1, int B2, typename CT, typename OT>
-iga_status run_sep3(Handle &h, const double *U, OT *vals) {
+iga_status run_sep3(Handle &h, const double *U, OT *vals, CT *mf, bool timed) {
   constexpr int W = 2 * P - 1;
   constexpr int NT = rs_threads(B1 * W * B2 * W);
   const int prec = sizeof(CT) == 8 ? 0 : 1;
-  CT *mf = (CT *)h.mfield;
   dim3 gm((unsigned)((h.pb.ne[1] + mf_chunk<P>() - 1) / mf_chunk<P>()), (unsigned)h.pb.ne[2], (unsigned)h.pb.ne[0]);
-  kt_begin(h, "k_mfield");
+  if (timed) kt_begin(h, "k_mfield");
   hipLaunchKernelGGL((k_mfield<P, CT>), gm, dim3(256), 0, h.stream, h.pb, U, mf);
-  kt_end(h);
+  if (timed) kt_end(h);
   IGA_HIP_CHECK(hipGetLastError());
   const SepPlan pl = plan_sep3<P, B1, B2, CT, OT>(h);
-  kt_begin(h, "k_rgsep3");
+  if (timed) kt_begin(h, "k_rgsep3");
   hipLaunchKernelGGL((k_rgsep3<P, B1, B2, CT, OT>), dim3((unsigned)pl.grid), dim3(NT), 0, h.stream, h.pb, mf,
                      (const CT *)h.sep_phi[prec][1], (const CT *)h.sep_phi[prec][2], (const CT *)h.sep_b0[prec], h.sep_cw, h.pb.sepM[0], h.pb.sepA[0], vals,
                      pl.seg_len, pl.nseg, pl.nlogical);
-  kt_end(h);
+  if (timed) kt_end(h);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
 }
 
 template <int P, int B1, int B2>
-iga_status run_sep3_prec(Handle &h, const double *U, void *vals, int prec) {
-  if (prec == IGA_FP32) return run_sep3<P, B1, B2, float, float>(h, U, (float *)vals);
-  return run_sep3<P, B1, B2, double, double>(h, U, (double *)vals);
+iga_status run_sep3_prec(Handle &h, const double *U, void *vals, int prec, void *field, bool timed) {
+  if (prec == IGA_FP32) return run_sep3<P, B1, B2, float, float>(h, U, (float *)vals, (float *)field, timed);
+  return run_sep3<P, B1, B2, double, double>(h, U, (double *)vals, (double *)field, timed);
 }
 
+// ------------------------------------------------------------------------------------------
+// Reaction-field memory for callers that cannot allocate (iga_assemble_jacobian_noalloc): one
+// 64 MiB array per GPU, part of the code object, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (in host code the name is a host-side stand-in); it uses
+// the device address looked up once per device by noalloc_scratch_init.
+// ------------------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+iga_status noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(IGA_EUNSUPPORTED, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return IGA_OK;
+  int cur = -1;
+  IGA_HIP_CHECK(hipGetDevice(&cur));
+  if (cur != device) IGA_HIP_CHECK(hipSetDevice(device));
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess || ptr == nullptr)
+    return fail(IGA_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return IGA_OK;
+}
 
 bool rgsep_supported(const Handle &h, int b1, int b2) {
   if (!h.pb.separable || !h.pb.simple_knots || h.pb.dim != 3 || !h.mfield) return false;
@@ -473,16 +504,40 @@ bool rgsep_supported(const Handle &h, int b1, int b2) {
   return (b1 == 4 && b2 == 2) || (b1 == 2 && b2 == 2) || (b1 == 4 && b2 == 4) || (b1 == 8 && b2 == 2);
 }
 
-iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, int b1, int b2) {
+static iga_status launch_jac_rgsep_field(Handle &h, const double *U, void *vals, int prec, int b1, int b2,
+                                         void *field, bool timed) {
   if (!rgsep_supported(h, b1, b2)) return fail(IGA_EUNSUPPORTED, "separable row-gather configuration");
 #define IGA_SEP(PP, X, Y) \
-  if (h.pb.P == PP && b1 == X && b2 == Y) return run_sep3_prec<PP, X, Y>(h, U, vals, prec);
+  if (h.pb.P == PP && b1 == X && b2 == Y) return run_sep3_prec<PP, X, Y>(h, U, vals, prec, field, timed);
   IGA_SEP(2, 4, 2) IGA_SEP(2, 2, 2) IGA_SEP(2, 4, 4) IGA_SEP(2, 8, 2)
   IGA_SEP(3, 4, 2) IGA_SEP(3, 2, 2) IGA_SEP(3, 4, 4) IGA_SEP(3, 8, 2)
   IGA_SEP(4, 4, 2) IGA_SEP(4, 2, 2) IGA_SEP(4, 4, 4) IGA_SEP(4, 8, 2)
   IGA_SEP(5, 2, 2) IGA_SEP(5, 2, 1)
 #undef IGA_SEP
   return fail(IGA_EUNSUPPORTED, "separable row-gather block");
+}
+
+iga_status launch_jac_rgsep(Handle &h, const double *U, void *vals, int prec, int b1, int b2) {
+  return launch_jac_rgsep_field(h, U, vals, prec, b1, b2, h.mfield, true);
+}
+
+size_t rgsep_field_bytes(const Handle &h, int prec) {
+  const size_t nqp = (size_t)h.pb.ne[0] * h.pb.Q * h.pb.ne[1] * h.pb.Q * h.pb.ne[2] * h.pb.Q;
+  return nqp * (prec == IGA_FP32 ? sizeof(float) : sizeof(double));
+}
+
+iga_status launch_jac_rgsep_scratch(Handle &h, const double *U, void *vals, int prec, int b1, int b2) {
+  void *ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (h.device >= 0 && h.device < kMaxDevices) ptr = g_scratch_ptr[h.device];
+  }
+  if (!ptr) return fail(IGA_ESTATE, "scratch address of this device was not looked up (iga_create does it)");
+  const size_t need = rgsep_field_bytes(h, prec);
+  if (need > kScratchBytes)
+    return fail(IGA_EINVAL, "reaction field of " + std::to_string(need) + " bytes exceeds the " +
+                                std::to_string(kScratchBytes) + "-byte scratch of the allocation-free entry point");
+  return launch_jac_rgsep_field(h, U, vals, prec, b1, b2, ptr, false);
 }
 
 }  // namespace iga

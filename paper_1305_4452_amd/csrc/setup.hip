@@ -374,6 +374,8 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   Handle *h = new Handle();
   h->stream = (hipStream_t)stream;
   if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(IGA_EHIP, "hipGetDevice failed"); }
+  // device address of the allocation-free Jacobian's scratch array, looked up once per device
+  if (iga_status sst = noalloc_scratch_init(h->device)) { delete h; return sst; }
   DevProblem &pb = h->pb;
   pb.dim = dim;
   pb.p = p;
