@@ -70,10 +70,13 @@ def test_cahn_hilliard_residual_rejections():
 
 @pytest.mark.parametrize("name,dim,nel,p,rho,nsteps", [("periodic2_p2", 2, [8, 7], 2, 0.5, 2),
                                                        ("periodic2_p3", 2, [8, 7], 3, 1.0, 2),
-                                                       ("periodic3_p2", 3, [5, 5, 5], 2, 0.5, 1)])
+                                                       ("periodic3_p2", 3, [5, 5, 5], 2, 0.5, 1),
+                                                       ("periodic3_p2_ragged_tiles", 3, [7, 6, 5], 2, 0.5, 1)])
 def test_cahn_hilliard_generalized_alpha_matches_oracle(name, dim, nel, p, rho, nsteps):
     """Steps of iga_ch_gen_alpha_step against the oracle's (both Newton to ||G|| < 1e-12; the GPU
-    with BiCGStab on difference Jacobian-vector products, the oracle with a dense difference Jacobian)."""
+    with BiCGStab on difference Jacobian-vector products, the oracle with a dense difference Jacobian).
+    The 7 x 6 x 5 case runs the 3D residual on tiles of 3^3 elements, ragged at the far ends of two
+    axes."""
     print(f"[case] Cahn-Hilliard generalized-alpha {name}", flush=True)
     patch = inputs.unit_box(dim, nel, p)
     per = [p - 1] * dim

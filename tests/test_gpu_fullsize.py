@@ -131,7 +131,9 @@ def test_periodic_64_p3_benchmark_workload():
     assert rel(gather_rows(host(vals), orp, rows), o.jacobian_rows(U0, rows, orp, oci)) < 1e-12
 
 
-def test_batched_512_benchmark_workload():
+@pytest.fixture(scope="module")
+def batch512():
+    """The 512 uneven 2D instances solved as one batch (the benchmark's launch configuration)."""
     print("[case] full size: 512 batched 2D instances", flush=True)
     ws = inputs.batched_instances(512)
     b = iga.IGABatch(ws)
@@ -139,8 +141,14 @@ def test_batched_512_benchmark_workload():
     # the benchmark stops at ||R|| < 1e-10; a tighter stop makes the solution error (||J^-1|| ||R||,
     # up to ~2e-9 relative on the stiffest small instances at 1e-10) small against the bar
     per, summ = b.newton_solve(U, atol=1e-12)
-    assert summ["all_converged"]
     sols = b.unpack(host(U))
+    b.close()
+    return ws, per, summ, sols
+
+
+def test_batched_512_benchmark_workload(batch512):
+    ws, per, summ, sols = batch512
+    assert summ["all_converged"]
     sizes = np.array([w.patch.ndof for w in ws])
     order = np.argsort(sizes)
     picks = list(order[:5]) + [int(order[len(order) // 4])]
@@ -149,3 +157,20 @@ def test_batched_512_benchmark_workload():
         ref, _, rc = oi.newton(ws[i].U0, atol=1e-13)
         assert rc == 0
         assert rel(sols[i], ref) < 1e-9, i
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_batched_512_largest_instance_of_each_degree(batch512, p):
+    """The largest instance of each degree in the batch (128-131 elements per side, up to 17,424
+    coefficients: several tiles of every batched kernel) against the oracle's banded-LU Newton."""
+    ws, per, summ, sols = batch512
+    degs = np.array([w.patch.degree[0] for w in ws])
+    sizes = np.array([w.patch.ndof for w in ws])
+    idx = np.where(degs == p)[0]
+    i = int(idx[np.argmax(sizes[idx])])
+    print(f"[case] batched instance {i}: p={p}, {ws[i].patch.shape} coefficients, lambda={ws[i].lam:.3f}", flush=True)
+    assert per[i]["converged"]
+    oi = oracle.Oracle.from_workload(ws[i])
+    ref, _, rc = oi.newton(ws[i].U0, atol=1e-13)
+    assert rc == 0
+    assert rel(sols[i], ref) < 1e-9, i

@@ -53,11 +53,14 @@ def test_training_reduces_loss():
 
 
 def test_learned_pipeline_small_with_fallback():
-    summary, net, std = learned.run(n_train=256, n_test=32, epochs=6, batch=64, lr=2e-3, log=None)
-    assert summary["train_instances"] > 200
+    """Trained as the default benchmark trains it (2,000 instances, 12 epochs), the guess must remove at
+    least half of the zero guess's error: mean relative L2 error < 0.5, against 1.0 for the zero guess
+    (0.25 measured at this size)."""
+    summary, net, std = learned.run(n_train=2000, n_test=100, epochs=12, log=None)
+    assert summary["train_instances"] > 1700
     for key in ("zero", "learned_raw", "learned_checked"):
         assert summary[key]["wrong"] == 0, key
-    assert summary["guess_rel_error_mean"] < 0.8                 # better than the zero guess (1.0)
+    assert summary["guess_rel_error_mean"] < 0.5
     assert summary["learned_checked"]["newton_iters_mean"] <= summary["zero"]["newton_iters_mean"]
     # a corrupted network output must fall back to the zero guess and still give the same answer
     test = learned.instances(range(20000, 20012))
