@@ -96,6 +96,24 @@ static double cdb_der2(const double *U, int nk, int i, int p, double xi) {
   return d;
 }
 
+/* Third derivative: the derivative formula applied to the second derivatives of the two degree p-1
+ * functions. */
+static double cdb_der3(const double *U, int nk, int i, int p, double xi) {
+  if (p <= 2) return 0.0;
+  double a = U[i + p] - U[i];
+  double b = U[i + p + 1] - U[i + 1];
+  double d = 0.0;
+  if (a != 0.0) d += p / a * cdb_der2(U, nk, i, p - 1, xi);
+  if (b != 0.0) d -= p / b * cdb_der2(U, nk, i + 1, p - 1, xi);
+  return d;
+}
+
+int orc_basis_1d_d3(int p, const double *U, int nk, int i, double xi, double *d3) {
+  if (p < 0 || !U || !d3 || i < 0 || i + p + 1 >= nk) return 1;
+  *d3 = cdb_der3(U, nk, i, p, xi);
+  return 0;
+}
+
 int orc_basis_1d_d2(int p, const double *U, int nk, int i, double xi, double *d2) {
   if (p < 0 || !U || !d2 || i < 0 || i + p + 1 >= nk) return 1;
   *d2 = cdb_der2(U, nk, i, p, xi);
@@ -998,6 +1016,7 @@ typedef struct {
   int nloc;
   int64_t A[ORC_MAXLOC];
   double N[ORC_MAXLOC], dN[ORC_MAXLOC][3], d2N[ORC_MAXLOC][3][3];   /* spatial */
+  double d3N[ORC_MAXLOC][3][3][3];                                  /* spatial third derivatives */
   double x[3];
   double detJ;      /* det of the map xi -> x (the parametric span factors excluded) */
   double span;      /* product of the span factors (xi_{s+1} - xi_s) / 2 */
@@ -1005,10 +1024,10 @@ typedef struct {
 
 static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], const double t[3], hpoint *h) {
   const int dim = L->dim;
-  double B[3][ORC_MAXP], dB[3][ORC_MAXP], d2B[3][ORC_MAXP];
+  double B[3][ORC_MAXP], dB[3][ORC_MAXP], d2B[3][ORC_MAXP], d3B[3][ORC_MAXP];
   h->span = 1.0;
   for (int d = 0; d < 3; ++d) {
-    if (d >= dim) { B[d][0] = 1.0; dB[d][0] = 0.0; d2B[d][0] = 0.0; continue; }
+    if (d >= dim) { B[d][0] = 1.0; dB[d][0] = 0.0; d2B[d][0] = 0.0; d3B[d][0] = 0.0; continue; }
     const double *K = L->kn[d];
     int s = L->span[d][e[d]], p = L->p[d];
     double a = K[s], b = K[s + 1];
@@ -1017,12 +1036,13 @@ static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], con
     for (int k = 0; k <= p; ++k) {
       orc_basis_1d(p, K, pb->nknots[d], s - p + k, xi, &B[d][k], &dB[d][k]);
       orc_basis_1d_d2(p, K, pb->nknots[d], s - p + k, xi, &d2B[d][k]);
+      orc_basis_1d_d3(p, K, pb->nknots[d], s - p + k, xi, &d3B[d][k]);
     }
   }
   const int P0 = L->p[0] + 1, P1 = L->p[1] + 1, P2 = L->p[2] + 1, nloc = P0 * P1 * P2;
   h->nloc = nloc;
-  static double M[ORC_MAXLOC], dM[ORC_MAXLOC][3], d2M[ORC_MAXLOC][3][3];
-  static double Np[ORC_MAXLOC], dNp[ORC_MAXLOC][3], d2Np[ORC_MAXLOC][3][3];
+  static double M[ORC_MAXLOC], dM[ORC_MAXLOC][3], d2M[ORC_MAXLOC][3][3], d3M[ORC_MAXLOC][3][3][3];
+  static double Np[ORC_MAXLOC], dNp[ORC_MAXLOC][3], d2Np[ORC_MAXLOC][3][3], d3Np[ORC_MAXLOC][3][3][3];
   for (int a2 = 0; a2 < P2; ++a2)
     for (int a1 = 0; a1 < P1; ++a1)
       for (int a0 = 0; a0 < P0; ++a0) {
@@ -1043,6 +1063,14 @@ static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], con
               w2 *= order == 0 ? B[d][ai[d]] : order == 1 ? dB[d][ai[d]] : d2B[d][ai[d]];
             }
             d2M[a][al][be] = w2;
+            for (int ga = 0; ga < 3; ++ga) {
+              double w3 = 1.0;
+              for (int d = 0; d < 3; ++d) {
+                int order = (d == al) + (d == be) + (d == ga);
+                w3 *= order == 0 ? B[d][ai[d]] : order == 1 ? dB[d][ai[d]] : order == 2 ? d2B[d][ai[d]] : d3B[d][ai[d]];
+              }
+              d3M[a][al][be][ga] = w3;
+            }
           }
         }
         M[a] = B[0][a0] * B[1][a1] * B[2][a2];
@@ -1050,13 +1078,16 @@ static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], con
   /* rational basis and its first and second parametric derivatives (eq:rational, eq:drational,
    * eq:ddrational); without weights N_A = M_A */
   if (pb->weights) {
-    double w = 0.0, dw[3] = {0, 0, 0}, d2w[3][3] = {{0}};
+    double w = 0.0, dw[3] = {0, 0, 0}, d2w[3][3] = {{0}}, d3w[3][3][3] = {{{0}}};
     for (int a = 0; a < nloc; ++a) {
       double wa = pb->weights[h->A[a]];
       w += wa * M[a];
       for (int al = 0; al < 3; ++al) {
         dw[al] += wa * dM[a][al];
-        for (int be = 0; be < 3; ++be) d2w[al][be] += wa * d2M[a][al][be];
+        for (int be = 0; be < 3; ++be) {
+          d2w[al][be] += wa * d2M[a][al][be];
+          for (int ga = 0; ga < 3; ++ga) d3w[al][be][ga] += wa * d3M[a][al][be][ga];
+        }
       }
     }
     for (int a = 0; a < nloc; ++a) {
@@ -1067,18 +1098,28 @@ static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], con
         for (int be = 0; be < 3; ++be)
           d2Np[a][al][be] = (wa * d2M[a][al][be] - Np[a] * d2w[al][be]) / w
                             - (dNp[a][be] * dw[al] + dNp[a][al] * dw[be]) / w;
+      /* eq:dddrational */
+      for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be)
+          for (int ga = 0; ga < 3; ++ga)
+            d3Np[a][al][be][ga] = (wa * d3M[a][al][be][ga] - Np[a] * d3w[al][be][ga]) / w
+                                  - (dNp[a][al] * d2w[be][ga] + dNp[a][be] * d2w[al][ga] + dNp[a][ga] * d2w[al][be]) / w
+                                  - (d2Np[a][be][ga] * dw[al] + d2Np[a][al][ga] * dw[be] + d2Np[a][al][be] * dw[ga]) / w;
     }
   } else {
     for (int a = 0; a < nloc; ++a) {
       Np[a] = M[a];
       for (int al = 0; al < 3; ++al) {
         dNp[a][al] = dM[a][al];
-        for (int be = 0; be < 3; ++be) d2Np[a][al][be] = d2M[a][al][be];
+        for (int be = 0; be < 3; ++be) {
+          d2Np[a][al][be] = d2M[a][al][be];
+          for (int ga = 0; ga < 3; ++ga) d3Np[a][al][be][ga] = d3M[a][al][be][ga];
+        }
       }
     }
   }
   /* geometry and its parametric derivatives (App. A): x_{i,alpha}, x_{i,alpha beta} */
-  double J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, H[3][3][3] = {{{0}}};
+  double J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, H[3][3][3] = {{{0}}}, T[3][3][3][3] = {{{{0}}}};
   for (int i = 0; i < 3; ++i) h->x[i] = 0.0;
   if (pb->ctrl) {
     for (int i = 0; i < dim; ++i)
@@ -1089,7 +1130,10 @@ static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], con
         h->x[i] += xa * Np[a];
         for (int al = 0; al < dim; ++al) {
           J[i][al] += xa * dNp[a][al];
-          for (int be = 0; be < dim; ++be) H[i][al][be] += xa * d2Np[a][al][be];
+          for (int be = 0; be < dim; ++be) {
+            H[i][al][be] += xa * d2Np[a][al][be];
+            for (int ga = 0; ga < dim; ++ga) T[i][al][be][ga] += xa * d3Np[a][al][be][ga];
+          }
         }
       }
   } else {
@@ -1152,6 +1196,104 @@ static int eval_hess(const orc_problem *pb, const layout *L, const int e[3], con
       }
     }
   }
+  /* eq:dddimap: xi_{alpha,ijk} = - x_{m,eps mu om} xi_{alpha,m} xi_{eps,i} xi_{mu,j} xi_{om,k}
+   *   - x_{m,eps mu} (xi_{alpha,mk} xi_{eps,i} xi_{mu,j} + xi_{alpha,m} xi_{eps,ik} xi_{mu,j}
+   *                   + xi_{alpha,m} xi_{eps,i} xi_{mu,jk}) */
+  static double X3[3][3][3][3];   /* [alpha][i][j][k] */
+  for (int al = 0; al < 3; ++al)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) {
+          double sum = 0.0;
+          if (al < dim && i < dim && j < dim && k < dim)
+            for (int m = 0; m < dim; ++m)
+              for (int ep = 0; ep < dim; ++ep)
+                for (int mu = 0; mu < dim; ++mu) {
+                  for (int om = 0; om < dim; ++om)
+                    sum += T[m][ep][mu][om] * Ji[al][m] * Ji[ep][i] * Ji[mu][j] * Ji[om][k];
+                  sum += H[m][ep][mu] * (X2[al][m][k] * Ji[ep][i] * Ji[mu][j] + Ji[al][m] * X2[ep][i][k] * Ji[mu][j] +
+                                         Ji[al][m] * Ji[ep][i] * X2[mu][j][k]);
+                }
+          X3[al][i][j][k] = -sum;
+        }
+  /* eq:dddspatial: N_{A,ijk} = N_{A,abc} xi_{a,i} xi_{b,j} xi_{c,k}
+   *   + N_{A,ab} (xi_{a,ik} xi_{b,j} + xi_{a,i} xi_{b,jk} + xi_{a,ij} xi_{b,k}) + N_{A,a} xi_{a,ijk} */
+  for (int a = 0; a < nloc; ++a)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) {
+          double v = 0.0;
+          if (i < dim && j < dim && k < dim) {
+            for (int al = 0; al < dim; ++al)
+              for (int be = 0; be < dim; ++be) {
+                for (int ga = 0; ga < dim; ++ga) v += d3Np[a][al][be][ga] * Ji[al][i] * Ji[be][j] * Ji[ga][k];
+                v += d2Np[a][al][be] * (X2[al][i][k] * Ji[be][j] + Ji[al][i] * X2[be][j][k] + X2[al][i][j] * Ji[be][k]);
+              }
+            for (int al = 0; al < dim; ++al) v += dNp[a][al] * X3[al][i][j][k];
+          }
+          h->d3N[a][i][j][k] = v;
+        }
+  return 0;
+}
+
+int orc_basis_third(const orc_problem *pb, int64_t elem, const double *t, int64_t *A, double *d3N) {
+  layout L;
+  if (!pb || !t || lay_init(pb, &L)) return 1;
+  int64_t ne = (int64_t)L.ne[0] * L.ne[1] * L.ne[2];
+  if (elem < 0 || elem >= ne) { lay_free(&L); return 1; }
+  int em[3];
+  elem_multi(&L, elem, em);
+  static hpoint h;
+  double tt[3] = {t[0], L.dim > 1 ? t[1] : 0.0, L.dim > 2 ? t[2] : 0.0};
+  int rc = eval_hess(pb, &L, em, tt, &h);
+  if (!rc)
+    for (int a = 0; a < h.nloc; ++a) {
+      if (A) A[a] = h.A[a];
+      if (d3N)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) d3N[((a * 3 + i) * 3 + j) * 3 + k] = h.d3N[a][i][j][k];
+    }
+  lay_free(&L);
+  return rc;
+}
+
+/* R_A = sum over elements and Gauss points of W grad N_A . grad(Lap u_h), with
+ * d_i Lap u_h = sum_B U_B sum_j N_{B,ijj} (eq:dddspatial), W as for the fourth-order operator below:
+ * the fourth-order operator in the form integrated by parts once (gradient of the Laplacian against
+ * the gradient of the test function). */
+int orc_grad_laplacian_residual(const orc_problem *pb, const double *U, double *R) {
+  layout L;
+  if (!pb || !U || !R || lay_init(pb, &L)) return 1;
+  int64_t N = (int64_t)L.n[0] * L.n[1] * L.n[2], ne = (int64_t)L.ne[0] * L.ne[1] * L.ne[2];
+  for (int64_t A = 0; A < N; ++A) R[A] = 0.0;
+  int nqt = L.nq[0] * L.nq[1] * L.nq[2];
+  static hpoint h;
+  for (int64_t e = 0; e < ne; ++e) {
+    int em[3];
+    elem_multi(&L, e, em);
+    for (int g = 0; g < nqt; ++g) {
+      int gm[3];
+      qp_multi(&L, g, gm);
+      double t[3], wq = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        t[d] = d < L.dim ? L.gx[d][gm[d]] : 0.0;
+        if (d < L.dim) wq *= L.gw[d][gm[d]];
+      }
+      int rc = eval_hess(pb, &L, em, t, &h);
+      if (rc) { lay_free(&L); return rc; }
+      double W = wq * h.span * h.detJ, glu[3] = {0, 0, 0};
+      for (int a = 0; a < h.nloc; ++a)
+        for (int i = 0; i < L.dim; ++i)
+          for (int j = 0; j < L.dim; ++j) glu[i] += U[h.A[a]] * h.d3N[a][i][j][j];
+      for (int a = 0; a < h.nloc; ++a) {
+        double s = 0.0;
+        for (int i = 0; i < L.dim; ++i) s += h.dN[a][i] * glu[i];
+        R[h.A[a]] += W * s;
+      }
+    }
+  }
+  lay_free(&L);
   return 0;
 }
 

@@ -86,6 +86,14 @@ int orc_mass_matrix(const orc_problem *pb, const int64_t *row_ptr, const int32_t
  * eq:ddspatial), and the point x [3].  Any output may be NULL. */
 int orc_basis_hessian(const orc_problem *pb, int64_t elem, const double *t, int64_t *A, double *N,
                       double *dN, double *d2N, double *x);
+/* Third derivative of B_{i,p} at xi (the derivative formula of Sec. 2.1 applied three times). */
+int orc_basis_1d_d3(int p, const double *U, int nk, int i, double xi, double *d3);
+/* Spatial third derivatives d3N [nloc][3][3][3] of the local functions of element elem at local
+ * coordinates t (eq:dddrational, eq:dddimap, eq:dddspatial) and their global indices A. */
+int orc_basis_third(const orc_problem *pb, int64_t elem, const double *t, int64_t *A, double *d3N);
+/* R_A = sum_e sum_q W grad N_A . grad(Lap u_h) over every function (no boundary rows): the
+ * fourth-order operator integrated by parts once, from third spatial derivatives. */
+int orc_grad_laplacian_residual(const orc_problem *pb, const double *U, double *R);
 /* R_A = sum_e sum_q W (Lap N_A)(Lap u_h) over every function (no boundary rows). */
 int orc_biharmonic_residual(const orc_problem *pb, const double *U, double *R);
 /* Cahn-Hilliard residual of the paper's strong form (D = 1) in primal weak form: R_A = sum W [N_A cdot
