@@ -17,13 +17,25 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(opt: str = "-O2") -> str:
+def build(opt: str = "-O2", out: str | None = None) -> str:
+    """Compile oracle.c into `out` (default: liboracle.so next to this file).  `opt` is one string
+    of gcc flags, e.g. "-O3 -march=native" for a timing copy built on the host that runs it."""
     src = os.path.join(_HERE, "oracle.c")
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", opt, "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"]
+    out = out or os.path.join(_HERE, "liboracle.so")
+    tmp = out + ".tmp"
+    cmd = ["gcc", *opt.split(), "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, out)
+    return out
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (e.g. a -O3 -march=native copy for
+    timing); every Oracle call made afterwards goes through it."""
+    global _lib, _LIB_PATH
+    _LIB_PATH = path
+    _lib = None
+    lib()
 
 
 class Problem(C.Structure):
@@ -78,6 +90,9 @@ def lib():
             "orc_mass_matrix": [P, _i64p, _i32p, _dp],
             "orc_basis_1d_d2": [C.c_int, _dp, C.c_int, C.c_int, C.c_double, _dp],
             "orc_basis_hessian": [P, C.c_int64, _dp, _i64p, _dp, _dp, _dp, _dp],
+            "orc_basis_1d_d3": [C.c_int, _dp, C.c_int, C.c_int, C.c_double, _dp],
+            "orc_basis_third": [P, C.c_int64, _dp, _i64p, _dp],
+            "orc_grad_laplacian_residual": [P, _dp, _dp],
             "orc_biharmonic_residual": [P, _dp, _dp],
             "orc_gen_alpha_params": [C.c_double, _dp, _dp, _dp],
             "orc_cahn_hilliard_residual": [P, _dp, _dp, C.c_double, C.c_double, _dp],
@@ -189,6 +204,26 @@ class Oracle:
         self._chk(lib().orc_basis_hessian(C.byref(self.pb), int(elem), _ptr(tt), _ptr(A, _i64p), _ptr(N), _ptr(dN),
                                           _ptr(d2N), _ptr(x)), "basis_hessian")
         return A, N, dN.reshape(nloc, 3), d2N.reshape(nloc, 3, 3), x
+
+    def basis_third(self, elem, t):
+        """Spatial third derivatives [nloc, 3, 3, 3] of the local functions of element `elem` at local
+        coordinates t (eq:dddrational, eq:dddimap, eq:dddspatial), with their global indices."""
+        nloc = int(np.prod([self.pb.degree[d] + 1 for d in range(self.dim)]))
+        tt = np.zeros(3)
+        tv = np.atleast_1d(np.asarray(t, dtype=np.float64))
+        tt[:len(tv)] = tv
+        A = np.zeros(nloc, dtype=np.int64)
+        d3N = np.zeros(nloc * 27)
+        self._chk(lib().orc_basis_third(C.byref(self.pb), int(elem), _ptr(tt), _ptr(A, _i64p), _ptr(d3N)),
+                  "basis_third")
+        return A, d3N.reshape(nloc, 3, 3, 3)
+
+    def grad_laplacian_residual(self, U):
+        """R_A = sum_e sum_q W grad N_A . grad(Lap u_h) for every function (no boundary rows)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        R = np.zeros(self.N)
+        self._chk(lib().orc_grad_laplacian_residual(C.byref(self.pb), _ptr(U), _ptr(R)), "grad_laplacian_residual")
+        return R
 
     def biharmonic_residual(self, U):
         """R_A = sum_e sum_q W (Lap N_A)(Lap u_h) for every function (no boundary rows)."""
@@ -358,6 +393,14 @@ def basis_1d(p, U, i, xi):
     if lib().orc_basis_1d(p, _ptr(U), len(U), i, float(xi), C.byref(v), C.byref(d)):
         raise ValueError("bad basis index")
     return v.value, d.value
+
+
+def basis_1d_d3(p, U, i, xi):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    d = C.c_double()
+    if lib().orc_basis_1d_d3(p, _ptr(U), len(U), i, float(xi), C.byref(d)):
+        raise ValueError("bad basis index")
+    return d.value
 
 
 def stencil(p, U, i):
