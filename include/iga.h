@@ -42,7 +42,14 @@ typedef enum {
   IGA_ESTATE = 6         /* call not valid in the handle's current state */
 } iga_status;
 
-typedef enum { IGA_FP64 = 0, IGA_FP32 = 1, IGA_BF16 = 2 } iga_prec;
+/* Precision of the element contractions of a Jacobian (eq:jacobian).  FP64 and FP32 contract in that
+ * precision and write values of that type.  BF16 and BF16X3 run the axis-2 contraction of the
+ * row-gather on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation) and write FP32
+ * values: BF16 rounds both operands to BF16 (relative error of the values ~1e-3), BF16X3 splits each
+ * FP32 operand x into hi = bf16(x) and lo = bf16(x - hi) and sums lo*hi + hi*lo + hi*hi (~1e-5).
+ * The geometry, u and e^u stay FP64 and the other contraction levels FP32.  Newton with a BF16 or
+ * BF16X3 Jacobian keeps the FP64 residual, so it converges to the FP64 solution (a refinement). */
+typedef enum { IGA_FP64 = 0, IGA_FP32 = 1, IGA_BF16 = 2, IGA_BF16X3 = 3 } iga_prec;
 
 typedef enum { IGA_KAPPA_ONE = 0, IGA_KAPPA_NODAL = 1, IGA_KAPPA_ELEMENT = 2 } iga_kappa_mode;
 
@@ -123,7 +130,7 @@ typedef struct {
   int max_newton;                /* Newton steps (<= 64) */
   int max_krylov;                /* CG iterations per Newton step */
   int matrix_free;               /* 0: assembled CSR Jacobian; 1: iga_apply inside CG */
-  int jac_prec;                  /* iga_prec of the Jacobian values (assembled mode) */
+  int jac_prec;                  /* iga_prec of the Jacobian contraction (assembled mode) */
   double forcing_max;            /* cap of the CG relative tolerance (Eisenstat-Walker); 0: 1e-2 */
   int check_every;               /* CG iterations between convergence checks; 0: automatic (4 with the
                                     fast-diagonalisation preconditioner, 16 with Jacobi) */
@@ -159,9 +166,11 @@ iga_status iga_csr_pattern(iga_t h, int64_t *row_ptr_dev, int32_t *col_idx_dev);
 iga_status iga_assemble_residual(iga_t h, const double *U_dev, double *R_dev);
 
 /* vals = J(U) (eq:jacobian) on the iga_csr_pattern pattern; prec IGA_FP64 writes double,
- * IGA_FP32 writes float (FP32 element contractions with FP32 accumulation).  Dirichlet rows
- * are identity rows and Dirichlet columns of the other rows are zero (symmetric elimination).
- * Every entry is written: no zeroing is needed. */
+ * IGA_FP32 writes float (FP32 element contractions with FP32 accumulation), IGA_BF16 and
+ * IGA_BF16X3 write float from the BF16 matrix-core row-gather (iga_prec; 3D, open axes, simple
+ * interior knots, degree 2..4, IGA_EUNSUPPORTED otherwise).  Dirichlet rows are identity rows and
+ * Dirichlet columns of the other rows are zero (symmetric elimination).  Every entry is written: no
+ * zeroing is needed. */
 iga_status iga_assemble_jacobian(iga_t h, const double *U_dev, void *vals_dev, int prec);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
@@ -232,16 +241,28 @@ iga_status iga_gen_alpha_step(iga_t h, const double *U0_dev, const double *V0_de
  * (IGA_EUNSUPPORTED otherwise).  Asynchronous on the handle's stream. */
 iga_status iga_biharmonic_residual(iga_t h, const double *U_dev, double *R_dev);
 
+/* The fourth-order operator integrated by parts once, from third spatial derivatives:
+ * R_A = sum_e sum_q W grad N_A . grad(Lap u_h), d_i Lap u_h = sum_B U_B sum_j N_{B,ijj}, for every
+ * function A (no Dirichlet rows), with the rational third derivatives of eq:dddrational, the
+ * inverse-map derivatives of eq:ddimap (the sign of reading eq:identity) and eq:dddimap, and the
+ * spatial third derivatives of eq:dddspatial (App. A).  On periodic axes with C^(p-1) continuity,
+ * p >= 3, it equals minus iga_biharmonic_residual.  U_dev, R_dev: N doubles on the device; R is
+ * overwritten.  Needs p >= 2; p <= 6 in 2D, p <= 3 in 3D (IGA_EUNSUPPORTED otherwise).  Asynchronous
+ * on the handle's stream. */
+iga_status iga_grad_laplacian_residual(iga_t h, const double *U_dev, double *R_dev);
+
 /* y = J(U) v without forming J (exact linearisation, same Dirichlet convention). */
 iga_status iga_apply(iga_t h, const double *U_dev, const double *v_dev, double *y_dev);
 
 /* y = A x for CSR values on the handle's pattern (prec IGA_FP64: double vals, IGA_FP32: float). */
 iga_status iga_spmv(iga_t h, const void *vals_dev, int prec, const double *x_dev, double *y_dev);
 
-/* Newton's method on R(U) = 0 starting from U (updated in place): each step assembles R and
- * J (or uses iga_apply) and solves J d = -R by Jacobi-preconditioned CG with an
- * Eisenstat-Walker forcing term; the residual is always FP64, so an FP32 Jacobian gives an
- * FP64-accurate fixed point.  Returns IGA_ENOCONV when the test is not met or on NaN/Inf.
+/* Newton's method on R(U) = 0 (Sec. 3: the residual eq:residual and Jacobian eq:jacobian of the
+ * Bratu problem, solved by Newton as in the tutorial run of App. B) starting from U (updated in
+ * place): each step assembles R and J (or uses iga_apply) and solves J d = -R by CG with an
+ * Eisenstat-Walker forcing term, preconditioned as IGA_OPT_PRECOND selects (fast diagonalisation
+ * or Jacobi).  The residual is always FP64, so an FP32, BF16 or BF16X3 Jacobian (opts->jac_prec)
+ * gives an FP64-accurate fixed point.  Returns IGA_ENOCONV when the test is not met or on NaN/Inf.
  * opts may be NULL (defaults); report may be NULL.  Synchronous. */
 iga_status iga_newton_solve(iga_t h, double *U_dev, const iga_newton_opts *opts, iga_newton_report *report);
 

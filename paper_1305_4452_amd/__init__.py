@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libiga.so")
 
 IGA_OK, IGA_EINVAL, IGA_ENOMEM, IGA_EHIP, IGA_ENOCONV, IGA_EUNSUPPORTED, IGA_ESTATE = range(7)
-IGA_FP64, IGA_FP32, IGA_BF16 = 0, 1, 2
+IGA_FP64, IGA_FP32, IGA_BF16, IGA_BF16X3 = 0, 1, 2, 3
 IGA_KAPPA_ONE, IGA_KAPPA_NODAL, IGA_KAPPA_ELEMENT = 0, 1, 2
 IGA_JAC_AUTO, IGA_JAC_ROWGATHER, IGA_JAC_ATOMIC, IGA_JAC_COLOR, IGA_JAC_ROWGATHER_GENERAL, IGA_JAC_LOCAL_ND = 0, 1, 2, 3, 4, 5
 IGA_OPT_JAC_ALGO, IGA_OPT_ROW_BLOCK, IGA_OPT_LAMBDA_BITS, IGA_OPT_ROW_SEGMENTS, IGA_OPT_KERNEL_TIMING = 1, 2, 3, 4, 5
@@ -125,6 +125,7 @@ _SIGNATURES = {
     "iga_gen_alpha_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.POINTER(iga_newton_opts),
                             C.c_void_p, C.c_void_p, C.POINTER(iga_newton_report)], C.c_int),
     "iga_assemble_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "iga_grad_laplacian_residual": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_assemble_jacobian_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "iga_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "iga_spmv": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p], C.c_int),
@@ -338,6 +339,14 @@ class IGA:
         _check(load().iga_cahn_hilliard_residual(self.h, _dev_ptr(Cv, torch.float64, self.N, "C"),
                                                  _dev_ptr(Cd, torch.float64, self.N, "Cdot"), float(theta), float(lam),
                                                  _dev_ptr(R, torch.float64, self.N, "R")), "iga_cahn_hilliard_residual")
+        return R
+
+    def grad_laplacian_residual(self, U, R):
+        """R_A = sum W grad N_A . grad(Lap u_h) over every function (iga_grad_laplacian_residual)."""
+        import torch
+        _check(load().iga_grad_laplacian_residual(self.h, _dev_ptr(U, torch.float64, self.N, "U"),
+                                                  _dev_ptr(R, torch.float64, self.N, "R")),
+               "iga_grad_laplacian_residual")
         return R
 
     def biharmonic_residual(self, U, R):

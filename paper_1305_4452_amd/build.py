@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libiga.so")
-SOURCES = ["setup.hip", "elem.hip", "rowgather.hip", "rg_sep.hip", "rg_tile2.hip", "krylov.hip", "precond.hip", "batch.hip", "nn.hip", "hess.hip", "api.hip"]
+SOURCES = ["setup.hip", "elem.hip", "rowgather.hip", "rg_sep.hip", "rg_tile2.hip", "rg_mfma.hip", "krylov.hip", "precond.hip", "batch.hip", "nn.hip", "hess.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

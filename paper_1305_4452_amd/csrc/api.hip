@@ -52,7 +52,11 @@ static void pick_sep_block(const Handle &h, int *b1, int *b2) {
   *b2 = 2;
 }
 
+// storage precision of the Jacobian values for a contraction precision (BF16 contractions write FP32)
+static int value_prec(int prec) { return prec == IGA_FP64 ? IGA_FP64 : IGA_FP32; }
+
 static iga_status assemble_jacobian(Handle &h, const double *U, void *vals, int prec) {
+  if (prec == IGA_BF16 || prec == IGA_BF16X3) return launch_jac_mma(h, U, (float *)vals, prec == IGA_BF16X3);
   int algo = h.jac_algo;
   int b1 = 0, b2 = 0;
   if (algo == IGA_JAC_AUTO || algo == IGA_JAC_ROWGATHER) {
@@ -91,7 +95,7 @@ static iga_status ensure_newton_ws(Handle &h, bool need_vals, int prec) {
   if (!h.scal && (st = alloc_owned(h, (void **)&h.scal, 1100 * sizeof(double)))) return st;
   if (h.fdm.ok && !h.fdm_w && (st = alloc_owned(h, (void **)&h.fdm_w, 2 * N * sizeof(double)))) return st;
   if (need_vals && (h.jvals == nullptr || h.jvals_prec != prec)) {
-    size_t bytes = (size_t)h.pb.nnz * (prec == IGA_FP32 ? 4 : 8);
+    size_t bytes = (size_t)h.pb.nnz * (prec == IGA_FP64 ? 8 : 4);
     if (h.jvals) {
       for (auto &q : h.owned)
         if (q == h.jvals) q = nullptr;
@@ -123,7 +127,11 @@ static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_
   if (o_in) o = *o_in;
   if (o.max_newton < 0 || o.max_newton > 64) return fail(IGA_EINVAL, "max_newton must be in 0..64");
   if (o.max_krylov < 1) return fail(IGA_EINVAL, "max_krylov must be positive");
-  if (o.jac_prec != IGA_FP64 && o.jac_prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian precision");
+  if (o.jac_prec != IGA_FP64 && o.jac_prec != IGA_FP32 && o.jac_prec != IGA_BF16 && o.jac_prec != IGA_BF16X3)
+    return fail(IGA_EUNSUPPORTED, "Jacobian precision");
+  if ((o.jac_prec == IGA_BF16 || o.jac_prec == IGA_BF16X3) && !o.matrix_free && !mma_supported(h.pb))
+    return fail(IGA_EUNSUPPORTED, "BF16 Jacobians need the matrix-core row-gather (3D, open axes, simple knots, p 2..4)");
+  const int vprec = value_prec(o.jac_prec);
   if (o.forcing_max <= 0) o.forcing_max = 1e-2;
   if (h.precond != IGA_PRECOND_JACOBI) {
     iga_status sf = ensure_fdm(h);
@@ -135,7 +143,7 @@ static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_
   if (o.check_every <= 0) o.check_every = fdm ? 4 : 16;
   if (o.check_every > 1024) o.check_every = 1024;
   iga_newton_report r{};
-  iga_status st = ensure_newton_ws(h, !o.matrix_free, o.jac_prec);
+  iga_status st = ensure_newton_ws(h, !o.matrix_free, vprec);
   if (st) return st;
   const int64_t N = h.pb.N;
   double *R = h.nw, *dvec = h.nw + N;
@@ -176,13 +184,13 @@ static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_
       if (!fdm && (st = launch_diag_mf(h, h.dinv))) break;
     } else {
       if ((st = assemble_jacobian(h, U, h.jvals, o.jac_prec))) break;
-      if (!fdm && (st = launch_diag_inv(h, h.jvals, o.jac_prec, h.dinv))) break;
+      if (!fdm && (st = launch_diag_inv(h, h.jvals, vprec, h.dinv))) break;
     }
     if (fdm && (st = launch_fdm_shift(h, U))) break;
     hipEventRecord(ev[1], h.stream);
     int its = 0;
     double rel = 0;
-    if ((st = cg_solve(h, R, dvec, eta, o.max_krylov, o.check_every, h.jvals, o.jac_prec, o.matrix_free != 0, fdm,
+    if ((st = cg_solve(h, R, dvec, eta, o.max_krylov, o.check_every, h.jvals, vprec, o.matrix_free != 0, fdm,
                        &its, &rel)))
       break;
     hipEventRecord(ev[2], h.stream);
@@ -714,6 +722,11 @@ iga_status iga_cahn_hilliard_residual(iga_t hh, const double *C, const double *C
   return launch_cahn_hilliard(*(Handle *)hh, C, Cdot, theta, lambda_ch, R);
 }
 
+iga_status iga_grad_laplacian_residual(iga_t hh, const double *U, double *R) {
+  if (!hh || !U || !R) return fail(IGA_EINVAL, "null argument");
+  return launch_grad_laplacian(*(Handle *)hh, U, R);
+}
+
 iga_status iga_biharmonic_residual(iga_t hh, const double *U, double *R) {
   if (!hh || !U || !R) return fail(IGA_EINVAL, "null argument");
   return launch_biharmonic(*(Handle *)hh, U, R);
@@ -721,7 +734,8 @@ iga_status iga_biharmonic_residual(iga_t hh, const double *U, double *R) {
 
 iga_status iga_assemble_jacobian(iga_t hh, const double *U, void *vals, int prec) {
   if (!hh || !U || !vals) return fail(IGA_EINVAL, "null argument");
-  if (prec != IGA_FP64 && prec != IGA_FP32) return fail(IGA_EUNSUPPORTED, "Jacobian values are FP64 or FP32");
+  if (prec != IGA_FP64 && prec != IGA_FP32 && prec != IGA_BF16 && prec != IGA_BF16X3)
+    return fail(IGA_EUNSUPPORTED, "unknown Jacobian precision");
   Handle &h = *(Handle *)hh;
   kt_reset(h);
   return assemble_jacobian(h, U, vals, prec);

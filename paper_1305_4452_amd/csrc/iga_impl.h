@@ -31,6 +31,7 @@ struct AxisDev {
   int nper;            // periodic axis: its number of functions (indices wrap); 0 on an open axis
   const int *nbr;      // periodic axis: [n][2p+1] sorted functions sharing an element with each one
   const double *d2B;   // [ne][Q][P]   d2/dxi2 (the fourth-order operator)
+  const double *d3B;   // [ne][Q][P]   d3/dxi3 (the fourth-order operator integrated by parts once)
 };
 
 // eq:map-wrap for the local-to-global index of an element function (i < 2 nper here)
@@ -158,6 +159,9 @@ struct Handle {
   int row_segments = 0;           // separable row-gather: segments along axis 0 (0 = planned)
   // separable row-gather tables (3D, identity geometry, kappa = 1, simple knots)
   void *mfield = nullptr;         // [ne0 Q][ne2 Q][ne1 Q] reaction coefficient, FP64 or FP32
+  // BF16 matrix-core Jacobian (lazily): FP32 coefficient streams [ne0 Q][stream][ne1 Q][ne2 Q + pad]
+  float *mma_cs = nullptr;
+  size_t mma_cs_bytes = 0;
   const void *sep_phi[2][3] = {}; // [FP64, FP32][axis] band products [n][2p+1][(p+1)^2]
   const void *sep_b0[2] = {};     // [FP64, FP32] axis-0 basis table [ne0][Q][P]
   const int64_t *sep_cw = nullptr; // prefix sums of the stencil widths, [n0+1 | n1+1 | n2+1]
@@ -236,6 +240,7 @@ iga_status launch_pattern(Handle &h);
 iga_status launch_residual(Handle &h, const double *U, double *R);
 iga_status launch_linearize(Handle &h, const double *U);
 iga_status launch_biharmonic(Handle &h, const double *U, double *R);
+iga_status launch_grad_laplacian(Handle &h, const double *U, double *R);
 // sum over `width` lanes of a wavefront (all of them get it)
 __device__ inline double warp_sum(double v, int width) {
   for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
@@ -279,6 +284,9 @@ iga_status launch_res3(Handle &h, const double *X, double *Y, int op);
 iga_status launch_res2(Handle &h, const double *U, double *R);
 iga_status launch_jac_rgt2(Handle &h, const double *U, void *vals, int prec);
 bool rgsep_supported(const Handle &h, int b1, int b2);
+// BF16 matrix-core row-gather Jacobian (FP32 values; split: three BF16 products per operand pair)
+bool mma_supported(const DevProblem &pb);
+iga_status launch_jac_mma(Handle &h, const double *U, float *vals, bool split);
 // allocation-free Jacobian: the separable path with its reaction field in a static per-device array
 #define NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 iga_status noalloc_scratch_init(int device);

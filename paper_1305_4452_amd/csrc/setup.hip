@@ -93,6 +93,22 @@ static void basis_second_derivative(const double *U, int s, int p, double xi, do
   }
 }
 
+// third derivatives of the p+1 functions of span s: the derivative formula of Sec. 2.1 applied to the
+// second derivatives of the degree p-1 functions
+static void basis_third_derivative(const double *U, int s, int p, double xi, double *d3N) {
+  double low[kMaxP + 1] = {0};
+  if (p >= 3) basis_second_derivative(U, s, p - 1, xi, low);
+  for (int j = 0; j <= p; ++j) {
+    int m = s - p + j;
+    double d = 0.0;
+    if (p >= 3) {
+      if (j >= 1) d += low[j - 1] / (U[m + p] - U[m]);
+      if (j <= p - 1) d -= low[j] / (U[m + p + 1] - U[m + 1]);
+    }
+    d3N[j] = p * d;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Device kernels used once at creation
 // ------------------------------------------------------------------------------------------
@@ -409,7 +425,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     const double *U = h->hknots[a].data();
     int n = nk - p - 1;
     std::vector<int> efirst;
-    std::vector<double> B, dB, d2B, wq;
+    std::vector<double> B, dB, d2B, d3B, wq;
     for (int s = p; s < n; ++s) {
       if (!(U[s] < U[s + 1])) continue;
       int e = (int)efirst.size();
@@ -419,10 +435,16 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       for (int q = 0; q < pb.Q; ++q) {
         double xi = 0.5 * (lo + hi) + 0.5 * (hi - lo) * gx[q];
         double N[kMaxP], dN[kMaxP];
-        double d2N[kMaxP];
+        double d2N[kMaxP], d3N[kMaxP];
         basis_and_derivative(U, s, p, xi, N, dN);
         basis_second_derivative(U, s, p, xi, d2N);
-        for (int j = 0; j <= p; ++j) { B.push_back(N[j]); dB.push_back(dN[j]); d2B.push_back(d2N[j]); }
+        basis_third_derivative(U, s, p, xi, d3N);
+        for (int j = 0; j <= p; ++j) {
+          B.push_back(N[j]);
+          dB.push_back(dN[j]);
+          d2B.push_back(d2N[j]);
+          d3B.push_back(d3N[j]);
+        }
         wq.push_back(gw[q] * 0.5 * (hi - lo));
       }
     }
@@ -499,12 +521,12 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       iga_destroy((iga_t)h);
       return st;
     }
-    double *d_d2B;
-    if ((st = dev_upload(*h, &d_d2B, d2B.data(), d2B.size()))) {
+    double *d_d2B, *d_d3B;
+    if ((st = dev_upload(*h, &d_d2B, d2B.data(), d2B.size())) || (st = dev_upload(*h, &d_d3B, d3B.data(), d3B.size()))) {
       iga_destroy((iga_t)h);
       return st;
     }
-    pb.ax[a] = AxisDev{d_B, d_dB, d_wq, d_ef, d_stl, d_stw, 0, nullptr, d_d2B};
+    pb.ax[a] = AxisDev{d_B, d_dB, d_wq, d_ef, d_stl, d_stw, 0, nullptr, d_d2B, d_d3B};
     if (kper >= 0) {
       int *d_nbr;
       if ((st = dev_upload(*h, &d_nbr, nbr[a].data(), nbr[a].size()))) {
