@@ -168,6 +168,11 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
   __shared__ __attribute__((aligned(16))) __bf16 z1[NL][4][NN][kLD];    // level-2 A operand [f1][m][g1]
   __shared__ __attribute__((aligned(16))) __bf16 t1[NL][NK][NN][kLD];   // level-2 B operand [k][n][g1]
   __shared__ float T2[4][NN][NN + 1];                     // level-2 results [c0][m][n]
+  __shared__ __attribute__((aligned(16))) __bf16 csw[NL][NS][G][kLD];  // level-1 A operand [s][g1][g2], one step
+  __shared__ float rowbuf[kMB * kMB][W * W * W];          // completed rows in CSR order
+  __shared__ int64_t rowBase[kMB * kMB];
+  __shared__ int rowLen[kMB * kMB];
+  constexpr int NPF = (NS * G * 32 + NT - 1) / NT;        // window values each thread stages per step
 
   const MCombo *combos = TABLE ? kCombosTable : kCombosDiag;
   const MGroup *groups = TABLE ? kGroupsTable : kGroupsDiag;
@@ -228,33 +233,60 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
 #pragma unroll
     for (int k = 0; k < W; ++k) acc[a][k] = 0.f;
 
+  // The coefficient window of a step (e0, q0): cs rows E1lo Q + [0, G) (rows past the window's end
+  // repeat its last row), columns E2lo Q + [0, 32) (the padding columns meet zero rows of Z2).  Each
+  // thread loads its NPF values of the next step at the start of a step and stores them, rounded to
+  // BF16 (hi, lo), once level 1 has read the current window.
+  float nxt[NPF];
+  // 32-bit offsets inside one step's plane (NS x ne1 Q x ld floats; checked on the host)
+  const int ldi = (int)ld, rowoff = E1lo * Q, coloff = E2lo * Q;
+  auto load_step = [&](int step) {
+    const float *plane = cs + (int64_t)step * NS * G1tot * ld;
+#pragma unroll
+    for (int r = 0; r < NPF; ++r) {
+      const int i = t + r * NT;
+      const int col = i % 32, row = (i / 32) % G, s = i / (32 * G);
+      const int off = (s * (int)G1tot + rowoff + min(row, G1 - 1)) * ldi + coloff + col;
+      nxt[r] = (s < NS) ? plane[off] : 0.f;
+    }
+  };
+  auto store_step = [&]() {
+#pragma unroll
+    for (int r = 0; r < NPF; ++r) {
+      const int i = t + r * NT;
+      const int col = i % 32, row = (i / 32) % G, s = i / (32 * G);
+      if (s < NS) {
+        const __bf16 h = to_bf16(nxt[r]);
+        csw[0][s][row][col] = h;
+        if constexpr (SPLIT) csw[1][s][row][col] = to_bf16(nxt[r] - (float)h);
+      }
+    }
+  };
+  load_step(0);
+  store_step();
+  const int nsteps = pb.ne[0] * Q;
+
   for (int e0 = 0; e0 < pb.ne[0]; ++e0) {
-    __syncthreads();
     for (int i = t; i < Q * P; i += NT) {
       const size_t o = (size_t)e0 * Q * P + i;
       (&fX0[0][0][0])[i] = (float)pb.ax[0].B[o];
       (&fX0[1][0][0])[i] = (float)pb.ax[0].dB[o];
     }
+    __syncthreads();
     for (int q0 = 0; q0 < Q; ++q0) {
+      const int step = e0 * Q + q0;
       // ---- level 1: jobs (group, 16-row tile of g1) ----
-      const float *plane = cs + (int64_t)(e0 * Q + q0) * NS * G1tot * ld;
       for (int job = wave; job < NG * S::MT; job += NWAVE) {
         const MGroup &Gr = groups[job / S::MT];
         const int tm = job % S::MT;
-        const int64_t grow = (int64_t)E1lo * Q + min(tm * 16 + lr, G1 - 1);     // rows past the window: any valid row
-        const int64_t gcol = (int64_t)E2lo * Q + kk;
+        const int row = min(tm * 16 + lr, G - 1);            // rows past the window: any staged row
         // A operands of the group's streams (register arrays indexed at compile time only)
         bf16x8 ah[3], al[3];
 #pragma unroll
         for (int si = 0; si < 3; ++si) {
           if (si >= Gr.ns) break;
-          const float *src = plane + ((int64_t)Gr.s[si] * G1tot + grow) * ld + gcol;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float x = src[j];
-            ah[si][j] = to_bf16(x);
-            if constexpr (SPLIT) al[si][j] = to_bf16(x - (float)ah[si][j]);
-          }
+          ah[si] = *(const bf16x8 *)&csw[0][Gr.s[si]][row][kk];
+          if constexpr (SPLIT) al[si] = *(const bf16x8 *)&csw[NL - 1][Gr.s[si]][row][kk];
         }
         f32x4 d0[T16], d1[T16];
 #pragma unroll
@@ -301,6 +333,7 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
           }
         }
       }
+      if (step + 1 < nsteps) load_step(step + 1);       // in flight during level 2
       __syncthreads();
       // ---- level 2: jobs (c0, 16-row tile of m, 16-column tile of n) ----
       for (int job = wave; job < 4 * T16 * T16; job += NWAVE) {
@@ -328,6 +361,7 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
         }
       }
       __syncthreads();
+      if (step + 1 < nsteps) store_step();            // level 1 of this step has read the window
       // ---- level 3 (FP32): axis-0 factors of this Gauss point into the register window ----
       if (live) {
 #pragma unroll
@@ -343,18 +377,29 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
           }
         }
       }
+      __syncthreads();                                  // the staged window of the next step is complete
     }
-    // ---- emit the completed row(s) of this column ----
-    if (live) {
-      const int last = (e0 == pb.ne[0] - 1) ? p : 0;
-#pragma unroll
-      for (int a0 = 0; a0 < P; ++a0) {
-        if (a0 > last) break;
-        const int i0 = e0 + a0;
+    // ---- emit the completed row(s) of this column: each owner stages its W values of a row in CSR
+    // order (the row's columns are the tensor product of the per-axis ranges, axis 0 fastest), then
+    // the block writes its rows as contiguous runs ----
+    const int last = (e0 == pb.ne[0] - 1) ? p : 0;
+    for (int a0 = 0; a0 <= last; ++a0) {
+      const int i0 = e0 + a0;
+      if (t < kMB * kMB) {
+        const int ri1 = I1 + (t & 1), ri2 = I2 + (t >> 1);
+        rowLen[t] = 0;
+        if (ri1 < n1 && ri2 < n2) {
+          rowBase[t] = pb.row_ptr[i0 + (int64_t)n0 * (ri1 + (int64_t)n1 * ri2)];
+          rowLen[t] = pb.ax[0].stw[i0] * pb.ax[1].stw[ri1] * pb.ax[2].stw[ri2];
+        }
+      }
+      if (live) {
         const bool rowDir = is_dirichlet_idx(pb, i0, i1, i2);
         const int64_t A = i0 + (int64_t)n0 * (i1 + (int64_t)n1 * i2);
-        const int64_t base = csr_slot(pb, i0, i1, i2, max(0, i0 - p), j1, j2);
         const double wA = (TABLE && pb.rational) ? pb.wts[A] : 1.0;
+        const int l0 = pb.ax[0].stl[i0], w0 = pb.ax[0].stw[i0], w1 = pb.ax[1].stw[i1];
+        const int seg = ((j2 - pb.ax[2].stl[i2]) * w1 + (j1 - pb.ax[1].stl[i1])) * w0 - l0;
+        float *dst = &rowbuf[(mo / W) + kMB * (no / W)][0];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
           const int j0 = i0 + k - p;
@@ -363,12 +408,21 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
           if (rowDir) v = (j0 == i0 && j1 == i1 && j2 == i2) ? 1.0 : 0.0;
           else if (is_dirichlet_idx(pb, j0, j1, j2)) v = 0.0;
           else {
-            v = (double)acc[a0][k];
+            float av = 0.f;
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+              if (a == a0) av = acc[a][k];                // register window row a0 (no dynamic indexing)
+            v = (double)av;
             if (TABLE && pb.rational) v *= wA * pb.wts[j0 + (int64_t)n0 * (j1 + (int64_t)n1 * j2)];
           }
-          __builtin_nontemporal_store((float)v, &vals[base + (j0 - max(0, i0 - p))]);
+          dst[seg + j0] = (float)v;
         }
       }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kMB * kMB; ++r)
+        for (int i = t; i < rowLen[r]; i += NT) __builtin_nontemporal_store(rowbuf[r][i], &vals[rowBase[r] + i]);
+      __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < P - 1; ++a)
