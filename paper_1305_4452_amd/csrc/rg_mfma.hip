@@ -37,7 +37,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMB = 2;     // pencils per block along axes 1 and 2
 constexpr int kLD = 40;    // row stride (elements) of the LDS operand tiles: 32 used, padded against bank conflicts
-constexpr int kPad = 32;   // zero padding at the end of every cs row (the 32-deep reductions may read past the window)
+constexpr int kPad = 36;   // zero padding at the end of every cs row (the 32-deep reductions may read past the window)
 
 template <int P>
 struct MShape {
@@ -166,13 +166,25 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
   __shared__ float fX0[2][Q][P];
   __shared__ __attribute__((aligned(16))) __bf16 z2[NL][4][NN][kLD];    // level-1 B operand [f2][n][g2]
   __shared__ __attribute__((aligned(16))) __bf16 z1[NL][4][NN][kLD];    // level-2 A operand [f1][m][g1]
-  __shared__ __attribute__((aligned(16))) __bf16 t1[NL][NK][NN][kLD];   // level-2 B operand [k][n][g1]
+  // level-2 B operand t1 [k][n][g1]; where level 1 rewrites all 32 rows of t1 every step (G > 16) the
+  // completed-row staging buffer of the emission shares its memory (used only between steps)
+  constexpr int T1B = NL * NK * NN * kLD * 2, RBB = kMB * kMB * W * W * W * 4;
+  constexpr bool ALIAS = S::MT * 16 >= 32 && RBB <= T1B;
+  __shared__ __attribute__((aligned(16))) unsigned char t1raw[ALIAS ? T1B : T1B + RBB];
+  auto t1 = reinterpret_cast<__bf16(*)[NK][NN][kLD]>(t1raw);
+  auto rowbuf = reinterpret_cast<float(*)[W * W * W]>(t1raw + (ALIAS ? 0 : T1B));
   __shared__ float T2[4][NN][NN + 1];                     // level-2 results [c0][m][n]
-  __shared__ __attribute__((aligned(16))) __bf16 csw[NL][NS][G][kLD];  // level-1 A operand [s][g1][g2], one step
-  __shared__ float rowbuf[kMB * kMB][W * W * W];          // completed rows in CSR order
+  // the coefficient window of one step (level-1 A operand), FP32 [s, g1][columns of g2].  Odd Q: 36
+  // columns, of which the 32 the reduction reads start d = 0 or 2 columns in (the window start
+  // rounded down to 16 bytes); rows of 144 bytes put 16 consecutive rows in distinct LDS banks.
+  // Q a multiple of 4: the window start is 16-byte aligned, rows hold the 32 columns as eight 16-byte
+  // chunks stored in the order chunk ^ (g1 % 8), against bank conflicts.
+  constexpr int NCH = (Q % 4 == 0) ? 8 : 9;               // 16-byte chunks per window row
+  constexpr int WCH = NS * G * NCH;                       // 16-byte chunks of the window
+  constexpr int WCHA = ((WCH + 63) / 64) * 64;            // whole global->LDS loads (64 chunks each)
+  __shared__ __attribute__((aligned(16))) float wbuf[WCHA * 4];
   __shared__ int64_t rowBase[kMB * kMB];
   __shared__ int rowLen[kMB * kMB];
-  constexpr int NPF = (NS * G * 32 + NT - 1) / NT;        // window values each thread stages per step
 
   const MCombo *combos = TABLE ? kCombosTable : kCombosDiag;
   const MGroup *groups = TABLE ? kGroupsTable : kGroupsDiag;
@@ -201,6 +213,8 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
   }
   // rows of t1 that level 1 never writes (g1 >= 16 MT) enter the 32-deep level-2 reduction: zero
   for (int i = t; i < NL * NK * NN * kLD; i += NT) (&t1[0][0][0][0])[i] = (__bf16)0.f;
+  // window entries that no load writes stay finite
+  for (int i = t; i < WCHA * 4; i += NT) wbuf[i] = 0.f;
   __syncthreads();
   // Z2_f[n][g2] and Z1_f[m][g1]: products of the 1D factors, zero outside the support overlap and
   // in the padding of the 32-deep reductions
@@ -234,36 +248,30 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
     for (int k = 0; k < W; ++k) acc[a][k] = 0.f;
 
   // The coefficient window of a step (e0, q0): cs rows E1lo Q + [0, G) (rows past the window's end
-  // repeat its last row), columns E2lo Q + [0, 32) (the padding columns meet zero rows of Z2).  Each
-  // thread loads its NPF values of the next step at the start of a step and stores them, rounded to
-  // BF16 (hi, lo), once level 1 has read the current window.
-  float nxt[NPF];
-  // 32-bit offsets inside one step's plane (NS x ne1 Q x ld floats; checked on the host)
-  const int ldi = (int)ld, rowoff = E1lo * Q, coloff = E2lo * Q;
-  auto load_step = [&](int step) {
+  // repeat its last row), columns E2lo Q + [0, 32) (the padding columns meet zero rows of Z2), moved
+  // by 16-byte global->LDS loads (lane i to LDS base + 16 i, no registers) issued once level 1 has
+  // read the previous window.  The window start E2lo Q is even (E2lo = I2 - p with I2 even, and Q odd
+  // only when p is even), so it lies d = 0 or 2 floats past a 16-byte boundary; cs rows are 16-byte
+  // multiples (ld % 4 == 0, set on the host).  32-bit offsets inside one step's plane (checked on the
+  // host).
+  const int ldi = (int)ld, rowoff = E1lo * Q, coloff = E2lo * Q, wd = coloff & 3, cbase = coloff - wd;
+  auto dma_step = [&](int step) {
     const float *plane = cs + (int64_t)step * NS * G1tot * ld;
-#pragma unroll
-    for (int r = 0; r < NPF; ++r) {
-      const int i = t + r * NT;
-      const int col = i % 32, row = (i / 32) % G, s = i / (32 * G);
-      const int off = (s * (int)G1tot + rowoff + min(row, G1 - 1)) * ldi + coloff + col;
-      nxt[r] = (s < NS) ? plane[off] : 0.f;
-    }
-  };
-  auto store_step = [&]() {
-#pragma unroll
-    for (int r = 0; r < NPF; ++r) {
-      const int i = t + r * NT;
-      const int col = i % 32, row = (i / 32) % G, s = i / (32 * G);
-      if (s < NS) {
-        const __bf16 h = to_bf16(nxt[r]);
-        csw[0][s][row][col] = h;
-        if constexpr (SPLIT) csw[1][s][row][col] = to_bf16(nxt[r] - (float)h);
+    for (int k = wave; k < WCHA / 64; k += NWAVE) {
+      const int f = 64 * k + lane, fr = f / NCH, slot = f % NCH;
+      const float *src = plane;                        // chunks past the window (whole loads): any valid value
+      if (f < WCH) {
+        const int s = fr / G, row = fr % G;
+        const int ch = NCH == 8 ? (slot ^ (row & 7)) : slot;   // the logical chunk stored in this slot
+        src = plane + (s * (int)G1tot + rowoff + min(row, G1 - 1)) * ldi + cbase + 4 * ch;
       }
+      __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)&wbuf[256 * k],
+                                       16, 0, 0);
     }
   };
-  load_step(0);
-  store_step();
+  dma_step(0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
   const int nsteps = pb.ne[0] * Q;
 
   for (int e0 = 0; e0 < pb.ne[0]; ++e0) {
@@ -285,8 +293,27 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
 #pragma unroll
         for (int si = 0; si < 3; ++si) {
           if (si >= Gr.ns) break;
-          ah[si] = *(const bf16x8 *)&csw[0][Gr.s[si]][row][kk];
-          if constexpr (SPLIT) al[si] = *(const bf16x8 *)&csw[NL - 1][Gr.s[si]][row][kk];
+          float xs[8];
+          if constexpr (NCH == 8) {
+            const float *wr = &wbuf[(Gr.s[si] * G + row) * 32];
+            const int c0 = kk >> 2, sw = row & 7;
+            const float4 x0 = *(const float4 *)&wr[4 * (c0 ^ sw)], x1 = *(const float4 *)&wr[4 * ((c0 + 1) ^ sw)];
+            xs[0] = x0.x; xs[1] = x0.y; xs[2] = x0.z; xs[3] = x0.w;
+            xs[4] = x1.x; xs[5] = x1.y; xs[6] = x1.z; xs[7] = x1.w;
+          } else {
+            const float *wr = &wbuf[(Gr.s[si] * G + row) * 36 + wd + kk];      // 8-byte aligned (wd even)
+#pragma unroll
+            for (int j = 0; j < 8; j += 2) {
+              const float2 x = *(const float2 *)&wr[j];
+              xs[j] = x.x;
+              xs[j + 1] = x.y;
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            ah[si][j] = to_bf16(xs[j]);
+            if constexpr (SPLIT) al[si][j] = to_bf16(xs[j] - (float)ah[si][j]);
+          }
         }
         f32x4 d0[T16], d1[T16];
 #pragma unroll
@@ -333,8 +360,8 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
           }
         }
       }
-      if (step + 1 < nsteps) load_step(step + 1);       // in flight during level 2
       __syncthreads();
+      if (step + 1 < nsteps) dma_step(step + 1);        // level 1 has read the window; in flight during levels 2, 3
       // ---- level 2: jobs (c0, 16-row tile of m, 16-column tile of n) ----
       for (int job = wave; job < 4 * T16 * T16; job += NWAVE) {
         const int c = job / (T16 * T16), tm = (job / T16) % T16, tn = job % T16;
@@ -361,7 +388,6 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
         }
       }
       __syncthreads();
-      if (step + 1 < nsteps) store_step();            // level 1 of this step has read the window
       // ---- level 3 (FP32): axis-0 factors of this Gauss point into the register window ----
       if (live) {
 #pragma unroll
@@ -377,7 +403,8 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
           }
         }
       }
-      __syncthreads();                                  // the staged window of the next step is complete
+      __builtin_amdgcn_s_waitcnt(0);                    // this wave's window loads have landed
+      __syncthreads();                                  // ... and every wave's
     }
     // ---- emit the completed row(s) of this column: each owner stages its W values of a row in CSR
     // order (the row's columns are the tensor product of the per-axis ranges, axis 0 fastest), then
@@ -436,7 +463,7 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
 // coefficient-stream buffer: rows of ne2 Q + kPad floats (the padding zeroed once, at allocation)
 iga_status ensure_cs(Handle &h, int64_t *ld) {
   const int Q = h.pb.Q, NS = h.pb.table ? 10 : 2;
-  *ld = (int64_t)h.pb.ne[2] * Q + kPad;
+  *ld = (((int64_t)h.pb.ne[2] * Q + kPad + 3) / 4) * 4;     // 16-byte rows (the window loads)
   const size_t bytes = (size_t)h.pb.ne[0] * Q * NS * (size_t)h.pb.ne[1] * Q * (size_t)(*ld) * sizeof(float);
   if (h.mma_cs && h.mma_cs_bytes == bytes) return IGA_OK;
   void *q = nullptr;
@@ -454,6 +481,8 @@ iga_status run_mma(Handle &h, const double *U, float *vals) {
   int64_t ld = 0;
   iga_status st = ensure_cs(h, &ld);
   if (st) return st;
+  if ((double)(TABLE ? 10 : 2) * h.pb.ne[1] * h.pb.Q * (double)ld >= 2147483647.0)
+    return fail(IGA_EUNSUPPORTED, "BF16 matrix-core Jacobian: a coefficient plane exceeds 32-bit offsets");
   kt_begin(h, "k_cs3");
   hipLaunchKernelGGL((k_cs3<P, TABLE>), dim3((unsigned)(h.pb.ne[0] * h.pb.ne[1])), dim3(256), 0, h.stream, h.pb, U,
                      h.mma_cs, ld);
