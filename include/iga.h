@@ -286,10 +286,14 @@ iga_status iga_kernel_times(iga_t h, int cap, double *ms, const char **names, in
 /* ---- batched solves ------------------------------------------------------------------------
  * Many independent 2D problems (identity geometry, kappa one or element-wise, simple interior
  * knots; degrees and sizes may differ) solved together: every kernel of the Newton step covers
- * all instances in one launch over per-instance work lists, per-instance CG scalars and
- * convergence decisions stay on the device, and each chunk of CG iterations is one replay of a
- * captured hipGraph.  Pencil-block and SpMV launch shapes are autotuned per (degree, size
- * class) when the batch is created.  The CG preconditioner is the fast diagonalisation of each
+ * all instances in one launch over per-instance work lists, and per-instance CG scalars, Newton
+ * stopping tests and forcing terms stay on the device.  A whole Newton step (the previous
+ * correction, residual and norms, the Newton control, Jacobian, preconditioner set-up and one
+ * chunk of CG iterations) is one replay of a captured hipGraph; further chunks of CG iterations,
+ * when some instance needs them, are replays of a second graph.  Launch shapes (pencils per
+ * row-gather block, SpMV lanes per row, and the tile shapes of the tiled row-gather and residual)
+ * are autotuned per (degree, size class) when the batch is created, cached for the process and,
+ * when the environment variable IGA_TUNE_CACHE names a file, kept there as JSON.  The CG preconditioner is the fast diagonalisation of each
  * instance (two 1D eigendecompositions per distinct 1D problem, computed at creation) when every
  * axis of every instance has at most 136 free coefficients, Jacobi otherwise.  Callers that need
  * many solves of small 2D problems (parameter sweeps, training-data generation) use this instead
@@ -306,9 +310,11 @@ typedef struct {
 typedef struct {
   int all_converged;
   int newton_steps;              /* Newton steps of the slowest instance */
-  int graph_launches;            /* CG chunk replays in total */
+  int graph_launches;            /* graph replays in total (Newton steps and extra CG chunks) */
   int krylov_iters_max;          /* CG iterations run (chunks x chunk length) */
-  double t_total_ms, t_residual_ms, t_jacobian_ms, t_krylov_ms, t_tune_ms;
+  double t_total_ms, t_residual_ms, t_jacobian_ms, t_krylov_ms, t_tune_ms;   /* t_jacobian_ms: the
+                                    Newton-step graphs (residual, Jacobian, first CG chunk); t_krylov_ms:
+                                    the extra CG chunks; t_residual_ms: 0 (inside the step graphs) */
 } iga_batch_report;
 
 /* n descriptions (host array); copied.  Errors as iga_create, plus IGA_EUNSUPPORTED for 3D,

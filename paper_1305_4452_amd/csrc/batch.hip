@@ -16,6 +16,8 @@
 #include <map>
 #include <mutex>
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
 #include <thread>
 #include <vector>
 
@@ -127,27 +129,27 @@ k_b_rowgather(const DevProblem *__restrict__ pbs, const Pair *__restrict__ work,
   rgk::rowgather2_body<P, false, B1, OT, OT>(pbs[w.inst], w.idx, U + off[w.inst], vals + noff[w.inst]);
 }
 
-template <int P>
+template <int P, int V>
 __global__ void __launch_bounds__(rst::kThreads) k_b_res2(const DevProblem *__restrict__ pbs,
                                                           const Pair *__restrict__ work,
                                                           const int64_t *__restrict__ off,
                                                           const int *__restrict__ act, const double *__restrict__ U,
                                                           double *__restrict__ R) {
-  __shared__ double lds[rst::Res2<P>::total / sizeof(double)];
+  __shared__ double lds[rst::Res2<P, V>::total / sizeof(double)];
   const Pair w = work[blockIdx.x];
   if (!act[w.inst]) return;
-  rst::res2_body<P>(pbs[w.inst], w.idx, U + off[w.inst], R + off[w.inst], lds);
+  rst::res2_body<P, V>(pbs[w.inst], w.idx, U + off[w.inst], R + off[w.inst], lds);
 }
 
-template <int P, typename OT>
+template <int P, typename OT, int V>
 __global__ void __launch_bounds__(rgt::kThreads)
 k_b_rgt2(const DevProblem *__restrict__ pbs, const Pair *__restrict__ work, const int64_t *__restrict__ off,
          const int64_t *__restrict__ noff, const int *__restrict__ act, const double *__restrict__ U,
          OT *__restrict__ vals) {
-  __shared__ __align__(16) char lds[rgt::Lds2<P, OT, OT>::total];
+  __shared__ __align__(16) char lds[rgt::Lds2<P, OT, OT, V>::total];
   const Pair w = work[blockIdx.x];
   if (!act[w.inst]) return;
-  rgt::rgt2_body<P, OT, OT>(pbs[w.inst], w.idx, U + off[w.inst], vals + noff[w.inst], lds);
+  rgt::rgt2_body<P, OT, OT, V>(pbs[w.inst], w.idx, U + off[w.inst], vals + noff[w.inst], lds);
 }
 
 template <typename VT>
@@ -332,6 +334,56 @@ __global__ void k_b_axpy(const Tile *__restrict__ tl, const int64_t *__restrict_
   U[i] += d[i];
 }
 
+// Newton control of every instance on the device, after the residual norms of step k = *kstep:
+// the stopping test (||R|| < atol, or ||R|| <= rtol ||R_0||, or k = max_newton, or a non-finite
+// norm) ends an instance (act = 0); otherwise the Eisenstat-Walker forcing term (second choice,
+// floor 0.1 target / ||R||, cap forcing_max) sets its CG target eta ||R||.  Also records the norm
+// history.  One workgroup; *nact receives the number of instances still iterating.
+// prm: atol, rtol, forcing_max, max_newton.
+constexpr int kHist = 65;
+__global__ void __launch_bounds__(1024) k_b_newton_ctl(int n, const double *__restrict__ norms, const double *__restrict__ prm,
+                                                       int *__restrict__ act, double *__restrict__ target,
+                                                       double *__restrict__ r0, double *__restrict__ nr_prev,
+                                                       double *__restrict__ eta, int *__restrict__ conv,
+                                                       int *__restrict__ hcount, double *__restrict__ hist,
+                                                       int *__restrict__ kstep, int *__restrict__ nact) {
+  __shared__ int cnt[16];
+  const int k = *kstep, t = threadIdx.x;
+  const double atol = prm[0], rtol = prm[1], fmax_ = prm[2];
+  const int max_newton = (int)prm[3];
+  int c = 0;
+  for (int i = t; i < n; i += blockDim.x) {
+    if (!act[i]) continue;
+    const double nr = norms[i];
+    if (k < kHist) hist[(size_t)i * kHist + k] = nr;
+    hcount[i] = k + 1;
+    if (r0[i] < 0) r0[i] = nr;
+    if (!isfinite(nr)) { act[i] = 0; continue; }
+    if (nr < atol || (rtol > 0 && nr <= rtol * r0[i])) { act[i] = 0; conv[i] = 1; continue; }
+    if (k >= max_newton) { act[i] = 0; continue; }
+    double e = eta[i];
+    if (k > 0) {
+      const double ratio = nr / nr_prev[i];
+      e = fmin(fmax_, 0.9 * ratio * ratio);
+    }
+    const double tgt = fmax(atol, rtol * r0[i]);
+    e = fmin(fmax_, fmax(e, 0.1 * tgt / nr));
+    eta[i] = e;
+    nr_prev[i] = nr;
+    target[i] = e * nr;
+    ++c;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((t & 63) == 0) cnt[t >> 6] = c;
+  __syncthreads();
+  if (t == 0) {
+    int s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += cnt[w];
+    *nact = s;
+    *kstep = k + 1;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Batched fast-diagonalisation preconditioner.  Per instance (2D) z = (a0 A0 (x) M1 + a1 M0 (x) A1
 // + c M)^{-1} r on the non-Dirichlet box, z = r elsewhere (the single-problem preconditioner of
@@ -478,6 +530,43 @@ __global__ void __launch_bounds__(256) k_b_pz(const Tile *__restrict__ tl, const
 // ------------------------------------------------------------------------------------------
 std::mutex g_tune_mu;
 std::map<long, int> g_tune;   // key = (kind << 16) | (p << 8) | size class
+bool g_tune_loaded = false;
+
+// The cache is also kept in the JSON file named by IGA_TUNE_CACHE (when set): an object whose
+// keys are "kind:degree:size class" (kind 1: row-gather pencils per block, 2: SpMV lanes per row,
+// 3: tiled row-gather shape, 4: tiled residual shape) and whose values are the chosen shapes.
+// Read once per process before the first tuning, rewritten after each tuning.  Caller holds g_tune_mu.
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = std::getenv("IGA_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  int c, kind, p, cls, v;
+  while ((c = std::fgetc(f)) != EOF) {
+    if (c != '"') continue;
+    if (std::fscanf(f, "%d:%d:%d\": %d", &kind, &p, &cls, &v) == 4 && kind >= 1 && kind <= 4)
+      g_tune[((long)kind << 16) | (p << 8) | cls] = v;
+  }
+  std::fclose(f);
+}
+
+void tune_cache_save() {
+  const char *path = std::getenv("IGA_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "{");
+  bool first = true;
+  for (const auto &kv : g_tune) {
+    std::fprintf(f, "%s\n  \"%ld:%ld:%ld\": %d", first ? "" : ",", kv.first >> 16, (kv.first >> 8) & 255, kv.first & 255,
+                 kv.second);
+    first = false;
+  }
+  std::fprintf(f, "\n}\n");
+  std::fclose(f);
+}
 
 int size_class(int64_t N) { return N < 1500 ? 0 : (N < 5000 ? 1 : 2); }
 
@@ -489,6 +578,8 @@ struct Group {
   std::vector<int> insts;
   int b1 = 4;               // row-gather pencils per block, 0: tiled kernel (autotuned)
   int lpr = 8;              // SpMV lanes per row (autotuned)
+  int rgt_v = 0;            // tiled row-gather tile shape (rgt::Shape2 variant, autotuned)
+  int res_v = 0;            // tiled residual tile shape (rst::Res2 variant, autotuned)
   std::vector<Pair> pencils;
   Pair *d_pencils = nullptr;
   std::vector<Pair> tiles;   // (instance, tile) of the tiled row-gather
@@ -527,6 +618,13 @@ struct Batch {
   double *norms = nullptr, *target = nullptr;
   int *act = nullptr, *iters = nullptr, *count = nullptr, *flags = nullptr;
   hipGraphExec_t graph = nullptr;
+  // one Newton step as one graph (see batch_newton) and its device-side Newton state
+  hipGraphExec_t step_graph = nullptr;
+  const double *step_U = nullptr;
+  int step_prec = -1, step_chunk = 0;
+  bool step_fdm = false;
+  double *nprm = nullptr, *r0 = nullptr, *nr_prev = nullptr, *eta = nullptr, *hist = nullptr;
+  int *conv = nullptr, *hcount = nullptr, *kstep = nullptr, *nact = nullptr;
   // batched fast-diagonalisation preconditioner (bf_on: every instance has one)
   bool bf_on = false;
   int precond = IGA_PRECOND_AUTO;   // iga_precond chosen by the caller
@@ -563,6 +661,7 @@ static void batch_free(Batch *b) {
   if (!b) return;
   if (b->bs) (void)hipStreamSynchronize(b->bs);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->step_graph) (void)hipGraphExecDestroy(b->step_graph);
   for (void *p : b->owned)
     if (p) (void)hipFree(p);
   for (Handle *h : b->hs) iga_destroy((iga_t)h);
@@ -571,16 +670,22 @@ static void batch_free(Batch *b) {
 }
 
 // ---- launch helpers -----------------------------------------------------------------------
+template <int P, int V>
+static void launch_rgt_v(Batch &b, const Group &g, const double *U, void *vals, int prec, hipStream_t s) {
+  dim3 grid((unsigned)g.tiles.size()), blk(rgt::kThreads);
+  if (prec == IGA_FP32)
+    hipLaunchKernelGGL((k_b_rgt2<P, float, V>), grid, blk, 0, s, b.d_pbs, g.d_tiles, b.d_off, b.d_noff, b.act, U,
+                       (float *)vals);
+  else
+    hipLaunchKernelGGL((k_b_rgt2<P, double, V>), grid, blk, 0, s, b.d_pbs, g.d_tiles, b.d_off, b.d_noff, b.act, U,
+                       (double *)vals);
+}
+
 template <int P>
 static void launch_rgt_group(Batch &b, const Group &g, const double *U, void *vals, int prec, hipStream_t s) {
   if constexpr (P >= 2 && P <= 5) {
-    dim3 grid((unsigned)g.tiles.size()), blk(rgt::kThreads);
-    if (prec == IGA_FP32)
-      hipLaunchKernelGGL((k_b_rgt2<P, float>), grid, blk, 0, s, b.d_pbs, g.d_tiles, b.d_off, b.d_noff, b.act, U,
-                         (float *)vals);
-    else
-      hipLaunchKernelGGL((k_b_rgt2<P, double>), grid, blk, 0, s, b.d_pbs, g.d_tiles, b.d_off, b.d_noff, b.act, U,
-                         (double *)vals);
+    if (g.rgt_v == 1) launch_rgt_v<P, 1>(b, g, U, vals, prec, s);
+    else launch_rgt_v<P, 0>(b, g, U, vals, prec, s);
   }
 }
 
@@ -622,12 +727,19 @@ static void launch_res(Batch &b, const Group &g, const double *U, double *R, hip
   dim3 grid((unsigned)g.elems.size()), blk(64);
   if (g.res_tiles) {
     dim3 bt(rst::kThreads);
-    switch (g.P) {
-      case 2: hipLaunchKernelGGL(k_b_res2<2>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
-      case 3: hipLaunchKernelGGL(k_b_res2<3>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
-      case 4: hipLaunchKernelGGL(k_b_res2<4>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
-      case 5: hipLaunchKernelGGL(k_b_res2<5>, grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R); break;
+#define IGA_BRES(PP, VV) \
+  hipLaunchKernelGGL((k_b_res2<PP, VV>), grid, bt, 0, s, b.d_pbs, g.d_elems, b.d_off, b.act, U, R)
+    switch (g.P * 2 + g.res_v) {
+      case 4: IGA_BRES(2, 0); break;
+      case 5: IGA_BRES(2, 1); break;
+      case 6: IGA_BRES(3, 0); break;
+      case 7: IGA_BRES(3, 1); break;
+      case 8: IGA_BRES(4, 0); break;
+      case 9: IGA_BRES(4, 1); break;
+      case 10: IGA_BRES(5, 0); break;
+      case 11: IGA_BRES(5, 1); break;
     }
+#undef IGA_BRES
     return;
   }
   switch (g.P) {
@@ -695,14 +807,22 @@ static bool tiles_supported(const Batch &b, const Group &g) {
   return true;
 }
 
+template <int P>
+static void rgt_shape(int v, int *T0, int *B1) {
+  if constexpr (P >= 2 && P <= 5) {
+    *T0 = v ? rgt::Shape2<P, 1>::T0 : rgt::Shape2<P, 0>::T0;
+    *B1 = v ? rgt::Shape2<P, 1>::B1 : rgt::Shape2<P, 0>::B1;
+  }
+}
+
 static iga_status build_tiles(Batch &b, Group &g) {
   g.tiles.clear();
   int T0 = 0, B1 = 0;
   switch (g.P) {
-    case 2: T0 = rgt::Shape2<2>::T0; B1 = rgt::Shape2<2>::B1; break;
-    case 3: T0 = rgt::Shape2<3>::T0; B1 = rgt::Shape2<3>::B1; break;
-    case 4: T0 = rgt::Shape2<4>::T0; B1 = rgt::Shape2<4>::B1; break;
-    case 5: T0 = rgt::Shape2<5>::T0; B1 = rgt::Shape2<5>::B1; break;
+    case 2: rgt_shape<2>(g.rgt_v, &T0, &B1); break;
+    case 3: rgt_shape<3>(g.rgt_v, &T0, &B1); break;
+    case 4: rgt_shape<4>(g.rgt_v, &T0, &B1); break;
+    case 5: rgt_shape<5>(g.rgt_v, &T0, &B1); break;
     default: return IGA_OK;
   }
   for (int i : g.insts) {
@@ -711,6 +831,28 @@ static iga_status build_tiles(Batch &b, Group &g) {
     for (int k = 0; k < nt; ++k) g.tiles.push_back(Pair{i, k});
   }
   return bupload(b, &g.d_tiles, g.tiles);
+}
+
+// (instance, element) or (instance, element tile) work list of the residual
+static iga_status build_elems(Batch &b, Group &g) {
+  g.elems.clear();
+  int TE = 0;
+  switch (g.P * 2 + g.res_v) {
+    case 4: TE = rst::Res2<2, 0>::TE; break;
+    case 5: TE = rst::Res2<2, 1>::TE; break;
+    case 6: TE = rst::Res2<3, 0>::TE; break;
+    case 7: TE = rst::Res2<3, 1>::TE; break;
+    case 8: TE = rst::Res2<4, 0>::TE; break;
+    case 9: TE = rst::Res2<4, 1>::TE; break;
+    case 10: TE = rst::Res2<5, 0>::TE; break;
+    case 11: TE = rst::Res2<5, 1>::TE; break;
+  }
+  for (int k : g.insts) {
+    const DevProblem &pk = b.hs[k]->pb;
+    const int64_t cnt = g.res_tiles ? rst::res2_tiles(pk.ne[0], pk.ne[1], TE) : pk.E;
+    for (int64_t e = 0; e < cnt; ++e) g.elems.push_back(Pair{k, (int)e});
+  }
+  return bupload(b, &g.d_elems, g.elems);
 }
 
 static iga_status build_pencils(Batch &b, Group &g) {
@@ -744,6 +886,7 @@ static iga_status autotune(Batch &b) {
     bool have_rg, have_sp;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_cache_load();
       have_rg = g_tune.count(key_rg);
       have_sp = g_tune.count(key_sp);
       if (have_rg) g.b1 = g_tune[key_rg];
@@ -774,6 +917,63 @@ static iga_status autotune(Batch &b) {
       g_tune[key_rg] = bestb;
     }
     if (g.b1 > 0 && (st = build_pencils(b, g))) return st;
+    // tile shapes of the tiled row-gather and residual: time both variants (values are never read)
+    const long key_rt = (3L << 16) | (g.P << 8) | g.cls, key_rs = (4L << 16) | (g.P << 8) | g.cls;
+    int cached_rt = -1, cached_rs = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      if (g_tune.count(key_rt)) cached_rt = g_tune[key_rt];
+      if (g_tune.count(key_rs)) cached_rs = g_tune[key_rs];
+    }
+    if (g.b1 == 0 && tiles) {
+      if (cached_rt >= 0) {
+        g.rgt_v = cached_rt;
+      } else {
+        float best = 1e30f;
+        int bestv = 0;
+        for (int v : {0, 1}) {
+          g.rgt_v = v;
+          if ((st = build_tiles(b, g))) return st;
+          IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
+          launch_rg(b, g, 0, U, b.vals, IGA_FP64, b.bs);
+          hipEventRecord(e0, b.bs);
+          for (int r = 0; r < 3; ++r) launch_rg(b, g, 0, U, b.vals, IGA_FP64, b.bs);
+          hipEventRecord(e1, b.bs);
+          IGA_HIP_CHECK(hipEventSynchronize(e1));
+          const float ms = elapsed(e0, e1);
+          if (ms < best) { best = ms; bestv = v; }
+        }
+        g.rgt_v = bestv;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key_rt] = bestv;
+      }
+      if ((st = build_tiles(b, g))) return st;
+    }
+    if (g.res_tiles) {
+      if (cached_rs >= 0) {
+        g.res_v = cached_rs;
+      } else {
+        double *R = b.ws;
+        float best = 1e30f;
+        int bestv = 0;
+        for (int v : {0, 1}) {
+          g.res_v = v;
+          if ((st = build_elems(b, g))) return st;
+          IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
+          launch_res(b, g, U, R, b.bs);
+          hipEventRecord(e0, b.bs);
+          for (int r = 0; r < 3; ++r) launch_res(b, g, U, R, b.bs);
+          hipEventRecord(e1, b.bs);
+          IGA_HIP_CHECK(hipEventSynchronize(e1));
+          const float ms = elapsed(e0, e1);
+          if (ms < best) { best = ms; bestv = v; }
+        }
+        g.res_v = bestv;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key_rs] = bestv;
+      }
+      if ((st = build_elems(b, g))) return st;
+    }
   }
   // SpMV lanes per row: tune each group with the others fixed
   for (size_t gi = 0; gi < b.groups.size(); ++gi) {
@@ -805,6 +1005,10 @@ static iga_status autotune(Batch &b) {
     g_tune[key_sp] = bestl;
   }
   if ((st = upload_spmv(b))) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_save();
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b.t_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1045,7 +1249,11 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
       (st = balloc(*b, &b->partB, nvt)) || (st = balloc(*b, &b->partC, nvt)) || (st = balloc(*b, &b->partD, nvt)) ||
       (st = balloc(*b, &b->norms, (size_t)n)) || (st = balloc(*b, &b->target, (size_t)n)) ||
       (st = balloc(*b, &b->act, (size_t)n)) || (st = balloc(*b, &b->iters, (size_t)n)) ||
-      (st = balloc(*b, &b->count, 1)) || (st = balloc(*b, &b->flags, (size_t)n))) {
+      (st = balloc(*b, &b->count, 1)) || (st = balloc(*b, &b->flags, (size_t)n)) ||
+      (st = balloc(*b, &b->nprm, 4)) || (st = balloc(*b, &b->r0, (size_t)n)) || (st = balloc(*b, &b->nr_prev, (size_t)n)) ||
+      (st = balloc(*b, &b->eta, (size_t)n)) || (st = balloc(*b, &b->hist, (size_t)n * kHist)) ||
+      (st = balloc(*b, &b->conv, (size_t)n)) || (st = balloc(*b, &b->hcount, (size_t)n)) ||
+      (st = balloc(*b, &b->kstep, 1)) || (st = balloc(*b, &b->nact, 2))) {
     batch_free(b);
     return st;
   }
@@ -1060,19 +1268,7 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
   for (Group &g : b->groups) {
     g.res_tiles = g.P >= 2 && g.P <= 5;
     for (int k : g.insts) g.res_tiles = g.res_tiles && res2_supported(b->hs[k]->pb);
-    int TE = 0;
-    switch (g.P) {
-      case 2: TE = rst::Res2<2>::TE; break;
-      case 3: TE = rst::Res2<3>::TE; break;
-      case 4: TE = rst::Res2<4>::TE; break;
-      case 5: TE = rst::Res2<5>::TE; break;
-    }
-    for (int k : g.insts) {
-      const DevProblem &pk = b->hs[k]->pb;
-      const int64_t cnt = g.res_tiles ? rst::res2_tiles(pk.ne[0], pk.ne[1], TE) : pk.E;
-      for (int64_t e = 0; e < cnt; ++e) g.elems.push_back(Pair{k, (int)e});
-    }
-    if ((st = bupload(*b, &g.d_elems, g.elems))) {
+    if ((st = build_elems(*b, g))) {
       batch_free(b);
       return st;
     }
@@ -1106,16 +1302,12 @@ static iga_status batch_create(int n, const iga_desc *descs, void *stream, Batch
   return IGA_OK;
 }
 
-static iga_status capture_cg_graph(Batch &b, int prec, int chunk, bool fdm) {
-  if (b.graph && b.graph_prec == prec && b.graph_chunk == chunk && b.graph_fdm == fdm) return IGA_OK;
-  if (b.graph) {
-    (void)hipGraphExecDestroy(b.graph);
-    b.graph = nullptr;
-  }
+// `chunk` CG iterations of every instance, then the count of instances whose CG has not converged
+// (recorded into the capturing stream)
+static void record_cg_chunk(Batch &b, int prec, int chunk, bool fdm) {
   const int64_t N = b.Ntot;
   double *d = b.ws + N, *r = b.ws + 2 * N, *z = b.ws + 3 * N, *p = b.ws + 4 * N, *q = b.ws + 5 * N;
   const unsigned nvt = (unsigned)b.vt.size();
-  IGA_HIP_CHECK(hipStreamBeginCapture(b.bs, hipStreamCaptureModeThreadLocal));
   // partial buffers: rz in A/B, rr in C/D; iteration k reads (A,C) or (B,D) alternately
   for (int it = 0; it < chunk; ++it) {
     double *rz_cur = (it % 2 == 0) ? b.partA : b.partB, *rz_new = (it % 2 == 0) ? b.partB : b.partA;
@@ -1138,18 +1330,94 @@ static iga_status capture_cg_graph(Batch &b, int prec, int chunk, bool fdm) {
   hipLaunchKernelGGL(k_b_flags, dim3((unsigned)((b.n + 3) / 4)), dim3(256), 0, b.bs, b.n, b.d_vt_start, b.act,
                      b.target, b.partC, b.flags);
   hipLaunchKernelGGL(k_b_count, dim3(1), dim3(256), 0, b.bs, b.n, (const int *)b.flags, b.count);
+}
+
+static iga_status end_capture(Batch &b, hipGraphExec_t *out) {
   hipGraph_t g;
   hipError_t e = hipStreamEndCapture(b.bs, &g);
   if (e != hipSuccess) return fail(IGA_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(IGA_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return IGA_OK;
+}
+
+static iga_status capture_cg_graph(Batch &b, int prec, int chunk, bool fdm) {
+  if (b.graph && b.graph_prec == prec && b.graph_chunk == chunk && b.graph_fdm == fdm) return IGA_OK;
+  if (b.graph) {
+    (void)hipGraphExecDestroy(b.graph);
+    b.graph = nullptr;
+  }
+  IGA_HIP_CHECK(hipStreamBeginCapture(b.bs, hipStreamCaptureModeThreadLocal));
+  record_cg_chunk(b, prec, chunk, fdm);
+  iga_status st = end_capture(b, &b.graph);
+  if (st) return st;
   b.graph_prec = prec;
   b.graph_chunk = chunk;
   b.graph_fdm = fdm;
   return IGA_OK;
 }
 
+// One whole Newton step of every instance as one graph: U += d (the previous step's correction, on
+// the instances that solved for it), the residual and its norms, the device-side Newton control
+// (stopping test and CG targets), the Jacobian, the preconditioner set-up, the CG start and one chunk
+// of CG iterations.  Kernels skip instances that are done (act = 0), so the same graph serves every
+// step; the host reads two counters per step.
+static iga_status capture_step_graph(Batch &b, const double *Uc, int prec, int chunk, bool fdm) {
+  if (b.step_graph && b.step_U == Uc && b.step_prec == prec && b.step_chunk == chunk && b.step_fdm == fdm)
+    return IGA_OK;
+  if (b.step_graph) {
+    (void)hipGraphExecDestroy(b.step_graph);
+    b.step_graph = nullptr;
+  }
+  double *U = const_cast<double *>(Uc);
+  const int n = b.n;
+  const int64_t N = b.Ntot;
+  double *R = b.ws, *d = b.ws + N;
+  const unsigned nvt = (unsigned)b.vt.size();
+  IGA_HIP_CHECK(hipStreamBeginCapture(b.bs, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(k_b_axpy, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)d, U);
+  hipLaunchKernelGGL(k_b_fill, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, R, 0.0);
+  for (const Group &g : b.groups) launch_res(b, g, U, R, b.bs);
+  hipLaunchKernelGGL(k_b_bc_copy, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.act, (const double *)U, R);
+  hipLaunchKernelGGL(k_b_sq_partial, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, (const double *)R, b.partA);
+  hipLaunchKernelGGL(k_b_inst_norms, dim3(std::min(n, 1024)), dim3(256), 0, b.bs, n, b.d_vt_start,
+                     (const double *)b.partA, b.norms);
+  hipLaunchKernelGGL(k_b_newton_ctl, dim3(1), dim3(1024), 0, b.bs, n, (const double *)b.norms,
+                     (const double *)b.nprm, b.act, b.target, b.r0, b.nr_prev, b.eta, b.conv, b.hcount, b.hist,
+                     b.kstep, b.nact);
+  for (const Group &g : b.groups) launch_rg(b, g, g.b1, U, b.vals, prec, b.bs);
+  if (fdm) {
+    hipLaunchKernelGGL(k_bf_shift, dim3((unsigned)n), dim3(256), 0, b.bs, b.d_pbs, b.d_bf, (const double *)b.bf_pool,
+                       b.d_off, b.act, (const double *)U, b.bf_shift);
+  } else if (prec == IGA_FP32) {
+    hipLaunchKernelGGL(k_b_diag_inv<float>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff, b.act,
+                       (const float *)b.vals, b.dinv);
+  } else {
+    hipLaunchKernelGGL(k_b_diag_inv<double>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff,
+                       b.act, (const double *)b.vals, b.dinv);
+  }
+  hipLaunchKernelGGL(k_b_cg_init, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)R,
+                     fdm ? nullptr : (const double *)b.dinv, d, b.ws + 2 * N, b.ws + 3 * N, b.ws + 4 * N,
+                     b.partA, b.partC);
+  if (fdm) {
+    launch_bf_apply(b, b.ws + 2 * N, b.ws + 3 * N, nullptr, b.bs);
+    hipLaunchKernelGGL(k_b_pz, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)(b.ws + 2 * N),
+                       (const double *)(b.ws + 3 * N), b.ws + 4 * N, b.partA);
+  }
+  record_cg_chunk(b, prec, chunk, fdm);
+  iga_status st = end_capture(b, &b.step_graph);
+  if (st) return st;
+  b.step_U = Uc;
+  b.step_prec = prec;
+  b.step_chunk = chunk;
+  b.step_fdm = fdm;
+  return IGA_OK;
+}
+
+// Newton on every instance: one replay of the step graph per Newton step, plus replays of the
+// CG-chunk graph while some instance's CG has not met its target; the host reads the number of
+// active instances and of unconverged CG solves once per replay.
 static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in, iga_batch_item_report *items,
                                iga_batch_report *rep) {
   iga_newton_opts o{};
@@ -1165,7 +1433,6 @@ static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in,
   if (o.forcing_max <= 0) o.forcing_max = 1e-2;
   const int n = b.n;
   const int64_t N = b.Ntot;
-  double *R = b.ws, *d = b.ws + N;
   const unsigned nvt = (unsigned)b.vt.size();
   iga_batch_report r{};
   r.t_tune_ms = b.t_tune_ms;
@@ -1175,70 +1442,37 @@ static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in,
   const int chunk = o.check_every > 0 ? std::min(64, (o.check_every + 1) & ~1) : (fdm ? kChunkFdm : kChunkJacobi);
   iga_status st = capture_cg_graph(b, o.jac_prec, chunk, fdm);
   if (st) return st;
-  std::vector<double> nr(n), nr_prev(n, 0.0), r0(n, -1.0), eta(n, o.forcing_max), tgt(n);
-  std::vector<int> act(n, 1), conv(n, 0), nits(n, 0), kits(n, 0);
-  std::vector<std::vector<double>> hist(n);
+  if ((st = capture_step_graph(b, U, o.jac_prec, chunk, fdm))) return st;
+  // device-side Newton state: every instance active, zero correction, no history
+  const double prm[4] = {o.atol, o.rtol, o.forcing_max, (double)o.max_newton};
+  std::vector<int> ones(n, 1), zeros(n, 0);
+  std::vector<double> mone(n, -1.0), fmx(n, o.forcing_max);
+  IGA_HIP_CHECK(hipMemcpyAsync(b.nprm, prm, sizeof(prm), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.act, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.conv, zeros.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.hcount, zeros.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.iters, zeros.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.r0, mone.data(), n * sizeof(double), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.eta, fmx.data(), n * sizeof(double), hipMemcpyHostToDevice, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(b.kstep, zeros.data(), sizeof(int), hipMemcpyHostToDevice, b.bs));
+  hipLaunchKernelGGL(k_b_fill, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, b.ws + N, 0.0);   // d = 0
+  IGA_HIP_CHECK(hipGetLastError());
   hipEvent_t ev[3];
   for (auto &e : ev) IGA_HIP_CHECK(hipEventCreate(&e));
-  IGA_HIP_CHECK(hipMemcpyAsync(b.act, act.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
-  IGA_HIP_CHECK(hipMemsetAsync(b.iters, 0, n * sizeof(int), b.bs));
-  int k;
-  for (k = 0;; ++k) {
+  int k = 0;
+  for (;; ++k) {
+    int ctr[2] = {0, 0};   // active instances, unconverged CG solves
     (void)hipEventRecord(ev[0], b.bs);
-    hipLaunchKernelGGL(k_b_fill, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, R, 0.0);
-    for (const Group &g : b.groups) launch_res(b, g, U, R, b.bs);
-    hipLaunchKernelGGL(k_b_bc_copy, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.act, (const double *)U, R);
-    hipLaunchKernelGGL(k_b_sq_partial, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, (const double *)R, b.partA);
-    hipLaunchKernelGGL(k_b_inst_norms, dim3(std::min(n, 1024)), dim3(256), 0, b.bs, n, b.d_vt_start,
-                       (const double *)b.partA, b.norms);
-    IGA_HIP_CHECK(hipMemcpyAsync(nr.data(), b.norms, n * sizeof(double), hipMemcpyDeviceToHost, b.bs));
+    IGA_HIP_CHECK(hipGraphLaunch(b.step_graph, b.bs));
     (void)hipEventRecord(ev[1], b.bs);
+    IGA_HIP_CHECK(hipMemcpyAsync(&ctr[0], b.nact, sizeof(int), hipMemcpyDeviceToHost, b.bs));
+    IGA_HIP_CHECK(hipMemcpyAsync(&ctr[1], b.count, sizeof(int), hipMemcpyDeviceToHost, b.bs));
     IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
-    r.t_residual_ms += elapsed(ev[0], ev[1]);
-    int nact = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!act[i]) continue;
-      hist[i].push_back(nr[i]);
-      if (r0[i] < 0) r0[i] = nr[i];
-      if (!std::isfinite(nr[i])) { act[i] = 0; continue; }
-      if (nr[i] < o.atol || (o.rtol > 0 && nr[i] <= o.rtol * r0[i])) { act[i] = 0; conv[i] = 1; continue; }
-      if (k >= o.max_newton) { act[i] = 0; continue; }
-      if (k > 0) {
-        double ratio = nr[i] / nr_prev[i];
-        eta[i] = std::min(o.forcing_max, 0.9 * ratio * ratio);
-      }
-      double target = std::max(o.atol, o.rtol * r0[i]);
-      eta[i] = std::min(o.forcing_max, std::max(eta[i], 0.1 * target / nr[i]));
-      nr_prev[i] = nr[i];
-      tgt[i] = eta[i] * nr[i];
-      nits[i] = k + 1;
-      ++nact;
-    }
-    if (nact == 0) break;
-    IGA_HIP_CHECK(hipMemcpyAsync(b.act, act.data(), n * sizeof(int), hipMemcpyHostToDevice, b.bs));
-    IGA_HIP_CHECK(hipMemcpyAsync(b.target, tgt.data(), n * sizeof(double), hipMemcpyHostToDevice, b.bs));
-    (void)hipEventRecord(ev[0], b.bs);
-    for (const Group &g : b.groups) launch_rg(b, g, g.b1, U, b.vals, o.jac_prec, b.bs);
-    if (fdm) {
-      hipLaunchKernelGGL(k_bf_shift, dim3((unsigned)n), dim3(256), 0, b.bs, b.d_pbs, b.d_bf, (const double *)b.bf_pool,
-                         b.d_off, b.act, (const double *)U, b.bf_shift);
-    } else if (o.jac_prec == IGA_FP32) {
-      hipLaunchKernelGGL(k_b_diag_inv<float>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff, b.act,
-                         (const float *)b.vals, b.dinv);
-    } else {
-      hipLaunchKernelGGL(k_b_diag_inv<double>, dim3(nvt), dim3(kVT), 0, b.bs, b.d_pbs, b.d_vt, b.d_off, b.d_noff,
-                         b.act, (const double *)b.vals, b.dinv);
-    }
-    hipLaunchKernelGGL(k_b_cg_init, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)R,
-                       fdm ? nullptr : (const double *)b.dinv, d, b.ws + 2 * N, b.ws + 3 * N, b.ws + 4 * N,
-                       b.partA, b.partC);
-    if (fdm) {
-      launch_bf_apply(b, b.ws + 2 * N, b.ws + 3 * N, nullptr, b.bs);
-      hipLaunchKernelGGL(k_b_pz, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)(b.ws + 2 * N),
-                         (const double *)(b.ws + 3 * N), b.ws + 4 * N, b.partA);
-    }
+    r.graph_launches += 1;
+    r.t_jacobian_ms += elapsed(ev[0], ev[1]);
+    if (ctr[0] == 0) break;
+    int done_iters = chunk, remaining = ctr[1];
     (void)hipEventRecord(ev[1], b.bs);
-    int done_iters = 0, remaining = 1;
     while (done_iters < o.max_krylov && remaining > 0) {
       IGA_HIP_CHECK(hipGraphLaunch(b.graph, b.bs));
       IGA_HIP_CHECK(hipMemcpyAsync(&remaining, b.count, sizeof(int), hipMemcpyDeviceToHost, b.bs));
@@ -1246,15 +1480,18 @@ static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in,
       done_iters += chunk;
       r.graph_launches += 1;
     }
-    r.krylov_iters_max += done_iters;
-    hipLaunchKernelGGL(k_b_axpy, dim3(nvt), dim3(kVT), 0, b.bs, b.d_vt, b.d_off, b.act, (const double *)d, U);
     (void)hipEventRecord(ev[2], b.bs);
     IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
-    r.t_jacobian_ms += elapsed(ev[0], ev[1]);
     r.t_krylov_ms += elapsed(ev[1], ev[2]);
+    r.krylov_iters_max += done_iters;
   }
-  std::vector<int> dev_iters(n);
+  std::vector<int> dev_iters(n), conv(n), hcount(n);
+  std::vector<double> r0(n), hist((size_t)n * kHist);
   IGA_HIP_CHECK(hipMemcpyAsync(dev_iters.data(), b.iters, n * sizeof(int), hipMemcpyDeviceToHost, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(conv.data(), b.conv, n * sizeof(int), hipMemcpyDeviceToHost, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(hcount.data(), b.hcount, n * sizeof(int), hipMemcpyDeviceToHost, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(r0.data(), b.r0, n * sizeof(double), hipMemcpyDeviceToHost, b.bs));
+  IGA_HIP_CHECK(hipMemcpyAsync(hist.data(), b.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, b.bs));
   IGA_HIP_CHECK(hipStreamSynchronize(b.bs));
   for (auto &e : ev) (void)hipEventDestroy(e);
   r.newton_steps = k;
@@ -1264,10 +1501,10 @@ static iga_status batch_newton(Batch &b, double *U, const iga_newton_opts *o_in,
     if (items) {
       iga_batch_item_report &it = items[b.perm_[kk]];
       it.converged = conv[kk];
-      it.newton_iters = (int)hist[kk].size() - 1;
+      it.newton_iters = hcount[kk] - 1;
       it.krylov_iters = dev_iters[kk];
       it.res_norm0 = r0[kk];
-      it.res_norm = hist[kk].empty() ? 0.0 : hist[kk].back();
+      it.res_norm = hcount[kk] > 0 ? hist[(size_t)kk * kHist + std::min(hcount[kk], kHist) - 1] : 0.0;
     }
   }
   r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

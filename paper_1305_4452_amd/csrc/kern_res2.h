@@ -19,11 +19,12 @@ namespace rst {
 
 constexpr int kThreads = 256;
 
-// elements per tile side: TE * Q = 40 Gauss points per axis
-template <int P>
+// elements per tile side: TE * Q = 40 Gauss points per axis (V = 0), or about 20 (V = 1: less idle work
+// on small meshes; the batched solver picks per degree and size class by timing both)
+template <int P, int VS = 0>
 struct Res2 {
   static constexpr int p = P - 1, Q = P;
-  static constexpr int TE = 40 / Q;
+  static constexpr int TE = (VS ? 20 : 40) / Q;
   static constexpr int NI = TE + p, G = TE * Q;
   // doubles: sU, sF [NI][NI]; V, D, VF [NI][G]; F0, F1, S [G][G]; the tile's basis values and
   // derivatives [axis][B|dB][G][P] and quadrature weights [axis][G]
@@ -39,10 +40,10 @@ __host__ __device__ inline int res2_tiles(int ne0, int ne1, int TE) {
   return ((ne0 + TE - 1) / TE) * ((ne1 + TE - 1) / TE);
 }
 
-template <int P>
+template <int P, int VS = 0>
 __device__ inline void res2_body(const DevProblem &pb, const int tile, const double *__restrict__ U,
                                  double *__restrict__ R, double *__restrict__ lds) {
-  using S_ = Res2<P>;
+  using S_ = Res2<P, VS>;
   constexpr int p = S_::p, Q = S_::Q, TE = S_::TE, NI = S_::NI, G = S_::G;
   const int n0 = pb.n[0], ne0 = pb.ne[0], ne1 = pb.ne[1];
   const int nt0 = (ne0 + TE - 1) / TE;

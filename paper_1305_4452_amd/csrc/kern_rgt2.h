@@ -24,24 +24,34 @@ namespace rgt {
 constexpr int kThreads = 256;
 
 // Tile shape per P = p + 1: B1 * (2p + 1) <= 64 (one lane per pair) and (T0 + p) * Q <= 64 (one
-// lane per Gauss point along axis 0).
-template <int P>
+// lane per Gauss point along axis 0).  V = 0: the largest such tiles; V = 1: tiles of about half the
+// rows per axis (less idle work on small meshes; the batched solver picks per degree and size class
+// by timing both).
+template <int P, int VS = 0>
 struct Shape2;
 template <>
-struct Shape2<2> { static constexpr int B1 = 21, T0 = 24; };
+struct Shape2<2, 0> { static constexpr int B1 = 21, T0 = 24; };
 template <>
-struct Shape2<3> { static constexpr int B1 = 12, T0 = 19; };
+struct Shape2<3, 0> { static constexpr int B1 = 12, T0 = 19; };
 template <>
-struct Shape2<4> { static constexpr int B1 = 9, T0 = 12; };
+struct Shape2<4, 0> { static constexpr int B1 = 9, T0 = 12; };
 template <>
-struct Shape2<5> { static constexpr int B1 = 7, T0 = 8; };
+struct Shape2<5, 0> { static constexpr int B1 = 7, T0 = 8; };
+template <>
+struct Shape2<2, 1> { static constexpr int B1 = 10, T0 = 12; };
+template <>
+struct Shape2<3, 1> { static constexpr int B1 = 6, T0 = 10; };
+template <>
+struct Shape2<4, 1> { static constexpr int B1 = 5, T0 = 6; };
+template <>
+struct Shape2<5, 1> { static constexpr int B1 = 4, T0 = 4; };
 
 constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
-template <int P, typename CT, typename OT>
+template <int P, typename CT, typename OT, int VS = 0>
 struct Lds2 {
   static constexpr int p = P - 1, Q = P, W = 2 * p + 1;
-  static constexpr int B1 = Shape2<P>::B1, T0 = Shape2<P>::T0;
+  static constexpr int B1 = Shape2<P, VS>::B1, T0 = Shape2<P, VS>::T0;
   static constexpr int NPAIR = B1 * W;
   static constexpr int G0M = (T0 + p) * Q, G1M = (B1 + p) * Q;
   static constexpr int SP = G0M + 1;   // odd pitch of Sm rows (lanes = pairs read one column)
@@ -60,10 +70,10 @@ struct Lds2 {
 // number of tiles of one problem
 __host__ __device__ inline int rgt2_tiles_0(int n0, int T0) { return (n0 + T0 - 1) / T0; }
 
-template <int P, typename CT, typename OT>
+template <int P, typename CT, typename OT, int VS = 0>
 __device__ inline void rgt2_body(const DevProblem &pb, const int tile, const double *__restrict__ U,
                                  OT *__restrict__ vals, char *__restrict__ lds) {
-  using L = Lds2<P, CT, OT>;
+  using L = Lds2<P, CT, OT, VS>;
   constexpr int p = L::p, Q = L::Q, W = L::W, B1 = L::B1, T0 = L::T0;
   constexpr int NW = kThreads / 64;
   const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1];
