@@ -259,26 +259,50 @@ def bench_fourth_order():
     out["cahn_hilliard_256_p2_periodic"] = dict(ndof=g.N, nelem=g.E, ms=ms, elements_per_s=g.E / (ms * 1e-3))
     print(f"[bench] Cahn-Hilliard residual 256^3 p=2 periodic: {ms:.2f} ms", file=sys.stderr, flush=True)
     del g, C, Cd, R
-    # generalized-alpha steps of Cahn-Hilliard on 256^2 C^1 quadratics, periodic (rho_inf = 0.5, dt = 1e-6)
-    patch = inputs.unit_box(2, 256, 2)
-    g = iga.IGA(patch.knots, patch.degree, periodic=[1, 1])
-    C = torch.as_tensor(0.5 + 0.05 * inputs.uniform(31, 0, g.N, -1.0, 1.0), device="cuda")
-    V = torch.zeros_like(C)
-    C1, V1 = torch.empty_like(C), torch.empty_like(C)
-    steps, newton, krylov = 3, 0, 0
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
-        rep = g.ch_gen_alpha_step(C, V, 1e-6, 0.5, 1.5, 1.0 / 256 ** 2, C1, V1, atol=1e-9)
-        newton += rep["newton_iters"]
-        krylov += rep["krylov_iters_total"]
-        C, V, C1, V1 = C1, V1, C, V
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t) / steps * 1e3
-    out["cahn_hilliard_gen_alpha_256x256_p2"] = dict(ndof=g.N, ms_per_step=ms, newton_iters_per_step=newton / steps,
-                                                     bicgstab_iters_per_step=krylov / steps)
-    print(f"[bench] Cahn-Hilliard generalized-alpha 256^2 p=2: {ms:.1f} ms/step ({newton / steps:.1f} Newton, "
-          f"{krylov / steps:.1f} BiCGStab its)", file=sys.stderr, flush=True)
+    out.update(bench_ch_steps())
+    return out
+
+
+def bench_ch_steps(steps: int = 3):
+    """Generalized-alpha steps of Cahn-Hilliard (rho_inf = 0.5, theta = 1.5, lambda = 1 / nel^2) on
+    C^1 quadratics with every axis periodic: 256^2 and the paper's 256^3 mesh, from c = 0.5 plus a
+    seeded 5% perturbation, at dt = 1e-6 and 1e-5; BiCGStab right-preconditioned by fast
+    diagonalisation (the default) and without a preconditioner."""
+    import torch
+
+    import inputs
+    import paper_1305_4452_amd as iga
+    out = {}
+    for dim, key in ((2, "cahn_hilliard_gen_alpha_256x256_p2"), (3, "cahn_hilliard_gen_alpha_256cube_p2")):
+        nel = 256
+        patch = inputs.unit_box(dim, nel, 2)
+        res = {}
+        for dt in (1e-6, 1e-5):
+            for mode, mname in ((iga.IGA_PRECOND_AUTO, "fdm"), (iga.IGA_PRECOND_JACOBI, "none")):
+                g = iga.IGA(patch.knots, patch.degree, periodic=[1] * dim)
+                g.set_option(iga.IGA_OPT_PRECOND, mode)
+                C = torch.as_tensor(0.5 + 0.05 * inputs.uniform(31, 0, g.N, -1.0, 1.0), device="cuda")
+                V = torch.zeros_like(C)
+                C1, V1 = torch.empty_like(C), torch.empty_like(C)
+                g.ch_gen_alpha_step(C, V, dt, 0.5, 1.5, 1.0 / nel ** 2, C1, V1, atol=1e-9)   # set-up, warm-up
+                newton = krylov = 0
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(steps):
+                    rep = g.ch_gen_alpha_step(C, V, dt, 0.5, 1.5, 1.0 / nel ** 2, C1, V1, atol=1e-9)
+                    newton += rep["newton_iters"]
+                    krylov += rep["krylov_iters_total"]
+                    C, V, C1, V1 = C1, V1, C, V
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t) / steps * 1e3
+                res[f"dt{dt:g}_{mname}"] = dict(ms_per_step=ms, newton_iters_per_step=newton / steps,
+                                                bicgstab_iters_per_step=krylov / steps)
+                print(f"[bench] Cahn-Hilliard generalized-alpha {nel}^{dim} p=2 dt={dt:g} precond={mname}: "
+                      f"{ms:.1f} ms/step ({newton / steps:.1f} Newton, {krylov / steps:.1f} BiCGStab its)",
+                      file=sys.stderr, flush=True)
+                del g, C, V, C1, V1
+        res["ndof"] = nel ** dim
+        out[key] = res
     return out
 
 
@@ -546,14 +570,15 @@ def main():
     ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--no-fourth-order", action="store_true")
     ap.add_argument("--no-gen-alpha", action="store_true")
+    ap.add_argument("--ch-only", action="store_true", help="run only the Cahn-Hilliard step section")
     ap.add_argument("--learned-train", type=int, default=2000, help="0 skips the learned-guess section")
     ap.add_argument("--learned-test", type=int, default=300)
     ap.add_argument("--learned-epochs", type=int, default=12)
     ap.add_argument("--cyl-nel", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "single-GPU program: --gpus must be 1 (no sharded path is implemented)",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
@@ -573,6 +598,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
+    if args.ch_only:
+        print(json.dumps({"cahn_hilliard_steps": bench_ch_steps()}))
+        return
     torch.cuda.set_device(0)
     if args.kernels_only_cylinder:
         wc = inputs.config_cylinder(nel=args.cyl_nel, p=args.kernels_only_cylinder)

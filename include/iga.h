@@ -204,11 +204,18 @@ iga_status iga_cahn_hilliard_residual(iga_t h, const double *C_dev, const double
  * iga_cahn_hilliard_residual; theta, lambda_ch as there).  C0_dev, V0_dev: c and its rate at t_n;
  * C1_dev, V1_dev (outputs, not aliasing the inputs): at t_n + dt.  Newton on cdot_{n+1} from
  * cdot_n; each linear system by BiCGStab (the Jacobian is not symmetric) on Jacobian-vector products
- * by a forward difference of the residual (the matrix-free approach of Sec. 2.8), step
- * sqrt(eps) (1 + ||c_{n+af}||) / ||x||; stops when ||G||_2 < opts->atol.  opts: atol, rtol,
- * max_newton, max_krylov (BiCGStab iterations per Newton step), forcing_max; NULL: defaults.  BiCGStab
- * keeps its scalars on the device and the host tests its residual norm every 4 iterations; the report
- * counts the iterations that changed the iterate.
+ * by a forward difference of the residual (the matrix-free approach of Sec. 2.8): the residual is
+ * linear in cdot, so the step moves c by sqrt(eps) (1 + ||c_{n+af}||) along the direction.  Stops
+ * when ||G||_2 < opts->atol.  opts: atol, rtol, max_newton, max_krylov (BiCGStab iterations per
+ * Newton step), forcing_max; NULL: defaults.  BiCGStab keeps its scalars on the device and the host
+ * tests its residual norm every 4 iterations (every iteration when preconditioned); the report
+ * counts the iterations that changed the iterate.  With every axis periodic on uniform knots and at
+ * most 256 functions per axis, BiCGStab is right-preconditioned by fast diagonalisation of
+ * am M + af gamma dt (a K + lambda_ch b B) (M, K the mass and stiffness matrices,
+ * B = int Lap N_A Lap N_B, a = 1/(2 theta) - 2 b and b the mean of c (1 - c) over the
+ * coefficients: the Jacobian linearised about a uniform state), its 1D eigenbases built at the
+ * first call; IGA_OPT_PRECOND = IGA_PRECOND_JACOBI turns it off (the difference products give no
+ * diagonal, so no other preconditioner is used).
  * Same geometry limits as iga_cahn_hilliard_residual.  IGA_ENOCONV if Newton or BiCGStab fails.
  * Synchronous. */
 iga_status iga_ch_gen_alpha_step(iga_t h, const double *C0_dev, const double *V0_dev, double dt, double rho_inf,

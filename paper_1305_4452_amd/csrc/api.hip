@@ -409,12 +409,13 @@ __global__ void __launch_bounds__(256) k_bcg_s(int64_t n, const double *__restri
   }
 }
 
-// x += alpha p + omega s, r = s - omega t, omega = (t, s) / (t, t) (0 when t = 0, i.e. s = 0);
-// partials of ||r||^2 and (rh, r)
+// x += alpha ph + omega sh, r = s - omega t, omega = (t, s) / (t, t) (0 when t = 0, i.e. s = 0);
+// partials of ||r||^2 and (rh, r).  ph, sh: the preconditioned p and s (p and s without one)
 __global__ void __launch_bounds__(256) k_bcg_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ s,
                                                 const double *__restrict__ t, const double *__restrict__ rh,
                                                 double *__restrict__ x, double *__restrict__ r, double *__restrict__ S,
-                                                double tol, double *__restrict__ part, double *__restrict__ part2) {
+                                                double tol, double *__restrict__ part, double *__restrict__ part2,
+                                                const double *__restrict__ ph, const double *__restrict__ sh_) {
   __shared__ double sh[4];
   const bool live = !(S[kRes] <= tol);
   const double tt = S[kTt], om = tt > 0 ? S[kTs] / tt : 0.0, al = S[kAlpha];
@@ -422,7 +423,7 @@ __global__ void __launch_bounds__(256) k_bcg_xr(int64_t n, const double *__restr
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double ri = r[i];
     if (live) {
-      x[i] += al * p[i] + om * s[i];
+      x[i] += al * ph[i] + om * sh_[i];
       ri = s[i] - om * t[i];
       r[i] = ri;
     }
@@ -476,6 +477,22 @@ __global__ void __launch_bounds__(256) k_diffq(int64_t n, const double *__restri
   }
 }
 
+// partials of sum x and sum x^2
+__global__ void __launch_bounds__(256) k_moments(int64_t n, const double *__restrict__ x, double *__restrict__ part,
+                                                 double *__restrict__ part2) {
+  __shared__ double sh[4];
+  double a1 = 0, a2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    a1 += x[i];
+    a2 += x[i] * x[i];
+  }
+  const double b1 = block_sum(a1, sh), b2 = block_sum(a2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = b1;
+    part2[blockIdx.x] = b2;
+  }
+}
+
 static iga_status host_scalar(Handle &h, const double *dev, double *out, int n = 1) {
   if (hipMemcpyAsync(out, dev, n * sizeof(double), hipMemcpyDeviceToHost, h.stream) != hipSuccess ||
       hipStreamSynchronize(h.stream) != hipSuccess)
@@ -501,17 +518,25 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
   iga_status st;
   if ((st = ensure_newton_ws(h, false, IGA_FP64))) return st;
   const int64_t N = h.pb.N;
+  if ((st = ensure_chfdm(h))) return st;
+  const bool pc = h.chfdm_ok && h.precond != IGA_PRECOND_JACOBI;
   if (!h.chw && (st = alloc_owned(h, (void **)&h.chw, (size_t)13 * N * sizeof(double)))) return st;
+  if (pc && !h.chw_pc && (st = alloc_owned(h, (void **)&h.chw_pc, (size_t)4 * N * sizeof(double)))) return st;
   double *Ca = h.chw, *Va = Ca + N, *G = Va + N, *Gp = G + N, *tC = Gp + N, *tV = tC + N;
   double *x = tV + N, *r = x + N, *rh = r + N, *p = rh + N, *v = p + N, *sv = v + N;
   double *t = sv + N;
+  // right preconditioning: the iteration runs on A P^-1 with ph = P^-1 p and sh = P^-1 s
+  double *ph = pc ? h.chw_pc : p, *sh = pc ? h.chw_pc + N : sv, *w1 = pc ? h.chw_pc + 2 * N : nullptr,
+         *w2 = pc ? w1 + N : nullptr;
   const unsigned nb = ga_blocks(N);
   iga_newton_report rr{};
   auto t0 = std::chrono::steady_clock::now();
   IGA_HIP_CHECK(hipMemcpyAsync(V1, V0, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
-  double ca_norm = 0;
-  // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV), step
-  // sqrt(eps_machine) (1 + ||c_{n+af}||) / ||y|| with ||y|| = *yn on the device
+  double ca_norm = 0, cmom[2] = {0, 0};
+  // A y: forward difference of the stage residual along y (writes out; uses Gp, tC, tV).  The
+  // residual is linear in cdot, so only the change of c needs a small step: c moves by
+  // sqrt(eps_machine) (1 + ||c_{n+af}||) along y / ||y|| (||y|| = *yn on the device), which is
+  // a step K / ||y|| in cdot with K = sqrt(eps_machine) (1 + ||c_{n+af}||) / (af gamma dt).
   double K = 0;
   // with the partials of (a, out) in P1 and, when both is set, of (out, out) in P2
   const int nbv = vec_blocks(N, h.npartials);
@@ -527,7 +552,9 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
     return IGA_OK;
   };
   double *S = h.scal;
-  constexpr int kCheck = 4;   // iterations between read-backs of the residual norm
+  // iterations between read-backs of the residual norm: preconditioned solves take a few long
+  // iterations, so each is checked (a converged chunk still runs its launches as no-ops)
+  const int kCheck = pc ? 1 : 4;
   double nr = 0, r0 = -1;
   int k;
   st = IGA_OK;
@@ -543,12 +570,25 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
     if (nr < o.atol || (o.rtol > 0 && nr <= o.rtol * r0)) { rr.converged = 1; break; }
     if (k >= o.max_newton) { st = fail(IGA_ENOCONV, "Cahn-Hilliard Newton did not converge"); break; }
     if ((st = launch_norm(h, Ca, h.scal)) || (st = host_scalar(h, h.scal, &ca_norm))) break;
+    // preconditioner coefficients from the means of c and c^2 over the coefficients: linearised
+    // about a uniform state the Jacobian is am M + af gamma dt ((M mu')(c) K + lam M(c) B), with
+    // M mu' = 1 / (2 theta) - 2 c (1 - c); the state's mean of c (1 - c) stands in for c (1 - c)
+    double sa = 0, sb = 0;
+    if (pc) {
+      hipLaunchKernelGGL(k_moments, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)Ca, P1, P2);
+      if ((st = launch_reduce(h, P1, nbv, S + kYn, 0)) || (st = launch_reduce(h, P2, nbv, S + kSn, 0)) ||
+          (st = host_scalar(h, S + kYn, cmom, 2)))
+        break;
+      const double mc = cmom[0] / N, m2 = fmax(0.0, mc - cmom[1] / N);
+      sa = af * gm * dt * (0.5 / theta - 2.0 * m2);
+      sb = af * gm * dt * lam * m2;
+    }
     // BiCGStab on A x = -G from x = 0
     const double tol = fmin(o.forcing_max, fmax(1e-12, 0.1 * o.atol / nr)) * nr;
     if ((st = launch_fill(h, x, N, 0.0)) || (st = launch_fill(h, p, N, 0.0)) || (st = launch_fill(h, v, N, 0.0))) break;
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, -1.0, (const double *)G, 0.0, r);
     hipLaunchKernelGGL(k_axpby, dim3(nb), dim3(256), 0, h.stream, N, 1.0, (const double *)r, 0.0, rh);
-    K = 1.4901161193847656e-8 * (1.0 + ca_norm);
+    K = 1.4901161193847656e-8 * (1.0 + ca_norm) / (af * gm * dt);
     hipLaunchKernelGGL(k_bcg_init, dim3(1), dim3(1), 0, h.stream, S, nr);
     if ((st = launch_dot(h, rh, r, S + kRho))) break;
     double chk[3] = {nr, 0, 0};   // residual norm, iterations taken, rho
@@ -556,16 +596,25 @@ static iga_status ch_gen_alpha_step(Handle &h, const double *C0, const double *V
       for (int j = 0; j < kCheck && launched < o.max_krylov; ++j, ++launched) {
         hipLaunchKernelGGL(k_bcg_p, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, p,
                            (const double *)S, tol, P1);
-        if ((st = launch_reduce(h, P1, nbv, S + kYn, 1)) || (st = apply(p, v, S + kYn, rh, false)) ||
-            (st = launch_reduce(h, P1, nbv, S + kRhv, 0)))
+        if (pc) {
+          if ((st = launch_chfdm_apply(h, p, ph, w1, w2, am, sa, sb)) || (st = launch_norm(h, ph, S + kYn))) break;
+        } else if ((st = launch_reduce(h, P1, nbv, S + kYn, 1))) {
           break;
+        }
+        if ((st = apply(ph, v, S + kYn, rh, false)) || (st = launch_reduce(h, P1, nbv, S + kRhv, 0))) break;
         hipLaunchKernelGGL(k_bcg_s, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)r, (const double *)v, sv, S,
                            tol, P1);
-        if ((st = launch_reduce(h, P1, nbv, S + kSn, 1)) || (st = apply(sv, t, S + kSn, sv, true)) ||
-            (st = launch_reduce(h, P1, nbv, S + kTs, 0)) || (st = launch_reduce(h, P2, nbv, S + kTt, 0)))
+        if (pc) {
+          if ((st = launch_chfdm_apply(h, sv, sh, w1, w2, am, sa, sb)) || (st = launch_norm(h, sh, S + kSn))) break;
+        } else if ((st = launch_reduce(h, P1, nbv, S + kSn, 1))) {
+          break;
+        }
+        if ((st = apply(sh, t, S + kSn, sv, true)) || (st = launch_reduce(h, P1, nbv, S + kTs, 0)) ||
+            (st = launch_reduce(h, P2, nbv, S + kTt, 0)))
           break;
         hipLaunchKernelGGL(k_bcg_xr, dim3(nbv), dim3(256), 0, h.stream, N, (const double *)p, (const double *)sv,
-                           (const double *)t, (const double *)rh, x, r, S, tol, P1, P2);
+                           (const double *)t, (const double *)rh, x, r, S, tol, P1, P2, (const double *)ph,
+                           (const double *)sh);
         if ((st = launch_reduce(h, P1, nbv, S + kRes, 1)) || (st = launch_reduce(h, P2, nbv, S + kRho, 0))) break;
       }
       if (st) break;

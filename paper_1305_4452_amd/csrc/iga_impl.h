@@ -173,6 +173,13 @@ struct Handle {
   int precond = IGA_PRECOND_AUTO;
   int fdm_tried = 0;              // build attempted (lazily, by the first Newton solve that uses it)
   std::vector<double> hsepM[3], hsepA[3];   // host copies of the 1D band matrices
+  std::vector<double> hsepH[3];              // ... and of the second-derivative one, sum w B_i'' B_j''
+  // Cahn-Hilliard fast diagonalisation (every axis periodic on uniform knots): per axis the
+  // transforms V^T, V of A V = M V diag(mu), V^T M V = I, and eta = diag(V^T H V) (H is diagonal in
+  // the same basis on uniform periodic knots, where A, M and H are circulant); built lazily
+  int chfdm_tried = 0, chfdm_ok = 0;
+  const double *ch_Tf[3] = {}, *ch_Tb[3] = {}, *ch_mu[3] = {}, *ch_eta[3] = {};
+  double *chw_pc = nullptr;                  // 2 N scratch of its transforms
   // per-kernel timing (IGA_OPT_KERNEL_TIMING): event pairs of up to kMaxTimed kernels for each
   // of the last kTimedCalls Jacobian assemblies (a ring)
   static constexpr int kMaxTimed = 4, kTimedCalls = 64;
@@ -241,6 +248,10 @@ iga_status launch_residual(Handle &h, const double *U, double *R);
 iga_status launch_linearize(Handle &h, const double *U);
 iga_status launch_biharmonic(Handle &h, const double *U, double *R);
 iga_status launch_grad_laplacian(Handle &h, const double *U, double *R);
+// Cahn-Hilliard preconditioner: z = P^{-1} r with P = am M + s (a K + b B) (see precond.hip)
+iga_status ensure_chfdm(Handle &h);
+iga_status launch_chfdm_apply(Handle &h, const double *r, double *z, double *w1, double *w2, double am, double sa,
+                              double sb);
 // sum over `width` lanes of a wavefront (all of them get it)
 __device__ inline double warp_sum(double v, int width) {
   for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, width);

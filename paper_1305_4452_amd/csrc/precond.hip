@@ -352,7 +352,17 @@ iga_status ensure_fdm(Handle &h) {
 // ---------------------------------------------------------------------------------------------
 namespace {
 
-constexpr int kTC = 16;   // columns per block of a 1D transform
+constexpr int kTC = 16;   // columns per block of a 1D transform (8 for the Cahn-Hilliard transforms of up to 256)
+
+// Eigenvalue of the Cahn-Hilliard preconditioner am M + sa K + sb B in the product basis: with
+// V^T M V = I, V^T A V = diag(mu), V^T H V = diag(eta) per axis, M = M0 M1 M2, K = sum_d A_d (x) M (x) M
+// and B = sum_d H_d (x) M (x) M + 2 sum_{d<e} A_d (x) A_e (x) M (Laplacians of tensor products; on
+// periodic axes int B_i'' B_j = -A_ij), it is am + sa sum mu + sb (sum eta + 2 sum_{d<e} mu_d mu_e),
+// kept at least 0.05 am (the linearisation about the mean can lose definiteness inside the spinodal).
+struct ChScale {
+  const double *eta0, *eta1, *eta2;
+  double am, sa, sb;
+};
 
 struct BoxView {
   int64_t off, s0, s1, s2;   // element (i0,i1,i2) of the box at off + i0 s0 + i1 s1 + i2 s2
@@ -361,11 +371,12 @@ struct BoxView {
 // out(.., i, ..) = sum_k T[i m + k] in(.., k, ..) along axis AX of the box m0 x m1 x m2; the
 // other two axes form the columns, kTC columns per block, staged in LDS.  With mu != null the
 // result is divided by mu0[i0] + mu1[i1] + mu2[i2] + shift.
-template <int AX>
+template <int AX, int kTC = kTC>
 __global__ void __launch_bounds__(256) k_fdm_axis(const double *__restrict__ in, BoxView vi, double *__restrict__ out,
                                                   BoxView vo, const double *__restrict__ T, int m0, int m1, int m2,
                                                   const double *__restrict__ mu0, const double *__restrict__ mu1,
-                                                  const double *__restrict__ mu2, const double *__restrict__ shift) {
+                                                  const double *__restrict__ mu2, const double *__restrict__ shift,
+                                                  ChScale chs = ChScale{}) {
   extern __shared__ double lds[];
   const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
   const int ca = AX == 0 ? m1 : m0;                       // faster column axis extent
@@ -398,14 +409,21 @@ __global__ void __launch_bounds__(256) k_fdm_axis(const double *__restrict__ in,
     y[(size_t)i * (kTC + 1) + cl] = s;
   }
   __syncthreads();
-  const double c_shift = mu0 ? *shift : 0.0;
+  const double c_shift = (mu0 && shift) ? *shift : 0.0;   // the Cahn-Hilliard scaling passes no shift
   for (int e = t; e < m * kTC; e += 256) {
     const int i = AX == 0 ? e % m : e / kTC, cl2 = AX == 0 ? e / m : e % kTC, c = c0 + cl2;
     if (c >= ncol) continue;
     int i0, i1, i2;
     coords(i, c, i0, i1, i2);
     double v = y[(size_t)i * (kTC + 1) + cl2];
-    if (mu0) v /= mu0[i0] + mu1[i1] + (mu2 ? mu2[i2] : 0.0) + c_shift;
+    if (chs.eta0) {
+      const double a0 = mu0[i0], a1 = mu1[i1], a2 = mu2[i2];
+      const double lam = chs.am + chs.sa * (a0 + a1 + a2) +
+                         chs.sb * (chs.eta0[i0] + chs.eta1[i1] + chs.eta2[i2] + 2.0 * (a0 * a1 + a0 * a2 + a1 * a2));
+      v /= fmax(lam, 0.05 * chs.am);
+    } else if (mu0) {
+      v /= mu0[i0] + mu1[i1] + (mu2 ? mu2[i2] : 0.0) + c_shift;
+    }
     out[vo.off + i0 * vo.s0 + i1 * vo.s1 + i2 * vo.s2] = v;
   }
 }
@@ -471,7 +489,117 @@ void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView v
                      vo, T, m[0], m[1], m[2], mu0, mu1, mu2, shift);
 }
 
+template <int AX>
+void launch_ch_axis(Handle &h, const double *in, double *out, const double *T, const int *m, const double *const *mu,
+                    ChScale chs) {
+  constexpr int TC = 8;
+  const int mm = m[AX];
+  const int ncol = AX == 0 ? m[1] * m[2] : (AX == 1 ? m[0] * m[2] : m[0] * m[1]);
+  const size_t lds = 2 * (size_t)mm * (TC + 1) * sizeof(double);
+  const BoxView box{0, 1, m[0], (int64_t)m[0] * m[1]};
+  hipLaunchKernelGGL((k_fdm_axis<AX, TC>), dim3((unsigned)((ncol + TC - 1) / TC)), dim3(256), lds, h.stream, in, box,
+                     out, box, T, m[0], m[1], m[2], mu ? mu[0] : nullptr, mu ? mu[1] : nullptr, mu ? mu[2] : nullptr,
+                     nullptr, chs);
+}
+
 }  // namespace
+
+// Cahn-Hilliard fast diagonalisation: every axis periodic, x = xi without weights, at most 256
+// functions per axis, and the second-derivative matrix diagonal in the (A, M) eigenbasis (uniform
+// knots); otherwise chfdm_ok stays 0 and the Krylov solve runs without a preconditioner.  In 2D
+// the third axis has one function with mu = eta = 0.
+iga_status ensure_chfdm(Handle &h) {
+  if (h.chfdm_tried) return IGA_OK;
+  h.chfdm_tried = 1;
+  const DevProblem &pb = h.pb;
+  if (pb.dim < 2 || pb.ctrl || pb.wts) return IGA_OK;
+  const int p = pb.p, W = 2 * p + 1;
+  if (pb.dim == 2) {
+    const double zero = 0.0;
+    double *dz;
+    iga_status st;
+    if ((st = upload_owned(h, &dz, &zero, 1))) return st;
+    h.ch_mu[2] = h.ch_eta[2] = dz;
+  }
+  for (int d = 0; d < pb.dim; ++d) {
+    const int n = pb.n[d];
+    if (!pb.ax[d].nper || n > 256 || h.hsepH[d].empty()) return IGA_OK;
+    std::vector<double> A((size_t)n * n, 0.0), M((size_t)n * n, 0.0), H((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int o = 0; o < W; ++o) {
+        const int j = ((i + o - p) % n + n) % n;
+        A[(size_t)i * n + j] += h.hsepA[d][(size_t)i * W + o];
+        M[(size_t)i * n + j] += h.hsepM[d][(size_t)i * W + o];
+        H[(size_t)i * n + j] += h.hsepH[d][(size_t)i * W + o];
+      }
+    int same = -1;
+    for (int e = 0; e < d && same < 0; ++e)
+      if (pb.n[e] == n && h.hsepM[e] == h.hsepM[d] && h.hsepA[e] == h.hsepA[d] && h.hsepH[e] == h.hsepH[d]) same = e;
+    if (same >= 0) {
+      h.ch_Tf[d] = h.ch_Tf[same];
+      h.ch_Tb[d] = h.ch_Tb[same];
+      h.ch_mu[d] = h.ch_mu[same];
+      h.ch_eta[d] = h.ch_eta[same];
+      continue;
+    }
+    std::vector<double> V, mu;
+    if (!gen_eigen(A, M, n, V, mu)) return IGA_OK;
+    // eta = diag(V^T H V); the off-diagonal part must vanish (relative to the largest eta)
+    std::vector<double> HV((size_t)n * n, 0.0), eta(n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) {
+        const double hik = H[(size_t)i * n + k];
+        if (hik == 0.0) continue;
+        for (int c = 0; c < n; ++c) HV[(size_t)i * n + c] += hik * V[(size_t)k * n + c];
+      }
+    double emax = 0, off = 0;
+    for (int a = 0; a < n; ++a)
+      for (int c = 0; c < n; ++c) {
+        double s = 0;
+        for (int i = 0; i < n; ++i) s += V[(size_t)i * n + a] * HV[(size_t)i * n + c];
+        if (a == c) { eta[a] = s; emax = fmax(emax, fabs(s)); }
+        else off = fmax(off, fabs(s));
+      }
+    if (!(off <= 1e-8 * emax)) return IGA_OK;
+    std::vector<double> Tf((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) Tf[(size_t)i * n + k] = V[(size_t)k * n + i];
+    double *dTf, *dTb, *dmu, *deta;
+    iga_status st;
+    if ((st = upload_owned(h, &dTf, Tf.data(), Tf.size())) || (st = upload_owned(h, &dTb, V.data(), V.size())) ||
+        (st = upload_owned(h, &dmu, mu.data(), mu.size())) || (st = upload_owned(h, &deta, eta.data(), eta.size())))
+      return st;
+    h.ch_Tf[d] = dTf;
+    h.ch_Tb[d] = dTb;
+    h.ch_mu[d] = dmu;
+    h.ch_eta[d] = deta;
+  }
+  h.chfdm_ok = 1;
+  return IGA_OK;
+}
+
+iga_status launch_chfdm_apply(Handle &h, const double *r, double *z, double *w1, double *w2, double am, double sa,
+                              double sb) {
+  const int m[3] = {h.pb.n[0], h.pb.n[1], h.pb.n[2]};
+  const ChScale none{};
+  const ChScale chs{h.ch_eta[0], h.ch_eta[1], h.ch_eta[2], am, sa, sb};
+  if (h.pb.dim == 2) {
+    launch_ch_axis<0>(h, r, w1, h.ch_Tf[0], m, nullptr, none);
+    launch_ch_axis<1>(h, w1, w2, h.ch_Tf[1], m, h.ch_mu, chs);
+    launch_ch_axis<1>(h, w2, w1, h.ch_Tb[1], m, nullptr, none);
+    launch_ch_axis<0>(h, w1, z, h.ch_Tb[0], m, nullptr, none);
+    IGA_HIP_CHECK(hipGetLastError());
+    return IGA_OK;
+  }
+  launch_ch_axis<0>(h, r, w1, h.ch_Tf[0], m, nullptr, none);
+  launch_ch_axis<1>(h, w1, w2, h.ch_Tf[1], m, nullptr, none);
+  launch_ch_axis<2>(h, w2, w1, h.ch_Tf[2], m, h.ch_mu, chs);
+  launch_ch_axis<2>(h, w1, w2, h.ch_Tb[2], m, nullptr, none);
+  launch_ch_axis<1>(h, w2, w1, h.ch_Tb[1], m, nullptr, none);
+  launch_ch_axis<0>(h, w1, z, h.ch_Tb[0], m, nullptr, none);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
 
 iga_status launch_fdm_shift(Handle &h, const double *U, double mass_coef) {
   const int nb = 256;

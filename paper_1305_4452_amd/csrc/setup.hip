@@ -407,7 +407,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   double gx[kMaxP], gw[kMaxP];
   gauss_legendre(pb.Q, gx, gw);
   std::vector<int> stl[3], stw[3];
-  std::vector<double> hostB[3], hostSM[3], hostSA[3];
+  std::vector<double> hostB[3], hostSM[3], hostSA[3], hostSH[3];
   std::vector<int> nbr[3];
   for (int a = 0; a < 3; ++a) {
     if (a >= dim) { pb.n[a] = 1; pb.ne[a] = 1; continue; }
@@ -483,11 +483,12 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     // 1D mass and stiffness in band storage (row i, offset o: column i + o - p, wrapped on a
     // periodic axis), used by the separable kernels and the fast-diagonalisation set-up
     const int P1 = p + 1;
-    std::vector<double> sM((size_t)n * W, 0.0), sA((size_t)n * W, 0.0);
+    std::vector<double> sM((size_t)n * W, 0.0), sA((size_t)n * W, 0.0), sH((size_t)n * W, 0.0);
     std::vector<double> eM(efirst.size() * P1 * P1, 0.0), eA(efirst.size() * P1 * P1, 0.0);
     for (size_t e = 0; e < efirst.size(); ++e)
       for (int q = 0; q < pb.Q; ++q) {
         const double *Bq = &B[(e * pb.Q + q) * (p + 1)], *dBq = &dB[(e * pb.Q + q) * (p + 1)];
+        const double *d2Bq = &d2B[(e * pb.Q + q) * (p + 1)];
         double wgt = wq[e * pb.Q + q];
         for (int ia = 0; ia <= p; ++ia)
           for (int ib = 0; ib <= p; ++ib) {
@@ -495,6 +496,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
             const double m = wgt * Bq[ia] * Bq[ib], k = wgt * dBq[ia] * dBq[ib];
             sM[o] += m;
             sA[o] += k;
+            sH[o] += wgt * d2Bq[ia] * d2Bq[ib];
             eM[(e * P1 + ia) * P1 + ib] += m;
             eA[(e * P1 + ia) * P1 + ib] += k;
           }
@@ -511,6 +513,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
     pb.elA[a] = d_eA;
     hostSM[a] = sM;
     hostSA[a] = sA;
+    hostSH[a] = sH;
     int *d_ef, *d_stl, *d_stw;
     double *d_B, *d_dB, *d_wq;
     if ((st = dev_upload(*h, &d_ef, efirst.data(), efirst.size())) ||
@@ -576,6 +579,7 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
   for (int a = 0; a < dim; ++a) {
     h->hsepM[a] = hostSM[a];
     h->hsepA[a] = hostSA[a];
+    h->hsepH[a] = hostSH[a];
   }
   double *d_w = nullptr, *d_ctrl = nullptr, *d_kn = nullptr, *d_kel = nullptr, *d_src = nullptr;
   if (d->weights && (st = dev_upload(*h, &d_w, d->weights, (size_t)pb.N))) { iga_destroy((iga_t)h); return st; }
