@@ -80,7 +80,7 @@ def rowgather_flops(n: int, p: int, b1: int, b2: int) -> float:
 # WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device
 # copy (FETCH x2.0, WRITE x1.0); the summary is under profiles/.  Valid only for the kernel source
 # the counters were taken on (SHA-1 of rg_sep.hip); otherwise the traffic is reported as null.
-TRAFFIC = {"src_sha1": "9eba95171154c242ce7d2f817dbd53ab88f86521", "fetch_kib": 130801, "write_kib": 813289,
+TRAFFIC = {"src_sha1": "ea39d02d563e0d9c1c9ea2ab8ae335369d44480c", "fetch_kib": 130359, "write_kib": 813783,
            "fetch_scale": 2.0, "write_scale": 1.0}
 
 
