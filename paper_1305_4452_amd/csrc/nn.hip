@@ -10,6 +10,9 @@
 // Convolutions are cross-correlations; a transposed convolution adds W[ci][co][ky][kx] in
 // at output (iy*s + ky, ix*s + kx).  Parameters are one flat FP32 vector
 // [W0 b0 W1 b1 W2 b2 W3 b3] with W0, W1 as [co][ci][ky][kx] and W2, W3 as [ci][co][ky][kx].
+// Activations are [sample][channel][y][x].  The two 64 -> 64 layers (forward, data gradient, weight
+// gradient) run on the BF16 matrix cores (k_nn_gemm); the thin first and last layers (2 -> 64,
+// 64 -> 1) and the elementwise steps run on the vector units.
 #include <hip/hip_bfloat16.h>
 
 #include <cmath>
@@ -70,21 +73,6 @@ __global__ void k_conv_fwd(int B, const bf16_t *__restrict__ in, const bf16_t *_
       }
     }
   }
-  out[i] = f2bf(s > 0.f ? s : 0.f);
-}
-
-// transposed conv 4x4 stride 4 (64->64): each output pixel has exactly one source pixel
-__global__ void k_convT4_fwd(int B, const bf16_t *__restrict__ in, const bf16_t *__restrict__ W,
-                             const float *__restrict__ bias, bf16_t *__restrict__ out) {
-  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= (long)B * C * H3 * H3) return;
-  int ox = i % H3, oy = (i / H3) % H3, co = (i / (H3 * H3)) % C;
-  long n = i / ((long)C * H3 * H3);
-  int iy = oy >> 2, ix = ox >> 2, ky = oy & 3, kx = ox & 3;
-  float s = bias[co];
-  const bf16_t *ip = in + n * C * H2 * H2 + iy * H2 + ix;
-  const bf16_t *wp = W + co * 16 + ky * 4 + kx;
-  for (int ci = 0; ci < C; ++ci) s += bf2f(wp[ci * C * 16]) * bf2f(ip[ci * H2 * H2]);
   out[i] = f2bf(s > 0.f ? s : 0.f);
 }
 
@@ -230,53 +218,6 @@ __global__ void k_convT2_bwd_data(int B, const float *__restrict__ dy, const bf1
   da3[i] = bf2f(a3[i]) > 0.f ? s : 0.f;
 }
 
-// convT4: da2[n][ci][iy][ix] = sum_{co,ky,kx} W2[ci][co][ky][kx] dz3[n][co][4iy+ky][4ix+kx]
-__global__ void k_convT4_bwd_data(int B, const float *__restrict__ dz3, const bf16_t *__restrict__ W,
-                                  float *__restrict__ dg) {
-  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= (long)B * C * H2 * H2) return;
-  int ix = i % H2, iy = (i / H2) % H2, ci = (i / (H2 * H2)) % C;
-  long n = i / ((long)C * H2 * H2);
-  float s = 0;
-  for (int co = 0; co < C; ++co) {
-    const float *dp = dz3 + ((n * C + co) * H3 + 4 * iy) * H3 + 4 * ix;
-    const bf16_t *wp = W + (ci * C + co) * 16;
-#pragma unroll
-    for (int ky = 0; ky < 4; ++ky)
-#pragma unroll
-      for (int kx = 0; kx < 4; ++kx) s += bf2f(wp[ky * 4 + kx]) * dp[ky * H3 + kx];
-  }
-  dg[i] = s;
-}
-
-// conv (3x3, stride S, pad 1): din[n][ci][iy][ix] = sum_{co,ky,kx} W[co][ci][ky][kx] dout[n][co][oy][ox]
-// with iy = oy*S + ky - 1
-template <int CIN, int HIN, int HOUT, int S>
-__global__ void k_conv_bwd_data(int B, const float *__restrict__ dout, const bf16_t *__restrict__ W,
-                                const bf16_t *__restrict__ ain, float *__restrict__ din) {
-  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= (long)B * CIN * HIN * HIN) return;
-  int ix = i % HIN, iy = (i / HIN) % HIN, ci = (i / (HIN * HIN)) % CIN;
-  long n = i / ((long)CIN * HIN * HIN);
-  float s = 0;
-  for (int ky = 0; ky < 3; ++ky) {
-    int t = iy + 1 - ky;
-    if (t < 0 || t % S) continue;
-    int oy = t / S;
-    if (oy >= HOUT) continue;
-    for (int kx = 0; kx < 3; ++kx) {
-      int u = ix + 1 - kx;
-      if (u < 0 || u % S) continue;
-      int ox = u / S;
-      if (ox >= HOUT) continue;
-      const float *dp = dout + (n * C * HOUT + oy) * HOUT + ox;
-      const bf16_t *wp = W + ci * 9 + ky * 3 + kx;
-      for (int co = 0; co < C; ++co) s += bf2f(wp[co * CIN * 9]) * dp[(long)co * HOUT * HOUT];
-    }
-  }
-  din[i] = bf2f(ain[i]) > 0.f ? s : 0.f;
-}
-
 // ---- weight gradients: one block per weight, reduction over (n, output pixels) ----
 __device__ inline float block_reduce(float v, float *sh) {
   sh[threadIdx.x] = v;
@@ -313,34 +254,6 @@ __global__ void k_conv_bwd_w(int B, const float *__restrict__ dout, const bf16_t
   }
 }
 
-// convT4: dW2[ci][co][ky][kx] = sum_{n,iy,ix} a2[n][ci][iy][ix] dz3[n][co][4iy+ky][4ix+kx]
-__global__ void k_convT4_bwd_w(int B, const float *__restrict__ dz3, const bf16_t *__restrict__ a2,
-                               float *__restrict__ dW, float *__restrict__ db) {
-  __shared__ float sh[256];
-  const int w = blockIdx.x;
-  const int kx = w % 4, ky = (w / 4) % 4, co = (w / 16) % C, ci = w / (16 * C);
-  const long tot = (long)B * H2 * H2;
-  float s = 0;
-  for (long j = threadIdx.x; j < tot; j += blockDim.x) {
-    int ix = j % H2, iy = (j / H2) % H2;
-    long n = j / (H2 * H2);
-    s += bf2f(a2[((n * C + ci) * H2 + iy) * H2 + ix]) * dz3[((n * C + co) * H3 + 4 * iy + ky) * H3 + 4 * ix + kx];
-  }
-  float r = block_reduce(s, sh);
-  if (threadIdx.x == 0) dW[w] = r;
-  __syncthreads();
-  if (ci == 0 && ky == 0 && kx == 0) {
-    float sb = 0;
-    const long tb = (long)B * H3 * H3;
-    for (long j = threadIdx.x; j < tb; j += blockDim.x) {
-      long n = j / (H3 * H3);
-      sb += dz3[(n * C + co) * H3 * H3 + j % (H3 * H3)];
-    }
-    float rb = block_reduce(sb, sh);
-    if (threadIdx.x == 0) db[co] = rb;
-  }
-}
-
 // convT2: dW3[ci][ky][kx] = sum_{n,iy,ix} a3[n][ci][iy][ix] dy[n][iy+ky][ix+kx]
 __global__ void k_convT2_bwd_w(int B, const float *__restrict__ dy, const bf16_t *__restrict__ a3,
                                float *__restrict__ dW, float *__restrict__ db) {
@@ -363,6 +276,229 @@ __global__ void k_convT2_bwd_w(int B, const float *__restrict__ dy, const bf16_t
     float rb = block_reduce(sb, sh);
     if (threadIdx.x == 0) db[0] = rb;
   }
+}
+
+// ---- matrix-core layers ------------------------------------------------------------------
+// The six large contractions of the network (conv 3x3 s2 and transposed conv 4x4 s4: forward, data
+// gradient, weight gradient) run as implicit GEMMs C[M][N] = sum_k A[m][k] B[k][n] on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  A workgroup of four waves owns a 64 x 64 tile of C
+// and a range of k (the weight gradients split their long k = (sample, pixel) reduction over
+// workgroups and add the partial tiles in a fixed order afterwards).  Per 32-deep step the tile's A
+// and B operands are gathered from the activation / gradient / weight layouts by the layer's loader
+// (zero padding included) into LDS as BF16, A as [m][k] and B as [n][k], so each lane reads its 8
+// consecutive k of one row with one 16-byte load.  Weights and activations are BF16 already;
+// gradients are FP32 and enter as hi = bf16(g), lo = bf16(g - hi) with two products (about 16
+// significant bits, as exact as the FP32 kernels they replace to within the FP32 accumulation).
+// Lane l of a 16 x 16 x 32 product holds A[l % 16][8 (l / 16) + j], B[8 (l / 16) + j][l % 16] (j < 8)
+// and receives D[4 (l / 16) + i][l % 16] (i < 4).
+typedef __bf16 nbf16x8 __attribute__((ext_vector_type(8)));
+typedef float nf32x4 __attribute__((ext_vector_type(4)));
+constexpr int kGT = 64, kGK = 32, kGLD = 40;   // tile side, reduction step, LDS row stride (bf16)
+
+__device__ inline __bf16 raw_bf(bf16_t b) { return __builtin_bit_cast(__bf16, b); }
+
+// gather one 8-deep k segment of a row (A: row m, B: column n) into LDS as hi (and lo) BF16
+template <bool SPLIT, typename F>
+__device__ inline void gather8(F &&get, __bf16 *hi, __bf16 *lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if constexpr (SPLIT) {
+      const float v = get(j);
+      const __bf16 h = (__bf16)v;
+      hi[j] = h;
+      lo[j] = (__bf16)(v - (float)h);
+    } else {
+      hi[j] = get(j);
+    }
+  }
+}
+
+// Op: static SPLIT_A / SPLIT_B (the operand is FP32 and split), a(m, k) / b(k, n) returning float
+// (split) or __bf16, and out(m, n, value, kz).  M, N multiples of 64, K and kchunk multiples of 32.
+template <class Op>
+__global__ void __launch_bounds__(256) k_nn_gemm(Op op, int M, int N, int K, int kchunk) {
+  constexpr bool SA = Op::SPLIT_A, SB = Op::SPLIT_B;
+  __shared__ __align__(16) __bf16 sA[SA ? 2 : 1][kGT][kGLD];
+  __shared__ __align__(16) __bf16 sB[SB ? 2 : 1][kGT][kGLD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+  const int ntn = N / kGT;
+  const int m0 = (blockIdx.x / ntn) * kGT, n0 = (blockIdx.x % ntn) * kGT;
+  const int kz = blockIdx.y, kb = kz * kchunk, ke = min(K, kb + kchunk);
+  nf32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = nf32x4{0.f, 0.f, 0.f, 0.f};
+  const int lr = t >> 2, lk = (t & 3) * 8;   // this thread's loader row and k segment
+  for (int k0 = kb; k0 < ke; k0 += kGK) {
+    gather8<SA>([&](int j) { return op.a(m0 + lr, k0 + lk + j); }, &sA[0][lr][lk], &sA[SA ? 1 : 0][lr][lk]);
+    gather8<SB>([&](int j) { return op.b(k0 + lk + j, n0 + lr); }, &sB[0][lr][lk], &sB[SB ? 1 : 0][lr][lk]);
+    __syncthreads();
+    const int r = lane & 15, kk = 8 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ra = wm * 32 + i * 16 + r;
+      const nbf16x8 ah = *(const nbf16x8 *)&sA[0][ra][kk];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int rb = wn * 32 + j * 16 + r;
+        const nbf16x8 bh = *(const nbf16x8 *)&sB[0][rb][kk];
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i][j], 0, 0, 0);
+        if constexpr (SA) {
+          const nbf16x8 al = *(const nbf16x8 *)&sA[1][ra][kk];
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i][j], 0, 0, 0);
+        }
+        if constexpr (SB) {
+          const nbf16x8 bl = *(const nbf16x8 *)&sB[1][rb][kk];
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        op.out(m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + q, n0 + wn * 32 + j * 16 + (lane & 15), acc[i][j][q], kz);
+}
+
+// conv 3x3 s2 p1 (64 -> 64), 32^2 -> 16^2: m = (n, oy, ox), n = co, k = (ci, ky, kx); ReLU, BF16 out
+struct OpConv1Fwd {
+  static constexpr bool SPLIT_A = false, SPLIT_B = false;
+  const bf16_t *in, *W;
+  const float *bias;
+  bf16_t *out_;
+  __device__ __bf16 a(int m, int k) const {
+    const int s = m >> 8, oy = (m >> 4) & 15, ox = m & 15, ci = k / 9, r = k - 9 * ci, ky = r / 3, kx = r - 3 * ky;
+    const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
+    if (iy < 0 || iy >= H1 || ix < 0 || ix >= H1) return raw_bf(0);
+    return raw_bf(in[(((long)s * C + ci) * H1 + iy) * H1 + ix]);
+  }
+  __device__ __bf16 b(int k, int n) const { return raw_bf(W[n * C * 9 + k]); }
+  __device__ void out(int m, int n, float v, int) const {
+    v += bias[n];
+    out_[((long)(m >> 8) * C + n) * (H2 * H2) + (m & 255)] = f2bf(v > 0.f ? v : 0.f);
+  }
+};
+
+// transposed conv 4x4 s4 (64 -> 64), 16^2 -> 64^2: m = (n, iy, ix), n = (co, ky, kx), k = ci; ReLU
+struct OpConvT4Fwd {
+  static constexpr bool SPLIT_A = false, SPLIT_B = false;
+  const bf16_t *in, *W;
+  const float *bias;
+  bf16_t *out_;
+  __device__ __bf16 a(int m, int k) const { return raw_bf(in[((long)(m >> 8) * C + k) * (H2 * H2) + (m & 255)]); }
+  __device__ __bf16 b(int k, int n) const { return raw_bf(W[k * C * 16 + n]); }
+  __device__ void out(int m, int n, float v, int) const {
+    const int co = n >> 4, ky = (n >> 2) & 3, kx = n & 3, iy = (m >> 4) & 15, ix = m & 15;
+    v += bias[co];
+    out_[(((long)(m >> 8) * C + co) * H3 + 4 * iy + ky) * H3 + 4 * ix + kx] = f2bf(v > 0.f ? v : 0.f);
+  }
+};
+
+// its data gradient: dg[n][ci][iy][ix] = sum_{co,ky,kx} W2[ci][co][ky][kx] dz3[n][co][4iy+ky][4ix+kx]
+// m = (n, iy, ix), n = ci, k = (co, ky, kx)
+struct OpConvT4Data {
+  static constexpr bool SPLIT_A = true, SPLIT_B = false;
+  const float *dz;
+  const bf16_t *W;
+  float *out_;
+  __device__ float a(int m, int k) const {
+    const int co = k >> 4, ky = (k >> 2) & 3, kx = k & 3, iy = (m >> 4) & 15, ix = m & 15;
+    return dz[(((long)(m >> 8) * C + co) * H3 + 4 * iy + ky) * H3 + 4 * ix + kx];
+  }
+  __device__ __bf16 b(int k, int n) const { return raw_bf(W[n * C * 16 + k]); }
+  __device__ void out(int m, int n, float v, int) const { out_[((long)(m >> 8) * C + n) * (H2 * H2) + (m & 255)] = v; }
+};
+
+// its weight gradient: dW2[ci][(co,ky,kx)] = sum_{(n,iy,ix)} g[n][ci][iy][ix] dz3[n][co][4iy+ky][4ix+kx];
+// m = ci, n = (co, ky, kx), k = (n, iy, ix); partial tiles per k chunk
+struct OpConvT4W {
+  static constexpr bool SPLIT_A = false, SPLIT_B = true;
+  const bf16_t *g;
+  const float *dz;
+  float *part;
+  __device__ __bf16 a(int m, int k) const { return raw_bf(g[((long)(k >> 8) * C + m) * (H2 * H2) + (k & 255)]); }
+  __device__ float b(int k, int n) const {
+    const int co = n >> 4, ky = (n >> 2) & 3, kx = n & 3, iy = (k >> 4) & 15, ix = k & 15;
+    return dz[(((long)(k >> 8) * C + co) * H3 + 4 * iy + ky) * H3 + 4 * ix + kx];
+  }
+  __device__ void out(int m, int n, float v, int kz) const { part[((long)kz * C + m) * (C * 16) + n] = v; }
+};
+
+// conv 3x3 s2 data gradient: din[n][ci][iy][ix] = sum_{co,ky,kx} W1[co][ci][ky][kx] dz2[n][co][oy][ox]
+// over 2 oy + ky - 1 = iy, 2 ox + kx - 1 = ix; m = (n, iy, ix), n = ci, k = (co, ky, kx); ReLU mask of a1
+struct OpConv1Data {
+  static constexpr bool SPLIT_A = true, SPLIT_B = false;
+  const float *dz;
+  const bf16_t *W, *ain;
+  float *out_;
+  __device__ float a(int m, int k) const {
+    const int iy = (m >> 5) & 31, ix = m & 31, co = k / 9, r = k - 9 * co, ky = r / 3, kx = r - 3 * ky;
+    const int ty = iy + 1 - ky, tx = ix + 1 - kx;
+    if (ty < 0 || tx < 0 || (ty & 1) || (tx & 1) || ty >= 2 * H2 || tx >= 2 * H2) return 0.f;
+    return dz[(((long)(m >> 10) * C + co) * H2 + (ty >> 1)) * H2 + (tx >> 1)];
+  }
+  __device__ __bf16 b(int k, int n) const {
+    const int co = k / 9, r = k - 9 * co;
+    return raw_bf(W[(co * C + n) * 9 + r]);
+  }
+  __device__ void out(int m, int n, float v, int) const {
+    const long i = ((long)(m >> 10) * C + n) * (H1 * H1) + (m & 1023);
+    out_[i] = bf2f(ain[i]) > 0.f ? v : 0.f;
+  }
+};
+
+// conv 3x3 s2 weight gradient: dW1[co][(ci,ky,kx)] = sum_{(n,oy,ox)} dz2[n][co][oy][ox] a1[n][ci][2oy+ky-1][2ox+kx-1];
+// m = co, n = (ci, ky, kx), k = (n, oy, ox); partial tiles per k chunk
+struct OpConv1W {
+  static constexpr bool SPLIT_A = true, SPLIT_B = false;
+  const float *dz;
+  const bf16_t *ain;
+  float *part;
+  __device__ float a(int m, int k) const { return dz[((long)(k >> 8) * C + m) * (H2 * H2) + (k & 255)]; }
+  __device__ __bf16 b(int k, int n) const {
+    const int oy = (k >> 4) & 15, ox = k & 15, ci = n / 9, r = n - 9 * ci, ky = r / 3, kx = r - 3 * ky;
+    const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
+    if (iy < 0 || iy >= H1 || ix < 0 || ix >= H1) return raw_bf(0);
+    return raw_bf(ain[(((long)(k >> 8) * C + ci) * H1 + iy) * H1 + ix]);
+  }
+  __device__ void out(int m, int n, float v, int kz) const { part[((long)kz * C + m) * (C * 9) + n] = v; }
+};
+
+// dW[i] = sum over the nz partial tiles, in order
+__global__ void k_sum_parts(const float *__restrict__ part, int nz, long nw, float *__restrict__ dW) {
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= nw) return;
+  float s = 0.f;
+  for (int z = 0; z < nz; ++z) s += part[z * nw + i];
+  dW[i] = s;
+}
+
+// db[c] = sum over samples and pixels of d[n][c][:] (one block per channel)
+__global__ void k_bias_grad(int B, const float *__restrict__ d, int hw, float *__restrict__ db) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (long j = threadIdx.x; j < (long)B * hw; j += blockDim.x) s += d[((j / hw) * C + c) * hw + j % hw];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[c] = sh[0];
+}
+
+constexpr int kWChunk = 512;   // k = (sample, pixel) per partial tile of the weight gradients
+
+template <class Op>
+void launch_gemm(hipStream_t s, const Op &op, int M, int N, int K, int kchunk) {
+  const dim3 grid((unsigned)((M / kGT) * (N / kGT)), (unsigned)((K + kchunk - 1) / kchunk));
+  hipLaunchKernelGGL(k_nn_gemm<Op>, grid, dim3(256), 0, s, op, M, N, K, kchunk);
 }
 
 // Adam on the FP32 master weights, then refresh the BF16 copy
@@ -392,6 +528,7 @@ struct Net {
   bf16_t *pb = nullptr;
   bf16_t *x = nullptr, *a1 = nullptr, *a2 = nullptr, *a2g = nullptr, *a3 = nullptr;
   float *y = nullptr, *dy = nullptr, *lap = nullptr, *d3 = nullptr, *dg = nullptr, *d2 = nullptr, *d1 = nullptr;
+  float *wpart = nullptr;     // partial tiles of the split weight-gradient reductions
   std::vector<void *> owned;
 };
 
@@ -419,11 +556,9 @@ static iga_status forward(Net &n, const float *x, int B) {
   hipLaunchKernelGGL(k_to_bf16, dim3(nblk((long)B * 2 * H0 * H0)), dim3(256), 0, s, x, n.x, (long)B * 2 * H0 * H0);
   hipLaunchKernelGGL((k_conv_fwd<2, H0, H1, 1>), dim3(nblk((long)B * C * H1 * H1)), dim3(256), 0, s, B, n.x,
                      pb + O_W0, p + O_B0, n.a1);
-  hipLaunchKernelGGL((k_conv_fwd<C, H1, H2, 2>), dim3(nblk((long)B * C * H2 * H2)), dim3(256), 0, s, B, n.a1,
-                     pb + O_W1, p + O_B1, n.a2);
+  launch_gemm(s, OpConv1Fwd{n.a1, pb + O_W1, p + O_B1, n.a2}, B * H2 * H2, C, C * 9, C * 9);
   hipLaunchKernelGGL(k_gctx_fwd, dim3((unsigned)(B * C)), dim3(256), 0, s, (const bf16_t *)n.a2, n.a2g);
-  hipLaunchKernelGGL(k_convT4_fwd, dim3(nblk((long)B * C * H3 * H3)), dim3(256), 0, s, B, n.a2g, pb + O_W2, p + O_B2,
-                     n.a3);
+  launch_gemm(s, OpConvT4Fwd{n.a2g, pb + O_W2, p + O_B2, n.a3}, B * H2 * H2, C * 16, C, C);
   hipLaunchKernelGGL(k_convT2_fwd, dim3(nblk((long)B * H4 * H4)), dim3(256), 0, s, B, n.a3, pb + O_W3, p + O_B3, n.y);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
@@ -440,13 +575,17 @@ static iga_status backward(Net &n, const float *target, int B) {
   hipLaunchKernelGGL(k_convT2_bwd_w, dim3(NP_W3), dim3(256), 0, s, B, n.dy, n.a3, g + O_W3, g + O_B3);
   hipLaunchKernelGGL(k_convT2_bwd_data, dim3(nblk((long)B * C * H3 * H3)), dim3(256), 0, s, B, n.dy, pb + O_W3, n.a3,
                      n.d3);
-  hipLaunchKernelGGL(k_convT4_bwd_w, dim3(NP_W2), dim3(256), 0, s, B, n.d3, n.a2g, g + O_W2, g + O_B2);
-  hipLaunchKernelGGL(k_convT4_bwd_data, dim3(nblk((long)B * C * H2 * H2)), dim3(256), 0, s, B, n.d3, pb + O_W2, n.dg);
+  const int KW = B * H2 * H2, nz = (KW + kWChunk - 1) / kWChunk;
+  launch_gemm(s, OpConvT4W{n.a2g, n.d3, n.wpart}, C, C * 16, KW, kWChunk);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(NP_W2)), dim3(256), 0, s, (const float *)n.wpart, nz, (long)NP_W2, g + O_W2);
+  hipLaunchKernelGGL(k_bias_grad, dim3(C), dim3(256), 0, s, B, (const float *)n.d3, H3 * H3, g + O_B2);
+  launch_gemm(s, OpConvT4Data{n.d3, pb + O_W2, n.dg}, B * H2 * H2, C, C * 16, C * 16);
   hipLaunchKernelGGL(k_gctx_bwd, dim3((unsigned)(B * C)), dim3(256), 0, s, (const float *)n.dg, (const bf16_t *)n.a2,
                      n.d2);
-  hipLaunchKernelGGL((k_conv_bwd_w<C, H1, H2, 2>), dim3(NP_W1), dim3(256), 0, s, B, n.d2, n.a1, g + O_W1, g + O_B1);
-  hipLaunchKernelGGL((k_conv_bwd_data<C, H1, H2, 2>), dim3(nblk((long)B * C * H1 * H1)), dim3(256), 0, s, B, n.d2,
-                     pb + O_W1, n.a1, n.d1);
+  launch_gemm(s, OpConv1W{n.d2, n.a1, n.wpart}, C, C * 9, KW, kWChunk);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(NP_W1)), dim3(256), 0, s, (const float *)n.wpart, nz, (long)NP_W1, g + O_W1);
+  hipLaunchKernelGGL(k_bias_grad, dim3(C), dim3(256), 0, s, B, (const float *)n.d2, H2 * H2, g + O_B1);
+  launch_gemm(s, OpConv1Data{n.d2, pb + O_W1, n.a1, n.d1}, B * H1 * H1, C, C * 9, C * 9);
   hipLaunchKernelGGL((k_conv_bwd_w<2, H0, H1, 1>), dim3(NP_W0), dim3(256), 0, s, B, n.d1, n.x, g + O_W0, g + O_B0);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
@@ -486,7 +625,8 @@ iga_status igann_create(int batch_max, void *hip_stream, igann_t *out) {
       (st = nalloc(*n, &n->y, B * H4 * H4)) || (st = nalloc(*n, &n->dy, B * H4 * H4)) ||
       (st = nalloc(*n, &n->lap, B * H4 * H4)) ||
       (st = nalloc(*n, &n->d3, B * C * H3 * H3)) || (st = nalloc(*n, &n->d2, B * C * H2 * H2)) ||
-      (st = nalloc(*n, &n->d1, B * C * H1 * H1))) {
+      (st = nalloc(*n, &n->d1, B * C * H1 * H1)) ||
+      (st = nalloc(*n, &n->wpart, (B * H2 * H2 + kWChunk - 1) / kWChunk * (size_t)NP_W2))) {
     net_free(n);
     return st;
   }

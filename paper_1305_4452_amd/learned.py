@@ -239,6 +239,15 @@ def evaluate(net, std, test, sols_ref, atol=1e-10, chunk=1000, corrupt=None):
 
 LAP_WEIGHT = 0.0
 
+# Algorithmic multiply-adds x 2 per sample (stride and padding zeros not counted): forward = conv 3x3
+# 2->64 on 32^2 + conv 3x3 s2 64->64 to 16^2 + transposed conv 4x4 s4 64->64 to 64^2 + transposed conv 2x2
+# 64->1 to 65^2; a training step adds both gradients of the three inner layers and the weight gradient
+# of the first.
+FWD_FLOP = 2.0 * (64 * 2 * 9 * 32 * 32 + 64 * 64 * 9 * 16 * 16 + 64 * 64 * 16 * 16 * 16 + 64 * 4 * 64 * 64)
+TRAIN_FLOP = FWD_FLOP + 2.0 * (2 * 64 * 4 * 64 * 64 + 2 * 64 * 64 * 16 * 16 * 16 + 2 * 64 * 64 * 9 * 16 * 16
+                               + 64 * 2 * 9 * 32 * 32)
+BF16_PEAK_TFLOPS = 2500.0
+
 
 def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print, lap_weight=LAP_WEIGHT):
     """Generate, train and evaluate; returns a summary dict."""
@@ -267,10 +276,17 @@ def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print, la
     if log:
         log("evaluating the learned guess")
     ev = evaluate(net, std, te_k, [sols_te[i] for i in keep_te])
+    steps = epochs * (len(keep) // batch)
+    train_tf = TRAIN_FLOP * steps * batch / t_train / 1e12
+    infer_tf = FWD_FLOP * len(te_k) / ev["inference_s"] / 1e12
     ev.update(train_instances=len(keep), train_rejected=rej_tr, test_rejected=len(te) - len(keep_te),
               epochs=epochs, lap_weight=lap_weight, loss_first=hist[0], loss_last=hist[-1], train_s=t_train,
               datagen_s=t_gen,
-              instance_setup_s=t_inst)
+              instance_setup_s=t_inst,
+              train_tflop_per_s=train_tf, train_frac_bf16_peak=train_tf / BF16_PEAK_TFLOPS,
+              inference_tflop_per_s=infer_tf, inference_frac_bf16_peak=infer_tf / BF16_PEAK_TFLOPS,
+              flop_note="algorithmic flops per sample: forward %.3g, training step %.3g; inference time includes "
+                        "the host-side input preparation and the copy of the guesses back" % (FWD_FLOP, TRAIN_FLOP))
     return ev, net, std
 
 
