@@ -218,64 +218,96 @@ __global__ void k_convT2_bwd_data(int B, const float *__restrict__ dy, const bf1
   da3[i] = bf2f(a3[i]) > 0.f ? s : 0.f;
 }
 
-// ---- weight gradients: one block per weight, reduction over (n, output pixels) ----
-__device__ inline float block_reduce(float v, float *sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
+// ---- weight and bias gradients of the thin layers: a block per (channel, chunk of kSampChunk samples)
+// forms every sum of its channel in one pass and leaves them as a partial row; k_sum_parts adds the
+// chunks in order ----
+constexpr int kSampChunk = 4;
+
+template <int NV>
+__device__ inline void block_sum_n(float (&v)[NV], float (*sh)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    float x = v[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) sh[j][w] = x;
   }
-  return sh[0];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = sh[j][0] + sh[j][1] + sh[j][2] + sh[j][3];
 }
 
-template <int CIN, int HIN, int HOUT, int S>
-__global__ void k_conv_bwd_w(int B, const float *__restrict__ dout, const bf16_t *__restrict__ ain,
-                             float *__restrict__ dW, float *__restrict__ db) {
-  __shared__ float sh[256];
-  const int w = blockIdx.x;                 // [co][ci][ky][kx]
-  const int kx = w % 3, ky = (w / 3) % 3, ci = (w / 9) % CIN, co = w / (9 * CIN);
-  const long tot = (long)B * HOUT * HOUT;
-  float s = 0, sb = 0;
-  for (long j = threadIdx.x; j < tot; j += blockDim.x) {
-    int ox = j % HOUT, oy = (j / HOUT) % HOUT;
-    long n = j / (HOUT * HOUT);
-    float d = dout[((n * C + co) * HOUT + oy) * HOUT + ox];
-    int iy = oy * S + ky - 1, ix = ox * S + kx - 1;
-    if (iy >= 0 && iy < HIN && ix >= 0 && ix < HIN) s += d * bf2f(ain[((n * CIN + ci) * HIN + iy) * HIN + ix]);
-    sb += d;
+// conv 3x3 2 -> 64 (stride 1, pad 1): dW0[co][ci][ky][kx] = sum dz1[n][co][oy][ox] x[n][ci][oy+ky-1][ox+kx-1]
+// and db0[co] = sum dz1[n][co][:]; partial row [chunk][co 18 weights ..., 1152 + co bias]
+__global__ void __launch_bounds__(256) k_conv0_wgrad(int B, const float *__restrict__ dz, const bf16_t *__restrict__ x,
+                                                     float *__restrict__ part) {
+  __shared__ float sh[19][4];
+  const int co = blockIdx.x, n0 = blockIdx.y * kSampChunk, n1 = min(B, n0 + kSampChunk);
+  float acc[19];
+#pragma unroll
+  for (int j = 0; j < 19; ++j) acc[j] = 0.f;
+  for (long j = threadIdx.x; j < (long)(n1 - n0) * H1 * H1; j += 256) {
+    const long n = n0 + j / (H1 * H1);
+    const int oy = (int)(j / H1) % H1, ox = (int)(j % H1);
+    const float d = dz[(n * C + co) * H1 * H1 + oy * H1 + ox];
+#pragma unroll
+    for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+          const int iy = oy + ky - 1, ix = ox + kx - 1;
+          if (iy >= 0 && iy < H0 && ix >= 0 && ix < H0) acc[ci * 9 + ky * 3 + kx] += d * bf2f(x[((n * 2 + ci) * H0 + iy) * H0 + ix]);
+        }
+    acc[18] += d;
   }
-  float r = block_reduce(s, sh);
-  if (threadIdx.x == 0) dW[w] = r;
-  __syncthreads();
-  if (ci == 0 && ky == 0 && kx == 0) {
-    float rb = block_reduce(sb, sh);
-    if (threadIdx.x == 0) db[co] = rb;
+  block_sum_n<19>(acc, sh);
+  if (threadIdx.x == 0) {
+    float *row = part + (long)blockIdx.y * (NP_W0 + C);
+#pragma unroll
+    for (int j = 0; j < 18; ++j) row[co * 18 + j] = acc[j];
+    row[NP_W0 + co] = acc[18];
   }
 }
 
-// convT2: dW3[ci][ky][kx] = sum_{n,iy,ix} a3[n][ci][iy][ix] dy[n][iy+ky][ix+kx]
-__global__ void k_convT2_bwd_w(int B, const float *__restrict__ dy, const bf16_t *__restrict__ a3,
-                               float *__restrict__ dW, float *__restrict__ db) {
-  __shared__ float sh[256];
-  const int w = blockIdx.x;
-  const int kx = w % 2, ky = (w / 2) % 2, ci = w / 4;
-  const long tot = (long)B * H3 * H3;
-  float s = 0;
-  for (long j = threadIdx.x; j < tot; j += blockDim.x) {
-    int ix = j % H3, iy = (j / H3) % H3;
-    long n = j / (H3 * H3);
-    s += bf2f(a3[((n * C + ci) * H3 + iy) * H3 + ix]) * dy[(n * H4 + iy + ky) * H4 + ix + kx];
+// transposed conv 2x2 64 -> 1: dW3[ci][ky][kx] = sum a3[n][ci][iy][ix] dy[n][iy+ky][ix+kx], db3 = sum dy;
+// partial row [chunk][ci 4 weights ..., 256 bias] (the bias by the ci = 0 blocks)
+__global__ void __launch_bounds__(256) k_convT2_wgrad(int B, const float *__restrict__ dy, const bf16_t *__restrict__ a3,
+                                                      float *__restrict__ part) {
+  __shared__ float sh[5][4];
+  const int ci = blockIdx.x, n0 = blockIdx.y * kSampChunk, n1 = min(B, n0 + kSampChunk);
+  float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  for (long j = threadIdx.x; j < (long)(n1 - n0) * H3 * H3; j += 256) {
+    const long n = n0 + j / (H3 * H3);
+    const int iy = (int)(j / H3) % H3, ix = (int)(j % H3);
+    const float a = bf2f(a3[((n * C + ci) * H3 + iy) * H3 + ix]);
+    const float *d = dy + (n * H4 + iy) * H4 + ix;
+    acc[0] += a * d[0];
+    acc[1] += a * d[1];
+    acc[2] += a * d[H4];
+    acc[3] += a * d[H4 + 1];
   }
-  float r = block_reduce(s, sh);
-  if (threadIdx.x == 0) dW[w] = r;
-  __syncthreads();
-  if (w == 0) {
-    float sb = 0;
-    for (long j = threadIdx.x; j < (long)B * H4 * H4; j += blockDim.x) sb += dy[j];
-    float rb = block_reduce(sb, sh);
-    if (threadIdx.x == 0) db[0] = rb;
+  if (ci == 0)
+    for (long j = threadIdx.x; j < (long)(n1 - n0) * H4 * H4; j += 256) acc[4] += dy[(long)n0 * H4 * H4 + j];
+  block_sum_n<5>(acc, sh);
+  if (threadIdx.x == 0) {
+    float *row = part + (long)blockIdx.y * (NP_W3 + 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) row[ci * 4 + j] = acc[j];
+    if (ci == 0) row[NP_W3] = acc[4];
   }
+}
+
+// bias gradient of a 64-channel layer: partial row [chunk][c] = sum over the chunk's samples of d[n][c][:]
+__global__ void __launch_bounds__(256) k_bias_part(int B, const float *__restrict__ d, int hw, float *__restrict__ part) {
+  __shared__ float sh[1][4];
+  const int c = blockIdx.x, n0 = blockIdx.y * kSampChunk, n1 = min(B, n0 + kSampChunk);
+  float acc[1] = {0.f};
+  for (long j = threadIdx.x; j < (long)(n1 - n0) * hw; j += 256) acc[0] += d[((n0 + j / hw) * C + c) * hw + j % hw];
+  block_sum_n<1>(acc, sh);
+  if (threadIdx.x == 0) part[(long)blockIdx.y * C + c] = acc[0];
 }
 
 // ---- matrix-core layers ------------------------------------------------------------------
@@ -478,21 +510,6 @@ __global__ void k_sum_parts(const float *__restrict__ part, int nz, long nw, flo
   dW[i] = s;
 }
 
-// db[c] = sum over samples and pixels of d[n][c][:] (one block per channel)
-__global__ void k_bias_grad(int B, const float *__restrict__ d, int hw, float *__restrict__ db) {
-  __shared__ float sh[256];
-  const int c = blockIdx.x;
-  float s = 0.f;
-  for (long j = threadIdx.x; j < (long)B * hw; j += blockDim.x) s += d[((j / hw) * C + c) * hw + j % hw];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) db[c] = sh[0];
-}
-
 constexpr int kWChunk = 512;   // k = (sample, pixel) per partial tile of the weight gradients
 
 template <class Op>
@@ -572,21 +589,30 @@ static iga_status backward(Net &n, const float *target, int B) {
     hipLaunchKernelGGL(k_lap_err, dim3(nblk((long)B * H4 * H4)), dim3(256), 0, s, B, (const float *)n.y, target, n.lap);
   hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, s, B, (const float *)n.y, target, (const float *)n.lap, n.beta,
                      n.dy, n.part);
-  hipLaunchKernelGGL(k_convT2_bwd_w, dim3(NP_W3), dim3(256), 0, s, B, n.dy, n.a3, g + O_W3, g + O_B3);
+  const int nch = (B + kSampChunk - 1) / kSampChunk;
+  hipLaunchKernelGGL(k_convT2_wgrad, dim3(C, nch), dim3(256), 0, s, B, (const float *)n.dy, (const bf16_t *)n.a3,
+                     n.wpart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(NP_W3 + 1)), dim3(256), 0, s, (const float *)n.wpart, nch,
+                     (long)(NP_W3 + 1), g + O_W3);   // W3 then b3 (contiguous)
   hipLaunchKernelGGL(k_convT2_bwd_data, dim3(nblk((long)B * C * H3 * H3)), dim3(256), 0, s, B, n.dy, pb + O_W3, n.a3,
                      n.d3);
   const int KW = B * H2 * H2, nz = (KW + kWChunk - 1) / kWChunk;
   launch_gemm(s, OpConvT4W{n.a2g, n.d3, n.wpart}, C, C * 16, KW, kWChunk);
   hipLaunchKernelGGL(k_sum_parts, dim3(nblk(NP_W2)), dim3(256), 0, s, (const float *)n.wpart, nz, (long)NP_W2, g + O_W2);
-  hipLaunchKernelGGL(k_bias_grad, dim3(C), dim3(256), 0, s, B, (const float *)n.d3, H3 * H3, g + O_B2);
+  hipLaunchKernelGGL(k_bias_part, dim3(C, nch), dim3(256), 0, s, B, (const float *)n.d3, H3 * H3, n.wpart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const float *)n.wpart, nch, (long)C, g + O_B2);
   launch_gemm(s, OpConvT4Data{n.d3, pb + O_W2, n.dg}, B * H2 * H2, C, C * 16, C * 16);
   hipLaunchKernelGGL(k_gctx_bwd, dim3((unsigned)(B * C)), dim3(256), 0, s, (const float *)n.dg, (const bf16_t *)n.a2,
                      n.d2);
   launch_gemm(s, OpConv1W{n.d2, n.a1, n.wpart}, C, C * 9, KW, kWChunk);
   hipLaunchKernelGGL(k_sum_parts, dim3(nblk(NP_W1)), dim3(256), 0, s, (const float *)n.wpart, nz, (long)NP_W1, g + O_W1);
-  hipLaunchKernelGGL(k_bias_grad, dim3(C), dim3(256), 0, s, B, (const float *)n.d2, H2 * H2, g + O_B1);
+  hipLaunchKernelGGL(k_bias_part, dim3(C, nch), dim3(256), 0, s, B, (const float *)n.d2, H2 * H2, n.wpart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const float *)n.wpart, nch, (long)C, g + O_B1);
   launch_gemm(s, OpConv1Data{n.d2, pb + O_W1, n.a1, n.d1}, B * H1 * H1, C, C * 9, C * 9);
-  hipLaunchKernelGGL((k_conv_bwd_w<2, H0, H1, 1>), dim3(NP_W0), dim3(256), 0, s, B, n.d1, n.x, g + O_W0, g + O_B0);
+  hipLaunchKernelGGL(k_conv0_wgrad, dim3(C, nch), dim3(256), 0, s, B, (const float *)n.d1, (const bf16_t *)n.x,
+                     n.wpart);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(NP_W0 + C)), dim3(256), 0, s, (const float *)n.wpart, nch,
+                     (long)(NP_W0 + C), g + O_W0);   // W0 then b0 (contiguous)
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
 }
