@@ -85,9 +85,10 @@ typedef enum {
                                 by colour with plain adds ((p+1)^d launches, no two workgroups of a
                                 launch share a value) */
   IGA_OPT_TILED_3D = 8       /* 3D residual and matrix-free apply with x = xi, no weights, no source:
-                                1 by tiles of elements (default), 0 one element per workgroup; also the
-                                3D fourth-order operator on x = xi without weights, and the 2D and 3D
-                                Cahn-Hilliard residual */
+                                1 by tiles of elements (default: (16/Q)^2 x 4 elements with one lane per
+                                Gauss-point column), 2 by cubic tiles of elements, 0 one element per
+                                workgroup; 1 and 2 also select tiles for the 3D fourth-order operator on
+                                x = xi without weights and the 2D and 3D Cahn-Hilliard residual */
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):

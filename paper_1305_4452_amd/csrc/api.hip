@@ -711,7 +711,7 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
       h->kt_n = 0;
       return IGA_OK;
     case IGA_OPT_TILED_3D:
-      if (value != 0 && value != 1) return fail(IGA_EINVAL, "IGA_OPT_TILED_3D is 0 or 1");
+      if (value < 0 || value > 2) return fail(IGA_EINVAL, "IGA_OPT_TILED_3D is 0, 1 or 2");
       h->tiled_3d = (int)value;
       return IGA_OK;
     case IGA_OPT_ND_SCATTER:

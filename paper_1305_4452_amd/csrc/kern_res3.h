@@ -594,5 +594,237 @@ __device__ inline void ch3_body(const DevProblem &pb, const int tile, const doub
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Column-register variant of the residual, the apply and the point linearisation.  The x-y extent of a tile
+// is TEX = 16 / Q elements, so its TEX Q x TEX Q Gauss-point columns (g0, g1) are one lane each, and
+// a tile is TEZ elements deep.  The axis-0 contraction goes through LDS; then every lane holds the
+// axis-1 results of its column for all NZ = TEZ + p function planes in registers and runs the axis-2
+// contraction, the point integrands and the transposed axis-2 contraction for all of its column's
+// points in registers (the axis-2 basis rows are the same for every lane: uniform loads).  Only the
+// transposed axis-1 and axis-0 contractions go through LDS again.  Compared with res3_body this
+// removes the point arrays from LDS and most of the LDS reads per multiply-add; it adds
+// (TEX + p)^2 / TEX^2 of x-y halo work instead of (TE + p)^3 / TE^3.  Border functions are shared
+// with neighbouring tiles: one FP64 atomic per tile function, the output zeroed before.  OP3_LIN
+// stops after the point values and writes m = -lambda W e^u per point, layout [element][q].
+template <int P, int TEZ>
+struct Res3R {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TEX = 16 / Q, G = TEX * Q;
+  static constexpr int NI = TEX + p, NZ = TEZ + p;
+  static constexpr int n_c = NZ * NI * NI, n_a = NZ * NI * G, n_y = NZ * G * G;
+  static constexpr int n_b = 4 * G * P + 2 * G;
+  static constexpr size_t total = (size_t)(n_c + 2 * n_a + 3 * n_y + n_b) * sizeof(double);
+  static_assert(G * G <= kThreads, "one lane per Gauss-point column");
+};
+
+template <int P>
+struct Res3RDepth {
+  static constexpr int TEZ = P == 5 ? 3 : 4;
+};
+
+__host__ __device__ inline int res3r_tiles(int ne0, int ne1, int ne2, int TEX, int TEZ) {
+  return ((ne0 + TEX - 1) / TEX) * ((ne1 + TEX - 1) / TEX) * ((ne2 + TEZ - 1) / TEZ);
+}
+
+template <int P, int TEZ, int OP>
+__device__ inline void res3r_body(const DevProblem &pb, const int tile, const double *__restrict__ X,
+                                  const double *__restrict__ lin, double *__restrict__ Y, double *__restrict__ lds) {
+  constexpr bool LIN = OP == OP3_LIN;
+  using S_ = Res3R<P, TEZ>;
+  constexpr int p = S_::p, Q = S_::Q, TEX = S_::TEX, G = S_::G, NI = S_::NI, NZ = S_::NZ;
+  constexpr int NT = kThreads, L = P * P * P, GP = G * P;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
+  const int nt0 = (ne0 + TEX - 1) / TEX, nt1 = (ne1 + TEX - 1) / TEX;
+  const int E0 = (tile % nt0) * TEX, E1 = ((tile / nt0) % nt1) * TEX, E2 = (tile / (nt0 * nt1)) * TEZ;
+  const int NE0 = min(TEX, ne0 - E0), NE1 = min(TEX, ne1 - E1), NE2 = min(TEZ, ne2 - E2);
+  const int G0 = NE0 * Q, G1 = NE1 * Q;
+  const int NI0 = NE0 + p, NI1 = NE1 + p, NI2 = NE2 + p;
+  double *c = lds;                                     // [k2][k1][k0]
+  double *A0 = c + S_::n_c, *D0 = A0 + S_::n_a;        // [k2][k1][g0]; later Za, Zb
+  double *Ys = D0 + S_::n_a;                           // [3][k2][g1][g0]
+  double *sB = Ys + 3 * S_::n_y, *sW = sB + 4 * GP;
+  const double *B0 = sB, *dB0 = sB + GP, *B1 = sB + 2 * GP, *dB1 = sB + 3 * GP, *W0 = sW, *W1 = sW + G;
+  double *Za = A0, *Zb = D0;
+  const int t = threadIdx.x;
+  const bool kel = pb.kappa_mode == IGA_KAPPA_ELEMENT;
+
+  for (int i = t; i < GP; i += NT)
+    if (i / P < G0) {
+      sB[i] = pb.ax[0].B[(size_t)E0 * Q * P + i];
+      sB[GP + i] = pb.ax[0].dB[(size_t)E0 * Q * P + i];
+    }
+  for (int i = t; i < GP; i += NT)
+    if (i / P < G1) {
+      sB[2 * GP + i] = pb.ax[1].B[(size_t)E1 * Q * P + i];
+      sB[3 * GP + i] = pb.ax[1].dB[(size_t)E1 * Q * P + i];
+    }
+  for (int i = t; i < G; i += NT) {
+    if (i < G0) sW[i] = pb.ax[0].wq[(size_t)E0 * Q + i];
+    if (i < G1) sW[G + i] = pb.ax[1].wq[(size_t)E1 * Q + i];
+  }
+  for (int i = t; i < S_::n_c; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+    const int i0 = wrap_fn(pb.ax[0], E0 + k0), i1 = wrap_fn(pb.ax[1], E1 + k1), i2 = wrap_fn(pb.ax[2], E2 + k2);
+    double x = X[i0 + (int64_t)n0 * (i1 + (int64_t)n1 * i2)];
+    if (OP == OP3_APPLY && is_dirichlet_idx(pb, i0, i1, i2)) x = 0.0;
+    c[i] = x;
+  }
+  __syncthreads();
+  // axis 0: value and derivative per function pair (k1, k2)
+  for (int i = t; i < S_::n_a; i += NT) {
+    const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), el0 = g0 / Q;
+    if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+    const double *cc = c + (k2 * NI + k1) * NI + el0;
+    double a = 0, d = 0;
+#pragma unroll
+    for (int a0 = 0; a0 < P; ++a0) {
+      a += B0[g0 * P + a0] * cc[a0];
+      if constexpr (!LIN) d += dB0[g0 * P + a0] * cc[a0];
+    }
+    A0[i] = a;
+    if constexpr (!LIN) D0[i] = d;
+  }
+  __syncthreads();
+  // one lane per Gauss-point column: axis 1, axis 2, the point integrands and the transposed axis 2
+  const int g0 = t % G, g1 = t / G;
+  const bool act = t < G * G && g0 < G0 && g1 < G1;
+  double Y0[NZ], Y1[NZ], Y2[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) Y0[k] = Y1[k] = Y2[k] = 0.0;
+  if (act) {
+    const int el0 = g0 / Q, el1 = g1 / Q, q0 = g0 % Q, q1 = g1 % Q;
+    // the apply's point factors of this column, loaded before the axis-1 work so that they arrive
+    // while it runs
+    double lv[OP == OP3_APPLY ? TEZ * Q : 1];
+    if constexpr (OP == OP3_APPLY) {
+#pragma unroll
+      for (int el2 = 0; el2 < TEZ; ++el2) {
+        const int64_t e = (E0 + el0) + (int64_t)ne0 * ((E1 + el1) + (int64_t)ne1 * (E2 + min(el2, NE2 - 1)));
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) lv[el2 * Q + q2] = lin[e * L + q0 + Q * (q1 + Q * q2)];
+      }
+    }
+    double b1[P], db1[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      b1[a] = B1[g1 * P + a];
+      db1[a] = dB1[g1 * P + a];
+    }
+    double U[NZ], U01[NZ], U10[NZ];
+#pragma unroll
+    for (int k2 = 0; k2 < NZ; ++k2) {
+      double u = 0, u01 = 0, u10 = 0;
+      if (k2 < NI2) {
+#pragma unroll
+        for (int a1 = 0; a1 < P; ++a1) {
+          const int r = (k2 * NI + el1 + a1) * G + g0;
+          u += b1[a1] * A0[r];
+          if constexpr (!LIN) {
+            u01 += b1[a1] * D0[r];
+            u10 += db1[a1] * A0[r];
+          }
+        }
+      }
+      U[k2] = u;
+      U01[k2] = u01;
+      U10[k2] = u10;
+    }
+    const double w01 = W0[g0] * W1[g1], lam = pb.lambda;
+#pragma unroll
+    for (int el2 = 0; el2 < TEZ; ++el2) {
+      if (el2 >= NE2) break;
+      const int e2 = E2 + el2;
+      const int64_t e = (E0 + el0) + (int64_t)ne0 * ((E1 + el1) + (int64_t)ne1 * e2);
+      const double kap = kel ? pb.kel[e] : 1.0;
+#pragma unroll
+      for (int q2 = 0; q2 < Q; ++q2) {
+        const size_t o = ((size_t)e2 * Q + q2) * P;
+        double b2[P], db2[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          b2[a] = pb.ax[2].B[o + a];
+          db2[a] = pb.ax[2].dB[o + a];
+        }
+        double u = 0, d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < P; ++a2) {
+          u += b2[a2] * U[el2 + a2];
+          d0 += b2[a2] * U01[el2 + a2];
+          d1 += b2[a2] * U10[el2 + a2];
+          d2 += db2[a2] * U[el2 + a2];
+        }
+        const double W = w01 * pb.ax[2].wq[(size_t)e2 * Q + q2], kw = kap * W;
+        if constexpr (LIN) {
+          Y[e * L + q0 + Q * (q1 + Q * q2)] = -lam * W * exp(u);
+          continue;
+        }
+        const double F0 = kw * d0, F1 = kw * d1, F2 = kw * d2;
+        double S;
+        if constexpr (OP == OP3_RES) S = -W * lam * exp(u);
+        else S = lv[el2 * Q + q2] * u;
+#pragma unroll
+        for (int a2 = 0; a2 < P; ++a2) {
+          Y0[el2 + a2] += b2[a2] * F0;
+          Y1[el2 + a2] += b2[a2] * F1;
+          Y2[el2 + a2] += db2[a2] * F2 + b2[a2] * S;
+        }
+      }
+    }
+    if constexpr (LIN) return;
+#pragma unroll
+    for (int k2 = 0; k2 < NZ; ++k2) {
+      if (k2 < NI2) {
+        const int w = (k2 * G + g1) * G + g0;
+        Ys[w] = Y0[k2];
+        Ys[S_::n_y + w] = Y1[k2];
+        Ys[2 * S_::n_y + w] = Y2[k2];
+      }
+    }
+  }
+  if constexpr (LIN) return;
+  __syncthreads();
+  // transposed axis 1: Za = sum B1 Y0, Zb = sum dB1 Y1 + B1 Y2 (over A0 / D0, whose reads are done)
+  for (int i = t; i < S_::n_a; i += NT) {
+    const int gg0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI);
+    if (gg0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+    double za = 0, zb = 0;
+#pragma unroll
+    for (int a1 = 0; a1 <= p; ++a1) {
+      const int el1 = k1 - a1;
+      if (el1 < 0 || el1 >= NE1) continue;
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1) {
+        const int gg1 = el1 * Q + q1, w = (k2 * G + gg1) * G + gg0;
+        const double b = B1[gg1 * P + a1];
+        za += b * Ys[w];
+        zb += dB1[gg1 * P + a1] * Ys[S_::n_y + w] + b * Ys[2 * S_::n_y + w];
+      }
+    }
+    Za[i] = za;
+    Zb[i] = zb;
+  }
+  __syncthreads();
+  // transposed axis 0 and the scatter of the tile's contributions
+  for (int i = t; i < S_::n_c; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+    double r = 0;
+#pragma unroll
+    for (int a0 = 0; a0 <= p; ++a0) {
+      const int el0 = k0 - a0;
+      if (el0 < 0 || el0 >= NE0) continue;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) {
+        const int gg0 = el0 * Q + q0, w = (k2 * NI + k1) * G + gg0;
+        r += dB0[gg0 * P + a0] * Za[w] + B0[gg0 * P + a0] * Zb[w];
+      }
+    }
+    atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
+                 (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], E2 + k2))],
+              r);
+  }
+}
+
 }  // namespace rs3
 }  // namespace iga

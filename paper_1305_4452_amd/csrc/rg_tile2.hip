@@ -51,10 +51,30 @@ __global__ void __launch_bounds__(rs3::kThreads) k_res3(DevProblem pb, const dou
   rs3::res3_body<P, OP>(pb, (int)blockIdx.x, X, lin, Y, lds);
 }
 
+template <int P, int OP>
+__global__ void __launch_bounds__(rs3::kThreads) k_res3r(DevProblem pb, const double *__restrict__ X,
+                                                         const double *__restrict__ lin, double *__restrict__ Y) {
+  constexpr int TEZ = rs3::Res3RDepth<P>::TEZ;
+  __shared__ double lds[rs3::Res3R<P, TEZ>::total / sizeof(double)];
+  rs3::res3r_body<P, TEZ, OP>(pb, (int)blockIdx.x, X, lin, Y, lds);
+}
+
 template <int P>
 iga_status run_res3(Handle &h, const double *X, double *Y, int op) {
   const unsigned nb = (unsigned)rs3::res3_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], rs3::Res3<P>::TE);
-  if (op == rs3::OP3_APPLY)
+  if (h.tiled_3d == 1) {
+    using R = rs3::Res3R<P, rs3::Res3RDepth<P>::TEZ>;
+    const unsigned nr = (unsigned)rs3::res3r_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], R::TEX, rs3::Res3RDepth<P>::TEZ);
+    if (op == rs3::OP3_APPLY)
+      hipLaunchKernelGGL((k_res3r<P, rs3::OP3_APPLY>), dim3(nr), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                         (const double *)h.lin, Y);
+    else if (op == rs3::OP3_LIN)
+      hipLaunchKernelGGL((k_res3r<P, rs3::OP3_LIN>), dim3(nr), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                         (const double *)nullptr, Y);
+    else
+      hipLaunchKernelGGL((k_res3r<P, rs3::OP3_RES>), dim3(nr), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                         (const double *)nullptr, Y);
+  } else if (op == rs3::OP3_APPLY)
     hipLaunchKernelGGL((k_res3<P, rs3::OP3_APPLY>), dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
                        (const double *)h.lin, Y);
   else if (op == rs3::OP3_LIN)
