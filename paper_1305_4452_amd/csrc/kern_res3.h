@@ -611,10 +611,12 @@ struct Res3R {
   static constexpr int p = P - 1, Q = P;
   static constexpr int TEX = 16 / Q, G = TEX * Q;
   static constexpr int NI = TEX + p, NZ = TEZ + p;
-  static constexpr int n_c = NZ * NI * NI, n_a = NZ * NI * G, n_y = NZ * G * G;
-  static constexpr int n_b = 4 * G * P + 2 * G;
+  static constexpr int GS = G % 2 ? G : G + 1;   // LDS row stride along g0 (odd: rows fall in different banks)
+  static constexpr int n_c = NZ * NI * NI, n_a = NZ * NI * GS, n_y = NZ * G * GS;
+  static constexpr int n_b = 4 * G * P + 2 * G + 2 * TEZ * Q * P + TEZ * Q;
   static constexpr size_t total = (size_t)(n_c + 2 * n_a + 3 * n_y + n_b) * sizeof(double);
   static_assert(G * G <= kThreads, "one lane per Gauss-point column");
+  static_assert(total <= 65536, "static LDS");
 };
 
 template <int P>
@@ -631,8 +633,8 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
                                   const double *__restrict__ lin, double *__restrict__ Y, double *__restrict__ lds) {
   constexpr bool LIN = OP == OP3_LIN;
   using S_ = Res3R<P, TEZ>;
-  constexpr int p = S_::p, Q = S_::Q, TEX = S_::TEX, G = S_::G, NI = S_::NI, NZ = S_::NZ;
-  constexpr int NT = kThreads, L = P * P * P, GP = G * P;
+  constexpr int p = S_::p, Q = S_::Q, TEX = S_::TEX, G = S_::G, GS = S_::GS, NI = S_::NI, NZ = S_::NZ;
+  constexpr int NT = kThreads, L = P * P * P, GP = G * P, NA = NZ * NI * G;
   const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
   const int nt0 = (ne0 + TEX - 1) / TEX, nt1 = (ne1 + TEX - 1) / TEX;
   const int E0 = (tile % nt0) * TEX, E1 = ((tile / nt0) % nt1) * TEX, E2 = (tile / (nt0 * nt1)) * TEZ;
@@ -640,9 +642,10 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
   const int G0 = NE0 * Q, G1 = NE1 * Q;
   const int NI0 = NE0 + p, NI1 = NE1 + p, NI2 = NE2 + p;
   double *c = lds;                                     // [k2][k1][k0]
-  double *A0 = c + S_::n_c, *D0 = A0 + S_::n_a;        // [k2][k1][g0]; later Za, Zb
-  double *Ys = D0 + S_::n_a;                           // [3][k2][g1][g0]
+  double *A0 = c + S_::n_c, *D0 = A0 + S_::n_a;        // [k2][k1][g0] (row stride GS); later Za, Zb
+  double *Ys = D0 + S_::n_a;                           // [3][k2][g1][g0] (row stride GS)
   double *sB = Ys + 3 * S_::n_y, *sW = sB + 4 * GP;
+  double *sB2 = sW + 2 * G, *sW2 = sB2 + 2 * TEZ * Q * P;   // axis-2 rows of the tile: [B|dB][z point][a], weights
   const double *B0 = sB, *dB0 = sB + GP, *B1 = sB + 2 * GP, *dB1 = sB + 3 * GP, *W0 = sW, *W1 = sW + G;
   double *Za = A0, *Zb = D0;
   const int t = threadIdx.x;
@@ -662,6 +665,13 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
     if (i < G0) sW[i] = pb.ax[0].wq[(size_t)E0 * Q + i];
     if (i < G1) sW[G + i] = pb.ax[1].wq[(size_t)E1 * Q + i];
   }
+  for (int i = t; i < TEZ * Q * P; i += NT)
+    if (i / (Q * P) < NE2) {
+      sB2[i] = pb.ax[2].B[(size_t)E2 * Q * P + i];
+      sB2[TEZ * Q * P + i] = pb.ax[2].dB[(size_t)E2 * Q * P + i];
+    }
+  for (int i = t; i < TEZ * Q; i += NT)
+    if (i / Q < NE2) sW2[i] = pb.ax[2].wq[(size_t)E2 * Q + i];
   for (int i = t; i < S_::n_c; i += NT) {
     const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
     if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
@@ -672,7 +682,7 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
   }
   __syncthreads();
   // axis 0: value and derivative per function pair (k1, k2)
-  for (int i = t; i < S_::n_a; i += NT) {
+  for (int i = t; i < NA; i += NT) {
     const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), el0 = g0 / Q;
     if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
     const double *cc = c + (k2 * NI + k1) * NI + el0;
@@ -682,8 +692,9 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
       a += B0[g0 * P + a0] * cc[a0];
       if constexpr (!LIN) d += dB0[g0 * P + a0] * cc[a0];
     }
-    A0[i] = a;
-    if constexpr (!LIN) D0[i] = d;
+    const int o = (k2 * NI + k1) * GS + g0;
+    A0[o] = a;
+    if constexpr (!LIN) D0[o] = d;
   }
   __syncthreads();
   // one lane per Gauss-point column: axis 1, axis 2, the point integrands and the transposed axis 2
@@ -718,7 +729,7 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
       if (k2 < NI2) {
 #pragma unroll
         for (int a1 = 0; a1 < P; ++a1) {
-          const int r = (k2 * NI + el1 + a1) * G + g0;
+          const int r = (k2 * NI + el1 + a1) * GS + g0;
           u += b1[a1] * A0[r];
           if constexpr (!LIN) {
             u01 += b1[a1] * D0[r];
@@ -739,12 +750,12 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
       const double kap = kel ? pb.kel[e] : 1.0;
 #pragma unroll
       for (int q2 = 0; q2 < Q; ++q2) {
-        const size_t o = ((size_t)e2 * Q + q2) * P;
+        const int o = (el2 * Q + q2) * P;
         double b2[P], db2[P];
 #pragma unroll
         for (int a = 0; a < P; ++a) {
-          b2[a] = pb.ax[2].B[o + a];
-          db2[a] = pb.ax[2].dB[o + a];
+          b2[a] = sB2[o + a];
+          db2[a] = sB2[TEZ * Q * P + o + a];
         }
         double u = 0, d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
@@ -754,7 +765,7 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
           d1 += b2[a2] * U10[el2 + a2];
           d2 += db2[a2] * U[el2 + a2];
         }
-        const double W = w01 * pb.ax[2].wq[(size_t)e2 * Q + q2], kw = kap * W;
+        const double W = w01 * sW2[el2 * Q + q2], kw = kap * W;
         if constexpr (LIN) {
           Y[e * L + q0 + Q * (q1 + Q * q2)] = -lam * W * exp(u);
           continue;
@@ -775,7 +786,7 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
 #pragma unroll
     for (int k2 = 0; k2 < NZ; ++k2) {
       if (k2 < NI2) {
-        const int w = (k2 * G + g1) * G + g0;
+        const int w = (k2 * G + g1) * GS + g0;
         Ys[w] = Y0[k2];
         Ys[S_::n_y + w] = Y1[k2];
         Ys[2 * S_::n_y + w] = Y2[k2];
@@ -785,7 +796,7 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
   if constexpr (LIN) return;
   __syncthreads();
   // transposed axis 1: Za = sum B1 Y0, Zb = sum dB1 Y1 + B1 Y2 (over A0 / D0, whose reads are done)
-  for (int i = t; i < S_::n_a; i += NT) {
+  for (int i = t; i < NA; i += NT) {
     const int gg0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI);
     if (gg0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
     double za = 0, zb = 0;
@@ -795,14 +806,14 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
       if (el1 < 0 || el1 >= NE1) continue;
 #pragma unroll
       for (int q1 = 0; q1 < Q; ++q1) {
-        const int gg1 = el1 * Q + q1, w = (k2 * G + gg1) * G + gg0;
+        const int gg1 = el1 * Q + q1, w = (k2 * G + gg1) * GS + gg0;
         const double b = B1[gg1 * P + a1];
         za += b * Ys[w];
         zb += dB1[gg1 * P + a1] * Ys[S_::n_y + w] + b * Ys[2 * S_::n_y + w];
       }
     }
-    Za[i] = za;
-    Zb[i] = zb;
+    Za[(k2 * NI + k1) * GS + gg0] = za;
+    Zb[(k2 * NI + k1) * GS + gg0] = zb;
   }
   __syncthreads();
   // transposed axis 0 and the scatter of the tile's contributions
@@ -816,7 +827,7 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
       if (el0 < 0 || el0 >= NE0) continue;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) {
-        const int gg0 = el0 * Q + q0, w = (k2 * NI + k1) * G + gg0;
+        const int gg0 = el0 * Q + q0, w = (k2 * NI + k1) * GS + gg0;
         r += dB0[gg0 * P + a0] * Za[w] + B0[gg0 * P + a0] * Zb[w];
       }
     }
