@@ -309,6 +309,25 @@ iga_status run_ch3(Handle &h, const double *C, const double *Cd, double theta, d
   return IGA_OK;
 }
 
+constexpr int kChrTEZ = 3;   // depth of the column tiles of the Cahn-Hilliard residual (C^1 quadratics)
+
+template <int P>
+__global__ void __launch_bounds__(rs3::kThreads) k_chr3(DevProblem pb, const double *__restrict__ C,
+                                                        const double *__restrict__ Cd, double theta, double lam,
+                                                        double *__restrict__ R) {
+  __shared__ double lds[rs3::Chr3<P, kChrTEZ>::total / sizeof(double)];
+  rs3::chr3_body<P, kChrTEZ>(pb, (int)blockIdx.x, C, Cd, theta, lam, R, lds);
+}
+
+template <int P>
+iga_status run_chr3(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R) {
+  using S = rs3::Chr3<P, kChrTEZ>;
+  const unsigned nb = (unsigned)rs3::res3r_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], S::TEX, kChrTEZ);
+  hipLaunchKernelGGL(k_chr3<P>, dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, C, Cd, theta, lam, R);
+  IGA_HIP_CHECK(hipGetLastError());
+  return IGA_OK;
+}
+
 template <int P>
 __global__ void __launch_bounds__(rs3::kThreads) k_bih3(DevProblem pb, const double *__restrict__ U,
                                                         double *__restrict__ R) {
@@ -555,7 +574,7 @@ iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, do
   // for comparison)
   if (h.pb.simple_knots && h.tiled_3d) {
     if (h.pb.dim == 3) {
-      if (p == 2) return run_ch3<3>(h, C, Cd, theta, lam, R);
+      if (p == 2) return h.tiled_3d == 1 ? run_chr3<3>(h, C, Cd, theta, lam, R) : run_ch3<3>(h, C, Cd, theta, lam, R);
       if (p == 3) return run_ch3<4>(h, C, Cd, theta, lam, R);
     } else {
       switch (p) {

@@ -837,5 +837,225 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
   }
 }
 
+// Column-register variant of the Cahn-Hilliard residual (the arithmetic of ch3_body, regrouped):
+// tiles of TEX x TEX x TEZ elements with TEX Q <= 16, one lane per Gauss-point column (g0, g1).  The
+// axis-0 contraction (B.c, B'.c, B''.c, B.cdot) goes through LDS; each lane then holds the six axis-1
+// products of its column for all NZ = TEZ + p function planes in registers, forms c, grad c, Lap c and
+// cdot at its points, the point terms S0, F, S2 and the four transposed axis-2 sums in registers; the
+// transposed axis-1 and axis-0 contractions go through LDS.  One FP64 atomic per tile function, the
+// output zeroed before.
+template <int P, int TEZ>
+struct Chr3 {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TEX = 16 / Q, G = TEX * Q, GS = G % 2 ? G : G + 1;
+  static constexpr int NI = TEX + p, NZ = TEZ + p;
+  static constexpr int n_c = NZ * NI * NI, n_a = NZ * NI * GS, n_y = NZ * G * GS;
+  static constexpr int n_b = 6 * G * P + 2 * G + 3 * TEZ * Q * P + TEZ * Q;
+  static constexpr size_t total = (size_t)(2 * n_c + 4 * n_a + 4 * n_y + n_b) * sizeof(double);
+  static_assert(G * G <= kThreads, "one lane per Gauss-point column");
+  static_assert(total <= 65536, "static LDS");
+};
+
+template <int P, int TEZ>
+__device__ inline void chr3_body(const DevProblem &pb, const int tile, const double *__restrict__ Cv,
+                                 const double *__restrict__ Cd, double theta, double lam, double *__restrict__ Y,
+                                 double *__restrict__ lds) {
+  using S_ = Chr3<P, TEZ>;
+  constexpr int p = S_::p, Q = S_::Q, TEX = S_::TEX, G = S_::G, GS = S_::GS, NI = S_::NI, NZ = S_::NZ;
+  constexpr int NT = kThreads, GP = G * P, NA = NZ * NI * G, ZP = TEZ * Q * P;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
+  const int nt0 = (ne0 + TEX - 1) / TEX, nt1 = (ne1 + TEX - 1) / TEX;
+  const int E0 = (tile % nt0) * TEX, E1 = ((tile / nt0) % nt1) * TEX, E2 = (tile / (nt0 * nt1)) * TEZ;
+  const int NE0 = min(TEX, ne0 - E0), NE1 = min(TEX, ne1 - E1), NE2 = min(TEZ, ne2 - E2);
+  const int G0 = NE0 * Q, G1 = NE1 * Q;
+  const int NI0 = NE0 + p, NI1 = NE1 + p, NI2 = NE2 + p;
+  double *c = lds, *cd = c + S_::n_c;                                       // [k2][k1][k0]
+  double *aB = cd + S_::n_c, *aD = aB + S_::n_a, *aE = aD + S_::n_a, *aR = aE + S_::n_a;   // [k2][k1][g0]
+  double *Yb = aR + S_::n_a, *Y0 = Yb + S_::n_y, *Y1 = Y0 + S_::n_y, *Ysl = Y1 + S_::n_y;   // [k2][g1][g0]
+  double *tb = Ysl + S_::n_y, *tw = tb + 6 * GP, *t2 = tw + 2 * G, *w2 = t2 + 3 * ZP;
+  double *Zb = aB, *Zd = aD, *Ze = aE;                                      // transposed axis 1, [k2][k1][g0]
+  const double *B0 = tb, *D0 = tb + GP, *E0t = tb + 2 * GP, *B1 = tb + 3 * GP, *D1 = tb + 4 * GP, *E1t = tb + 5 * GP;
+  const int t = threadIdx.x;
+  for (int i = t; i < GP; i += NT) {
+    if (i / P < G0) {
+      const size_t o = (size_t)E0 * Q * P + i;
+      tb[i] = pb.ax[0].B[o];
+      tb[GP + i] = pb.ax[0].dB[o];
+      tb[2 * GP + i] = pb.ax[0].d2B[o];
+    }
+    if (i / P < G1) {
+      const size_t o = (size_t)E1 * Q * P + i;
+      tb[3 * GP + i] = pb.ax[1].B[o];
+      tb[4 * GP + i] = pb.ax[1].dB[o];
+      tb[5 * GP + i] = pb.ax[1].d2B[o];
+    }
+  }
+  for (int i = t; i < G; i += NT) {
+    if (i < G0) tw[i] = pb.ax[0].wq[(size_t)E0 * Q + i];
+    if (i < G1) tw[G + i] = pb.ax[1].wq[(size_t)E1 * Q + i];
+  }
+  for (int i = t; i < ZP; i += NT)
+    if (i / (Q * P) < NE2) {
+      const size_t o = (size_t)E2 * Q * P + i;
+      t2[i] = pb.ax[2].B[o];
+      t2[ZP + i] = pb.ax[2].dB[o];
+      t2[2 * ZP + i] = pb.ax[2].d2B[o];
+    }
+  for (int i = t; i < TEZ * Q; i += NT)
+    if (i / Q < NE2) w2[i] = pb.ax[2].wq[(size_t)E2 * Q + i];
+  for (int i = t; i < S_::n_c; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+    const int64_t A = wrap_fn(pb.ax[0], E0 + k0) +
+                      (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], E2 + k2));
+    c[i] = Cv[A];
+    cd[i] = Cd[A];
+  }
+  __syncthreads();
+  for (int i = t; i < NA; i += NT) {
+    const int g0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), el0 = g0 / Q;
+    if (g0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+    const int o = (k2 * NI + k1) * NI + el0;
+    double vb = 0, vd = 0, ve = 0, vr = 0;
+#pragma unroll
+    for (int a0 = 0; a0 < P; ++a0) {
+      vb += B0[g0 * P + a0] * c[o + a0];
+      vd += D0[g0 * P + a0] * c[o + a0];
+      ve += E0t[g0 * P + a0] * c[o + a0];
+      vr += B0[g0 * P + a0] * cd[o + a0];
+    }
+    const int w = (k2 * NI + k1) * GS + g0;
+    aB[w] = vb;
+    aD[w] = vd;
+    aE[w] = ve;
+    aR[w] = vr;
+  }
+  __syncthreads();
+  const int g0 = t % G, g1 = t / G;
+  const bool act = t < G * G && g0 < G0 && g1 < G1;
+  if (act) {
+    const int el1 = g1 / Q;
+    double b1[P], d1[P], e1[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      b1[a] = B1[g1 * P + a];
+      d1[a] = D1[g1 * P + a];
+      e1[a] = E1t[g1 * P + a];
+    }
+    // axis 1: bb = B1 B0 c, db = B1 B0' c, be = B1'' B0 c, eb = B1 B0'' c, bd = B1' B0 c, rb = B1 B0 cdot
+    double bb[NZ], db[NZ], be[NZ], eb[NZ], bd[NZ], rb[NZ];
+#pragma unroll
+    for (int k2 = 0; k2 < NZ; ++k2) {
+      double x0 = 0, x1 = 0, x2 = 0, x3 = 0, x4 = 0, x5 = 0;
+      if (k2 < NI2) {
+#pragma unroll
+        for (int a1 = 0; a1 < P; ++a1) {
+          const int r = (k2 * NI + el1 + a1) * GS + g0;
+          x0 += b1[a1] * aB[r];
+          x1 += b1[a1] * aD[r];
+          x2 += e1[a1] * aB[r];
+          x3 += b1[a1] * aE[r];
+          x4 += d1[a1] * aB[r];
+          x5 += b1[a1] * aR[r];
+        }
+      }
+      bb[k2] = x0;
+      db[k2] = x1;
+      be[k2] = x2;
+      eb[k2] = x3;
+      bd[k2] = x4;
+      rb[k2] = x5;
+    }
+    double yb[NZ], y0[NZ], y1[NZ], ys[NZ];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) yb[k] = y0[k] = y1[k] = ys[k] = 0.0;
+    const double w01 = tw[g0] * tw[G + g1];
+#pragma unroll
+    for (int el2 = 0; el2 < TEZ; ++el2) {
+      if (el2 >= NE2) break;
+#pragma unroll
+      for (int q2 = 0; q2 < Q; ++q2) {
+        const int o = (el2 * Q + q2) * P;
+        double cv = 0, c0 = 0, c1 = 0, c2 = 0, lc = 0, cr = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < P; ++a2) {
+          const double b = t2[o + a2], d = t2[ZP + o + a2], e = t2[2 * ZP + o + a2];
+          const int k = el2 + a2;
+          cv += b * bb[k];
+          c0 += b * db[k];
+          c1 += b * bd[k];
+          c2 += d * bb[k];
+          lc += b * (eb[k] + be[k]) + e * bb[k];
+          cr += b * rb[k];
+        }
+        const double W = w01 * w2[el2 * Q + q2];
+        const double M = cv * (1.0 - cv), dM = 1.0 - 2.0 * cv, dmu = 1.0 / (2.0 * theta * cv * (1.0 - cv)) - 2.0;
+        const double sg = W * (M * dmu + lam * dM * lc);
+        const double F0 = sg * c0, F1 = sg * c1, F2 = sg * c2, S0 = W * cr, S2 = W * lam * M * lc;
+#pragma unroll
+        for (int a2 = 0; a2 < P; ++a2) {
+          const double b = t2[o + a2], d = t2[ZP + o + a2], e = t2[2 * ZP + o + a2];
+          const int k = el2 + a2;
+          yb[k] += b * S0 + d * F2 + e * S2;
+          y0[k] += b * F0;
+          y1[k] += b * F1;
+          ys[k] += b * S2;
+        }
+      }
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < NZ; ++k2) {
+      if (k2 < NI2) {
+        const int w = (k2 * G + g1) * GS + g0;
+        Yb[w] = yb[k2];
+        Y0[w] = y0[k2];
+        Y1[w] = y1[k2];
+        Ysl[w] = ys[k2];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < NA; i += NT) {
+    const int gg0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI);
+    if (gg0 >= G0 || k1 >= NI1 || k2 >= NI2) continue;
+    double zb = 0, zd = 0, ze = 0;
+#pragma unroll
+    for (int a1 = 0; a1 <= p; ++a1) {
+      const int el1 = k1 - a1;
+      if (el1 < 0 || el1 >= NE1) continue;
+#pragma unroll
+      for (int q1 = 0; q1 < Q; ++q1) {
+        const int gg1 = el1 * Q + q1, w = (k2 * G + gg1) * GS + gg0, o = gg1 * P + a1;
+        zb += B1[o] * Yb[w] + D1[o] * Y1[w] + E1t[o] * Ysl[w];
+        zd += B1[o] * Y0[w];
+        ze += B1[o] * Ysl[w];
+      }
+    }
+    const int w = (k2 * NI + k1) * GS + gg0;
+    Zb[w] = zb;
+    Zd[w] = zd;
+    Ze[w] = ze;
+  }
+  __syncthreads();
+  for (int i = t; i < S_::n_c; i += NT) {
+    const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+    if (k0 >= NI0 || k1 >= NI1 || k2 >= NI2) continue;
+    double r = 0;
+#pragma unroll
+    for (int a0 = 0; a0 <= p; ++a0) {
+      const int el0 = k0 - a0;
+      if (el0 < 0 || el0 >= NE0) continue;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) {
+        const int gg0 = el0 * Q + q0, w = (k2 * NI + k1) * GS + gg0, o = gg0 * P + a0;
+        r += B0[o] * Zb[w] + D0[o] * Zd[w] + E0t[o] * Ze[w];
+      }
+    }
+    atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
+                 (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], E2 + k2))],
+              r);
+  }
+}
+
 }  // namespace rs3
 }  // namespace iga

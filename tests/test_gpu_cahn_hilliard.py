@@ -32,11 +32,12 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("tiled", [1, 0])
+@pytest.mark.parametrize("tiled", [1, 2, 0])
 @pytest.mark.parametrize("name", list(CASES))
 def test_cahn_hilliard_residual_matches_oracle(name, tiled):
-    """Both on tiles with sum factorisation (the *_tiles cases span several tiles, ragged at the far
-    ends) and one element per workgroup."""
+    """On tiles with sum factorisation (1: column tiles for 3D C^1 quadratics, cubic tiles otherwise;
+    2: cubic tiles; the *_tiles and 3D cases span several tiles, ragged at the far ends) and one
+    element per workgroup (0)."""
     dim, nel, p, periodic = CASES[name]
     print(f"[case] Cahn-Hilliard residual {name} tiled={tiled}", flush=True)
     patch = inputs.unit_box(dim, nel, p)
