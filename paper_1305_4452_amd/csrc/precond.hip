@@ -489,17 +489,108 @@ void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView v
                      vo, T, m[0], m[1], m[2], mu0, mu1, mu2, shift);
 }
 
+// One dense 1D transform of the full box m0 x m1 x m2 along axis AX as a register-tiled product
+// Y = T X (T: m x m row-major; X: the box with axis AX as the reduction index and the other two axes
+// as columns).  A workgroup owns 64 rows x 64 columns; per 16-deep step the T and X tiles are staged
+// in LDS (each with its contiguous direction on consecutive lanes) and every lane accumulates a
+// 4 x 4 block.  With chs.eta0 set, the result is divided by the Cahn-Hilliard eigenvalue (as in
+// k_fdm_axis).
+constexpr int kGM = 64, kGN = 64, kGK = 16;
+
+template <int AX>
+__device__ inline int64_t box_addr(int r, int64_t c, int m0, int m1) {
+  if (AX == 0) return r + (int64_t)m0 * c;
+  if (AX == 1) return (c % m0) + (int64_t)m0 * r + (int64_t)m0 * m1 * (c / m0);
+  return c + (int64_t)m0 * m1 * r;
+}
+
+template <int AX>
+__global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in, double *__restrict__ out,
+                                                  const double *__restrict__ T, int m0, int m1, int m2,
+                                                  const double *__restrict__ mu0, const double *__restrict__ mu1,
+                                                  const double *__restrict__ mu2, ChScale chs) {
+  __shared__ double Ts[kGK][kGM + 1], Xs[kGK][kGN + 1];
+  const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
+  const int64_t ncol = AX == 0 ? (int64_t)m1 * m2 : (AX == 1 ? (int64_t)m0 * m2 : (int64_t)m0 * m1);
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  const int nbr = (m + kGM - 1) / kGM;
+  const int r0 = (blockIdx.x % nbr) * kGM;
+  const int64_t c0 = (int64_t)(blockIdx.x / nbr) * kGN;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < m; k0 += kGK) {
+    // T tile: 16 consecutive k per row on consecutive lanes
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = (t >> 4) * 4 + j, k = t & 15, gr = r0 + row, gk = k0 + k;
+      Ts[k][row] = (gr < m && gk < m) ? T[(int64_t)gr * m + gk] : 0.0;
+    }
+    // X tile: consecutive lanes on the contiguous direction (k for axis 0, columns otherwise)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int k, col;
+      if (AX == 0) {
+        k = t & 15;
+        col = (t >> 4) * 4 + j;
+      } else {
+        k = (t >> 6) * 4 + j;
+        col = t & 63;
+      }
+      const int gk = k0 + k;
+      const int64_t gc = c0 + col;
+      Xs[k][col] = (gk < m && gc < ncol) ? in[box_addr<AX>(gk, gc, m0, m1)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kGK; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = Ts[k][tr * 4 + i];
+        b[i] = Xs[k][tc * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gr = r0 + tr * 4 + i;
+    if (gr >= m) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gc = c0 + tc * 4 + j;
+      if (gc >= ncol) continue;
+      double v = acc[i][j];
+      if (chs.eta0) {
+        int i0, i1, i2;
+        if (AX == 0) { i0 = gr; i1 = (int)(gc % m1); i2 = (int)(gc / m1); }
+        else if (AX == 1) { i0 = (int)(gc % m0); i1 = gr; i2 = (int)(gc / m0); }
+        else { i0 = (int)(gc % m0); i1 = (int)(gc / m0); i2 = gr; }
+        const double a0 = mu0[i0], a1 = mu1[i1], a2 = mu2[i2];
+        const double lam = chs.am + chs.sa * (a0 + a1 + a2) +
+                           chs.sb * (chs.eta0[i0] + chs.eta1[i1] + chs.eta2[i2] + 2.0 * (a0 * a1 + a0 * a2 + a1 * a2));
+        v /= fmax(lam, 0.05 * chs.am);
+      }
+      out[box_addr<AX>(gr, gc, m0, m1)] = v;
+    }
+  }
+}
+
 template <int AX>
 void launch_ch_axis(Handle &h, const double *in, double *out, const double *T, const int *m, const double *const *mu,
                     ChScale chs) {
-  constexpr int TC = 8;
   const int mm = m[AX];
-  const int ncol = AX == 0 ? m[1] * m[2] : (AX == 1 ? m[0] * m[2] : m[0] * m[1]);
-  const size_t lds = 2 * (size_t)mm * (TC + 1) * sizeof(double);
-  const BoxView box{0, 1, m[0], (int64_t)m[0] * m[1]};
-  hipLaunchKernelGGL((k_fdm_axis<AX, TC>), dim3((unsigned)((ncol + TC - 1) / TC)), dim3(256), lds, h.stream, in, box,
-                     out, box, T, m[0], m[1], m[2], mu ? mu[0] : nullptr, mu ? mu[1] : nullptr, mu ? mu[2] : nullptr,
-                     nullptr, chs);
+  const int64_t ncol = AX == 0 ? (int64_t)m[1] * m[2] : (AX == 1 ? (int64_t)m[0] * m[2] : (int64_t)m[0] * m[1]);
+  const int64_t nb = (int64_t)((mm + kGM - 1) / kGM) * ((ncol + kGN - 1) / kGN);
+  hipLaunchKernelGGL((k_fdm_gemm<AX>), dim3((unsigned)nb), dim3(256), 0, h.stream, in, out, T, m[0], m[1], m[2],
+                     mu ? mu[0] : nullptr, mu ? mu[1] : nullptr, mu ? mu[2] : nullptr, chs);
 }
 
 }  // namespace
