@@ -92,7 +92,7 @@ typedef enum {
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):
- *   AUTO:   FDM when every axis has at most 240 non-Dirichlet coefficients, Jacobi otherwise;
+ *   AUTO:   FDM when every axis has at most 512 non-Dirichlet coefficients, Jacobi otherwise;
  *   JACOBI: the inverse diagonal of the Jacobian;
  *   FDM:    fast diagonalisation of a0 A0(x)M1(x)M2 + a1 M0(x)A1(x)M2 + a2 M0(x)M1(x)A2 + c M, the
  *           parametric 1D stiffness / mass matrices of the tensor-product B-spline basis (Sec. 2.1),
@@ -211,7 +211,7 @@ iga_status iga_cahn_hilliard_residual(iga_t h, const double *C_dev, const double
  * Newton step), forcing_max; NULL: defaults.  BiCGStab keeps its scalars on the device and the host
  * tests its residual norm every 4 iterations (every iteration when preconditioned); the report
  * counts the iterations that changed the iterate.  With every axis periodic on uniform knots and at
- * most 256 functions per axis, BiCGStab is right-preconditioned by fast diagonalisation of
+ * most 512 functions per axis, BiCGStab is right-preconditioned by fast diagonalisation of
  * am M + af gamma dt (a K + lambda_ch b B) (M, K the mass and stiffness matrices,
  * B = int Lap N_A Lap N_B, a = 1/(2 theta) - 2 b and b the mean of c (1 - c) over the
  * coefficients: the Jacobian linearised about a uniform state), its 1D eigenbases built at the

@@ -139,7 +139,7 @@ static iga_status newton(Handle &h, double *U, const iga_newton_opts *o_in, iga_
   }
   const bool fdm = h.precond != IGA_PRECOND_JACOBI && h.fdm.ok;
   if (h.precond == IGA_PRECOND_FDM && !fdm)
-    return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs at most 240 unknowns per axis");
+    return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs at most 512 unknowns per axis");
   if (o.check_every <= 0) o.check_every = fdm ? 4 : 16;
   if (o.check_every > 1024) o.check_every = 1024;
   iga_newton_report r{};
@@ -721,7 +721,7 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
     case IGA_OPT_PRECOND:
       if (value < IGA_PRECOND_AUTO || value > IGA_PRECOND_FDM) return fail(IGA_EINVAL, "bad preconditioner");
       if (value == IGA_PRECOND_FDM && !fdm_possible(*h))
-        return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs at most 240 unknowns per axis and a Dirichlet face");
+        return fail(IGA_EUNSUPPORTED, "the FDM preconditioner needs at most 512 unknowns per axis and a Dirichlet face");
       h->precond = (int)value;
       return IGA_OK;
     case IGA_OPT_LAMBDA_BITS: {

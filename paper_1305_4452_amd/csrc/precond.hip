@@ -480,35 +480,45 @@ __global__ void k_fdm_shift_final(const double *__restrict__ part, int nb, doubl
 }
 
 template <int AX>
+void launch_gemm_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView vo, const double *T, const int *m,
+                      const double *mu0, const double *mu1, const double *mu2, const double *shift, ChScale chs);
+
+template <int AX>
 void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView vo, const double *T, const int *m,
                  const double *mu0, const double *mu1, const double *mu2, const double *shift) {
   const int mm = m[AX];
+  if (mm > kFdmLdsMax) {   // long axis: register-tiled product
+    launch_gemm_axis<AX>(h, in, vi, out, vo, T, m, mu0, mu1, mu2, shift, ChScale{});
+    return;
+  }
   const int ncol = AX == 0 ? m[1] * m[2] : (AX == 1 ? m[0] * m[2] : m[0] * m[1]);
   const size_t lds = 2 * (size_t)mm * (kTC + 1) * sizeof(double);
   hipLaunchKernelGGL((k_fdm_axis<AX>), dim3((unsigned)((ncol + kTC - 1) / kTC)), dim3(256), lds, h.stream, in, vi, out,
                      vo, T, m[0], m[1], m[2], mu0, mu1, mu2, shift);
 }
 
-// One dense 1D transform of the full box m0 x m1 x m2 along axis AX as a register-tiled product
-// Y = T X (T: m x m row-major; X: the box with axis AX as the reduction index and the other two axes
-// as columns).  A workgroup owns 64 rows x 64 columns; per 16-deep step the T and X tiles are staged
-// in LDS (each with its contiguous direction on consecutive lanes) and every lane accumulates a
-// 4 x 4 block.  With chs.eta0 set, the result is divided by the Cahn-Hilliard eigenvalue (as in
-// k_fdm_axis).
+// One dense 1D transform along axis AX of the box m0 x m1 x m2 (element (i0, i1, i2) of a view at
+// off + i0 s0 + i1 s1 + i2 s2) as a register-tiled product Y = T X (T: m x m row-major; X: the box with
+// axis AX as the reduction index and the other two axes as columns), for transforms too long for the
+// LDS column tiles of k_fdm_axis.  A workgroup owns 64 rows x 64 columns; per 16-deep step the T and X
+// tiles are staged in LDS (each with its contiguous direction on consecutive lanes) and every lane
+// accumulates a 4 x 4 block.  The result is divided by the Cahn-Hilliard eigenvalue when chs.eta0 is
+// set, else by mu0[i0] + mu1[i1] + mu2[i2] + shift when mu0 is set (as in k_fdm_axis).
 constexpr int kGM = 64, kGN = 64, kGK = 16;
 
 template <int AX>
-__device__ inline int64_t box_addr(int r, int64_t c, int m0, int m1) {
-  if (AX == 0) return r + (int64_t)m0 * c;
-  if (AX == 1) return (c % m0) + (int64_t)m0 * r + (int64_t)m0 * m1 * (c / m0);
-  return c + (int64_t)m0 * m1 * r;
+__device__ inline void box_coords(int r, int64_t c, int m0, int m1, int &i0, int &i1, int &i2) {
+  if (AX == 0) { i0 = r; i1 = (int)(c % m1); i2 = (int)(c / m1); }
+  else if (AX == 1) { i0 = (int)(c % m0); i1 = r; i2 = (int)(c / m0); }
+  else { i0 = (int)(c % m0); i1 = (int)(c / m0); i2 = r; }
 }
 
 template <int AX>
-__global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in, double *__restrict__ out,
-                                                  const double *__restrict__ T, int m0, int m1, int m2,
+__global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in, BoxView vi, double *__restrict__ out,
+                                                  BoxView vo, const double *__restrict__ T, int m0, int m1, int m2,
                                                   const double *__restrict__ mu0, const double *__restrict__ mu1,
-                                                  const double *__restrict__ mu2, ChScale chs) {
+                                                  const double *__restrict__ mu2, const double *__restrict__ shift,
+                                                  ChScale chs) {
   __shared__ double Ts[kGK][kGM + 1], Xs[kGK][kGN + 1];
   const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
   const int64_t ncol = AX == 0 ? (int64_t)m1 * m2 : (AX == 1 ? (int64_t)m0 * m2 : (int64_t)m0 * m1);
@@ -541,7 +551,13 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
       }
       const int gk = k0 + k;
       const int64_t gc = c0 + col;
-      Xs[k][col] = (gk < m && gc < ncol) ? in[box_addr<AX>(gk, gc, m0, m1)] : 0.0;
+      double v = 0.0;
+      if (gk < m && gc < ncol) {
+        int i0, i1, i2;
+        box_coords<AX>(gk, gc, m0, m1, i0, i1, i2);
+        v = in[vi.off + i0 * vi.s0 + i1 * vi.s1 + i2 * vi.s2];
+      }
+      Xs[k][col] = v;
     }
     __syncthreads();
 #pragma unroll
@@ -559,6 +575,7 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
     }
     __syncthreads();
   }
+  const double c_shift = (mu0 && shift) ? *shift : 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int gr = r0 + tr * 4 + i;
@@ -567,35 +584,43 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
     for (int j = 0; j < 4; ++j) {
       const int64_t gc = c0 + tc * 4 + j;
       if (gc >= ncol) continue;
+      int i0, i1, i2;
+      box_coords<AX>(gr, gc, m0, m1, i0, i1, i2);
       double v = acc[i][j];
       if (chs.eta0) {
-        int i0, i1, i2;
-        if (AX == 0) { i0 = gr; i1 = (int)(gc % m1); i2 = (int)(gc / m1); }
-        else if (AX == 1) { i0 = (int)(gc % m0); i1 = gr; i2 = (int)(gc / m0); }
-        else { i0 = (int)(gc % m0); i1 = (int)(gc / m0); i2 = gr; }
         const double a0 = mu0[i0], a1 = mu1[i1], a2 = mu2[i2];
         const double lam = chs.am + chs.sa * (a0 + a1 + a2) +
                            chs.sb * (chs.eta0[i0] + chs.eta1[i1] + chs.eta2[i2] + 2.0 * (a0 * a1 + a0 * a2 + a1 * a2));
         v /= fmax(lam, 0.05 * chs.am);
+      } else if (mu0) {
+        v /= mu0[i0] + mu1[i1] + (mu2 ? mu2[i2] : 0.0) + c_shift;
       }
-      out[box_addr<AX>(gr, gc, m0, m1)] = v;
+      out[vo.off + i0 * vo.s0 + i1 * vo.s1 + i2 * vo.s2] = v;
     }
   }
 }
 
 template <int AX>
-void launch_ch_axis(Handle &h, const double *in, double *out, const double *T, const int *m, const double *const *mu,
-                    ChScale chs) {
+void launch_gemm_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView vo, const double *T, const int *m,
+                      const double *mu0, const double *mu1, const double *mu2, const double *shift, ChScale chs) {
   const int mm = m[AX];
   const int64_t ncol = AX == 0 ? (int64_t)m[1] * m[2] : (AX == 1 ? (int64_t)m[0] * m[2] : (int64_t)m[0] * m[1]);
   const int64_t nb = (int64_t)((mm + kGM - 1) / kGM) * ((ncol + kGN - 1) / kGN);
-  hipLaunchKernelGGL((k_fdm_gemm<AX>), dim3((unsigned)nb), dim3(256), 0, h.stream, in, out, T, m[0], m[1], m[2],
-                     mu ? mu[0] : nullptr, mu ? mu[1] : nullptr, mu ? mu[2] : nullptr, chs);
+  hipLaunchKernelGGL((k_fdm_gemm<AX>), dim3((unsigned)nb), dim3(256), 0, h.stream, in, vi, out, vo, T, m[0], m[1], m[2],
+                     mu0, mu1, mu2, shift, chs);
+}
+
+template <int AX>
+void launch_ch_axis(Handle &h, const double *in, double *out, const double *T, const int *m, const double *const *mu,
+                    ChScale chs) {
+  const BoxView box{0, 1, m[0], (int64_t)m[0] * m[1]};
+  launch_gemm_axis<AX>(h, in, box, out, box, T, m, mu ? mu[0] : nullptr, mu ? mu[1] : nullptr, mu ? mu[2] : nullptr,
+                       nullptr, chs);
 }
 
 }  // namespace
 
-// Cahn-Hilliard fast diagonalisation: every axis periodic, x = xi without weights, at most 256
+// Cahn-Hilliard fast diagonalisation: every axis periodic, x = xi without weights, at most kFdmMax
 // functions per axis, and the second-derivative matrix diagonal in the (A, M) eigenbasis (uniform
 // knots); otherwise chfdm_ok stays 0 and the Krylov solve runs without a preconditioner.  In 2D
 // the third axis has one function with mu = eta = 0.
@@ -614,7 +639,7 @@ iga_status ensure_chfdm(Handle &h) {
   }
   for (int d = 0; d < pb.dim; ++d) {
     const int n = pb.n[d];
-    if (!pb.ax[d].nper || n > 256 || h.hsepH[d].empty()) return IGA_OK;
+    if (!pb.ax[d].nper || n > kFdmMax || h.hsepH[d].empty()) return IGA_OK;
     std::vector<double> A((size_t)n * n, 0.0), M((size_t)n * n, 0.0), H((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i)
       for (int o = 0; o < W; ++o) {
