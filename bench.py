@@ -80,7 +80,7 @@ def rowgather_flops(n: int, p: int, b1: int, b2: int) -> float:
 # WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device
 # copy (FETCH x2.0, WRITE x1.0); the summary is under profiles/.  Valid only for the kernel source
 # the counters were taken on (SHA-1 of rg_sep.hip); otherwise the traffic is reported as null.
-TRAFFIC = {"src_sha1": "ea39d02d563e0d9c1c9ea2ab8ae335369d44480c", "fetch_kib": 130359, "write_kib": 813783,
+TRAFFIC = {"src_sha1": "2c8a67b0f7b196d84aeef08952c5bf9b59454208", "fetch_kib": 119467, "write_kib": 814773,
            "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -135,6 +135,17 @@ def bench_batched(n: int):
     t_batch = time.perf_counter() - t
     print(f"[bench] batched {n}: {t_batch:.3f} s", file=sys.stderr, flush=True)
     sols = b.unpack(U.cpu().numpy())
+    # the same batch with FP32 Jacobian values (FP64 residuals and Krylov vectors: Newton refines to the
+    # FP64 solution)
+    U32 = torch.as_tensor(U0, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    per32, summ32 = b.newton_solve(U32, atol=1e-10, jac_prec=iga.IGA_FP32, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t_batch32 = time.perf_counter() - t
+    sols32 = b.unpack(U32.cpu().numpy())
+    diff32 = max(float(np.abs(a - r).max() / max(np.abs(r).max(), 1e-300)) for a, r in zip(sols32, sols))
+    print(f"[bench] batched {n}, FP32 Jacobian values: {t_batch32:.3f} s", file=sys.stderr, flush=True)
     b.close()
     # per-instance FP64 Newton, once with the batched solver's Jacobi-CG (same algorithm) and once
     # with the single-problem default (fast-diagonalisation preconditioner for these separable squares)
@@ -164,6 +175,10 @@ def bench_batched(n: int):
                 speedup_vs_default_precond=t_def / t_batch, batched_converged=int(sum(p["converged"] for p in per)),
                 per_instance_converged=conv_single, max_rel_diff=maxdiff, graph_launches=summ["graph_launches"],
                 newton_steps=summ["newton_steps"], tune_ms=summ["t_tune_ms"], create_s=t_create,
+                batched_fp32_refined_s=t_batch32,
+                batched_fp32_refined_converged=int(sum(p["converged"] for p in per32)),
+                batched_fp32_refined_newton_steps=summ32["newton_steps"],
+                batched_fp32_refined_max_rel_diff_vs_fp64=diff32,
                 t_newton_step_graphs_ms=summ["t_jacobian_ms"], t_extra_cg_chunks_ms=summ["t_krylov_ms"],
                 tuned_shapes=_tuned_shapes())
 
@@ -551,8 +566,8 @@ def cpu_full_assembly(w, reps: int = 5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=200, help="untimed steps (also bring the GPU clocks up)")
     ap.add_argument("--nel", type=int, default=64)
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
