@@ -135,21 +135,22 @@ def train(net, X, T, epochs=20, batch=128, lr=2e-3, seed=12, log=None):
     return hist
 
 
-def predict(net, std, logk, lam, batch=256, smooth=0):
+def predict(net, std, logk, lam, batch=None, smooth=0):
     """Network output -> interior coefficients: the network predicts the standardised U/lambda
     (which removes the lambda scale, u ~ lambda v for small lambda); libiga un-standardises and
-    multiplies by lambda."""
+    multiplies by lambda.  Batches of `batch` instances (default: as many as the network was
+    created for); the guesses are copied back once."""
     import torch
-    X = std.x(logk, lam)
-    lam = np.asarray(lam, dtype=np.float32).reshape(-1)
+    batch = batch or net.bmax
+    X = torch.as_tensor(std.x(logk, lam), device="cuda")
+    lam = torch.as_tensor(np.asarray(lam, dtype=np.float32).reshape(-1), device="cuda")
     mu = torch.as_tensor(std.t_mu, dtype=torch.float32, device="cuda")
     out = []
     for s in range(0, len(X), batch):
-        xb = torch.as_tensor(X[s:s + batch], device="cuda")
-        y = net.forward(xb)
-        net.postprocess(y, mu, std.t_sd, torch.as_tensor(lam[s:s + batch], device="cuda"), smooth)
-        out.append(y.cpu().numpy())
-    return np.concatenate(out).astype(np.float64)
+        y = net.forward(X[s:s + batch])
+        net.postprocess(y, mu, std.t_sd, lam[s:s + batch], smooth)
+        out.append(y)
+    return torch.cat(out).cpu().numpy().astype(np.float64)
 
 
 def _solve_from(b, starts, atol, max_newton=50):
@@ -264,7 +265,7 @@ def run(n_train=20000, n_test=2000, epochs=40, batch=128, lr=2e-3, log=print, la
     lam = np.array([tr[i][1] for i in keep])
     tgt = np.array([interior(sols_tr[i]) / tr[i][1] for i in keep])     # U / lambda
     std = Standardiser(logk, lam, tgt)
-    net = GuessNet(batch_max=max(batch, 256))
+    net = GuessNet(batch_max=max(batch, 512))   # the held-out set is predicted in batches of 512
     net.set_weights(init_weights())
     net.set_loss(lap_weight)
     t = time.perf_counter()
