@@ -153,10 +153,14 @@ def predict(net, std, logk, lam, batch=None, smooth=0):
     return torch.cat(out).cpu().numpy().astype(np.float64)
 
 
-def _solve_from(b, starts, atol, max_newton=50):
-    """Newton on an existing batch from the given starts; returns solutions, reports, seconds."""
+def _solve_from(b, starts, atol, max_newton=50, U=None):
+    """Newton on an existing batch from the given starts; returns solutions, reports, seconds.  With a
+    device buffer U (reused across calls) the batch's captured step graph is reused too."""
     import torch
-    U = torch.as_tensor(b.pack(starts), device="cuda")
+    if U is None:
+        U = torch.as_tensor(b.pack(starts), device="cuda")
+    else:
+        U.copy_(torch.as_tensor(b.pack(starts)))
     torch.cuda.synchronize()
     t = time.perf_counter()
     per, _ = b.newton_solve(U, atol=atol, max_newton=max_newton, raise_on_fail=False)
@@ -195,6 +199,7 @@ def evaluate(net, std, test, sols_ref, atol=1e-10, chunk=1000, corrupt=None):
     `corrupt(guesses)` (tests only) perturbs the guesses to exercise the fallback."""
     import torch
     ws = [w for _, _, w in test]
+    predict(net, std, [test[0][0]], [test[0][1]])   # untimed: first launches load the kernels
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     guesses = predict(net, std, [l for l, _, _ in test], [lam for _, lam, _ in test])
@@ -220,8 +225,10 @@ def evaluate(net, std, test, sols_ref, atol=1e-10, chunk=1000, corrupt=None):
         bad = ~np.isfinite(eg) | (eg > ez)
         fallbacks += int(bad.sum())
         checked = [zeros[i] if bad[i] else Ug[s + i] for i in range(len(part))]
+        Ubuf = torch.empty(b.N, dtype=torch.float64, device="cuda")
+        _solve_from(b, zeros, atol, U=Ubuf)   # untimed: captures the step graph the timed solves replay
         for key, starts, extra in (("zero", zeros, 0.0), ("learned_raw", raw, 0.0), ("learned_checked", checked, t_check)):
-            out, per, dt = _solve_from(b, starts, atol)
+            out, per, dt = _solve_from(b, starts, atol, U=Ubuf)
             r = res[key]
             r["time"] += dt + extra
             for i in range(len(part)):
