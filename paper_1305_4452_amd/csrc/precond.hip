@@ -500,11 +500,12 @@ void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView v
 // One dense 1D transform along axis AX of the box m0 x m1 x m2 (element (i0, i1, i2) of a view at
 // off + i0 s0 + i1 s1 + i2 s2) as a register-tiled product Y = T X (T: m x m row-major; X: the box with
 // axis AX as the reduction index and the other two axes as columns), for transforms too long for the
-// LDS column tiles of k_fdm_axis.  A workgroup owns 64 rows x 64 columns; per 16-deep step the T and X
-// tiles are staged in LDS (each with its contiguous direction on consecutive lanes) and every lane
-// accumulates a 4 x 4 block.  The result is divided by the Cahn-Hilliard eigenvalue when chs.eta0 is
-// set, else by mu0[i0] + mu1[i1] + mu2[i2] + shift when mu0 is set (as in k_fdm_axis).
-constexpr int kGM = 64, kGN = 64, kGK = 16;
+// LDS column tiles of k_fdm_axis.  A workgroup owns 128 rows x 128 columns; per 8-deep step the T and
+// X tiles are staged in LDS (each with its contiguous direction on consecutive lanes) and every lane
+// accumulates an 8 x 8 block (16 LDS reads per 64 multiply-adds).  The result is divided by the
+// Cahn-Hilliard eigenvalue when chs.eta0 is set, else by mu0[i0] + mu1[i1] + mu2[i2] + shift when mu0
+// is set (as in k_fdm_axis).
+constexpr int kGM = 128, kGN = 128, kGK = 8, kGR = 8;
 
 template <int AX>
 __device__ inline void box_coords(int r, int64_t c, int m0, int m1, int &i0, int &i1, int &i2) {
@@ -519,23 +520,23 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
                                                   const double *__restrict__ mu0, const double *__restrict__ mu1,
                                                   const double *__restrict__ mu2, const double *__restrict__ shift,
                                                   ChScale chs) {
-  __shared__ double Ts[kGK][kGM + 1], Xs[kGK][kGN + 1];
+  __shared__ __align__(16) double Ts[kGK][kGM + 2], Xs[kGK][kGN + 2];
   const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
   const int64_t ncol = AX == 0 ? (int64_t)m1 * m2 : (AX == 1 ? (int64_t)m0 * m2 : (int64_t)m0 * m1);
   const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
   const int nbr = (m + kGM - 1) / kGM;
   const int r0 = (blockIdx.x % nbr) * kGM;
   const int64_t c0 = (int64_t)(blockIdx.x / nbr) * kGN;
-  double acc[4][4];
+  double acc[kGR][kGR];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kGR; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < kGR; ++j) acc[i][j] = 0.0;
   for (int k0 = 0; k0 < m; k0 += kGK) {
-    // T tile: 16 consecutive k per row on consecutive lanes
+    // T tile: 8 consecutive k per row on consecutive lanes
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int row = (t >> 4) * 4 + j, k = t & 15, gr = r0 + row, gk = k0 + k;
+      const int k = t & 7, row = (t >> 3) + 32 * j, gr = r0 + row, gk = k0 + k;
       Ts[k][row] = (gr < m && gk < m) ? T[(int64_t)gr * m + gk] : 0.0;
     }
     // X tile: consecutive lanes on the contiguous direction (k for axis 0, columns otherwise)
@@ -543,11 +544,11 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
     for (int j = 0; j < 4; ++j) {
       int k, col;
       if (AX == 0) {
-        k = t & 15;
-        col = (t >> 4) * 4 + j;
+        k = t & 7;
+        col = (t >> 3) + 32 * j;
       } else {
-        k = (t >> 6) * 4 + j;
-        col = t & 63;
+        k = (t >> 7) + 2 * j;
+        col = t & 127;
       }
       const int gk = k0 + k;
       const int64_t gc = c0 + col;
@@ -562,27 +563,27 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kGK; ++k) {
-      double a[4], b[4];
+      double a[kGR], b[kGR];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = Ts[k][tr * 4 + i];
-        b[i] = Xs[k][tc * 4 + i];
+      for (int i = 0; i < kGR; ++i) {
+        a[i] = Ts[k][tr * kGR + i];
+        b[i] = Xs[k][tc * kGR + i];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < kGR; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int j = 0; j < kGR; ++j) acc[i][j] += a[i] * b[j];
     }
     __syncthreads();
   }
   const double c_shift = (mu0 && shift) ? *shift : 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gr = r0 + tr * 4 + i;
+  for (int i = 0; i < kGR; ++i) {
+    const int gr = r0 + tr * kGR + i;
     if (gr >= m) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t gc = c0 + tc * 4 + j;
+    for (int j = 0; j < kGR; ++j) {
+      const int64_t gc = c0 + tc * kGR + j;
       if (gc >= ncol) continue;
       int i0, i1, i2;
       box_coords<AX>(gr, gc, m0, m1, i0, i1, i2);
