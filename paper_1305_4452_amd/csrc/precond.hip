@@ -500,12 +500,12 @@ void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView v
 // One dense 1D transform along axis AX of the box m0 x m1 x m2 (element (i0, i1, i2) of a view at
 // off + i0 s0 + i1 s1 + i2 s2) as a register-tiled product Y = T X (T: m x m row-major; X: the box with
 // axis AX as the reduction index and the other two axes as columns), for transforms too long for the
-// LDS column tiles of k_fdm_axis.  A workgroup owns 128 rows x 128 columns; per 8-deep step the T and
-// X tiles are staged in LDS (each with its contiguous direction on consecutive lanes) and every lane
-// accumulates an 8 x 8 block (16 LDS reads per 64 multiply-adds).  The result is divided by the
+// LDS column tiles of k_fdm_axis.  A workgroup owns 16 R rows x 16 R columns (R = 8 for large
+// boxes, 4 or 2 where larger tiles would leave the chip idle); per (64 / R)-deep step the T and X tiles
+// are staged in LDS (each with its contiguous direction on consecutive lanes) and every lane
+// accumulates an R x R block (2 R LDS reads per R^2 multiply-adds).  The result is divided by the
 // Cahn-Hilliard eigenvalue when chs.eta0 is set, else by mu0[i0] + mu1[i1] + mu2[i2] + shift when mu0
 // is set (as in k_fdm_axis).
-constexpr int kGM = 128, kGN = 128, kGK = 8, kGR = 8;
 
 template <int AX>
 __device__ inline void box_coords(int r, int64_t c, int m0, int m1, int &i0, int &i1, int &i2) {
@@ -514,12 +514,13 @@ __device__ inline void box_coords(int r, int64_t c, int m0, int m1, int &i0, int
   else { i0 = (int)(c % m0); i1 = (int)(c / m0); i2 = r; }
 }
 
-template <int AX>
+template <int AX, int kGR>
 __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in, BoxView vi, double *__restrict__ out,
                                                   BoxView vo, const double *__restrict__ T, int m0, int m1, int m2,
                                                   const double *__restrict__ mu0, const double *__restrict__ mu1,
                                                   const double *__restrict__ mu2, const double *__restrict__ shift,
                                                   ChScale chs) {
+  constexpr int kGM = 16 * kGR, kGN = 16 * kGR, kGK = 64 / kGR;   // 1024 entries per staged tile
   __shared__ __align__(16) double Ts[kGK][kGM + 2], Xs[kGK][kGN + 2];
   const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
   const int64_t ncol = AX == 0 ? (int64_t)m1 * m2 : (AX == 1 ? (int64_t)m0 * m2 : (int64_t)m0 * m1);
@@ -533,10 +534,10 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
 #pragma unroll
     for (int j = 0; j < kGR; ++j) acc[i][j] = 0.0;
   for (int k0 = 0; k0 < m; k0 += kGK) {
-    // T tile: 8 consecutive k per row on consecutive lanes
+    // T tile: kGK consecutive k per row on consecutive lanes
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = t & 7, row = (t >> 3) + 32 * j, gr = r0 + row, gk = k0 + k;
+      const int k = t % kGK, row = t / kGK + (256 / kGK) * j, gr = r0 + row, gk = k0 + k;
       Ts[k][row] = (gr < m && gk < m) ? T[(int64_t)gr * m + gk] : 0.0;
     }
     // X tile: consecutive lanes on the contiguous direction (k for axis 0, columns otherwise)
@@ -544,11 +545,11 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
     for (int j = 0; j < 4; ++j) {
       int k, col;
       if (AX == 0) {
-        k = t & 7;
-        col = (t >> 3) + 32 * j;
+        k = t % kGK;
+        col = t / kGK + (256 / kGK) * j;
       } else {
-        k = (t >> 7) + 2 * j;
-        col = t & 127;
+        k = t / kGN + (256 / kGN) * j;
+        col = t % kGN;
       }
       const int gk = k0 + k;
       const int64_t gc = c0 + col;
@@ -606,9 +607,19 @@ void launch_gemm_axis(Handle &h, const double *in, BoxView vi, double *out, BoxV
                       const double *mu0, const double *mu1, const double *mu2, const double *shift, ChScale chs) {
   const int mm = m[AX];
   const int64_t ncol = AX == 0 ? (int64_t)m[1] * m[2] : (AX == 1 ? (int64_t)m[0] * m[2] : (int64_t)m[0] * m[1]);
-  const int64_t nb = (int64_t)((mm + kGM - 1) / kGM) * ((ncol + kGN - 1) / kGN);
-  hipLaunchKernelGGL((k_fdm_gemm<AX>), dim3((unsigned)nb), dim3(256), 0, h.stream, in, vi, out, vo, T, m[0], m[1], m[2],
-                     mu0, mu1, mu2, shift, chs);
+  // the largest per-lane block that still gives at least 1024 workgroups (4 per CU)
+  auto blocks = [&](int R) { return (int64_t)((mm + 16 * R - 1) / (16 * R)) * ((ncol + 16 * R - 1) / (16 * R)); };
+  const int R = blocks(8) >= 1024 ? 8 : (blocks(4) >= 1024 ? 4 : 2);
+  const unsigned nb = (unsigned)blocks(R);
+  if (R == 8)
+    hipLaunchKernelGGL((k_fdm_gemm<AX, 8>), dim3(nb), dim3(256), 0, h.stream, in, vi, out, vo, T, m[0], m[1], m[2], mu0,
+                       mu1, mu2, shift, chs);
+  else if (R == 4)
+    hipLaunchKernelGGL((k_fdm_gemm<AX, 4>), dim3(nb), dim3(256), 0, h.stream, in, vi, out, vo, T, m[0], m[1], m[2], mu0,
+                       mu1, mu2, shift, chs);
+  else
+    hipLaunchKernelGGL((k_fdm_gemm<AX, 2>), dim3(nb), dim3(256), 0, h.stream, in, vi, out, vo, T, m[0], m[1], m[2], mu0,
+                       mu1, mu2, shift, chs);
 }
 
 template <int AX>
