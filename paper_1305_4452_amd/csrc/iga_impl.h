@@ -117,7 +117,6 @@ __device__ inline int64_t csr_slot(const DevProblem &pb, int i0, int i1, int i2,
 // generalised eigenvalues times the axis coefficient a_d, and the 1D basis integrals (row sums
 // of the mass matrix).
 constexpr int kFdmMax = 512;      // longest axis (non-Dirichlet coefficients) of the FDM preconditioner
-constexpr int kFdmLdsMax = 240;   // longest axis of the LDS column-tile transform (longer: tiled products)
 struct FdmData {
   int ok;
   int lo[3], m[3];

@@ -352,7 +352,6 @@ iga_status ensure_fdm(Handle &h) {
 // ---------------------------------------------------------------------------------------------
 namespace {
 
-constexpr int kTC = 16;   // columns per block of a 1D transform (8 for the Cahn-Hilliard transforms of up to 256)
 
 // Eigenvalue of the Cahn-Hilliard preconditioner am M + sa K + sb B in the product basis: with
 // V^T M V = I, V^T A V = diag(mu), V^T H V = diag(eta) per axis, M = M0 M1 M2, K = sum_d A_d (x) M (x) M
@@ -367,66 +366,6 @@ struct ChScale {
 struct BoxView {
   int64_t off, s0, s1, s2;   // element (i0,i1,i2) of the box at off + i0 s0 + i1 s1 + i2 s2
 };
-
-// out(.., i, ..) = sum_k T[i m + k] in(.., k, ..) along axis AX of the box m0 x m1 x m2; the
-// other two axes form the columns, kTC columns per block, staged in LDS.  With mu != null the
-// result is divided by mu0[i0] + mu1[i1] + mu2[i2] + shift.
-template <int AX, int kTC = kTC>
-__global__ void __launch_bounds__(256) k_fdm_axis(const double *__restrict__ in, BoxView vi, double *__restrict__ out,
-                                                  BoxView vo, const double *__restrict__ T, int m0, int m1, int m2,
-                                                  const double *__restrict__ mu0, const double *__restrict__ mu1,
-                                                  const double *__restrict__ mu2, const double *__restrict__ shift,
-                                                  ChScale chs = ChScale{}) {
-  extern __shared__ double lds[];
-  const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
-  const int ca = AX == 0 ? m1 : m0;                       // faster column axis extent
-  const int ncol = AX == 0 ? m1 * m2 : (AX == 1 ? m0 * m2 : m0 * m1);
-  double *x = lds, *y = lds + (size_t)m * (kTC + 1);     // [m][kTC+1] each
-  const int c0 = blockIdx.x * kTC, t = threadIdx.x;
-  auto coords = [&](int k, int c, int &i0, int &i1, int &i2) {
-    const int a = c % ca, b = c / ca;
-    if (AX == 0) { i0 = k; i1 = a; i2 = b; }
-    else if (AX == 1) { i0 = a; i1 = k; i2 = b; }
-    else { i0 = a; i1 = b; i2 = k; }
-  };
-  // load: axis 0 walks k fastest (contiguous), the others walk the columns (i0) fastest
-  for (int e = t; e < m * kTC; e += 256) {
-    const int k = AX == 0 ? e % m : e / kTC, cl = AX == 0 ? e / m : e % kTC, c = c0 + cl;
-    double v = 0;
-    if (c < ncol) {
-      int i0, i1, i2;
-      coords(k, c, i0, i1, i2);
-      v = in[vi.off + i0 * vi.s0 + i1 * vi.s1 + i2 * vi.s2];
-    }
-    x[(size_t)k * (kTC + 1) + cl] = v;
-  }
-  __syncthreads();
-  const int cl = t % kTC, g = t / kTC;
-  for (int i = g; i < m; i += 256 / kTC) {
-    const double *Ti = T + (size_t)i * m;
-    double s = 0;
-    for (int k = 0; k < m; ++k) s += Ti[k] * x[(size_t)k * (kTC + 1) + cl];
-    y[(size_t)i * (kTC + 1) + cl] = s;
-  }
-  __syncthreads();
-  const double c_shift = (mu0 && shift) ? *shift : 0.0;   // the Cahn-Hilliard scaling passes no shift
-  for (int e = t; e < m * kTC; e += 256) {
-    const int i = AX == 0 ? e % m : e / kTC, cl2 = AX == 0 ? e / m : e % kTC, c = c0 + cl2;
-    if (c >= ncol) continue;
-    int i0, i1, i2;
-    coords(i, c, i0, i1, i2);
-    double v = y[(size_t)i * (kTC + 1) + cl2];
-    if (chs.eta0) {
-      const double a0 = mu0[i0], a1 = mu1[i1], a2 = mu2[i2];
-      const double lam = chs.am + chs.sa * (a0 + a1 + a2) +
-                         chs.sb * (chs.eta0[i0] + chs.eta1[i1] + chs.eta2[i2] + 2.0 * (a0 * a1 + a0 * a2 + a1 * a2));
-      v /= fmax(lam, 0.05 * chs.am);
-    } else if (mu0) {
-      v /= mu0[i0] + mu1[i1] + (mu2 ? mu2[i2] : 0.0) + c_shift;
-    }
-    out[vo.off + i0 * vo.s0 + i1 * vo.s1 + i2 * vo.s2] = v;
-  }
-}
 
 __global__ void k_copy(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += gridDim.x * (int64_t)blockDim.x) b[i] = a[i];
@@ -486,26 +425,17 @@ void launch_gemm_axis(Handle &h, const double *in, BoxView vi, double *out, BoxV
 template <int AX>
 void launch_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView vo, const double *T, const int *m,
                  const double *mu0, const double *mu1, const double *mu2, const double *shift) {
-  const int mm = m[AX];
-  if (mm > kFdmLdsMax) {   // long axis: register-tiled product
-    launch_gemm_axis<AX>(h, in, vi, out, vo, T, m, mu0, mu1, mu2, shift, ChScale{});
-    return;
-  }
-  const int ncol = AX == 0 ? m[1] * m[2] : (AX == 1 ? m[0] * m[2] : m[0] * m[1]);
-  const size_t lds = 2 * (size_t)mm * (kTC + 1) * sizeof(double);
-  hipLaunchKernelGGL((k_fdm_axis<AX>), dim3((unsigned)((ncol + kTC - 1) / kTC)), dim3(256), lds, h.stream, in, vi, out,
-                     vo, T, m[0], m[1], m[2], mu0, mu1, mu2, shift);
+  launch_gemm_axis<AX>(h, in, vi, out, vo, T, m, mu0, mu1, mu2, shift, ChScale{});
 }
 
 // One dense 1D transform along axis AX of the box m0 x m1 x m2 (element (i0, i1, i2) of a view at
 // off + i0 s0 + i1 s1 + i2 s2) as a register-tiled product Y = T X (T: m x m row-major; X: the box with
-// axis AX as the reduction index and the other two axes as columns), for transforms too long for the
-// LDS column tiles of k_fdm_axis.  A workgroup owns 16 R rows x 16 R columns (R = 8 for large
-// boxes, 4 or 2 where larger tiles would leave the chip idle); per (64 / R)-deep step the T and X tiles
-// are staged in LDS (each with its contiguous direction on consecutive lanes) and every lane
-// accumulates an R x R block (2 R LDS reads per R^2 multiply-adds).  The result is divided by the
-// Cahn-Hilliard eigenvalue when chs.eta0 is set, else by mu0[i0] + mu1[i1] + mu2[i2] + shift when mu0
-// is set (as in k_fdm_axis).
+// axis AX as the reduction index and the other two axes as columns).  A workgroup owns 16 R rows x
+// 16 R columns (R = 8 for large boxes, 4 or 2 where larger tiles would leave the chip idle); per
+// (64 / R)-deep step the T and X tiles are staged in LDS (each with its contiguous direction on
+// consecutive lanes) and every lane accumulates an R x R block (2 R LDS reads per R^2 multiply-adds).
+// The result is divided by the Cahn-Hilliard eigenvalue when chs.eta0 is set, else by
+// mu0[i0] + mu1[i1] + mu2[i2] + shift when mu0 is set (the scaling of the third forward transform).
 
 template <int AX>
 __device__ inline void box_coords(int r, int64_t c, int m0, int m1, int &i0, int &i1, int &i2) {
