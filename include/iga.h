@@ -84,11 +84,16 @@ typedef enum {
   IGA_OPT_ND_SCATTER = 7,    /* IGA_JAC_LOCAL_ND: 0 FP64 atomics in one launch (default), 1 colour
                                 by colour with plain adds ((p+1)^d launches, no two workgroups of a
                                 launch share a value) */
-  IGA_OPT_TILED_3D = 8       /* 3D residual and matrix-free apply with x = xi, no weights, no source:
-                                1 by tiles of elements (default: (16/Q)^2 x 4 elements with one lane per
-                                Gauss-point column), 2 by cubic tiles of elements, 0 one element per
-                                workgroup; 1 and 2 also select tiles for the 3D fourth-order operator on
-                                x = xi without weights and the 2D and 3D Cahn-Hilliard residual */
+  IGA_OPT_TILED_3D = 8,      /* 3D residual and matrix-free apply with x = xi, no weights, no source:
+                                1 by tiles of elements (default: (16/Q)^2 elements in x-y with one lane per
+                                Gauss-point column, streamed along axis 2 in chunks of 4 elements that
+                                keep the open function planes in registers), 3 the same tiles with a
+                                fixed depth of 4 elements (3 at p = 4), 2 by cubic tiles of elements, 0 one
+                                element per workgroup; 1, 2 and 3 also select tiles for the 3D
+                                fourth-order operator on x = xi without weights and the 2D and 3D
+                                Cahn-Hilliard residual */
+  IGA_OPT_RES_ZRUN = 9       /* IGA_OPT_TILED_3D = 1: chunks of 4 elements per run along axis 2 (one
+                                workgroup's work), 1..4; 0 (default) plans it from the mesh size */
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):

@@ -711,8 +711,12 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
       h->kt_n = 0;
       return IGA_OK;
     case IGA_OPT_TILED_3D:
-      if (value < 0 || value > 2) return fail(IGA_EINVAL, "IGA_OPT_TILED_3D is 0, 1 or 2");
+      if (value < 0 || value > 3) return fail(IGA_EINVAL, "IGA_OPT_TILED_3D is 0, 1, 2 or 3");
       h->tiled_3d = (int)value;
+      return IGA_OK;
+    case IGA_OPT_RES_ZRUN:
+      if (value < 0 || value > 4) return fail(IGA_EINVAL, "IGA_OPT_RES_ZRUN is 0..4");
+      h->res_zrun = (int)value;
       return IGA_OK;
     case IGA_OPT_ND_SCATTER:
       if (value != 0 && value != 1) return fail(IGA_EINVAL, "IGA_OPT_ND_SCATTER is 0 or 1");

@@ -574,7 +574,7 @@ iga_status launch_cahn_hilliard(Handle &h, const double *C, const double *Cd, do
   // for comparison)
   if (h.pb.simple_knots && h.tiled_3d) {
     if (h.pb.dim == 3) {
-      if (p == 2) return h.tiled_3d == 1 ? run_chr3<3>(h, C, Cd, theta, lam, R) : run_ch3<3>(h, C, Cd, theta, lam, R);
+      if (p == 2) return h.tiled_3d != 2 ? run_chr3<3>(h, C, Cd, theta, lam, R) : run_ch3<3>(h, C, Cd, theta, lam, R);
       if (p == 3) return run_ch3<4>(h, C, Cd, theta, lam, R);
     } else {
       switch (p) {

@@ -155,7 +155,8 @@ struct Handle {
   int jac_algo = IGA_JAC_AUTO;
   int nd_color = 0;   // local-ND scatter: 0 atomics (default), 1 colour-ordered plain adds
   int tiled_3d = 1;   // 3D residual / apply by element tiles where supported (0: one element per workgroup;
-                      // 1: column tiles for the residual and apply; 2: cube tiles for them)
+                      // 1: column tiles streamed along axis 2; 2: cube tiles; 3: column tiles of fixed depth)
+  int res_zrun = 0;   // streamed column tiles: chunks of 4 elements per run along axis 2 (0 = planned)
   int row_b1 = 0, row_b2 = 0;
   int row_segments = 0;           // separable row-gather: segments along axis 0 (0 = planned)
   // separable row-gather tables (3D, identity geometry, kappa = 1, simple knots)

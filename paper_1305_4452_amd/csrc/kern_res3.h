@@ -837,6 +837,272 @@ __device__ inline void res3r_body(const DevProblem &pb, const int tile, const do
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Streaming column tiles for the residual and the apply: the x-y extent and the lane layout of
+// res3r_body, but a workgroup walks a run of chunks of TEZ elements along axis 2.  A function plane
+// k2 receives contributions from elements k2 - p .. k2 only, so after a chunk its first TEZ planes
+// are complete and go out (transposed axis 1 and axis 0 through LDS, one FP64 atomic per function:
+// the x-y borders are still shared with neighbouring tiles), while the last p planes stay open in
+// registers and become the first p planes of the next chunk, together with their axis-1 results of
+// the forward pass.  Per chunk only TEZ new coefficient planes are loaded and contracted, so the
+// axis-2 halo work ((TEZ + p) / TEZ in res3r_body) and the atomics on the planes that two z tiles
+// share are paid once per run instead of once per chunk.  The run's last chunk flushes all of its
+// open planes.  Runs of zc <= kRes3sRunMax chunks start every zc TEZ elements; the last run ends with
+// the mesh.
+template <int P, int TEZ>
+struct Res3S {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TEX = 16 / Q, G = TEX * Q;
+  static constexpr int NI = TEX + p, NZ = TEZ + p;
+  static constexpr int GS = G % 2 ? G : G + 1;
+  static constexpr int n_c = NZ * NI * NI, n_a = NZ * NI * GS, n_y = TEZ * G * GS;
+  static constexpr int n_b = 4 * G * P + 2 * G + 2 * TEZ * Q * P + TEZ * Q;
+  static constexpr size_t total = (size_t)(n_c + 2 * n_a + 3 * n_y + n_b) * sizeof(double);
+  static_assert(G * G <= kThreads, "one lane per Gauss-point column");
+  static_assert(TEZ >= p, "the planes left open by a chunk fit one emission");
+  static_assert(total <= 65536, "static LDS");
+};
+
+constexpr int kRes3sRunMax = 4;   // chunks per run, at most
+
+__host__ __device__ inline int res3s_blocks(int ne0, int ne1, int ne2, int TEX, int TEZ, int zc) {
+  return ((ne0 + TEX - 1) / TEX) * ((ne1 + TEX - 1) / TEX) * ((ne2 + TEZ * zc - 1) / (TEZ * zc));
+}
+
+template <int P, int TEZ, int OP>
+__device__ inline void res3s_body(const DevProblem &pb, const int blk, const int zc, const double *__restrict__ X,
+                                  const double *__restrict__ lin, double *__restrict__ Y, double *__restrict__ lds) {
+  static_assert(OP == OP3_RES || OP == OP3_APPLY, "residual or apply");
+  using S_ = Res3S<P, TEZ>;
+  constexpr int p = S_::p, Q = S_::Q, TEX = S_::TEX, G = S_::G, GS = S_::GS, NI = S_::NI, NZ = S_::NZ;
+  constexpr int NT = kThreads, L = P * P * P, GP = G * P;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
+  const int nt0 = (ne0 + TEX - 1) / TEX, nt1 = (ne1 + TEX - 1) / TEX;
+  const int E0 = (blk % nt0) * TEX, E1 = ((blk / nt0) % nt1) * TEX;
+  const int Zlo = (blk / (nt0 * nt1)) * zc * TEZ, Zhi = min(ne2, Zlo + zc * TEZ);
+  const int NE0 = min(TEX, ne0 - E0), NE1 = min(TEX, ne1 - E1);
+  const int G0 = NE0 * Q, G1 = NE1 * Q;
+  const int NI0 = NE0 + p, NI1 = NE1 + p;
+  double *c = lds;                                     // [k2][k1][k0], plane k2 = function Ez + k2
+  double *A0 = c + S_::n_c, *D0 = A0 + S_::n_a;        // [k2][k1][g0] (row stride GS); later Za, Zb
+  double *Ys = D0 + S_::n_a;                           // [3][slot][g1][g0] (row stride GS)
+  double *sB = Ys + 3 * S_::n_y, *sW = sB + 4 * GP;
+  double *sB2 = sW + 2 * G, *sW2 = sB2 + 2 * TEZ * Q * P;   // the chunk's axis-2 rows [B|dB][z point][a], weights
+  const double *B0 = sB, *dB0 = sB + GP, *B1 = sB + 2 * GP, *dB1 = sB + 3 * GP, *W0 = sW, *W1 = sW + G;
+  double *Za = A0, *Zb = D0;
+  const int t = threadIdx.x;
+  const bool kel = pb.kappa_mode == IGA_KAPPA_ELEMENT;
+
+  for (int i = t; i < GP; i += NT)
+    if (i / P < G0) {
+      sB[i] = pb.ax[0].B[(size_t)E0 * Q * P + i];
+      sB[GP + i] = pb.ax[0].dB[(size_t)E0 * Q * P + i];
+    }
+  for (int i = t; i < GP; i += NT)
+    if (i / P < G1) {
+      sB[2 * GP + i] = pb.ax[1].B[(size_t)E1 * Q * P + i];
+      sB[3 * GP + i] = pb.ax[1].dB[(size_t)E1 * Q * P + i];
+    }
+  for (int i = t; i < G; i += NT) {
+    if (i < G0) sW[i] = pb.ax[0].wq[(size_t)E0 * Q + i];
+    if (i < G1) sW[G + i] = pb.ax[1].wq[(size_t)E1 * Q + i];
+  }
+
+  // open planes: the axis-1 results of the forward pass and the transposed axis-2 sums
+  double U[NZ], U01[NZ], U10[NZ], Y0[NZ], Y1[NZ], Y2[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) U[k] = U01[k] = U10[k] = Y0[k] = Y1[k] = Y2[k] = 0.0;
+
+  // planes [pl0, pl1) of the chunk at Ez (pl1 - pl0 <= TEZ): transposed axes 1 and 0, then the atomics
+  auto emit = [&](int Ez, int pl0, int pl1, int t, int g0, int g1, bool act) {
+    if (act) {
+#pragma unroll
+      for (int k2 = 0; k2 < NZ; ++k2)
+        if (k2 >= pl0 && k2 < pl1) {
+          const int w = ((k2 - pl0) * G + g1) * GS + g0;
+          Ys[w] = Y0[k2];
+          Ys[S_::n_y + w] = Y1[k2];
+          Ys[2 * S_::n_y + w] = Y2[k2];
+        }
+    }
+    __syncthreads();
+    const int ns = pl1 - pl0;
+    for (int i = t; i < TEZ * NI * G; i += NT) {
+      const int gg0 = i % G, k1 = (i / G) % NI, s = i / (G * NI);
+      if (gg0 >= G0 || k1 >= NI1 || s >= ns) continue;
+      double za = 0, zb = 0;
+#pragma unroll
+      for (int a1 = 0; a1 <= p; ++a1) {
+        const int e1 = k1 - a1;
+        if (e1 < 0 || e1 >= NE1) continue;
+#pragma unroll
+        for (int r1 = 0; r1 < Q; ++r1) {
+          const int gg1 = e1 * Q + r1, w = (s * G + gg1) * GS + gg0;
+          const double b = B1[gg1 * P + a1];
+          za += b * Ys[w];
+          zb += dB1[gg1 * P + a1] * Ys[S_::n_y + w] + b * Ys[2 * S_::n_y + w];
+        }
+      }
+      Za[(s * NI + k1) * GS + gg0] = za;
+      Zb[(s * NI + k1) * GS + gg0] = zb;
+    }
+    __syncthreads();
+    for (int i = t; i < TEZ * NI * NI; i += NT) {
+      const int k0 = i % NI, k1 = (i / NI) % NI, s = i / (NI * NI);
+      if (k0 >= NI0 || k1 >= NI1 || s >= ns) continue;
+      double r = 0;
+#pragma unroll
+      for (int a0 = 0; a0 <= p; ++a0) {
+        const int e0 = k0 - a0;
+        if (e0 < 0 || e0 >= NE0) continue;
+#pragma unroll
+        for (int r0 = 0; r0 < Q; ++r0) {
+          const int gg0 = e0 * Q + r0, w = (s * NI + k1) * GS + gg0;
+          r += dB0[gg0 * P + a0] * Za[w] + B0[gg0 * P + a0] * Zb[w];
+        }
+      }
+      atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
+                   (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], Ez + pl0 + s))],
+                r);
+    }
+  };
+
+  // the chunks of a run are unrolled: carried through a runtime loop, the open planes and everything the
+  // compiler hoists out of it exceed the register budget of three waves per SIMD
+#pragma unroll
+  for (int ch = 0; ch < kRes3sRunMax; ++ch) {
+    const int Ez = Zlo + ch * TEZ;
+    if (Ez >= Zhi) break;
+    const int NE2 = min(TEZ, Zhi - Ez), NI2 = NE2 + p;
+    const bool last = Ez + TEZ >= Zhi;
+    const int kf = Ez == Zlo ? 0 : p;                  // planes below kf are open from the previous chunk
+    // the lane's column and strided indices, re-derived in every chunk from an opaque copy of the thread
+    // index (otherwise the compiler keeps every address it can share between chunks live in registers)
+    int tt = t;
+    asm volatile("" : "+v"(tt));
+    const int g0 = tt % G, g1 = tt / G;
+    const bool act = tt < G * G && g0 < G0 && g1 < G1;
+    const int el0 = g0 / Q, el1 = g1 / Q, q0 = g0 % Q, q1 = g1 % Q;
+    // (1) coefficients of the new planes and the chunk's axis-2 rows.  The previous chunk's readers of
+    // c and sB2 finished before its emission; its transposed axis 0 may still read Za / Zb (= A0 / D0),
+    // which the barrier below separates from the axis-0 writes.
+    for (int i = tt; i < S_::n_c; i += NT) {
+      const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+      if (k0 >= NI0 || k1 >= NI1 || k2 < kf || k2 >= NI2) continue;
+      const int i0 = wrap_fn(pb.ax[0], E0 + k0), i1 = wrap_fn(pb.ax[1], E1 + k1), i2 = wrap_fn(pb.ax[2], Ez + k2);
+      double x = X[i0 + (int64_t)n0 * (i1 + (int64_t)n1 * i2)];
+      if (OP == OP3_APPLY && is_dirichlet_idx(pb, i0, i1, i2)) x = 0.0;
+      c[i] = x;
+    }
+    for (int i = tt; i < TEZ * Q * P; i += NT)
+      if (i / (Q * P) < NE2) {
+        sB2[i] = pb.ax[2].B[(size_t)Ez * Q * P + i];
+        sB2[TEZ * Q * P + i] = pb.ax[2].dB[(size_t)Ez * Q * P + i];
+      }
+    for (int i = tt; i < TEZ * Q; i += NT)
+      if (i / Q < NE2) sW2[i] = pb.ax[2].wq[(size_t)Ez * Q + i];
+    __syncthreads();
+    // (2) axis 0 on the new planes
+    for (int i = tt; i < NZ * NI * G; i += NT) {
+      const int gg0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), e0 = gg0 / Q;
+      if (gg0 >= G0 || k1 >= NI1 || k2 < kf || k2 >= NI2) continue;
+      const double *cc = c + (k2 * NI + k1) * NI + e0;
+      double a = 0, d = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < P; ++a0) {
+        a += B0[gg0 * P + a0] * cc[a0];
+        d += dB0[gg0 * P + a0] * cc[a0];
+      }
+      const int o = (k2 * NI + k1) * GS + gg0;
+      A0[o] = a;
+      D0[o] = d;
+    }
+    __syncthreads();
+    // (3) one lane per Gauss-point column: axis 1 on the new planes, axis 2, the point integrands and
+    // the transposed axis 2 into the open planes
+    if (act) {
+      double b1[P], db1[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        b1[a] = B1[g1 * P + a];
+        db1[a] = dB1[g1 * P + a];
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < NZ; ++k2) {
+        if (k2 < kf) continue;
+        double u = 0, u01 = 0, u10 = 0;
+        if (k2 < NI2) {
+#pragma unroll
+          for (int a1 = 0; a1 < P; ++a1) {
+            const int r = (k2 * NI + el1 + a1) * GS + g0;
+            u += b1[a1] * A0[r];
+            u01 += b1[a1] * D0[r];
+            u10 += db1[a1] * A0[r];
+          }
+        }
+        U[k2] = u;
+        U01[k2] = u01;
+        U10[k2] = u10;
+      }
+      const double w01 = W0[g0] * W1[g1], lam = pb.lambda;
+#pragma unroll
+      for (int el2 = 0; el2 < TEZ; ++el2) {
+        if (el2 >= NE2) break;
+        const int64_t e = (E0 + el0) + (int64_t)ne0 * ((E1 + el1) + (int64_t)ne1 * (Ez + el2));
+        const double kap = kel ? pb.kel[e] : 1.0;
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) {
+          const int o = (el2 * Q + q2) * P;
+          double b2[P], db2[P];
+#pragma unroll
+          for (int a = 0; a < P; ++a) {
+            b2[a] = sB2[o + a];
+            db2[a] = sB2[TEZ * Q * P + o + a];
+          }
+          double u = 0, d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+          for (int a2 = 0; a2 < P; ++a2) {
+            u += b2[a2] * U[el2 + a2];
+            d0 += b2[a2] * U01[el2 + a2];
+            d1 += b2[a2] * U10[el2 + a2];
+            d2 += db2[a2] * U[el2 + a2];
+          }
+          const double W = w01 * sW2[el2 * Q + q2], kw = kap * W;
+          const double F0 = kw * d0, F1 = kw * d1, F2 = kw * d2;
+          double S;
+          if constexpr (OP == OP3_RES) S = -W * lam * exp(u);
+          else S = lin[e * L + q0 + Q * (q1 + Q * q2)] * u;
+#pragma unroll
+          for (int a2 = 0; a2 < P; ++a2) {
+            Y0[el2 + a2] += b2[a2] * F0;
+            Y1[el2 + a2] += b2[a2] * F1;
+            Y2[el2 + a2] += db2[a2] * F2 + b2[a2] * S;
+          }
+        }
+      }
+    }
+    // (4) the complete planes go out (the run's last chunk: all of them, in passes of at most TEZ
+    // planes); the open ones move down to the first p planes
+    const int npass = (last && NI2 > TEZ) ? 2 : 1;
+    for (int ps = 0; ps < npass; ++ps) emit(Ez, ps * TEZ, last ? min(ps * TEZ + TEZ, NI2) : TEZ, tt, g0, g1, act);
+    if (!last) {
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) {
+        if (k < p) {
+          U[k] = U[k + TEZ];
+          U01[k] = U01[k + TEZ];
+          U10[k] = U10[k + TEZ];
+          Y0[k] = Y0[k + TEZ];
+          Y1[k] = Y1[k + TEZ];
+          Y2[k] = Y2[k + TEZ];
+        } else {
+          Y0[k] = Y1[k] = Y2[k] = 0.0;
+        }
+      }
+    }
+  }
+}
+
 // Column-register variant of the Cahn-Hilliard residual (the arithmetic of ch3_body, regrouped):
 // tiles of TEX x TEX x TEZ elements with TEX Q <= 16, one lane per Gauss-point column (g0, g1).  The
 // axis-0 contraction (B.c, B'.c, B''.c, B.cdot) goes through LDS; each lane then holds the six axis-1

@@ -59,10 +59,41 @@ __global__ void __launch_bounds__(rs3::kThreads) k_res3r(DevProblem pb, const do
   rs3::res3r_body<P, TEZ, OP>(pb, (int)blockIdx.x, X, lin, Y, lds);
 }
 
+template <int P, int OP>
+__global__ void __launch_bounds__(rs3::kThreads) k_res3s(DevProblem pb, const double *__restrict__ X,
+                                                         const double *__restrict__ lin, double *__restrict__ Y, int zc) {
+  __shared__ double lds[rs3::Res3S<P, 4>::total / sizeof(double)];
+  rs3::res3s_body<P, 4, OP>(pb, (int)blockIdx.x, zc, X, lin, Y, lds);
+}
+
+// chunks of 4 elements per run along axis 2: the option value, else the longest run of at most 3 chunks
+// that still leaves 512 workgroups.  Measured at 64^3 (p = 1, 2, 3) and 48^3 (p = 4), residual in us for
+// runs of 1 / 2 / 3 / 4 chunks: p = 3 125.7 / 107.5 / 102.7 / 105.9, p = 4 129.5 / 109.8 / 103.1 / 108.8,
+// p = 2 57.7 / 53.0 / 54.4 / 52.0, p = 1 25.0 / 22.6 / 28.3 / 29.9 (fixed-depth tiles: 143.1, 144.2,
+// 54.0, 22.0).
+int res3s_run_chunks(const Handle &h, int TEX) {
+  const int nz = (h.pb.ne[2] + 3) / 4;
+  if (h.res_zrun > 0) return std::max(1, std::min(h.res_zrun, nz));
+  const int64_t nxy = (int64_t)((h.pb.ne[0] + TEX - 1) / TEX) * ((h.pb.ne[1] + TEX - 1) / TEX);
+  int zc = std::min(3, nz);
+  while (zc > 1 && nxy * ((nz + zc - 1) / zc) < 512) --zc;
+  return zc;
+}
+
 template <int P>
 iga_status run_res3(Handle &h, const double *X, double *Y, int op) {
   const unsigned nb = (unsigned)rs3::res3_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], rs3::Res3<P>::TE);
-  if (h.tiled_3d == 1) {
+  if (h.tiled_3d == 1 && op != rs3::OP3_LIN) {
+    using R = rs3::Res3S<P, 4>;
+    const int zc = res3s_run_chunks(h, R::TEX);
+    const unsigned nr = (unsigned)rs3::res3s_blocks(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], R::TEX, 4, zc);
+    if (op == rs3::OP3_APPLY)
+      hipLaunchKernelGGL((k_res3s<P, rs3::OP3_APPLY>), dim3(nr), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                         (const double *)h.lin, Y, zc);
+    else
+      hipLaunchKernelGGL((k_res3s<P, rs3::OP3_RES>), dim3(nr), dim3(rs3::kThreads), 0, h.stream, h.pb, X,
+                         (const double *)nullptr, Y, zc);
+  } else if (h.tiled_3d == 1 || h.tiled_3d == 3) {
     using R = rs3::Res3R<P, rs3::Res3RDepth<P>::TEZ>;
     const unsigned nr = (unsigned)rs3::res3r_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], R::TEX, rs3::Res3RDepth<P>::TEZ);
     if (op == rs3::OP3_APPLY)

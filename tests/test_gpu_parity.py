@@ -307,12 +307,15 @@ def test_tiled_residual_2d(p, nel, km, mask, src):
                                            (2, [9, 5, 6], 2, None), (2, [11, 6, 9], 0, 0b110000),
                                            (3, [7, 9, 5], 0, 0b010110), (3, [5, 3, 4], 2, 0b101001),
                                            (3, [9, 10, 11], 2, 0b001100), (3, 1, 0, None),
-                                           (4, [3, 4, 2], 2, None), (4, [7, 5, 8], 0, 0b100001)])
+                                           (4, [3, 4, 2], 2, None), (4, [7, 5, 8], 0, 0b100001),
+                                           (1, [9, 8, 21], 0, 0b110000), (2, [7, 4, 18], 0, None),
+                                           (3, [6, 5, 23], 2, 0b010110), (4, [4, 3, 13], 2, 0b100001)])
 def test_tiled_residual_apply_3d(p, nel, km, mask):
-    """The tiled 3D residual and matrix-free apply (default for the identity map): column tiles
-    ((16/Q)^2 x 4 elements, 3 deep at p = 4) and cubic tiles, several tiles per axis with ragged last
-    tiles, unit and element-wise kappa, partial Dirichlet masks, a single element; against the oracle
-    and against one element per workgroup."""
+    """The tiled 3D residual and matrix-free apply (default for the identity map): column tiles streamed
+    along axis 2 in runs of 1..4 chunks of 4 elements (the planned run and each forced length), column
+    tiles of fixed depth ((16/Q)^2 x 4 elements, 3 deep at p = 4) and cubic tiles, several tiles per
+    axis with ragged last tiles, chunks and runs, unit and element-wise kappa, partial Dirichlet masks,
+    a single element; against the oracle and against one element per workgroup."""
     print(f"[case] tiled 3D residual/apply p={p} nel={nel} kappa={km} mask={mask}", flush=True)
     patch = inputs.unit_box(3, nel, p)
     ne = [n - p for n in patch.shape]
@@ -323,17 +326,18 @@ def test_tiled_residual_apply_3d(p, nel, km, mask):
     v = inputs.uniform(12, 4, patch.ndof, -1.0, 1.0)
     Rref, Jv = o.residual(U), o.jacobian_csr(U) @ v
     out = {}
-    for tiled in (1, 2, 0):
+    for tiled, zrun in ((1, 0), (1, 1), (1, 2), (1, 3), (1, 4), (3, 0), (2, 0), (0, 0)):
         g.set_option(iga.IGA_OPT_TILED_3D, tiled)
+        g.set_option(iga.IGA_OPT_RES_ZRUN, zrun)
         R = torch.full((g.N,), np.nan, dtype=torch.float64, device="cuda")
         g.assemble_residual(dev(U), R)
         y = torch.full((g.N,), np.nan, dtype=torch.float64, device="cuda")
         g.apply(dev(U), dev(v), y)
-        out[tiled] = (host(R), host(y))
-        assert rel(out[tiled][0], Rref) < TOL64, tiled
-        assert rel(out[tiled][1], Jv) < TOL64, tiled
-    for tiled in (1, 2):
-        assert rel(out[tiled][0], out[0][0]) < TOL64 and rel(out[tiled][1], out[0][1]) < TOL64
+        out[tiled, zrun] = (host(R), host(y))
+        assert rel(out[tiled, zrun][0], Rref) < TOL64, (tiled, zrun)
+        assert rel(out[tiled, zrun][1], Jv) < TOL64, (tiled, zrun)
+    for key in out:
+        assert rel(out[key][0], out[0, 0][0]) < TOL64 and rel(out[key][1], out[0, 0][1]) < TOL64, key
 
 
 @pytest.mark.parametrize("name", CASES)

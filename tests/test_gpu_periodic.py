@@ -24,6 +24,9 @@ CASES = {
     "per3_p3_c2_x": (3, [8, 5, 6], 3, [2, None, None], 3.0, False),
     # three functions per periodic axis: a residual tile covers the axis and wraps onto itself
     "per3_p1_tiny": (3, [3, 3, 5], 1, [0, 0, None], 1.0, False),
+    # periodic axis 2 walked by runs of chunks (residual and apply for every run length)
+    "per3_p2_z_long": (3, [5, 4, 18], 2, [None, None, 1], 2.0, True),
+    "per3_p2_z_wrap": (3, [6, 5, 5], 2, [None, 1, 1], 1.5, False),   # the first chunk wraps onto itself
 }
 
 
@@ -82,6 +85,16 @@ def test_periodic_pattern_residual_jacobians(name):
     g.apply(dev(U), dev(v), y)
     Jv = o.jacobian_csr(U) @ v
     assert rel(host(y), Jv) < TOL64
+    if len(CASES[name][1]) == 3:
+        Rref = o.residual(U)
+        for zrun in (1, 2, 3, 4):
+            g.set_option(iga.IGA_OPT_RES_ZRUN, zrun)
+            R = torch.full((g.N,), np.nan, dtype=torch.float64, device="cuda")
+            g.assemble_residual(dev(U), R)
+            y = torch.full((g.N,), np.nan, dtype=torch.float64, device="cuda")
+            g.apply(dev(U), dev(v), y)
+            assert rel(host(R), Rref) < TOL64 and rel(host(y), Jv) < TOL64, zrun
+        g.set_option(iga.IGA_OPT_RES_ZRUN, 0)
     g.set_option(iga.IGA_OPT_JAC_ALGO, iga.IGA_JAC_AUTO)
     vals = torch.zeros(g.nnz, dtype=torch.float64, device="cuda")
     g.assemble_jacobian(dev(U), vals)
