@@ -715,7 +715,7 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
       h->tiled_3d = (int)value;
       return IGA_OK;
     case IGA_OPT_RES_ZRUN:
-      if (value < 0 || value > 4) return fail(IGA_EINVAL, "IGA_OPT_RES_ZRUN is 0..4");
+      if (value < 0 || value > 8) return fail(IGA_EINVAL, "IGA_OPT_RES_ZRUN is 0..8");
       h->res_zrun = (int)value;
       return IGA_OK;
     case IGA_OPT_ND_SCATTER:

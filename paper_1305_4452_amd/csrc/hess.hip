@@ -309,7 +309,12 @@ iga_status run_ch3(Handle &h, const double *C, const double *Cd, double theta, d
   return IGA_OK;
 }
 
-constexpr int kChrTEZ = 3;   // depth of the column tiles of the Cahn-Hilliard residual (C^1 quadratics)
+// Cahn-Hilliard residual on column tiles (C^1 quadratics): tile depth / chunk length along axis 2 and the
+// longest run of the streamed tiles.  Measured at 256^3 (ms per residual): fixed-depth tiles 4.44 (depth
+// 3), 4.13 (depth 2); streamed chunks of 3 at 184 VGPRs (2 waves per SIMD) 3.95, capped at 168 VGPRs (3
+// waves, 44 spilled) 3.31; chunks of 2 (150 VGPRs, 3 waves) in runs of 4 / 6 / 8: 3.50 / 3.33 / 3.28.
+constexpr int kChrTEZ = 2;
+constexpr int kChrRunMax = 8;
 
 template <int P>
 __global__ void __launch_bounds__(rs3::kThreads) k_chr3(DevProblem pb, const double *__restrict__ C,
@@ -320,10 +325,31 @@ __global__ void __launch_bounds__(rs3::kThreads) k_chr3(DevProblem pb, const dou
 }
 
 template <int P>
+__global__ void __launch_bounds__(rs3::kThreads) k_chr3s(DevProblem pb, const double *__restrict__ C,
+                                                         const double *__restrict__ Cd, double theta, double lam,
+                                                         double *__restrict__ R, int zc) {
+  __shared__ double lds[rs3::Chr3S<P, kChrTEZ>::total / sizeof(double)];
+  rs3::chr3s_body<P, kChrTEZ, kChrRunMax>(pb, (int)blockIdx.x, zc, C, Cd, theta, lam, R, lds);
+}
+
+// IGA_OPT_TILED_3D = 1: column tiles streamed along axis 2 in runs of zc chunks (the option value, else the
+// longest run of at most kChrRunMax chunks that leaves 1024 workgroups); 3: column tiles of fixed depth
+template <int P>
 iga_status run_chr3(Handle &h, const double *C, const double *Cd, double theta, double lam, double *R) {
   using S = rs3::Chr3<P, kChrTEZ>;
-  const unsigned nb = (unsigned)rs3::res3r_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], S::TEX, kChrTEZ);
-  hipLaunchKernelGGL(k_chr3<P>, dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, C, Cd, theta, lam, R);
+  if (h.tiled_3d == 1) {
+    const int nz = (h.pb.ne[2] + kChrTEZ - 1) / kChrTEZ;
+    const int64_t nxy = (int64_t)((h.pb.ne[0] + S::TEX - 1) / S::TEX) * ((h.pb.ne[1] + S::TEX - 1) / S::TEX);
+    int zc = std::min(kChrRunMax, nz);
+    if (h.res_zrun > 0) zc = std::max(1, std::min(std::min(h.res_zrun, kChrRunMax), nz));
+    else
+      while (zc > 1 && nxy * ((nz + zc - 1) / zc) < 1024) --zc;
+    const unsigned nb = (unsigned)rs3::res3s_blocks(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], S::TEX, kChrTEZ, zc);
+    hipLaunchKernelGGL(k_chr3s<P>, dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, C, Cd, theta, lam, R, zc);
+  } else {
+    const unsigned nb = (unsigned)rs3::res3r_tiles(h.pb.ne[0], h.pb.ne[1], h.pb.ne[2], S::TEX, kChrTEZ);
+    hipLaunchKernelGGL(k_chr3<P>, dim3(nb), dim3(rs3::kThreads), 0, h.stream, h.pb, C, Cd, theta, lam, R);
+  }
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
 }

@@ -1323,5 +1323,266 @@ __device__ inline void chr3_body(const DevProblem &pb, const int tile, const dou
   }
 }
 
+// Streamed variant of chr3_body: the x-y tiles and lanes of chr3_body, walking a run of chunks of TEZ
+// elements along axis 2 with the p open function planes (their six axis-1 products and four transposed
+// axis-2 sums) carried in registers from chunk to chunk, as res3s_body does for the Bratu residual.
+template <int P, int TEZ>
+struct Chr3S {
+  static constexpr int p = P - 1, Q = P;
+  static constexpr int TEX = 16 / Q, G = TEX * Q, GS = G % 2 ? G : G + 1;
+  static constexpr int NI = TEX + p, NZ = TEZ + p;
+  static constexpr int n_c = NZ * NI * NI, n_a = NZ * NI * GS, n_y = TEZ * G * GS;
+  static constexpr int n_b = 6 * G * P + 2 * G + 3 * TEZ * Q * P + TEZ * Q;
+  static constexpr size_t total = (size_t)(2 * n_c + 4 * n_a + 4 * n_y + n_b) * sizeof(double);
+  static_assert(G * G <= kThreads, "one lane per Gauss-point column");
+  static_assert(TEZ >= p, "the planes left open by a chunk fit one emission");
+  static_assert(total <= 65536, "static LDS");
+};
+
+template <int P, int TEZ, int RUNMAX>
+__device__ inline void chr3s_body(const DevProblem &pb, const int blk, const int zc, const double *__restrict__ Cv,
+                                  const double *__restrict__ Cd, double theta, double lam, double *__restrict__ Y,
+                                  double *__restrict__ lds) {
+  using S_ = Chr3S<P, TEZ>;
+  constexpr int p = S_::p, Q = S_::Q, TEX = S_::TEX, G = S_::G, GS = S_::GS, NI = S_::NI, NZ = S_::NZ;
+  constexpr int NT = kThreads, GP = G * P, ZP = TEZ * Q * P;
+  const int n0 = pb.n[0], n1 = pb.n[1], ne0 = pb.ne[0], ne1 = pb.ne[1], ne2 = pb.ne[2];
+  const int nt0 = (ne0 + TEX - 1) / TEX, nt1 = (ne1 + TEX - 1) / TEX;
+  const int E0 = (blk % nt0) * TEX, E1 = ((blk / nt0) % nt1) * TEX;
+  const int Zlo = (blk / (nt0 * nt1)) * zc * TEZ, Zhi = min(ne2, Zlo + zc * TEZ);
+  const int NE0 = min(TEX, ne0 - E0), NE1 = min(TEX, ne1 - E1);
+  const int G0 = NE0 * Q, G1 = NE1 * Q;
+  const int NI0 = NE0 + p, NI1 = NE1 + p;
+  double *c = lds, *cd = c + S_::n_c;                                       // [k2][k1][k0], plane k2 = Ez + k2
+  double *aB = cd + S_::n_c, *aD = aB + S_::n_a, *aE = aD + S_::n_a, *aR = aE + S_::n_a;   // [k2][k1][g0]
+  double *Yb = aR + S_::n_a, *Y0 = Yb + S_::n_y, *Y1 = Y0 + S_::n_y, *Ysl = Y1 + S_::n_y;   // [slot][g1][g0]
+  double *tb = Ysl + S_::n_y, *tw = tb + 6 * GP, *t2 = tw + 2 * G, *w2 = t2 + 3 * ZP;
+  double *Zb = aB, *Zd = aD, *Ze = aE;                                      // transposed axis 1, [slot][k1][g0]
+  const double *B0 = tb, *D0 = tb + GP, *E0t = tb + 2 * GP, *B1 = tb + 3 * GP, *D1 = tb + 4 * GP, *E1t = tb + 5 * GP;
+  const int t = threadIdx.x;
+  for (int i = t; i < GP; i += NT) {
+    if (i / P < G0) {
+      const size_t o = (size_t)E0 * Q * P + i;
+      tb[i] = pb.ax[0].B[o];
+      tb[GP + i] = pb.ax[0].dB[o];
+      tb[2 * GP + i] = pb.ax[0].d2B[o];
+    }
+    if (i / P < G1) {
+      const size_t o = (size_t)E1 * Q * P + i;
+      tb[3 * GP + i] = pb.ax[1].B[o];
+      tb[4 * GP + i] = pb.ax[1].dB[o];
+      tb[5 * GP + i] = pb.ax[1].d2B[o];
+    }
+  }
+  for (int i = t; i < G; i += NT) {
+    if (i < G0) tw[i] = pb.ax[0].wq[(size_t)E0 * Q + i];
+    if (i < G1) tw[G + i] = pb.ax[1].wq[(size_t)E1 * Q + i];
+  }
+  // open planes: axis-1 products bb = B1 B0 c, db = B1 B0' c, bd = B1' B0 c, rb = B1 B0 cdot and
+  // le = (B1'' B0 + B1 B0'') c (the two enter only as a sum, in the Laplacian), and the transposed
+  // axis-2 sums yb, y0, y1, ys
+  double bb[NZ], db[NZ], le[NZ], bd[NZ], rb[NZ], yb[NZ], y0[NZ], y1[NZ], ys[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) bb[k] = db[k] = le[k] = bd[k] = rb[k] = yb[k] = y0[k] = y1[k] = ys[k] = 0.0;
+
+  // planes [pl0, pl1) of the chunk at Ez (pl1 - pl0 <= TEZ): transposed axes 1 and 0, then the atomics
+  auto emit = [&](int Ez, int pl0, int pl1, int t, int g0, int g1, bool act) {
+    if (act) {
+#pragma unroll
+      for (int k2 = 0; k2 < NZ; ++k2)
+        if (k2 >= pl0 && k2 < pl1) {
+          const int w = ((k2 - pl0) * G + g1) * GS + g0;
+          Yb[w] = yb[k2];
+          Y0[w] = y0[k2];
+          Y1[w] = y1[k2];
+          Ysl[w] = ys[k2];
+        }
+    }
+    __syncthreads();
+    const int ns = pl1 - pl0;
+    for (int i = t; i < TEZ * NI * G; i += NT) {
+      const int gg0 = i % G, k1 = (i / G) % NI, s = i / (G * NI);
+      if (gg0 >= G0 || k1 >= NI1 || s >= ns) continue;
+      double zb = 0, zd = 0, ze = 0;
+#pragma unroll
+      for (int a1 = 0; a1 <= p; ++a1) {
+        const int e1 = k1 - a1;
+        if (e1 < 0 || e1 >= NE1) continue;
+#pragma unroll
+        for (int r1 = 0; r1 < Q; ++r1) {
+          const int gg1 = e1 * Q + r1, w = (s * G + gg1) * GS + gg0, o = gg1 * P + a1;
+          zb += B1[o] * Yb[w] + D1[o] * Y1[w] + E1t[o] * Ysl[w];
+          zd += B1[o] * Y0[w];
+          ze += B1[o] * Ysl[w];
+        }
+      }
+      const int w = (s * NI + k1) * GS + gg0;
+      Zb[w] = zb;
+      Zd[w] = zd;
+      Ze[w] = ze;
+    }
+    __syncthreads();
+    for (int i = t; i < TEZ * NI * NI; i += NT) {
+      const int k0 = i % NI, k1 = (i / NI) % NI, s = i / (NI * NI);
+      if (k0 >= NI0 || k1 >= NI1 || s >= ns) continue;
+      double r = 0;
+#pragma unroll
+      for (int a0 = 0; a0 <= p; ++a0) {
+        const int e0 = k0 - a0;
+        if (e0 < 0 || e0 >= NE0) continue;
+#pragma unroll
+        for (int r0 = 0; r0 < Q; ++r0) {
+          const int gg0 = e0 * Q + r0, w = (s * NI + k1) * GS + gg0, o = gg0 * P + a0;
+          r += B0[o] * Zb[w] + D0[o] * Zd[w] + E0t[o] * Ze[w];
+        }
+      }
+      atomicAdd(&Y[wrap_fn(pb.ax[0], E0 + k0) +
+                   (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], Ez + pl0 + s))],
+                r);
+    }
+  };
+
+  // the chunks of a run (at most RUNMAX) are unrolled (see res3s_body)
+#pragma unroll
+  for (int ch = 0; ch < RUNMAX; ++ch) {
+    const int Ez = Zlo + ch * TEZ;
+    if (Ez >= Zhi) break;
+    const int NE2 = min(TEZ, Zhi - Ez), NI2 = NE2 + p;
+    const bool last = Ez + TEZ >= Zhi;
+    const int kf = Ez == Zlo ? 0 : p;                  // planes below kf are open from the previous chunk
+    int tt = t;                                        // opaque copy of the thread index (see res3s_body)
+    asm volatile("" : "+v"(tt));
+    const int g0 = tt % G, g1 = tt / G;
+    const bool act = tt < G * G && g0 < G0 && g1 < G1;
+    // (1) coefficients of the new planes and the chunk's axis-2 rows
+    for (int i = tt; i < ZP; i += NT)
+      if (i / (Q * P) < NE2) {
+        const size_t o = (size_t)Ez * Q * P + i;
+        t2[i] = pb.ax[2].B[o];
+        t2[ZP + i] = pb.ax[2].dB[o];
+        t2[2 * ZP + i] = pb.ax[2].d2B[o];
+      }
+    for (int i = tt; i < TEZ * Q; i += NT)
+      if (i / Q < NE2) w2[i] = pb.ax[2].wq[(size_t)Ez * Q + i];
+    for (int i = tt; i < S_::n_c; i += NT) {
+      const int k0 = i % NI, k1 = (i / NI) % NI, k2 = i / (NI * NI);
+      if (k0 >= NI0 || k1 >= NI1 || k2 < kf || k2 >= NI2) continue;
+      const int64_t A = wrap_fn(pb.ax[0], E0 + k0) +
+                        (int64_t)n0 * (wrap_fn(pb.ax[1], E1 + k1) + (int64_t)n1 * wrap_fn(pb.ax[2], Ez + k2));
+      c[i] = Cv[A];
+      cd[i] = Cd[A];
+    }
+    __syncthreads();
+    // (2) axis 0 on the new planes
+    for (int i = tt; i < NZ * NI * G; i += NT) {
+      const int gg0 = i % G, k1 = (i / G) % NI, k2 = i / (G * NI), e0 = gg0 / Q;
+      if (gg0 >= G0 || k1 >= NI1 || k2 < kf || k2 >= NI2) continue;
+      const int o = (k2 * NI + k1) * NI + e0;
+      double vb = 0, vd = 0, ve = 0, vr = 0;
+#pragma unroll
+      for (int a0 = 0; a0 < P; ++a0) {
+        vb += B0[gg0 * P + a0] * c[o + a0];
+        vd += D0[gg0 * P + a0] * c[o + a0];
+        ve += E0t[gg0 * P + a0] * c[o + a0];
+        vr += B0[gg0 * P + a0] * cd[o + a0];
+      }
+      const int w = (k2 * NI + k1) * GS + gg0;
+      aB[w] = vb;
+      aD[w] = vd;
+      aE[w] = ve;
+      aR[w] = vr;
+    }
+    __syncthreads();
+    // (3) one lane per Gauss-point column: axis 1 on the new planes, axis 2, the point terms of the
+    // Cahn-Hilliard weak form and the transposed axis 2 into the open planes
+    if (act) {
+      const int el1 = g1 / Q;
+      double b1[P], d1[P], e1[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        b1[a] = B1[g1 * P + a];
+        d1[a] = D1[g1 * P + a];
+        e1[a] = E1t[g1 * P + a];
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < NZ; ++k2) {
+        if (k2 < kf) continue;
+        double x0 = 0, x1 = 0, x2 = 0, x4 = 0, x5 = 0;
+        if (k2 < NI2) {
+#pragma unroll
+          for (int a1 = 0; a1 < P; ++a1) {
+            const int r = (k2 * NI + el1 + a1) * GS + g0;
+            x0 += b1[a1] * aB[r];
+            x1 += b1[a1] * aD[r];
+            x2 += e1[a1] * aB[r] + b1[a1] * aE[r];
+            x4 += d1[a1] * aB[r];
+            x5 += b1[a1] * aR[r];
+          }
+        }
+        bb[k2] = x0;
+        db[k2] = x1;
+        le[k2] = x2;
+        bd[k2] = x4;
+        rb[k2] = x5;
+      }
+      const double w01 = tw[g0] * tw[G + g1];
+#pragma unroll
+      for (int el2 = 0; el2 < TEZ; ++el2) {
+        if (el2 >= NE2) break;
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) {
+          const int o = (el2 * Q + q2) * P;
+          double cv = 0, c0 = 0, c1 = 0, c2 = 0, lc = 0, cr = 0;
+#pragma unroll
+          for (int a2 = 0; a2 < P; ++a2) {
+            const double b = t2[o + a2], d = t2[ZP + o + a2], e = t2[2 * ZP + o + a2];
+            const int k = el2 + a2;
+            cv += b * bb[k];
+            c0 += b * db[k];
+            c1 += b * bd[k];
+            c2 += d * bb[k];
+            lc += b * le[k] + e * bb[k];
+            cr += b * rb[k];
+          }
+          const double W = w01 * w2[el2 * Q + q2];
+          const double M = cv * (1.0 - cv), dM = 1.0 - 2.0 * cv, dmu = 1.0 / (2.0 * theta * cv * (1.0 - cv)) - 2.0;
+          const double sg = W * (M * dmu + lam * dM * lc);
+          const double F0 = sg * c0, F1 = sg * c1, F2 = sg * c2, S0 = W * cr, S2 = W * lam * M * lc;
+#pragma unroll
+          for (int a2 = 0; a2 < P; ++a2) {
+            const double b = t2[o + a2], d = t2[ZP + o + a2], e = t2[2 * ZP + o + a2];
+            const int k = el2 + a2;
+            yb[k] += b * S0 + d * F2 + e * S2;
+            y0[k] += b * F0;
+            y1[k] += b * F1;
+            ys[k] += b * S2;
+          }
+        }
+      }
+    }
+    // (4) the complete planes go out; the open ones move down to the first p planes
+    const int npass = (last && NI2 > TEZ) ? 2 : 1;
+    for (int ps = 0; ps < npass; ++ps) emit(Ez, ps * TEZ, last ? min(ps * TEZ + TEZ, NI2) : TEZ, tt, g0, g1, act);
+    if (!last) {
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) {
+        if (k < p) {
+          bb[k] = bb[k + TEZ];
+          db[k] = db[k + TEZ];
+          le[k] = le[k + TEZ];
+          bd[k] = bd[k + TEZ];
+          rb[k] = rb[k + TEZ];
+          yb[k] = yb[k + TEZ];
+          y0[k] = y0[k + TEZ];
+          y1[k] = y1[k + TEZ];
+          ys[k] = ys[k + TEZ];
+        } else {
+          yb[k] = y0[k] = y1[k] = ys[k] = 0.0;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace rs3
 }  // namespace iga

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(rs3::kThreads) k_res3s(DevProblem pb, const do
 // 54.0, 22.0).
 int res3s_run_chunks(const Handle &h, int TEX) {
   const int nz = (h.pb.ne[2] + 3) / 4;
-  if (h.res_zrun > 0) return std::max(1, std::min(h.res_zrun, nz));
+  if (h.res_zrun > 0) return std::max(1, std::min(std::min(h.res_zrun, rs3::kRes3sRunMax), nz));
   const int64_t nxy = (int64_t)((h.pb.ne[0] + TEX - 1) / TEX) * ((h.pb.ne[1] + TEX - 1) / TEX);
   int zc = std::min(3, nz);
   while (zc > 1 && nxy * ((nz + zc - 1) / zc) < 512) --zc;

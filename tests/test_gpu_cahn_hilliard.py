@@ -35,9 +35,9 @@ CASES = {
 @pytest.mark.parametrize("tiled", [1, 2, 0])
 @pytest.mark.parametrize("name", list(CASES))
 def test_cahn_hilliard_residual_matches_oracle(name, tiled):
-    """On tiles with sum factorisation (1: column tiles for 3D C^1 quadratics, cubic tiles otherwise;
-    2: cubic tiles; the *_tiles and 3D cases span several tiles, ragged at the far ends) and one
-    element per workgroup (0)."""
+    """On tiles with sum factorisation (1: streamed column tiles for 3D C^1 quadratics, cubic tiles
+    otherwise; 2: cubic tiles; the *_tiles and 3D cases span several tiles, ragged at the far ends) and
+    one element per workgroup (0)."""
     dim, nel, p, periodic = CASES[name]
     print(f"[case] Cahn-Hilliard residual {name} tiled={tiled}", flush=True)
     patch = inputs.unit_box(dim, nel, p)
@@ -55,6 +55,30 @@ def test_cahn_hilliard_residual_matches_oracle(name, tiled):
         got = R.cpu().numpy()
         assert np.all(np.isfinite(got))
         assert rel(got, o.cahn_hilliard_residual(C, Cd, theta, lam)) < 1e-11
+
+
+@pytest.mark.parametrize("nel,periodic", [([6, 5, 23], True), ([7, 6, 17], False), ([8, 7, 7], True),
+                                          ([9, 5, 6], False), ([6, 11, 41], True)])
+def test_cahn_hilliard_streamed_runs(nel, periodic):
+    """3D C^1 quadratics on column tiles streamed along axis 2 in runs of 1..8 chunks (forced and planned),
+    with ragged last chunks and runs, and on column tiles of fixed depth (IGA_OPT_TILED_3D = 3)."""
+    print(f"[case] Cahn-Hilliard streamed runs nel={nel} periodic={periodic}", flush=True)
+    patch = inputs.unit_box(3, nel, 2)
+    per = [1, 1, 1] if periodic else None
+    g = iga.IGA(patch.knots, patch.degree, periodic=per)
+    o = oracle.Oracle(patch.knots, patch.degree, periodic=per)
+    C = inputs.uniform(29, 0, g.N, 0.2, 0.8)
+    Cd = inputs.uniform(29, 1, g.N, -1.0, 1.0)
+    ref = o.cahn_hilliard_residual(C, Cd, 1.5, 0.05)
+    for tiled, zrun in ((1, 0), (1, 1), (1, 2), (1, 3), (1, 5), (1, 8), (3, 0)):
+        g.set_option(iga.IGA_OPT_TILED_3D, tiled)
+        g.set_option(iga.IGA_OPT_RES_ZRUN, zrun)
+        R = torch.full((g.N,), float("nan"), dtype=torch.float64, device="cuda")
+        g.cahn_hilliard_residual(torch.as_tensor(C, device="cuda"), torch.as_tensor(Cd, device="cuda"), 1.5, 0.05, R)
+        torch.cuda.synchronize()
+        got = R.cpu().numpy()
+        assert np.all(np.isfinite(got)), (tiled, zrun)
+        assert rel(got, ref) < 1e-11, (tiled, zrun)
 
 
 def test_cahn_hilliard_residual_rejections():
