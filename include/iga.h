@@ -76,8 +76,9 @@ typedef enum {
   IGA_OPT_JAC_ALGO = 1,      /* iga_jac_algo */
   IGA_OPT_ROW_BLOCK = 2,     /* row-gather pencil block: (b1 << 8) | b2, 0 = autotuned */
   IGA_OPT_LAMBDA_BITS = 3,   /* replace lambda: value is the IEEE-754 bit pattern of a double */
-  IGA_OPT_ROW_SEGMENTS = 4,  /* separable row-gather: split each pencil into this many segments along
-                                axis 0 (each a workgroup; 0 = planned from the occupancy), 0..64 */
+  IGA_OPT_ROW_SEGMENTS = 4,  /* separable and BF16 matrix-core row-gathers: split each pencil into this
+                                many segments along axis 0 (each a workgroup; 0 = planned from the
+                                occupancy), 0..64 */
   IGA_OPT_KERNEL_TIMING = 5, /* 1: record a HIP event pair around each kernel of iga_assemble_jacobian
                                 (read back with iga_kernel_times); 0: off (default) */
   IGA_OPT_PRECOND = 6,       /* CG preconditioner of iga_newton_solve: iga_precond */

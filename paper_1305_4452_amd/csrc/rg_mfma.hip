@@ -153,7 +153,8 @@ __global__ void __launch_bounds__(256) k_cs3(DevProblem pb, const double *__rest
 // ------------------------------------------------------------------------------------------
 template <int P, bool TABLE, bool SPLIT>
 __global__ void __launch_bounds__(MShape<P>::NT)
-k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restrict__ vals, int nb1, int nlogical) {
+k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restrict__ vals, int nb1, int seg_len,
+         int nseg, int nlogical) {
   using S = MShape<P>;
   constexpr int p = S::p, Q = S::Q, W = S::W, ME = S::ME, G = S::G, NN = S::NN, NT = S::NT, T16 = S::NT16;
   constexpr int NS = TABLE ? 10 : 2;
@@ -190,11 +191,17 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
   const MGroup *groups = TABLE ? kGroupsTable : kGroupsDiag;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, kk = 8 * (lane >> 4);
   // XCD-aware numbering: workgroups b, b + 8, b + 16, ... share an XCD (and its L2); give them
-  // neighbouring pencil blocks, whose coefficient windows overlap
+  // neighbouring pencil blocks of one segment, whose coefficient windows overlap
   const int nper = (nlogical + 7) / 8;
   const int logical = (int)(blockIdx.x % 8) * nper + (int)(blockIdx.x / 8);
   if (logical >= nlogical) return;
-  const int I1 = (logical % nb1) * kMB, I2 = (logical / nb1) * kMB;
+  const int npb = nb1 * ((pb.n[2] + kMB - 1) / kMB);
+  const int seg = logical / npb, pbi = logical % npb;
+  const int I1 = (pbi % nb1) * kMB, I2 = (pbi / nb1) * kMB;
+  // rows [row_lo, row_hi) of the pencils along axis 0; their element columns start p before row_lo
+  // (warm-up columns, whose rows belong to the previous segment and are not emitted)
+  const int row_lo = seg * seg_len, row_hi = seg == nseg - 1 ? pb.n[0] : row_lo + seg_len;
+  const int e_lo = max(0, row_lo - (P - 1)), e_hi = min(pb.ne[0], row_hi);
   const int E1lo = max(0, I1 - p), E1hi = min(pb.ne[1] - 1, I1 + kMB - 1);
   const int E2lo = max(0, I2 - p), E2hi = min(pb.ne[2] - 1, I2 + kMB - 1);
   const int G1 = (E1hi - E1lo + 1) * Q, G2 = (E2hi - E2lo + 1) * Q;
@@ -269,12 +276,12 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
                                        16, 0, 0);
     }
   };
-  dma_step(0);
+  dma_step(e_lo * Q);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const int nsteps = pb.ne[0] * Q;
+  const int nsteps = e_hi * Q;
 
-  for (int e0 = 0; e0 < pb.ne[0]; ++e0) {
+  for (int e0 = e_lo; e0 < e_hi; ++e0) {
     for (int i = t; i < Q * P; i += NT) {
       const size_t o = (size_t)e0 * Q * P + i;
       (&fX0[0][0][0])[i] = (float)pb.ax[0].B[o];
@@ -412,6 +419,7 @@ k_rgmma3(DevProblem pb, const float *__restrict__ cs, int64_t ld, float *__restr
     const int last = (e0 == pb.ne[0] - 1) ? p : 0;
     for (int a0 = 0; a0 <= last; ++a0) {
       const int i0 = e0 + a0;
+      if (i0 < row_lo || i0 >= row_hi) continue;          // uniform: a warm-up column's row
       if (t < kMB * kMB) {
         const int ri1 = I1 + (t & 1), ri2 = I2 + (t >> 1);
         rowLen[t] = 0;
@@ -488,11 +496,38 @@ iga_status run_mma(Handle &h, const double *U, float *vals) {
                      h.mma_cs, ld);
   kt_end(h);
   IGA_HIP_CHECK(hipGetLastError());
-  const int nb1 = (h.pb.n[1] + kMB - 1) / kMB, nb2 = (h.pb.n[2] + kMB - 1) / kMB;
-  const int nlogical = nb1 * nb2, grid = ((nlogical + 7) / 8) * 8;
+  const int nb1 = (h.pb.n[1] + kMB - 1) / kMB, nb2 = (h.pb.n[2] + kMB - 1) / kMB, npb = nb1 * nb2;
+  // segments along axis 0 (IGA_OPT_ROW_SEGMENTS, else planned): minimise (rounds of resident blocks) x
+  // (element columns per block), a segment's p warm-up columns weighted twice (they also restart the
+  // window stream).  Measured on the quarter cylinder 48^3, Jacobian in ms for 1 / 2 / 3 / 4 segments:
+  // p = 4 BF16 4.25 / 4.81 / 4.61 / 5.01, split 5.04 / 5.73 / 5.48 / 5.96; p = 3 BF16 1.46 / 1.59 / 1.64 /
+  // 1.69, split 2.38 / 2.26 / 2.21 / 2.32; p = 2 BF16 0.755 / 0.768 / 0.661 / 0.697, split 0.855 / 0.887 /
+  // 0.878 / 0.873 (the rule picks 1, 1, 1, 3, 3, 1).
+  const int ne0 = h.pb.ne[0], p = h.pb.P - 1;
+  int nseg = h.row_segments;
+  if (nseg <= 0) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rgmma3<P, TABLE, SPLIT>, MShape<P>::NT, 0) !=
+            hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h.device) != hipSuccess || ncu < 1)
+      ncu = 256;
+    const long slots = (long)per_cu * ncu;
+    double best = 1e300;
+    nseg = 1;
+    for (int s = 1; s <= 16 && s <= ne0; ++s) {
+      const int len = (ne0 + s - 1) / s, ns = (ne0 + len - 1) / len;
+      const double cost = (double)((npb * (long)ns + slots - 1) / slots) * (len + (ns > 1 ? 2 * p : 0));
+      if (cost < best) { best = cost; nseg = s; }
+    }
+  }
+  if (nseg > ne0) nseg = ne0;
+  const int seg_len = (ne0 + nseg - 1) / nseg;
+  nseg = (ne0 + seg_len - 1) / seg_len;
+  const int nlogical = npb * nseg, grid = ((nlogical + 7) / 8) * 8;
   kt_begin(h, SPLIT ? "k_rgmma3 (split BF16)" : "k_rgmma3 (BF16)");
   hipLaunchKernelGGL((k_rgmma3<P, TABLE, SPLIT>), dim3((unsigned)grid), dim3(MShape<P>::NT), 0, h.stream, h.pb,
-                     (const float *)h.mma_cs, ld, vals, nb1, nlogical);
+                     (const float *)h.mma_cs, ld, vals, nb1, seg_len, nseg, nlogical);
   kt_end(h);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;

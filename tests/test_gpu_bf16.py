@@ -78,6 +78,34 @@ def test_bf16_jacobian_matches_oracle(name, prec):
 
 
 @pytest.mark.parametrize("prec", [iga.IGA_BF16, iga.IGA_BF16X3])
+@pytest.mark.parametrize("p,nel", [(3, [13, 5, 4]), (4, [11, 4, 3]), (2, [9, 5, 4])])
+def test_bf16_segments_along_axis0(p, nel, prec):
+    """Pencils split into segments along axis 0 (IGA_OPT_ROW_SEGMENTS; ragged last segments, segments
+    shorter than the p warm-up columns): every row sums the same element columns in the same order,
+    so the values equal the unsplit ones bit for bit, and meet the oracle's bar."""
+    print(f"[case] BF16 segments p={p} nel={nel} prec={prec}", flush=True)
+    patch = inputs.quarter_cylinder(nel, p, dim=3)
+    kap = np.exp(inputs.grf_rff(patch.ctrl, 3, 1))
+    kw = dict(lam=1.0, kappa_mode=1, kappa=kap)
+    o = oracle.Oracle(patch.knots, patch.degree, patch.ctrl, patch.weights, **kw)
+    g = iga.IGA(patch.knots, patch.degree, patch.ctrl, patch.weights, **kw)
+    U = torch.as_tensor(inputs.uniform(11, 3, patch.ndof, 0.0, 0.3), device="cuda")
+    ref = o.jacobian(U.cpu().numpy())
+    base = None
+    for nseg in (1, 2, 3, 5, nel[0], 0):
+        g.set_option(iga.IGA_OPT_ROW_SEGMENTS, nseg)
+        vals = torch.full((g.nnz,), float("nan"), dtype=torch.float32, device="cuda")
+        g.assemble_jacobian(U, vals, prec)
+        torch.cuda.synchronize()
+        got = vals.cpu().numpy()
+        assert np.all(np.isfinite(got)), nseg
+        if base is None:
+            base = got
+        assert np.array_equal(got, base), nseg
+        assert rel(got, ref) < BARS[prec], nseg
+
+
+@pytest.mark.parametrize("prec", [iga.IGA_BF16, iga.IGA_BF16X3])
 @pytest.mark.parametrize("name", ["cyl3_p3_nodal", "box3_p3_kel"])
 def test_newton_with_bf16_jacobian_reaches_fp64_solution(name, prec):
     print(f"[case] Newton with BF16 jacobian {name} prec={prec}", flush=True)
