@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) k_mfield(DevProblem pb, const double *__r
   const int nc = min(C1, ne1 - e1s), nk = nc + p;
   for (int i = t; i < P * P * nk; i += 256) {   // a0 fastest: runs of P consecutive coefficients of U
     const int a0 = i % P, k1 = (i / P) % nk, a2 = i / (nk * P);
-    sU[a2][a0][k1] = U[(e0 + a0) + (int64_t)n0 * ((e1s + k1) + (int64_t)n1 * (e2 + a2))];
+    sU[a2][a0][k1] = U[wrap_fn(pb.ax[0], e0 + a0) + (int64_t)n0 * ((e1s + k1) + (int64_t)n1 * (e2 + a2))];
   }
   if (t < Q * P) {
     (&b0[0][0])[t] = pb.ax[0].B[(size_t)e0 * Q * P + t];
@@ -186,7 +186,11 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
   const int I1 = (pbi % nb1) * B1, I2 = (pbi / nb1) * B2;
   const int W1lo = I1 - p, W2lo = I2 - p;   // first window element (may be negative)
   const int row_lo = seg * seg_len, row_hi = (seg == nseg - 1) ? n0 : (seg + 1) * seg_len;
-  const int e_start = max(0, row_lo - p), e_end = row_hi;   // columns past ne0 only flush rows
+  // a periodic axis 0 (C^(p-1) across the seam: n0 = ne0 functions, element e carries rows e .. e + p
+  // mod n0) takes its warm-up columns from the far end of the axis (column e < 0 is element e + ne0);
+  // an open one starts at column 0 and flushes its last p rows with columns past ne0
+  const bool per0 = pb.ax[0].nper != 0;
+  const int e_start = per0 ? row_lo - p : max(0, row_lo - p), e_end = row_hi;
   const int t = threadIdx.x;
   const size_t GG1 = (size_t)ne1 * Q, GG2 = (size_t)ne2 * Q;
 
@@ -244,7 +248,7 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
   // every lane loads (points outside the mesh read the column's first point and are zeroed when
   // stored), so no register is written while a load into it may still be in flight
   auto load_win = [&](int e0) {
-    const CT *base = mf + (size_t)e0 * Q * GG2 * GG1;
+    const CT *base = mf + (size_t)(e0 < 0 ? e0 + ne0 : e0) * Q * GG2 * GG1;
 #pragma unroll
     for (int j = 0; j < NLD; ++j) pre[j] = base[woff[j] >= 0 ? woff[j] : 0];
   };
@@ -259,6 +263,7 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
   double tv = 0;
   int64_t tc = 0;
   auto load_tab = [&](int e0) {
+    e0 = e0 < 0 ? e0 + ne0 : e0;   // a warm-up column of a periodic axis: its rows are not emitted
     if (t < QP) {
       if (e0 < ne0) tv = (double)b0t[(size_t)e0 * QP + t];
     } else if (t < QP + W) {
@@ -349,23 +354,33 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
     // row i0 = e0 has received its last element column: stage it, then reuse its slot
     const int i0 = e0;
     const bool emit = e0 >= row_lo;
-    const int l0 = max(0, i0 - p), w0 = min(n0 - 1, i0 + p) - l0 + 1;
+    // the row's axis-0 columns: an open axis stores column j0 at j0 - l0; on a periodic axis the 2p + 1
+    // columns i0 - p .. i0 + p wrap, and a row at the seam lists them sorted: those at or below
+    // (i0 + p) mod n0 first, the wrapped-around ones after (position j - (n0 - W))
+    const int l0 = per0 ? 0 : max(0, i0 - p), w0 = per0 ? W : min(n0 - 1, i0 + p) - l0 + 1;
+    const bool seam = per0 && (i0 < p || i0 + p >= n0);
+    const int lowEnd = i0 + p >= n0 ? i0 + p - n0 : i0 + p;
     const int slot = il1 * B2 + il2;
     if (live && emit) {
       // the column range and the axis-0 Dirichlet tests depend on i0 and k only (wave-uniform)
       const bool rowDir = dirRow12 || (((msk >> 0) & 1u) && i0 == 0) || (((msk >> 1) & 1u) && i0 == n0 - 1);
       const bool diag = o1 == p && o2 == p;
       const double *sM0 = tsm[buf], *sA0 = tsa[buf];
-      OT *dst = &stage[slot][off12 * w0 - l0];
+      OT *dst = &stage[slot][off12 * w0];
 #pragma unroll
       for (int k = 0; k < W; ++k) {
-        const int j0 = i0 + k - p;
-        if (j0 < 0 || j0 >= n0) continue;
+        int j0 = i0 + k - p;
+        if (!per0 && (j0 < 0 || j0 >= n0)) continue;
         const bool colDir = dirCol12 || (((msk >> 0) & 1u) && j0 == 0) || (((msk >> 1) & 1u) && j0 == n0 - 1);
         double v = (double)acc[R][k] + sA0[k] * c1 + sM0[k] * c2;
         v = colDir ? 0.0 : v;
         v = rowDir ? ((k == p && diag) ? 1.0 : 0.0) : v;
-        dst[j0] = (OT)v;
+        int pos = j0 - l0;
+        if (per0) {
+          j0 = j0 < 0 ? j0 + n0 : (j0 >= n0 ? j0 - n0 : j0);
+          pos = !seam ? k : (j0 <= lowEnd ? j0 : j0 - (n0 - W));
+        }
+        dst[pos] = (OT)v;
       }
     }
     if (owner && o1 == p && o2 == p) {   // the diagonal window of each pencil row describes it
@@ -499,6 +514,9 @@ iga_status noalloc_scratch_init(int device) {
 
 bool rgsep_supported(const Handle &h, int b1, int b2) {
   if (!h.pb.separable || !h.pb.simple_knots || h.pb.dim != 3 || !h.mfield) return false;
+  // a periodic axis 0: C^(p-1) across the seam (as many functions as elements, so element e carries
+  // rows e .. e + p mod n0) and 2p + 1 distinct columns per row
+  if (h.pb.ax[0].nper && (h.pb.n[0] != h.pb.ne[0] || h.pb.n[0] < 2 * h.pb.p + 1)) return false;
   // window offsets inside the Q point planes of one element column are 32-bit
   if ((double)h.pb.Q * h.pb.ne[1] * h.pb.Q * h.pb.ne[2] * h.pb.Q >= 2147483647.0) return false;
   if (h.pb.P < 2 || h.pb.P > 5) return false;

@@ -284,8 +284,8 @@ static iga_status dev_upload(Handle &h, T **p, const T *src, size_t count) {
 //  phi_d[i][o][k] = B_i(g) B_{i+o-p}(g) at the k-th Gauss point g of supp(B_i) (element i-p+k/Q,
 //                   point k mod Q), zero where j = i+o-p is not a function or g is outside the mesh;
 // and the axis-0 basis table [ne0][Q][P], both in FP64 and FP32; the prefix sums of the stencil widths (row pointers of the tensor-product pattern)
-// and the per-point reaction-coefficient buffer.
-static iga_status build_separable_tables(Handle &h, const std::vector<double> *hostB) {
+// and the per-point reaction-coefficient buffer.  Axes 1 and 2 are open; axis 0 may be periodic.
+static iga_status build_separable_tables(Handle &h, const std::vector<double> *hostB, const std::vector<int> *stw) {
   const DevProblem &pb = h.pb;
   const int p = pb.p, P = pb.P, Q = pb.Q, W = 2 * p + 1, KM = P * Q;
   iga_status st;
@@ -325,7 +325,7 @@ static iga_status build_separable_tables(Handle &h, const std::vector<double> *h
       int64_t c = 0;
       for (int i = 0; i < pb.n[a]; ++i) {
         cw.push_back(c);
-        c += std::min(pb.n[a] - 1, i + p) - std::max(0, i - p) + 1;
+        c += stw[a][i];
       }
       cw.push_back(c);
     }
@@ -570,9 +570,10 @@ iga_status create_impl(const iga_desc *d, void *stream, Handle **out) {
       }
   pb.rational = d->weights != nullptr;
   pb.table = (d->ctrl != nullptr || d->weights != nullptr || d->kappa_mode == IGA_KAPPA_NODAL) ? 1 : 0;
-  pb.separable = (!pb.table && d->kappa_mode == IGA_KAPPA_ONE && !pb.periodic) ? 1 : 0;
+  // x = xi and kappa one; a periodic axis only as axis 0 (the streaming axis of the separable row-gather)
+  pb.separable = (!pb.table && d->kappa_mode == IGA_KAPPA_ONE && !pb.ax[1].nper && !pb.ax[2].nper) ? 1 : 0;
   if (pb.separable && pb.simple_knots && dim == 3 && pb.P >= 2 && pb.P <= 5 &&
-      (st = build_separable_tables(*h, hostB))) {
+      (st = build_separable_tables(*h, hostB, stw))) {
     iga_destroy((iga_t)h);
     return st;
   }

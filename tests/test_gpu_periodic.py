@@ -103,6 +103,41 @@ def test_periodic_pattern_residual_jacobians(name):
     assert rel(host(y2), Jv) < TOL64
 
 
+@pytest.mark.parametrize("p,nel,cont", [(1, [6, 7, 5], 0), (2, [9, 5, 6], 1), (2, [5, 4, 3], 1), (3, [12, 4, 5], 2),
+                                        (3, [7, 6, 5], 2), (4, [10, 3, 4], 3), (4, [9, 4, 3], 3), (3, [8, 5, 4], 0)])
+def test_periodic_axis0_separable_jacobian(p, nel, cont):
+    """A periodic axis 0 with C^(p-1) across the seam on the separable row-gather (x = xi, kappa one,
+    axes 1 and 2 open): warm-up columns from the far end of the axis, rows at the seam listed in sorted
+    column order.  FP64 against the oracle at 1e-12 and FP32 at 1e-5, for every segment count along axis 0
+    (values identical to the unsplit pencils); the kernel that ran is the separable one, and a lower
+    continuity across the seam (more functions than elements) takes the element path (atomic adds, so
+    only the oracle's bar applies)."""
+    print(f"[case] periodic axis-0 separable jacobian p={p} nel={nel} C^{cont}", flush=True)
+    patch = inputs.unit_box(3, nel, p)
+    per = [cont, None, None]
+    o = oracle.Oracle(patch.knots, patch.degree, lam=2.0, periodic=per)
+    g = iga.IGA(patch.knots, patch.degree, lam=2.0, periodic=per)
+    U = inputs.uniform(13, 1, o.N, 0.0, 0.3)
+    ref = o.jacobian(U)
+    g.set_option(iga.IGA_OPT_KERNEL_TIMING, 1)
+    base = None
+    for nseg in (0, 1, 2, 3, nel[0]):
+        g.set_option(iga.IGA_OPT_ROW_SEGMENTS, nseg)
+        vals = torch.full((g.nnz,), np.nan, dtype=torch.float64, device="cuda")
+        g.assemble_jacobian(dev(U), vals)
+        got = host(vals)
+        assert np.all(np.isfinite(got)), nseg
+        assert rel(got, ref) < TOL64, nseg
+        if base is None:
+            base = got
+        # the row-gather writes each value once in a fixed order; the element path adds atomically
+        assert np.array_equal(got, base) or cont != p - 1, nseg
+    assert any(name.startswith("k_rgsep3") for name, _ in g.kernel_times()) == (cont == p - 1)
+    v32 = torch.full((g.nnz,), np.nan, dtype=torch.float32, device="cuda")
+    g.assemble_jacobian(dev(U), v32, iga.IGA_FP32)
+    assert rel(host(v32), ref) < 1e-5
+
+
 @pytest.mark.parametrize("name", ["per2_p2_c1_x", "per2_p3_c0_x_kel", "per3_p2_xz", "per3_p3_c2_x"])
 @pytest.mark.parametrize("mf", [False, True])
 def test_periodic_newton_matches_oracle(name, mf):
