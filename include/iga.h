@@ -93,10 +93,14 @@ typedef enum {
                                 element per workgroup; 1, 2 and 3 also select tiles for the 3D
                                 fourth-order operator on x = xi without weights and the 2D and 3D
                                 Cahn-Hilliard residual */
-  IGA_OPT_RES_ZRUN = 9       /* IGA_OPT_TILED_3D = 1: chunks per run along axis 2 (one workgroup's
+  IGA_OPT_RES_ZRUN = 9,      /* IGA_OPT_TILED_3D = 1: chunks per run along axis 2 (one workgroup's
                                 work), 1..8, capped at a kernel's longest run (4 chunks of 4 elements for
                                 the residual and apply, 8 chunks of 2 elements for the 3D Cahn-Hilliard
                                 residual of C^1 quadratics); 0 (default) plans it from the mesh size */
+  IGA_OPT_FDM_KERNEL = 10    /* dense 1D transforms of the fast-diagonalisation preconditioners: 0
+                                (default) matrix cores for boxes that give 1024 tiles of 128 x 64, the
+                                vector units otherwise; 1 always the vector units; 2 always the FP64
+                                matrix cores */
 } iga_option;
 
 /* CG preconditioner (iga_set_option(IGA_OPT_PRECOND)):

@@ -24,6 +24,7 @@ IGA_OPT_PRECOND = 6
 IGA_OPT_ND_SCATTER = 7
 IGA_OPT_TILED_3D = 8
 IGA_OPT_RES_ZRUN = 9
+IGA_OPT_FDM_KERNEL = 10
 IGA_PRECOND_AUTO, IGA_PRECOND_JACOBI, IGA_PRECOND_FDM = 0, 1, 2
 
 _STATUS = {0: "IGA_OK", 1: "IGA_EINVAL", 2: "IGA_ENOMEM", 3: "IGA_EHIP", 4: "IGA_ENOCONV",

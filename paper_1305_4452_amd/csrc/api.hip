@@ -714,6 +714,10 @@ iga_status iga_set_option(iga_t hh, int key, int64_t value) {
       if (value < 0 || value > 3) return fail(IGA_EINVAL, "IGA_OPT_TILED_3D is 0, 1, 2 or 3");
       h->tiled_3d = (int)value;
       return IGA_OK;
+    case IGA_OPT_FDM_KERNEL:
+      if (value < 0 || value > 2) return fail(IGA_EINVAL, "IGA_OPT_FDM_KERNEL is 0, 1 or 2");
+      h->fdm_kernel = (int)value;
+      return IGA_OK;
     case IGA_OPT_RES_ZRUN:
       if (value < 0 || value > 8) return fail(IGA_EINVAL, "IGA_OPT_RES_ZRUN is 0..8");
       h->res_zrun = (int)value;

@@ -157,6 +157,7 @@ struct Handle {
   int tiled_3d = 1;   // 3D residual / apply by element tiles where supported (0: one element per workgroup;
                       // 1: column tiles streamed along axis 2; 2: cube tiles; 3: column tiles of fixed depth)
   int res_zrun = 0;   // streamed column tiles: chunks of 4 elements per run along axis 2 (0 = planned)
+  int fdm_kernel = 0; // dense 1D transforms of the fast diagonalisation: 0 planned, 1 vector units, 2 matrix cores
   int row_b1 = 0, row_b2 = 0;
   int row_segments = 0;           // separable row-gather: segments along axis 0 (0 = planned)
   // separable row-gather tables (3D, identity geometry, kappa = 1, simple knots)

@@ -532,13 +532,134 @@ __global__ void __launch_bounds__(256) k_fdm_gemm(const double *__restrict__ in,
   }
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// The same transform on the FP64 matrix cores (v_mfma_f64_16x16x4f64; lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16] and receives D[l / 16 + 4 r][l % 16], r = 0..3, checked by an in-bounds probe).  A workgroup owns 128 rows x 64
+// columns, each of its four waves 32 rows as 2 x 4 products of 16 x 16 tiles (32 accumulators per lane;
+// 64 held the epilogue's copies in VGPRs as well and left one wave per SIMD); per 16-deep step the T and
+// X tiles are staged in LDS with the reduction index fastest (row stride 17 doubles), so a wave reads 6
+// operands per 8 products and the vector units only move data.  The next step's tiles are loaded into
+// registers while the current step's products run: without that, every step waited for its own loads
+// and the kernel ran no faster than the vector one.
+template <int AX>
+__global__ void __launch_bounds__(256) k_fdm_mfma(const double *__restrict__ in, BoxView vi, double *__restrict__ out,
+                                                  BoxView vo, const double *__restrict__ T, int m0, int m1, int m2,
+                                                  const double *__restrict__ mu0, const double *__restrict__ mu1,
+                                                  const double *__restrict__ mu2, const double *__restrict__ shift,
+                                                  ChScale chs) {
+  constexpr int kM = 128, kN = 64, kK = 16, kS = kK + 1;
+  __shared__ double Ts[kM * kS], Xs[kN * kS];   // [row][k], [column][k]
+  const int m = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
+  const int64_t ncol = AX == 0 ? (int64_t)m1 * m2 : (AX == 1 ? (int64_t)m0 * m2 : (int64_t)m0 * m1);
+  const int t = threadIdx.x, lane = t & 63, wr = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nbr = (m + kM - 1) / kM;
+  const int r0 = (blockIdx.x % nbr) * kM;
+  const int64_t c0 = (int64_t)(blockIdx.x / nbr) * kN;
+  const int64_t sin = AX == 0 ? vi.s0 : (AX == 1 ? vi.s1 : vi.s2), sout = AX == 0 ? vo.s0 : (AX == 1 ? vo.s1 : vo.s2);
+  // the part of a column's address that does not depend on the reduction index (-1: past the box)
+  auto col_part = [&](int64_t gc, const BoxView &v) -> int64_t {
+    if (gc >= ncol) return -1;
+    int i0, i1, i2;
+    box_coords<AX>(0, gc, m0, m1, i0, i1, i2);
+    return v.off + i0 * v.s0 + i1 * v.s1 + i2 * v.s2;
+  };
+  // X tile: consecutive lanes on the contiguous direction (k for axis 0: four columns per lane; the
+  // columns otherwise: one column per lane, four k)
+  constexpr int NXC = AX == 0 ? 4 : 1;
+  int64_t xc[NXC];
+#pragma unroll
+  for (int j = 0; j < NXC; ++j) xc[j] = col_part(c0 + (AX == 0 ? (t >> 4) + 16 * j : (t & 63)), vi);
+  f64x4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // the tiles of step k0 are loaded into registers one step ahead (in flight while the previous step's
+  // products run): T 16 consecutive k of a row on consecutive lanes; X as described above
+  double tp[8], xp[4];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = t & 15, gr = r0 + (t >> 4) + 16 * j, gk = k0 + k;
+      tp[j] = (gr < m && gk < m) ? T[(int64_t)gr * m + gk] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = AX == 0 ? (t & 15) : (t >> 6) + 4 * j;
+      const int64_t base = xc[AX == 0 ? j : 0];
+      const int gk = k0 + k;
+      xp[j] = (gk < m && base >= 0) ? in[base + gk * sin] : 0.0;
+    }
+  };
+  load_tiles(0);
+  for (int k0 = 0; k0 < m; k0 += kK) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Ts[((t >> 4) + 16 * j) * kS + (t & 15)] = tp[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = AX == 0 ? (t & 15) : (t >> 6) + 4 * j, col = AX == 0 ? (t >> 4) + 16 * j : (t & 63);
+      Xs[col * kS + k] = xp[j];
+    }
+    __syncthreads();
+    if (k0 + kK < m) load_tiles(k0 + kK);
+#pragma unroll
+    for (int kk = 0; kk < kK; kk += 4) {
+      double a[2], b[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = Ts[(wr * 32 + i * 16 + lr) * kS + kk + lk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Xs[(j * 16 + lr) * kS + kk + lk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const double c_shift = (mu0 && shift) ? *shift : 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t gc = c0 + j * 16 + lr, oc = col_part(gc, vo);
+    if (oc < 0) continue;
+    int c0i, c1i, c2i;
+    box_coords<AX>(0, gc, m0, m1, c0i, c1i, c2i);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = r0 + wr * 32 + i * 16 + lk + 4 * r;
+        if (gr >= m) continue;
+        const int i0 = AX == 0 ? gr : c0i, i1 = AX == 1 ? gr : c1i, i2 = AX == 2 ? gr : c2i;
+        double v = acc[i][j][r];
+        if (chs.eta0) {
+          const double a0 = mu0[i0], a1 = mu1[i1], a2 = mu2[i2];
+          const double lam = chs.am + chs.sa * (a0 + a1 + a2) +
+                             chs.sb * (chs.eta0[i0] + chs.eta1[i1] + chs.eta2[i2] + 2.0 * (a0 * a1 + a0 * a2 + a1 * a2));
+          v /= fmax(lam, 0.05 * chs.am);
+        } else if (mu0) {
+          v /= mu0[i0] + mu1[i1] + (mu2 ? mu2[i2] : 0.0) + c_shift;
+        }
+        out[oc + gr * sout] = v;
+      }
+  }
+}
+
 template <int AX>
 void launch_gemm_axis(Handle &h, const double *in, BoxView vi, double *out, BoxView vo, const double *T, const int *m,
                       const double *mu0, const double *mu1, const double *mu2, const double *shift, ChScale chs) {
   const int mm = m[AX];
   const int64_t ncol = AX == 0 ? (int64_t)m[1] * m[2] : (AX == 1 ? (int64_t)m[0] * m[2] : (int64_t)m[0] * m[1]);
-  // the largest per-lane block that still gives at least 1024 workgroups (4 per CU)
+  // the largest per-lane block that still gives at least 1024 workgroups (4 per CU); the matrix cores
+  // take boxes whose 128 x 64 tiles reach that count too (IGA_OPT_FDM_KERNEL forces either kernel)
   auto blocks = [&](int R) { return (int64_t)((mm + 16 * R - 1) / (16 * R)) * ((ncol + 16 * R - 1) / (16 * R)); };
+  const int64_t mblocks = (int64_t)((mm + 127) / 128) * ((ncol + 63) / 64);
+  if (h.fdm_kernel == 2 || (h.fdm_kernel == 0 && mblocks >= 1024)) {
+    hipLaunchKernelGGL((k_fdm_mfma<AX>), dim3((unsigned)mblocks), dim3(256), 0, h.stream, in, vi, out, vo, T, m[0],
+                       m[1], m[2], mu0, mu1, mu2, shift, chs);
+    return;
+  }
   const int R = blocks(8) >= 1024 ? 8 : (blocks(4) >= 1024 ? 4 : 2);
   const unsigned nb = (unsigned)blocks(R);
   if (R == 8)

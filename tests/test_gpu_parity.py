@@ -414,7 +414,8 @@ def test_newton_3d_modes(mf, prec):
 @pytest.mark.parametrize("case", ["cube_p3", "cube_p2_ragged_mask", "square_p3", "square_p4_partial_mask"])
 def test_newton_fdm_preconditioner(case):
     """The fast-diagonalisation preconditioner reaches the oracle's solution with far fewer CG
-    iterations than Jacobi (and the same answer in every Newton mode)."""
+    iterations than Jacobi (and the same answer in every Newton mode), with its dense 1D transforms on
+    the vector units and on the FP64 matrix cores (IGA_OPT_FDM_KERNEL 1, 2)."""
     print(f"[case] fdm {case}", flush=True)
     if case == "cube_p3":
         patch, lam, mask = inputs.unit_box(3, 6, 3), 5.0, None
@@ -428,18 +429,20 @@ def test_newton_fdm_preconditioner(case):
     o = oracle.Oracle(patch.knots, patch.degree, lam=lam, dirichlet_mask=mask)
     Uo, ho, rc = o.newton(U0, atol=1e-14, linear_solver=2, cg_rtol=1e-14)
     its = {}
-    for pre in (iga.IGA_PRECOND_JACOBI, iga.IGA_PRECOND_FDM):
+    for pre, fk in ((iga.IGA_PRECOND_JACOBI, 0), (iga.IGA_PRECOND_FDM, 1), (iga.IGA_PRECOND_FDM, 2)):
         for mf in (False, True):
             g = iga.IGA(patch.knots, patch.degree, lam=lam, dirichlet_mask=mask)
             g.set_option(iga.IGA_OPT_PRECOND, pre)
+            g.set_option(iga.IGA_OPT_FDM_KERNEL, fk)
             U = dev(U0)
             rep = g.newton_solve(U, atol=0.0, rtol=1e-10, matrix_free=mf)
-            assert rep["converged"], (pre, mf)
-            assert rel(host(U), Uo) < 1e-8, (pre, mf)
-            its[(pre, mf)] = rep["krylov_iters_total"]
+            assert rep["converged"], (pre, fk, mf)
+            assert rel(host(U), Uo) < 1e-8, (pre, fk, mf)
+            its[(pre, fk, mf)] = rep["krylov_iters_total"]
     print("[fdm] CG iterations", its, flush=True)
     for mf in (False, True):
-        assert its[(iga.IGA_PRECOND_FDM, mf)] * 2 <= its[(iga.IGA_PRECOND_JACOBI, mf)], its
+        for fk in (1, 2):
+            assert its[(iga.IGA_PRECOND_FDM, fk, mf)] * 2 <= its[(iga.IGA_PRECOND_JACOBI, 0, mf)], its
 
 
 def test_fdm_rejected_for_long_axes():
@@ -461,16 +464,18 @@ def test_fdm_long_axes(dim, nel, p):
     o = oracle.Oracle(patch.knots, patch.degree, lam=2.0)
     Uo, ho, rc = o.newton(U0, atol=1e-14, linear_solver=2, cg_rtol=1e-14)
     its = {}
-    for pre in (iga.IGA_PRECOND_JACOBI, iga.IGA_PRECOND_FDM):
+    for pre, fk in ((iga.IGA_PRECOND_JACOBI, 0), (iga.IGA_PRECOND_FDM, 1), (iga.IGA_PRECOND_FDM, 2)):
         g = iga.IGA(patch.knots, patch.degree, lam=2.0)
         g.set_option(iga.IGA_OPT_PRECOND, pre)
+        g.set_option(iga.IGA_OPT_FDM_KERNEL, fk)
         U = dev(U0)
         rep = g.newton_solve(U, atol=0.0, rtol=1e-12, max_krylov=20000)
-        assert rep["converged"], pre
-        assert rel(host(U), Uo) < 1e-8, (pre, rel(host(U), Uo))
-        its[pre] = rep["krylov_iters_total"]
+        assert rep["converged"], (pre, fk)
+        assert rel(host(U), Uo) < 1e-8, (pre, fk, rel(host(U), Uo))
+        its[pre, fk] = rep["krylov_iters_total"]
     print("[fdm] CG iterations", its, flush=True)
-    assert its[iga.IGA_PRECOND_FDM] * 2 <= its[iga.IGA_PRECOND_JACOBI], its
+    for fk in (1, 2):
+        assert its[iga.IGA_PRECOND_FDM, fk] * 2 <= its[iga.IGA_PRECOND_JACOBI, 0], its
 
 
 @pytest.mark.parametrize("name", ["cyl3_p2_nodal", "cyl3_p3_nodal", "ann2_p3_nodal", "box2_p4_kel"])
