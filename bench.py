@@ -80,7 +80,7 @@ def rowgather_flops(n: int, p: int, b1: int, b2: int) -> float:
 # WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a 256 MiB device
 # copy (FETCH x2.0, WRITE x1.0); the summary is under profiles/.  Valid only for the kernel source
 # the counters were taken on (SHA-1 of rg_sep.hip); otherwise the traffic is reported as null.
-TRAFFIC = {"src_sha1": "2c8a67b0f7b196d84aeef08952c5bf9b59454208", "fetch_kib": 119467, "write_kib": 814773,
+TRAFFIC = {"src_sha1": "1a6c297a7c29736578ffb44c3904775691580f86", "fetch_kib": 119434, "write_kib": 819303,
            "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -143,7 +143,7 @@ __device__ __forceinline__ void band_dots(const CT *__restrict__ ph, const CT (&
       std::make_integer_sequence<int, W>{});
 }
 
-template <int P, int B1, int B2, typename CT, typename OT>
+template <int P, int B1, int B2, typename CT, typename OT, bool PER0>
 __global__ void __launch_bounds__(rs_threads(B1 * (2 * P - 1) * B2 * (2 * P - 1)), sep_min_waves(P, B1, B2, sizeof(CT) == 8))
 k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, const CT *__restrict__ phi2,
          const CT *__restrict__ b0t, const int64_t *__restrict__ cw0, const double *__restrict__ sepM0,
@@ -186,10 +186,11 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
   const int I1 = (pbi % nb1) * B1, I2 = (pbi / nb1) * B2;
   const int W1lo = I1 - p, W2lo = I2 - p;   // first window element (may be negative)
   const int row_lo = seg * seg_len, row_hi = (seg == nseg - 1) ? n0 : (seg + 1) * seg_len;
-  // a periodic axis 0 (C^(p-1) across the seam: n0 = ne0 functions, element e carries rows e .. e + p
-  // mod n0) takes its warm-up columns from the far end of the axis (column e < 0 is element e + ne0);
-  // an open one starts at column 0 and flushes its last p rows with columns past ne0
-  const bool per0 = pb.ax[0].nper != 0;
+  // a periodic axis 0 (PER0; C^(p-1) across the seam: n0 = ne0 functions, element e carries rows
+  // e .. e + p mod n0) takes its warm-up columns from the far end of the axis (column e < 0 is element
+  // e + ne0); an open one starts at column 0 and flushes its last p rows with columns past ne0.  A
+  // template parameter, so that the open kernel carries none of the seam arithmetic.
+  constexpr bool per0 = PER0;
   const int e_start = per0 ? row_lo - p : max(0, row_lo - p), e_end = row_hi;
   const int t = threadIdx.x;
   const size_t GG1 = (size_t)ne1 * Q, GG2 = (size_t)ne2 * Q;
@@ -248,7 +249,7 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
   // every lane loads (points outside the mesh read the column's first point and are zeroed when
   // stored), so no register is written while a load into it may still be in flight
   auto load_win = [&](int e0) {
-    const CT *base = mf + (size_t)(e0 < 0 ? e0 + ne0 : e0) * Q * GG2 * GG1;
+    const CT *base = mf + (size_t)(PER0 && e0 < 0 ? e0 + ne0 : e0) * Q * GG2 * GG1;
 #pragma unroll
     for (int j = 0; j < NLD; ++j) pre[j] = base[woff[j] >= 0 ? woff[j] : 0];
   };
@@ -263,7 +264,7 @@ k_rgsep3(DevProblem pb, const CT *__restrict__ mf, const CT *__restrict__ phi1, 
   double tv = 0;
   int64_t tc = 0;
   auto load_tab = [&](int e0) {
-    e0 = e0 < 0 ? e0 + ne0 : e0;   // a warm-up column of a periodic axis: its rows are not emitted
+    if (PER0 && e0 < 0) e0 += ne0;   // a warm-up column of a periodic axis: its rows are not emitted
     if (t < QP) {
       if (e0 < ne0) tv = (double)b0t[(size_t)e0 * QP + t];
     } else if (t < QP + W) {
@@ -416,14 +417,14 @@ struct SepPlan {
   int nseg, seg_len, nlogical, grid;
 };
 
-template <int P, int B1, int B2, typename CT, typename OT>
+template <int P, int B1, int B2, typename CT, typename OT, bool PER0>
 SepPlan plan_sep3(const Handle &h) {
   constexpr int W = 2 * P - 1;
   constexpr int NT = rs_threads(B1 * W * B2 * W);
   const int nb1 = (h.pb.n[1] + B1 - 1) / B1, nb2 = (h.pb.n[2] + B2 - 1) / B2;
   const int npb = nb1 * nb2, ne0 = h.pb.ne[0], p = P - 1;
   int per_cu = 0, ncu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rgsep3<P, B1, B2, CT, OT>, NT, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rgsep3<P, B1, B2, CT, OT, PER0>, NT, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h.device) != hipSuccess || ncu < 1)
@@ -465,11 +466,18 @@ iga_status run_sep3(Handle &h, const double *U, OT *vals, CT *mf, bool timed) {
   hipLaunchKernelGGL((k_mfield<P, CT>), gm, dim3(256), 0, h.stream, h.pb, U, mf);
   if (timed) kt_end(h);
   IGA_HIP_CHECK(hipGetLastError());
-  const SepPlan pl = plan_sep3<P, B1, B2, CT, OT>(h);
   if (timed) kt_begin(h, "k_rgsep3");
-  hipLaunchKernelGGL((k_rgsep3<P, B1, B2, CT, OT>), dim3((unsigned)pl.grid), dim3(NT), 0, h.stream, h.pb, mf,
-                     (const CT *)h.sep_phi[prec][1], (const CT *)h.sep_phi[prec][2], (const CT *)h.sep_b0[prec], h.sep_cw, h.pb.sepM[0], h.pb.sepA[0], vals,
-                     pl.seg_len, pl.nseg, pl.nlogical);
+  if (h.pb.ax[0].nper) {
+    const SepPlan pl = plan_sep3<P, B1, B2, CT, OT, true>(h);
+    hipLaunchKernelGGL((k_rgsep3<P, B1, B2, CT, OT, true>), dim3((unsigned)pl.grid), dim3(NT), 0, h.stream, h.pb, mf,
+                       (const CT *)h.sep_phi[prec][1], (const CT *)h.sep_phi[prec][2], (const CT *)h.sep_b0[prec], h.sep_cw,
+                       h.pb.sepM[0], h.pb.sepA[0], vals, pl.seg_len, pl.nseg, pl.nlogical);
+  } else {
+    const SepPlan pl = plan_sep3<P, B1, B2, CT, OT, false>(h);
+    hipLaunchKernelGGL((k_rgsep3<P, B1, B2, CT, OT, false>), dim3((unsigned)pl.grid), dim3(NT), 0, h.stream, h.pb, mf,
+                       (const CT *)h.sep_phi[prec][1], (const CT *)h.sep_phi[prec][2], (const CT *)h.sep_b0[prec], h.sep_cw,
+                       h.pb.sepM[0], h.pb.sepA[0], vals, pl.seg_len, pl.nseg, pl.nlogical);
+  }
   if (timed) kt_end(h);
   IGA_HIP_CHECK(hipGetLastError());
   return IGA_OK;
