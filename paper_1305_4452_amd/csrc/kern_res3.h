@@ -914,7 +914,7 @@ __device__ inline void res3s_body(const DevProblem &pb, const int blk, const int
   for (int k = 0; k < NZ; ++k) U[k] = U01[k] = U10[k] = Y0[k] = Y1[k] = Y2[k] = 0.0;
 
   // planes [pl0, pl1) of the chunk at Ez (pl1 - pl0 <= TEZ): transposed axes 1 and 0, then the atomics
-  auto emit = [&](int Ez, int pl0, int pl1, int t, int g0, int g1, bool act) {
+  auto emit = [&](int Ez, int pl0, int pl1, int ti, int g0, int g1, bool act) {
     if (act) {
 #pragma unroll
       for (int k2 = 0; k2 < NZ; ++k2)
@@ -927,7 +927,7 @@ __device__ inline void res3s_body(const DevProblem &pb, const int blk, const int
     }
     __syncthreads();
     const int ns = pl1 - pl0;
-    for (int i = t; i < TEZ * NI * G; i += NT) {
+    for (int i = ti; i < TEZ * NI * G; i += NT) {
       const int gg0 = i % G, k1 = (i / G) % NI, s = i / (G * NI);
       if (gg0 >= G0 || k1 >= NI1 || s >= ns) continue;
       double za = 0, zb = 0;
@@ -947,7 +947,7 @@ __device__ inline void res3s_body(const DevProblem &pb, const int blk, const int
       Zb[(s * NI + k1) * GS + gg0] = zb;
     }
     __syncthreads();
-    for (int i = t; i < TEZ * NI * NI; i += NT) {
+    for (int i = ti; i < TEZ * NI * NI; i += NT) {
       const int k0 = i % NI, k1 = (i / NI) % NI, s = i / (NI * NI);
       if (k0 >= NI0 || k1 >= NI1 || s >= ns) continue;
       double r = 0;
@@ -1386,7 +1386,7 @@ __device__ inline void chr3s_body(const DevProblem &pb, const int blk, const int
   for (int k = 0; k < NZ; ++k) bb[k] = db[k] = le[k] = bd[k] = rb[k] = yb[k] = y0[k] = y1[k] = ys[k] = 0.0;
 
   // planes [pl0, pl1) of the chunk at Ez (pl1 - pl0 <= TEZ): transposed axes 1 and 0, then the atomics
-  auto emit = [&](int Ez, int pl0, int pl1, int t, int g0, int g1, bool act) {
+  auto emit = [&](int Ez, int pl0, int pl1, int ti, int g0, int g1, bool act) {
     if (act) {
 #pragma unroll
       for (int k2 = 0; k2 < NZ; ++k2)
@@ -1400,7 +1400,7 @@ __device__ inline void chr3s_body(const DevProblem &pb, const int blk, const int
     }
     __syncthreads();
     const int ns = pl1 - pl0;
-    for (int i = t; i < TEZ * NI * G; i += NT) {
+    for (int i = ti; i < TEZ * NI * G; i += NT) {
       const int gg0 = i % G, k1 = (i / G) % NI, s = i / (G * NI);
       if (gg0 >= G0 || k1 >= NI1 || s >= ns) continue;
       double zb = 0, zd = 0, ze = 0;
@@ -1422,7 +1422,7 @@ __device__ inline void chr3s_body(const DevProblem &pb, const int blk, const int
       Ze[w] = ze;
     }
     __syncthreads();
-    for (int i = t; i < TEZ * NI * NI; i += NT) {
+    for (int i = ti; i < TEZ * NI * NI; i += NT) {
       const int k0 = i % NI, k1 = (i / NI) % NI, s = i / (NI * NI);
       if (k0 >= NI0 || k1 >= NI1 || s >= ns) continue;
       double r = 0;
