@@ -36,3 +36,18 @@ def test_struct_layouts_match_header_sizes():
     # iga_desc: 4 + 12 + 12 (+4 pad) + 24 + 8 + 8 + 12 (+4) + 8 + 4 (+4) + 8 + 8 + 4 + 12 (+4) = 136 bytes
     assert ctypes.sizeof(iga.iga_desc) == 136
     assert ctypes.sizeof(iga.iga_newton_opts) == 48
+
+
+def test_binding_constants_match_header_enums():
+    """Every enumerator the header defines (status codes, precisions, kappa modes, Jacobian algorithms,
+    options, preconditioners) has the same value in the Python binding."""
+    src = open(os.path.join(ROOT, "include", "iga.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    enums = re.findall(r"typedef enum\s*\{(.*?)\}", src, flags=re.S)
+    values = {}
+    for body in enums:
+        for name, val in re.findall(r"\b(IGA_[A-Z0-9_]+)\s*=\s*(\d+)", body):
+            values[name] = int(val)
+    assert len(values) >= 30 and "IGA_OPT_FDM_KERNEL" in values and "IGA_OPT_RES_ZRUN" in values
+    for name, val in values.items():
+        assert getattr(iga, name) == val, name
